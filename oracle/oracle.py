@@ -1,0 +1,221 @@
+"""ctypes wrapper of the FP64 CPU oracle (libns_oracle.so).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this module.  The oracle shares no
+code with the GPU library; its parameter struct below is declared
+independently of the GPU binding's.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libns_oracle.so")
+SRC = os.path.join(HERE, "ns_oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-ffp-contract=off",
+               SRC, "-o", LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Body(C.Structure):
+    _fields_ = [("kind", C.c_int), ("c", C.c_double * 3), ("half", C.c_double * 3),
+                ("heave_amp", C.c_double), ("heave_omega", C.c_double), ("heave_phase", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
+                ("rho_w", C.c_double), ("mu_w", C.c_double), ("rho_a", C.c_double),
+                ("mu_a", C.c_double), ("rho_s", C.c_double), ("mu_s", C.c_double), ("g", C.c_double),
+                ("n_cells", C.c_double), ("inv_kappa_p", C.c_double),
+                ("proj_penalty_weight", C.c_double), ("n_bodies", C.c_int), ("body", _Body * 4),
+                ("reinit_iters", C.c_int), ("reinit_dtau_over_h", C.c_double),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_sweeps", C.c_int),
+                ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("rel_resid0", C.c_double), ("rel_resid", C.c_double),
+                ("true_rel_resid", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        P = C.POINTER(Params)
+        S = C.POINTER(Stats)
+        d = C.c_double
+        sig = {
+            "orc_levelset_advect": [P, dp, dp, dp, dp, d, dp],
+            "orc_reinit": [P, dp, dp],
+            "orc_properties": [P, dp, d, dp, dp, dp, dp],
+            "orc_momentum": [P, dp, dp, dp, dp, d, d, dp, dp, dp],
+            "orc_face_beta": [P, dp, d, d, dp, dp, dp],
+            "orc_rhs": [P, dp, dp, dp, d, dp],
+            "orc_apply_A": [C.c_int, C.c_int, C.c_int, d, dp, dp, dp, dp, dp],
+            "orc_num_levels": [C.c_int, C.c_int, C.c_int],
+            "orc_vcycle": [P, dp, dp, dp, dp, dp],
+            "orc_pcg": [P, dp, dp, dp, dp, dp, S],
+            "orc_correct": [P, dp, dp, dp, dp, dp, dp, dp, d, dp, dp, dp],
+            "orc_step": [P, dp, dp, dp, dp, dp, d, d, C.c_int, S],
+            "orc_diagnostics": [P, dp, dp, dp, dp, dp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int if name in ("orc_num_levels", "orc_pcg", "orc_step") else None
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _arr(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2,
+                       coarse_sweeps=10, max_iters=200, rtol=1e-10, prec=0)
+
+
+def params(wl, **solver) -> Params:
+    """Oracle parameters for a workload (paper_2206_07732_amd.inputs.Workload)."""
+    P = Params()
+    P.nx, P.ny, P.nz, P.h = wl.nx, wl.ny, wl.nz, wl.h
+    P.rho_w, P.mu_w, P.rho_a, P.mu_a = wl.rho_w, wl.mu_w, wl.rho_a, wl.mu_a
+    P.rho_s, P.mu_s, P.g = wl.rho_s, wl.mu_s, wl.g
+    P.n_cells, P.inv_kappa_p, P.proj_penalty_weight = wl.n_cells, wl.inv_kappa_p, wl.proj_penalty_weight
+    P.n_bodies = len(wl.bodies)
+    for m, b in enumerate(wl.bodies):
+        P.body[m].kind = b.kind
+        for q in range(3):
+            P.body[m].c[q] = b.c[q]
+            P.body[m].half[q] = b.half[q]
+        P.body[m].heave_amp, P.body[m].heave_omega, P.body[m].heave_phase = \
+            b.heave_amp, b.heave_omega, b.heave_phase
+    opts = dict(SOLVER_DEFAULTS)
+    opts.update(solver)
+    for k, v in opts.items():
+        setattr(P, k, v)
+    return P
+
+
+def _shapes(P):
+    nx, ny, nz = P.nx, P.ny, P.nz
+    return (nz, ny, nx), (nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)
+
+
+def levelset_advect(P, sigma, u, v, w, dt):
+    sigma, u, v, w = map(_arr, (sigma, u, v, w))
+    out = np.empty_like(sigma)
+    lib().orc_levelset_advect(C.byref(P), _p(sigma), _p(u), _p(v), _p(w), dt, _p(out))
+    return out
+
+
+def reinit(P, sigma0):
+    sigma0 = _arr(sigma0)
+    out = np.empty_like(sigma0)
+    lib().orc_reinit(C.byref(P), _p(sigma0), _p(out))
+    return out
+
+
+def properties(P, sigma, t):
+    sigma = _arr(sigma)
+    outs = [np.empty_like(sigma) for _ in range(4)]
+    lib().orc_properties(C.byref(P), _p(sigma), t, *[_p(o) for o in outs])
+    return tuple(outs)   # rho, rho_flow, mu, chi
+
+
+def momentum(P, u, v, w, sigma, t_np1, dt):
+    u, v, w, sigma = map(_arr, (u, v, w, sigma))
+    us, vs, ws = np.empty_like(u), np.empty_like(v), np.empty_like(w)
+    lib().orc_momentum(C.byref(P), _p(u), _p(v), _p(w), _p(sigma), t_np1, dt, _p(us), _p(vs), _p(ws))
+    return us, vs, ws
+
+
+def face_beta(P, sigma, t_np1, dt):
+    sigma = _arr(sigma)
+    _, su, sv, sw = _shapes(P)
+    bx, by, bz = np.empty(su), np.empty(sv), np.empty(sw)
+    lib().orc_face_beta(C.byref(P), _p(sigma), t_np1, dt, _p(bx), _p(by), _p(bz))
+    return bx, by, bz
+
+
+def rhs(P, us, vs, ws, dt):
+    us, vs, ws = map(_arr, (us, vs, ws))
+    b = np.empty(_shapes(P)[0])
+    lib().orc_rhs(C.byref(P), _p(us), _p(vs), _p(ws), dt, _p(b))
+    return b
+
+
+def apply_A(nx, ny, nz, h, bx, by, bz, x):
+    bx, by, bz, x = map(_arr, (bx, by, bz, x))
+    y = np.empty_like(x)
+    lib().orc_apply_A(nx, ny, nz, h, _p(bx), _p(by), _p(bz), _p(x), _p(y))
+    return y
+
+
+def num_levels(nx, ny, nz):
+    return lib().orc_num_levels(nx, ny, nz)
+
+
+def vcycle(P, bx, by, bz, r):
+    bx, by, bz, r = map(_arr, (bx, by, bz, r))
+    z = np.empty_like(r)
+    lib().orc_vcycle(C.byref(P), _p(bx), _p(by), _p(bz), _p(r), _p(z))
+    return z
+
+
+def pcg(P, bx, by, bz, b, x0=None):
+    bx, by, bz, b = map(_arr, (bx, by, bz, b))
+    x = np.zeros_like(b) if x0 is None else _arr(x0).copy()
+    st = Stats()
+    rc = lib().orc_pcg(C.byref(P), _p(bx), _p(by), _p(bz), _p(b), _p(x), C.byref(st))
+    return x, st.as_dict(), rc
+
+
+def correct(P, us, vs, ws, p, bx, by, bz, dt):
+    us, vs, ws, p, bx, by, bz = map(_arr, (us, vs, ws, p, bx, by, bz))
+    u, v, w = np.empty_like(us), np.empty_like(vs), np.empty_like(ws)
+    lib().orc_correct(C.byref(P), _p(us), _p(vs), _p(ws), _p(p), _p(bx), _p(by), _p(bz), dt,
+                      _p(u), _p(v), _p(w))
+    return u, v, w
+
+
+def step(P, fields, dt, t_n, x0_prev=True):
+    """One time step on copies of the fields; returns (fields, stats, rc)."""
+    f = {k: _arr(fields[k]).copy() for k in ("sigma", "u", "v", "w", "p")}
+    st = Stats()
+    rc = lib().orc_step(C.byref(P), _p(f["sigma"]), _p(f["u"]), _p(f["v"]), _p(f["w"]), _p(f["p"]),
+                        dt, t_n, 1 if x0_prev else 0, C.byref(st))
+    return f, st.as_dict(), rc
+
+
+def diagnostics(P, sigma, u, v, w):
+    sigma, u, v, w = map(_arr, (sigma, u, v, w))
+    out = np.empty(4)
+    lib().orc_diagnostics(C.byref(P), _p(sigma), _p(u), _p(v), _p(w), _p(out))
+    return out   # max|div|, water volume, kinetic energy, max|u|

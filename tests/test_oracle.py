@@ -1,0 +1,549 @@
+"""Pins of the FP64 CPU oracle against closed forms, invariants, brute force
+and the paper's printed values.  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2206_07732_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+FL = json.load(open(os.path.join(GOLD, "fluids.json")))
+
+
+def flat_wl(nx=16, ny=1, nz=16, h=0.125, depth=1.0, bodies=(), **kw):
+    wl = I.workload("tiny2d", nx=nx, ny=ny, nz=nz, h=h, depth=depth, bodies=list(bodies),
+                    wave={"kind": "flat"}, **kw)
+    return wl
+
+
+def zeros(wl):
+    nx, ny, nz = wl.nx, wl.ny, wl.nz
+    return (np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx + 1)), np.zeros((nz, ny + 1, nx)),
+            np.zeros((nz + 1, ny, nx)))
+
+
+def cell_centres(wl):
+    h = wl.h
+    z, y, x = np.meshgrid((np.arange(wl.nz) + 0.5) * h, (np.arange(wl.ny) + 0.5) * h,
+                          (np.arange(wl.nx) + 0.5) * h, indexing="ij")
+    return x, y, z
+
+
+# ---------------------------------------------------------------------------
+# Heaviside / properties (eqn_Hflow, eqn_ls_flow, eqn_ls_solid)
+# ---------------------------------------------------------------------------
+def test_pure_phases_and_half_point(orc):
+    wl = flat_wl(nx=4, nz=1)
+    P = orc.params(wl)
+    eps = wl.h
+    sigma = np.array([-10.0, -eps * 1.0000001, 0.0, 10.0]).reshape(1, 1, 4)
+    rho, rfl, mu, chi = orc.properties(P, sigma, 0.0)
+    # eqn_ls_flow evaluates rho_w + (rho_a - rho_w) * 1 in air: exact to rounding
+    assert rho[0, 0, 0] == FL["rho_w"] and abs(rho[0, 0, 3] / FL["rho_a"] - 1) < 1e-13
+    assert rho[0, 0, 1] == FL["rho_w"]
+    assert rho[0, 0, 2] == FL["rho_w"] + 0.5 * (FL["rho_a"] - FL["rho_w"])
+    assert mu[0, 0, 0] == FL["mu_w"] and abs(mu[0, 0, 3] / FL["mu_a"] - 1) < 1e-13
+    assert np.all(chi == 0.0) and np.array_equal(rho, rfl)
+
+
+def test_heaviside_symmetry_and_continuity(orc):
+    wl = flat_wl(nx=64, nz=1)
+    P = orc.params(wl)
+    eps = wl.h
+    phi = np.linspace(-1.5 * eps, 1.5 * eps, 64).reshape(1, 1, 64)
+    r1 = orc.properties(P, phi, 0.0)[0]
+    r2 = orc.properties(P, -phi, 0.0)[0]
+    # H(phi) + H(-phi) = 1  =>  rho(phi) + rho(-phi) = rho_w + rho_a
+    assert np.allclose(r1 + r2, FL["rho_w"] + FL["rho_a"], rtol=0, atol=1e-12 * FL["rho_w"])
+    # continuous at +-eps (the smooth branch reaches 0 and 1 there)
+    e = np.array([eps * (1 - 1e-12), eps * (1 + 1e-12), -eps * (1 - 1e-12), -eps * (1 + 1e-12)]).reshape(1, 1, 4)
+    wl4 = flat_wl(nx=4, nz=1)
+    r = orc.properties(orc.params(wl4), e, 0.0)[0].ravel()
+    assert abs(r[0] - r[1]) < 1e-9 * FL["rho_w"] and abs(r[2] - r[3]) < 1e-9 * FL["rho_w"]
+    # monotone from water to air
+    assert np.all(np.diff(r1.ravel()) <= 0)
+
+
+def test_body_level_set_box_and_cylinder(orc):
+    # 2-D box centred on a cell centre so that psi hits 0 and -h exactly at cell centres
+    h = 0.125
+    box = I.Body(0, (4.0625, 0.0, 1.0625), (0.25, 0.0, 0.5))
+    wl = flat_wl(nx=64, nz=16, h=h, bodies=[box])
+    P = orc.params(wl)
+    sigma = -np.ones((16, 1, 64))          # all water: rho_flow = rho_w
+    rho, rfl, mu, chi = orc.properties(P, sigma, 0.0)
+    assert chi[8, 0, 32] == 1.0                      # psi = -0.25 < -eps: inside
+    assert abs(chi[8, 0, 34] - 0.5) < 1e-15          # psi = 0 on the surface
+    assert chi[8, 0, 40] == 0.0                      # outside
+    assert abs(chi[8, 0, 33] - 1.0) < 1e-15          # psi = -eps
+    assert np.array_equal(rfl, np.full_like(rfl, FL["rho_w"]))
+    # solid takes rho_s = rho_w, so rho is uniform here
+    assert np.allclose(rho, FL["rho_w"], rtol=1e-15)
+    # 3-D vertical cylinder R = 0.25, z in [0.75, 1.25], axis through a cell centre
+    cyl = I.Body(1, (1.0625, 1.0625, 0.0), (0.25, 0.75, 1.25))
+    wl3 = flat_wl(nx=16, ny=16, nz=16, h=h, bodies=[cyl])
+    chi3 = orc.properties(orc.params(wl3), -np.ones((16, 16, 16)), 0.0)[3]
+    assert chi3[8, 8, 8] == 1.0                      # on the axis, mid-height
+    assert abs(chi3[8, 8, 10] - 0.5) < 1e-15         # r = 0.25 exactly
+    assert chi3[8, 8, 12] == 0.0
+    assert chi3[2, 8, 8] == 0.0                      # below the bottom cap
+    # heave moves the body: zeta(t) = A sin(w t); at w t = pi/2 it is up by A = 2h
+    cylh = I.Body(1, (1.0625, 1.0625, 0.0), (0.25, 0.75, 1.25), heave_amp=0.25, heave_omega=1.0)
+    wl3h = flat_wl(nx=16, ny=16, nz=16, h=h, bodies=[cylh])
+    chi3h = orc.properties(orc.params(wl3h), -np.ones((16, 16, 16)), math.pi / 2)[3]
+    assert np.array_equal(chi3h[2:14], chi3[0:12])
+
+
+# ---------------------------------------------------------------------------
+# level-set advection
+# ---------------------------------------------------------------------------
+def test_advection_exact_for_linear_field(orc):
+    wl = flat_wl(nx=12, ny=10, nz=11, h=0.1)
+    P = orc.params(wl)
+    x, y, z = cell_centres(wl)
+    sigma = 0.3 * x - 0.7 * y + 1.1 * z
+    _, u, v, w = zeros(wl)
+    U, V, W = 0.8, -0.35, 0.5
+    u[:, :, 1:-1] = U
+    v[:, 1:-1, :] = V
+    w[1:-1] = W
+    dt = 0.01
+    out = orc.levelset_advect(P, sigma, u, v, w, dt)
+    exact = sigma - dt * (U * 0.3 + V * (-0.7) + W * 1.1)
+    s = (slice(2, -2),) * 3
+    assert np.max(np.abs(out[s] - exact[s])) < 1e-14
+
+
+def test_advection_conserves_total_in_closed_box(orc):
+    # discretely divergence-free field from a nodal stream function zero on the walls
+    wl = flat_wl(nx=24, nz=20, h=0.1)
+    P = orc.params(wl)
+    h = wl.h
+    rng = np.random.default_rng(0)
+    psi = np.zeros((wl.nz + 1, wl.nx + 1))
+    psi[1:-1, 1:-1] = rng.standard_normal((wl.nz - 1, wl.nx - 1)) * 0.05
+    _, u, v, w = zeros(wl)
+    u[:, 0, :] = (psi[1:, :] - psi[:-1, :]) / h
+    w[:, 0, :] = -(psi[:, 1:] - psi[:, :-1]) / h
+    div = (u[:, 0, 1:] - u[:, 0, :-1] + w[1:, 0, :] - w[:-1, 0, :]) / h
+    assert np.max(np.abs(div)) < 1e-13
+    sigma = rng.standard_normal((wl.nz, 1, wl.nx))
+    out = orc.levelset_advect(P, sigma, u, v, w, 0.02)
+    assert abs(out.sum() - sigma.sum()) < 1e-12 * np.abs(sigma).sum()
+    assert np.max(np.abs(out - sigma)) > 1e-3      # it did move
+
+
+def test_advection_is_tvd_on_a_step(orc):
+    wl = flat_wl(nx=64, nz=1, h=0.1)
+    P = orc.params(wl)
+    sigma = np.where(np.arange(64) < 20, 1.0, -1.0).reshape(1, 1, 64).astype(float)
+    _, u, v, w = zeros(wl)
+    u[:, :, 1:-1] = 1.0
+    s = sigma
+    for _ in range(40):
+        s = orc.levelset_advect(P, s, u, v, w, 0.05)        # CFL 0.5
+        assert s.max() <= 1.0 + 1e-14 and s.min() >= -1.0 - 1e-14
+    # the front moved 20 cells downstream (from i = 20 to i = 40)
+    assert s[0, 0, 36] > 0.5 and s[0, 0, 44] < -0.5
+
+
+# ---------------------------------------------------------------------------
+# reinitialisation
+# ---------------------------------------------------------------------------
+def test_reinit_planar_sdf_is_fixed_point(orc):
+    wl = flat_wl(nx=8, ny=6, nz=32, h=0.0625)
+    P = orc.params(wl)
+    _, _, z = cell_centres(wl)
+    sigma = z - 1.03
+    out = orc.reinit(P, sigma)
+    assert np.max(np.abs(out - sigma)) < 1e-14
+
+
+def test_reinit_relaxes_to_distance(orc):
+    wl = flat_wl(nx=4, nz=64, h=1.0 / 32)
+    P = orc.params(wl, reinit_iters=600)
+    _, _, z = cell_centres(wl)
+    z0 = 1.0                                         # on a face: symmetric
+    out = orc.reinit(P, 2.0 * (z - z0))
+    assert np.max(np.abs(out - (z - z0))) < 1e-6
+    # with the default 5 pseudo-steps the slope moves towards 1 and the zero stays
+    P5 = orc.params(wl)
+    out5 = orc.reinit(P5, 2.0 * (z - z0))
+    g_before = 2.0
+    g_after = np.max(np.abs(np.diff(out5[:, 0, 0]))) / wl.h
+    assert g_after < g_before
+    assert out5[31, 0, 0] < 0 < out5[32, 0, 0]
+    assert abs(out5[31, 0, 0] + out5[32, 0, 0]) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# momentum predictor
+# ---------------------------------------------------------------------------
+def test_momentum_quiescent_free_fall_and_rigid_body(orc):
+    box = I.Body(0, (1.0, 0.0, 1.0), (0.5, 0.0, 0.5))
+    wl = flat_wl(nx=16, nz=16, h=0.125, bodies=[box])
+    P = orc.params(wl)
+    _, _, z = cell_centres(wl)
+    sigma = z - 1.0
+    _, u, v, w = zeros(wl)
+    dt = 0.01
+    us, vs, ws = orc.momentum(P, u, v, w, sigma, dt, dt)
+    assert np.all(us == 0) and np.all(vs == 0)
+    g = FL["g"]
+    # pure water or pure air, away from the body: free fall over dt
+    assert abs(ws[3, 0, 14] + g * dt) < 1e-15 * g * dt + 1e-16
+    assert abs(ws[14, 0, 14] + g * dt) < 1e-14
+    # deep inside the solid (chi = 1) the implicit penalty reduces the free
+    # fall by rho/(rho + dt/kappa_p)
+    rho = FL["rho_w"]
+    held = -g * dt * rho / (rho + dt / FL["kappa_p"])
+    assert abs(ws[6, 0, 8] - held) < 1e-14 * abs(held)
+    # the bottom wall face never moves
+    assert np.all(ws[0] == 0)
+
+
+def test_momentum_advection_exact_for_linear_fields(orc):
+    wl = flat_wl(nx=16, nz=12, h=0.1, mu_w=0.0)
+    P = orc.params(wl)
+    sigma = -np.ones((12, 1, 16))
+    _, u, v, w = zeros(wl)
+    xf = np.arange(17) * wl.h
+    a = 0.7
+    u[:, 0, :] = a * xf[None, :]
+    u[:, :, 0] = 0.0
+    u[:, :, -1] = 0.0
+    dt = 1e-3
+    us, _, _ = orc.momentum(P, u, v, w, sigma, dt, dt)
+    i = slice(3, 12)                    # stencil i-2..i+2 clear of the walls
+    exact = u[:, 0, i] - dt * a * a * xf[None, i]        # u du/dx = a^2 x
+    assert np.max(np.abs(us[:, 0, i] - exact)) < 1e-14
+    # transverse advection: u = c z carried by a uniform w gives u* = u - dt W c
+    _, u, v, w = zeros(wl)
+    zc = (np.arange(12) + 0.5) * wl.h
+    c, W = 0.9, 0.4
+    u[:, 0, 1:-1] = c * zc[:, None]
+    w[1:] = W
+    us, _, _ = orc.momentum(P, u, v, w, sigma, dt, dt)
+    k = slice(2, 10)
+    exact = u[k, 0, 3:14] - dt * W * c
+    assert np.max(np.abs(us[k, 0, 3:14] - exact)) < 1e-14
+
+
+def test_momentum_viscous_normal_shear_and_transpose(orc):
+    g0 = dict(g=0.0)
+    wl = flat_wl(nx=16, nz=16, h=0.1, **g0)
+    P = orc.params(wl)
+    sigma = -np.ones((16, 1, 16))
+    mu, rho = FL["mu_w"], FL["rho_w"]
+    dt = 1e-2
+    # shear: u = c z^2  ->  div tau_x = mu u_zz = 2 c mu
+    _, u, v, w = zeros(wl)
+    zc = (np.arange(16) + 0.5) * wl.h
+    c = 3.0
+    u[:, 0, 1:-1] = c * zc[:, None] ** 2
+    us, _, _ = orc.momentum(P, u, v, w, sigma, dt, dt)
+    k, i = slice(2, 14), slice(3, 14)
+    assert np.max(np.abs(us[k, 0, i] - (u[k, 0, i] + dt * 2 * c * mu / rho))) < 1e-14
+    # normal: u = c x^2 (kept clear of the walls) -> d/dx(2 mu u_x) = 4 c mu, advection u u_x = 2 c^2 x^3
+    # transpose term: u = 0, w = s x z  ->  x-momentum gets d/dz(mu dw/dx) = mu s
+    _, u, v, w = zeros(wl)
+    s = 2.5
+    xc = (np.arange(16) + 0.5) * wl.h
+    zf = np.arange(17) * wl.h
+    w[:, 0, :] = s * zf[:, None] * xc[None, :]
+    us, _, ws = orc.momentum(P, u, v, w, sigma, dt, dt)
+    assert np.max(np.abs(us[1:-1, 0, 1:-1] - dt * mu * s / rho)) < 1e-15
+    # z-momentum of the same field: viscous part vanishes, advection w w_z = s^2 x^2 z
+    # (the columns next to the x-walls see the free-slip shear and are left out)
+    k = slice(2, 15)
+    exact = w[k, 0, 1:-1] - dt * s * s * xc[None, 1:-1] ** 2 * zf[k, None]
+    assert np.max(np.abs(ws[k, 0, 1:-1] - exact)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+def test_hydrostatic_tank_closed_form(orc):
+    box = I.Body(0, (1.0, 0.0, 1.0), (0.25, 0.0, 0.2))
+    for bodies in ([], [box]):
+        wl = flat_wl(nx=16, nz=24, h=1.0 / 12, depth=1.0, bodies=bodies)
+        P = orc.params(wl, rtol=1e-13)
+        _, _, z = cell_centres(wl)
+        f = {"sigma": z - 1.0, "u": zeros(wl)[1], "v": zeros(wl)[2], "w": zeros(wl)[3],
+             "p": np.zeros_like(z)}
+        dt = 0.01
+        out, st, rc = orc.step(P, f, dt, 0.0)
+        assert rc == 0
+        # p_c = g [rho_flow(top) h/2 + sum over z-faces above c of rho_flow_f h]
+        rfl = orc.properties(P, out["sigma"], dt)[1][:, 0, :]
+        rf_face = 0.5 * (rfl[1:] + rfl[:-1])
+        g, h, nz = FL["g"], wl.h, wl.nz
+        p_exact = np.empty_like(rfl)
+        p_exact[nz - 1] = g * rfl[nz - 1] * h / 2
+        for k in range(nz - 2, -1, -1):
+            p_exact[k] = p_exact[k + 1] + g * rf_face[k] * h
+        assert np.max(np.abs(out["p"][:, 0, :] - p_exact)) < 1e-9 * p_exact.max()
+        # bottom pressure ~ rho g depth (water) + rho_a g (air column)
+        assert abs(p_exact[0].mean() - (FL["rho_w"] * g * (1 - h / 2) + FL["rho_a"] * g * 1.0)) < 2.0
+        # the fluid stays at rest
+        for c in ("u", "v", "w"):
+            assert np.max(np.abs(out[c])) < 1e-10 * g * dt
+
+
+def _manufactured(nx, ny, nz, L=(1.0, 1.0, 1.0)):
+    """beta = 1 + 1/2 sin(pi x/Lx) sin(pi z/Lz) [* cos(pi y/Ly)^2 in 3-D],
+    p = cos(pi x/Lx) cos(pi z/(2 Lz)) [cos(pi y/Ly)]: dp/dn = 0 on the walls,
+    p = 0 on top.  Returns faces beta, rhs f = -div(beta grad p), exact p."""
+    Lx, Ly, Lz = L
+    h = Lx / nx
+    three = ny > 1
+    ax, ay, az = math.pi / Lx, math.pi / Ly, math.pi / (2 * Lz)
+    bz_ = math.pi / Lz
+
+    def beta(x, y, z):
+        b = 1 + 0.5 * np.sin(ax * x) * np.sin(bz_ * z)
+        return b * (1 + 0.5 * np.cos(ay * y) ** 2) if three else b
+
+    def grad_beta(x, y, z):
+        s = np.sin(ax * x) * np.sin(bz_ * z)
+        fy = (1 + 0.5 * np.cos(ay * y) ** 2) if three else 1.0
+        b0 = 1 + 0.5 * s
+        bx = 0.5 * ax * np.cos(ax * x) * np.sin(bz_ * z) * fy
+        bz = 0.5 * bz_ * np.sin(ax * x) * np.cos(bz_ * z) * fy
+        by = b0 * (-ay * np.cos(ay * y) * np.sin(ay * y)) if three else 0.0
+        return bx, by, bz
+
+    def p(x, y, z):
+        q = np.cos(ax * x) * np.cos(az * z)
+        return q * np.cos(ay * y) if three else q
+
+    def lap_terms(x, y, z):
+        cy = np.cos(ay * y) if three else 1.0
+        sy = np.sin(ay * y) if three else 0.0
+        px = -ax * np.sin(ax * x) * np.cos(az * z) * cy
+        pz = -az * np.cos(ax * x) * np.sin(az * z) * cy
+        py = -ay * np.cos(ax * x) * np.cos(az * z) * sy if three else 0.0
+        lap = -(ax ** 2 + az ** 2 + (ay ** 2 if three else 0.0)) * p(x, y, z)
+        bx, by, bz = grad_beta(x, y, z)
+        return beta(x, y, z) * lap + bx * px + by * py + bz * pz
+
+    xc = (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    zc = (np.arange(nz) + 0.5) * h
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    f = -lap_terms(X, Y, Z)
+    pex = p(X, Y, Z)
+    Z, Y, X = np.meshgrid(zc, yc, np.arange(nx + 1) * h, indexing="ij")
+    bx = beta(X, Y, Z)
+    bx[:, :, 0] = bx[:, :, -1] = 0.0
+    Z, Y, X = np.meshgrid(zc, np.arange(ny + 1) * h, xc, indexing="ij")
+    by = beta(X, Y, Z)
+    by[:, 0, :] = by[:, -1, :] = 0.0
+    Z, Y, X = np.meshgrid(np.arange(nz + 1) * h, yc, xc, indexing="ij")
+    bz = beta(X, Y, Z)
+    bz[0] = 0.0
+    return h, bx, by, bz, f, pex
+
+
+@pytest.mark.parametrize("three", [False, True])
+def test_manufactured_poisson_second_order(orc, three):
+    sizes = [16, 32, 64] if three else [32, 64, 128, 256]
+    errs = []
+    for n in sizes:
+        nx, ny, nz = (n, n, n) if three else (n, 1, n)
+        h, bx, by, bz, f, pex = _manufactured(nx, ny, nz)
+        wl = flat_wl(nx=nx, ny=ny, nz=nz, h=h)
+        P = orc.params(wl, rtol=1e-12, max_iters=100)
+        x, st, rc = orc.pcg(P, bx, by, bz, f)
+        assert rc == 0 and st["true_rel_resid"] <= 1e-12
+        errs.append(np.sqrt(np.mean((x - pex) ** 2)))
+    orders = [math.log2(errs[q] / errs[q + 1]) for q in range(len(errs) - 1)]
+    assert min(orders[-2:]) > 1.9, orders
+
+
+def test_divergence_identity_after_step(orc):
+    wl = I.workload("tiny3d")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    P = orc.params(wl)
+    s1 = orc.levelset_advect(P, f["sigma"], f["u"], f["v"], f["w"], dt)
+    sig = orc.reinit(P, s1)
+    us, vs, ws = orc.momentum(P, f["u"], f["v"], f["w"], sig, dt, dt)
+    bx, by, bz = orc.face_beta(P, sig, dt, dt)
+    b = orc.rhs(P, us, vs, ws, dt)
+    # any pressure: div_h u^{n+1} = -dt (b - A p) holds identically
+    p = np.random.default_rng(5).standard_normal(b.shape) * 100.0
+    u1, v1, w1 = orc.correct(P, us, vs, ws, p, bx, by, bz, dt)
+    h = wl.h
+    div = ((u1[:, :, 1:] - u1[:, :, :-1]) + (v1[:, 1:] - v1[:, :-1]) + (w1[1:] - w1[:-1])) / h
+    Ap = orc.apply_A(wl.nx, wl.ny, wl.nz, h, bx, by, bz, p)
+    assert np.max(np.abs(div + dt * (b - Ap))) < 1e-10 * np.max(np.abs(div))
+    # and after the solve the divergence is at the solver tolerance
+    p, st, rc = orc.pcg(P, bx, by, bz, b, np.zeros_like(b))
+    u1, v1, w1 = orc.correct(P, us, vs, ws, p, bx, by, bz, dt)
+    div1 = ((u1[:, :, 1:] - u1[:, :, :-1]) + (v1[:, 1:] - v1[:, :-1]) + (w1[1:] - w1[:-1])) / h
+    divs = ((us[:, :, 1:] - us[:, :, :-1]) + (vs[:, 1:] - vs[:, :-1]) + (ws[1:] - ws[:-1])) / h
+    assert np.linalg.norm(div1) <= 1.01e-10 * np.linalg.norm(divs)
+
+
+def _dense_A(orc, nx, ny, nz, h, bx, by, bz):
+    n = nx * ny * nz
+    A = np.empty((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        A[:, c] = orc.apply_A(nx, ny, nz, h, bx, by, bz, e.reshape(nz, ny, nx)).ravel()
+    return A
+
+
+@pytest.mark.parametrize("dims", [(8, 1, 4), (4, 4, 4), (6, 2, 4)])
+def test_operator_spd_and_pcg_matches_dense_solve(orc, dims):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(sum(dims))
+    f = I.random_fields(nx, ny, nz, seed=7)
+    bx = np.exp(rng.standard_normal(f["u"].shape) * 2)
+    by = np.exp(rng.standard_normal(f["v"].shape) * 2)
+    bz = np.exp(rng.standard_normal(f["w"].shape) * 2)
+    bx[:, :, 0] = bx[:, :, -1] = 0
+    by[:, 0] = by[:, -1] = 0
+    bz[0] = 0
+    h = 0.5
+    A = _dense_A(orc, nx, ny, nz, h, bx, by, bz)
+    assert np.allclose(A, A.T, rtol=0, atol=1e-14 * np.abs(A).max())
+    assert np.linalg.eigvalsh(A).min() > 0
+    # each row couples only grid neighbours, with -beta/h^2 off the diagonal
+    nnz = (np.abs(A) > 0).sum(axis=1)
+    assert nnz.max() <= 7
+    b = f["c"]
+    xd = np.linalg.solve(A, b.ravel()).reshape(b.shape)
+    wl = flat_wl(nx=nx, ny=ny, nz=nz, h=h)
+    x, st, rc = orc.pcg(orc.params(wl, rtol=1e-13, max_iters=500), bx, by, bz, b)
+    assert rc == 0
+    assert np.max(np.abs(x - xd)) < 1e-11 * np.max(np.abs(xd))
+
+
+def test_vcycle_symmetric_positive_definite(orc):
+    wl = I.workload("tiny3d")
+    f = I.make_fields(wl)
+    P = orc.params(wl)
+    bx, by, bz = orc.face_beta(P, f["sigma"], 0.0, 0.03)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(f["sigma"].shape)
+    s = rng.standard_normal(f["sigma"].shape)
+    Mr = orc.vcycle(P, bx, by, bz, r)
+    Ms = orc.vcycle(P, bx, by, bz, s)
+    lhs, rhs_ = np.sum(Mr * s), np.sum(r * Ms)
+    assert abs(lhs - rhs_) < 1e-12 * np.sqrt(np.sum(Mr * Mr) * np.sum(s * s))
+    assert np.sum(Mr * r) > 0 and np.sum(Ms * s) > 0
+    # linear: M(a r + s) = a M r + M s
+    Mc = orc.vcycle(P, bx, by, bz, 2.5 * r + s)
+    assert np.max(np.abs(Mc - (2.5 * Mr + Ms))) < 1e-10 * np.max(np.abs(Mc))
+
+
+def test_vcycle_contraction_constant_coefficient(orc):
+    n = 64
+    wl = flat_wl(nx=n, nz=n, h=1.0 / n)
+    P = orc.params(wl)
+    _, _, u, _ = I.random_fields(n, 1, n, 0).values().__iter__().__next__(), None, None, None
+    bx = np.ones((n, 1, n + 1)); bx[:, :, 0] = bx[:, :, -1] = 0
+    by = np.zeros((n, 2, n))
+    bz = np.ones((n + 1, 1, n)); bz[0] = 0
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal((n, 1, n))
+    x = np.zeros_like(b)
+    res = [np.linalg.norm(b)]
+    for _ in range(6):
+        r = b - orc.apply_A(n, 1, n, wl.h, bx, by, bz, x)
+        x = x + orc.vcycle(P, bx, by, bz, r)
+        res.append(np.linalg.norm(b - orc.apply_A(n, 1, n, wl.h, bx, by, bz, x)))
+    rate = (res[-1] / res[1]) ** (1 / 5)
+    assert rate < 0.35, rate
+
+
+def test_mixed_precision_vcycle_and_pcg(orc):
+    wl = I.workload("tiny3d")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    P64 = orc.params(wl)
+    P32 = orc.params(wl, prec=1)
+    bx, by, bz = orc.face_beta(P64, f["sigma"], dt, dt)
+    r = np.random.default_rng(4).standard_normal(f["sigma"].shape)
+    z64 = orc.vcycle(P64, bx, by, bz, r)
+    z32 = orc.vcycle(P32, bx, by, bz, r)
+    rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    assert 0 < rel < 1e-4
+    # the FP64 outer CG still meets the FP64 tolerance with the FP32 preconditioner
+    x, st, rc = orc.pcg(P32, bx, by, bz, r)
+    assert rc == 0 and st["true_rel_resid"] <= 1e-10
+
+
+def test_pcg_edge_cases(orc):
+    wl = I.workload("tiny2d")
+    f = I.make_fields(wl)
+    P = orc.params(wl, max_iters=1)
+    bx, by, bz = orc.face_beta(P, f["sigma"], 0.01, 0.01)
+    b = np.random.default_rng(2).standard_normal(f["sigma"].shape)
+    x, st, rc = orc.pcg(P, bx, by, bz, b)
+    assert rc == 1 and st["iters"] == 1 and st["rel_resid"] > 1e-10
+    x, st, rc = orc.pcg(orc.params(wl), bx, by, bz, np.zeros_like(b), np.ones_like(b))
+    assert rc == 0 and st["iters"] == 0 and np.all(x == 0)
+    # an exact initial guess takes zero iterations
+    xs, st, rc = orc.pcg(orc.params(wl, rtol=1e-12), bx, by, bz, b)
+    x, st2, rc = orc.pcg(orc.params(wl, rtol=1e-10), bx, by, bz, b, xs)
+    assert rc == 0 and st2["iters"] == 0
+
+
+# ---------------------------------------------------------------------------
+# whole step
+# ---------------------------------------------------------------------------
+def test_standing_wave_follows_dispersion_relation(orc):
+    # two-fluid linear theory for a standing wave kappa = 10 pi / 8 in 1 m water
+    # under 1 m air (eq_dispersion_relation with the air layer's inertia)
+    kap = 10 * math.pi / 8
+    nx, nz = 128, 32
+    wl = I.workload("tiny2d", nx=nx, nz=nz, h=8.0 / nx, bodies=[],
+                    wave={"kind": "standing", "a": 0.01, "kappa": kap})
+    f = I.make_fields(wl)
+    rw, ra, g = wl.rho_w, wl.rho_a, wl.g
+    om = math.sqrt(g * kap * (rw - ra) / (rw / math.tanh(kap) + ra / math.tanh(kap)))
+    T = 2 * math.pi / om
+    dt = T / 64
+    P = orc.params(wl)
+    zc = (np.arange(nz) + 0.5) * wl.h
+
+    def eta(sig):
+        col = sig[:, 0, 0]
+        k = np.where((col[:-1] < 0) & (col[1:] >= 0))[0][0]
+        return zc[k] - col[k] * (zc[k + 1] - zc[k]) / (col[k + 1] - col[k]) - 1.0
+
+    ts, es, t = [0.0], [eta(f["sigma"])], 0.0
+    for _ in range(int(2.6 * T / dt)):
+        f, st, rc = orc.step(P, f, dt, t)
+        assert rc == 0
+        t += dt
+        ts.append(t)
+        es.append(eta(f["sigma"]))
+    ts, es = np.array(ts), np.array(es)
+    cross = [ts[q] - es[q] * (ts[q + 1] - ts[q]) / (es[q + 1] - es[q])
+             for q in range(len(es) - 1) if es[q] * es[q + 1] < 0]
+    Tm = 2 * np.mean(np.diff(cross))
+    assert abs(Tm / T - 1) < 0.03, (Tm, T)
+
+
+def test_c1_volume_and_convergence(orc):
+    wl = I.workload("c1")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    P = orc.params(wl)
+    v0 = orc.diagnostics(P, f["sigma"], f["u"], f["v"], f["w"])[1]
+    t = 0.0
+    for _ in range(wl.steps):
+        f, st, rc = orc.step(P, f, dt, t)
+        t += dt
+        assert rc == 0 and st["true_rel_resid"] <= 1e-10
+    d = orc.diagnostics(P, f["sigma"], f["u"], f["v"], f["w"])
+    assert abs(d[1] - v0) / v0 < 1e-3
+    assert d[0] < 1e-7                       # max |div u| after projection
