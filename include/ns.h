@@ -1,0 +1,192 @@
+/* ns.h - C ABI of the MI355X (gfx950) library for one time step of the
+ * level-set, Brinkman-penalised, two-phase (water/air) incompressible
+ * Navier-Stokes solver of arXiv 2206.07732 on a uniform staggered grid.
+ *
+ * The step (Sec. "Solution methodology", one fixed-point cycle per step as in
+ * Sec. "Time stepping scheme") is
+ *   1. levelset_advect_reinit: sigma^n -> sigma^{n+1}           (Sec. "Level set
+ *      advection"; reinitialisation of Sec. "Interface tracking")
+ *   2. momentum_step: rho, mu, chi at t^{n+1} from sigma^{n+1} and the body
+ *      level set psi (eqn_ls_flow, eqn_ls_solid, eqn_Hflow, eqn_Hbody), then
+ *      the predictor u* of eqn_c_discrete_momentum with the Brinkman force
+ *      eqn_bp_discrete implicit and gravity on rho^flow
+ *   3. projection_solve: -div(beta grad p) = -div(u*)/dt so that the
+ *      corrected velocity meets eqn_c_discrete_continuity, solved by flexible
+ *      CG preconditioned with a geometric multigrid V(2,2) cycle (red-black
+ *      Gauss-Seidel smoother), in FP64 or with the V-cycle in FP32.
+ *
+ * Grid (Sec. "Spatial discretization"): nx*ny*nz cells of size h, cell
+ * (i,j,k) centred at ((i+1/2)h, (j+1/2)h, (k+1/2)h); gravity along -z; a 2-D
+ * tank in the (x,z) plane is ny == 1.  Arrays are x-fastest, FP64:
+ *   cell  a[i + nx*(j + ny*k)]                    nx*ny*nz
+ *   u     u[i + (nx+1)*(j + ny*k)]  x = i h       (nx+1)*ny*nz
+ *   v     v[i + nx*(j + (ny+1)*k)]  y = j h       nx*(ny+1)*nz
+ *   w     w[i + nx*(j + ny*k)]      z = k h       nx*ny*(nz+1)
+ * Boundaries: x, y and bottom are free-slip walls (their normal faces stay
+ * 0); the top (z = nz h) is open with p = 0 on the boundary face.
+ *
+ * Memory and streams.  Every array pointer is a DEVICE pointer owned by the
+ * caller.  ns_init borrows the field arrays and the workspace for the life of
+ * the context; the library never allocates device memory (it allocates only
+ * a small host context and a few bytes of pinned host memory for scalar
+ * read-back).  All device work is enqueued on the stream given to ns_init;
+ * calls that return solver statistics or diagnostics synchronise that stream.
+ * A context must not be used from two host threads at once.
+ *
+ * Errors.  Every call returns an ns_status and never aborts the process.
+ * ns_last_error gives a message for the last failing call on a context.
+ */
+#ifndef NS_H
+#define NS_H
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NS_OK = 0,
+  NS_EINVAL = -1,   /* bad argument: sizes, null or misaligned pointer, too small workspace */
+  NS_ENOCONV = -2,  /* projection hit max_iters before rtol; u and p hold the last iterate */
+  NS_ENAN = -3,     /* a non-finite value appeared in the solve */
+  NS_EHIP = -4,     /* a HIP runtime call failed */
+  NS_ESTATE = -5    /* call out of order (e.g. projection before momentum) */
+} ns_status;
+
+typedef enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 } ns_prec;   /* V-cycle precision   */
+typedef enum { NS_X0_ZERO = 0, NS_X0_PREV = 1 } ns_x0;           /* projection guess    */
+
+/* A rigid body given by an analytic level set psi (negative inside), built
+ * from primitive distance functions with min/max (Sec. "Interface tracking":
+ * psi is reset directly from the geometry each step).  Prescribed heave
+ * zeta(t) = A sin(omega t + phase) shifts it along z; its velocity
+ * u_b = dzeta/dt e_z (eq_ub_velocity restricted to heave). */
+typedef struct {
+  int kind;           /* 0: box in the (x,z) plane, psi = max(|x-xc|-a, |z-zc|-b)
+                         1: vertical cylinder, psi = max(r - R, z_bot - z, z - z_top) */
+  double c[3];        /* kind 0: (xc, unused, zc); kind 1: (xc, yc, unused)            */
+  double half[3];     /* kind 0: (a, unused, b);  kind 1: (R, z_bot, z_top)            */
+  double heave_amp, heave_omega, heave_phase;
+} ns_body;
+
+typedef struct {
+  int nx, ny, nz;              /* cells; ny == 1 for a 2-D (x,z) tank; each >= 1      */
+  double h;                    /* uniform spacing (m), > 0                           */
+  double rho_w, mu_w;          /* water (liquid) density and viscosity              */
+  double rho_a, mu_a;          /* air (gas)                                         */
+  double rho_s, mu_s;          /* solid                                             */
+  double g;                    /* gravity magnitude, acting along -z                */
+  double n_cells;              /* Heaviside half-width in cells (eqn_Hflow)         */
+  double inv_kappa_p;          /* 1/kappa_p of eqn_brinkman_force                   */
+  double proj_penalty_weight;  /* w in beta = 1/(rho_f + w dt chi_f/kappa_p)        */
+  int n_bodies;                /* 0..4                                              */
+  ns_body body[4];
+  int reinit_iters;            /* pseudo-time steps of the reinitialisation         */
+  double reinit_dtau_over_h;   /* pseudo-time step / h (<= 1/3 in 3-D)              */
+  int nu_pre, nu_post;         /* red-black sweep pairs before / after coarse grid  */
+  int coarse_sweeps;           /* sweep pairs each way on the coarsest level        */
+  int max_iters;               /* CG iteration cap                                  */
+  double rtol;                 /* stop when ||b - A p||_2 <= rtol ||b||_2           */
+  int prec;                    /* ns_prec                                           */
+  int x0;                      /* ns_x0                                             */
+} ns_params;
+
+/* The caller's state arrays (device, FP64, layouts above); read and written
+ * in place.  p holds the full pressure p^{n+1/2}; on entry to a step it is the
+ * previous step's pressure, used as the initial guess when x0 = NS_X0_PREV. */
+typedef struct {
+  double* sigma;
+  double* u;
+  double* v;
+  double* w;
+  double* p;
+} ns_fields;
+
+typedef struct {
+  int iters;               /* CG iterations of the last projection                    */
+  int converged;           /* 1 if the true residual met rtol                         */
+  double rel_resid0;       /* ||b - A x0|| / ||b||                                    */
+  double rel_resid;        /* last recursive residual / ||b||                         */
+  double true_rel_resid;   /* ||b - A p|| / ||b|| recomputed at exit                  */
+  double ms;               /* wall time of the call, stream-synchronised (ms)         */
+} ns_stats;
+
+/* Internal arrays a caller may inspect or fill through ns_buffer (device
+ * pointers into the workspace; element counts as listed). */
+typedef enum {
+  NS_BUF_US = 0,    /* u* (predictor), u-face count, FP64      */
+  NS_BUF_VS = 1,    /* v*                                      */
+  NS_BUF_WS = 2,    /* w*                                      */
+  NS_BUF_BX = 3,    /* beta on x faces (level 0), FP64        */
+  NS_BUF_BY = 4,
+  NS_BUF_BZ = 5,
+  NS_BUF_RHS = 6,   /* b = -div(u*)/dt, cells, FP64            */
+  NS_BUF_RHO = 7,   /* rho at cell centres (t^{n+1}), FP64     */
+  NS_BUF_MU = 8,
+  NS_BUF_CHI = 9,
+  NS_BUF_RHOFLOW = 10,
+  NS_BUF_COUNT = 11
+} ns_buffer_id;
+
+typedef struct ns_ctx ns_ctx;
+
+/* Bytes of device workspace ns_init needs for these parameters (0 if the
+ * parameters are invalid). */
+size_t ns_workspace_bytes(const ns_params* params);
+
+/* Validate params, carve the workspace (device, >= ns_workspace_bytes,
+ * 256-byte aligned) and bind the fields.  hip_stream is a hipStream_t (NULL:
+ * the default stream).  On success *out owns a new context. */
+ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, size_t ws_bytes,
+                  void* hip_stream, ns_ctx** out);
+
+/* Step 1: sigma^n -> sigma^{n+1} in place (advection by u^n over dt, then
+ * reinit_iters relaxation steps). */
+ns_status levelset_advect_reinit(ns_ctx* ctx, double dt);
+
+/* Step 2: properties at t_np1 from the current sigma and the bodies, then
+ * the predictor u* (internal buffer NS_BUF_US/VS/WS) and the projection
+ * coefficients beta (NS_BUF_BX/BY/BZ) from u^n. */
+ns_status momentum_step(ns_ctx* ctx, double dt, double t_np1);
+
+/* Step 3: b = -div(u*)/dt, solve A p = b (guess from params.x0), then
+ * u^{n+1} = u* - dt beta grad p into the fields.  stats may be NULL.
+ * Returns NS_ENOCONV if max_iters was reached before rtol. */
+ns_status projection_solve(ns_ctx* ctx, double dt, ns_stats* stats);
+
+/* Steps 1-3 in order for t^n -> t^n + dt. */
+ns_status ns_step(ns_ctx* ctx, double dt, double t_n, ns_stats* stats);
+
+/* Solve A p = b with the beta and b currently in NS_BUF_BX/BY/BZ and
+ * NS_BUF_RHS (caller-filled or from momentum_step/projection), p = fields.p
+ * holding the initial guess; no velocity correction. */
+ns_status ns_pcg_solve(ns_ctx* ctx, ns_stats* stats);
+
+/* y = A x with the current level-0 beta (x, y: device, cells). */
+ns_status ns_apply_A(ns_ctx* ctx, const double* x, double* y);
+
+/* z = M r: one V-cycle of the current hierarchy (rebuilt from the level-0
+ * beta) in the precision of params.prec (r, z: device, cells). */
+ns_status ns_vcycle(ns_ctx* ctx, const double* r, double* z);
+
+/* Device pointer and element count of an internal array. */
+ns_status ns_buffer(ns_ctx* ctx, int which, void** dev_ptr, size_t* count);
+
+/* out[0] max|div_h u|, out[1] water volume sum (1 - H(sigma)) h^d,
+ * out[2] kinetic energy 1/2 sum rho^flow |u_c|^2 h^d, out[3] max|u_face|.
+ * out is host memory; synchronises the stream. */
+ns_status ns_diagnostics(ns_ctx* ctx, double out[4]);
+
+/* Number of multigrid levels for these sizes. */
+int ns_num_levels(int nx, int ny, int nz);
+
+const char* ns_last_error(ns_ctx* ctx);
+
+/* Release the context (host memory only; the caller's device memory is
+ * untouched).  NULL is accepted. */
+void ns_destroy(ns_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,613 @@
+// C ABI of the gfx950 library (declared in include/ns.h): context and
+// workspace management, the V-cycle schedule and the flexible
+// preconditioned CG driver.  Every arithmetic step runs in the kernels of
+// ns_grid.hip and ns_mg.hip; this file only sequences launches on the
+// caller's stream and reads back the one residual scalar per CG iteration
+// that the stopping test needs.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ns_internal.h"
+
+using namespace nsk;
+
+struct ns_ctx {
+  ns_params P;
+  ns_fields F;
+  Phys phys;
+  hipStream_t st;
+  size_t nc, nu, nv, nw;
+  // workspace views
+  double *us, *vs, *ws;
+  double *sig_a, *sig_b;
+  double *rho, *rfl, *mu, *chi;
+  double *b, *r, *z, *zn, *d, *q;
+  double *partials;
+  double *scal;
+  int nparts;
+  int L;
+  Level lev[32];
+  double* host;   // pinned host scalars
+  bool have_beta;
+  char err[512];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carve {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+ns_status fail(ns_ctx* X, ns_status s, const char* fmt, ...) {
+  if (X) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(X->err, sizeof(X->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+#define HIPCHK(X, call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail((X), NS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int count_levels(int nx, int ny, int nz) {
+  int n[3] = {nx, ny, nz};
+  bool act[3] = {nx > 1, ny > 1, nz > 1};
+  int L = 1;
+  while (L < 30) {
+    bool ok = true;
+    for (int d = 0; d < 3; ++d)
+      if (act[d] && (n[d] < 2 || (n[d] & 1))) ok = false;
+    if (!ok) break;
+    for (int d = 0; d < 3; ++d)
+      if (act[d]) n[d] /= 2;
+    ++L;
+  }
+  return L;
+}
+
+bool valid_params(const ns_params* P, char* why, size_t nwhy) {
+  if (!P) return snprintf(why, nwhy, "params is NULL"), false;
+  if (P->nx < 2 || P->ny < 1 || P->nz < 2)
+    return snprintf(why, nwhy, "grid %dx%dx%d: need nx >= 2, ny >= 1, nz >= 2", P->nx, P->ny, P->nz), false;
+  if ((double)P->nx * P->ny * P->nz > 2.0e9) return snprintf(why, nwhy, "grid too large"), false;
+  if (!(P->h > 0.0)) return snprintf(why, nwhy, "h must be > 0"), false;
+  if (P->n_bodies < 0 || P->n_bodies > 4) return snprintf(why, nwhy, "n_bodies must be 0..4"), false;
+  if (!(P->rho_w > 0 && P->rho_a > 0 && P->rho_s > 0))
+    return snprintf(why, nwhy, "densities must be > 0"), false;
+  if (!(P->n_cells > 0.0)) return snprintf(why, nwhy, "n_cells must be > 0"), false;
+  if (P->reinit_iters < 0 || P->nu_pre < 0 || P->nu_post < 0 || P->coarse_sweeps < 0 || P->max_iters < 0)
+    return snprintf(why, nwhy, "iteration counts must be >= 0"), false;
+  if (P->prec != NS_PREC_FP64 && P->prec != NS_PREC_MIXED) return snprintf(why, nwhy, "bad prec"), false;
+  if (P->x0 != NS_X0_ZERO && P->x0 != NS_X0_PREV) return snprintf(why, nwhy, "bad x0"), false;
+  for (int m = 0; m < P->n_bodies; ++m)
+    if (P->body[m].kind != 0 && P->body[m].kind != 1) return snprintf(why, nwhy, "bad body kind"), false;
+  return true;
+}
+
+// lay out every internal array; with ctx == nullptr only the size is computed
+size_t carve(const ns_params* P, ns_ctx* X, char* base) {
+  Carve cv{base, 0};
+  const size_t nc = (size_t)P->nx * P->ny * P->nz;
+  const size_t nu = (size_t)(P->nx + 1) * P->ny * P->nz;
+  const size_t nv = (size_t)P->nx * (P->ny + 1) * P->nz;
+  const size_t nw = (size_t)P->nx * P->ny * (P->nz + 1);
+  Dims n0{P->nx, P->ny, P->nz};
+  const int nparts = std::max(cg_blocks(n0), 1);
+  double* us = cv.take<double>(nu);
+  double* vs = cv.take<double>(nv);
+  double* ws = cv.take<double>(nw);
+  double* sa = cv.take<double>(nc);
+  double* sb = cv.take<double>(nc);
+  double* rho = cv.take<double>(nc);
+  double* rfl = cv.take<double>(nc);
+  double* mu = cv.take<double>(nc);
+  double* chi = cv.take<double>(nc);
+  double* b = cv.take<double>(nc);
+  double* r = cv.take<double>(nc);
+  double* z = cv.take<double>(nc);
+  double* zn = cv.take<double>(nc);
+  double* d = cv.take<double>(nc);
+  double* q = cv.take<double>(nc);
+  double* part = cv.take<double>((size_t)4 * nparts);
+  double* scal = cv.take<double>(S_COUNT);
+  const int L = count_levels(P->nx, P->ny, P->nz);
+  Level lev[32];
+  bool act[3] = {P->nx > 1, P->ny > 1, P->nz > 1};
+  for (int l = 0; l < L; ++l) {
+    Level& V = lev[l];
+    if (l == 0) {
+      V.n = n0;
+      V.h = P->h;
+    } else {
+      const Level& F = lev[l - 1];
+      V.n = Dims{F.n.nx / F.f[0], F.n.ny / F.f[1], F.n.nz / F.f[2]};
+      V.h = 2.0 * F.h;
+    }
+    for (int dd = 0; dd < 3; ++dd) V.f[dd] = act[dd] ? 2 : 1;
+    const size_t c = (size_t)V.n.nx * V.n.ny * V.n.nz;
+    const size_t fu = (size_t)(V.n.nx + 1) * V.n.ny * V.n.nz;
+    const size_t fv = (size_t)V.n.nx * (V.n.ny + 1) * V.n.nz;
+    const size_t fw = (size_t)V.n.nx * V.n.ny * (V.n.nz + 1);
+    V.bxf = cv.take<float>(fu);
+    V.byf = cv.take<float>(fv);
+    V.bzf = cv.take<float>(fw);
+    V.bf = cv.take<float>(c);
+    V.ef = cv.take<float>(c);
+    if (l == 0) {
+      V.bx = V.by = V.bz = nullptr;   // level-0 FP64 beta lives in its own arrays below
+      V.b = V.e = nullptr;            // and its b, e alias CG vectors
+    } else {
+      V.bx = cv.take<double>(fu);
+      V.by = cv.take<double>(fv);
+      V.bz = cv.take<double>(fw);
+      V.b = cv.take<double>(c);
+      V.e = cv.take<double>(c);
+    }
+  }
+  double* bx0 = cv.take<double>(nu);
+  double* by0 = cv.take<double>(nv);
+  double* bz0 = cv.take<double>(nw);
+  if (X) {
+    X->nc = nc;
+    X->nu = nu;
+    X->nv = nv;
+    X->nw = nw;
+    X->us = us;
+    X->vs = vs;
+    X->ws = ws;
+    X->sig_a = sa;
+    X->sig_b = sb;
+    X->rho = rho;
+    X->rfl = rfl;
+    X->mu = mu;
+    X->chi = chi;
+    X->b = b;
+    X->r = r;
+    X->z = z;
+    X->zn = zn;
+    X->d = d;
+    X->q = q;
+    X->partials = part;
+    X->scal = scal;
+    X->nparts = nparts;
+    X->L = L;
+    for (int l = 0; l < L; ++l) X->lev[l] = lev[l];
+    X->lev[0].bx = bx0;
+    X->lev[0].by = by0;
+    X->lev[0].bz = bz0;
+  }
+  return cv.off + kAlign;
+}
+
+Phys make_phys(const ns_params& P) {
+  Phys ph{};
+  ph.n = Dims{P.nx, P.ny, P.nz};
+  ph.h = P.h;
+  ph.rho_w = P.rho_w;
+  ph.mu_w = P.mu_w;
+  ph.rho_a = P.rho_a;
+  ph.mu_a = P.mu_a;
+  ph.rho_s = P.rho_s;
+  ph.mu_s = P.mu_s;
+  ph.g = P.g;
+  ph.eps = P.n_cells * P.h;
+  ph.inv_kp = P.inv_kappa_p;
+  ph.pen_w = P.proj_penalty_weight;
+  ph.nb = P.n_bodies;
+  for (int m = 0; m < P.n_bodies; ++m) {
+    const ns_body& B = P.body[m];
+    ph.body[m] = BodyK{B.kind, B.c[0], B.c[1], B.c[2], B.half[0], B.half[1], B.half[2],
+                       B.heave_amp, B.heave_omega, B.heave_phase};
+  }
+  return ph;
+}
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+struct LV;
+template <>
+struct LV<double> {
+  static double* bx(const Level& L) { return L.bx; }
+  static double* by(const Level& L) { return L.by; }
+  static double* bz(const Level& L) { return L.bz; }
+  static double* b(const Level& L) { return L.b; }
+  static double* e(const Level& L) { return L.e; }
+};
+template <>
+struct LV<float> {
+  static float* bx(const Level& L) { return L.bxf; }
+  static float* by(const Level& L) { return L.byf; }
+  static float* bz(const Level& L) { return L.bzf; }
+  static float* b(const Level& L) { return L.bf; }
+  static float* e(const Level& L) { return L.ef; }
+};
+
+// coarse coefficients of every level from level 0, in precision T
+template <typename T>
+void build_hierarchy(ns_ctx* X) {
+  for (int l = 1; l < X->L; ++l) {
+    const Level& F = X->lev[l - 1];
+    const Level& C = X->lev[l];
+    launch_coarsen_beta<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
+                           LV<T>::bz(C), X->st);
+  }
+}
+
+// e_l = V(l, b_l); level 0 uses the given b0, e0
+template <typename T>
+void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
+  const ns_params& P = X->P;
+  const Level& L = X->lev[l];
+  const T* b = (l == 0) ? b0 : LV<T>::b(L);
+  T* e = (l == 0) ? e0 : LV<T>::e(L);
+  const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
+  hipStream_t st = X->st;
+  if (l == X->L - 1) {
+    launch_coarse_solve<T>(L, bx, by, bz, b, e, P.coarse_sweeps, st);
+    return;
+  }
+  if (P.nu_pre > 0) {
+    launch_gs<T>(L, bx, by, bz, b, e, 0, 1, st);
+    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st);
+    for (int s = 1; s < P.nu_pre; ++s) {
+      launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st);
+    }
+  } else {
+    launch_fill<T>(e, (size_t)L.n.nx * L.n.ny * L.n.nz, st);
+  }
+  const Level& C = X->lev[l + 1];
+  launch_resid_restrict<T>(L, bx, by, bz, b, e, C, LV<T>::b(C), st);
+  vcycle<T>(X, l + 1, nullptr, nullptr);
+  launch_prolong<T>(L, e, C, LV<T>::e(C), st);
+  for (int s = 0; s < P.nu_post; ++s) {
+    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st);
+    launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st);
+  }
+}
+
+// z = M r
+void precond(ns_ctx* X, const double* r, double* z) {
+  if (X->P.prec == NS_PREC_FP64) {
+    vcycle<double>(X, 0, r, z);
+  } else {
+    Level& L0 = X->lev[0];
+    launch_d2f(r, L0.bf, X->nc, X->st);
+    vcycle<float>(X, 0, L0.bf, L0.ef);
+    launch_f2d(L0.ef, z, X->nc, X->st);
+  }
+}
+
+void prepare_hierarchy(ns_ctx* X) {
+  if (X->P.prec == NS_PREC_FP64)
+    build_hierarchy<double>(X);
+  else
+    build_hierarchy<float>(X);
+}
+
+ns_status read_scal(ns_ctx* X) {
+  HIPCHK(X, hipMemcpyAsync(X->host, X->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, X->st));
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  return NS_OK;
+}
+
+// flexible PCG on A p = b with x = fields.p as the initial guess
+ns_status pcg(ns_ctx* X, ns_stats* stats) {
+  const ns_params& P = X->P;
+  const Dims n = X->lev[0].n;
+  const double h = P.h;
+  const Level& L0 = X->lev[0];
+  hipStream_t st = X->st;
+  double* x = X->F.p;
+  const int np = X->nparts;
+  ns_stats S{};
+  prepare_hierarchy(X);
+  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, X->partials, st);
+  launch_finalize(X->partials, np, FIN_RESID0, X->scal, st);
+  ns_status s = read_scal(X);
+  if (s != NS_OK) return s;
+  const double bb = X->host[S_BB];
+  double rr = X->host[S_RR];
+  if (!std::isfinite(bb) || !std::isfinite(rr)) return fail(X, NS_ENAN, "non-finite right-hand side or guess");
+  if (bb == 0.0) {
+    launch_fill<double>(x, X->nc, st);
+    S.converged = 1;
+    if (stats) *stats = S;
+    return NS_OK;
+  }
+  const double bnorm = std::sqrt(bb);
+  const double tol2 = P.rtol * P.rtol * bb;
+  S.rel_resid0 = S.rel_resid = std::sqrt(rr) / bnorm;
+  bool conv = rr <= tol2;
+  int it = 0;
+  double* z = X->z;
+  double* zn = X->zn;
+  if (!conv) {
+    precond(X, X->r, z);
+    launch_cg_dir(n, X->scal, z, X->d, 1, st);
+    launch_dot1(n, X->r, z, X->partials, st);
+    launch_finalize(X->partials, np, FIN_RHO, X->scal, st);
+    while (it < P.max_iters) {
+      launch_spmv_dot(n, h, L0.bx, L0.by, L0.bz, X->d, X->q, X->partials, st);
+      launch_finalize(X->partials, np, FIN_ALPHA, X->scal, st);
+      launch_cg_update(n, X->scal, X->d, X->q, x, X->r, X->partials, st);
+      launch_finalize(X->partials, np, FIN_RR, X->scal, st);
+      ++it;
+      if ((s = read_scal(X)) != NS_OK) return s;
+      rr = X->host[S_RR];
+      if (!std::isfinite(rr)) {
+        S.iters = it;
+        if (stats) *stats = S;
+        return fail(X, NS_ENAN, "non-finite residual at CG iteration %d", it);
+      }
+      S.rel_resid = std::sqrt(rr) / bnorm;
+      if (rr <= tol2) {
+        // confirm on the true residual; restart from it when it fails
+        launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, X->partials, st);
+        launch_finalize(X->partials, np, FIN_RESID0, X->scal, st);
+        if ((s = read_scal(X)) != NS_OK) return s;
+        rr = X->host[S_RR];
+        S.rel_resid = std::sqrt(rr) / bnorm;
+        if (rr <= tol2) {
+          conv = true;
+          break;
+        }
+        precond(X, X->r, z);
+        launch_cg_dir(n, X->scal, z, X->d, 1, st);
+        launch_dot1(n, X->r, z, X->partials, st);
+        launch_finalize(X->partials, np, FIN_RHO, X->scal, st);
+        continue;
+      }
+      precond(X, X->r, zn);
+      launch_dots2(n, X->r, zn, z, X->partials, st);
+      launch_finalize(X->partials, np, FIN_BETA, X->scal, st);
+      launch_cg_dir(n, X->scal, zn, X->d, 0, st);
+      std::swap(z, zn);
+    }
+  }
+  // true residual at exit (into q, leaving r as the recursion left it)
+  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, X->partials, st);
+  launch_finalize(X->partials, np, FIN_TRR, X->scal, st);
+  if ((s = read_scal(X)) != NS_OK) return s;
+  S.iters = it;
+  S.true_rel_resid = std::sqrt(X->host[S_TRR]) / bnorm;
+  S.converged = S.true_rel_resid <= P.rtol ? 1 : 0;
+  if (stats) *stats = S;
+  if (!std::isfinite(S.true_rel_resid)) return fail(X, NS_ENAN, "non-finite final residual");
+  if (!conv) return fail(X, NS_ENOCONV, "CG reached max_iters=%d at rel resid %.3e", P.max_iters, S.rel_resid);
+  return NS_OK;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+bool aligned8(const void* p) { return p && ((uintptr_t)p & 7) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int ns_num_levels(int nx, int ny, int nz) { return count_levels(nx, ny, nz); }
+
+size_t ns_workspace_bytes(const ns_params* params) {
+  char why[256];
+  if (!valid_params(params, why, sizeof(why))) return 0;
+  return carve(params, nullptr, nullptr);
+}
+
+ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, size_t ws_bytes,
+                  void* hip_stream, ns_ctx** out) {
+  if (!out) return NS_EINVAL;
+  *out = nullptr;
+  ns_ctx* X = new (std::nothrow) ns_ctx();
+  if (!X) return NS_EINVAL;
+  char why[256];
+  if (!valid_params(params, why, sizeof(why))) {
+    delete X;
+    return NS_EINVAL;
+  }
+  if (!aligned8(fields.sigma) || !aligned8(fields.u) || !aligned8(fields.v) || !aligned8(fields.w) ||
+      !aligned8(fields.p) || !workspace || ((uintptr_t)workspace % kAlign) != 0) {
+    delete X;
+    return NS_EINVAL;
+  }
+  const size_t need = carve(params, nullptr, nullptr);
+  if (ws_bytes < need) {
+    delete X;
+    return NS_EINVAL;
+  }
+  X->P = *params;
+  X->F = fields;
+  X->st = (hipStream_t)hip_stream;
+  X->phys = make_phys(*params);
+  carve(params, X, (char*)workspace);
+  if (hipHostMalloc((void**)&X->host, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete X;
+    return NS_EHIP;
+  }
+  X->have_beta = false;
+  launch_fill<double>(X->scal, S_COUNT, X->st);
+  *out = X;
+  return NS_OK;
+}
+
+void ns_destroy(ns_ctx* X) {
+  if (!X) return;
+  if (X->host) (void)hipHostFree(X->host);
+  delete X;
+}
+
+const char* ns_last_error(ns_ctx* X) { return X ? X->err : "null context"; }
+
+ns_status levelset_advect_reinit(ns_ctx* X, double dt) {
+  if (!X) return NS_EINVAL;
+  if (!(dt > 0.0)) return fail(X, NS_EINVAL, "dt must be > 0");
+  const Phys& ph = X->phys;
+  hipStream_t st = X->st;
+  launch_advect(ph, X->F.sigma, X->F.u, X->F.v, X->F.w, dt, X->sig_a, st);
+  const int nr = X->P.reinit_iters;
+  const double dtau = X->P.reinit_dtau_over_h * X->P.h;
+  if (nr == 0) {
+    launch_copy(X->sig_a, X->F.sigma, X->nc, st);
+  } else {
+    // sig_a keeps sigma0 (for the sign); ping-pong between the field and
+    // sig_b so that the last pseudo-step lands in the field
+    const double* cur = X->sig_a;
+    for (int it = 0; it < nr; ++it) {
+      double* dst = ((nr - 1 - it) % 2 == 0) ? X->F.sigma : X->sig_b;
+      launch_reinit(ph, X->sig_a, cur, dst, dtau, st);
+      cur = dst;
+    }
+  }
+  HIPCHK(X, hipGetLastError());
+  return NS_OK;
+}
+
+ns_status momentum_step(ns_ctx* X, double dt, double t_np1) {
+  if (!X) return NS_EINVAL;
+  if (!(dt > 0.0)) return fail(X, NS_EINVAL, "dt must be > 0");
+  const Phys& ph = X->phys;
+  hipStream_t st = X->st;
+  launch_props(ph, X->F.sigma, t_np1, X->rho, X->rfl, X->mu, X->chi, st);
+  Level& L0 = X->lev[0];
+  launch_momentum(ph, X->F.u, X->F.v, X->F.w, X->rho, X->rfl, X->mu, X->chi, dt, t_np1, X->us, X->vs,
+                  X->ws, L0.bx, L0.by, L0.bz, L0.bxf, L0.byf, L0.bzf, st);
+  HIPCHK(X, hipGetLastError());
+  X->have_beta = true;
+  return NS_OK;
+}
+
+ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
+  if (!X) return NS_EINVAL;
+  if (!(dt > 0.0)) return fail(X, NS_EINVAL, "dt must be > 0");
+  if (!X->have_beta) return fail(X, NS_ESTATE, "projection_solve before momentum_step");
+  const double t0 = now_ms();
+  const Phys& ph = X->phys;
+  hipStream_t st = X->st;
+  launch_rhs(ph, X->us, X->vs, X->ws, dt, X->b, st);
+  if (X->P.x0 == NS_X0_ZERO) launch_fill<double>(X->F.p, X->nc, st);
+  ns_stats S{};
+  ns_status s = pcg(X, &S);
+  if (s != NS_OK && s != NS_ENOCONV) {
+    if (stats) *stats = S;
+    return s;
+  }
+  const Level& L0 = X->lev[0];
+  launch_correct(ph, X->us, X->vs, X->ws, X->F.p, L0.bx, L0.by, L0.bz, dt, X->F.u, X->F.v, X->F.w, st);
+  HIPCHK(X, hipGetLastError());
+  HIPCHK(X, hipStreamSynchronize(st));
+  S.ms = now_ms() - t0;
+  if (stats) *stats = S;
+  return s;
+}
+
+ns_status ns_step(ns_ctx* X, double dt, double t_n, ns_stats* stats) {
+  if (!X) return NS_EINVAL;
+  const double t0 = now_ms();
+  ns_status s = levelset_advect_reinit(X, dt);
+  if (s != NS_OK) return s;
+  if ((s = momentum_step(X, dt, t_n + dt)) != NS_OK) return s;
+  ns_stats S{};
+  s = projection_solve(X, dt, &S);
+  S.ms = now_ms() - t0;
+  if (stats) *stats = S;
+  return s;
+}
+
+ns_status ns_pcg_solve(ns_ctx* X, ns_stats* stats) {
+  if (!X) return NS_EINVAL;
+  const double t0 = now_ms();
+  // the FP32 level-0 copy follows the (possibly caller-written) FP64 beta
+  Level& L0 = X->lev[0];
+  launch_d2f(L0.bx, L0.bxf, X->nu, X->st);
+  launch_d2f(L0.by, L0.byf, X->nv, X->st);
+  launch_d2f(L0.bz, L0.bzf, X->nw, X->st);
+  ns_stats S{};
+  ns_status s = pcg(X, &S);
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  S.ms = now_ms() - t0;
+  if (stats) *stats = S;
+  return s;
+}
+
+ns_status ns_apply_A(ns_ctx* X, const double* x, double* y) {
+  if (!X) return NS_EINVAL;
+  if (!aligned8(x) || !aligned8(y)) return fail(X, NS_EINVAL, "x and y must be 8-byte aligned device pointers");
+  const Level& L0 = X->lev[0];
+  launch_apply_A(L0.n, X->P.h, L0.bx, L0.by, L0.bz, x, y, X->st);
+  HIPCHK(X, hipGetLastError());
+  return NS_OK;
+}
+
+ns_status ns_vcycle(ns_ctx* X, const double* r, double* z) {
+  if (!X) return NS_EINVAL;
+  if (!aligned8(r) || !aligned8(z)) return fail(X, NS_EINVAL, "r and z must be 8-byte aligned device pointers");
+  Level& L0 = X->lev[0];
+  launch_d2f(L0.bx, L0.bxf, X->nu, X->st);
+  launch_d2f(L0.by, L0.byf, X->nv, X->st);
+  launch_d2f(L0.bz, L0.bzf, X->nw, X->st);
+  prepare_hierarchy(X);
+  precond(X, r, z);
+  HIPCHK(X, hipGetLastError());
+  return NS_OK;
+}
+
+ns_status ns_buffer(ns_ctx* X, int which, void** dev_ptr, size_t* count) {
+  if (!X || !dev_ptr) return NS_EINVAL;
+  const Level& L0 = X->lev[0];
+  void* p = nullptr;
+  size_t c = 0;
+  switch (which) {
+    case NS_BUF_US: p = X->us; c = X->nu; break;
+    case NS_BUF_VS: p = X->vs; c = X->nv; break;
+    case NS_BUF_WS: p = X->ws; c = X->nw; break;
+    case NS_BUF_BX: p = L0.bx; c = X->nu; break;
+    case NS_BUF_BY: p = L0.by; c = X->nv; break;
+    case NS_BUF_BZ: p = L0.bz; c = X->nw; break;
+    case NS_BUF_RHS: p = X->b; c = X->nc; break;
+    case NS_BUF_RHO: p = X->rho; c = X->nc; break;
+    case NS_BUF_MU: p = X->mu; c = X->nc; break;
+    case NS_BUF_CHI: p = X->chi; c = X->nc; break;
+    case NS_BUF_RHOFLOW: p = X->rfl; c = X->nc; break;
+    default: return fail(X, NS_EINVAL, "unknown buffer id %d", which);
+  }
+  *dev_ptr = p;
+  if (count) *count = c;
+  if (which == NS_BUF_BX || which == NS_BUF_BY || which == NS_BUF_BZ || which == NS_BUF_RHS)
+    X->have_beta = true;   // the caller may fill the projection inputs directly
+  return NS_OK;
+}
+
+ns_status ns_diagnostics(ns_ctx* X, double out[4]) {
+  if (!X || !out) return NS_EINVAL;
+  const int np = launch_diag_partials(X->phys, X->F.sigma, X->F.u, X->F.v, X->F.w, X->partials, X->st);
+  launch_diag_finalize(X->partials, np, X->scal, X->st);
+  ns_status s = read_scal(X);
+  if (s != NS_OK) return s;
+  for (int q = 0; q < 4; ++q) out[q] = X->host[S_DIAG + q];
+  return NS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,513 @@
+// Grid kernels of the time step on gfx950: level-set advection and
+// reinitialisation, material properties, the momentum predictor, the
+// projection right-hand side, the velocity correction and diagnostics.
+//
+// Threads are laid out 64 along x (one wavefront per x-row segment, so every
+// load of a row is one contiguous 512-byte FP64 segment) by 4 along y (or
+// along z for a 2-D tank).  Out-of-grid neighbours are the nearest interior
+// value: zero normal gradient for scalars, free slip for tangential
+// velocity, zero for wall-normal velocity (whose faces hold 0).
+#include <cmath>
+
+#include "ns_internal.h"
+
+namespace nsk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Geo {
+  dim3 grid, block;
+};
+
+inline Geo geo3(int mx, int my, int mz) {
+  dim3 b = (my >= 4) ? dim3(64, 4, 1) : dim3(64, 1, 4);
+  return {dim3((mx + 63) / 64, (my + b.y - 1) / b.y, (mz + b.z - 1) / b.z), b};
+}
+
+__device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+// cell value with clamped indices
+__device__ __forceinline__ double cv(const double* __restrict__ a, const Dims& n, int i, int j, int k) {
+  i = clampi(i, 0, n.nx - 1);
+  j = clampi(j, 0, n.ny - 1);
+  k = clampi(k, 0, n.nz - 1);
+  return a[i + (size_t)n.nx * (j + (size_t)n.ny * k)];
+}
+
+// face value of component C with clamped indices
+template <int C>
+__device__ __forceinline__ double fv(const double* __restrict__ a, const Dims& n, int i, int j, int k) {
+  const int mx = n.nx + (C == 0), my = n.ny + (C == 1), mz = n.nz + (C == 2);
+  i = clampi(i, 0, mx - 1);
+  j = clampi(j, 0, my - 1);
+  k = clampi(k, 0, mz - 1);
+  return a[i + (size_t)mx * (j + (size_t)my * k)];
+}
+
+// Koren-limited upwind face value; up2 is the cell behind the upwind cell up,
+// dn the downwind cell.  Third order (kappa = 1/3) where smooth, first order
+// at extrema, total-variation diminishing.
+__device__ __forceinline__ double koren(double up2, double up, double dn) {
+  const double a = up - up2;
+  const double b = dn - up;
+  if (a * b <= 0.0) return up;
+  const double fa = fabs(a), fb = fabs(b);
+  const double lim = fmin(fmin(2.0 * fa, (2.0 * fb + fa) * (1.0 / 3.0)), 2.0 * fb);
+  return up + copysign(0.5 * lim, b);
+}
+
+__device__ __forceinline__ double heaviside(double phi, double eps) {
+  if (phi < -eps) return 0.0;
+  if (phi > eps) return 1.0;
+  return 0.5 * (1.0 + phi / eps + sin(kPi * phi / eps) * (1.0 / kPi));
+}
+
+// union of the analytic bodies at (x,y,z,t); zdot of the nearest one
+__device__ double body_psi(const Phys& P, double x, double y, double z, double t, double* zdot) {
+  double best = INFINITY;
+  double zd_best = 0.0;
+  for (int m = 0; m < P.nb; ++m) {
+    const BodyK& B = P.body[m];
+    double arg = B.om * t + B.ph;
+    double zeta = B.amp * sin(arg);
+    double zd = B.amp * B.om * cos(arg);
+    double s;
+    if (B.kind == 0) {
+      s = fmax(fabs(x - B.c0) - B.h0, fabs(z - (B.c2 + zeta)) - B.h2);
+    } else {
+      double dx = x - B.c0, dy = y - B.c1;
+      double r = sqrt(dx * dx + dy * dy);
+      s = fmax(r - B.h0, fmax((B.h1 + zeta) - z, z - (B.h2 + zeta)));
+    }
+    if (s < best) {
+      best = s;
+      zd_best = zd;
+    }
+  }
+  *zdot = zd_best;
+  return best;
+}
+
+// --------------------------------------------------------------------------
+// level-set advection: sigma* = sigma - dt/h sum_d [a+ (s+ - s) - a- (s- - s)]
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_advect(Phys P, const double* __restrict__ s,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ v,
+                                                const double* __restrict__ w, double dt,
+                                                double* __restrict__ out) {
+  const Dims n = P.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= n.nx || j >= n.ny || k >= n.nz) return;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const size_t c = i + (size_t)n.nx * j + sxy * k;
+  const double sc = s[c];
+  double acc = 0.0;
+  {  // x
+    const size_t fm = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+    const double am = u[fm], ap = u[fm + 1];
+    auto S = [&](int o) { return s[c + (clampi(i + o, 0, n.nx - 1) - i)]; };
+    const double sp = ap >= 0.0 ? koren(S(-1), sc, S(1)) : koren(S(2), S(1), sc);
+    const double sm = am >= 0.0 ? koren(S(-2), S(-1), sc) : koren(S(1), sc, S(-1));
+    acc += ap * (sp - sc) - am * (sm - sc);
+  }
+  {  // y
+    const size_t fm = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+    const double am = v[fm], ap = v[fm + n.nx];
+    auto S = [&](int o) { return s[c + (ptrdiff_t)(clampi(j + o, 0, n.ny - 1) - j) * n.nx]; };
+    const double sp = ap >= 0.0 ? koren(S(-1), sc, S(1)) : koren(S(2), S(1), sc);
+    const double sm = am >= 0.0 ? koren(S(-2), S(-1), sc) : koren(S(1), sc, S(-1));
+    acc += ap * (sp - sc) - am * (sm - sc);
+  }
+  {  // z
+    const double am = w[c], ap = w[c + sxy];
+    auto S = [&](int o) { return s[c + (ptrdiff_t)(clampi(k + o, 0, n.nz - 1) - k) * (ptrdiff_t)sxy]; };
+    const double sp = ap >= 0.0 ? koren(S(-1), sc, S(1)) : koren(S(2), S(1), sc);
+    const double sm = am >= 0.0 ? koren(S(-2), S(-1), sc) : koren(S(1), sc, S(-1));
+    acc += ap * (sp - sc) - am * (sm - sc);
+  }
+  out[c] = sc - (dt / P.h) * acc;
+}
+
+// --------------------------------------------------------------------------
+// reinitialisation pseudo-step: Godunov upwind |grad sigma|, smoothed sign of
+// the pre-reinitialisation field sigma0.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_reinit(Phys P, const double* __restrict__ s0,
+                                                const double* __restrict__ cur,
+                                                double* __restrict__ nxt, double dtau) {
+  const Dims n = P.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= n.nx || j >= n.ny || k >= n.nz) return;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const size_t c = i + (size_t)n.nx * j + sxy * k;
+  const double a0 = s0[c];
+  const double h = P.h;
+  const double sg = a0 / sqrt(a0 * a0 + h * h);
+  const double sc = cur[c];
+  if (sg == 0.0) {
+    nxt[c] = sc;
+    return;
+  }
+  const double ih = 1.0 / h;
+  const double nb[6] = {cur[i > 0 ? c - 1 : c],
+                        cur[i < n.nx - 1 ? c + 1 : c],
+                        cur[j > 0 ? c - n.nx : c],
+                        cur[j < n.ny - 1 ? c + n.nx : c],
+                        cur[k > 0 ? c - sxy : c],
+                        cur[k < n.nz - 1 ? c + sxy : c]};
+  double g2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double a = (sc - nb[2 * d]) * ih;      // backward difference
+    const double b = (nb[2 * d + 1] - sc) * ih;  // forward difference
+    double t1, t2;
+    if (sg > 0.0) {
+      t1 = fmax(a, 0.0);
+      t2 = fmin(b, 0.0);
+    } else {
+      t1 = fmin(a, 0.0);
+      t2 = fmax(b, 0.0);
+    }
+    g2 += fmax(t1 * t1, t2 * t2);
+  }
+  nxt[c] = sc - dtau * sg * (sqrt(g2) - 1.0);
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t n) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) b[q] = a[q];
+}
+
+// --------------------------------------------------------------------------
+// properties at cell centres: two-stage Heaviside blend (flowing phases by
+// sigma, then the solid by psi); chi = 1 - H_body.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_props(Phys P, const double* __restrict__ sigma, double t,
+                                               double* __restrict__ rho, double* __restrict__ rfl,
+                                               double* __restrict__ mu, double* __restrict__ chi) {
+  const Dims n = P.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= n.nx || j >= n.ny || k >= n.nz) return;
+  const size_t c = i + (size_t)n.nx * (j + (size_t)n.ny * k);
+  double zd;
+  const double psi = body_psi(P, (i + 0.5) * P.h, (j + 0.5) * P.h, (k + 0.5) * P.h, t, &zd);
+  const double hf = heaviside(sigma[c], P.eps);
+  const double hb = heaviside(psi, P.eps);
+  const double rf = P.rho_w + (P.rho_a - P.rho_w) * hf;
+  const double mf = P.mu_w + (P.mu_a - P.mu_w) * hf;
+  rfl[c] = rf;
+  rho[c] = P.rho_s + (rf - P.rho_s) * hb;
+  mu[c] = P.mu_s + (mf - P.mu_s) * hb;
+  chi[c] = 1.0 - hb;
+}
+
+// --------------------------------------------------------------------------
+// momentum predictor for velocity component C (faces normal to C)
+// --------------------------------------------------------------------------
+// contribution of direction D to advection and viscous stress of component C
+template <int C, int D>
+__device__ __forceinline__ void mom_dir(const double* __restrict__ uc, const double* __restrict__ ud,
+                                        const double* __restrict__ mu, const Dims& n, int i, int j,
+                                        int k, double uf, double ih, double& adv, double& visc) {
+  constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
+  constexpr int di = (D == 0), dj = (D == 1), dk = (D == 2);
+  const double m2 = fv<C>(uc, n, i - 2 * di, j - 2 * dj, k - 2 * dk);
+  const double m1 = fv<C>(uc, n, i - di, j - dj, k - dk);
+  const double p1 = fv<C>(uc, n, i + di, j + dj, k + dk);
+  const double p2 = fv<C>(uc, n, i + 2 * di, j + 2 * dj, k + 2 * dk);
+  double ap, am, dvp = 0.0, dvm = 0.0;
+  if constexpr (C == D) {
+    ap = 0.5 * (uf + p1);
+    am = 0.5 * (m1 + uf);
+  } else {
+    // transverse velocity on the two faces meeting the edge above / below
+    const double vpp = fv<D>(ud, n, i + di, j + dj, k + dk);
+    const double vpm = fv<D>(ud, n, i + di - ci, j + dj - cj, k + dk - ck);
+    const double vmp = fv<D>(ud, n, i, j, k);
+    const double vmm = fv<D>(ud, n, i - ci, j - cj, k - ck);
+    ap = 0.5 * (vpm + vpp);
+    am = 0.5 * (vmm + vmp);
+    dvp = (vpp - vpm) * ih;
+    dvm = (vmp - vmm) * ih;
+  }
+  const double vp = ap >= 0.0 ? koren(m1, uf, p1) : koren(p2, p1, uf);
+  const double vm = am >= 0.0 ? koren(m2, m1, uf) : koren(p1, uf, m1);
+  adv += ap * (vp - uf) - am * (vm - uf);
+  double tp, tm;
+  if constexpr (C == D) {
+    tp = 2.0 * cv(mu, n, i, j, k) * (p1 - uf) * ih;
+    tm = 2.0 * cv(mu, n, i - ci, j - cj, k - ck) * (uf - m1) * ih;
+  } else {
+    const double mep = 0.25 * (cv(mu, n, i - ci, j - cj, k - ck) + cv(mu, n, i, j, k) +
+                               cv(mu, n, i - ci + di, j - cj + dj, k - ck + dk) +
+                               cv(mu, n, i + di, j + dj, k + dk));
+    const double mem = 0.25 * (cv(mu, n, i - ci - di, j - cj - dj, k - ck - dk) +
+                               cv(mu, n, i - di, j - dj, k - dk) + cv(mu, n, i - ci, j - cj, k - ck) +
+                               cv(mu, n, i, j, k));
+    tp = mep * ((p1 - uf) * ih + dvp);
+    tm = mem * ((uf - m1) * ih + dvm);
+  }
+  visc += (tp - tm) * ih;
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restrict__ u,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ w,
+                                                  const double* __restrict__ rho,
+                                                  const double* __restrict__ rfl,
+                                                  const double* __restrict__ mu,
+                                                  const double* __restrict__ chi, double dt, double t1,
+                                                  double* __restrict__ out, double* __restrict__ beta,
+                                                  float* __restrict__ betaf) {
+  const Dims n = P.n;
+  constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
+  const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= mx || j >= my || k >= mz) return;
+  const size_t f = i + (size_t)mx * (j + (size_t)my * k);
+  const bool wall = (C == 0) ? (i == 0 || i == n.nx) : (C == 1) ? (j == 0 || j == n.ny) : (k == 0);
+  if (wall) {
+    out[f] = 0.0;
+    beta[f] = 0.0;
+    betaf[f] = 0.0f;
+    return;
+  }
+  const double* uc = (C == 0) ? u : (C == 1) ? v : w;
+  const double uf = uc[f];
+  const double ih = 1.0 / P.h;
+  double adv = 0.0, visc = 0.0;
+  mom_dir<C, 0>(uc, u, mu, n, i, j, k, uf, ih, adv, visc);
+  mom_dir<C, 1>(uc, v, mu, n, i, j, k, uf, ih, adv, visc);
+  mom_dir<C, 2>(uc, w, mu, n, i, j, k, uf, ih, adv, visc);
+  adv *= ih;
+  const double rf = 0.5 * (cv(rho, n, i - ci, j - cj, k - ck) + cv(rho, n, i, j, k));
+  const double rff = 0.5 * (cv(rfl, n, i - ci, j - cj, k - ck) + cv(rfl, n, i, j, k));
+  const double xf = 0.5 * (cv(chi, n, i - ci, j - cj, k - ck) + cv(chi, n, i, j, k));
+  double ub = 0.0;
+  if (C == 2 && P.nb > 0) body_psi(P, (i + 0.5) * P.h, (j + 0.5) * P.h, k * P.h, t1, &ub);
+  const double grav = (C == 2) ? -P.g * rff : 0.0;
+  const double pen = xf * P.inv_kp;
+  out[f] = (rf * (uf / dt - adv) + visc + grav + pen * ub) / (rf / dt + pen);
+  const double bt = 1.0 / (rf + P.pen_w * dt * pen);
+  beta[f] = bt;
+  betaf[f] = (float)bt;
+}
+
+// b = -div_h(u*) / dt
+__global__ void __launch_bounds__(256) k_rhs(Phys P, const double* __restrict__ us,
+                                             const double* __restrict__ vs,
+                                             const double* __restrict__ ws, double scale,
+                                             double* __restrict__ b) {
+  const Dims n = P.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= n.nx || j >= n.ny || k >= n.nz) return;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const size_t c = i + (size_t)n.nx * j + sxy * k;
+  const size_t fu = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+  const size_t fv_ = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+  const double div = (us[fu + 1] - us[fu]) + (vs[fv_ + n.nx] - vs[fv_]) + (ws[c + sxy] - ws[c]);
+  b[c] = div * scale;
+}
+
+// u^{n+1} = u* - dt beta grad_h p on non-wall faces of component C
+template <int C>
+__global__ void __launch_bounds__(256) k_correct(Phys P, const double* __restrict__ us,
+                                                 const double* __restrict__ p,
+                                                 const double* __restrict__ beta, double dt,
+                                                 double* __restrict__ u) {
+  const Dims n = P.n;
+  constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
+  const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= mx || j >= my || k >= mz) return;
+  const size_t f = i + (size_t)mx * (j + (size_t)my * k);
+  const bool wall = (C == 0) ? (i == 0 || i == n.nx) : (C == 1) ? (j == 0 || j == n.ny) : (k == 0);
+  if (wall) {
+    u[f] = 0.0;
+    return;
+  }
+  const double ih = 1.0 / P.h;
+  double grad;
+  if (C == 2 && k == n.nz) {
+    grad = -cv(p, n, i, j, k - 1) * (2.0 * ih);   // p = 0 half a cell above
+  } else {
+    grad = (cv(p, n, i, j, k) - cv(p, n, i - ci, j - cj, k - ck)) * ih;
+  }
+  u[f] = us[f] - dt * beta[f] * grad;
+}
+
+// per-block partial diagnostics: max|div|, water volume, kinetic energy, max|u_c|
+__global__ void __launch_bounds__(256) k_diag(Phys P, const double* __restrict__ sigma,
+                                              const double* __restrict__ u,
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ w,
+                                              double* __restrict__ partials) {
+  const Dims n = P.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  double vals[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n.nx && j < n.ny && k < n.nz) {
+    const size_t sxy = (size_t)n.nx * n.ny;
+    const size_t c = i + (size_t)n.nx * j + sxy * k;
+    const size_t fu = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+    const size_t fvv = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+    const double um = u[fu], up = u[fu + 1], vm = v[fvv], vp = v[fvv + n.nx], wm = w[c],
+                 wp = w[c + sxy];
+    const double h = P.h;
+    const double vol = (n.ny == 1) ? h * h : h * h * h;
+    const double div = ((up - um) + (vp - vm) + (wp - wm)) / h;
+    const double hf = heaviside(sigma[c], P.eps);
+    const double rf = P.rho_w + (P.rho_a - P.rho_w) * hf;
+    const double uc = 0.5 * (up + um), vc = 0.5 * (vp + vm), wc = 0.5 * (wp + wm);
+    vals[0] = fabs(div);
+    vals[1] = (1.0 - hf) * vol;
+    vals[2] = 0.5 * rf * (uc * uc + vc * vc + wc * wc) * vol;
+    vals[3] = fmax(fmax(fmax(fabs(um), fabs(up)), fmax(fabs(vm), fabs(vp))), fmax(fabs(wm), fabs(wp)));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    vals[0] = fmax(vals[0], __shfl_down(vals[0], off, 64));
+    vals[1] += __shfl_down(vals[1], off, 64);
+    vals[2] += __shfl_down(vals[2], off, 64);
+    vals[3] = fmax(vals[3], __shfl_down(vals[3], off, 64));
+  }
+  __shared__ double sm[4][4];
+  const int tid = threadIdx.x + 64 * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int lane = tid & 63, wid = tid >> 6;
+  if (lane == 0)
+    for (int q = 0; q < 4; ++q) sm[wid][q] = vals[q];
+  __syncthreads();
+  if (tid == 0) {
+    const size_t blk = blockIdx.x + gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+    partials[4 * blk + 0] = fmax(fmax(sm[0][0], sm[1][0]), fmax(sm[2][0], sm[3][0]));
+    partials[4 * blk + 1] = (sm[0][1] + sm[1][1]) + (sm[2][1] + sm[3][1]);
+    partials[4 * blk + 2] = (sm[0][2] + sm[1][2]) + (sm[2][2] + sm[3][2]);
+    partials[4 * blk + 3] = fmax(fmax(sm[0][3], sm[1][3]), fmax(sm[2][3], sm[3][3]));
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_diag_finalize(const double* __restrict__ partials, int nparts,
+                                                        double* __restrict__ scal) {
+  double vals[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q = threadIdx.x; q < nparts; q += 1024) {
+    vals[0] = fmax(vals[0], partials[4 * q + 0]);
+    vals[1] += partials[4 * q + 1];
+    vals[2] += partials[4 * q + 2];
+    vals[3] = fmax(vals[3], partials[4 * q + 3]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    vals[0] = fmax(vals[0], __shfl_down(vals[0], off, 64));
+    vals[1] += __shfl_down(vals[1], off, 64);
+    vals[2] += __shfl_down(vals[2], off, 64);
+    vals[3] = fmax(vals[3], __shfl_down(vals[3], off, 64));
+  }
+  __shared__ double sm[16][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int q = 0; q < 4; ++q) sm[wid][q] = vals[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 16; ++q) {
+      r[0] = fmax(r[0], sm[q][0]);
+      r[1] += sm[q][1];
+      r[2] += sm[q][2];
+      r[3] = fmax(r[3], sm[q][3]);
+    }
+    for (int q = 0; q < 4; ++q) scal[S_DIAG + q] = r[q];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void launch_advect(const Phys& P, const double* s, const double* u, const double* v, const double* w,
+                   double dt, double* out, hipStream_t st) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  hipLaunchKernelGGL(k_advect, g.grid, g.block, 0, st, P, s, u, v, w, dt, out);
+}
+
+void launch_reinit(const Phys& P, const double* s0, const double* cur, double* nxt, double dtau,
+                   hipStream_t st) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  hipLaunchKernelGGL(k_reinit, g.grid, g.block, 0, st, P, s0, cur, nxt, dtau);
+}
+
+void launch_copy(const double* src, double* dst, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+}
+
+void launch_props(const Phys& P, const double* sigma, double t, double* rho, double* rfl, double* mu,
+                  double* chi, hipStream_t st) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  hipLaunchKernelGGL(k_props, g.grid, g.block, 0, st, P, sigma, t, rho, rfl, mu, chi);
+}
+
+void launch_momentum(const Phys& P, const double* u, const double* v, const double* w,
+                     const double* rho, const double* rfl, const double* mu, const double* chi,
+                     double dt, double t1, double* us, double* vs, double* ws, double* bx, double* by,
+                     double* bz, float* bxf, float* byf, float* bzf, hipStream_t st) {
+  const Dims n = P.n;
+  Geo gx = geo3(n.nx + 1, n.ny, n.nz);
+  hipLaunchKernelGGL(k_momentum<0>, gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, dt, t1,
+                     us, bx, bxf);
+  Geo gy = geo3(n.nx, n.ny + 1, n.nz);
+  hipLaunchKernelGGL(k_momentum<1>, gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, dt, t1,
+                     vs, by, byf);
+  Geo gz = geo3(n.nx, n.ny, n.nz + 1);
+  hipLaunchKernelGGL(k_momentum<2>, gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, dt, t1,
+                     ws, bz, bzf);
+}
+
+void launch_rhs(const Phys& P, const double* us, const double* vs, const double* ws, double dt,
+                double* b, hipStream_t st) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  hipLaunchKernelGGL(k_rhs, g.grid, g.block, 0, st, P, us, vs, ws, -1.0 / (P.h * dt), b);
+}
+
+void launch_correct(const Phys& P, const double* us, const double* vs, const double* ws,
+                    const double* p, const double* bx, const double* by, const double* bz, double dt,
+                    double* u, double* v, double* w, hipStream_t st) {
+  const Dims n = P.n;
+  Geo gx = geo3(n.nx + 1, n.ny, n.nz);
+  hipLaunchKernelGGL(k_correct<0>, gx.grid, gx.block, 0, st, P, us, p, bx, dt, u);
+  Geo gy = geo3(n.nx, n.ny + 1, n.nz);
+  hipLaunchKernelGGL(k_correct<1>, gy.grid, gy.block, 0, st, P, vs, p, by, dt, v);
+  Geo gz = geo3(n.nx, n.ny, n.nz + 1);
+  hipLaunchKernelGGL(k_correct<2>, gz.grid, gz.block, 0, st, P, ws, p, bz, dt, w);
+}
+
+int diag_blocks(const Phys& P) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  return (int)(g.grid.x * g.grid.y * g.grid.z);
+}
+
+int launch_diag_partials(const Phys& P, const double* sigma, const double* u, const double* v,
+                         const double* w, double* partials, hipStream_t st) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  hipLaunchKernelGGL(k_diag, g.grid, g.block, 0, st, P, sigma, u, v, w, partials);
+  return (int)(g.grid.x * g.grid.y * g.grid.z);
+}
+
+void launch_diag_finalize(const double* partials, int nparts, double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_finalize, dim3(1), dim3(1024), 0, st, partials, nparts, scal);
+}
+
+}  // namespace nsk

@@ -1,0 +1,123 @@
+// Internal declarations shared by the kernel and ABI translation units of
+// the gfx950 library.  Not part of the public ABI (see include/ns.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ns.h"
+
+namespace nsk {
+
+struct Dims {
+  int nx, ny, nz;
+};
+
+struct BodyK {
+  int kind;
+  double c0, c1, c2;
+  double h0, h1, h2;
+  double amp, om, ph;
+};
+
+// Physical constants and geometry passed by value to the grid kernels.
+struct Phys {
+  Dims n;
+  double h;
+  double rho_w, mu_w, rho_a, mu_a, rho_s, mu_s, g;
+  double eps;      // Heaviside half-width n_cells * h
+  double inv_kp;   // 1 / kappa_p
+  double pen_w;    // projection penalty weight
+  int nb;
+  BodyK body[4];
+};
+
+// One multigrid level.  Level 0 of the FP64 hierarchy aliases the CG
+// vectors (b = r, e = z); level 0 of the FP32 hierarchy has its own b, e.
+struct Level {
+  Dims n;
+  double h;
+  int f[3];                     // coarsening factor towards level + 1
+  double *bx, *by, *bz;         // FP64 face coefficients (walls = 0)
+  float *bxf, *byf, *bzf;       // FP32 copies
+  double *b, *e;                // FP64 right-hand side and correction
+  float *bf, *ef;               // FP32
+};
+
+// Device scalars of the CG iteration (one cache line each group).
+enum ScalIdx {
+  S_BB = 0,     // ||b||^2
+  S_RR = 1,     // ||r||^2 (latest)
+  S_RHO = 2,    // <r, z>
+  S_ALPHA = 3,
+  S_BETA = 4,
+  S_DQ = 5,     // <d, A d>
+  S_TRR = 6,    // ||b - A x||^2 recomputed
+  S_DIAG = 8,   // 4 diagnostics
+  S_COUNT = 16
+};
+
+enum FinMode { FIN_RESID0 = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_RR = 3, FIN_BETA = 4, FIN_TRR = 5 };
+
+// ---------------------------------------------------------------- launchers
+// grid step kernels (ns_grid.hip)
+void launch_advect(const Phys& P, const double* s, const double* u, const double* v, const double* w,
+                   double dt, double* out, hipStream_t st);
+void launch_reinit(const Phys& P, const double* s0, const double* cur, double* nxt, double dtau,
+                   hipStream_t st);
+void launch_copy(const double* src, double* dst, size_t n, hipStream_t st);
+void launch_props(const Phys& P, const double* sigma, double t, double* rho, double* rfl, double* mu,
+                  double* chi, hipStream_t st);
+void launch_momentum(const Phys& P, const double* u, const double* v, const double* w,
+                     const double* rho, const double* rfl, const double* mu, const double* chi,
+                     double dt, double t1, double* us, double* vs, double* ws, double* bx, double* by,
+                     double* bz, float* bxf, float* byf, float* bzf, hipStream_t st);
+void launch_rhs(const Phys& P, const double* us, const double* vs, const double* ws, double dt,
+                double* b, hipStream_t st);
+void launch_correct(const Phys& P, const double* us, const double* vs, const double* ws,
+                    const double* p, const double* bx, const double* by, const double* bz, double dt,
+                    double* u, double* v, double* w, hipStream_t st);
+int launch_diag_partials(const Phys& P, const double* sigma, const double* u, const double* v,
+                         const double* w, double* partials, hipStream_t st);
+void launch_diag_finalize(const double* partials, int nparts, double* scal, hipStream_t st);
+int diag_blocks(const Phys& P);
+
+// multigrid and CG kernels (ns_mg.hip)
+template <typename T>
+void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
+               int first, hipStream_t st);
+template <typename T>
+void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
+                           const T* e, const Level& C, T* bc, hipStream_t st);
+template <typename T>
+void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, hipStream_t st);
+template <typename T>
+void launch_coarse_solve(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
+                         int sweeps, hipStream_t st);
+template <typename T>
+void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C,
+                         T* cbx, T* cby, T* cbz, hipStream_t st);
+template <typename T>
+void launch_fill(T* a, size_t n, hipStream_t st);
+void launch_d2f(const double* a, float* b, size_t n, hipStream_t st);
+void launch_f2d(const float* a, double* b, size_t n, hipStream_t st);
+
+int cg_blocks(const Dims& n);
+void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
+                       const double* b, const double* x, double* r, double* partials, hipStream_t st);
+void launch_spmv_dot(const Dims& n, double h, const double* bx, const double* by, const double* bz,
+                     const double* d, double* q, double* partials, hipStream_t st);
+void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
+                    const double* x, double* y, hipStream_t st);
+void launch_cg_update(const Dims& n, const double* scal, const double* d, const double* q, double* x,
+                      double* r, double* partials, hipStream_t st);
+void launch_dots2(const Dims& n, const double* r, const double* zn, const double* z, double* partials,
+                  hipStream_t st);
+void launch_dot1(const Dims& n, const double* a, const double* b, double* partials, hipStream_t st);
+void launch_cg_dir(const Dims& n, const double* scal, const double* zn, double* d, int first,
+                   hipStream_t st);
+void launch_finalize(const double* partials, int nparts, int mode, double* scal, hipStream_t st);
+
+}  // namespace nsk

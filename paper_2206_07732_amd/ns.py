@@ -1,0 +1,250 @@
+"""Python binding of the gfx950 library libns.so (C ABI in include/ns.h).
+
+Argument marshalling only: PyTorch provides device memory (the state arrays
+and the workspace) and the HIP stream; every arithmetic step of the time
+step runs in the library's kernels.  There is no CPU fallback: if the
+library or a GPU is missing, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libns.so")
+
+NS_OK, NS_EINVAL, NS_ENOCONV, NS_ENAN, NS_EHIP, NS_ESTATE = 0, -1, -2, -3, -4, -5
+STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_ENOCONV", -3: "NS_ENAN", -4: "NS_EHIP", -5: "NS_ESTATE"}
+PREC_FP64, PREC_MIXED = 0, 1
+X0_ZERO, X0_PREV = 0, 1
+BUF = {"us": 0, "vs": 1, "ws": 2, "bx": 3, "by": 4, "bz": 5, "rhs": 6, "rho": 7, "mu": 8, "chi": 9,
+       "rho_flow": 10}
+
+
+class NSBody(C.Structure):
+    _fields_ = [("kind", C.c_int), ("c", C.c_double * 3), ("half", C.c_double * 3),
+                ("heave_amp", C.c_double), ("heave_omega", C.c_double), ("heave_phase", C.c_double)]
+
+
+class NSParams(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
+                ("rho_w", C.c_double), ("mu_w", C.c_double), ("rho_a", C.c_double), ("mu_a", C.c_double),
+                ("rho_s", C.c_double), ("mu_s", C.c_double), ("g", C.c_double),
+                ("n_cells", C.c_double), ("inv_kappa_p", C.c_double), ("proj_penalty_weight", C.c_double),
+                ("n_bodies", C.c_int), ("body", NSBody * 4),
+                ("reinit_iters", C.c_int), ("reinit_dtau_over_h", C.c_double),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_sweeps", C.c_int),
+                ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int), ("x0", C.c_int)]
+
+
+class NSFields(C.Structure):
+    _fields_ = [("sigma", C.c_void_p), ("u", C.c_void_p), ("v", C.c_void_p), ("w", C.c_void_p),
+                ("p", C.c_void_p)]
+
+
+class NSStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_resid0", C.c_double),
+                ("rel_resid", C.c_double), ("true_rel_resid", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NSError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} -> {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libns.so (built by paper_2206_07732_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2206_07732_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, d, i = C.c_void_p, C.c_double, C.c_int
+        P = C.POINTER(NSParams)
+        S = C.POINTER(NSStats)
+        sig = {
+            "ns_workspace_bytes": ([P], C.c_size_t),
+            "ns_init": ([P, NSFields, vp, C.c_size_t, vp, C.POINTER(vp)], i),
+            "levelset_advect_reinit": ([vp, d], i),
+            "momentum_step": ([vp, d, d], i),
+            "projection_solve": ([vp, d, S], i),
+            "ns_step": ([vp, d, d, S], i),
+            "ns_pcg_solve": ([vp, S], i),
+            "ns_apply_A": ([vp, vp, vp], i),
+            "ns_vcycle": ([vp, vp, vp], i),
+            "ns_buffer": ([vp, i, C.POINTER(vp), C.POINTER(C.c_size_t)], i),
+            "ns_diagnostics": ([vp, C.POINTER(C.c_double)], i),
+            "ns_num_levels": ([i, i, i], i),
+            "ns_last_error": ([vp], C.c_char_p),
+            "ns_destroy": ([vp], None),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
+            "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
+            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy"]
+
+SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2, coarse_sweeps=10,
+                       max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV)
+
+
+def params(wl, **opts) -> NSParams:
+    """ns_params for a workload (paper_2206_07732_amd.inputs.Workload)."""
+    P = NSParams()
+    P.nx, P.ny, P.nz, P.h = wl.nx, wl.ny, wl.nz, wl.h
+    P.rho_w, P.mu_w, P.rho_a, P.mu_a, P.rho_s, P.mu_s, P.g = (
+        wl.rho_w, wl.mu_w, wl.rho_a, wl.mu_a, wl.rho_s, wl.mu_s, wl.g)
+    P.n_cells, P.inv_kappa_p, P.proj_penalty_weight = wl.n_cells, wl.inv_kappa_p, wl.proj_penalty_weight
+    P.n_bodies = len(wl.bodies)
+    for m, b in enumerate(wl.bodies):
+        P.body[m].kind = b.kind
+        for q in range(3):
+            P.body[m].c[q] = b.c[q]
+            P.body[m].half[q] = b.half[q]
+        P.body[m].heave_amp, P.body[m].heave_omega, P.body[m].heave_phase = (
+            b.heave_amp, b.heave_omega, b.heave_phase)
+    o = dict(SOLVER_DEFAULTS)
+    o.update(opts)
+    for k, v in o.items():
+        setattr(P, k, v)
+    return P
+
+
+def num_levels(nx, ny, nz) -> int:
+    return lib().ns_num_levels(nx, ny, nz)
+
+
+def _dev_f64(t: torch.Tensor, name: str):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+class Solver:
+    """One time-stepping context bound to caller-owned device fields.
+
+    fields: dict with 'sigma', 'u', 'v', 'w', 'p' float64 CUDA tensors of
+    shapes (nz,ny,nx), (nz,ny,nx+1), (nz,ny+1,nx), (nz+1,ny,nx), (nz,ny,nx).
+    """
+
+    def __init__(self, P: NSParams, fields: dict, stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the solver runs only on the gfx950 library")
+        L = lib()
+        self.P = P
+        self.fields = fields
+        self.device = fields["p"].device
+        nx, ny, nz = P.nx, P.ny, P.nz
+        shapes = {"sigma": (nz, ny, nx), "u": (nz, ny, nx + 1), "v": (nz, ny + 1, nx),
+                  "w": (nz + 1, ny, nx), "p": (nz, ny, nx)}
+        for k, s in shapes.items():
+            if tuple(fields[k].shape) != s:
+                raise ValueError(f"{k} has shape {tuple(fields[k].shape)}, expected {s}")
+        F = NSFields(*[_dev_f64(fields[k], k) for k in ("sigma", "u", "v", "w", "p")])
+        nbytes = L.ns_workspace_bytes(C.byref(P))
+        if nbytes == 0:
+            raise ValueError("invalid ns_params")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        st = L.ns_init(C.byref(P), F, C.c_void_p(base + self._ws_off), nbytes,
+                       C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if st != NS_OK:
+            raise NSError("ns_init", st, "invalid parameters, fields or workspace")
+        self.ctx = ctx
+
+    # -- helpers
+    def _chk(self, fn, st, allow=(NS_OK,)):
+        if st not in allow:
+            msg = lib().ns_last_error(self.ctx)
+            raise NSError(fn, st, msg.decode() if msg else "")
+        return st
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().ns_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the ABI calls
+    def levelset_advect_reinit(self, dt: float):
+        self._chk("levelset_advect_reinit", lib().levelset_advect_reinit(self.ctx, dt))
+
+    def momentum_step(self, dt: float, t_np1: float):
+        self._chk("momentum_step", lib().momentum_step(self.ctx, dt, t_np1))
+
+    def projection_solve(self, dt: float, allow_noconv: bool = False) -> dict:
+        S = NSStats()
+        st = lib().projection_solve(self.ctx, dt, C.byref(S))
+        self._chk("projection_solve", st, (NS_OK, NS_ENOCONV) if allow_noconv else (NS_OK,))
+        d = S.as_dict()
+        d["status"] = st
+        return d
+
+    def step(self, dt: float, t_n: float, allow_noconv: bool = False) -> dict:
+        S = NSStats()
+        st = lib().ns_step(self.ctx, dt, t_n, C.byref(S))
+        self._chk("ns_step", st, (NS_OK, NS_ENOCONV) if allow_noconv else (NS_OK,))
+        d = S.as_dict()
+        d["status"] = st
+        return d
+
+    def pcg_solve(self, allow_noconv: bool = False) -> dict:
+        S = NSStats()
+        st = lib().ns_pcg_solve(self.ctx, C.byref(S))
+        self._chk("ns_pcg_solve", st, (NS_OK, NS_ENOCONV) if allow_noconv else (NS_OK,))
+        d = S.as_dict()
+        d["status"] = st
+        return d
+
+    def apply_A(self, x: torch.Tensor, y: torch.Tensor):
+        self._chk("ns_apply_A", lib().ns_apply_A(self.ctx, _dev_f64(x, "x"), _dev_f64(y, "y")))
+
+    def vcycle(self, r: torch.Tensor, z: torch.Tensor):
+        self._chk("ns_vcycle", lib().ns_vcycle(self.ctx, _dev_f64(r, "r"), _dev_f64(z, "z")))
+
+    def buffer(self, name: str) -> torch.Tensor:
+        """A float64 view of an internal workspace array, shaped like its field."""
+        ptr, cnt = C.c_void_p(), C.c_size_t()
+        self._chk("ns_buffer", lib().ns_buffer(self.ctx, BUF[name], C.byref(ptr), C.byref(cnt)))
+        off = ptr.value - self.workspace.data_ptr()
+        flat = self.workspace[off: off + 8 * cnt.value].view(torch.float64)
+        nx, ny, nz = self.P.nx, self.P.ny, self.P.nz
+        shape = {"us": (nz, ny, nx + 1), "bx": (nz, ny, nx + 1), "vs": (nz, ny + 1, nx),
+                 "by": (nz, ny + 1, nx), "ws": (nz + 1, ny, nx), "bz": (nz + 1, ny, nx)}.get(
+            name, (nz, ny, nx))
+        return flat.view(shape)
+
+    def diagnostics(self):
+        out = (C.c_double * 4)()
+        self._chk("ns_diagnostics", lib().ns_diagnostics(self.ctx, out))
+        return list(out)
+
+
+def device_fields(host_fields: dict, device="cuda") -> dict:
+    """Copy numpy initial fields to float64 device tensors."""
+    return {k: torch.from_numpy(host_fields[k]).to(device=device, dtype=torch.float64).contiguous()
+            for k in ("sigma", "u", "v", "w", "p")}

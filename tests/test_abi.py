@@ -1,0 +1,71 @@
+"""The C-ABI library loads on the host and exports every declared entry point
+(no compute calls: no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ns.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def nslib():
+    from paper_2206_07732_amd import ns
+    if not os.path.exists(ns.LIB_PATH):
+        from paper_2206_07732_amd import build
+        build.build()
+    return ns
+
+
+def test_header_declares_the_five_path_calls():
+    names = declared_functions()
+    for n in ("ns_init", "levelset_advect_reinit", "momentum_step", "projection_solve", "ns_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(nslib):
+    L = ctypes.CDLL(nslib.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(nslib.EXPORTED) == names
+
+
+def test_workspace_size_and_validation(nslib):
+    from paper_2206_07732_amd import inputs as I
+    L = nslib.lib()
+    wl = I.workload("c2")
+    P = nslib.params(wl)
+    nb = L.ns_workspace_bytes(ctypes.byref(P))
+    ncell = wl.nx * wl.ny * wl.nz
+    assert 8 * 20 * ncell < nb < 8 * 40 * ncell
+    bad = nslib.params(wl)
+    bad.nx = 0
+    assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = nslib.params(wl)
+    bad.h = -1.0
+    assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = nslib.params(wl)
+    bad.n_bodies = 5
+    assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = nslib.params(wl, prec=7)
+    assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_level_count_matches_oracle(nslib, orc):
+    for dims in [(256, 1, 64), (128, 64, 64), (256, 128, 128), (70, 6, 22), (37, 1, 19), (512, 256, 256)]:
+        assert nslib.num_levels(*dims) == orc.num_levels(*dims)
+    assert nslib.num_levels(256, 1, 64) == 7
+    assert nslib.num_levels(128, 64, 64) == 7
+    assert nslib.num_levels(512, 256, 256) == 9

@@ -1,0 +1,275 @@
+"""Parity of the gfx950 library (through its C ABI) with the FP64 CPU oracle.
+
+Tolerances: elementwise stages (advection, reinitialisation, properties,
+momentum, beta, rhs, operator, correction) differ from the oracle only by
+rounding order and fused multiply-adds, so they must agree to 1e-13
+relative.  The projection is iterative: with the CG iteration count forced
+to the oracle's (rtol = 0, max_iters = k) both sides run the same Krylov
+recurrence and must agree to 1e-10 relative per field.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2206_07732_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ns():
+    from paper_2206_07732_amd import ns
+    return ns
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def case(name):
+    if name == "ragged3d":
+        # sizes that are not multiples of the 64-wide tile; two MG levels only
+        return I.workload("tiny3d", nx=70, ny=6, nz=22, h=4.0 / 70, seed=21,
+                          bodies=[I.Body(1, (2.0, 0.17, 0.0), (0.3, 0.7, 1.5))])
+    if name == "heave3d":
+        return I.workload("tiny3d", nx=32, ny=16, nz=16,
+                          bodies=[I.Body(1, (2.0, 1.0, 0.0), (0.25, 0.7, 1.5), heave_amp=0.05,
+                                         heave_omega=math.pi, heave_phase=0.3)])
+    return I.workload(name)
+
+
+STAGE_CASES = ["tiny2d", "tiny3d", "ragged3d", "heave3d", "c1", "c2"]
+
+
+def make_solver(wl, fields, **opts):
+    ns = _ns()
+    dev = ns.device_fields(fields)
+    return ns.Solver(ns.params(wl, **opts), dev), dev
+
+
+@pytest.mark.parametrize("name", STAGE_CASES)
+def test_stage_parity(orc, name):
+    wl = case(name)
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    t1 = dt
+    Po = orc.params(wl)
+    S, dev = make_solver(wl, f)
+    print(f"[stage parity] case={name} dims={wl.nx}x{wl.ny}x{wl.nz}", flush=True)
+
+    # 1. level set
+    S.levelset_advect_reinit(dt)
+    torch.cuda.synchronize()
+    s_adv = orc.levelset_advect(Po, f["sigma"], f["u"], f["v"], f["w"], dt)
+    s_o = orc.reinit(Po, s_adv)
+    assert rel(host(dev["sigma"]), s_o) < 1e-13
+
+    # 2. properties, momentum predictor, beta (from the oracle's sigma on both sides)
+    dev["sigma"].copy_(torch.from_numpy(s_o))
+    S.momentum_step(dt, t1)
+    torch.cuda.synchronize()
+    rho_o, rfl_o, mu_o, chi_o = orc.properties(Po, s_o, t1)
+    assert rel(host(S.buffer("rho")), rho_o) < 1e-14
+    assert rel(host(S.buffer("rho_flow")), rfl_o) < 1e-14
+    assert rel(host(S.buffer("mu")), mu_o) < 1e-14
+    assert np.max(np.abs(host(S.buffer("chi")) - chi_o)) < 1e-14
+    us_o, vs_o, ws_o = orc.momentum(Po, f["u"], f["v"], f["w"], s_o, t1, dt)
+    for k, ref in (("us", us_o), ("vs", vs_o), ("ws", ws_o)):
+        if np.linalg.norm(ref) > 0:
+            assert rel(host(S.buffer(k)), ref) < 1e-13, k
+        else:
+            assert np.max(np.abs(host(S.buffer(k)))) == 0.0
+    bx_o, by_o, bz_o = orc.face_beta(Po, s_o, t1, dt)
+    for k, ref in (("bx", bx_o), ("by", by_o), ("bz", bz_o)):
+        if np.linalg.norm(ref) > 0:
+            assert rel(host(S.buffer(k)), ref) < 1e-14, k
+
+    # 3. projection with the GPU's own u* and beta fed to both sides
+    us_g, vs_g, ws_g = host(S.buffer("us")), host(S.buffer("vs")), host(S.buffer("ws"))
+    bx_g, by_g, bz_g = host(S.buffer("bx")), host(S.buffer("by")), host(S.buffer("bz"))
+    b_o = orc.rhs(Po, us_g, vs_g, ws_g, dt)
+    p_ref, st_o, rc = orc.pcg(Po, bx_g, by_g, bz_g, b_o, f["p"])
+    assert rc == 0
+    k = st_o["iters"]
+    Pk = orc.params(wl, max_iters=k, rtol=0.0)
+    p_o, _, _ = orc.pcg(Pk, bx_g, by_g, bz_g, b_o, f["p"])
+    u_o, v_o, w_o = orc.correct(Po, us_g, vs_g, ws_g, p_o, bx_g, by_g, bz_g, dt)
+    # a second context with the iteration count forced, on the same fields
+    ns = _ns()
+    Sk = ns.Solver(ns.params(wl, max_iters=k, rtol=0.0), dev)
+    dev["sigma"].copy_(torch.from_numpy(s_o))
+    Sk.momentum_step(dt, t1)
+    st_g = Sk.projection_solve(dt, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert st_g["iters"] == k
+    assert rel(host(Sk.buffer("rhs")), b_o) < 1e-13
+    assert rel(host(dev["p"]), p_o) < 1e-10
+    for key, ref in (("u", u_o), ("v", v_o), ("w", w_o)):
+        if np.linalg.norm(ref) > 0:
+            assert rel(host(dev[key]), ref) < 1e-10, key
+    print(f"[stage parity] case={name} iters={k} p_rel={rel(host(dev['p']), p_o):.2e}", flush=True)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d", "c1", "c2"])
+def test_step_parity_forced_iterations(orc, name):
+    """One whole ns_step from identical state, CG count forced to the oracle's."""
+    wl = case(name)
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    _, st, rc = orc.step(orc.params(wl), f, dt, 0.0)
+    assert rc == 0
+    k = st["iters"]
+    ref, _, _ = orc.step(orc.params(wl, max_iters=k, rtol=0.0), f, dt, 0.0)
+    S, dev = make_solver(wl, f, max_iters=k, rtol=0.0)
+    sg = S.step(dt, 0.0, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert sg["iters"] == k
+    for key in ("sigma", "u", "v", "w", "p"):
+        r = rel(host(dev[key]), ref[key])
+        print(f"[step parity] case={name} field={key} rel={r:.2e}", flush=True)
+        if np.linalg.norm(ref[key]) > 0:
+            assert r < 1e-10, key
+
+
+def test_c1_ten_steps_free_running(orc):
+    """The measured 2-D configuration, 10 free-running steps at rtol 1e-10
+    on both sides: iteration counts agree within one and fields stay close."""
+    wl = I.workload("c1")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    Po = orc.params(wl)
+    S, dev = make_solver(wl, f)
+    fo, t = f, 0.0
+    for s in range(wl.steps):
+        fo, sto, rc = orc.step(Po, fo, dt, t)
+        stg = S.step(dt, t)
+        t += dt
+        assert rc == 0 and stg["converged"] == 1
+        assert stg["true_rel_resid"] <= 1e-10
+        assert abs(stg["iters"] - sto["iters"]) <= 1
+    torch.cuda.synchronize()
+    for key in ("sigma", "u", "w", "p"):
+        r = rel(host(dev[key]), fo[key])
+        print(f"[c1 free] field={key} rel={r:.2e}", flush=True)
+        assert r < 1e-7, key
+    dg = S.diagnostics()
+    do = orc.diagnostics(Po, fo["sigma"], fo["u"], fo["v"], fo["w"])
+    assert abs(dg[1] - do[1]) < 1e-9 * do[1]
+    assert dg[0] < 1e-7
+
+
+def test_operator_and_vcycle_parity(orc):
+    for name in ("tiny3d", "ragged3d", "c1"):
+        wl = case(name)
+        f = I.make_fields(wl)
+        dt = I.cfl_dt(wl, f)
+        S, dev = make_solver(wl, f)
+        S.momentum_step(dt, dt)
+        torch.cuda.synchronize()
+        bx, by, bz = host(S.buffer("bx")), host(S.buffer("by")), host(S.buffer("bz"))
+        rng = np.random.default_rng(8)
+        x = rng.standard_normal(f["p"].shape)
+        xd = torch.from_numpy(x).cuda()
+        y = torch.empty_like(xd)
+        S.apply_A(xd, y)
+        torch.cuda.synchronize()
+        yo = orc.apply_A(wl.nx, wl.ny, wl.nz, wl.h, bx, by, bz, x)
+        assert rel(host(y), yo) < 1e-13
+        S.vcycle(xd, y)
+        torch.cuda.synchronize()
+        zo = orc.vcycle(orc.params(wl), bx, by, bz, x)
+        r64 = rel(host(y), zo)
+        assert r64 < 1e-12, (name, r64)
+        ns = _ns()
+        S32 = ns.Solver(ns.params(wl, prec=ns.PREC_MIXED), dev)
+        S32.momentum_step(dt, dt)
+        S32.vcycle(xd, y)
+        torch.cuda.synchronize()
+        zo32 = orc.vcycle(orc.params(wl, prec=1), bx, by, bz, x)
+        r32 = rel(host(y), zo32)
+        print(f"[vcycle] case={name} fp64 rel={r64:.2e} fp32 rel={r32:.2e}", flush=True)
+        assert r32 < 1e-5
+
+
+def test_mixed_precision_projection_meets_fp64_tolerance(orc):
+    wl = I.workload("c2")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    ns = _ns()
+    S64, d64 = make_solver(wl, f)
+    S32, d32 = make_solver(wl, f, prec=ns.PREC_MIXED)
+    a = S64.step(dt, 0.0)
+    b = S32.step(dt, 0.0)
+    torch.cuda.synchronize()
+    assert a["true_rel_resid"] <= 1e-10 and b["true_rel_resid"] <= 1e-10
+    for key in ("u", "w", "p"):
+        r = rel(host(d32[key]), host(d64[key]))
+        print(f"[mixed vs fp64] field={key} rel={r:.2e} iters {b['iters']} vs {a['iters']}", flush=True)
+        assert r < 1e-8
+
+
+def test_hydrostatic_closed_form_on_gpu(orc):
+    box = I.Body(0, (1.0, 0.0, 1.0), (0.25, 0.0, 0.2))
+    wl = I.workload("tiny2d", nx=16, nz=24, h=1.0 / 12, bodies=[box], wave={"kind": "flat"})
+    f = I.make_fields(wl)
+    dt = 0.01
+    S, dev = make_solver(wl, f, rtol=1e-13)
+    st = S.step(dt, 0.0)
+    torch.cuda.synchronize()
+    Po = orc.params(wl)
+    rfl = orc.properties(Po, host(dev["sigma"]), dt)[1][:, 0, :]
+    g, h, nz = wl.g, wl.h, wl.nz
+    pe = np.empty_like(rfl)
+    pe[nz - 1] = g * rfl[nz - 1] * h / 2
+    for k in range(nz - 2, -1, -1):
+        pe[k] = pe[k + 1] + g * 0.5 * (rfl[k] + rfl[k + 1]) * h
+    assert np.max(np.abs(host(dev["p"])[:, 0, :] - pe)) < 1e-9 * pe.max()
+    for key in ("u", "w"):
+        assert np.max(np.abs(host(dev[key]))) < 1e-10 * g * dt
+
+
+def test_bitwise_deterministic():
+    wl = I.workload("tiny3d")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    outs = []
+    for _ in range(2):
+        S, dev = make_solver(wl, f)
+        for s in range(2):
+            S.step(dt, s * dt)
+        torch.cuda.synchronize()
+        outs.append({k: host(v).copy() for k, v in dev.items()})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_error_paths():
+    ns = _ns()
+    wl = I.workload("tiny2d")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    S, dev = make_solver(wl, f, max_iters=1)
+    with pytest.raises(ns.NSError) as e:
+        S.step(dt, 0.0)
+    assert e.value.status == ns.NS_ENOCONV
+    S2, dev2 = make_solver(wl, f)
+    with pytest.raises(ns.NSError) as e:
+        S2.projection_solve(dt)          # before momentum_step
+    assert e.value.status == ns.NS_ESTATE
+    dev2["sigma"][3, 0, 5] = float("nan")
+    with pytest.raises(ns.NSError) as e:
+        S2.step(dt, 0.0)
+    assert e.value.status == ns.NS_ENAN
+    with pytest.raises(ns.NSError):
+        S2.levelset_advect_reinit(-1.0)
+    with pytest.raises(TypeError):
+        ns.Solver(ns.params(wl), {**dev, "p": dev["p"].float()})
