@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the two-phase Navier-Stokes time step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--no-cpu-baseline]
+
+A step is one whole pass of the hot path: level-set advection and
+reinitialisation, properties, the momentum predictor, and the projection
+solved by MG-preconditioned CG to ||b - A p|| <= 1e-10 ||b||.  The default
+workload is the 3-D tank of 128x64x64 cells (4 x 2 x 2 m, 1 m water,
+second-order Stokes wave a = 0.05 m, T = 1.2 s, fixed cylinder buoy) in
+plain FP64, with synthetic seeded inputs already resident in device memory
+when the timed region starts.
+
+Printed: ONE JSON line with
+  value        Mcell-steps/s over the K timed steps (cells x K / seconds)
+  projection   projection wall time and CG iterations, FP64 V-cycle vs FP32
+               V-cycle inside FP64 CG, both to the same 1e-10 residual
+  roofline     the finest-level smoother pass (the dominant kernel): its
+               algorithmic bytes per launch over its average duration, the
+               duration taken from HIP events recorded with each dispatch
+  cpu_baseline the FP64 CPU oracle, single-threaded, on a bounded sample of
+               the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def smoother_bytes_per_cell(prec: int) -> float:
+    """Algorithmic bytes per cell of one colour pass of red-black Gauss-Seidel:
+    beta on the three face arrays (every face touches a cell of each colour),
+    b and the new e of that colour's half of the cells, and the old e of the
+    other colour's half (its neighbours).  FP64: 24 + 4 + 4 + 4 = 36 B."""
+    w = 8 if prec == 0 else 4
+    return 3 * w + 0.5 * w + 0.5 * w + 0.5 * w
+
+
+def run_gpu(args):
+    import torch
+
+    from paper_2206_07732_amd import inputs as I
+    from paper_2206_07732_amd import ns
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU (the hot path runs only on the gfx950 library)")
+    if not os.path.exists(ns.LIB_PATH):
+        from paper_2206_07732_amd import build
+        build.build()
+    wl = I.workload(args.workload)
+    f0 = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f0)
+    ncell = wl.ncells
+
+    # ---- main timed region: K whole FP64 steps
+    dev = ns.device_fields(f0)
+    S = ns.Solver(ns.params(wl, prec=ns.PREC_FP64), dev)
+    t = 0.0
+    for _ in range(args.warmup):
+        S.step(dt, t)
+        t += dt
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = S.step(dt, t)
+        iters.append(st["iters"])
+        t += dt
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = ncell * args.steps / elapsed / 1e6
+    log(f"[bench] {args.workload}: {ms_per_step:.3f} ms/step, {value:.1f} Mcell-steps/s, CG iters {iters}")
+
+    # ---- dominant kernel: finest-level smoother pass, event-timed per dispatch
+    S.timing_enable(ns.TIME_SMOOTH0, 4096)
+    for _ in range(2):
+        S.step(dt, t)
+        t += dt
+    kms, kn = S.timing_read()
+    S.timing_enable(ns.TIME_SMOOTH0, 0)
+    avg_ms = kms / max(kn, 1)
+    kbytes = smoother_bytes_per_cell(0) * ncell
+    achieved = kbytes / (avg_ms * 1e-3) / 1e9
+    roofline = {"kernel": "k_gs<double, fine> (one red-black colour pass, finest level)",
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_us": round(avg_ms * 1e3, 3), "launches": kn,
+                "bytes_per_launch": int(kbytes)}
+    log(f"[bench] smoother pass: {kn} launches, avg {avg_ms*1e3:.2f} us, {achieved:.0f} GB/s")
+    S.close()
+
+    # ---- projection time to 1e-10, FP64 V-cycle vs FP32 V-cycle in FP64 CG
+    proj = {}
+    for name, prec in (("fp64", ns.PREC_FP64), ("mixed", ns.PREC_MIXED)):
+        d = ns.device_fields(f0)
+        Sp = ns.Solver(ns.params(wl, prec=prec), d)
+        tt = 0.0
+        for _ in range(args.warmup):
+            Sp.step(dt, tt)
+            tt += dt
+        ms, its, res = [], [], []
+        for _ in range(max(3, min(args.steps, 10))):
+            Sp.levelset_advect_reinit(dt)
+            Sp.momentum_step(dt, tt + dt)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = Sp.projection_solve(dt)
+            ms.append(1e3 * (time.perf_counter() - a))
+            its.append(st["iters"])
+            res.append(st["true_rel_resid"])
+            tt += dt
+        proj[name] = {"ms_median": round(statistics.median(ms), 4), "iters": its,
+                      "max_true_rel_resid": max(res)}
+        Sp.close()
+    proj["speedup_mixed_vs_fp64"] = round(proj["fp64"]["ms_median"] / proj["mixed"]["ms_median"], 3)
+    log(f"[bench] projection fp64 {proj['fp64']['ms_median']:.3f} ms, mixed {proj['mixed']['ms_median']:.3f} ms")
+
+    config = {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "cells": ncell, "h": wl.h,
+              "dt": dt, "cfl": wl.cfl, "solver": "flexible PCG, V(2,2) red-black GS, FP64",
+              "rtol": 1e-10, "mg_levels": ns.num_levels(wl.nx, wl.ny, wl.nz)}
+    return {"value": value, "ms_per_step": ms_per_step, "iters": iters, "roofline": roofline,
+            "projection": proj, "config": config, "wl": wl, "f0": f0, "dt": dt}
+
+
+def run_cpu_baseline(wl, f0, dt, seconds: float):
+    """The oracle as it stands, single-threaded, for about `seconds`."""
+    from oracle import oracle as O
+    O.lib()
+    P = O.params(wl)
+    f, t, n = f0, 0.0, 0
+    t0 = time.perf_counter()
+    while True:
+        f, st, rc = O.step(P, f, dt, t)
+        t += dt
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= wl.steps:
+            break
+    return {"value": round(wl.ncells * n / el / 1e6, 4), "unit": "Mcell-steps/s", "cores": 1,
+            "kind": "oracle", "sample": f"first {n} step(s) of the same workload from its initial "
+                                        f"condition, {el:.1f} s, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(how the step would shard is described in the design notes). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    r = run_gpu(args)
+    if args.copy_calibration_mib > 0:
+        import torch
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {args.copy_calibration_mib} MiB device copies")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = run_cpu_baseline(r["wl"], r["f0"], r["dt"], args.cpu_seconds)
+        log(f"[bench] cpu oracle {cpu['value']} Mcell-steps/s ({cpu['sample']})")
+    out = {
+        "metric": "Mcell-steps/s + projection time @1e-10 resid: FP64 MG-CG vs mixed-prec+learned",
+        "value": round(r["value"], 3),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": r["config"],
+        "cg_iters": r["iters"],
+        "projection": r["projection"],
+        "roofline": r["roofline"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,6 +177,21 @@ ns_status ns_buffer(ns_ctx* ctx, int which, void** dev_ptr, size_t* count);
  * out is host memory; synchronises the stream. */
 ns_status ns_diagnostics(ns_ctx* ctx, double out[4]);
 
+/* Kernel timing, a profiling aid.  While enabled for a kernel, each of its
+ * next max_launches dispatches on the context's stream carries a start and
+ * stop HIP event recorded by the dispatch itself (hipExtLaunchKernelGGL),
+ * so the elapsed time is the kernel's own execution.  max_launches <= 0
+ * disables.  Events are host-API objects; no device memory is allocated. */
+typedef enum {
+  NS_TIME_SMOOTH0 = 0,   /* the finest-level smoother pass (one colour)            */
+  NS_TIME_SPMV = 1       /* the CG operator application with its dot product       */
+} ns_timed_kernel;
+ns_status ns_timing_enable(ns_ctx* ctx, int kernel, int max_launches);
+
+/* Sum of the recorded kernel durations (ms) and their count since the last
+ * read; synchronises the stream and restarts the count. */
+ns_status ns_timing_read(ns_ctx* ctx, double* total_ms, int* launches);
+
 /* Number of multigrid levels for these sizes. */
 int ns_num_levels(int nx, int ny, int nz);
 

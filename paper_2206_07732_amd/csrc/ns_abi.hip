@@ -34,6 +34,11 @@ struct ns_ctx {
   Level lev[32];
   double* host;   // pinned host scalars
   bool have_beta;
+  int timed_kernel;   // -1 or an ns_timed_kernel id
+  KTimer kt;
+  hipEvent_t ev_rr;   // marks the residual read-back of a CG iteration
+  int tail64, tail32; // first level of the LDS tail per precision (L: none)
+  size_t lds64, lds32;
   char err[512];
 };
 
@@ -143,6 +148,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       V.n = Dims{F.n.nx / F.f[0], F.n.ny / F.f[1], F.n.nz / F.f[2]};
       V.h = 2.0 * F.h;
     }
+    V.h0 = P->h;
     for (int dd = 0; dd < 3; ++dd) V.f[dd] = act[dd] ? 2 : 1;
     const size_t c = (size_t)V.n.nx * V.n.ny * V.n.nz;
     const size_t fu = (size_t)(V.n.nx + 1) * V.n.ny * V.n.nz;
@@ -253,6 +259,77 @@ void build_hierarchy(ns_ctx* X) {
   }
 }
 
+// LDS elements of the tail from level l down, or 0 when it does not fit
+size_t tail_elems(const Level* lev, int L, int l) {
+  size_t tot = 0;
+  for (int q = l; q < L; ++q) {
+    const Dims n = lev[q].n;
+    const size_t c = (size_t)n.nx * n.ny * n.nz;
+    const size_t f = (size_t)(n.nx + 1) * n.ny * n.nz + (size_t)n.nx * (n.ny + 1) * n.nz +
+                     (size_t)n.nx * n.ny * (n.nz + 1);
+    tot += f + 2 * c + 5 * 4;   // five arrays, each padded to 16 bytes
+  }
+  return tot;
+}
+
+// first level whose tail fits the LDS budget (L when none does)
+int plan_tail(const Level* lev, int L, size_t w, size_t* bytes) {
+  for (int l = 0; l < L; ++l) {
+    const Dims n = lev[l].n;
+    if ((size_t)n.nx * n.ny * n.nz > 2 * (size_t)kTailThreads) continue;
+    if (L - l > kTailMaxLevels) continue;
+    const size_t b = tail_elems(lev, L, l) * w;
+    if (b <= kTailLdsBytes) {
+      *bytes = b;
+      return l;
+    }
+  }
+  *bytes = 0;
+  return L;
+}
+
+template <typename T>
+void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
+  TailDesc<T> D{};
+  D.nl = X->L - l0;
+  D.nu_pre = X->P.nu_pre;
+  D.nu_post = X->P.nu_post;
+  D.coarse_sweeps = X->P.coarse_sweeps;
+  int off = 0;
+  auto take = [&](size_t n) {
+    int o = off;
+    off += (int)((n + 3) / 4 * 4);
+    return o;
+  };
+  for (int q = 0; q < D.nl; ++q) {
+    const Level& V = X->lev[l0 + q];
+    const Dims n = V.n;
+    D.n[q] = n;
+    for (int d = 0; d < 3; ++d) D.f[q][d] = V.f[d];
+    D.h2[q] = (T)(V.h * V.h);
+    D.gbx[q] = LV<T>::bx(V);
+    D.gby[q] = LV<T>::by(V);
+    D.gbz[q] = LV<T>::bz(V);
+    D.obx[q] = take((size_t)(n.nx + 1) * n.ny * n.nz);
+    D.oby[q] = take((size_t)n.nx * (n.ny + 1) * n.nz);
+    D.obz[q] = take((size_t)n.nx * n.ny * (n.nz + 1));
+    D.ob[q] = take((size_t)n.nx * n.ny * n.nz);
+    D.oe[q] = take((size_t)n.nx * n.ny * n.nz);
+  }
+  D.gb = b;
+  D.ge = e;
+  launch_vcycle_tail<T>(D, bytes, X->st);
+}
+
+template <typename T>
+int tail_start(const ns_ctx* X) {
+  return sizeof(T) == 8 ? X->tail64 : X->tail32;
+}
+template <typename T>
+size_t tail_bytes(const ns_ctx* X) {
+  return sizeof(T) == 8 ? X->lds64 : X->lds32;
+}
+
 // e_l = V(l, b_l); level 0 uses the given b0, e0
 template <typename T>
 void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
@@ -262,16 +339,21 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   T* e = (l == 0) ? e0 : LV<T>::e(L);
   const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
   hipStream_t st = X->st;
+  if (l == tail_start<T>(X)) {
+    launch_tail<T>(X, l, b, e, tail_bytes<T>(X));
+    return;
+  }
+  KTimer* kt = (l == 0 && X->timed_kernel == NS_TIME_SMOOTH0) ? &X->kt : nullptr;
   if (l == X->L - 1) {
     launch_coarse_solve<T>(L, bx, by, bz, b, e, P.coarse_sweeps, st);
     return;
   }
   if (P.nu_pre > 0) {
-    launch_gs<T>(L, bx, by, bz, b, e, 0, 1, st);
-    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st);
+    launch_gs<T>(L, bx, by, bz, b, e, 0, 1, st, kt);
+    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st, kt);
     for (int s = 1; s < P.nu_pre; ++s) {
-      launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st);
-      launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st, kt);
     }
   } else {
     launch_fill<T>(e, (size_t)L.n.nx * L.n.ny * L.n.nz, st);
@@ -281,8 +363,8 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   vcycle<T>(X, l + 1, nullptr, nullptr);
   launch_prolong<T>(L, e, C, LV<T>::e(C), st);
   for (int s = 0; s < P.nu_post; ++s) {
-    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st);
-    launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st);
+    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st, kt);
+    launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st, kt);
   }
 }
 
@@ -348,12 +430,24 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     launch_dot1(n, X->r, z, X->partials, st);
     launch_finalize(X->partials, np, FIN_RHO, X->scal, st);
     while (it < P.max_iters) {
-      launch_spmv_dot(n, h, L0.bx, L0.by, L0.bz, X->d, X->q, X->partials, st);
+      launch_spmv_dot(n, h, L0.bx, L0.by, L0.bz, X->d, X->q, X->partials, st,
+                      X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr);
       launch_finalize(X->partials, np, FIN_ALPHA, X->scal, st);
       launch_cg_update(n, X->scal, X->d, X->q, x, X->r, X->partials, st);
       launch_finalize(X->partials, np, FIN_RR, X->scal, st);
       ++it;
-      if ((s = read_scal(X)) != NS_OK) return s;
+      // ask for ||r||^2, and keep the device busy with the next direction
+      // while the host waits for it; if the test passes, that work is unused
+      HIPCHK(X, hipMemcpyAsync(X->host, X->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(X, hipEventRecord(X->ev_rr, st));
+      const bool ahead = it < P.max_iters;
+      if (ahead) {
+        precond(X, X->r, zn);
+        launch_dots2(n, X->r, zn, z, X->partials, st);
+        launch_finalize(X->partials, np, FIN_BETA, X->scal, st);
+        launch_cg_dir(n, X->scal, zn, X->d, 0, st);
+      }
+      HIPCHK(X, hipEventSynchronize(X->ev_rr));
       rr = X->host[S_RR];
       if (!std::isfinite(rr)) {
         S.iters = it;
@@ -378,10 +472,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
         launch_finalize(X->partials, np, FIN_RHO, X->scal, st);
         continue;
       }
-      precond(X, X->r, zn);
-      launch_dots2(n, X->r, zn, z, X->partials, st);
-      launch_finalize(X->partials, np, FIN_BETA, X->scal, st);
-      launch_cg_dir(n, X->scal, zn, X->d, 0, st);
+      if (!ahead) break;
       std::swap(z, zn);
     }
   }
@@ -447,16 +538,75 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     delete X;
     return NS_EHIP;
   }
+  if (hipEventCreateWithFlags(&X->ev_rr, hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(X->host);
+    delete X;
+    return NS_EHIP;
+  }
+  X->tail64 = plan_tail(X->lev, X->L, sizeof(double), &X->lds64);
+  X->tail32 = plan_tail(X->lev, X->L, sizeof(float), &X->lds32);
   X->have_beta = false;
+  X->timed_kernel = -1;
+  X->kt = KTimer{nullptr, 0, 0};
   launch_fill<double>(X->scal, S_COUNT, X->st);
   *out = X;
   return NS_OK;
 }
 
+static void free_timer(ns_ctx* X) {
+  if (X->kt.ev) {
+    for (int q = 0; q < 2 * X->kt.cap; ++q) (void)hipEventDestroy(X->kt.ev[q]);
+    delete[] X->kt.ev;
+  }
+  X->kt = KTimer{nullptr, 0, 0};
+  X->timed_kernel = -1;
+}
+
 void ns_destroy(ns_ctx* X) {
   if (!X) return;
+  free_timer(X);
+  if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
   if (X->host) (void)hipHostFree(X->host);
   delete X;
+}
+
+ns_status ns_timing_enable(ns_ctx* X, int kernel, int max_launches) {
+  if (!X) return NS_EINVAL;
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  free_timer(X);
+  if (max_launches <= 0) return NS_OK;
+  if (kernel != NS_TIME_SMOOTH0 && kernel != NS_TIME_SPMV)
+    return fail(X, NS_EINVAL, "unknown timed kernel %d", kernel);
+  X->kt.ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches];
+  if (!X->kt.ev) return fail(X, NS_EINVAL, "cannot hold %d event pairs", max_launches);
+  for (int q = 0; q < 2 * max_launches; ++q) {
+    if (hipEventCreate(&X->kt.ev[q]) != hipSuccess) {
+      X->kt.cap = q / 2;
+      for (int r = 0; r < q; ++r) (void)hipEventDestroy(X->kt.ev[r]);
+      delete[] X->kt.ev;
+      X->kt = KTimer{nullptr, 0, 0};
+      return fail(X, NS_EHIP, "hipEventCreate failed");
+    }
+  }
+  X->kt.cap = max_launches;
+  X->kt.n = 0;
+  X->timed_kernel = kernel;
+  return NS_OK;
+}
+
+ns_status ns_timing_read(ns_ctx* X, double* total_ms, int* launches) {
+  if (!X || !total_ms || !launches) return NS_EINVAL;
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  double tot = 0.0;
+  for (int q = 0; q < X->kt.n; ++q) {
+    float ms = 0.0f;
+    HIPCHK(X, hipEventElapsedTime(&ms, X->kt.ev[2 * q], X->kt.ev[2 * q + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = X->kt.n;
+  X->kt.n = 0;
+  return NS_OK;
 }
 
 const char* ns_last_error(ns_ctx* X) { return X ? X->err : "null context"; }

@@ -39,6 +39,7 @@ struct Phys {
 struct Level {
   Dims n;
   double h;
+  double h0;                    // finest-level spacing (h == h0 on level 0)
   int f[3];                     // coarsening factor towards level + 1
   double *bx, *by, *bz;         // FP64 face coefficients (walls = 0)
   float *bxf, *byf, *bzf;       // FP32 copies
@@ -57,6 +58,34 @@ enum ScalIdx {
   S_TRR = 6,    // ||b - A x||^2 recomputed
   S_DIAG = 8,   // 4 diagnostics
   S_COUNT = 16
+};
+
+// Event pairs recorded with selected dispatches (profiling aid).
+struct KTimer {
+  hipEvent_t* ev;   // 2 * cap events: start, stop per launch
+  int cap;
+  int n;
+};
+
+// Coarse-level tail of the V-cycle run by one workgroup from LDS.
+constexpr int kTailMaxLevels = 12;
+constexpr int kTailThreads = 1024;
+constexpr size_t kTailLdsBytes = 64 * 1024;
+
+template <typename T>
+struct TailDesc {
+  int nl;                                   // levels in the tail (>= 1)
+  int nu_pre, nu_post, coarse_sweeps;
+  Dims n[kTailMaxLevels];
+  int f[kTailMaxLevels][3];                 // coarsening factor of level l towards l + 1
+  T h2[kTailMaxLevels];
+  const T* gbx[kTailMaxLevels];             // global face coefficients
+  const T* gby[kTailMaxLevels];
+  const T* gbz[kTailMaxLevels];
+  int obx[kTailMaxLevels], oby[kTailMaxLevels], obz[kTailMaxLevels];  // LDS offsets (elements)
+  int ob[kTailMaxLevels], oe[kTailMaxLevels];
+  const T* gb;                              // right-hand side of the first tail level
+  T* ge;                                    // its correction (output)
 };
 
 enum FinMode { FIN_RESID0 = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_RR = 3, FIN_BETA = 4, FIN_TRR = 5 };
@@ -87,7 +116,7 @@ int diag_blocks(const Phys& P);
 // multigrid and CG kernels (ns_mg.hip)
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
-               int first, hipStream_t st);
+               int first, hipStream_t st, KTimer* kt = nullptr);
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
                            const T* e, const Level& C, T* bc, hipStream_t st);
@@ -101,6 +130,8 @@ void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fb
                          T* cbx, T* cby, T* cbz, hipStream_t st);
 template <typename T>
 void launch_fill(T* a, size_t n, hipStream_t st);
+template <typename T>
+void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st);
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st);
 void launch_f2d(const float* a, double* b, size_t n, hipStream_t st);
 
@@ -108,7 +139,8 @@ int cg_blocks(const Dims& n);
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                        const double* b, const double* x, double* r, double* partials, hipStream_t st);
 void launch_spmv_dot(const Dims& n, double h, const double* bx, const double* by, const double* bz,
-                     const double* d, double* q, double* partials, hipStream_t st);
+                     const double* d, double* q, double* partials, hipStream_t st,
+                     KTimer* kt = nullptr);
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                     const double* x, double* y, hipStream_t st);
 void launch_cg_update(const Dims& n, const double* scal, const double* d, const double* q, double* x,

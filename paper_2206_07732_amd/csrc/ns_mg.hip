@@ -8,6 +8,8 @@
 // the CG vectors and their reductions are always FP64.  Reductions are
 // deterministic: wavefront shuffle, then LDS across the block's four
 // wavefronts, then one fixed-order pass over the per-block partials.
+#include <hip/hip_ext.h>
+
 #include "ns_internal.h"
 
 namespace nsk {
@@ -73,7 +75,8 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* __restri
 // its row and updates the one of the requested colour.  With first != 0 the
 // correction is taken as zero before the pass: the colour cell gets
 // h^2 b / D and the other cell of the pair is cleared.
-template <typename T>
+// FINE marks the finest-level instance (a separate symbol for profiling).
+template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx,
                                             const T* __restrict__ by, const T* __restrict__ bz,
                                             const T* __restrict__ b, T* __restrict__ e, int colour,
@@ -204,6 +207,141 @@ __global__ void __launch_bounds__(256) k_coarsen_beta(Dims nf, int fx, int fy, i
         sum += fb[i + (size_t)fmx * (j + (size_t)fmy * k)];
       }
   cb[I + (size_t)mx * (J + (size_t)my * K)] = sum / (T)(ni * nj * nk);
+}
+
+
+// ------------------------------------------------------- coarse-level tail
+// All levels from `first` down to the coarsest run in one workgroup of 1024
+// threads with coefficients, right-hand sides and corrections held in LDS,
+// so that each smoothing pass costs a barrier instead of a kernel launch.
+template <typename T>
+__device__ __forceinline__ void tail_gs(const Dims& n, T h2, const T* bx, const T* by, const T* bz,
+                                        const T* b, T* e, int colour, bool first) {
+  const int N = n.nx * n.ny * n.nz;
+  const int sxy = n.nx * n.ny;
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    const int i = c % n.nx;
+    const int j = (c / n.nx) % n.ny;
+    const int k = c / sxy;
+    const bool mine = ((i + j + k) & 1) == colour;
+    if (!mine) {
+      if (first) e[c] = (T)0;
+      continue;
+    }
+    const int fx = i + (n.nx + 1) * (j + n.ny * k);
+    const int fy = i + n.nx * (j + (n.ny + 1) * k);
+    const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+    const bool top = (k == n.nz - 1);
+    const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
+    T num = h2 * b[c];
+    if (!first) {
+      num += bw * e[i > 0 ? c - 1 : c] + be * e[i < n.nx - 1 ? c + 1 : c] +
+             bs * e[j > 0 ? c - n.nx : c] + bn * e[j < n.ny - 1 ? c + n.nx : c] +
+             bd * e[k > 0 ? c - sxy : c] + (top ? (T)0 : bu * e[c + sxy]);
+    }
+    e[c] = num / diag;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_vcycle_tail(TailDesc<T> D) {
+  extern __shared__ double tail_smem[];
+  T* sm = reinterpret_cast<T*>(tail_smem);
+  const int nl = D.nl;
+  // stage coefficients of every tail level and the first right-hand side
+  for (int l = 0; l < nl; ++l) {
+    const Dims n = D.n[l];
+    const int mu = (n.nx + 1) * n.ny * n.nz, mv = n.nx * (n.ny + 1) * n.nz, mw = n.nx * n.ny * (n.nz + 1);
+    for (int q = threadIdx.x; q < mu; q += blockDim.x) sm[D.obx[l] + q] = D.gbx[l][q];
+    for (int q = threadIdx.x; q < mv; q += blockDim.x) sm[D.oby[l] + q] = D.gby[l][q];
+    for (int q = threadIdx.x; q < mw; q += blockDim.x) sm[D.obz[l] + q] = D.gbz[l][q];
+  }
+  {
+    const int N0 = D.n[0].nx * D.n[0].ny * D.n[0].nz;
+    for (int q = threadIdx.x; q < N0; q += blockDim.x) sm[D.ob[0] + q] = D.gb[q];
+  }
+  __syncthreads();
+  auto smooth = [&](int l, int first_colour, int pairs, bool from_zero) {
+    const Dims n = D.n[l];
+    const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l], *b = sm + D.ob[l];
+    T* e = sm + D.oe[l];
+    for (int s = 0; s < pairs; ++s) {
+      tail_gs<T>(n, D.h2[l], bx, by, bz, b, e, first_colour, from_zero && s == 0);
+      tail_gs<T>(n, D.h2[l], bx, by, bz, b, e, 1 - first_colour, false);
+    }
+  };
+  auto zero = [&](int l) {
+    const int N = D.n[l].nx * D.n[l].ny * D.n[l].nz;
+    T* e = sm + D.oe[l];
+    for (int c = threadIdx.x; c < N; c += blockDim.x) e[c] = (T)0;
+    __syncthreads();
+  };
+  // down-leg
+  for (int l = 0; l < nl - 1; ++l) {
+    if (D.nu_pre > 0)
+      smooth(l, 0, D.nu_pre, true);
+    else
+      zero(l);
+    const Dims nf = D.n[l], nc = D.n[l + 1];
+    const int fx = D.f[l][0], fy = D.f[l][1], fz = D.f[l][2];
+    const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l], *b = sm + D.ob[l];
+    const T* e = sm + D.oe[l];
+    T* bc = sm + D.ob[l + 1];
+    const T ih2 = (T)1 / D.h2[l];
+    const T inv = (T)1 / (T)(fx * fy * fz);
+    const int Nc = nc.nx * nc.ny * nc.nz;
+    const int sxy = nf.nx * nf.ny;
+    for (int C = threadIdx.x; C < Nc; C += blockDim.x) {
+      const int I = C % nc.nx, J = (C / nc.nx) % nc.ny, K = C / (nc.nx * nc.ny);
+      T sum = 0;
+      for (int dk = 0; dk < fz; ++dk)
+        for (int dj = 0; dj < fy; ++dj)
+          for (int di = 0; di < fx; ++di) {
+            const int i = fx * I + di, j = fy * J + dj, k = fz * K + dk;
+            const int c = i + nf.nx * (j + nf.ny * k);
+            const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
+            const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
+            const T xc = e[c];
+            T acc = bx[ix] * (xc - e[i > 0 ? c - 1 : c]) + bx[ix + 1] * (xc - e[i < nf.nx - 1 ? c + 1 : c]) +
+                    by[iy] * (xc - e[j > 0 ? c - nf.nx : c]) +
+                    by[iy + nf.nx] * (xc - e[j < nf.ny - 1 ? c + nf.nx : c]) +
+                    bz[c] * (xc - e[k > 0 ? c - sxy : c]);
+            acc += (k < nf.nz - 1) ? bz[c + sxy] * (xc - e[c + sxy]) : (T)2 * bz[c + sxy] * xc;
+            sum += b[c] - ih2 * acc;
+          }
+      bc[C] = sum * inv;
+    }
+    __syncthreads();
+  }
+  // coarsest level: sweeps forward (red, black) then backward (black, red) from zero
+  {
+    const int l = nl - 1;
+    if (D.coarse_sweeps > 0) {
+      smooth(l, 0, D.coarse_sweeps, true);
+      smooth(l, 1, D.coarse_sweeps, false);
+    } else {
+      zero(l);
+    }
+  }
+  // up-leg
+  for (int l = nl - 2; l >= 0; --l) {
+    const Dims nf = D.n[l], nc = D.n[l + 1];
+    const int fx = D.f[l][0], fy = D.f[l][1], fz = D.f[l][2];
+    T* e = sm + D.oe[l];
+    const T* ec = sm + D.oe[l + 1];
+    const int N = nf.nx * nf.ny * nf.nz;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const int i = c % nf.nx, j = (c / nf.nx) % nf.ny, k = c / (nf.nx * nf.ny);
+      e[c] += ec[(i / fx) + nc.nx * ((j / fy) + nc.ny * (k / fz))];
+    }
+    __syncthreads();
+    smooth(l, 1, D.nu_post, false);
+  }
+  {
+    const int N0 = D.n[0].nx * D.n[0].ny * D.n[0].nz;
+    for (int q = threadIdx.x; q < N0; q += blockDim.x) D.ge[q] = sm[D.oe[0] + q];
+  }
 }
 
 template <typename T>
@@ -384,10 +522,18 @@ __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ pa
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
-               int first, hipStream_t st) {
+               int first, hipStream_t st, KTimer* kt) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
-  hipLaunchKernelGGL(k_gs<T>, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour,
-                     first);
+  const bool fine = (L.h == L.h0);
+  auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
+  if (kt && kt->n < kt->cap) {
+    (void)hipStreamSynchronize(st);   // time the kernel alone, not its wait for the previous one
+    hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
+                          (T)(L.h * L.h), bx, by, bz, b, e, colour, first);
+    ++kt->n;
+    return;
+  }
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, first);
 }
 
 template <typename T>
@@ -428,6 +574,11 @@ void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fb
 }
 
 template <typename T>
+void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(1), dim3(kTailThreads), lds_bytes, st, D);
+}
+
+template <typename T>
 void launch_fill(T* a, size_t n, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n);
@@ -454,8 +605,15 @@ void launch_resid_norm(const Dims& n, double h, const double* bx, const double* 
 }
 
 void launch_spmv_dot(const Dims& n, double h, const double* bx, const double* by, const double* bz,
-                     const double* d, double* q, double* partials, hipStream_t st) {
+                     const double* d, double* q, double* partials, hipStream_t st, KTimer* kt) {
   Geo g = geo3(n.nx, n.ny, n.nz);
+  if (kt && kt->n < kt->cap) {
+    (void)hipStreamSynchronize(st);
+    hipExtLaunchKernelGGL(k_spmv_dot, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1],
+                          0, n, 1.0 / (h * h), bx, by, bz, d, q, partials);
+    ++kt->n;
+    return;
+  }
   hipLaunchKernelGGL(k_spmv_dot, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, d, q, partials);
 }
 
@@ -495,7 +653,7 @@ void launch_finalize(const double* partials, int nparts, int mode, double* scal,
 
 #define NSK_INST(T)                                                                                 \
   template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int, int,    \
-                             hipStream_t);                                                          \
+                             hipStream_t, KTimer*);                                                 \
   template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*,      \
                                          const T*, const Level&, T*, hipStream_t);                  \
   template void launch_prolong<T>(const Level&, T*, const Level&, const T*, hipStream_t);           \
@@ -503,7 +661,8 @@ void launch_finalize(const double* partials, int nparts, int mode, double* scal,
                                        hipStream_t);                                                \
   template void launch_coarsen_beta<T>(const Level&, const T*, const T*, const T*, const Level&, T*, \
                                        T*, T*, hipStream_t);                                        \
-  template void launch_fill<T>(T*, size_t, hipStream_t);
+  template void launch_fill<T>(T*, size_t, hipStream_t);                                            \
+  template void launch_vcycle_tail<T>(const TailDesc<T>&, size_t, hipStream_t);
 NSK_INST(double)
 NSK_INST(float)
 #undef NSK_INST

@@ -85,6 +85,8 @@ def lib() -> C.CDLL:
             "ns_buffer": ([vp, i, C.POINTER(vp), C.POINTER(C.c_size_t)], i),
             "ns_diagnostics": ([vp, C.POINTER(C.c_double)], i),
             "ns_num_levels": ([i, i, i], i),
+            "ns_timing_enable": ([vp, i, i], i),
+            "ns_timing_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int)], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
         }
@@ -98,7 +100,9 @@ def lib() -> C.CDLL:
 
 EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
             "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
-            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy"]
+            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_timing_enable",
+            "ns_timing_read"]
+TIME_SMOOTH0, TIME_SPMV = 0, 1
 
 SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2, coarse_sweeps=10,
                        max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV)
@@ -237,6 +241,15 @@ class Solver:
                  "by": (nz, ny + 1, nx), "ws": (nz + 1, ny, nx), "bz": (nz + 1, ny, nx)}.get(
             name, (nz, ny, nx))
         return flat.view(shape)
+
+    def timing_enable(self, kernel: int, max_launches: int):
+        self._chk("ns_timing_enable", lib().ns_timing_enable(self.ctx, kernel, max_launches))
+
+    def timing_read(self):
+        """(total ms, launches) of the timed kernel since the last read."""
+        ms, n = C.c_double(), C.c_int()
+        self._chk("ns_timing_read", lib().ns_timing_read(self.ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def diagnostics(self):
         out = (C.c_double * 4)()
