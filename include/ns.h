@@ -192,6 +192,15 @@ ns_status ns_timing_enable(ns_ctx* ctx, int kernel, int max_launches);
  * read; synchronises the stream and restarts the count. */
 ns_status ns_timing_read(ns_ctx* ctx, double* total_ms, int* launches);
 
+/* Average duration (ms) of `reps` back-to-back dispatches of one kernel on
+ * the context's stream, bracketed by one pair of HIP events: the finest-level
+ * smoother pass (one colour, params.prec precision) or the CG operator
+ * application.  Runs on the current coefficients with vectors that are dead
+ * between steps, so it may be called between time steps without changing
+ * the state; synchronises the stream.  Needs momentum_step (or filled
+ * coefficients) first, else NS_ESTATE. */
+ns_status ns_time_kernel(ns_ctx* ctx, int kernel, int reps, double* avg_ms);
+
 /* Number of multigrid levels for these sizes. */
 int ns_num_levels(int nx, int ny, int nz);
 

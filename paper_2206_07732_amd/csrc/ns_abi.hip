@@ -26,7 +26,7 @@ struct ns_ctx {
   double *us, *vs, *ws;
   double *sig_a, *sig_b;
   double *rho, *rfl, *mu, *chi;
-  double *b, *r, *z, *zn, *d, *q;
+  double *b, *r, *z, *zn, *d, *d2, *q;
   double *partials;
   double *scal;
   int nparts;
@@ -132,6 +132,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
   double* z = cv.take<double>(nc);
   double* zn = cv.take<double>(nc);
   double* d = cv.take<double>(nc);
+  double* d2 = cv.take<double>(nc);
   double* q = cv.take<double>(nc);
   double* part = cv.take<double>((size_t)4 * nparts);
   double* scal = cv.take<double>(S_COUNT);
@@ -159,6 +160,8 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     V.bzf = cv.take<float>(fw);
     V.bf = cv.take<float>(c);
     V.ef = cv.take<float>(c);
+    V.invdf = cv.take<float>(c);
+    V.invd = cv.take<double>(c);
     if (l == 0) {
       V.bx = V.by = V.bz = nullptr;   // level-0 FP64 beta lives in its own arrays below
       V.b = V.e = nullptr;            // and its b, e alias CG vectors
@@ -192,6 +195,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     X->z = z;
     X->zn = zn;
     X->d = d;
+    X->d2 = d2;
     X->q = q;
     X->partials = part;
     X->scal = scal;
@@ -238,6 +242,7 @@ struct LV<double> {
   static double* bz(const Level& L) { return L.bz; }
   static double* b(const Level& L) { return L.b; }
   static double* e(const Level& L) { return L.e; }
+  static double* invd(const Level& L) { return L.invd; }
 };
 template <>
 struct LV<float> {
@@ -246,20 +251,11 @@ struct LV<float> {
   static float* bz(const Level& L) { return L.bzf; }
   static float* b(const Level& L) { return L.bf; }
   static float* e(const Level& L) { return L.ef; }
+  static float* invd(const Level& L) { return L.invdf; }
 };
 
-// coarse coefficients of every level from level 0, in precision T
-template <typename T>
-void build_hierarchy(ns_ctx* X) {
-  for (int l = 1; l < X->L; ++l) {
-    const Level& F = X->lev[l - 1];
-    const Level& C = X->lev[l];
-    launch_coarsen_beta<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
-                           LV<T>::bz(C), X->st);
-  }
-}
-
-// LDS elements of the tail from level l down, or 0 when it does not fit
+// LDS elements of the tail from level l down (five face/cell arrays per level
+// plus 1/D, each padded to 16 bytes)
 size_t tail_elems(const Level* lev, int L, int l) {
   size_t tot = 0;
   for (int q = l; q < L; ++q) {
@@ -267,16 +263,17 @@ size_t tail_elems(const Level* lev, int L, int l) {
     const size_t c = (size_t)n.nx * n.ny * n.nz;
     const size_t f = (size_t)(n.nx + 1) * n.ny * n.nz + (size_t)n.nx * (n.ny + 1) * n.nz +
                      (size_t)n.nx * n.ny * (n.nz + 1);
-    tot += f + 2 * c + 5 * 4;   // five arrays, each padded to 16 bytes
+    tot += f + 3 * c + 6 * 4;
   }
   return tot;
 }
 
-// first level whose tail fits the LDS budget (L when none does)
+// first level whose tail fits the LDS budget and the workgroup (L: none)
 int plan_tail(const Level* lev, int L, size_t w, size_t* bytes) {
   for (int l = 0; l < L; ++l) {
     const Dims n = lev[l].n;
-    if ((size_t)n.nx * n.ny * n.nz > 2 * (size_t)kTailThreads) continue;
+    const size_t pairs = (size_t)((n.nx + 1) / 2) * n.ny * n.nz;
+    if (pairs > 2 * (size_t)kTailThreads) continue;
     if (L - l > kTailMaxLevels) continue;
     const size_t b = tail_elems(lev, L, l) * w;
     if (b <= kTailLdsBytes) {
@@ -286,6 +283,32 @@ int plan_tail(const Level* lev, int L, size_t w, size_t* bytes) {
   }
   *bytes = 0;
   return L;
+}
+
+template <typename T>
+int tail_start(const ns_ctx* X) {
+  return sizeof(T) == 8 ? X->tail64 : X->tail32;
+}
+template <typename T>
+size_t tail_bytes(const ns_ctx* X) {
+  return sizeof(T) == 8 ? X->lds64 : X->lds32;
+}
+
+// coarse coefficients of every level from level 0, and 1/D of the levels
+// above the tail, in precision T
+template <typename T>
+void build_hierarchy(ns_ctx* X) {
+  for (int l = 1; l < X->L; ++l) {
+    const Level& F = X->lev[l - 1];
+    const Level& C = X->lev[l];
+    launch_coarsen_beta<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
+                           LV<T>::bz(C), X->st);
+  }
+  const int lt = tail_start<T>(X);
+  for (int l = 0; l < lt; ++l) {
+    const Level& V = X->lev[l];
+    launch_invdiag<T>(V, LV<T>::bx(V), LV<T>::by(V), LV<T>::bz(V), LV<T>::invd(V), X->st);
+  }
 }
 
 template <typename T>
@@ -301,33 +324,36 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
     off += (int)((n + 3) / 4 * 4);
     return o;
   };
+  int nseg = 0, pos = 0;
+  D.seg_start[0] = 0;
+  auto seg = [&](const T* src, int dst, size_t cnt) {
+    D.seg_src[nseg] = src;
+    D.seg_dst[nseg] = dst;
+    pos += (int)cnt;
+    D.seg_start[++nseg] = pos;
+  };
   for (int q = 0; q < D.nl; ++q) {
     const Level& V = X->lev[l0 + q];
     const Dims n = V.n;
     D.n[q] = n;
     for (int d = 0; d < 3; ++d) D.f[q][d] = V.f[d];
     D.h2[q] = (T)(V.h * V.h);
-    D.gbx[q] = LV<T>::bx(V);
-    D.gby[q] = LV<T>::by(V);
-    D.gbz[q] = LV<T>::bz(V);
-    D.obx[q] = take((size_t)(n.nx + 1) * n.ny * n.nz);
-    D.oby[q] = take((size_t)n.nx * (n.ny + 1) * n.nz);
-    D.obz[q] = take((size_t)n.nx * n.ny * (n.nz + 1));
-    D.ob[q] = take((size_t)n.nx * n.ny * n.nz);
-    D.oe[q] = take((size_t)n.nx * n.ny * n.nz);
+    const size_t mu = (size_t)(n.nx + 1) * n.ny * n.nz, mv = (size_t)n.nx * (n.ny + 1) * n.nz,
+                 mw = (size_t)n.nx * n.ny * (n.nz + 1), mc = (size_t)n.nx * n.ny * n.nz;
+    D.obx[q] = take(mu);
+    D.oby[q] = take(mv);
+    D.obz[q] = take(mw);
+    D.ob[q] = take(mc);
+    D.oe[q] = take(mc);
+    D.oid[q] = take(mc);
+    seg(LV<T>::bx(V), D.obx[q], mu);
+    seg(LV<T>::by(V), D.oby[q], mv);
+    seg(LV<T>::bz(V), D.obz[q], mw);
   }
-  D.gb = b;
+  seg(b, D.ob[0], (size_t)D.n[0].nx * D.n[0].ny * D.n[0].nz);
+  D.nseg = nseg;
   D.ge = e;
   launch_vcycle_tail<T>(D, bytes, X->st);
-}
-
-template <typename T>
-int tail_start(const ns_ctx* X) {
-  return sizeof(T) == 8 ? X->tail64 : X->tail32;
-}
-template <typename T>
-size_t tail_bytes(const ns_ctx* X) {
-  return sizeof(T) == 8 ? X->lds64 : X->lds32;
 }
 
 // e_l = V(l, b_l); level 0 uses the given b0, e0
@@ -344,16 +370,12 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
     return;
   }
   KTimer* kt = (l == 0 && X->timed_kernel == NS_TIME_SMOOTH0) ? &X->kt : nullptr;
-  if (l == X->L - 1) {
-    launch_coarse_solve<T>(L, bx, by, bz, b, e, P.coarse_sweeps, st);
-    return;
-  }
+  // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
-    launch_gs<T>(L, bx, by, bz, b, e, 0, 1, st, kt);
-    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st, kt);
+    launch_gs_first<T>(L, bx, by, bz, b, LV<T>::invd(L), e, st);
     for (int s = 1; s < P.nu_pre; ++s) {
-      launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st, kt);
-      launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
     }
   } else {
     launch_fill<T>(e, (size_t)L.n.nx * L.n.ny * L.n.nz, st);
@@ -361,10 +383,16 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   const Level& C = X->lev[l + 1];
   launch_resid_restrict<T>(L, bx, by, bz, b, e, C, LV<T>::b(C), st);
   vcycle<T>(X, l + 1, nullptr, nullptr);
-  launch_prolong<T>(L, e, C, LV<T>::e(C), st);
-  for (int s = 0; s < P.nu_post; ++s) {
-    launch_gs<T>(L, bx, by, bz, b, e, 1, 0, st, kt);
-    launch_gs<T>(L, bx, by, bz, b, e, 0, 0, st, kt);
+  // post-smoothing: (prolongation + black) fused, then red, then black, red pairs
+  if (P.nu_post > 0) {
+    launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), st);
+    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+    for (int s = 1; s < P.nu_post; ++s) {
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+    }
+  } else {
+    launch_prolong<T>(L, e, C, LV<T>::e(C), st);
   }
 }
 
@@ -401,11 +429,10 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   const Level& L0 = X->lev[0];
   hipStream_t st = X->st;
   double* x = X->F.p;
-  const int np = X->nparts;
+  const CgScratch cs{X->partials, X->scal};
   ns_stats S{};
   prepare_hierarchy(X);
-  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, X->partials, st);
-  launch_finalize(X->partials, np, FIN_RESID0, X->scal, st);
+  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
   ns_status s = read_scal(X);
   if (s != NS_OK) return s;
   const double bb = X->host[S_BB];
@@ -424,28 +451,30 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   int it = 0;
   double* z = X->z;
   double* zn = X->zn;
+  double* d = X->d;
+  double* dn = X->d2;
   if (!conv) {
+    // first direction d = z = M r, rho = <r, z>
     precond(X, X->r, z);
-    launch_cg_dir(n, X->scal, z, X->d, 1, st);
-    launch_dot1(n, X->r, z, X->partials, st);
-    launch_finalize(X->partials, np, FIN_RHO, X->scal, st);
+    launch_dot_rho(n, X->r, z, cs, st);
+    bool first = true;
     while (it < P.max_iters) {
-      launch_spmv_dot(n, h, L0.bx, L0.by, L0.bz, X->d, X->q, X->partials, st,
+      // d = z + beta d (or z), q = A d, alpha = rho / <d, q>
+      launch_dir_spmv(n, h, L0.bx, L0.by, L0.bz, z, d, dn, X->q, first ? 1 : 0, cs, st,
                       X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr);
-      launch_finalize(X->partials, np, FIN_ALPHA, X->scal, st);
-      launch_cg_update(n, X->scal, X->d, X->q, x, X->r, X->partials, st);
-      launch_finalize(X->partials, np, FIN_RR, X->scal, st);
+      std::swap(d, dn);
+      first = false;
+      launch_cg_update(n, d, X->q, x, X->r, cs, st);
       ++it;
-      // ask for ||r||^2, and keep the device busy with the next direction
-      // while the host waits for it; if the test passes, that work is unused
+      // ask for ||r||^2, and keep the device busy with the next
+      // preconditioner application while the host waits for it; if the test
+      // passes, that work is simply unused
       HIPCHK(X, hipMemcpyAsync(X->host, X->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(X, hipEventRecord(X->ev_rr, st));
       const bool ahead = it < P.max_iters;
       if (ahead) {
         precond(X, X->r, zn);
-        launch_dots2(n, X->r, zn, z, X->partials, st);
-        launch_finalize(X->partials, np, FIN_BETA, X->scal, st);
-        launch_cg_dir(n, X->scal, zn, X->d, 0, st);
+        launch_dots_beta(n, X->r, zn, z, cs, st);
       }
       HIPCHK(X, hipEventSynchronize(X->ev_rr));
       rr = X->host[S_RR];
@@ -457,8 +486,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
       S.rel_resid = std::sqrt(rr) / bnorm;
       if (rr <= tol2) {
         // confirm on the true residual; restart from it when it fails
-        launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, X->partials, st);
-        launch_finalize(X->partials, np, FIN_RESID0, X->scal, st);
+        launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
         if ((s = read_scal(X)) != NS_OK) return s;
         rr = X->host[S_RR];
         S.rel_resid = std::sqrt(rr) / bnorm;
@@ -467,9 +495,8 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
           break;
         }
         precond(X, X->r, z);
-        launch_cg_dir(n, X->scal, z, X->d, 1, st);
-        launch_dot1(n, X->r, z, X->partials, st);
-        launch_finalize(X->partials, np, FIN_RHO, X->scal, st);
+        launch_dot_rho(n, X->r, z, cs, st);
+        first = true;
         continue;
       }
       if (!ahead) break;
@@ -477,8 +504,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     }
   }
   // true residual at exit (into q, leaving r as the recursion left it)
-  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, X->partials, st);
-  launch_finalize(X->partials, np, FIN_TRR, X->scal, st);
+  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st);
   if ((s = read_scal(X)) != NS_OK) return s;
   S.iters = it;
   S.true_rel_resid = std::sqrt(X->host[S_TRR]) / bnorm;
@@ -591,6 +617,45 @@ ns_status ns_timing_enable(ns_ctx* X, int kernel, int max_launches) {
   X->kt.cap = max_launches;
   X->kt.n = 0;
   X->timed_kernel = kernel;
+  return NS_OK;
+}
+
+ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
+  if (!X || !avg_ms || reps <= 0) return NS_EINVAL;
+  if (kernel != NS_TIME_SMOOTH0 && kernel != NS_TIME_SPMV)
+    return fail(X, NS_EINVAL, "unknown timed kernel %d", kernel);
+  if (!X->have_beta) return fail(X, NS_ESTATE, "no coefficients yet: call momentum_step first");
+  hipEvent_t a, b;
+  HIPCHK(X, hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(X, NS_EHIP, "hipEventCreate failed");
+  }
+  Level& L0 = X->lev[0];
+  const Dims n = L0.n;
+  const CgScratch cs{X->partials, X->scal};
+  (void)hipStreamSynchronize(X->st);
+  (void)hipEventRecord(a, X->st);
+  for (int q = 0; q < reps; ++q) {
+    if (kernel == NS_TIME_SMOOTH0) {
+      // the finest smoother pass of the configured precision, on scratch
+      // vectors that are dead between steps (r read as b, zn or ef written)
+      if (X->P.prec == NS_PREC_FP64)
+        launch_gs<double>(L0, L0.bx, L0.by, L0.bz, X->r, X->zn, q & 1, X->st);
+      else
+        launch_gs<float>(L0, L0.bxf, L0.byf, L0.bzf, L0.bf, L0.ef, q & 1, X->st);
+    } else {
+      launch_dir_spmv(n, X->P.h, L0.bx, L0.by, L0.bz, X->zn, X->d, X->d2, X->q, 1, cs, X->st);
+    }
+  }
+  (void)hipEventRecord(b, X->st);
+  hipError_t e = hipEventSynchronize(b);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(X, NS_EHIP, "event timing: %s", hipGetErrorString(e));
+  *avg_ms = (double)ms / reps;
   return NS_OK;
 }
 

@@ -45,6 +45,8 @@ struct Level {
   float *bxf, *byf, *bzf;       // FP32 copies
   double *b, *e;                // FP64 right-hand side and correction
   float *bf, *ef;               // FP32
+  double* invd;                 // 1 / diagonal (h^2 scaled), FP64
+  float* invdf;                 // FP32
 };
 
 // Device scalars of the CG iteration (one cache line each group).
@@ -69,7 +71,7 @@ struct KTimer {
 
 // Coarse-level tail of the V-cycle run by one workgroup from LDS.
 constexpr int kTailMaxLevels = 12;
-constexpr int kTailThreads = 1024;
+constexpr int kTailThreads = 512;
 constexpr size_t kTailLdsBytes = 64 * 1024;
 
 template <typename T>
@@ -79,16 +81,24 @@ struct TailDesc {
   Dims n[kTailMaxLevels];
   int f[kTailMaxLevels][3];                 // coarsening factor of level l towards l + 1
   T h2[kTailMaxLevels];
-  const T* gbx[kTailMaxLevels];             // global face coefficients
-  const T* gby[kTailMaxLevels];
-  const T* gbz[kTailMaxLevels];
   int obx[kTailMaxLevels], oby[kTailMaxLevels], obz[kTailMaxLevels];  // LDS offsets (elements)
-  int ob[kTailMaxLevels], oe[kTailMaxLevels];
-  const T* gb;                              // right-hand side of the first tail level
-  T* ge;                                    // its correction (output)
+  int ob[kTailMaxLevels], oe[kTailMaxLevels], oid[kTailMaxLevels];
+  // staging: segment sg copies seg_start[sg+1] - seg_start[sg] elements from
+  // seg_src[sg] to LDS offset seg_dst[sg]
+  int nseg;
+  const T* seg_src[3 * kTailMaxLevels + 1];
+  int seg_dst[3 * kTailMaxLevels + 1];
+  int seg_start[3 * kTailMaxLevels + 2];
+  T* ge;                                    // correction of the first tail level (output)
 };
 
 enum FinMode { FIN_RESID0 = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_RR = 3, FIN_BETA = 4, FIN_TRR = 5 };
+
+// Per-block partial sums and the CG scalars.
+struct CgScratch {
+  double* partials;
+  double* scal;
+};
 
 // ---------------------------------------------------------------- launchers
 // grid step kernels (ns_grid.hip)
@@ -116,15 +126,20 @@ int diag_blocks(const Phys& P);
 // multigrid and CG kernels (ns_mg.hip)
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
-               int first, hipStream_t st, KTimer* kt = nullptr);
+               hipStream_t st, KTimer* kt = nullptr);
+template <typename T>
+void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, const T* invd,
+                     T* e, hipStream_t st);
+template <typename T>
+void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
+                       const Level& C, const T* ec, hipStream_t st);
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
                            const T* e, const Level& C, T* bc, hipStream_t st);
 template <typename T>
 void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, hipStream_t st);
 template <typename T>
-void launch_coarse_solve(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
-                         int sweeps, hipStream_t st);
+void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, hipStream_t st);
 template <typename T>
 void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C,
                          T* cbx, T* cby, T* cbz, hipStream_t st);
@@ -137,19 +152,17 @@ void launch_f2d(const float* a, double* b, size_t n, hipStream_t st);
 
 int cg_blocks(const Dims& n);
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
-                       const double* b, const double* x, double* r, double* partials, hipStream_t st);
-void launch_spmv_dot(const Dims& n, double h, const double* bx, const double* by, const double* bz,
-                     const double* d, double* q, double* partials, hipStream_t st,
-                     KTimer* kt = nullptr);
+                       const double* b, const double* x, double* r, const CgScratch& cs, int mode,
+                       hipStream_t st);
+void launch_dot_rho(const Dims& n, const double* r, const double* z, const CgScratch& cs, hipStream_t st);
+void launch_dots_beta(const Dims& n, const double* r, const double* zn, const double* z,
+                      const CgScratch& cs, hipStream_t st);
+void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,
+                     const double* zn, const double* dold, double* dnew, double* q, int first,
+                     const CgScratch& cs, hipStream_t st, KTimer* kt = nullptr);
+void launch_cg_update(const Dims& n, const double* d, const double* q, double* x, double* r,
+                      const CgScratch& cs, hipStream_t st);
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                     const double* x, double* y, hipStream_t st);
-void launch_cg_update(const Dims& n, const double* scal, const double* d, const double* q, double* x,
-                      double* r, double* partials, hipStream_t st);
-void launch_dots2(const Dims& n, const double* r, const double* zn, const double* z, double* partials,
-                  hipStream_t st);
-void launch_dot1(const Dims& n, const double* a, const double* b, double* partials, hipStream_t st);
-void launch_cg_dir(const Dims& n, const double* scal, const double* zn, double* d, int first,
-                   hipStream_t st);
-void launch_finalize(const double* partials, int nparts, int mode, double* scal, hipStream_t st);
 
 }  // namespace nsk

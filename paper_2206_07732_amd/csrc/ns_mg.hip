@@ -5,9 +5,22 @@
 // sums all six faces; the open top face couples to the ghost -x_c):
 //   (A x)_c = (1/h^2) [ sum_f beta_f (x_c - x_nb) + 2 beta_top x_c (top row) ]
 // V-cycle kernels are templated on the arithmetic type (double or float);
-// the CG vectors and their reductions are always FP64.  Reductions are
-// deterministic: wavefront shuffle, then LDS across the block's four
-// wavefronts, then one fixed-order pass over the per-block partials.
+// the CG vectors and their reductions are always FP64.
+//
+// Launch count, not bandwidth, limits the small levels, so the schedule fuses
+// what the algorithm allows:
+//   * the first pre-smoothing pass (red from a zero guess) and the black pass
+//     after it are one kernel: the red values h^2 b / D are recomputed by
+//     the black cells from b and 1/D;
+//   * prolongation and the first post-smoothing (black) pass are one kernel:
+//     the black cells read their red neighbours plus the parent correction,
+//     and the red cells are left for the red pass that follows, which
+//     overwrites them without reading them;
+//   * all levels from about a thousand cells down run in one workgroup out of
+//     LDS;
+//   * the direction update d = z + beta d is folded into the operator
+//     application; every CG reduction ends in one fixed-order pass over the
+//     per-block partials, so results are bitwise reproducible.
 #include <hip/hip_ext.h>
 
 #include "ns_internal.h"
@@ -49,64 +62,129 @@ __device__ __forceinline__ T stencil(const Dims& n, const T* __restrict__ bx, co
   return acc;
 }
 
-// reduce NV doubles over a 256-thread block (4 wavefronts), thread 0 writes
+// --------------------------------------------------------------- reductions
+__device__ __forceinline__ int block_tid() {
+  return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+}
+
+// sum NV values over the block; the totals end in thread 0 (fixed tree)
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ partials) {
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] += __shfl_down(v[q], off, 64);
-  __shared__ double sm[4][NV];
-  const int tid = threadIdx.x + 64 * (threadIdx.y + blockDim.y * threadIdx.z);
-  const int lane = tid & 63, wid = tid >> 6;
-  if (lane == 0)
+  __shared__ double sm[16][NV];
+  const int tid = block_tid();
+  const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) >> 6;
+  if ((tid & 63) == 0)
 #pragma unroll
-    for (int q = 0; q < NV; ++q) sm[wid][q] = v[q];
+    for (int q = 0; q < NV; ++q) sm[tid >> 6][q] = v[q];
   __syncthreads();
   if (tid == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sm[w][q];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// write the block's NV sums to partials[NV * block + q] (thread 0)
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ partials) {
+  block_sum<NV>(v);
+  if (block_tid() == 0) {
     const size_t blk = blockIdx.x + gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) partials[NV * blk + q] = (sm[0][q] + sm[1][q]) + (sm[2][q] + sm[3][q]);
+    for (int q = 0; q < NV; ++q) partials[NV * blk + q] = v[q];
   }
 }
 
-// --------------------------------------------------------------- smoother
-// One colour of Gauss-Seidel.  Thread ti owns the cell pair (2ti, 2ti+1) of
-// its row and updates the one of the requested colour.  With first != 0 the
-// correction is taken as zero before the pass: the colour cell gets
-// h^2 b / D and the other cell of the pair is cleared.
-// FINE marks the finest-level instance (a separate symbol for profiling).
+// --------------------------------------------------------------- smoothers
+// Threads own cell pairs (2ti, 2ti+1) of a row; the red cell of the pair is
+// 2ti + ((j+k) & 1), the black one the other.
+#define PAIR_INDEX                                           \
+  const int ti = blockIdx.x * blockDim.x + threadIdx.x;      \
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;       \
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;       \
+  if (j >= n.ny || k >= n.nz) return;                        \
+  const size_t sxy = (size_t)n.nx * n.ny;                    \
+  const size_t row = (size_t)n.nx * j + sxy * k
+
+// one colour of Gauss-Seidel (FINE: finest-level instance, own symbol)
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx,
                                             const T* __restrict__ by, const T* __restrict__ bz,
-                                            const T* __restrict__ b, T* __restrict__ e, int colour,
-                                            int first) {
-  const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
-  if (j >= n.ny || k >= n.nz) return;
-  const int par = (j + k + colour) & 1;
-  const int i = 2 * ti + par;
-  const size_t sxy = (size_t)n.nx * n.ny;
-  const size_t row = (size_t)n.nx * j + sxy * k;
-  if (first) {
-    const int io = 2 * ti + 1 - par;
-    if (io < n.nx) e[row + io] = (T)0;
-  }
+                                            const T* __restrict__ b, T* __restrict__ e, int colour) {
+  PAIR_INDEX;
+  const int i = 2 * ti + ((j + k + colour) & 1);
   if (i >= n.nx) return;
   const size_t c = row + i;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c],
-          bu = bz[c + sxy];
+  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
   const bool top = (k == n.nz - 1);
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  T num = h2 * b[c];
-  if (!first) {
-    num += bw * e[i > 0 ? c - 1 : c] + be * e[i < n.nx - 1 ? c + 1 : c] +
-           bs * e[j > 0 ? c - n.nx : c] + bn * e[j < n.ny - 1 ? c + n.nx : c] +
-           bd * e[k > 0 ? c - sxy : c] + (top ? (T)0 : bu * e[c + sxy]);
-  }
+  // wall neighbours are skipped, never read through a clamped index
+  const T num = h2 * b[c] + (i > 0 ? bw * e[c - 1] : (T)0) + (i < n.nx - 1 ? be * e[c + 1] : (T)0) +
+                (j > 0 ? bs * e[c - n.nx] : (T)0) + (j < n.ny - 1 ? bn * e[c + n.nx] : (T)0) +
+                (k > 0 ? bd * e[c - sxy] : (T)0) + (top ? (T)0 : bu * e[c + sxy]);
+  e[c] = num / diag;
+}
+
+// red pass from a zero guess followed by the black pass, in one launch
+template <typename T, bool FINE>
+__global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx,
+                                                  const T* __restrict__ by, const T* __restrict__ bz,
+                                                  const T* __restrict__ b, const T* __restrict__ invd,
+                                                  T* __restrict__ e) {
+  PAIR_INDEX;
+  const int par = (j + k) & 1;
+  const int ir = 2 * ti + par, ib = 2 * ti + 1 - par;
+  if (ir < n.nx) e[row + ir] = h2 * b[row + ir] * invd[row + ir];
+  if (ib >= n.nx) return;
+  const int i = ib;
+  const size_t c = row + i;
+  auto red = [&](size_t q) { return h2 * b[q] * invd[q]; };
+  const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+  const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  const bool top = (k == n.nz - 1);
+  const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
+  const T num = h2 * b[c] + bw * red(i > 0 ? c - 1 : c) + be * red(i < n.nx - 1 ? c + 1 : c) +
+                bs * red(j > 0 ? c - n.nx : c) + bn * red(j < n.ny - 1 ? c + n.nx : c) +
+                bd * red(k > 0 ? c - sxy : c) + (top ? (T)0 : bu * red(c + sxy));
+  e[c] = num / diag;
+}
+
+// prolongation e += P ec followed by the black pass, in one launch; only the
+// black cells are written (the red pass that follows overwrites the red ones
+// without reading them)
+template <typename T, bool FINE>
+__global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx,
+                                                    const T* __restrict__ by, const T* __restrict__ bz,
+                                                    const T* __restrict__ b, T* __restrict__ e, Dims nc,
+                                                    int fxc, int fyc, int fzc, const T* __restrict__ ec) {
+  PAIR_INDEX;
+  const int i = 2 * ti + 1 - ((j + k) & 1);   // the black cell
+  if (i >= n.nx) return;
+  const size_t c = row + i;
+  auto up = [&](int ii, int jj, int kk) {
+    const size_t q = ii + (size_t)n.nx * jj + sxy * kk;
+    return e[q] + ec[(ii / fxc) + (size_t)nc.nx * ((jj / fyc) + (size_t)nc.ny * (kk / fzc))];
+  };
+  const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+  const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  const bool top = (k == n.nz - 1);
+  const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
+  // wall faces carry beta = 0: their (clamped) neighbour is never used
+  const T num = h2 * b[c] + (i > 0 ? bw * up(i - 1, j, k) : (T)0) + (i < n.nx - 1 ? be * up(i + 1, j, k) : (T)0) +
+                (j > 0 ? bs * up(i, j - 1, k) : (T)0) + (j < n.ny - 1 ? bn * up(i, j + 1, k) : (T)0) +
+                (k > 0 ? bd * up(i, j, k - 1) : (T)0) + (top ? (T)0 : bu * up(i, j, k + 1));
   e[c] = num / diag;
 }
 
@@ -134,7 +212,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
   bc[I + (size_t)nc.nx * (J + (size_t)nc.ny * K)] = sum * inv;
 }
 
-// fine correction += parent's coarse correction
+// fine correction += parent's coarse correction (used when nu_post == 0)
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong(Dims nf, int fx, int fy, int fz, T* __restrict__ e,
                                                  Dims nc, const T* __restrict__ ec) {
@@ -146,45 +224,22 @@ __global__ void __launch_bounds__(256) k_prolong(Dims nf, int fx, int fy, int fz
       ec[(i / fx) + (size_t)nc.nx * ((j / fy) + (size_t)nc.ny * (k / fz))];
 }
 
-// coarsest level: `sweeps` red-black pairs forward then backward, from zero,
-// in one workgroup
+// 1 / (sum of the cell's face coefficients, top face counted twice)
 template <typename T>
-__global__ void __launch_bounds__(256) k_coarse_solve(Dims n, T h2, const T* __restrict__ bx,
-                                                      const T* __restrict__ by,
-                                                      const T* __restrict__ bz,
-                                                      const T* __restrict__ b, T* __restrict__ e,
-                                                      int sweeps) {
-  const int N = n.nx * n.ny * n.nz;
+__global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ bx,
+                                                 const T* __restrict__ by, const T* __restrict__ bz,
+                                                 T* __restrict__ invd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t sxy = (size_t)n.nx * n.ny;
-  for (int c = threadIdx.x; c < N; c += blockDim.x) e[c] = (T)0;
-  __syncthreads();
-  auto pass = [&](int colour) {
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-      const int i = c % n.nx;
-      const int j = (c / n.nx) % n.ny;
-      const int k = c / (int)sxy;
-      if (((i + j + k) & 1) != colour) continue;
-      const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
-      const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-      const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c],
-              bu = bz[c + sxy];
-      const bool top = (k == n.nz - 1);
-      const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-      const T num = h2 * b[c] + bw * e[i > 0 ? c - 1 : c] + be * e[i < n.nx - 1 ? c + 1 : c] +
-                    bs * e[j > 0 ? c - n.nx : c] + bn * e[j < n.ny - 1 ? c + n.nx : c] +
-                    bd * e[k > 0 ? c - sxy : c] + (top ? (T)0 : bu * e[c + sxy]);
-      e[c] = num / diag;
-    }
-    __syncthreads();
-  };
-  for (int s = 0; s < sweeps; ++s) {
-    pass(0);
-    pass(1);
-  }
-  for (int s = 0; s < sweeps; ++s) {
-    pass(1);
-    pass(0);
-  }
+  const size_t c = i + (size_t)n.nx * j + sxy * k;
+  const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+  const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+  const T bu = bz[c + sxy];
+  const T diag = bx[fx] + bx[fx + 1] + by[fy] + by[fy + n.nx] + bz[c] + (k == n.nz - 1 ? (T)2 * bu : bu);
+  invd[c] = (T)1 / diag;
 }
 
 // coarse face coefficient = mean of the fine faces covering it
@@ -209,80 +264,118 @@ __global__ void __launch_bounds__(256) k_coarsen_beta(Dims nf, int fx, int fy, i
   cb[I + (size_t)mx * (J + (size_t)my * K)] = sum / (T)(ni * nj * nk);
 }
 
-
 // ------------------------------------------------------- coarse-level tail
-// All levels from `first` down to the coarsest run in one workgroup of 1024
-// threads with coefficients, right-hand sides and corrections held in LDS,
-// so that each smoothing pass costs a barrier instead of a kernel launch.
-template <typename T>
-__device__ __forceinline__ void tail_gs(const Dims& n, T h2, const T* bx, const T* by, const T* bz,
-                                        const T* b, T* e, int colour, bool first) {
-  const int N = n.nx * n.ny * n.nz;
-  const int sxy = n.nx * n.ny;
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    const int i = c % n.nx;
-    const int j = (c / n.nx) % n.ny;
-    const int k = c / sxy;
-    const bool mine = ((i + j + k) & 1) == colour;
-    if (!mine) {
-      if (first) e[c] = (T)0;
-      continue;
+// Every level from the first tail level down to the coarsest runs in one
+// workgroup with coefficients, 1/D, right-hand sides and corrections held in
+// LDS, so a smoothing pass costs a barrier instead of a launch.  Levels whose
+// cell pairs fit one wavefront run in wavefront 0 alone, ordered by
+// wavefront-level fences instead of workgroup barriers.  Each thread decodes
+// its cell pairs once per level visit.
+struct TailPairs {
+  int ti[2], j[2], k[2];
+  int np;
+};
+
+// lanes 0..nthr-1 take pairs t and t + nthr
+__device__ __forceinline__ void tail_decode(const Dims& n, int tid, int nthr, TailPairs& tp) {
+  const int hx = (n.nx + 1) >> 1;
+  const int NP = hx * n.ny * n.nz;
+  tp.np = 0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int t = tid + q * nthr;
+    if (t < NP) {
+      tp.ti[q] = t % hx;
+      const int r = t / hx;
+      tp.j[q] = r % n.ny;
+      tp.k[q] = r / n.ny;
+      tp.np = q + 1;
     }
-    const int fx = i + (n.nx + 1) * (j + n.ny * k);
-    const int fy = i + n.nx * (j + (n.ny + 1) * k);
-    const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
-    const bool top = (k == n.nz - 1);
-    const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-    T num = h2 * b[c];
-    if (!first) {
-      num += bw * e[i > 0 ? c - 1 : c] + be * e[i < n.nx - 1 ? c + 1 : c] +
-             bs * e[j > 0 ? c - n.nx : c] + bn * e[j < n.ny - 1 ? c + n.nx : c] +
-             bd * e[k > 0 ? c - sxy : c] + (top ? (T)0 : bu * e[c + sxy]);
-    }
-    e[c] = num / diag;
   }
-  __syncthreads();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_vcycle_tail(TailDesc<T> D) {
-  extern __shared__ double tail_smem[];
-  T* sm = reinterpret_cast<T*>(tail_smem);
-  const int nl = D.nl;
-  // stage coefficients of every tail level and the first right-hand side
-  for (int l = 0; l < nl; ++l) {
-    const Dims n = D.n[l];
-    const int mu = (n.nx + 1) * n.ny * n.nz, mv = n.nx * (n.ny + 1) * n.nz, mw = n.nx * n.ny * (n.nz + 1);
-    for (int q = threadIdx.x; q < mu; q += blockDim.x) sm[D.obx[l] + q] = D.gbx[l][q];
-    for (int q = threadIdx.x; q < mv; q += blockDim.x) sm[D.oby[l] + q] = D.gby[l][q];
-    for (int q = threadIdx.x; q < mw; q += blockDim.x) sm[D.obz[l] + q] = D.gbz[l][q];
+// ordering point between two phases: a workgroup barrier, or (WAVE) a
+// wavefront-level fence for phases run by wavefront 0 alone
+template <bool WAVE>
+__device__ __forceinline__ void tail_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
   }
-  {
-    const int N0 = D.n[0].nx * D.n[0].ny * D.n[0].nz;
-    for (int q = threadIdx.x; q < N0; q += blockDim.x) sm[D.ob[0] + q] = D.gb[q];
+}
+
+template <typename T, bool WAVE>
+__device__ __forceinline__ void tail_pass(const Dims& n, const TailPairs& tp, T h2, const T* bx, const T* by,
+                                          const T* bz, const T* invd, const T* b, T* e, int colour,
+                                          bool from_zero) {
+  const int sxy = n.nx * n.ny;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {   // compile-time index: the pairs stay in registers
+    if (q >= tp.np) break;
+    const int j = tp.j[q], k = tp.k[q];
+    const int i = 2 * tp.ti[q] + ((j + k + colour) & 1);
+    if (i < n.nx) {
+      const int c = i + n.nx * j + sxy * k;
+      T num = h2 * b[c];
+      if (!from_zero) {
+        // wall faces are skipped outright: a cell's own entry may still be
+        // unset after a red pass from zero, and 0 * garbage need not be 0
+        const int fx = i + (n.nx + 1) * (j + n.ny * k);
+        const int fy = i + n.nx * (j + (n.ny + 1) * k);
+        if (i > 0) num += bx[fx] * e[c - 1];
+        if (i < n.nx - 1) num += bx[fx + 1] * e[c + 1];
+        if (j > 0) num += by[fy] * e[c - n.nx];
+        if (j < n.ny - 1) num += by[fy + n.nx] * e[c + n.nx];
+        if (k > 0) num += bz[c] * e[c - sxy];
+        if (k < n.nz - 1) num += bz[c + sxy] * e[c + sxy];
+      }
+      e[c] = num * invd[c];
+    }
   }
-  __syncthreads();
-  auto smooth = [&](int l, int first_colour, int pairs, bool from_zero) {
+  tail_sync<WAVE>();
+}
+
+// One level's share of the tail, run either by the whole workgroup or (WAVE)
+// by wavefront 0 alone.
+template <typename T, bool WAVE>
+struct TailLevel {
+  const TailDesc<T>& D;
+  T* sm;
+  int tid, nthr;
+
+  __device__ void smooth(int l, const TailPairs& tp, int first_colour, int pairs, bool from_zero) const {
     const Dims n = D.n[l];
     const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l], *b = sm + D.ob[l];
+    const T* invd = sm + D.oid[l];
     T* e = sm + D.oe[l];
+    const T h2 = D.h2[l];
     for (int s = 0; s < pairs; ++s) {
-      tail_gs<T>(n, D.h2[l], bx, by, bz, b, e, first_colour, from_zero && s == 0);
-      tail_gs<T>(n, D.h2[l], bx, by, bz, b, e, 1 - first_colour, false);
+      tail_pass<T, WAVE>(n, tp, h2, bx, by, bz, invd, b, e, first_colour, from_zero && s == 0);
+      tail_pass<T, WAVE>(n, tp, h2, bx, by, bz, invd, b, e, 1 - first_colour, false);
     }
-  };
-  auto zero = [&](int l) {
+  }
+
+  __device__ void zero(int l) const {
     const int N = D.n[l].nx * D.n[l].ny * D.n[l].nz;
     T* e = sm + D.oe[l];
-    for (int c = threadIdx.x; c < N; c += blockDim.x) e[c] = (T)0;
-    __syncthreads();
-  };
-  // down-leg
-  for (int l = 0; l < nl - 1; ++l) {
-    if (D.nu_pre > 0)
-      smooth(l, 0, D.nu_pre, true);
-    else
+    for (int c = tid; c < N; c += nthr) e[c] = (T)0;
+    tail_sync<WAVE>();
+  }
+
+  // pre-smoothing, then the restricted residual into the next level's b
+  __device__ void down(int l) const {
+    TailPairs tp;
+    tail_decode(D.n[l], tid, nthr, tp);
+    if (D.nu_pre > 0) {
+      // the red pass from zero leaves the black cells unset; the black pass
+      // that follows writes every one of them before anything reads them
+      smooth(l, tp, 0, D.nu_pre, true);
+    } else {
       zero(l);
+    }
     const Dims nf = D.n[l], nc = D.n[l + 1];
     const int fx = D.f[l][0], fy = D.f[l][1], fz = D.f[l][2];
     const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l], *b = sm + D.ob[l];
@@ -292,7 +385,7 @@ __global__ void __launch_bounds__(1024) k_vcycle_tail(TailDesc<T> D) {
     const T inv = (T)1 / (T)(fx * fy * fz);
     const int Nc = nc.nx * nc.ny * nc.nz;
     const int sxy = nf.nx * nf.ny;
-    for (int C = threadIdx.x; C < Nc; C += blockDim.x) {
+    for (int C = tid; C < Nc; C += nthr) {
       const int I = C % nc.nx, J = (C / nc.nx) % nc.ny, K = C / (nc.nx * nc.ny);
       T sum = 0;
       for (int dk = 0; dk < fz; ++dk)
@@ -303,44 +396,114 @@ __global__ void __launch_bounds__(1024) k_vcycle_tail(TailDesc<T> D) {
             const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
             const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
             const T xc = e[c];
-            T acc = bx[ix] * (xc - e[i > 0 ? c - 1 : c]) + bx[ix + 1] * (xc - e[i < nf.nx - 1 ? c + 1 : c]) +
-                    by[iy] * (xc - e[j > 0 ? c - nf.nx : c]) +
-                    by[iy + nf.nx] * (xc - e[j < nf.ny - 1 ? c + nf.nx : c]) +
-                    bz[c] * (xc - e[k > 0 ? c - sxy : c]);
+            T acc = 0;
+            if (i > 0) acc += bx[ix] * (xc - e[c - 1]);
+            if (i < nf.nx - 1) acc += bx[ix + 1] * (xc - e[c + 1]);
+            if (j > 0) acc += by[iy] * (xc - e[c - nf.nx]);
+            if (j < nf.ny - 1) acc += by[iy + nf.nx] * (xc - e[c + nf.nx]);
+            if (k > 0) acc += bz[c] * (xc - e[c - sxy]);
             acc += (k < nf.nz - 1) ? bz[c + sxy] * (xc - e[c + sxy]) : (T)2 * bz[c + sxy] * xc;
             sum += b[c] - ih2 * acc;
           }
       bc[C] = sum * inv;
     }
-    __syncthreads();
+    tail_sync<WAVE>();
   }
+
   // coarsest level: sweeps forward (red, black) then backward (black, red) from zero
-  {
-    const int l = nl - 1;
+  __device__ void coarsest(int l) const {
     if (D.coarse_sweeps > 0) {
-      smooth(l, 0, D.coarse_sweeps, true);
-      smooth(l, 1, D.coarse_sweeps, false);
+      TailPairs tp;
+      tail_decode(D.n[l], tid, nthr, tp);
+      smooth(l, tp, 0, D.coarse_sweeps, true);
+      smooth(l, tp, 1, D.coarse_sweeps, false);
     } else {
       zero(l);
     }
   }
-  // up-leg
-  for (int l = nl - 2; l >= 0; --l) {
+
+  // prolongation of the next level's correction, then post-smoothing
+  __device__ void up(int l) const {
     const Dims nf = D.n[l], nc = D.n[l + 1];
     const int fx = D.f[l][0], fy = D.f[l][1], fz = D.f[l][2];
     T* e = sm + D.oe[l];
     const T* ec = sm + D.oe[l + 1];
     const int N = nf.nx * nf.ny * nf.nz;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    for (int c = tid; c < N; c += nthr) {
       const int i = c % nf.nx, j = (c / nf.nx) % nf.ny, k = c / (nf.nx * nf.ny);
       e[c] += ec[(i / fx) + nc.nx * ((j / fy) + nc.ny * (k / fz))];
     }
-    __syncthreads();
-    smooth(l, 1, D.nu_post, false);
+    tail_sync<WAVE>();
+    TailPairs tp;
+    tail_decode(nf, tid, nthr, tp);
+    smooth(l, tp, 1, D.nu_post, false);
   }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailDesc<T> D) {
+  extern __shared__ double tail_smem[];
+  T* sm = reinterpret_cast<T*>(tail_smem);
+  const int nl = D.nl;
+  const int tid = threadIdx.x;
+  // stage every coefficient array and the first right-hand side: one flat
+  // loop over all segments with eight independent loads in flight per thread
+  {
+    const int total = D.seg_start[D.nseg];
+    for (int base = tid; base < total; base += 8 * kTailThreads) {
+      T v[8];
+      int dst[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = base + u * kTailThreads;
+        dst[u] = -1;
+        if (q < total) {
+          int sg = 0;
+          while (q >= D.seg_start[sg + 1]) ++sg;
+          const int o = q - D.seg_start[sg];
+          v[u] = D.seg_src[sg][o];
+          dst[u] = D.seg_dst[sg] + o;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (dst[u] >= 0) sm[dst[u]] = v[u];
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < nl; ++l) {
+    const Dims n = D.n[l];
+    const int N = n.nx * n.ny * n.nz, sxy = n.nx * n.ny;
+    const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l];
+    T* invd = sm + D.oid[l];
+    for (int c = tid; c < N; c += kTailThreads) {
+      const int i = c % n.nx, j = (c / n.nx) % n.ny, k = c / sxy;
+      const int fx = i + (n.nx + 1) * (j + n.ny * k);
+      const int fy = i + n.nx * (j + (n.ny + 1) * k);
+      const T bu = bz[c + sxy];
+      invd[c] = (T)1 / (bx[fx] + bx[fx + 1] + by[fy] + by[fy + n.nx] + bz[c] + (k == n.nz - 1 ? (T)2 * bu : bu));
+    }
+  }
+  __syncthreads();
+  // first level (ls) from which every level fits one wavefront
+  int ls = nl;
+  while (ls > 0 && ((D.n[ls - 1].nx + 1) / 2) * D.n[ls - 1].ny * D.n[ls - 1].nz <= 64) --ls;
+  const TailLevel<T, false> big{D, sm, tid, kTailThreads};
+  for (int l = 0; l < ls && l < nl - 1; ++l) big.down(l);
+  if (ls >= nl) big.coarsest(nl - 1);
+  if (ls < nl) {
+    if (tid < 64) {
+      const TailLevel<T, true> small{D, sm, tid, 64};
+      for (int l = ls; l < nl - 1; ++l) small.down(l);
+      small.coarsest(nl - 1);
+      for (int l = nl - 2; l >= ls; --l) small.up(l);
+    }
+    __syncthreads();
+  }
+  for (int l = (ls < nl ? ls : nl - 1) - 1; l >= 0; --l) big.up(l);
   {
     const int N0 = D.n[0].nx * D.n[0].ny * D.n[0].nz;
-    for (int q = threadIdx.x; q < N0; q += blockDim.x) D.ge[q] = sm[D.oe[0] + q];
+    for (int q = tid; q < N0; q += kTailThreads) D.ge[q] = sm[D.oe[0] + q];
   }
 }
 
@@ -368,7 +531,7 @@ __global__ void k_f2d(const float* __restrict__ a, double* __restrict__ b, size_
   const bool inside = (i < n.nx && j < n.ny && k < n.nz);       \
   const size_t c = inside ? i + (size_t)n.nx * (j + (size_t)n.ny * k) : 0
 
-// r = b - A x; partials (r.r, b.b)
+// r = b - A x; totals (r.r, b.b) -> scal (RESID0: S_RR, S_BB; TRR: S_TRR)
 __global__ void __launch_bounds__(256) k_resid_norm(Dims n, double ih2, const double* __restrict__ bx,
                                                     const double* __restrict__ by,
                                                     const double* __restrict__ bz,
@@ -388,37 +551,67 @@ __global__ void __launch_bounds__(256) k_resid_norm(Dims n, double ih2, const do
   block_partials<2>(v, partials);
 }
 
-// q = A d; partial d.q
-__global__ void __launch_bounds__(256) k_spmv_dot(Dims n, double ih2, const double* __restrict__ bx,
+// rho = <r, z>
+__global__ void __launch_bounds__(256) k_dot_rho(Dims n, const double* __restrict__ r,
+                                                 const double* __restrict__ z, double* __restrict__ partials) {
+  CELL_INDEX;
+  double v[1] = {inside ? r[c] * z[c] : 0.0};
+  block_partials<1>(v, partials);
+}
+
+// flexible (Polak-Ribiere) beta = (<r, zn> - <r, z>) / rho, then rho = <r, zn>
+__global__ void __launch_bounds__(256) k_dots_beta(Dims n, const double* __restrict__ r,
+                                                   const double* __restrict__ zn,
+                                                   const double* __restrict__ z,
+                                                   double* __restrict__ partials) {
+  CELL_INDEX;
+  double v[2] = {0.0, 0.0};
+  if (inside) {
+    const double rc = r[c];
+    v[0] = rc * zn[c];
+    v[1] = rc * z[c];
+  }
+  block_partials<2>(v, partials);
+}
+
+// d = zn + beta d_old (first: d = zn); q = A d; alpha = rho / <d, q>
+__global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const double* __restrict__ bx,
                                                   const double* __restrict__ by,
                                                   const double* __restrict__ bz,
-                                                  const double* __restrict__ d,
-                                                  double* __restrict__ q,
+                                                  const double* __restrict__ zn,
+                                                  const double* __restrict__ dold,
+                                                  double* __restrict__ dnew, double* __restrict__ q,
+                                                  int first, const double* __restrict__ scal,
                                                   double* __restrict__ partials) {
   CELL_INDEX;
   double v[1] = {0.0};
   if (inside) {
-    const double qc = ih2 * stencil<double>(n, bx, by, bz, d, i, j, k, c);
+    const double beta = first ? 0.0 : scal[S_BETA];
+    auto D = [&](size_t p) { return first ? zn[p] : zn[p] + beta * dold[p]; };
+    const size_t sxy = (size_t)n.nx * n.ny;
+    const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+    const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+    const double dc = D(c);
+    const double bu = bz[c + sxy];
+    double acc = bx[fx] * (dc - D(i > 0 ? c - 1 : c)) + bx[fx + 1] * (dc - D(i < n.nx - 1 ? c + 1 : c)) +
+                 by[fy] * (dc - D(j > 0 ? c - n.nx : c)) + by[fy + n.nx] * (dc - D(j < n.ny - 1 ? c + n.nx : c)) +
+                 bz[c] * (dc - D(k > 0 ? c - sxy : c));
+    if (k < n.nz - 1)
+      acc += bu * (dc - D(c + sxy));
+    else
+      acc += 2.0 * bu * dc;
+    const double qc = ih2 * acc;
+    dnew[c] = dc;
     q[c] = qc;
-    v[0] = d[c] * qc;
+    v[0] = dc * qc;
   }
   block_partials<1>(v, partials);
 }
 
-__global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const double* __restrict__ bx,
-                                                 const double* __restrict__ by,
-                                                 const double* __restrict__ bz,
-                                                 const double* __restrict__ x,
-                                                 double* __restrict__ y) {
-  CELL_INDEX;
-  if (inside) y[c] = ih2 * stencil<double>(n, bx, by, bz, x, i, j, k, c);
-}
-
-// x += alpha d; r -= alpha q; partial r.r
-__global__ void __launch_bounds__(256) k_cg_update(Dims n, const double* __restrict__ scal,
-                                                   const double* __restrict__ d,
-                                                   const double* __restrict__ q,
-                                                   double* __restrict__ x, double* __restrict__ r,
+// x += alpha d; r -= alpha q; ||r||^2
+__global__ void __launch_bounds__(256) k_cg_update(Dims n, const double* __restrict__ d,
+                                                   const double* __restrict__ q, double* __restrict__ x,
+                                                   double* __restrict__ r, const double* __restrict__ scal,
                                                    double* __restrict__ partials) {
   CELL_INDEX;
   double v[1] = {0.0};
@@ -432,108 +625,72 @@ __global__ void __launch_bounds__(256) k_cg_update(Dims n, const double* __restr
   block_partials<1>(v, partials);
 }
 
-// partials (r.zn, r.z)
-__global__ void __launch_bounds__(256) k_dots2(Dims n, const double* __restrict__ r,
-                                               const double* __restrict__ zn,
-                                               const double* __restrict__ z,
-                                               double* __restrict__ partials) {
+__global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const double* __restrict__ bx,
+                                                 const double* __restrict__ by,
+                                                 const double* __restrict__ bz,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ y) {
   CELL_INDEX;
-  double v[2] = {0.0, 0.0};
-  if (inside) {
-    const double rc = r[c];
-    v[0] = rc * zn[c];
-    v[1] = rc * z[c];
-  }
-  block_partials<2>(v, partials);
+  if (inside) y[c] = ih2 * stencil<double>(n, bx, by, bz, x, i, j, k, c);
 }
 
-__global__ void __launch_bounds__(256) k_dot1(Dims n, const double* __restrict__ a,
-                                              const double* __restrict__ b,
-                                              double* __restrict__ partials) {
-  CELL_INDEX;
-  double v[1] = {0.0};
-  if (inside) v[0] = a[c] * b[c];
-  block_partials<1>(v, partials);
-}
 
-// d = zn + beta d   (first: d = zn)
-__global__ void __launch_bounds__(256) k_cg_dir(Dims n, const double* __restrict__ scal,
-                                                const double* __restrict__ zn,
-                                                double* __restrict__ d, int first) {
-  CELL_INDEX;
-  if (!inside) return;
-  d[c] = first ? zn[c] : zn[c] + scal[S_BETA] * d[c];
-}
-
-// fixed-order sum of the per-block partials and the scalar recurrences
+// fixed-order sum of the per-block partials and the CG scalar recurrences
 __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ partials, int nparts,
                                                    int nv, int mode, double* __restrict__ scal) {
-  double a = 0.0, b = 0.0;
+  double v[2] = {0.0, 0.0};
   for (int q = threadIdx.x; q < nparts; q += 1024) {
-    a += partials[nv * q];
-    if (nv > 1) b += partials[nv * q + 1];
+    v[0] += partials[nv * q];
+    if (nv > 1) v[1] += partials[nv * q + 1];
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off, 64);
-    b += __shfl_down(b, off, 64);
-  }
-  __shared__ double sa[16], sb[16];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    sa[wid] = a;
-    sb[wid] = b;
-  }
-  __syncthreads();
+  block_sum<2>(v);
   if (threadIdx.x == 0) {
-    a = 0.0;
-    b = 0.0;
-    for (int q = 0; q < 16; ++q) {
-      a += sa[q];
-      b += sb[q];
-    }
+    const double a = v[0], b = v[1];
     switch (mode) {
-      case FIN_RESID0:
-        scal[S_RR] = a;
-        scal[S_BB] = b;
-        break;
-      case FIN_RHO:
-        scal[S_RHO] = a;
-        break;
-      case FIN_ALPHA:
-        scal[S_DQ] = a;
-        scal[S_ALPHA] = scal[S_RHO] / a;
-        break;
-      case FIN_RR:
-        scal[S_RR] = a;
-        break;
-      case FIN_BETA:
-        scal[S_BETA] = (a - b) / scal[S_RHO];
-        scal[S_RHO] = a;
-        break;
-      case FIN_TRR:
-        scal[S_TRR] = a;
-        break;
+      case FIN_RESID0: scal[S_RR] = a; scal[S_BB] = b; break;
+      case FIN_TRR: scal[S_TRR] = a; break;
+      case FIN_RHO: scal[S_RHO] = a; break;
+      case FIN_BETA: scal[S_BETA] = (a - b) / scal[S_RHO]; scal[S_RHO] = a; break;
+      case FIN_ALPHA: scal[S_DQ] = a; scal[S_ALPHA] = scal[S_RHO] / a; break;
+      case FIN_RR: scal[S_RR] = a; break;
     }
   }
 }
+
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
-               int first, hipStream_t st, KTimer* kt) {
+               hipStream_t st, KTimer* kt) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
   auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
   if (kt && kt->n < kt->cap) {
-    (void)hipStreamSynchronize(st);   // time the kernel alone, not its wait for the previous one
     hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
-                          (T)(L.h * L.h), bx, by, bz, b, e, colour, first);
+                          (T)(L.h * L.h), bx, by, bz, b, e, colour);
     ++kt->n;
     return;
   }
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, first);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour);
+}
+
+template <typename T>
+void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, const T* invd,
+                     T* e, hipStream_t st) {
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
+  auto kern = (L.h == L.h0) ? k_gs_first<T, true> : k_gs_first<T, false>;
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e);
+}
+
+template <typename T>
+void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
+                       const Level& C, const T* ec, hipStream_t st) {
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
+  auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0],
+                     L.f[1], L.f[2], ec);
 }
 
 template <typename T>
@@ -553,10 +710,9 @@ void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, hipStream
 }
 
 template <typename T>
-void launch_coarse_solve(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
-                         int sweeps, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(256), 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b,
-                     e, sweeps);
+void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, hipStream_t st) {
+  Geo g = geo3(L.n.nx, L.n.ny, L.n.nz);
+  hipLaunchKernelGGL(k_invdiag<T>, g.grid, g.block, 0, st, L.n, bx, by, bz, invd);
 }
 
 template <typename T>
@@ -584,6 +740,7 @@ void launch_fill(T* a, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n);
 }
 
+
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
 }
@@ -597,24 +754,56 @@ int cg_blocks(const Dims& n) {
   return (int)(g.grid.x * g.grid.y * g.grid.z);
 }
 
-void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
-                       const double* b, const double* x, double* r, double* partials, hipStream_t st) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
-  hipLaunchKernelGGL(k_resid_norm, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, b, x, r,
-                     partials);
+static void finalize(const CgScratch& cs, int nparts, int mode, hipStream_t st) {
+  const int nv = (mode == FIN_RESID0 || mode == FIN_TRR || mode == FIN_BETA) ? 2 : 1;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, cs.partials, nparts, nv, mode, cs.scal);
 }
 
-void launch_spmv_dot(const Dims& n, double h, const double* bx, const double* by, const double* bz,
-                     const double* d, double* q, double* partials, hipStream_t st, KTimer* kt) {
+void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
+                       const double* b, const double* x, double* r, const CgScratch& cs, int mode,
+                       hipStream_t st) {
+  Geo g = geo3(n.nx, n.ny, n.nz);
+  hipLaunchKernelGGL(k_resid_norm, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, b, x, r,
+                     cs.partials);
+  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), mode, st);
+}
+
+void launch_dot_rho(const Dims& n, const double* r, const double* z, const CgScratch& cs, hipStream_t st) {
+  Geo g = geo3(n.nx, n.ny, n.nz);
+  hipLaunchKernelGGL(k_dot_rho, g.grid, g.block, 0, st, n, r, z, cs.partials);
+  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_RHO, st);
+}
+
+void launch_dots_beta(const Dims& n, const double* r, const double* zn, const double* z,
+                      const CgScratch& cs, hipStream_t st) {
+  Geo g = geo3(n.nx, n.ny, n.nz);
+  hipLaunchKernelGGL(k_dots_beta, g.grid, g.block, 0, st, n, r, zn, z, cs.partials);
+  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_BETA, st);
+}
+
+void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,
+                     const double* zn, const double* dold, double* dnew, double* q, int first,
+                     const CgScratch& cs, hipStream_t st, KTimer* kt) {
   Geo g = geo3(n.nx, n.ny, n.nz);
   if (kt && kt->n < kt->cap) {
     (void)hipStreamSynchronize(st);
-    hipExtLaunchKernelGGL(k_spmv_dot, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1],
-                          0, n, 1.0 / (h * h), bx, by, bz, d, q, partials);
+    hipExtLaunchKernelGGL(k_dir_spmv, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0,
+                          n, 1.0 / (h * h), bx, by, bz, zn, dold, dnew, q, first, (const double*)cs.scal,
+                          cs.partials);
     ++kt->n;
-    return;
+  } else {
+    hipLaunchKernelGGL(k_dir_spmv, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, zn, dold, dnew, q,
+                       first, (const double*)cs.scal, cs.partials);
   }
-  hipLaunchKernelGGL(k_spmv_dot, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, d, q, partials);
+  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_ALPHA, st);
+}
+
+void launch_cg_update(const Dims& n, const double* d, const double* q, double* x, double* r,
+                      const CgScratch& cs, hipStream_t st) {
+  Geo g = geo3(n.nx, n.ny, n.nz);
+  hipLaunchKernelGGL(k_cg_update, g.grid, g.block, 0, st, n, d, q, x, r, (const double*)cs.scal,
+                     cs.partials);
+  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_RR, st);
 }
 
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
@@ -623,45 +812,20 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
   hipLaunchKernelGGL(k_apply_A, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, x, y);
 }
 
-void launch_cg_update(const Dims& n, const double* scal, const double* d, const double* q, double* x,
-                      double* r, double* partials, hipStream_t st) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
-  hipLaunchKernelGGL(k_cg_update, g.grid, g.block, 0, st, n, scal, d, q, x, r, partials);
-}
-
-void launch_dots2(const Dims& n, const double* r, const double* zn, const double* z, double* partials,
-                  hipStream_t st) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
-  hipLaunchKernelGGL(k_dots2, g.grid, g.block, 0, st, n, r, zn, z, partials);
-}
-
-void launch_dot1(const Dims& n, const double* a, const double* b, double* partials, hipStream_t st) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
-  hipLaunchKernelGGL(k_dot1, g.grid, g.block, 0, st, n, a, b, partials);
-}
-
-void launch_cg_dir(const Dims& n, const double* scal, const double* zn, double* d, int first,
-                   hipStream_t st) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
-  hipLaunchKernelGGL(k_cg_dir, g.grid, g.block, 0, st, n, scal, zn, d, first);
-}
-
-void launch_finalize(const double* partials, int nparts, int mode, double* scal, hipStream_t st) {
-  const int nv = (mode == FIN_RESID0 || mode == FIN_BETA || mode == FIN_TRR) ? 2 : 1;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, partials, nparts, nv, mode, scal);
-}
-
-#define NSK_INST(T)                                                                                 \
-  template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int, int,    \
-                             hipStream_t, KTimer*);                                                 \
-  template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*,      \
-                                         const T*, const Level&, T*, hipStream_t);                  \
-  template void launch_prolong<T>(const Level&, T*, const Level&, const T*, hipStream_t);           \
-  template void launch_coarse_solve<T>(const Level&, const T*, const T*, const T*, const T*, T*, int, \
-                                       hipStream_t);                                                \
-  template void launch_coarsen_beta<T>(const Level&, const T*, const T*, const T*, const Level&, T*, \
-                                       T*, T*, hipStream_t);                                        \
-  template void launch_fill<T>(T*, size_t, hipStream_t);                                            \
+#define NSK_INST(T)                                                                                   \
+  template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int,          \
+                             hipStream_t, KTimer*);                                                   \
+  template void launch_gs_first<T>(const Level&, const T*, const T*, const T*, const T*, const T*,   \
+                                   T*, hipStream_t);                                                  \
+  template void launch_gs_prolong<T>(const Level&, const T*, const T*, const T*, const T*, T*,       \
+                                     const Level&, const T*, hipStream_t);                            \
+  template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*,        \
+                                         const T*, const Level&, T*, hipStream_t);                    \
+  template void launch_prolong<T>(const Level&, T*, const Level&, const T*, hipStream_t);             \
+  template void launch_invdiag<T>(const Level&, const T*, const T*, const T*, T*, hipStream_t);       \
+  template void launch_coarsen_beta<T>(const Level&, const T*, const T*, const T*, const Level&, T*,  \
+                                       T*, T*, hipStream_t);                                          \
+  template void launch_fill<T>(T*, size_t, hipStream_t);                                              \
   template void launch_vcycle_tail<T>(const TailDesc<T>&, size_t, hipStream_t);
 NSK_INST(double)
 NSK_INST(float)

@@ -87,6 +87,7 @@ def lib() -> C.CDLL:
             "ns_num_levels": ([i, i, i], i),
             "ns_timing_enable": ([vp, i, i], i),
             "ns_timing_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int)], i),
+            "ns_time_kernel": ([vp, i, i, C.POINTER(C.c_double)], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
         }
@@ -101,7 +102,7 @@ def lib() -> C.CDLL:
 EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
             "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
             "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_timing_enable",
-            "ns_timing_read"]
+            "ns_timing_read", "ns_time_kernel"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
 
 SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2, coarse_sweeps=10,
@@ -250,6 +251,12 @@ class Solver:
         ms, n = C.c_double(), C.c_int()
         self._chk("ns_timing_read", lib().ns_timing_read(self.ctx, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def time_kernel(self, kernel: int, reps: int) -> float:
+        """Average ms of `reps` back-to-back dispatches of a kernel (events around the batch)."""
+        ms = C.c_double()
+        self._chk("ns_time_kernel", lib().ns_time_kernel(self.ctx, kernel, reps, C.byref(ms)))
+        return ms.value
 
     def diagnostics(self):
         out = (C.c_double * 4)()
