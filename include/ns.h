@@ -54,7 +54,7 @@ typedef enum {
 } ns_status;
 
 typedef enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 } ns_prec;   /* V-cycle precision   */
-typedef enum { NS_X0_ZERO = 0, NS_X0_PREV = 1 } ns_x0;           /* projection guess    */
+typedef enum { NS_X0_ZERO = 0, NS_X0_PREV = 1, NS_X0_LEARNED = 2 } ns_x0;   /* projection guess */
 
 /* A rigid body given by an analytic level set psi (negative inside), built
  * from primitive distance functions with min/max (Sec. "Interface tracking":
@@ -89,6 +89,8 @@ typedef struct {
   double rtol;                 /* stop when ||b - A p||_2 <= rtol ||b||_2           */
   int prec;                    /* ns_prec                                           */
   int x0;                      /* ns_x0                                             */
+  double p_scale;              /* P0 of the learned guess p0 = p_prev + P0 delta,
+                                  e.g. rho_w g depth; > 0 when x0 = NS_X0_LEARNED  */
 } ns_params;
 
 /* The caller's state arrays (device, FP64, layouts above); read and written
@@ -109,6 +111,7 @@ typedef struct {
   double rel_resid;        /* last recursive residual / ||b||                         */
   double true_rel_resid;   /* ||b - A p|| / ||b|| recomputed at exit                  */
   double ms;               /* wall time of the call, stream-synchronised (ms)         */
+  int x0_fallback;         /* 1 if the learned guess was non-finite and p_prev was used */
 } ns_stats;
 
 /* Internal arrays a caller may inspect or fill through ns_buffer (device
@@ -200,6 +203,69 @@ ns_status ns_timing_read(ns_ctx* ctx, double* total_ms, int* launches);
  * the state; synchronises the stream.  Needs momentum_step (or filled
  * coefficients) first, else NS_ESTATE. */
 ns_status ns_time_kernel(ns_ctx* ctx, int kernel, int reps, double* avg_ms);
+
+/* ---------------------------------------------------------------------
+ * Learned initial guess (a small 3-level convolutional encoder-decoder,
+ * 16/32/64 channels, 3x3x3 kernels, bfloat16 on the matrix cores with FP32
+ * accumulation) mapping four features of the projection to a correction
+ * delta: p0 = p_prev + P0 delta.  The features are the right-hand side
+ * b h^2 rho_w / P0, the density as ln(rho/rho_w)/ln(rho_a/rho_w), p_prev / P0
+ * and the residual (b - A p_prev) h^2 rho_w / P0.  The CG solve that follows
+ * is unchanged and meets the same rtol whatever the guess.
+ * Parameters are exchanged as FP32 in a canonical flat order: for each of the
+ * six layers (4->16, 16->32, 32->64, 96->32, 48->16 3x3x3, 16->1 1x1x1) the
+ * weights w[co][ci][kz][ky][kx] then the biases b[co].
+ * ------------------------------------------------------------------- */
+typedef struct ns_net ns_net;
+
+/* Number of FP32 parameters in the canonical order. */
+size_t ns_net_param_count(void);
+
+/* Device workspace for a network on an nx*ny*nz grid (each a multiple of 4,
+ * >= 4); training != 0 adds gradients, optimiser state and backward
+ * buffers.  0 when the sizes are invalid. */
+size_t ns_net_workspace_bytes(int nx, int ny, int nz, int training);
+
+/* Bind a workspace (device, 256-byte aligned, caller-owned) and a stream.
+ * Parameters start at zero until ns_net_set_params. */
+ns_status ns_net_create(int nx, int ny, int nz, int training, void* workspace, size_t ws_bytes,
+                        void* hip_stream, ns_net** out);
+void ns_net_destroy(ns_net* net);
+const char* ns_net_last_error(ns_net* net);
+
+/* Upload / download the FP32 parameters (HOST arrays of
+ * ns_net_param_count() floats); set_params also resets the optimiser. */
+ns_status ns_net_set_params(ns_net* net, const float* host_params, size_t n);
+ns_status ns_net_get_params(ns_net* net, float* host_params, size_t n);
+
+/* Gradients of the last ns_net_train_step (host array, canonical order). */
+ns_status ns_net_get_grads(ns_net* net, float* host_grads, size_t n);
+
+/* Load four feature channels (device FP32, channel-first, 4*nx*ny*nz). */
+ns_status ns_net_set_input(ns_net* net, const float* feat4);
+
+/* Run the network on the loaded input; delta_out (device FP32, nx*ny*nz)
+ * receives delta when not NULL. */
+ns_status ns_net_forward(ns_net* net, float* delta_out);
+
+/* One training step on one sample (device FP32 features and target delta):
+ * forward, loss L = sum (delta - t)^2 / sum t^2 (the squared error of p0
+ * relative to that of p_prev), backward, and when update != 0 an Adam step
+ * (betas 0.9/0.999, eps 1e-8) of rate lr.  *loss gets L (synchronises). */
+ns_status ns_net_train_step(ns_net* net, const float* feat4, const float* target, float lr, int update,
+                            double* loss);
+
+/* Use `net` (same grid) for x0 = NS_X0_LEARNED in this context. */
+ns_status ns_attach_net(ns_ctx* ctx, ns_net* net);
+
+/* The four features of the projection about to be solved (after
+ * momentum_step), with p_prev (device FP64 cells) as the previous pressure,
+ * into feat4 (device FP32, 4 * cells, channel-first). */
+ns_status ns_features(ns_ctx* ctx, double dt, const double* p_prev, float* feat4);
+
+/* Training target t = (p - p_prev) / P0 of the solved pressure fields.p
+ * (device FP64 p_prev, device FP32 t). */
+ns_status ns_target(ns_ctx* ctx, const double* p_prev, float* t);
 
 /* Number of multigrid levels for these sizes. */
 int ns_num_levels(int nx, int ny, int nz);

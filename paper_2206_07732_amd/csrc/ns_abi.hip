@@ -37,6 +37,7 @@ struct ns_ctx {
   int timed_kernel;   // -1 or an ns_timed_kernel id
   KTimer kt;
   hipEvent_t ev_rr;   // marks the residual read-back of a CG iteration
+  ns_net* net;        // learned guess (not owned)
   int tail64, tail32; // first level of the LDS tail per precision (L: none)
   size_t lds64, lds32;
   char err[512];
@@ -103,7 +104,10 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
   if (P->reinit_iters < 0 || P->nu_pre < 0 || P->nu_post < 0 || P->coarse_sweeps < 0 || P->max_iters < 0)
     return snprintf(why, nwhy, "iteration counts must be >= 0"), false;
   if (P->prec != NS_PREC_FP64 && P->prec != NS_PREC_MIXED) return snprintf(why, nwhy, "bad prec"), false;
-  if (P->x0 != NS_X0_ZERO && P->x0 != NS_X0_PREV) return snprintf(why, nwhy, "bad x0"), false;
+  if (P->x0 != NS_X0_ZERO && P->x0 != NS_X0_PREV && P->x0 != NS_X0_LEARNED)
+    return snprintf(why, nwhy, "bad x0"), false;
+  if (P->x0 == NS_X0_LEARNED && !(P->p_scale > 0.0))
+    return snprintf(why, nwhy, "p_scale must be > 0 for the learned guess"), false;
   for (int m = 0; m < P->n_bodies; ++m)
     if (P->body[m].kind != 0 && P->body[m].kind != 1) return snprintf(why, nwhy, "bad body kind"), false;
   return true;
@@ -528,6 +532,37 @@ extern "C" {
 
 int ns_num_levels(int nx, int ny, int nz) { return count_levels(nx, ny, nz); }
 
+ns_status ns_attach_net(ns_ctx* X, ns_net* N) {
+  if (!X) return NS_EINVAL;
+  if (N && !net_matches(N, X->lev[0].n)) return fail(X, NS_EINVAL, "network grid differs from the solver grid");
+  X->net = N;
+  return NS_OK;
+}
+
+ns_status ns_features(ns_ctx* X, double dt, const double* p_prev, float* feat4) {
+  if (!X) return NS_EINVAL;
+  if (!aligned8(p_prev) || !feat4) return fail(X, NS_EINVAL, "p_prev and feat4 must be device pointers");
+  if (!(dt > 0.0)) return fail(X, NS_EINVAL, "dt must be > 0");
+  if (!X->have_beta) return fail(X, NS_ESTATE, "ns_features before momentum_step");
+  if (!(X->P.p_scale > 0.0)) return fail(X, NS_EINVAL, "p_scale must be > 0");
+  const Level& L0 = X->lev[0];
+  launch_rhs(X->phys, X->us, X->vs, X->ws, dt, X->b, X->st);
+  launch_apply_A(L0.n, X->P.h, L0.bx, L0.by, L0.bz, p_prev, X->q, X->st);
+  net_features(nullptr, L0.n, X->P.h, X->P.rho_w, X->P.rho_a, X->P.p_scale, X->b, X->rho, p_prev, X->q, feat4,
+               X->st);
+  HIPCHK(X, hipGetLastError());
+  return NS_OK;
+}
+
+ns_status ns_target(ns_ctx* X, const double* p_prev, float* t) {
+  if (!X) return NS_EINVAL;
+  if (!aligned8(p_prev) || !t) return fail(X, NS_EINVAL, "p_prev and t must be device pointers");
+  if (!(X->P.p_scale > 0.0)) return fail(X, NS_EINVAL, "p_scale must be > 0");
+  net_target((long)X->nc, X->F.p, p_prev, X->P.p_scale, t, X->st);
+  HIPCHK(X, hipGetLastError());
+  return NS_OK;
+}
+
 size_t ns_workspace_bytes(const ns_params* params) {
   char why[256];
   if (!valid_params(params, why, sizeof(why))) return 0;
@@ -722,9 +757,27 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   const Phys& ph = X->phys;
   hipStream_t st = X->st;
   launch_rhs(ph, X->us, X->vs, X->ws, dt, X->b, st);
-  if (X->P.x0 == NS_X0_ZERO) launch_fill<double>(X->F.p, X->nc, st);
+  int fallback = 0;
+  if (X->P.x0 == NS_X0_ZERO) {
+    launch_fill<double>(X->F.p, X->nc, st);
+  } else if (X->P.x0 == NS_X0_LEARNED) {
+    // p0 = p_prev + P0 delta(features of b, rho, p_prev); p_prev if not finite
+    ns_net* N = X->net;
+    if (!N) return fail(X, NS_ESTATE, "x0 = NS_X0_LEARNED needs ns_attach_net");
+    const Level& L0 = X->lev[0];
+    double* pprev = net_pprev(N);
+    launch_copy(X->F.p, pprev, X->nc, st);
+    launch_apply_A(L0.n, X->P.h, L0.bx, L0.by, L0.bz, pprev, net_Ap(N), st);
+    net_features(N, L0.n, X->P.h, X->P.rho_w, X->P.rho_a, X->P.p_scale, X->b, X->rho, pprev, net_Ap(N),
+                 net_feat(N), st);
+    if (net_guess(N, X->P.p_scale, X->F.p, st) != 0) {
+      launch_copy(pprev, X->F.p, X->nc, st);
+      fallback = 1;
+    }
+  }
   ns_stats S{};
   ns_status s = pcg(X, &S);
+  S.x0_fallback = fallback;
   if (s != NS_OK && s != NS_ENOCONV) {
     if (stats) *stats = S;
     return s;

@@ -165,4 +165,14 @@ void launch_cg_update(const Dims& n, const double* d, const double* q, double* x
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                     const double* x, double* y, hipStream_t st);
 
+// learned guess (ns_net.hip)
+void net_features(ns_net* N, const Dims& n, double h, double rho_w, double rho_a, double P0, const double* b,
+                  const double* rho, const double* pprev, const double* Ap, float* feat, hipStream_t st);
+int net_matches(const ns_net* N, const Dims& n);
+double* net_pprev(ns_net* N);
+double* net_Ap(ns_net* N);
+float* net_feat(ns_net* N);
+int net_guess(ns_net* N, double P0, double* p, hipStream_t st);
+void net_target(long nv, const double* p, const double* pprev, double P0, float* t, hipStream_t st);
+
 }  // namespace nsk

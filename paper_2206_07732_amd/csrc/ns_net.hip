@@ -1,0 +1,888 @@
+// Learned initial guess for the pressure projection on gfx950: a 3-level
+// convolutional encoder-decoder (16/32/64 channels, 3x3x3 kernels, ReLU,
+// 2x2x2 average pooling, nearest upsampling, skip connections by channel
+// concatenation, 1x1x1 head) in bfloat16 with FP32 accumulation on the
+// matrix cores, with its hand-written backward pass and Adam optimiser.
+//
+// Layout: activations are channels-last bfloat16, a[v * C + c] with the voxel
+// index v = x + nx (y + ny z) of their resolution.  The first layer's four
+// input channels are padded to 16 (zeros), so every convolution has C_in and
+// C_out in multiples of 16.  A convolution is an implicit GEMM,
+//   Y[v][co] = sum_{tap, ci} X[v + tap][ci] W[co][tap][ci],
+// M = voxels, N = C_out, K = 27 C_in, computed 16 voxels x 16 channels x 16
+// inputs at a time by v_mfma_f32_16x16x16_bf16:
+//   A (16 voxels x 16 inputs):  lane l holds row l%16, inputs 4(l/16)..+3
+//   B (16 inputs x 16 outputs): lane l holds column l%16, inputs 4(l/16)..+3
+//   D (16 voxels x 16 outputs): lane l holds column l%16, rows 4(l/16)..+3
+// The backward pass w.r.t. the input is the same convolution with the
+// kernel flipped in space and its channel roles swapped; the weight gradient
+// is a GEMM over voxels per tap, summed over voxel chunks in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ns_internal.h"
+
+namespace nsk {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct VDims {
+  int nx, ny, nz;
+};
+
+__device__ __forceinline__ long vox_count(const VDims& d) { return (long)d.nx * d.ny * d.nz; }
+
+// ------------------------------------------------------------ convolution
+// EPI 0: + bias, ReLU (forward); EPI 1: plain (gradient w.r.t. the input)
+template <int KS, int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restrict__ X,
+                                              const uint16_t* __restrict__ W,
+                                              const float* __restrict__ bias, uint16_t* __restrict__ Y,
+                                              int ys, int yo) {
+  constexpr int R = KS / 2;
+  constexpr int NT = COUT / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long nv = vox_count(d);
+  const long vb = ((long)blockIdx.x * 4 + wave) * 16;
+  if (vb >= nv) return;                        // whole wavefront idle
+  const int row = lane & 15, kq = lane >> 4;
+  const long v = vb + row;
+  const bool live = v < nv;
+  const int x = live ? (int)(v % d.nx) : 0;
+  const int y = live ? (int)((v / d.nx) % d.ny) : 0;
+  const int z = live ? (int)(v / ((long)d.nx * d.ny)) : 0;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x4 zero4 = {0, 0, 0, 0};
+  for (int tap = 0; tap < KS * KS * KS; ++tap) {
+    const int dz = tap / (KS * KS) - R, dy = (tap / KS) % KS - R, dx = tap % KS - R;
+    const int xx = x + dx, yy = y + dy, zz = z + dz;
+    const bool in = live && xx >= 0 && xx < d.nx && yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz;
+    const uint16_t* xp = X + (in ? ((long)xx + (long)d.nx * (yy + (long)d.ny * zz)) * CIN : 0);
+#pragma unroll
+    for (int c0 = 0; c0 < CIN; c0 += 16) {
+      const bf16x4 a = in ? *reinterpret_cast<const bf16x4*>(xp + c0 + 4 * kq) : zero4;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x4 b =
+            *reinterpret_cast<const bf16x4*>(W + ((long)(t * 16 + row) * (KS * KS * KS) + tap) * CIN + c0 + 4 * kq);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + row;
+    const float bb = (EPI == 0) ? bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long vo = vb + 4 * kq + i;
+      if (vo < nv) {
+        float val = acc[t][i] + bb;
+        if (EPI == 0) val = fmaxf(val, 0.f);
+        Y[vo * ys + yo + co] = f2bf(val);
+      }
+    }
+  }
+}
+
+// weight gradient of one tap: part[blk][tap][co][ci] = sum over this block's
+// voxels of dY[v][co] X[v + tap][ci]
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_wgrad(VDims d, const uint16_t* __restrict__ X,
+                                               const uint16_t* __restrict__ dY, int vox_per_block,
+                                               float* __restrict__ part) {
+  constexpr int NO = COUT / 16, NI = CIN / 16;
+  __shared__ float red[4][COUT * CIN];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  const int tap = blockIdx.y;
+  const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const long nv = vox_count(d);
+  const long v_begin = (long)blockIdx.x * vox_per_block;
+  const long v_end = v_begin + vox_per_block < nv ? v_begin + vox_per_block : nv;
+  f32x4 acc[NO][NI];
+#pragma unroll
+  for (int a = 0; a < NO; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (long vb = v_begin + 16 * wave; vb < v_end; vb += 64) {
+    // voxels vb + 4 kq + i, i = 0..3, are this lane's k entries
+    long nbv[4];
+    bool live[4], in[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long v = vb + 4 * kq + i;
+      live[i] = v < v_end;
+      const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+      const int xx = x + dx, yy = y + dy, zz = z + dz;
+      in[i] = live[i] && xx >= 0 && xx < d.nx && yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz;
+      nbv[i] = in[i] ? (long)xx + (long)d.nx * (yy + (long)d.ny * zz) : 0;
+    }
+    bf16x4 A[NO], B[NI];
+#pragma unroll
+    for (int a = 0; a < NO; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) A[a][i] = live[i] ? (short)dY[(vb + 4 * kq + i) * COUT + a * 16 + row] : (short)0;
+#pragma unroll
+    for (int b = 0; b < NI; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) B[b][i] = in[i] ? (short)X[nbv[i] * CIN + b * 16 + row] : (short)0;
+#pragma unroll
+    for (int a = 0; a < NO; ++a)
+#pragma unroll
+      for (int b = 0; b < NI; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[a], B[b], acc[a][b], 0, 0, 0);
+  }
+  // D lane layout: column ci = b*16 + row, rows co = a*16 + 4 kq + i
+#pragma unroll
+  for (int a = 0; a < NO; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[wave][(a * 16 + 4 * kq + i) * CIN + b * 16 + row] = acc[a][b][i];
+  __syncthreads();
+  float* out = part + ((size_t)blockIdx.x * 27 + tap) * (COUT * CIN);
+  for (int q = threadIdx.x; q < COUT * CIN; q += 256) out[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+}
+
+// g[(co * 27 + tap) * CIN + ci] = sum over blocks of part[blk][tap][co][ci]
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nblk, int cin, int cout,
+                               float* __restrict__ g) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = 27 * cout * cin;
+  if (q >= per) return;
+  const int tap = q / (cout * cin), r = q % (cout * cin), co = r / cin, ci = r % cin;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * per + q];
+  g[((size_t)co * 27 + tap) * cin + ci] = s;
+}
+
+// per-block channel sums of dY (bias gradient), then their fixed-order total
+__global__ void __launch_bounds__(256) k_bias_part(long nv, int C, const uint16_t* __restrict__ dY,
+                                                   int vox_per_block, float* __restrict__ part) {
+  const long v0 = (long)blockIdx.x * vox_per_block;
+  const long v1 = v0 + vox_per_block < nv ? v0 + vox_per_block : nv;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float s = 0.f;
+    for (long v = v0; v < v1; ++v) s += bf2f(dY[v * C + c]);
+    part[(size_t)blockIdx.x * C + c] = s;
+  }
+}
+
+__global__ void k_bias_reduce(const float* __restrict__ part, int nblk, int C, float* __restrict__ g) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * C + c];
+  g[c] = s;
+}
+
+// ------------------------------------------------------- resampling, head
+// 2x2x2 average of a fine tensor (channel stride is, offset io) into a dense coarse one
+__global__ void k_pool(VDims fine, const uint16_t* __restrict__ in, int is, int io, int C,
+                       uint16_t* __restrict__ out) {
+  const VDims c{fine.nx / 2, fine.ny / 2, fine.nz / 2};
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= vox_count(c) * C) return;
+  const int ch = (int)(q % C);
+  const long v = q / C;
+  const int X = (int)(v % c.nx), Y = (int)((v / c.nx) % c.ny), Z = (int)(v / ((long)c.nx * c.ny));
+  float s = 0.f;
+  for (int k = 0; k < 2; ++k)
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 2; ++i) {
+        const long f = (2L * X + i) + (long)fine.nx * ((2L * Y + j) + (long)fine.ny * (2L * Z + k));
+        s += bf2f(in[f * is + io + ch]);
+      }
+  out[q] = f2bf(s * 0.125f);
+}
+
+// nearest x2 upsampling of a dense coarse tensor into a fine one (stride os, offset oo)
+__global__ void k_up(VDims coarse, const uint16_t* __restrict__ in, int C, uint16_t* __restrict__ out,
+                     int os, int oo) {
+  const VDims f{coarse.nx * 2, coarse.ny * 2, coarse.nz * 2};
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= vox_count(f) * C) return;
+  const int ch = (int)(q % C);
+  const long v = q / C;
+  const int x = (int)(v % f.nx), y = (int)((v / f.nx) % f.ny), z = (int)(v / ((long)f.nx * f.ny));
+  const long p = (x / 2) + (long)coarse.nx * ((y / 2) + (long)coarse.ny * (z / 2));
+  out[v * os + oo + ch] = in[p * C + ch];
+}
+
+// delta = b + sum_c w_c a_c (1x1x1 head, FP32 out)
+__global__ void k_head(long nv, const uint16_t* __restrict__ a, const float* __restrict__ w,
+                       const float* __restrict__ b, float* __restrict__ delta) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  float s = b[0];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) s += w[c] * bf2f(a[v * 16 + c]);
+  delta[v] = s;
+}
+
+// ------------------------------------------------------------- backward
+// d5 = ddelta w_c (a_c > 0)
+__global__ void k_head_bwd(long nv, const float* __restrict__ dd, const uint16_t* __restrict__ a,
+                           const float* __restrict__ w, uint16_t* __restrict__ d5) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nv * 16) return;
+  const long v = q / 16;
+  const int c = (int)(q % 16);
+  d5[q] = f2bf(a[q] != 0 && bf2f(a[q]) > 0.f ? dd[v] * w[c] : 0.f);
+}
+
+// per-block partials of (sum ddelta a_c for c < 16, sum ddelta)
+__global__ void __launch_bounds__(256) k_head_wgrad_part(long nv, const float* __restrict__ dd,
+                                                         const uint16_t* __restrict__ a, int vox_per_block,
+                                                         float* __restrict__ part) {
+  __shared__ float sm[256][17];
+  const long v0 = (long)blockIdx.x * vox_per_block;
+  const long v1 = v0 + vox_per_block < nv ? v0 + vox_per_block : nv;
+  float s[17];
+#pragma unroll
+  for (int c = 0; c < 17; ++c) s[c] = 0.f;
+  for (long v = v0 + threadIdx.x; v < v1; v += 256) {
+    const float g = dd[v];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s[c] += g * bf2f(a[v * 16 + c]);
+    s[16] += g;
+  }
+#pragma unroll
+  for (int c = 0; c < 17; ++c) sm[threadIdx.x][c] = s[c];
+  __syncthreads();
+  if (threadIdx.x < 17) {
+    float t = 0.f;
+    for (int q = 0; q < 256; ++q) t += sm[q][threadIdx.x];
+    part[(size_t)blockIdx.x * 17 + threadIdx.x] = t;
+  }
+}
+
+// d (coarse, dense C) = (sum over the 8 children of dC[child][oo + c]) (a > 0)
+__global__ void k_up_bwd_mask(VDims coarse, const uint16_t* __restrict__ dC, int os, int oo, int C,
+                              const uint16_t* __restrict__ a, uint16_t* __restrict__ d) {
+  const VDims f{coarse.nx * 2, coarse.ny * 2, coarse.nz * 2};
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= vox_count(coarse) * C) return;
+  const int ch = (int)(q % C);
+  const long v = q / C;
+  if (!(bf2f(a[q]) > 0.f)) {
+    d[q] = 0;
+    return;
+  }
+  const int X = (int)(v % coarse.nx), Y = (int)((v / coarse.nx) % coarse.ny),
+            Z = (int)(v / ((long)coarse.nx * coarse.ny));
+  float s = 0.f;
+  for (int k = 0; k < 2; ++k)
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 2; ++i) {
+        const long fv = (2L * X + i) + (long)f.nx * ((2L * Y + j) + (long)f.ny * (2L * Z + k));
+        s += bf2f(dC[fv * os + oo + ch]);
+      }
+  d[q] = f2bf(s);
+}
+
+// d (fine, dense C) = (dC[v][c] (stride os) + dp[parent][c] / 8) (a[v][c] > 0, stride as)
+__global__ void k_skip_mask(VDims fine, const uint16_t* __restrict__ dC, int os, const uint16_t* __restrict__ dp,
+                            const uint16_t* __restrict__ a, int as, int C, uint16_t* __restrict__ d) {
+  const VDims c{fine.nx / 2, fine.ny / 2, fine.nz / 2};
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= vox_count(fine) * C) return;
+  const int ch = (int)(q % C);
+  const long v = q / C;
+  if (!(bf2f(a[v * as + ch]) > 0.f)) {
+    d[q] = 0;
+    return;
+  }
+  const int x = (int)(v % fine.nx), y = (int)((v / fine.nx) % fine.ny), z = (int)(v / ((long)fine.nx * fine.ny));
+  const long p = (x / 2) + (long)c.nx * ((y / 2) + (long)c.ny * (z / 2));
+  d[q] = f2bf(bf2f(dC[v * os + ch]) + 0.125f * bf2f(dp[p * C + ch]));
+}
+
+// W' [ci][26 - tap][co] = W[co][tap][ci]  (bfloat16, for the input gradient)
+__global__ void k_flip_transpose(const float* __restrict__ w, int cin, int cout, uint16_t* __restrict__ wt) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cout * 27 * cin) return;
+  const int co = q / (27 * cin), r = q % (27 * cin), tap = r / cin, ci = r % cin;
+  wt[((size_t)ci * 27 + (26 - tap)) * cout + co] = f2bf(w[q]);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ a, long n, uint16_t* __restrict__ b) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) b[q] = f2bf(a[q]);
+}
+
+// Adam with bias correction; padded (always-zero-gradient) entries stay put
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long n, float lr, float c1, float c2) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float gq = g[q];
+  const float mq = 0.9f * m[q] + 0.1f * gq;
+  const float vq = 0.999f * v[q] + 0.001f * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  th[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + 1e-8f);
+}
+
+// ------------------------------------------------ features, loss, guess
+// four input channels (channel-first FP32): rhs h^2 rho_w / P0, the
+// log-density fraction, p_prev / P0 and the residual (b - A p_prev) h^2 rho_w / P0
+__global__ void k_features(long nv, double s, double lr_w, double inv_lr, double inv_P0,
+                           const double* __restrict__ b, const double* __restrict__ rho,
+                           const double* __restrict__ pprev, const double* __restrict__ Ap,
+                           float* __restrict__ feat) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const double bb = b[v];
+  feat[v] = (float)(bb * s);
+  feat[nv + v] = (float)((log(rho[v]) - lr_w) * inv_lr);
+  feat[2 * nv + v] = (float)(pprev[v] * inv_P0);
+  feat[3 * nv + v] = (float)((bb - Ap[v]) * s);
+}
+
+// channel-first FP32 features -> channels-last bfloat16 input, padded to 16
+__global__ void k_set_input(long nv, const float* __restrict__ feat, uint16_t* __restrict__ x0) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nv * 16) return;
+  const long v = q / 16;
+  const int c = (int)(q % 16);
+  x0[q] = c < 4 ? f2bf(feat[c * nv + v]) : (uint16_t)0;
+}
+
+// p = p_prev + P0 delta
+__global__ void k_apply_delta(long nv, const double* __restrict__ pprev, const float* __restrict__ delta,
+                              double P0, double* __restrict__ p) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) p[v] = pprev[v] + P0 * (double)delta[v];
+}
+
+// target delta = (p* - p_prev) / P0
+__global__ void k_target(long nv, const double* __restrict__ p, const double* __restrict__ pprev, double inv_P0,
+                         float* __restrict__ t) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) t[v] = (float)((p[v] - pprev[v]) * inv_P0);
+}
+
+// per-block (sum (delta - t)^2, sum t^2)
+__global__ void __launch_bounds__(256) k_loss_part(long nv, const float* __restrict__ delta,
+                                                   const float* __restrict__ t, double* __restrict__ part) {
+  __shared__ double sa[256], sb[256];
+  double a = 0.0, b = 0.0;
+  for (long v = (long)blockIdx.x * 256 + threadIdx.x; v < nv; v += (long)gridDim.x * 256) {
+    const double e = (double)delta[v] - (double)t[v];
+    a += e * e;
+    b += (double)t[v] * (double)t[v];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sa[0];
+    part[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+// out[0] = loss, out[1] = 2 / sum t^2
+__global__ void k_loss_fin(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < nblk; ++q) {
+    a += part[2 * q];
+    b += part[2 * q + 1];
+  }
+  out[0] = b > 0.0 ? a / b : 0.0;
+  out[1] = b > 0.0 ? 2.0 / b : 0.0;
+}
+
+// ddelta = 2 (delta - t) / sum t^2
+__global__ void k_dloss(long nv, const float* __restrict__ delta, const float* __restrict__ t,
+                        const double* __restrict__ out, float* __restrict__ dd) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) dd[v] = (float)(out[1] * ((double)delta[v] - (double)t[v]));
+}
+
+__global__ void k_finite_count(long n, const float* __restrict__ a, int* __restrict__ bad) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n && !isfinite(a[q])) atomicAdd(bad, 1);
+}
+
+inline dim3 g1(long n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+}  // namespace
+
+// ==================================================================== the net
+// conv layers 1..5 (index 0..4): padded C_in, C_out, and the head (16 -> 1)
+static const int kCin[5] = {16, 16, 32, 96, 48};
+static const int kCinTrue[5] = {4, 16, 32, 96, 48};
+static const int kCout[5] = {16, 32, 64, 32, 16};
+
+}  // namespace nsk
+
+using namespace nsk;
+
+struct ns_net {
+  VDims res0, res1, res2;
+  long v0, v1, v2;
+  int training;
+  hipStream_t st;
+  // internal parameter layout: per conv layer W[co][tap][ci_pad] then b[co];
+  // then the head w[16], b[1]
+  size_t np;
+  size_t ow[5], ob[5], ohw, ohb;
+  float *theta, *m, *v, *g;
+  uint16_t *wf[5], *wt[5];
+  uint16_t *x0, *C1, *p1, *C2, *p2, *a3, *a4, *a5;
+  float* delta;
+  // backward
+  float* dd;
+  uint16_t *d5, *dC1, *d4, *dC2, *d3, *dp2, *d2, *dp1, *d1;
+  float* wpart;
+  size_t wpart_elems;
+  double* red;
+  int* bad;
+  double* host;
+  // learned-guess staging
+  float* feat;
+  float* target;
+  double* pprev;
+  double* Ap;
+  int step;
+  char err[256];
+};
+
+namespace {
+
+constexpr size_t kAlignN = 256;
+
+struct NetCarve {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlignN - 1) / kAlignN * kAlignN;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+constexpr int kWgradVox = 4096;   // voxels per weight-gradient block
+
+size_t net_layout(ns_net* N, int nx, int ny, int nz, int training, char* base) {
+  NetCarve cv{base, 0};
+  VDims d0{nx, ny, nz}, d1{nx / 2, ny / 2, nz / 2}, d2{nx / 4, ny / 4, nz / 4};
+  const long v0 = (long)nx * ny * nz, v1 = v0 / 8, v2 = v0 / 64;
+  size_t np = 0, ow[5], ob[5];
+  for (int l = 0; l < 5; ++l) {
+    ow[l] = np;
+    np += (size_t)kCout[l] * 27 * kCin[l];
+    ob[l] = np;
+    np += kCout[l];
+  }
+  const size_t ohw = np;
+  np += 16;
+  const size_t ohb = np;
+  np += 1;
+  float* theta = cv.take<float>(np);
+  float *m = nullptr, *v = nullptr, *g = nullptr;
+  if (training) {
+    m = cv.take<float>(np);
+    v = cv.take<float>(np);
+    g = cv.take<float>(np);
+  }
+  uint16_t *wf[5], *wt[5];
+  for (int l = 0; l < 5; ++l) {
+    wf[l] = cv.take<uint16_t>((size_t)kCout[l] * 27 * kCin[l]);
+    wt[l] = cv.take<uint16_t>((size_t)kCout[l] * 27 * kCin[l]);
+  }
+  uint16_t* x0 = cv.take<uint16_t>(v0 * 16);
+  uint16_t* C1 = cv.take<uint16_t>(v0 * 48);
+  uint16_t* p1 = cv.take<uint16_t>(v1 * 16);
+  uint16_t* C2 = cv.take<uint16_t>(v1 * 96);
+  uint16_t* p2 = cv.take<uint16_t>(v2 * 32);
+  uint16_t* a3 = cv.take<uint16_t>(v2 * 64);
+  uint16_t* a4 = cv.take<uint16_t>(v1 * 32);
+  uint16_t* a5 = cv.take<uint16_t>(v0 * 16);
+  float* delta = cv.take<float>(v0);
+  float* feat = cv.take<float>(4 * v0);
+  float* target = cv.take<float>(v0);
+  double* pprev = cv.take<double>(v0);
+  double* Ap = cv.take<double>(v0);
+  double* red = cv.take<double>(4096);
+  int* bad = cv.take<int>(64);
+  float* dd = nullptr;
+  uint16_t *d5 = nullptr, *dC1 = nullptr, *d4 = nullptr, *dC2 = nullptr, *d3 = nullptr, *dp2 = nullptr,
+           *d2p = nullptr, *dp1 = nullptr, *d1p = nullptr;
+  float* wpart = nullptr;
+  size_t wpart_elems = 0;
+  if (training) {
+    dd = cv.take<float>(v0);
+    d5 = cv.take<uint16_t>(v0 * 16);
+    dC1 = cv.take<uint16_t>(v0 * 48);
+    d4 = cv.take<uint16_t>(v1 * 32);
+    dC2 = cv.take<uint16_t>(v1 * 96);
+    d3 = cv.take<uint16_t>(v2 * 64);
+    dp2 = cv.take<uint16_t>(v2 * 32);
+    d2p = cv.take<uint16_t>(v1 * 32);
+    dp1 = cv.take<uint16_t>(v1 * 16);
+    d1p = cv.take<uint16_t>(v0 * 16);
+    // the largest (blocks x 27 x C_out x C_in) over the layers
+    for (int l = 0; l < 5; ++l) {
+      const long vl = (l == 0 || l == 4) ? v0 : (l == 1 || l == 3) ? v1 : v2;
+      const size_t nb = (size_t)((vl + kWgradVox - 1) / kWgradVox);
+      const size_t e = nb * 27 * (size_t)kCout[l] * kCin[l];
+      if (e > wpart_elems) wpart_elems = e;
+    }
+    // bias and head partials share the buffer
+    const size_t eb = (size_t)((v0 + kWgradVox - 1) / kWgradVox) * 96;
+    if (eb > wpart_elems) wpart_elems = eb;
+    wpart = cv.take<float>(wpart_elems);
+  }
+  if (N) {
+    N->res0 = d0;
+    N->res1 = d1;
+    N->res2 = d2;
+    N->v0 = v0;
+    N->v1 = v1;
+    N->v2 = v2;
+    N->training = training;
+    N->np = np;
+    for (int l = 0; l < 5; ++l) {
+      N->ow[l] = ow[l];
+      N->ob[l] = ob[l];
+      N->wf[l] = wf[l];
+      N->wt[l] = wt[l];
+    }
+    N->ohw = ohw;
+    N->ohb = ohb;
+    N->theta = theta;
+    N->m = m;
+    N->v = v;
+    N->g = g;
+    N->x0 = x0;
+    N->C1 = C1;
+    N->p1 = p1;
+    N->C2 = C2;
+    N->p2 = p2;
+    N->a3 = a3;
+    N->a4 = a4;
+    N->a5 = a5;
+    N->delta = delta;
+    N->feat = feat;
+    N->target = target;
+    N->pprev = pprev;
+    N->Ap = Ap;
+    N->red = red;
+    N->bad = bad;
+    N->dd = dd;
+    N->d5 = d5;
+    N->dC1 = dC1;
+    N->d4 = d4;
+    N->dC2 = dC2;
+    N->d3 = d3;
+    N->dp2 = dp2;
+    N->d2 = d2p;
+    N->dp1 = dp1;
+    N->d1 = d1p;
+    N->wpart = wpart;
+    N->wpart_elems = wpart_elems;
+  }
+  return cv.off + kAlignN;
+}
+
+ns_status nfail(ns_net* N, ns_status s, const char* msg) {
+  if (N) snprintf(N->err, sizeof(N->err), "%s", msg);
+  return s;
+}
+
+template <int KS, int CIN, int COUT, int EPI>
+void conv(const ns_net* N, VDims d, long nv, const uint16_t* X, const uint16_t* W, const float* bias,
+          uint16_t* Y, int ys, int yo) {
+  const unsigned blocks = (unsigned)((nv + 63) / 64);
+  hipLaunchKernelGGL((k_conv<KS, CIN, COUT, EPI>), dim3(blocks), dim3(256), 0, N->st, d, X, W, bias, Y, ys, yo);
+}
+
+// bf16 copies (forward and flipped-transposed) of the FP32 master weights
+void refresh_weights(ns_net* N) {
+  for (int l = 0; l < 5; ++l) {
+    const long n = (long)kCout[l] * 27 * kCin[l];
+    hipLaunchKernelGGL(k_to_bf16, g1(n), dim3(256), 0, N->st, N->theta + N->ow[l], n, N->wf[l]);
+    hipLaunchKernelGGL(k_flip_transpose, g1(n), dim3(256), 0, N->st, N->theta + N->ow[l], kCin[l], kCout[l],
+                       N->wt[l]);
+  }
+}
+
+void forward(ns_net* N) {
+  const float* th = N->theta;
+  conv<3, 16, 16, 0>(N, N->res0, N->v0, N->x0, N->wf[0], th + N->ob[0], N->C1, 48, 0);
+  hipLaunchKernelGGL(k_pool, g1(N->v1 * 16), dim3(256), 0, N->st, N->res0, N->C1, 48, 0, 16, N->p1);
+  conv<3, 16, 32, 0>(N, N->res1, N->v1, N->p1, N->wf[1], th + N->ob[1], N->C2, 96, 0);
+  hipLaunchKernelGGL(k_pool, g1(N->v2 * 32), dim3(256), 0, N->st, N->res1, N->C2, 96, 0, 32, N->p2);
+  conv<3, 32, 64, 0>(N, N->res2, N->v2, N->p2, N->wf[2], th + N->ob[2], N->a3, 64, 0);
+  hipLaunchKernelGGL(k_up, g1(N->v1 * 64), dim3(256), 0, N->st, N->res2, N->a3, 64, N->C2, 96, 32);
+  conv<3, 96, 32, 0>(N, N->res1, N->v1, N->C2, N->wf[3], th + N->ob[3], N->a4, 32, 0);
+  hipLaunchKernelGGL(k_up, g1(N->v0 * 32), dim3(256), 0, N->st, N->res1, N->a4, 32, N->C1, 48, 16);
+  conv<3, 48, 16, 0>(N, N->res0, N->v0, N->C1, N->wf[4], th + N->ob[4], N->a5, 16, 0);
+  hipLaunchKernelGGL(k_head, g1(N->v0), dim3(256), 0, N->st, N->v0, N->a5, th + N->ohw, th + N->ohb, N->delta);
+}
+
+template <int CIN, int COUT>
+void wgrad(ns_net* N, VDims d, long nv, const uint16_t* X, const uint16_t* dY, int layer) {
+  const int nb = (int)((nv + kWgradVox - 1) / kWgradVox);
+  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(nb, 27), dim3(256), 0, N->st, d, X, dY, kWgradVox, N->wpart);
+  const int per = 27 * COUT * CIN;
+  hipLaunchKernelGGL(k_wgrad_reduce, g1(per), dim3(256), 0, N->st, N->wpart, nb, CIN, COUT, N->g + N->ow[layer]);
+  hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(64), 0, N->st, nv, COUT, dY, kWgradVox, N->wpart);
+  hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(128), 0, N->st, N->wpart, nb, COUT, N->g + N->ob[layer]);
+}
+
+void backward(ns_net* N) {
+  const float* th = N->theta;
+  hipStream_t st = N->st;
+  // head
+  {
+    const int nb = (int)((N->v0 + kWgradVox - 1) / kWgradVox);
+    hipLaunchKernelGGL(k_head_wgrad_part, dim3(nb), dim3(256), 0, st, N->v0, N->dd, N->a5, kWgradVox, N->wpart);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(32), 0, st, N->wpart, nb, 17, N->g + N->ohw);
+    hipLaunchKernelGGL(k_head_bwd, g1(N->v0 * 16), dim3(256), 0, st, N->v0, N->dd, N->a5, th + N->ohw, N->d5);
+  }
+  // layer 5: input C1 (48), output 16
+  wgrad<48, 16>(N, N->res0, N->v0, N->C1, N->d5, 4);
+  conv<3, 16, 48, 1>(N, N->res0, N->v0, N->d5, N->wt[4], nullptr, N->dC1, 48, 0);
+  hipLaunchKernelGGL(k_up_bwd_mask, g1(N->v1 * 32), dim3(256), 0, st, N->res1, N->dC1, 48, 16, 32, N->a4, N->d4);
+  // layer 4: input C2 (96), output 32
+  wgrad<96, 32>(N, N->res1, N->v1, N->C2, N->d4, 3);
+  conv<3, 32, 96, 1>(N, N->res1, N->v1, N->d4, N->wt[3], nullptr, N->dC2, 96, 0);
+  hipLaunchKernelGGL(k_up_bwd_mask, g1(N->v2 * 64), dim3(256), 0, st, N->res2, N->dC2, 96, 32, 64, N->a3, N->d3);
+  // layer 3: input p2 (32), output 64
+  wgrad<32, 64>(N, N->res2, N->v2, N->p2, N->d3, 2);
+  conv<3, 64, 32, 1>(N, N->res2, N->v2, N->d3, N->wt[2], nullptr, N->dp2, 32, 0);
+  hipLaunchKernelGGL(k_skip_mask, g1(N->v1 * 32), dim3(256), 0, st, N->res1, N->dC2, 96, N->dp2, N->C2, 96, 32, N->d2);
+  // layer 2: input p1 (16), output 32
+  wgrad<16, 32>(N, N->res1, N->v1, N->p1, N->d2, 1);
+  conv<3, 32, 16, 1>(N, N->res1, N->v1, N->d2, N->wt[1], nullptr, N->dp1, 16, 0);
+  hipLaunchKernelGGL(k_skip_mask, g1(N->v0 * 16), dim3(256), 0, st, N->res0, N->dC1, 48, N->dp1, N->C1, 48, 16, N->d1);
+  // layer 1: input x0 (16), output 16
+  wgrad<16, 16>(N, N->res0, N->v0, N->x0, N->d1, 0);
+}
+
+// canonical index (oracle layout) <-> internal index
+// conv layer l: canonical w[co][ci][kz][ky][kx] (ci < true C_in) then b[co];
+// internal W[co][tap][ci_pad], tap = (kz * 3 + ky) * 3 + kx
+template <typename F>
+void for_each_param(const ns_net* N, F f) {
+  size_t c = 0;
+  for (int l = 0; l < 5; ++l) {
+    const int cin = kCinTrue[l], cinp = kCin[l], cout = kCout[l];
+    for (int co = 0; co < cout; ++co)
+      for (int ci = 0; ci < cin; ++ci)
+        for (int tap = 0; tap < 27; ++tap) f(c++, N->ow[l] + ((size_t)co * 27 + tap) * cinp + ci);
+    for (int co = 0; co < cout; ++co) f(c++, N->ob[l] + co);
+  }
+  for (int q = 0; q < 16; ++q) f(c++, N->ohw + q);
+  f(c++, N->ohb);
+}
+
+size_t canonical_count() {
+  size_t n = 0;
+  for (int l = 0; l < 5; ++l) n += (size_t)kCout[l] * kCinTrue[l] * 27 + kCout[l];
+  return n + 17;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+size_t ns_net_param_count(void) { return canonical_count(); }
+
+size_t ns_net_workspace_bytes(int nx, int ny, int nz, int training) {
+  if (nx < 4 || ny < 4 || nz < 4 || nx % 4 || ny % 4 || nz % 4) return 0;
+  return net_layout(nullptr, nx, ny, nz, training ? 1 : 0, nullptr);
+}
+
+ns_status ns_net_create(int nx, int ny, int nz, int training, void* ws, size_t bytes, void* stream,
+                        ns_net** out) {
+  if (!out) return NS_EINVAL;
+  *out = nullptr;
+  if (nx < 4 || ny < 4 || nz < 4 || nx % 4 || ny % 4 || nz % 4) return NS_EINVAL;
+  if (!ws || ((uintptr_t)ws % kAlignN) != 0) return NS_EINVAL;
+  const size_t need = net_layout(nullptr, nx, ny, nz, training ? 1 : 0, nullptr);
+  if (bytes < need) return NS_EINVAL;
+  ns_net* N = new (std::nothrow) ns_net();
+  if (!N) return NS_EINVAL;
+  net_layout(N, nx, ny, nz, training ? 1 : 0, (char*)ws);
+  N->st = (hipStream_t)stream;
+  N->step = 0;
+  if (hipHostMalloc((void**)&N->host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete N;
+    return NS_EHIP;
+  }
+  if (hipMemsetAsync(N->theta, 0, N->np * sizeof(float), N->st) != hipSuccess) {
+    (void)hipHostFree(N->host);
+    delete N;
+    return NS_EHIP;
+  }
+  if (training) {
+    (void)hipMemsetAsync(N->m, 0, N->np * sizeof(float), N->st);
+    (void)hipMemsetAsync(N->v, 0, N->np * sizeof(float), N->st);
+    (void)hipMemsetAsync(N->g, 0, N->np * sizeof(float), N->st);
+  }
+  *out = N;
+  return NS_OK;
+}
+
+void ns_net_destroy(ns_net* N) {
+  if (!N) return;
+  if (N->host) (void)hipHostFree(N->host);
+  delete N;
+}
+
+const char* ns_net_last_error(ns_net* N) { return N ? N->err : "null net"; }
+
+ns_status ns_net_set_params(ns_net* N, const float* host_params, size_t n) {
+  if (!N || !host_params) return NS_EINVAL;
+  if (n != canonical_count()) return nfail(N, NS_EINVAL, "parameter count mismatch");
+  std::vector<float> internal(N->np, 0.0f);
+  for_each_param(N, [&](size_t c, size_t i) { internal[i] = host_params[c]; });
+  if (hipMemcpyAsync(N->theta, internal.data(), N->np * sizeof(float), hipMemcpyHostToDevice, N->st) != hipSuccess)
+    return nfail(N, NS_EHIP, "upload failed");
+  if (N->training) {
+    (void)hipMemsetAsync(N->m, 0, N->np * sizeof(float), N->st);
+    (void)hipMemsetAsync(N->v, 0, N->np * sizeof(float), N->st);
+    N->step = 0;
+  }
+  refresh_weights(N);
+  if (hipStreamSynchronize(N->st) != hipSuccess) return nfail(N, NS_EHIP, "synchronise failed");
+  return NS_OK;
+}
+
+static ns_status download(ns_net* N, const float* dev, float* host, size_t n) {
+  if (n != canonical_count()) return nfail(N, NS_EINVAL, "parameter count mismatch");
+  std::vector<float> internal(N->np);
+  if (hipMemcpyAsync(internal.data(), dev, N->np * sizeof(float), hipMemcpyDeviceToHost, N->st) != hipSuccess ||
+      hipStreamSynchronize(N->st) != hipSuccess)
+    return nfail(N, NS_EHIP, "download failed");
+  for_each_param(N, [&](size_t c, size_t i) { host[c] = internal[i]; });
+  return NS_OK;
+}
+
+ns_status ns_net_get_params(ns_net* N, float* host_params, size_t n) {
+  if (!N || !host_params) return NS_EINVAL;
+  return download(N, N->theta, host_params, n);
+}
+
+ns_status ns_net_get_grads(ns_net* N, float* host_grads, size_t n) {
+  if (!N || !host_grads) return NS_EINVAL;
+  if (!N->training) return nfail(N, NS_ESTATE, "not a training net");
+  return download(N, N->g, host_grads, n);
+}
+
+ns_status ns_net_set_input(ns_net* N, const float* feat4) {
+  if (!N || !feat4) return NS_EINVAL;
+  hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, N->st, N->v0, feat4, N->x0);
+  return hipGetLastError() == hipSuccess ? NS_OK : nfail(N, NS_EHIP, "launch failed");
+}
+
+ns_status ns_net_forward(ns_net* N, float* delta_out) {
+  if (!N) return NS_EINVAL;
+  forward(N);
+  if (delta_out)
+    if (hipMemcpyAsync(delta_out, N->delta, N->v0 * sizeof(float), hipMemcpyDeviceToDevice, N->st) != hipSuccess)
+      return nfail(N, NS_EHIP, "copy failed");
+  return hipGetLastError() == hipSuccess ? NS_OK : nfail(N, NS_EHIP, "launch failed");
+}
+
+ns_status ns_net_train_step(ns_net* N, const float* feat4, const float* target, float lr, int update,
+                            double* loss) {
+  if (!N || !feat4 || !target) return NS_EINVAL;
+  if (!N->training) return nfail(N, NS_ESTATE, "not a training net");
+  hipStream_t st = N->st;
+  hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, st, N->v0, feat4, N->x0);
+  forward(N);
+  const int nb = 256;
+  hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, N->v0, N->delta, target, N->red);
+  hipLaunchKernelGGL(k_loss_fin, dim3(1), dim3(64), 0, st, N->red, nb, N->red + 2 * nb);
+  hipLaunchKernelGGL(k_dloss, g1(N->v0), dim3(256), 0, st, N->v0, N->delta, target, N->red + 2 * nb, N->dd);
+  backward(N);
+  if (update) {
+    ++N->step;
+    const float c1 = 1.0f - powf(0.9f, (float)N->step), c2 = 1.0f - powf(0.999f, (float)N->step);
+    hipLaunchKernelGGL(k_adam, g1((long)N->np), dim3(256), 0, st, N->theta, N->g, N->m, N->v, (long)N->np, lr, c1, c2);
+    refresh_weights(N);
+  }
+  if (hipMemcpyAsync(N->host, N->red + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return nfail(N, NS_EHIP, "train step failed");
+  if (loss) *loss = N->host[0];
+  return std::isfinite(N->host[0]) ? NS_OK : nfail(N, NS_ENAN, "non-finite loss");
+}
+
+}  // extern "C"
+
+// --------------------------------------------- hooks used by the projection
+namespace nsk {
+
+void net_features(ns_net* N, const Dims& n, double h, double rho_w, double rho_a, double P0, const double* b,
+                  const double* rho, const double* pprev, const double* Ap, float* feat, hipStream_t st) {
+  const long nv = (long)n.nx * n.ny * n.nz;
+  (void)N;
+  hipLaunchKernelGGL(k_features, g1(nv), dim3(256), 0, st, nv, h * h * rho_w / P0, log(rho_w),
+                     1.0 / (log(rho_a) - log(rho_w)), 1.0 / P0, b, rho, pprev, Ap, feat);
+}
+
+int net_matches(const ns_net* N, const Dims& n) {
+  return N && N->res0.nx == n.nx && N->res0.ny == n.ny && N->res0.nz == n.nz;
+}
+
+double* net_pprev(ns_net* N) { return N->pprev; }
+double* net_Ap(ns_net* N) { return N->Ap; }
+float* net_feat(ns_net* N) { return N->feat; }
+
+// p = p_prev + P0 delta from the current features; returns the number of
+// non-finite outputs (device counter read back synchronously)
+int net_guess(ns_net* N, double P0, double* p, hipStream_t st) {
+  hipStream_t keep = N->st;
+  N->st = st;
+  hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, st, N->v0, N->feat, N->x0);
+  forward(N);
+  (void)hipMemsetAsync(N->bad, 0, sizeof(int), st);
+  hipLaunchKernelGGL(k_finite_count, g1(N->v0), dim3(256), 0, st, N->v0, N->delta, N->bad);
+  hipLaunchKernelGGL(k_apply_delta, g1(N->v0), dim3(256), 0, st, N->v0, N->pprev, N->delta, P0, p);
+  int bad = 0;
+  (void)hipMemcpyAsync(N->host, N->bad, sizeof(int), hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  memcpy(&bad, N->host, sizeof(int));
+  N->st = keep;
+  return bad;
+}
+
+void net_target(long nv, const double* p, const double* pprev, double P0, float* t, hipStream_t st) {
+  hipLaunchKernelGGL(k_target, g1(nv), dim3(256), 0, st, nv, p, pprev, 1.0 / P0, t);
+}
+
+}  // namespace nsk

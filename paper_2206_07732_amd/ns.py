@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libns.so")
 NS_OK, NS_EINVAL, NS_ENOCONV, NS_ENAN, NS_EHIP, NS_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_ENOCONV", -3: "NS_ENAN", -4: "NS_EHIP", -5: "NS_ESTATE"}
 PREC_FP64, PREC_MIXED = 0, 1
-X0_ZERO, X0_PREV = 0, 1
+X0_ZERO, X0_PREV, X0_LEARNED = 0, 1, 2
 BUF = {"us": 0, "vs": 1, "ws": 2, "bx": 3, "by": 4, "bz": 5, "rhs": 6, "rho": 7, "mu": 8, "chi": 9,
        "rho_flow": 10}
 
@@ -37,7 +37,8 @@ class NSParams(C.Structure):
                 ("n_bodies", C.c_int), ("body", NSBody * 4),
                 ("reinit_iters", C.c_int), ("reinit_dtau_over_h", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_sweeps", C.c_int),
-                ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int), ("x0", C.c_int)]
+                ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int), ("x0", C.c_int),
+                ("p_scale", C.c_double)]
 
 
 class NSFields(C.Structure):
@@ -47,7 +48,8 @@ class NSFields(C.Structure):
 
 class NSStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_resid0", C.c_double),
-                ("rel_resid", C.c_double), ("true_rel_resid", C.c_double), ("ms", C.c_double)]
+                ("rel_resid", C.c_double), ("true_rel_resid", C.c_double), ("ms", C.c_double),
+                ("x0_fallback", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,6 +90,20 @@ def lib() -> C.CDLL:
             "ns_timing_enable": ([vp, i, i], i),
             "ns_timing_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int)], i),
             "ns_time_kernel": ([vp, i, i, C.POINTER(C.c_double)], i),
+            "ns_net_param_count": ([], C.c_size_t),
+            "ns_net_workspace_bytes": ([i, i, i, i], C.c_size_t),
+            "ns_net_create": ([i, i, i, i, vp, C.c_size_t, vp, C.POINTER(vp)], i),
+            "ns_net_destroy": ([vp], None),
+            "ns_net_last_error": ([vp], C.c_char_p),
+            "ns_net_set_params": ([vp, C.POINTER(C.c_float), C.c_size_t], i),
+            "ns_net_get_params": ([vp, C.POINTER(C.c_float), C.c_size_t], i),
+            "ns_net_get_grads": ([vp, C.POINTER(C.c_float), C.c_size_t], i),
+            "ns_net_set_input": ([vp, vp], i),
+            "ns_net_forward": ([vp, vp], i),
+            "ns_net_train_step": ([vp, vp, vp, C.c_float, i, C.POINTER(C.c_double)], i),
+            "ns_attach_net": ([vp, vp], i),
+            "ns_features": ([vp, d, vp, vp], i),
+            "ns_target": ([vp, vp, vp], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
         }
@@ -102,11 +118,14 @@ def lib() -> C.CDLL:
 EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
             "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
             "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_timing_enable",
-            "ns_timing_read", "ns_time_kernel"]
+            "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
+            "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
+            "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
+            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
 
 SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2, coarse_sweeps=10,
-                       max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV)
+                       max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV, p_scale=0.0)
 
 
 def params(wl, **opts) -> NSParams:
@@ -125,6 +144,7 @@ def params(wl, **opts) -> NSParams:
         P.body[m].heave_amp, P.body[m].heave_omega, P.body[m].heave_phase = (
             b.heave_amp, b.heave_omega, b.heave_phase)
     o = dict(SOLVER_DEFAULTS)
+    o["p_scale"] = wl.rho_w * wl.g * wl.depth      # P0 = rho_w g d
     o.update(opts)
     for k, v in o.items():
         setattr(P, k, v)
@@ -258,6 +278,18 @@ class Solver:
         self._chk("ns_time_kernel", lib().ns_time_kernel(self.ctx, kernel, reps, C.byref(ms)))
         return ms.value
 
+    def attach_net(self, net):
+        self._chk("ns_attach_net", lib().ns_attach_net(self.ctx, net.net if net is not None else None))
+        self._net = net
+
+    def features(self, dt: float, p_prev: torch.Tensor, feat4: torch.Tensor):
+        if not (feat4.is_cuda and feat4.dtype == torch.float32 and feat4.is_contiguous()):
+            raise TypeError("feat4 must be a contiguous float32 CUDA tensor")
+        self._chk("ns_features", lib().ns_features(self.ctx, dt, _dev_f64(p_prev, "p_prev"), feat4.data_ptr()))
+
+    def target(self, p_prev: torch.Tensor, t: torch.Tensor):
+        self._chk("ns_target", lib().ns_target(self.ctx, _dev_f64(p_prev, "p_prev"), t.data_ptr()))
+
     def diagnostics(self):
         out = (C.c_double * 4)()
         self._chk("ns_diagnostics", lib().ns_diagnostics(self.ctx, out))
@@ -268,3 +300,84 @@ def device_fields(host_fields: dict, device="cuda") -> dict:
     """Copy numpy initial fields to float64 device tensors."""
     return {k: torch.from_numpy(host_fields[k]).to(device=device, dtype=torch.float64).contiguous()
             for k in ("sigma", "u", "v", "w", "p")}
+
+
+def net_param_count() -> int:
+    return lib().ns_net_param_count()
+
+
+class Net:
+    """The learned-guess network on an nx*ny*nz grid (device workspace owned
+    by this object's torch tensor)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, training: bool = False, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the network runs only on the gfx950 library")
+        L = lib()
+        nbytes = L.ns_net_workspace_bytes(nx, ny, nz, 1 if training else 0)
+        if nbytes == 0:
+            raise ValueError("network grid sizes must be multiples of 4")
+        self.shape = (nz, ny, nx)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        net = C.c_void_p()
+        st = L.ns_net_create(nx, ny, nz, 1 if training else 0, C.c_void_p(base + off), nbytes,
+                             C.c_void_p(self.stream.cuda_stream), C.byref(net))
+        if st != NS_OK:
+            raise NSError("ns_net_create", st, "invalid sizes or workspace")
+        self.net = net
+        self.n = L.ns_net_param_count()
+
+    def _chk(self, fn, st):
+        if st != NS_OK:
+            msg = lib().ns_net_last_error(self.net)
+            raise NSError(fn, st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "net", None):
+            lib().ns_net_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.n
+        self._chk("ns_net_set_params",
+                  lib().ns_net_set_params(self.net, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.n, dtype=np.float32)
+        self._chk("ns_net_get_params",
+                  lib().ns_net_get_params(self.net, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def get_grads(self):
+        import numpy as np
+        a = np.empty(self.n, dtype=np.float32)
+        self._chk("ns_net_get_grads",
+                  lib().ns_net_get_grads(self.net, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def forward(self, feat4: torch.Tensor) -> torch.Tensor:
+        """delta (float32, (nz, ny, nx)) for features (float32, (4, nz, ny, nx))."""
+        assert feat4.is_cuda and feat4.dtype == torch.float32 and feat4.is_contiguous()
+        out = torch.empty(self.shape, dtype=torch.float32, device=feat4.device)
+        self._chk("ns_net_set_input", lib().ns_net_set_input(self.net, feat4.data_ptr()))
+        self._chk("ns_net_forward", lib().ns_net_forward(self.net, out.data_ptr()))
+        return out
+
+    def train_step(self, feat4: torch.Tensor, target: torch.Tensor, lr: float, update: bool = True) -> float:
+        loss = C.c_double()
+        self._chk("ns_net_train_step", lib().ns_net_train_step(self.net, feat4.data_ptr(), target.data_ptr(),
+                                                               lr, 1 if update else 0, C.byref(loss)))
+        return loss.value
