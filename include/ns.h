@@ -128,7 +128,10 @@ typedef enum {
   NS_BUF_MU = 8,
   NS_BUF_CHI = 9,
   NS_BUF_RHOFLOW = 10,
-  NS_BUF_COUNT = 11
+  NS_BUF_BXF = 11,  /* FP32 copies of the level-0 beta (written by momentum_step) */
+  NS_BUF_BYF = 12,
+  NS_BUF_BZF = 13,
+  NS_BUF_COUNT = 14
 } ns_buffer_id;
 
 typedef struct ns_ctx ns_ctx;
@@ -248,12 +251,15 @@ ns_status ns_net_set_input(ns_net* net, const float* feat4);
  * receives delta when not NULL. */
 ns_status ns_net_forward(ns_net* net, float* delta_out);
 
-/* One training step on one sample (device FP32 features and target delta):
- * forward, loss L = sum (delta - t)^2 / sum t^2 (the squared error of p0
- * relative to that of p_prev), backward, and when update != 0 an Adam step
- * (betas 0.9/0.999, eps 1e-8) of rate lr.  *loss gets L (synchronises). */
-ns_status ns_net_train_step(ns_net* net, const float* feat4, const float* target, float lr, int update,
-                            double* loss);
+/* One training step on one sample (device FP32 features, target delta* =
+ * (p* - p_prev)/P0 and the sample's face coefficients beta on x, y, z faces,
+ * layouts as the velocity faces): forward, the energy-norm loss
+ *   L = e'Ae / t'At,  e = t - delta,
+ * i.e. ||p* - p0||_A^2 / ||p* - p_prev||_A^2 (below 1 when the guess beats
+ * p_prev in the norm CG minimises), backward, and when update != 0 an Adam
+ * step (betas 0.9/0.999, eps 1e-8) of rate lr.  *loss gets L (synchronises). */
+ns_status ns_net_train_step(ns_net* net, const float* feat4, const float* target, const float* beta_x,
+                            const float* beta_y, const float* beta_z, float lr, int update, double* loss);
 
 /* Use `net` (same grid) for x0 = NS_X0_LEARNED in this context. */
 ns_status ns_attach_net(ns_ctx* ctx, ns_net* net);

@@ -170,6 +170,18 @@ def loss_and_grad(delta, target):
     return float(np.sum(e * e)) / den, 2.0 * e / den
 
 
+def energy_loss_and_grad(delta, target, apply_A):
+    """Energy-norm ratio ||e||_A^2 / ||target||_A^2 with e = target - delta:
+    with p0 = p_prev + P0 delta and p* = p_prev + P0 target this is
+    ||p* - p0||_A^2 / ||p* - p_prev||_A^2, the norm CG minimises, so values
+    below 1 mean the guess beats p_prev.  Returns (loss, d loss / d delta)
+    for a symmetric operator apply_A."""
+    e = target - delta
+    Ae = apply_A(e)
+    den = float(np.sum(target * apply_A(target)))
+    return float(np.sum(e * Ae)) / den, -2.0 * Ae / den
+
+
 def features(b, rho, p_prev, r0, h, rho_w, rho_a, P0):
     """The four input channels: scaled rhs, log-density fraction, scaled
     previous pressure, scaled residual of the previous pressure."""
@@ -177,13 +189,16 @@ def features(b, rho, p_prev, r0, h, rho_w, rho_a, P0):
     return np.stack([b * s, np.log(rho / rho_w) / np.log(rho_a / rho_w), p_prev / P0, r0 * s])
 
 
-def he_init(seed: int):
-    """He-normal weights (std sqrt(2 / fan_in)), zero biases, as a flat vector."""
+def he_init(seed: int, zero_head: bool = False):
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases, as a flat
+    vector; with zero_head the output layer starts at zero (delta = 0)."""
     rng = np.random.default_rng(seed)
     P = {}
     for name, ci, co, k in LAYERS:
         fan_in = ci * k ** 3
         P[name + ".w"] = rng.standard_normal((co, ci, k, k, k)) * np.sqrt(2.0 / fan_in)
+        if zero_head and name == "head":
+            P[name + ".w"][:] = 0.0
         P[name + ".b"] = np.zeros(co)
     return flatten(P)
 

@@ -859,6 +859,9 @@ ns_status ns_buffer(ns_ctx* X, int which, void** dev_ptr, size_t* count) {
     case NS_BUF_MU: p = X->mu; c = X->nc; break;
     case NS_BUF_CHI: p = X->chi; c = X->nc; break;
     case NS_BUF_RHOFLOW: p = X->rfl; c = X->nc; break;
+    case NS_BUF_BXF: p = L0.bxf; c = X->nu; break;
+    case NS_BUF_BYF: p = L0.byf; c = X->nv; break;
+    case NS_BUF_BZF: p = L0.bzf; c = X->nw; break;
     default: return fail(X, NS_EINVAL, "unknown buffer id %d", which);
   }
   *dev_ptr = p;

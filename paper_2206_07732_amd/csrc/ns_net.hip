@@ -173,15 +173,23 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nblk, int cin
   g[((size_t)co * 27 + tap) * cin + ci] = s;
 }
 
-// per-block channel sums of dY (bias gradient), then their fixed-order total
+// per-block channel sums of dY (bias gradient), then their fixed-order total:
+// thread t handles channel t % C of voxels v0 + t / C, v0 + t / C + 256 / C, ...
 __global__ void __launch_bounds__(256) k_bias_part(long nv, int C, const uint16_t* __restrict__ dY,
                                                    int vox_per_block, float* __restrict__ part) {
+  __shared__ float sm[256];
   const long v0 = (long)blockIdx.x * vox_per_block;
   const long v1 = v0 + vox_per_block < nv ? v0 + vox_per_block : nv;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    float s = 0.f;
-    for (long v = v0; v < v1; ++v) s += bf2f(dY[v * C + c]);
-    part[(size_t)blockIdx.x * C + c] = s;
+  const int c = threadIdx.x % C, lanes = 256 / C, r = threadIdx.x / C;
+  float s = 0.f;
+  if (r < lanes)
+    for (long v = v0 + r; v < v1; v += lanes) s += bf2f(dY[v * C + c]);
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < C) {
+    float t = 0.f;
+    for (int q = 0; q < lanes; ++q) t += sm[q * C + threadIdx.x];
+    part[(size_t)blockIdx.x * C + threadIdx.x] = t;
   }
 }
 
@@ -380,15 +388,43 @@ __global__ void k_target(long nv, const double* __restrict__ p, const double* __
   if (v < nv) t[v] = (float)((p[v] - pprev[v]) * inv_P0);
 }
 
-// per-block (sum (delta - t)^2, sum t^2)
-__global__ void __launch_bounds__(256) k_loss_part(long nv, const float* __restrict__ delta,
-                                                   const float* __restrict__ t, double* __restrict__ part) {
+// y = A x in FP32 on the finest grid (sum_f beta_f (x_c - x_nb), open top
+// face coupling to -x_c; the 1/h^2 factor cancels in the loss ratio)
+__global__ void __launch_bounds__(256) k_spmv_f32(VDims d, const float* __restrict__ bx,
+                                                  const float* __restrict__ by, const float* __restrict__ bz,
+                                                  const float* __restrict__ x, float* __restrict__ y) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= vox_count(d)) return;
+  const int i = (int)(c % d.nx), j = (int)((c / d.nx) % d.ny), k = (int)(c / ((long)d.nx * d.ny));
+  const long sxy = (long)d.nx * d.ny;
+  const long fx = i + (long)(d.nx + 1) * (j + (long)d.ny * k);
+  const long fy = i + (long)d.nx * (j + (long)(d.ny + 1) * k);
+  const float xc = x[c];
+  float a = 0.f;
+  if (i > 0) a += bx[fx] * (xc - x[c - 1]);
+  if (i < d.nx - 1) a += bx[fx + 1] * (xc - x[c + 1]);
+  if (j > 0) a += by[fy] * (xc - x[c - d.nx]);
+  if (j < d.ny - 1) a += by[fy + d.nx] * (xc - x[c + d.nx]);
+  if (k > 0) a += bz[c] * (xc - x[c - sxy]);
+  a += (k < d.nz - 1) ? bz[c + sxy] * (xc - x[c + sxy]) : 2.f * bz[c + sxy] * xc;
+  y[c] = a;
+}
+
+// e = t - delta (the guess's error in units of P0)
+__global__ void k_err(long nv, const float* __restrict__ delta, const float* __restrict__ t, float* __restrict__ e) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) e[v] = t[v] - delta[v];
+}
+
+// per-block (sum e Ae, sum t At)
+__global__ void __launch_bounds__(256) k_loss_part(long nv, const float* __restrict__ e, const float* __restrict__ Ae,
+                                                   const float* __restrict__ t, const float* __restrict__ At,
+                                                   double* __restrict__ part) {
   __shared__ double sa[256], sb[256];
   double a = 0.0, b = 0.0;
   for (long v = (long)blockIdx.x * 256 + threadIdx.x; v < nv; v += (long)gridDim.x * 256) {
-    const double e = (double)delta[v] - (double)t[v];
-    a += e * e;
-    b += (double)t[v] * (double)t[v];
+    a += (double)e[v] * (double)Ae[v];
+    b += (double)t[v] * (double)At[v];
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = b;
@@ -406,7 +442,7 @@ __global__ void __launch_bounds__(256) k_loss_part(long nv, const float* __restr
   }
 }
 
-// out[0] = loss, out[1] = 2 / sum t^2
+// out[0] = loss = e'Ae / t'At, out[1] = -2 / t'At
 __global__ void k_loss_fin(const double* __restrict__ part, int nblk, double* __restrict__ out) {
   if (threadIdx.x != 0) return;
   double a = 0.0, b = 0.0;
@@ -415,14 +451,13 @@ __global__ void k_loss_fin(const double* __restrict__ part, int nblk, double* __
     b += part[2 * q + 1];
   }
   out[0] = b > 0.0 ? a / b : 0.0;
-  out[1] = b > 0.0 ? 2.0 / b : 0.0;
+  out[1] = b > 0.0 ? -2.0 / b : 0.0;
 }
 
-// ddelta = 2 (delta - t) / sum t^2
-__global__ void k_dloss(long nv, const float* __restrict__ delta, const float* __restrict__ t,
-                        const double* __restrict__ out, float* __restrict__ dd) {
+// dL/ddelta = -2 A e / t'At  (A symmetric)
+__global__ void k_dloss(long nv, const float* __restrict__ Ae, const double* __restrict__ out, float* __restrict__ dd) {
   const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < nv) dd[v] = (float)(out[1] * ((double)delta[v] - (double)t[v]));
+  if (v < nv) dd[v] = (float)(out[1] * (double)Ae[v]);
 }
 
 __global__ void k_finite_count(long n, const float* __restrict__ a, int* __restrict__ bad) {
@@ -468,6 +503,7 @@ struct ns_net {
   // learned-guess staging
   float* feat;
   float* target;
+  float* eb;
   double* pprev;
   double* Ap;
   int step;
@@ -530,6 +566,7 @@ size_t net_layout(ns_net* N, int nx, int ny, int nz, int training, char* base) {
   float* delta = cv.take<float>(v0);
   float* feat = cv.take<float>(4 * v0);
   float* target = cv.take<float>(v0);
+  float* eb = cv.take<float>(3 * v0);   // e, A e, A t of the loss
   double* pprev = cv.take<double>(v0);
   double* Ap = cv.take<double>(v0);
   double* red = cv.take<double>(4096);
@@ -594,6 +631,7 @@ size_t net_layout(ns_net* N, int nx, int ny, int nz, int training, char* base) {
     N->delta = delta;
     N->feat = feat;
     N->target = target;
+    N->eb = eb;
     N->pprev = pprev;
     N->Ap = Ap;
     N->red = red;
@@ -656,7 +694,7 @@ void wgrad(ns_net* N, VDims d, long nv, const uint16_t* X, const uint16_t* dY, i
   hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(nb, 27), dim3(256), 0, N->st, d, X, dY, kWgradVox, N->wpart);
   const int per = 27 * COUT * CIN;
   hipLaunchKernelGGL(k_wgrad_reduce, g1(per), dim3(256), 0, N->st, N->wpart, nb, CIN, COUT, N->g + N->ow[layer]);
-  hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(64), 0, N->st, nv, COUT, dY, kWgradVox, N->wpart);
+  hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(256), 0, N->st, nv, COUT, dY, kWgradVox, N->wpart);
   hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(128), 0, N->st, N->wpart, nb, COUT, N->g + N->ob[layer]);
 }
 
@@ -817,17 +855,22 @@ ns_status ns_net_forward(ns_net* N, float* delta_out) {
   return hipGetLastError() == hipSuccess ? NS_OK : nfail(N, NS_EHIP, "launch failed");
 }
 
-ns_status ns_net_train_step(ns_net* N, const float* feat4, const float* target, float lr, int update,
-                            double* loss) {
-  if (!N || !feat4 || !target) return NS_EINVAL;
+ns_status ns_net_train_step(ns_net* N, const float* feat4, const float* target, const float* bx, const float* by,
+                            const float* bz, float lr, int update, double* loss) {
+  if (!N || !feat4 || !target || !bx || !by || !bz) return NS_EINVAL;
   if (!N->training) return nfail(N, NS_ESTATE, "not a training net");
   hipStream_t st = N->st;
   hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, st, N->v0, feat4, N->x0);
   forward(N);
+  // energy-norm loss L = e'Ae / t'At with e = t - delta
+  float *e = N->eb, *Ae = N->eb + N->v0, *At = N->eb + 2 * N->v0;
   const int nb = 256;
-  hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, N->v0, N->delta, target, N->red);
+  hipLaunchKernelGGL(k_err, g1(N->v0), dim3(256), 0, st, N->v0, N->delta, target, e);
+  hipLaunchKernelGGL(k_spmv_f32, g1(N->v0), dim3(256), 0, st, N->res0, bx, by, bz, e, Ae);
+  hipLaunchKernelGGL(k_spmv_f32, g1(N->v0), dim3(256), 0, st, N->res0, bx, by, bz, target, At);
+  hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, N->v0, e, Ae, target, At, N->red);
   hipLaunchKernelGGL(k_loss_fin, dim3(1), dim3(64), 0, st, N->red, nb, N->red + 2 * nb);
-  hipLaunchKernelGGL(k_dloss, g1(N->v0), dim3(256), 0, st, N->v0, N->delta, target, N->red + 2 * nb, N->dd);
+  hipLaunchKernelGGL(k_dloss, g1(N->v0), dim3(256), 0, st, N->v0, Ae, N->red + 2 * nb, N->dd);
   backward(N);
   if (update) {
     ++N->step;

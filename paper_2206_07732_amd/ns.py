@@ -21,7 +21,7 @@ STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_ENOCONV", -3: "NS_ENAN", -4: "NS_
 PREC_FP64, PREC_MIXED = 0, 1
 X0_ZERO, X0_PREV, X0_LEARNED = 0, 1, 2
 BUF = {"us": 0, "vs": 1, "ws": 2, "bx": 3, "by": 4, "bz": 5, "rhs": 6, "rho": 7, "mu": 8, "chi": 9,
-       "rho_flow": 10}
+       "rho_flow": 10, "bxf": 11, "byf": 12, "bzf": 13}
 
 
 class NSBody(C.Structure):
@@ -100,7 +100,7 @@ def lib() -> C.CDLL:
             "ns_net_get_grads": ([vp, C.POINTER(C.c_float), C.c_size_t], i),
             "ns_net_set_input": ([vp, vp], i),
             "ns_net_forward": ([vp, vp], i),
-            "ns_net_train_step": ([vp, vp, vp, C.c_float, i, C.POINTER(C.c_double)], i),
+            "ns_net_train_step": ([vp, vp, vp, vp, vp, vp, C.c_float, i, C.POINTER(C.c_double)], i),
             "ns_attach_net": ([vp, vp], i),
             "ns_features": ([vp, d, vp, vp], i),
             "ns_target": ([vp, vp, vp], i),
@@ -252,15 +252,19 @@ class Solver:
         self._chk("ns_vcycle", lib().ns_vcycle(self.ctx, _dev_f64(r, "r"), _dev_f64(z, "z")))
 
     def buffer(self, name: str) -> torch.Tensor:
-        """A float64 view of an internal workspace array, shaped like its field."""
+        """A view of an internal workspace array (float64, or float32 for the
+        *f beta copies), shaped like its field."""
         ptr, cnt = C.c_void_p(), C.c_size_t()
         self._chk("ns_buffer", lib().ns_buffer(self.ctx, BUF[name], C.byref(ptr), C.byref(cnt)))
         off = ptr.value - self.workspace.data_ptr()
-        flat = self.workspace[off: off + 8 * cnt.value].view(torch.float64)
+        f32 = name in ("bxf", "byf", "bzf")
+        w = 4 if f32 else 8
+        flat = self.workspace[off: off + w * cnt.value].view(torch.float32 if f32 else torch.float64)
         nx, ny, nz = self.P.nx, self.P.ny, self.P.nz
+        key = name[:-1] if f32 else name
         shape = {"us": (nz, ny, nx + 1), "bx": (nz, ny, nx + 1), "vs": (nz, ny + 1, nx),
                  "by": (nz, ny + 1, nx), "ws": (nz + 1, ny, nx), "bz": (nz + 1, ny, nx)}.get(
-            name, (nz, ny, nx))
+            key, (nz, ny, nx))
         return flat.view(shape)
 
     def timing_enable(self, kernel: int, max_launches: int):
@@ -376,8 +380,13 @@ class Net:
         self._chk("ns_net_forward", lib().ns_net_forward(self.net, out.data_ptr()))
         return out
 
-    def train_step(self, feat4: torch.Tensor, target: torch.Tensor, lr: float, update: bool = True) -> float:
+    def train_step(self, feat4: torch.Tensor, target: torch.Tensor, beta, lr: float, update: bool = True) -> float:
+        """beta: (bx, by, bz) float32 face tensors of the sample's operator."""
+        bx, by, bz = beta
+        for t in (feat4, target, bx, by, bz):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
         loss = C.c_double()
-        self._chk("ns_net_train_step", lib().ns_net_train_step(self.net, feat4.data_ptr(), target.data_ptr(),
-                                                               lr, 1 if update else 0, C.byref(loss)))
+        self._chk("ns_net_train_step", lib().ns_net_train_step(
+            self.net, feat4.data_ptr(), target.data_ptr(), bx.data_ptr(), by.data_ptr(), bz.data_ptr(),
+            lr, 1 if update else 0, C.byref(loss)))
         return loss.value

@@ -25,6 +25,19 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def random_beta(nx, ny, nz, seed):
+    """Positive face coefficients with zero walls (x, y, bottom) as FP32 device tensors."""
+    rng = np.random.default_rng(seed)
+    bx = np.exp(rng.standard_normal((nz, ny, nx + 1)))
+    by = np.exp(rng.standard_normal((nz, ny + 1, nx)))
+    bz = np.exp(rng.standard_normal((nz + 1, ny, nx)))
+    bx[:, :, 0] = bx[:, :, -1] = 0
+    by[:, 0] = by[:, -1] = 0
+    bz[0] = 0
+    b32 = [a.astype(np.float32) for a in (bx, by, bz)]
+    return b32, tuple(torch.from_numpy(a).cuda() for a in b32)
+
+
 def test_param_count_matches_oracle():
     assert _ns().net_param_count() == N.param_count()
 
@@ -47,7 +60,7 @@ def test_forward_matches_oracle_bf16(dims):
     assert r < 1e-2
 
 
-def test_gradients_match_oracle():
+def test_gradients_match_oracle(orc):
     ns = _ns()
     nx, ny, nz = 16, 8, 8
     rng = np.random.default_rng(3)
@@ -56,12 +69,15 @@ def test_gradients_match_oracle():
     th32 = theta.astype(np.float32).astype(np.float64)
     feat = rng.standard_normal((4, nz, ny, nx)).astype(np.float32)
     target = (rng.standard_normal((nz, ny, nx)) * 0.3).astype(np.float32)
+    (bx, by, bz), beta = random_beta(nx, ny, nz, 4)
     net = ns.Net(nx, ny, nz, training=True)
     net.set_params(theta)
-    loss = net.train_step(torch.from_numpy(feat).cuda(), torch.from_numpy(target).cuda(), 1e-3, update=False)
+    loss = net.train_step(torch.from_numpy(feat).cuda(), torch.from_numpy(target).cuda(), beta, 1e-3, update=False)
     g = net.get_grads()
     out, cache = N.forward(N.unflatten(th32), feat.astype(np.float64), bf16=True)
-    L, dout = N.loss_and_grad(out, target.astype(np.float64))
+    op = lambda x: orc.apply_A(nx, ny, nz, 1.0, bx.astype(np.float64), by.astype(np.float64),
+                               bz.astype(np.float64), x)
+    L, dout = N.energy_loss_and_grad(out, target.astype(np.float64), op)
     gr = N.backward(cache, dout)
     print(f"[net grad] loss gpu={loss:.6f} oracle={L:.6f}", flush=True)
     assert abs(loss - L) < 1e-2 * L
@@ -77,6 +93,7 @@ def test_training_reduces_loss():
     nx, ny, nz = 16, 16, 8
     rng = np.random.default_rng(5)
     teacher = N.he_init(21)
+    _, beta = random_beta(nx, ny, nz, 6)
     samples = []
     for s in range(4):
         feat = rng.standard_normal((4, nz, ny, nx))
@@ -84,12 +101,13 @@ def test_training_reduces_loss():
         samples.append((torch.from_numpy(feat.astype(np.float32)).cuda(),
                         torch.from_numpy(t.astype(np.float32)).cuda()))
     net = ns.Net(nx, ny, nz, training=True)
-    net.set_params(N.he_init(22))
-    first = np.mean([net.train_step(f, t, 1e-3, update=False) for f, t in samples])
+    net.set_params(N.he_init(22, zero_head=True))
+    first = np.mean([net.train_step(f, t, beta, 1e-3, update=False) for f, t in samples])
+    assert abs(first - 1.0) < 1e-6            # zero head: the guess is p_prev
     for epoch in range(40):
         for f, t in samples:
-            net.train_step(f, t, 2e-3)
-    last = np.mean([net.train_step(f, t, 1e-3, update=False) for f, t in samples])
+            net.train_step(f, t, beta, 2e-3)
+    last = np.mean([net.train_step(f, t, beta, 1e-3, update=False) for f, t in samples])
     print(f"[net train] loss {first:.4f} -> {last:.4f}", flush=True)
     assert last < 0.5 * first
 

@@ -99,3 +99,24 @@ def test_adam_first_step_moves_by_lr():
 def test_param_count():
     assert N.param_count() == (16 * 4 * 27 + 16) + (32 * 16 * 27 + 32) + (64 * 32 * 27 + 64) + \
         (32 * 96 * 27 + 32) + (16 * 48 * 27 + 16) + (16 + 1)
+
+
+def test_energy_loss_gradient_and_special_values():
+    rng = np.random.default_rng(8)
+    n = 30
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)                     # SPD
+    op = lambda x: (A @ x.ravel()).reshape(x.shape)
+    t = rng.standard_normal((2, 3, 5))
+    d = rng.standard_normal((2, 3, 5))
+    L, g = N.energy_loss_and_grad(d, t, op)
+    assert abs(N.energy_loss_and_grad(np.zeros_like(t), t, op)[0] - 1.0) < 1e-14   # delta = 0 is p_prev
+    assert N.energy_loss_and_grad(t, t, op)[0] == 0.0                             # exact guess
+    eps = 1e-6
+    for idx in [(0, 0, 0), (1, 2, 4), (0, 1, 3)]:
+        dp = d.copy()
+        dm = d.copy()
+        dp[idx] += eps
+        dm[idx] -= eps
+        fd = (N.energy_loss_and_grad(dp, t, op)[0] - N.energy_loss_and_grad(dm, t, op)[0]) / (2 * eps)
+        assert abs(fd - g[idx]) < 1e-7 * max(1.0, abs(fd))
