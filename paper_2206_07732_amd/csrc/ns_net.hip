@@ -32,6 +32,9 @@ namespace nsk {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -48,58 +51,269 @@ struct VDims {
 __device__ __forceinline__ long vox_count(const VDims& d) { return (long)d.nx * d.ny * d.nz; }
 
 // ------------------------------------------------------------ convolution
-// EPI 0: + bias, ReLU (forward); EPI 1: plain (gradient w.r.t. the input)
-template <int KS, int CIN, int COUT, int EPI>
-__global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restrict__ X,
-                                              const uint16_t* __restrict__ W,
-                                              const float* __restrict__ bias, uint16_t* __restrict__ Y,
-                                              int ys, int yo) {
-  constexpr int R = KS / 2;
-  constexpr int NT = COUT / 16;
+// 3x3x3 convolution with zero padding as an implicit GEMM on the matrix
+// cores.  A block computes a 16 x 4 x 4 tile of output voxels for every
+// output channel; wave w owns the four x-rows of z-plane w of the tile.  The
+// input is staged in LDS 16 channels at a time with its one-voxel halo
+// (18 x 6 x 6 voxels, 20.7 KB), and each v_mfma_f32_16x16x32_bf16 takes two
+// taps x 16 input channels as its K = 32 (a 28th, zero tap pads the last
+// pair).  With k = 16 (tap - 2p) + ci for tap pair p:
+//   A (16 voxels x 32 k): lane l holds voxel row l%16, k = 8(l/16)..+7
+//   B (32 k x 16 out):    lane l holds output column l%16, k = 8(l/16)..+7
+//   D (16 x 16):          lane l holds column l%16, rows 4(l/16)..+3
+// Each weight fragment read from the cache feeds the wave's four rows.
+// The input is the channel concatenation of a tensor at this resolution
+// (channels [0, ca), channel stride sa) and, for channels [ca, CIN), a tensor
+// at half resolution read through nearest upsampling (channel stride sb), so
+// the decoder never materialises its upsampled inputs.
+// EPI 0: + bias, ReLU; 1: plain (gradient w.r.t. the input); 2: + bias,
+// ReLU, then the 1x1x1 head 16 -> 1 into delta (FP32), storing the
+// activation only when Y is given.
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHV = kHX * kHY * kHZ;
+// the two 8-channel halves of a staged chunk live in separate planes (16-byte
+// entries), the second shifted by 64 bytes, so eight consecutive lanes of an
+// A-fragment read touch 128 contiguous bytes
+constexpr int kPlane = kHV + 4;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+// offset of tap (dz, dy, dx) = (tap / 9, tap / 3 % 3, tap % 3) in the halo tile (0 for the pad tap)
+__host__ __device__ constexpr int tap_off(int tap) {
+  return tap >= 27 ? 0 : ((tap / 9) * kHY + (tap / 3) % 3) * kHX + tap % 3;
+}
+
+template <int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restrict__ XA, int sa, int ca,
+                                              const uint16_t* __restrict__ XB, int sb,
+                                              const uint16_t* __restrict__ W, const float* __restrict__ bias,
+                                              uint16_t* __restrict__ Y, int ys, int yo,
+                                              const float* __restrict__ hw, const float* __restrict__ hb,
+                                              float* __restrict__ delta) {
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
+  static_assert(EPI != 2 || COUT == 16, "the fused head takes 16 channels");
+  constexpr int NT = COUT / 16, NC = CIN / 16;
+  constexpr int NE = (2 * kHV + 255) / 256;   // 16-byte tile pieces per thread
+  // Up to two output-channel tiles the chunk's weight fragments are loaded
+  // ahead of the next chunk's tile (kept in registers), so waiting for the
+  // weights never waits for that prefetch; wider layers load per tap pair.
+  constexpr bool AHEAD = NT <= 2;
+  __shared__ u32x4 tile[2][2 * kPlane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
+  const int cnx = d.nx >> 1, cny = d.ny >> 1;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  // this thread's tile pieces: fine and coarse voxel of each, in-grid mask
+  int vf[NE], vc[NE];
+  unsigned ok = 0;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = tid + 256 * i, hv = e >> 1;
+    const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+    vf[i] = vc[i] = 0;
+    if (e < 2 * kHV && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz) {
+      ok |= 1u << i;
+      vf[i] = gx + d.nx * (gy + d.ny * gz);
+      vc[i] = (gx >> 1) + cnx * ((gy >> 1) + cny * (gz >> 1));
+    }
+  }
+  const int half8 = 8 * (tid & 1);   // every piece of a thread has the same half (256 is even)
+  u32x4 pre[NE];
+  auto fetch = [&](int c) {
+    const bool fromA = 16 * c < ca;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      pre[i] = zero;
+      if (ok >> i & 1u) {
+        const uint16_t* src = fromA ? XA + (long)vf[i] * sa + 16 * c + half8
+                                    : XB + (long)vc[i] * sb + (16 * c - ca) + half8;
+        pre[i] = *reinterpret_cast<const u32x4*>(src);
+      }
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + 256 * i;
+      if (e < 2 * kHV) tile[buf][(e & 1) * kPlane + (e >> 1)] = pre[i];
+    }
+  };
+  // weight fragment of tap pair p, output tile t, chunk c
+  const uint16_t* wl = W + (long)r * 27 * CIN + (long)(kg >> 1) * CIN + 8 * (kg & 1);
+  auto wfrag = [&](int p, int t, int c) -> bf16x8 {
+    const int tap = 2 * p + (kg >> 1);
+    return as_bf16x8(tap < 27 ? *reinterpret_cast<const u32x4*>(wl + (long)t * 16 * 27 * CIN + 2 * p * CIN + 16 * c)
+                              : zero);
+  };
+  const int lbase = (kg & 1) * kPlane + wave * kHY * kHX + r;   // this lane's A piece for tap 0, row 0
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  put(0);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    bf16x8 bw[AHEAD ? 14 : 1][NT];
+    if constexpr (AHEAD) {
+#pragma unroll
+      for (int p = 0; p < 14; ++p)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bw[p][t] = wfrag(p, t, c);
+    }
+    if (c + 1 < NC) fetch(c + 1);
+    const u32x4* T = tile[c & 1] + lbase;
+#pragma unroll
+    for (int p = 0; p < 14; ++p) {
+      const bool tv = 2 * p + (kg >> 1) < 27;
+      const int o = (kg >> 1) ? tap_off(2 * p + 1) : tap_off(2 * p);
+      bf16x8 b[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = AHEAD ? bw[AHEAD ? p : 0][t] : wfrag(p, t, c);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bf16x8 a = as_bf16x8(tv ? T[o + m * kHX] : zero);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+      }
+    }
+    if (c + 1 < NC) put((c + 1) & 1);
+    __syncthreads();
+  }
+  // Epilogue.  Up to 64 output channels the wave's 64 voxels x COUT results
+  // are transposed through its own slice of the (now idle) tile memory and
+  // stored as 16-byte pieces of 8 channels; wider layers store directly.
+  constexpr bool STAGE = COUT <= 64;
+  static_assert(!STAGE || 4 * 64 * COUT * 2 <= (int)sizeof(tile), "staging fits in the tile");
+  const bool store = (EPI != 2) || (Y != nullptr);
+  uint16_t* stg = reinterpret_cast<uint16_t*>(&tile[0][0]) + wave * 64 * COUT;
+  const int z = z0 + wave;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int y = y0 + m;
+    const long row = (long)d.nx * (y + (long)d.ny * z);
+    float hs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + r;
+      const float bb = (EPI == 1) ? 0.f : bias[co];
+      const float wh = (EPI == 2) ? hw[co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = x0 + 4 * kg + i;
+        float val = acc[m][t][i] + bb;
+        if (EPI != 1) val = fmaxf(val, 0.f);
+        const uint16_t q = f2bf(val);
+        if (STAGE)
+          stg[(m * 16 + 4 * kg + i) * COUT + co] = q;
+        else if (store && x < d.nx && y < d.ny && z < d.nz)
+          Y[(row + x) * ys + yo + co] = q;
+        if (EPI == 2) hs[i] = wh * bf2f(q);
+      }
+    }
+    if (EPI == 2) {
+      // sum the 16 channels: the 16 lanes of one row group
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) hs[i] += __shfl_xor(hs[i], o, 16);
+      if (r == 0 && y < d.ny && z < d.nz) {
+        const float b0 = hb[0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int x = x0 + 4 * kg + i;
+          if (x < d.nx) delta[row + x] = hs[i] + b0;
+        }
+      }
+    }
+  }
+  if (STAGE && store) {
+    __syncthreads();
+    constexpr int G = COUT / 8;   // 16-byte pieces per voxel
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int q = lane + 64 * j, vl = q / G, cg = q % G;
+      const int x = x0 + (vl & 15), y = y0 + (vl >> 4);
+      if (x < d.nx && y < d.ny && z < d.nz)
+        *reinterpret_cast<u32x4*>(Y + ((long)x + (long)d.nx * (y + (long)d.ny * z)) * ys + yo + 8 * cg) =
+            *reinterpret_cast<const u32x4*>(stg + vl * COUT + 8 * cg);
+    }
+  }
+}
+
+// First layer at inference: the four FP32 feature channels (channel-first,
+// feat[c nv + v]) are converted to bfloat16 while staged in LDS (8 bytes per
+// halo voxel), and K runs over (tap, channel) compactly, k = 4 tap + ci with
+// 108 real entries padded to 128: four K = 32 steps instead of fourteen.
+// Wc is [16 outputs][128 k].  Output: + bias, ReLU, bfloat16, channel stride ys.
+__global__ void __launch_bounds__(256) k_conv_in(VDims d, const float* __restrict__ feat,
+                                                 const uint16_t* __restrict__ Wc, const float* __restrict__ bias,
+                                                 uint16_t* __restrict__ Y, int ys) {
+  __shared__ u32x2 tile[kHV + 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
   const long nv = vox_count(d);
-  const long vb = ((long)blockIdx.x * 4 + wave) * 16;
-  if (vb >= nv) return;                        // whole wavefront idle
-  const int row = lane & 15, kq = lane >> 4;
-  const long v = vb + row;
-  const bool live = v < nv;
-  const int x = live ? (int)(v % d.nx) : 0;
-  const int y = live ? (int)((v / d.nx) % d.ny) : 0;
-  const int z = live ? (int)(v / ((long)d.nx * d.ny)) : 0;
-  f32x4 acc[NT];
+  for (int e = threadIdx.x; e < kHV; e += 256) {
+    const int hx = e % kHX, hy = (e / kHX) % kHY, hz = e / (kHX * kHY);
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+    u32x2 val = {0u, 0u};
+    if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz) {
+      const long v = (long)gx + (long)d.nx * (gy + (long)d.ny * gz);
+      val[0] = (uint32_t)f2bf(feat[v]) | ((uint32_t)f2bf(feat[nv + v]) << 16);
+      val[1] = (uint32_t)f2bf(feat[2 * nv + v]) | ((uint32_t)f2bf(feat[3 * nv + v]) << 16);
+    }
+    tile[e] = val;
+  }
+  __syncthreads();
+  f32x4 acc[4];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16x4 zero4 = {0, 0, 0, 0};
-  for (int tap = 0; tap < KS * KS * KS; ++tap) {
-    const int dz = tap / (KS * KS) - R, dy = (tap / KS) % KS - R, dx = tap % KS - R;
-    const int xx = x + dx, yy = y + dy, zz = z + dz;
-    const bool in = live && xx >= 0 && xx < d.nx && yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz;
-    const uint16_t* xp = X + (in ? ((long)xx + (long)d.nx * (yy + (long)d.ny * zz)) * CIN : 0);
+  for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c0 = 0; c0 < CIN; c0 += 16) {
-      const bf16x4 a = in ? *reinterpret_cast<const bf16x4*>(xp + c0 + 4 * kq) : zero4;
+  for (int st = 0; st < 4; ++st) {
+    const int t0 = 8 * st + 2 * kg, t1 = t0 + 1;   // this lane's two taps
+    const bf16x8 b = as_bf16x8(*reinterpret_cast<const u32x4*>(Wc + r * 128 + 32 * st + 8 * kg));
+    const int o0 = ((t0 / 9) * kHY + (t0 / 3) % 3) * kHX + t0 % 3;
+    const int o1 = ((t1 / 9) * kHY + (t1 / 3) % 3) * kHX + t1 % 3;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x4 b =
-            *reinterpret_cast<const bf16x4*>(W + ((long)(t * 16 + row) * (KS * KS * KS) + tap) * CIN + c0 + 4 * kq);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-      }
+    for (int m = 0; m < 4; ++m) {
+      const int base = (wave * kHY + m) * kHX + r;
+      const u32x2 p0 = t0 < 27 ? tile[base + o0] : u32x2{0u, 0u};
+      const u32x2 p1 = t1 < 27 ? tile[base + o1] : u32x2{0u, 0u};
+      const u32x4 a = {p0[0], p0[1], p1[0], p1[1]};
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), b, acc[m], 0, 0, 0);
     }
   }
+  // transpose through LDS and store 16-byte pieces (as in k_conv)
+  __shared__ uint16_t stg_all[4 * 64 * 16];
+  uint16_t* stg = stg_all + wave * 64 * 16;
+  const float bb = bias[r];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + row;
-    const float bb = (EPI == 0) ? bias[co] : 0.f;
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long vo = vb + 4 * kq + i;
-      if (vo < nv) {
-        float val = acc[t][i] + bb;
-        if (EPI == 0) val = fmaxf(val, 0.f);
-        Y[vo * ys + yo + co] = f2bf(val);
-      }
-    }
+    for (int i = 0; i < 4; ++i) stg[(m * 16 + 4 * kg + i) * 16 + r] = f2bf(fmaxf(acc[m][i] + bb, 0.f));
+  __syncthreads();
+  const int z = z0 + wave;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = lane + 64 * j, vl = q >> 1, cg = q & 1;
+    const int x = x0 + (vl & 15), y = y0 + (vl >> 4);
+    if (x < d.nx && y < d.ny && z < d.nz)
+      *reinterpret_cast<u32x4*>(Y + ((long)x + (long)d.nx * (y + (long)d.ny * z)) * ys + 8 * cg) =
+          *reinterpret_cast<const u32x4*>(stg + vl * 16 + 8 * cg);
   }
+}
+
+// compact first-layer weights: Wc[co][4 tap + ci] from the padded FP32 master W[co][tap][16]
+__global__ void k_compact_w0(const float* __restrict__ w, uint16_t* __restrict__ wc) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 16 * 128) return;
+  const int co = q / 128, k = q % 128, tap = k / 4, ci = k % 4;
+  wc[q] = tap < 27 ? f2bf(w[(co * 27 + tap) * 16 + ci]) : (uint16_t)0;
 }
 
 // weight gradient of one tap: part[blk][tap][co][ci] = sum over this block's
@@ -202,23 +416,33 @@ __global__ void k_bias_reduce(const float* __restrict__ part, int nblk, int C, f
 }
 
 // ------------------------------------------------------- resampling, head
-// 2x2x2 average of a fine tensor (channel stride is, offset io) into a dense coarse one
+// 2x2x2 average of a fine tensor (channel stride is, offset io) into a dense
+// coarse one; a thread takes 8 channels of one coarse voxel
 __global__ void k_pool(VDims fine, const uint16_t* __restrict__ in, int is, int io, int C,
                        uint16_t* __restrict__ out) {
   const VDims c{fine.nx / 2, fine.ny / 2, fine.nz / 2};
   const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= vox_count(c) * C) return;
-  const int ch = (int)(q % C);
-  const long v = q / C;
+  const int groups = C / 8;
+  if (q >= vox_count(c) * groups) return;
+  const int g = (int)(q % groups);
+  const long v = q / groups;
   const int X = (int)(v % c.nx), Y = (int)((v / c.nx) % c.ny), Z = (int)(v / ((long)c.nx * c.ny));
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int k = 0; k < 2; ++k)
     for (int j = 0; j < 2; ++j)
       for (int i = 0; i < 2; ++i) {
         const long f = (2L * X + i) + (long)fine.nx * ((2L * Y + j) + (long)fine.ny * (2L * Z + k));
-        s += bf2f(in[f * is + io + ch]);
+        const u32x4 w = *reinterpret_cast<const u32x4*>(in + f * is + io + 8 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          s[2 * e] += __uint_as_float(w[e] << 16);
+          s[2 * e + 1] += __uint_as_float(w[e] & 0xFFFF0000u);
+        }
       }
-  out[q] = f2bf(s * 0.125f);
+  u32x4 o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o[e] = (uint32_t)f2bf(s[2 * e] * 0.125f) | ((uint32_t)f2bf(s[2 * e + 1] * 0.125f) << 16);
+  *reinterpret_cast<u32x4*>(out + v * C + 8 * g) = o;
 }
 
 // nearest x2 upsampling of a dense coarse tensor into a fine one (stride os, offset oo)
@@ -367,11 +591,14 @@ __global__ void k_features(long nv, double s, double lr_w, double inv_lr, double
 
 // channel-first FP32 features -> channels-last bfloat16 input, padded to 16
 __global__ void k_set_input(long nv, const float* __restrict__ feat, uint16_t* __restrict__ x0) {
-  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nv * 16) return;
-  const long v = q / 16;
-  const int c = (int)(q % 16);
-  x0[q] = c < 4 ? f2bf(feat[c * nv + v]) : (uint16_t)0;
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  u32x4 lo = {0u, 0u, 0u, 0u};
+  lo[0] = (uint32_t)f2bf(feat[v]) | ((uint32_t)f2bf(feat[nv + v]) << 16);
+  lo[1] = (uint32_t)f2bf(feat[2 * nv + v]) | ((uint32_t)f2bf(feat[3 * nv + v]) << 16);
+  u32x4* o = reinterpret_cast<u32x4*>(x0 + v * 16);
+  o[0] = lo;
+  o[1] = u32x4{0u, 0u, 0u, 0u};
 }
 
 // p = p_prev + P0 delta
@@ -490,6 +717,7 @@ struct ns_net {
   size_t ow[5], ob[5], ohw, ohb;
   float *theta, *m, *v, *g;
   uint16_t *wf[5], *wt[5];
+  uint16_t* wc0;   // first layer, compact K (inference)
   uint16_t *x0, *C1, *p1, *C2, *p2, *a3, *a4, *a5;
   float* delta;
   // backward
@@ -555,6 +783,7 @@ size_t net_layout(ns_net* N, int nx, int ny, int nz, int training, char* base) {
     wf[l] = cv.take<uint16_t>((size_t)kCout[l] * 27 * kCin[l]);
     wt[l] = cv.take<uint16_t>((size_t)kCout[l] * 27 * kCin[l]);
   }
+  uint16_t* wc0 = cv.take<uint16_t>(16 * 128);
   uint16_t* x0 = cv.take<uint16_t>(v0 * 16);
   uint16_t* C1 = cv.take<uint16_t>(v0 * 48);
   uint16_t* p1 = cv.take<uint16_t>(v1 * 16);
@@ -620,6 +849,7 @@ size_t net_layout(ns_net* N, int nx, int ny, int nz, int training, char* base) {
     N->m = m;
     N->v = v;
     N->g = g;
+    N->wc0 = wc0;
     N->x0 = x0;
     N->C1 = C1;
     N->p1 = p1;
@@ -657,15 +887,18 @@ ns_status nfail(ns_net* N, ns_status s, const char* msg) {
   return s;
 }
 
-template <int KS, int CIN, int COUT, int EPI>
-void conv(const ns_net* N, VDims d, long nv, const uint16_t* X, const uint16_t* W, const float* bias,
-          uint16_t* Y, int ys, int yo) {
-  const unsigned blocks = (unsigned)((nv + 63) / 64);
-  hipLaunchKernelGGL((k_conv<KS, CIN, COUT, EPI>), dim3(blocks), dim3(256), 0, N->st, d, X, W, bias, Y, ys, yo);
+template <int CIN, int COUT, int EPI>
+void conv(const ns_net* N, VDims d, const uint16_t* XA, int sa, int ca, const uint16_t* XB, int sb,
+          const uint16_t* W, const float* bias, uint16_t* Y, int ys, int yo, const float* hw = nullptr,
+          const float* hb = nullptr, float* delta = nullptr) {
+  const dim3 grid((d.nx + kTX - 1) / kTX, (d.ny + kTY - 1) / kTY, (d.nz + kTZ - 1) / kTZ);
+  hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), grid, dim3(256), 0, N->st, d, XA, sa, ca, XB, sb, W, bias, Y, ys,
+                     yo, hw, hb, delta);
 }
 
 // bf16 copies (forward and flipped-transposed) of the FP32 master weights
 void refresh_weights(ns_net* N) {
+  hipLaunchKernelGGL(k_compact_w0, dim3(8), dim3(256), 0, N->st, N->theta + N->ow[0], N->wc0);
   for (int l = 0; l < 5; ++l) {
     const long n = (long)kCout[l] * 27 * kCin[l];
     hipLaunchKernelGGL(k_to_bf16, g1(n), dim3(256), 0, N->st, N->theta + N->ow[l], n, N->wf[l]);
@@ -674,18 +907,50 @@ void refresh_weights(ns_net* N) {
   }
 }
 
-void forward(ns_net* N) {
+// Training forward: every activation the backward pass reads is stored,
+// including the concatenated decoder inputs C2 = [a2, up(a3)] and
+// C1 = [a1, up(a4)] and the last activation a5.
+void forward_train(ns_net* N) {
   const float* th = N->theta;
-  conv<3, 16, 16, 0>(N, N->res0, N->v0, N->x0, N->wf[0], th + N->ob[0], N->C1, 48, 0);
-  hipLaunchKernelGGL(k_pool, g1(N->v1 * 16), dim3(256), 0, N->st, N->res0, N->C1, 48, 0, 16, N->p1);
-  conv<3, 16, 32, 0>(N, N->res1, N->v1, N->p1, N->wf[1], th + N->ob[1], N->C2, 96, 0);
-  hipLaunchKernelGGL(k_pool, g1(N->v2 * 32), dim3(256), 0, N->st, N->res1, N->C2, 96, 0, 32, N->p2);
-  conv<3, 32, 64, 0>(N, N->res2, N->v2, N->p2, N->wf[2], th + N->ob[2], N->a3, 64, 0);
+  conv<16, 16, 0>(N, N->res0, N->x0, 16, 16, nullptr, 0, N->wf[0], th + N->ob[0], N->C1, 48, 0);
+  hipLaunchKernelGGL(k_pool, g1(N->v1 * 2), dim3(256), 0, N->st, N->res0, N->C1, 48, 0, 16, N->p1);
+  conv<16, 32, 0>(N, N->res1, N->p1, 16, 16, nullptr, 0, N->wf[1], th + N->ob[1], N->C2, 96, 0);
+  hipLaunchKernelGGL(k_pool, g1(N->v2 * 4), dim3(256), 0, N->st, N->res1, N->C2, 96, 0, 32, N->p2);
+  conv<32, 64, 0>(N, N->res2, N->p2, 32, 32, nullptr, 0, N->wf[2], th + N->ob[2], N->a3, 64, 0);
   hipLaunchKernelGGL(k_up, g1(N->v1 * 64), dim3(256), 0, N->st, N->res2, N->a3, 64, N->C2, 96, 32);
-  conv<3, 96, 32, 0>(N, N->res1, N->v1, N->C2, N->wf[3], th + N->ob[3], N->a4, 32, 0);
+  conv<96, 32, 0>(N, N->res1, N->C2, 96, 96, nullptr, 0, N->wf[3], th + N->ob[3], N->a4, 32, 0);
   hipLaunchKernelGGL(k_up, g1(N->v0 * 32), dim3(256), 0, N->st, N->res1, N->a4, 32, N->C1, 48, 16);
-  conv<3, 48, 16, 0>(N, N->res0, N->v0, N->C1, N->wf[4], th + N->ob[4], N->a5, 16, 0);
+  conv<48, 16, 0>(N, N->res0, N->C1, 48, 48, nullptr, 0, N->wf[4], th + N->ob[4], N->a5, 16, 0);
   hipLaunchKernelGGL(k_head, g1(N->v0), dim3(256), 0, N->st, N->v0, N->a5, th + N->ohw, th + N->ohb, N->delta);
+}
+
+// Inference forward: the decoder convolutions read the skip tensor and the
+// coarse tensor directly (no upsampled copies), and the head is fused into
+// the last convolution, so a5 is never stored.
+// The input is the FP32 feature tensor in N->feat.
+void forward_infer(ns_net* N) {
+  const float* th = N->theta;
+  uint16_t* a1 = N->C1;   // dense [v0][16] in the concatenation buffer's memory
+  uint16_t* a2 = N->C2;   // dense [v1][32]
+  {
+    const VDims d = N->res0;
+    const dim3 grid((d.nx + kTX - 1) / kTX, (d.ny + kTY - 1) / kTY, (d.nz + kTZ - 1) / kTZ);
+    hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, N->st, d, N->feat, N->wc0, th + N->ob[0], a1, 16);
+  }
+  hipLaunchKernelGGL(k_pool, g1(N->v1 * 2), dim3(256), 0, N->st, N->res0, a1, 16, 0, 16, N->p1);
+  conv<16, 32, 0>(N, N->res1, N->p1, 16, 16, nullptr, 0, N->wf[1], th + N->ob[1], a2, 32, 0);
+  hipLaunchKernelGGL(k_pool, g1(N->v2 * 4), dim3(256), 0, N->st, N->res1, a2, 32, 0, 32, N->p2);
+  conv<32, 64, 0>(N, N->res2, N->p2, 32, 32, nullptr, 0, N->wf[2], th + N->ob[2], N->a3, 64, 0);
+  conv<96, 32, 0>(N, N->res1, a2, 32, 32, N->a3, 64, N->wf[3], th + N->ob[3], N->a4, 32, 0);
+  conv<48, 16, 2>(N, N->res0, a1, 16, 16, N->a4, 32, N->wf[4], th + N->ob[4], nullptr, 16, 0, th + N->ohw,
+                  th + N->ohb, N->delta);
+}
+
+void forward(ns_net* N) {
+  if (N->training)
+    forward_train(N);
+  else
+    forward_infer(N);
 }
 
 template <int CIN, int COUT>
@@ -710,19 +975,19 @@ void backward(ns_net* N) {
   }
   // layer 5: input C1 (48), output 16
   wgrad<48, 16>(N, N->res0, N->v0, N->C1, N->d5, 4);
-  conv<3, 16, 48, 1>(N, N->res0, N->v0, N->d5, N->wt[4], nullptr, N->dC1, 48, 0);
+  conv<16, 48, 1>(N, N->res0, N->d5, 16, 16, nullptr, 0, N->wt[4], nullptr, N->dC1, 48, 0);
   hipLaunchKernelGGL(k_up_bwd_mask, g1(N->v1 * 32), dim3(256), 0, st, N->res1, N->dC1, 48, 16, 32, N->a4, N->d4);
   // layer 4: input C2 (96), output 32
   wgrad<96, 32>(N, N->res1, N->v1, N->C2, N->d4, 3);
-  conv<3, 32, 96, 1>(N, N->res1, N->v1, N->d4, N->wt[3], nullptr, N->dC2, 96, 0);
+  conv<32, 96, 1>(N, N->res1, N->d4, 32, 32, nullptr, 0, N->wt[3], nullptr, N->dC2, 96, 0);
   hipLaunchKernelGGL(k_up_bwd_mask, g1(N->v2 * 64), dim3(256), 0, st, N->res2, N->dC2, 96, 32, 64, N->a3, N->d3);
   // layer 3: input p2 (32), output 64
   wgrad<32, 64>(N, N->res2, N->v2, N->p2, N->d3, 2);
-  conv<3, 64, 32, 1>(N, N->res2, N->v2, N->d3, N->wt[2], nullptr, N->dp2, 32, 0);
+  conv<64, 32, 1>(N, N->res2, N->d3, 64, 64, nullptr, 0, N->wt[2], nullptr, N->dp2, 32, 0);
   hipLaunchKernelGGL(k_skip_mask, g1(N->v1 * 32), dim3(256), 0, st, N->res1, N->dC2, 96, N->dp2, N->C2, 96, 32, N->d2);
   // layer 2: input p1 (16), output 32
   wgrad<16, 32>(N, N->res1, N->v1, N->p1, N->d2, 1);
-  conv<3, 32, 16, 1>(N, N->res1, N->v1, N->d2, N->wt[1], nullptr, N->dp1, 16, 0);
+  conv<32, 16, 1>(N, N->res1, N->d2, 32, 32, nullptr, 0, N->wt[1], nullptr, N->dp1, 16, 0);
   hipLaunchKernelGGL(k_skip_mask, g1(N->v0 * 16), dim3(256), 0, st, N->res0, N->dC1, 48, N->dp1, N->C1, 48, 16, N->d1);
   // layer 1: input x0 (16), output 16
   wgrad<16, 16>(N, N->res0, N->v0, N->x0, N->d1, 0);
@@ -842,7 +1107,10 @@ ns_status ns_net_get_grads(ns_net* N, float* host_grads, size_t n) {
 
 ns_status ns_net_set_input(ns_net* N, const float* feat4) {
   if (!N || !feat4) return NS_EINVAL;
-  hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, N->st, N->v0, feat4, N->x0);
+  if (N->training)
+    hipLaunchKernelGGL(k_set_input, g1(N->v0), dim3(256), 0, N->st, N->v0, feat4, N->x0);
+  else if (hipMemcpyAsync(N->feat, feat4, 4 * N->v0 * sizeof(float), hipMemcpyDeviceToDevice, N->st) != hipSuccess)
+    return nfail(N, NS_EHIP, "copy failed");
   return hipGetLastError() == hipSuccess ? NS_OK : nfail(N, NS_EHIP, "launch failed");
 }
 
@@ -860,7 +1128,7 @@ ns_status ns_net_train_step(ns_net* N, const float* feat4, const float* target, 
   if (!N || !feat4 || !target || !bx || !by || !bz) return NS_EINVAL;
   if (!N->training) return nfail(N, NS_ESTATE, "not a training net");
   hipStream_t st = N->st;
-  hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, st, N->v0, feat4, N->x0);
+  hipLaunchKernelGGL(k_set_input, g1(N->v0), dim3(256), 0, st, N->v0, feat4, N->x0);
   forward(N);
   // energy-norm loss L = e'Ae / t'At with e = t - delta
   float *e = N->eb, *Ae = N->eb + N->v0, *At = N->eb + 2 * N->v0;
@@ -911,7 +1179,7 @@ float* net_feat(ns_net* N) { return N->feat; }
 int net_guess(ns_net* N, double P0, double* p, hipStream_t st) {
   hipStream_t keep = N->st;
   N->st = st;
-  hipLaunchKernelGGL(k_set_input, g1(N->v0 * 16), dim3(256), 0, st, N->v0, N->feat, N->x0);
+  if (N->training) hipLaunchKernelGGL(k_set_input, g1(N->v0), dim3(256), 0, st, N->v0, N->feat, N->x0);
   forward(N);
   (void)hipMemsetAsync(N->bad, 0, sizeof(int), st);
   hipLaunchKernelGGL(k_finite_count, g1(N->v0), dim3(256), 0, st, N->v0, N->delta, N->bad);
