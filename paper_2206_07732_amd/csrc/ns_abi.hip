@@ -40,6 +40,9 @@ struct ns_ctx {
   ns_net* net;        // learned guess (not owned)
   int tail64, tail32; // first level of the LDS tail per precision (L: none)
   size_t lds64, lds32;
+  double* pack64;     // the tail levels' bx, by, bz, 1/D (tail kernel's LDS image)
+  float* pack32;
+  size_t npack64, npack32;
   char err[512];
 };
 
@@ -113,6 +116,47 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
   return true;
 }
 
+size_t pad4(size_t n) { return (n + 3) / 4 * 4; }
+
+// elements of the tail pack from level l down: bx, by, bz and 1/D per level
+size_t tail_pack_elems(const Level* lev, int L, int l) {
+  size_t tot = 0;
+  for (int q = l; q < L; ++q) {
+    const Dims n = lev[q].n;
+    const size_t c = (size_t)n.nx * n.ny * n.nz;
+    tot += pad4((size_t)(n.nx + 1) * n.ny * n.nz) + pad4((size_t)n.nx * (n.ny + 1) * n.nz) +
+           pad4((size_t)n.nx * n.ny * (n.nz + 1)) + pad4(c);
+  }
+  return tot;
+}
+
+// LDS elements of the tail from level l down: the pack, then b and e per level
+size_t tail_elems(const Level* lev, int L, int l) {
+  size_t tot = tail_pack_elems(lev, L, l);
+  for (int q = l; q < L; ++q) {
+    const Dims n = lev[q].n;
+    tot += 2 * pad4((size_t)n.nx * n.ny * n.nz);
+  }
+  return tot;
+}
+
+// first level whose tail fits the LDS budget and the workgroup (L: none)
+int plan_tail(const Level* lev, int L, size_t w, size_t* bytes) {
+  for (int l = 0; l < L; ++l) {
+    const Dims n = lev[l].n;
+    const size_t pairs = (size_t)((n.nx + 1) / 2) * n.ny * n.nz;
+    if (pairs > 2 * (size_t)kTailThreads) continue;
+    if (L - l > kTailMaxLevels) continue;
+    const size_t b = tail_elems(lev, L, l) * w;
+    if (b <= kTailLdsBytes) {
+      *bytes = b;
+      return l;
+    }
+  }
+  *bytes = 0;
+  return L;
+}
+
 // lay out every internal array; with ctx == nullptr only the size is computed
 size_t carve(const ns_params* P, ns_ctx* X, char* base) {
   Carve cv{base, 0};
@@ -155,31 +199,65 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     }
     V.h0 = P->h;
     for (int dd = 0; dd < 3; ++dd) V.f[dd] = act[dd] ? 2 : 1;
+  }
+  // The levels of the single-workgroup tail keep their face coefficients and
+  // 1/D in one contiguous pack per precision, laid out as the tail kernel's
+  // LDS image (bx, by, bz, 1/D per level, each padded to 4 elements), so the
+  // kernel stages them with one flat copy.
+  size_t lds64 = 0, lds32 = 0;
+  const int t64 = plan_tail(lev, L, sizeof(double), &lds64);
+  const int t32 = plan_tail(lev, L, sizeof(float), &lds32);
+  const size_t np64 = tail_pack_elems(lev, L, t64), np32 = tail_pack_elems(lev, L, t32);
+  double* pk64 = cv.take<double>(np64);
+  float* pk32 = cv.take<float>(np32);
+  size_t o64 = 0, o32 = 0;
+  auto from64 = [&](size_t n) {
+    double* p = pk64 ? pk64 + o64 : nullptr;
+    o64 += pad4(n);
+    return p;
+  };
+  auto from32 = [&](size_t n) {
+    float* p = pk32 ? pk32 + o32 : nullptr;
+    o32 += pad4(n);
+    return p;
+  };
+  for (int l = 0; l < L; ++l) {
+    Level& V = lev[l];
     const size_t c = (size_t)V.n.nx * V.n.ny * V.n.nz;
     const size_t fu = (size_t)(V.n.nx + 1) * V.n.ny * V.n.nz;
     const size_t fv = (size_t)V.n.nx * (V.n.ny + 1) * V.n.nz;
     const size_t fw = (size_t)V.n.nx * V.n.ny * (V.n.nz + 1);
-    V.bxf = cv.take<float>(fu);
-    V.byf = cv.take<float>(fv);
-    V.bzf = cv.take<float>(fw);
-    V.bf = cv.take<float>(c);
-    V.ef = cv.take<float>(c);
-    V.invdf = cv.take<float>(c);
-    V.invd = cv.take<double>(c);
-    if (l == 0) {
-      V.bx = V.by = V.bz = nullptr;   // level-0 FP64 beta lives in its own arrays below
-      V.b = V.e = nullptr;            // and its b, e alias CG vectors
+    if (l >= t32) {
+      V.bxf = from32(fu);
+      V.byf = from32(fv);
+      V.bzf = from32(fw);
+      V.invdf = from32(c);
+    } else {
+      V.bxf = cv.take<float>(fu);
+      V.byf = cv.take<float>(fv);
+      V.bzf = cv.take<float>(fw);
+      V.invdf = cv.take<float>(c);
+    }
+    if (l >= t64) {
+      V.bx = from64(fu);
+      V.by = from64(fv);
+      V.bz = from64(fw);
+      V.invd = from64(c);
     } else {
       V.bx = cv.take<double>(fu);
       V.by = cv.take<double>(fv);
       V.bz = cv.take<double>(fw);
+      V.invd = cv.take<double>(c);
+    }
+    V.bf = cv.take<float>(c);
+    V.ef = cv.take<float>(c);
+    if (l == 0) {
+      V.b = V.e = nullptr;   // level 0's b and e are CG vectors
+    } else {
       V.b = cv.take<double>(c);
       V.e = cv.take<double>(c);
     }
   }
-  double* bx0 = cv.take<double>(nu);
-  double* by0 = cv.take<double>(nv);
-  double* bz0 = cv.take<double>(nw);
   if (X) {
     X->nc = nc;
     X->nu = nu;
@@ -206,9 +284,14 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     X->nparts = nparts;
     X->L = L;
     for (int l = 0; l < L; ++l) X->lev[l] = lev[l];
-    X->lev[0].bx = bx0;
-    X->lev[0].by = by0;
-    X->lev[0].bz = bz0;
+    X->tail64 = t64;
+    X->tail32 = t32;
+    X->lds64 = lds64;
+    X->lds32 = lds32;
+    X->pack64 = pk64;
+    X->pack32 = pk32;
+    X->npack64 = np64;
+    X->npack32 = np32;
   }
   return cv.off + kAlign;
 }
@@ -258,37 +341,6 @@ struct LV<float> {
   static float* invd(const Level& L) { return L.invdf; }
 };
 
-// LDS elements of the tail from level l down (five face/cell arrays per level
-// plus 1/D, each padded to 16 bytes)
-size_t tail_elems(const Level* lev, int L, int l) {
-  size_t tot = 0;
-  for (int q = l; q < L; ++q) {
-    const Dims n = lev[q].n;
-    const size_t c = (size_t)n.nx * n.ny * n.nz;
-    const size_t f = (size_t)(n.nx + 1) * n.ny * n.nz + (size_t)n.nx * (n.ny + 1) * n.nz +
-                     (size_t)n.nx * n.ny * (n.nz + 1);
-    tot += f + 3 * c + 6 * 4;
-  }
-  return tot;
-}
-
-// first level whose tail fits the LDS budget and the workgroup (L: none)
-int plan_tail(const Level* lev, int L, size_t w, size_t* bytes) {
-  for (int l = 0; l < L; ++l) {
-    const Dims n = lev[l].n;
-    const size_t pairs = (size_t)((n.nx + 1) / 2) * n.ny * n.nz;
-    if (pairs > 2 * (size_t)kTailThreads) continue;
-    if (L - l > kTailMaxLevels) continue;
-    const size_t b = tail_elems(lev, L, l) * w;
-    if (b <= kTailLdsBytes) {
-      *bytes = b;
-      return l;
-    }
-  }
-  *bytes = 0;
-  return L;
-}
-
 template <typename T>
 int tail_start(const ns_ctx* X) {
   return sizeof(T) == 8 ? X->tail64 : X->tail32;
@@ -298,8 +350,8 @@ size_t tail_bytes(const ns_ctx* X) {
   return sizeof(T) == 8 ? X->lds64 : X->lds32;
 }
 
-// coarse coefficients of every level from level 0, and 1/D of the levels
-// above the tail, in precision T
+// coarse coefficients of every level from level 0, and 1/D of every level
+// (the tail stages it), in precision T
 template <typename T>
 void build_hierarchy(ns_ctx* X) {
   for (int l = 1; l < X->L; ++l) {
@@ -308,8 +360,7 @@ void build_hierarchy(ns_ctx* X) {
     launch_coarsen_beta<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
                            LV<T>::bz(C), X->st);
   }
-  const int lt = tail_start<T>(X);
-  for (int l = 0; l < lt; ++l) {
+  for (int l = 0; l < X->L; ++l) {
     const Level& V = X->lev[l];
     launch_invdiag<T>(V, LV<T>::bx(V), LV<T>::by(V), LV<T>::bz(V), LV<T>::invd(V), X->st);
   }
@@ -322,19 +373,12 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
   D.nu_pre = X->P.nu_pre;
   D.nu_post = X->P.nu_post;
   D.coarse_sweeps = X->P.coarse_sweeps;
+  // LDS image: the pack (bx, by, bz, 1/D per level) then b, e per level
   int off = 0;
   auto take = [&](size_t n) {
-    int o = off;
-    off += (int)((n + 3) / 4 * 4);
+    const int o = off;
+    off += (int)pad4(n);
     return o;
-  };
-  int nseg = 0, pos = 0;
-  D.seg_start[0] = 0;
-  auto seg = [&](const T* src, int dst, size_t cnt) {
-    D.seg_src[nseg] = src;
-    D.seg_dst[nseg] = dst;
-    pos += (int)cnt;
-    D.seg_start[++nseg] = pos;
   };
   for (int q = 0; q < D.nl; ++q) {
     const Level& V = X->lev[l0 + q];
@@ -342,20 +386,19 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
     D.n[q] = n;
     for (int d = 0; d < 3; ++d) D.f[q][d] = V.f[d];
     D.h2[q] = (T)(V.h * V.h);
-    const size_t mu = (size_t)(n.nx + 1) * n.ny * n.nz, mv = (size_t)n.nx * (n.ny + 1) * n.nz,
-                 mw = (size_t)n.nx * n.ny * (n.nz + 1), mc = (size_t)n.nx * n.ny * n.nz;
-    D.obx[q] = take(mu);
-    D.oby[q] = take(mv);
-    D.obz[q] = take(mw);
+    D.obx[q] = take((size_t)(n.nx + 1) * n.ny * n.nz);
+    D.oby[q] = take((size_t)n.nx * (n.ny + 1) * n.nz);
+    D.obz[q] = take((size_t)n.nx * n.ny * (n.nz + 1));
+    D.oid[q] = take((size_t)n.nx * n.ny * n.nz);
+  }
+  D.npack = off;
+  for (int q = 0; q < D.nl; ++q) {
+    const size_t mc = (size_t)D.n[q].nx * D.n[q].ny * D.n[q].nz;
     D.ob[q] = take(mc);
     D.oe[q] = take(mc);
-    D.oid[q] = take(mc);
-    seg(LV<T>::bx(V), D.obx[q], mu);
-    seg(LV<T>::by(V), D.oby[q], mv);
-    seg(LV<T>::bz(V), D.obz[q], mw);
   }
-  seg(b, D.ob[0], (size_t)D.n[0].nx * D.n[0].ny * D.n[0].nz);
-  D.nseg = nseg;
+  D.pack = LV<T>::bx(X->lev[l0]);   // the pack starts with the first tail level's bx
+  D.b0 = b;
   D.ge = e;
   launch_vcycle_tail<T>(D, bytes, X->st);
 }
@@ -604,8 +647,6 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     delete X;
     return NS_EHIP;
   }
-  X->tail64 = plan_tail(X->lev, X->L, sizeof(double), &X->lds64);
-  X->tail32 = plan_tail(X->lev, X->L, sizeof(float), &X->lds32);
   X->have_beta = false;
   X->timed_kernel = -1;
   X->kt = KTimer{nullptr, 0, 0};

@@ -83,12 +83,11 @@ struct TailDesc {
   T h2[kTailMaxLevels];
   int obx[kTailMaxLevels], oby[kTailMaxLevels], obz[kTailMaxLevels];  // LDS offsets (elements)
   int ob[kTailMaxLevels], oe[kTailMaxLevels], oid[kTailMaxLevels];
-  // staging: segment sg copies seg_start[sg+1] - seg_start[sg] elements from
-  // seg_src[sg] to LDS offset seg_dst[sg]
-  int nseg;
-  const T* seg_src[3 * kTailMaxLevels + 1];
-  int seg_dst[3 * kTailMaxLevels + 1];
-  int seg_start[3 * kTailMaxLevels + 2];
+  // staging: the first npack LDS elements are a flat copy of pack (the tail
+  // levels' bx, by, bz, 1/D), then the first level's b goes to ob[0]
+  const T* pack;
+  int npack;
+  const T* b0;
   T* ge;                                    // correction of the first tail level (output)
 };
 

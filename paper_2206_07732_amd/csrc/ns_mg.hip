@@ -52,13 +52,11 @@ __device__ __forceinline__ T stencil(const Dims& n, const T* __restrict__ bx, co
   const T xs = x[j > 0 ? c - n.nx : c];
   const T xn = x[j < n.ny - 1 ? c + n.nx : c];
   const T xd = x[k > 0 ? c - sxy : c];
+  const T xu = x[k < n.nz - 1 ? c + sxy : c];
   const T bu = bz[c + sxy];
   T acc = bx[fx] * (xc - xw) + bx[fx + 1] * (xc - xe) + by[fy] * (xc - xs) +
           by[fy + n.nx] * (xc - xn) + bz[c] * (xc - xd);
-  if (k < n.nz - 1)
-    acc += bu * (xc - x[c + sxy]);
-  else
-    acc += (T)2 * bu * xc;
+  acc += (k < n.nz - 1) ? bu * (xc - xu) : (T)2 * bu * xc;
   return acc;
 }
 
@@ -128,10 +126,16 @@ __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ 
   const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
   const bool top = (k == n.nz - 1);
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  // wall neighbours are skipped, never read through a clamped index
-  const T num = h2 * b[c] + (i > 0 ? bw * e[c - 1] : (T)0) + (i < n.nx - 1 ? be * e[c + 1] : (T)0) +
-                (j > 0 ? bs * e[c - n.nx] : (T)0) + (j < n.ny - 1 ? bn * e[c + n.nx] : (T)0) +
-                (k > 0 ? bd * e[c - sxy] : (T)0) + (top ? (T)0 : bu * e[c + sxy]);
+  // every neighbour is loaded unconditionally (a wall neighbour through the
+  // cell's own index, so all loads are in flight together) and a wall term is
+  // then dropped by a select, never multiplied in: the cell's own entry may
+  // still be unset, and 0 * garbage need not be 0
+  const T ew = e[i > 0 ? c - 1 : c], ee = e[i < n.nx - 1 ? c + 1 : c];
+  const T es = e[j > 0 ? c - n.nx : c], en = e[j < n.ny - 1 ? c + n.nx : c];
+  const T ed = e[k > 0 ? c - sxy : c], eu = e[top ? c : c + sxy];
+  const T num = h2 * b[c] + (i > 0 ? bw * ew : (T)0) + (i < n.nx - 1 ? be * ee : (T)0) +
+                (j > 0 ? bs * es : (T)0) + (j < n.ny - 1 ? bn * en : (T)0) + (k > 0 ? bd * ed : (T)0) +
+                (top ? (T)0 : bu * eu);
   e[c] = num / diag;
 }
 
@@ -156,7 +160,7 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
   const T num = h2 * b[c] + bw * red(i > 0 ? c - 1 : c) + be * red(i < n.nx - 1 ? c + 1 : c) +
                 bs * red(j > 0 ? c - n.nx : c) + bn * red(j < n.ny - 1 ? c + n.nx : c) +
-                bd * red(k > 0 ? c - sxy : c) + (top ? (T)0 : bu * red(c + sxy));
+                bd * red(k > 0 ? c - sxy : c) + (top ? (T)0 : bu * red(top ? c : c + sxy));
   e[c] = num / diag;
 }
 
@@ -181,10 +185,14 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
   const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
   const bool top = (k == n.nz - 1);
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  // wall faces carry beta = 0: their (clamped) neighbour is never used
-  const T num = h2 * b[c] + (i > 0 ? bw * up(i - 1, j, k) : (T)0) + (i < n.nx - 1 ? be * up(i + 1, j, k) : (T)0) +
-                (j > 0 ? bs * up(i, j - 1, k) : (T)0) + (j < n.ny - 1 ? bn * up(i, j + 1, k) : (T)0) +
-                (k > 0 ? bd * up(i, j, k - 1) : (T)0) + (top ? (T)0 : bu * up(i, j, k + 1));
+  // neighbours loaded unconditionally through clamped indices, wall terms
+  // dropped by a select (as in k_gs)
+  const T uw = up(i > 0 ? i - 1 : i, j, k), ue = up(i < n.nx - 1 ? i + 1 : i, j, k);
+  const T us = up(i, j > 0 ? j - 1 : j, k), un = up(i, j < n.ny - 1 ? j + 1 : j, k);
+  const T ud = up(i, j, k > 0 ? k - 1 : k), uu = up(i, j, top ? k : k + 1);
+  const T num = h2 * b[c] + (i > 0 ? bw * uw : (T)0) + (i < n.nx - 1 ? be * ue : (T)0) +
+                (j > 0 ? bs * us : (T)0) + (j < n.ny - 1 ? bn * un : (T)0) + (k > 0 ? bd * ud : (T)0) +
+                (top ? (T)0 : bu * uu);
   e[c] = num / diag;
 }
 
@@ -321,16 +329,21 @@ __device__ __forceinline__ void tail_pass(const Dims& n, const TailPairs& tp, T 
       const int c = i + n.nx * j + sxy * k;
       T num = h2 * b[c];
       if (!from_zero) {
-        // wall faces are skipped outright: a cell's own entry may still be
-        // unset after a red pass from zero, and 0 * garbage need not be 0
+        // all loads unconditional (walls through the cell's own index), wall
+        // terms dropped by a select: a cell's own entry may still be unset
+        // after a red pass from zero, and 0 * garbage need not be 0
         const int fx = i + (n.nx + 1) * (j + n.ny * k);
         const int fy = i + n.nx * (j + (n.ny + 1) * k);
-        if (i > 0) num += bx[fx] * e[c - 1];
-        if (i < n.nx - 1) num += bx[fx + 1] * e[c + 1];
-        if (j > 0) num += by[fy] * e[c - n.nx];
-        if (j < n.ny - 1) num += by[fy + n.nx] * e[c + n.nx];
-        if (k > 0) num += bz[c] * e[c - sxy];
-        if (k < n.nz - 1) num += bz[c + sxy] * e[c + sxy];
+        const bool w = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, d = k > 0, u = k < n.nz - 1;
+        const T tw = bx[fx] * e[w ? c - 1 : c], te = bx[fx + 1] * e[E ? c + 1 : c];
+        const T ts = by[fy] * e[S ? c - n.nx : c], tn = by[fy + n.nx] * e[N ? c + n.nx : c];
+        const T td = bz[c] * e[d ? c - sxy : c], tu = bz[c + sxy] * e[u ? c + sxy : c];
+        if (w) num += tw;
+        if (E) num += te;
+        if (S) num += ts;
+        if (N) num += tn;
+        if (d) num += td;
+        if (u) num += tu;
       }
       e[c] = num * invd[c];
     }
@@ -396,13 +409,18 @@ struct TailLevel {
             const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
             const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
             const T xc = e[c];
+            const bool w = i > 0, E = i < nf.nx - 1, S = j > 0, N = j < nf.ny - 1, d = k > 0, u = k < nf.nz - 1;
+            const T tw = bx[ix] * (xc - e[w ? c - 1 : c]), te = bx[ix + 1] * (xc - e[E ? c + 1 : c]);
+            const T ts = by[iy] * (xc - e[S ? c - nf.nx : c]), tn = by[iy + nf.nx] * (xc - e[N ? c + nf.nx : c]);
+            const T td = bz[c] * (xc - e[d ? c - sxy : c]);
+            const T tu = u ? bz[c + sxy] * (xc - e[u ? c + sxy : c]) : (T)2 * bz[c + sxy] * xc;
             T acc = 0;
-            if (i > 0) acc += bx[ix] * (xc - e[c - 1]);
-            if (i < nf.nx - 1) acc += bx[ix + 1] * (xc - e[c + 1]);
-            if (j > 0) acc += by[iy] * (xc - e[c - nf.nx]);
-            if (j < nf.ny - 1) acc += by[iy + nf.nx] * (xc - e[c + nf.nx]);
-            if (k > 0) acc += bz[c] * (xc - e[c - sxy]);
-            acc += (k < nf.nz - 1) ? bz[c + sxy] * (xc - e[c + sxy]) : (T)2 * bz[c + sxy] * xc;
+            if (w) acc += tw;
+            if (E) acc += te;
+            if (S) acc += ts;
+            if (N) acc += tn;
+            if (d) acc += td;
+            acc += tu;
             sum += b[c] - ih2 * acc;
           }
       bc[C] = sum * inv;
@@ -412,6 +430,11 @@ struct TailLevel {
 
   // coarsest level: sweeps forward (red, black) then backward (black, red) from zero
   __device__ void coarsest(int l) const {
+    const Dims n = D.n[l];
+    if (n.nx <= 2 && n.ny == 1 && n.nz == 1) {
+      coarsest_row(l);
+      return;
+    }
     if (D.coarse_sweeps > 0) {
       TailPairs tp;
       tail_decode(D.n[l], tid, nthr, tp);
@@ -420,6 +443,41 @@ struct TailLevel {
     } else {
       zero(l);
     }
+  }
+
+  // A coarsest level of one or two cells in a row: the same sweeps, with the
+  // same arithmetic, done by one thread in registers.  Cell 0 is red, cell 1
+  // black; the face between them is bx[1]; there is no other neighbour.
+  __device__ void coarsest_row(int l) const {
+    if (tid == 0) {
+      const bool two = D.n[l].nx == 2;
+      const T h2 = D.h2[l];
+      const T *b = sm + D.ob[l], *invd = sm + D.oid[l], *bx = sm + D.obx[l];
+      T* e = sm + D.oe[l];
+      const T r0 = h2 * b[0], i0 = invd[0];
+      const T r1 = two ? h2 * b[1] : (T)0, i1 = two ? invd[1] : (T)0, w = two ? bx[1] : (T)0;
+      T e0 = 0, e1 = 0;
+      const int S = D.coarse_sweeps;
+      for (int s = 0; s < S; ++s) {   // forward: red (from zero first), black
+        T num = r0;
+        if (two && s > 0) num += w * e1;
+        e0 = num * i0;
+        num = r1;
+        num += w * e0;
+        e1 = num * i1;
+      }
+      for (int s = 0; s < S; ++s) {   // backward: black, red
+        T num = r1;
+        num += w * e0;
+        e1 = num * i1;
+        num = r0;
+        if (two) num += w * e1;
+        e0 = num * i0;
+      }
+      e[0] = e0;
+      if (two) e[1] = e1;
+    }
+    tail_sync<WAVE>();
   }
 
   // prolongation of the next level's correction, then post-smoothing
@@ -446,42 +504,23 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailDesc<T> D) {
   T* sm = reinterpret_cast<T*>(tail_smem);
   const int nl = D.nl;
   const int tid = threadIdx.x;
-  // stage every coefficient array and the first right-hand side: one flat
-  // loop over all segments with eight independent loads in flight per thread
+  // stage the pack (every coefficient array and 1/D) and the first
+  // right-hand side: one flat loop, sixteen independent loads in flight per
+  // thread
   {
-    const int total = D.seg_start[D.nseg];
-    for (int base = tid; base < total; base += 8 * kTailThreads) {
-      T v[8];
-      int dst[8];
+    const int np = D.npack, n0 = D.n[0].nx * D.n[0].ny * D.n[0].nz, total = np + n0;
+    for (int base = tid; base < total; base += 16 * kTailThreads) {
+      T v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int q = base + u * kTailThreads;
-        dst[u] = -1;
-        if (q < total) {
-          int sg = 0;
-          while (q >= D.seg_start[sg + 1]) ++sg;
-          const int o = q - D.seg_start[sg];
-          v[u] = D.seg_src[sg][o];
-          dst[u] = D.seg_dst[sg] + o;
-        }
+        v[u] = q < np ? D.pack[q] : (q < total ? D.b0[q - np] : (T)0);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (dst[u] >= 0) sm[dst[u]] = v[u];
-    }
-  }
-  __syncthreads();
-  for (int l = 0; l < nl; ++l) {
-    const Dims n = D.n[l];
-    const int N = n.nx * n.ny * n.nz, sxy = n.nx * n.ny;
-    const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l];
-    T* invd = sm + D.oid[l];
-    for (int c = tid; c < N; c += kTailThreads) {
-      const int i = c % n.nx, j = (c / n.nx) % n.ny, k = c / sxy;
-      const int fx = i + (n.nx + 1) * (j + n.ny * k);
-      const int fy = i + n.nx * (j + (n.ny + 1) * k);
-      const T bu = bz[c + sxy];
-      invd[c] = (T)1 / (bx[fx] + bx[fx + 1] + by[fy] + by[fy + n.nx] + bz[c] + (k == n.nz - 1 ? (T)2 * bu : bu));
+      for (int u = 0; u < 16; ++u) {
+        const int q = base + u * kTailThreads;
+        if (q < total) sm[q < np ? q : D.ob[0] + (q - np)] = v[u];
+      }
     }
   }
   __syncthreads();
