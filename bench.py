@@ -13,8 +13,16 @@ when the timed region starts.
 
 Printed: ONE JSON line with
   value        Mcell-steps/s over the K timed steps (cells x K / seconds)
-  projection   projection wall time and CG iterations, FP64 V-cycle vs FP32
-               V-cycle inside FP64 CG, both to the same 1e-10 residual
+  projection   projection wall time and CG iterations on the same workload,
+               FP64 V-cycle vs FP32 V-cycle inside FP64 CG, both to the same
+               1e-10 residual
+  projection_study  the same on the 256x128x128 tanks (JONSWAP waves, and a
+               held-out draw of the learned guess's Airy-wave training runs)
+               for the FP64 V-cycle (zero and previous-pressure guesses) and
+               the FP32 V-cycle (previous-pressure and learned guesses,
+               inference included), the per-field difference of the
+               FP32-V-cycle step from the FP64 one, and the network forward's
+               BF16 rate
   roofline     the finest-level smoother pass (the dominant kernel): its
                algorithmic bytes per launch over its average duration, the
                duration taken from HIP events recorded with each dispatch
@@ -148,6 +156,107 @@ def run_gpu(args):
             "projection": proj, "config": config, "wl": wl, "f0": f0, "dt": dt}
 
 
+# FLOPs of one inference of the learned-guess network per voxel of the full
+# grid: 2 * 27 * C_in * C_out per output voxel and layer (first layer with its
+# 4 real input channels; levels 2 and 3 hold 1/8 and 1/64 of the voxels), plus
+# the 1x1x1 head.
+NET_FLOP_PER_VOXEL = (2 * 27 * 4 * 16 + 2 * 27 * 48 * 16 + 2 * 16) + (2 * 27 * 16 * 32 + 2 * 27 * 96 * 32) / 8 + \
+    (2 * 27 * 32 * 64) / 64
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak, published
+
+
+def projection_study(name: str, steps: int, warmup: int, weights: str):
+    """Projection wall time and CG iterations to the same 1e-10 true residual
+    on one workload for: FP64 V-cycle from zero and from the previous
+    pressure, FP32 V-cycle from the previous pressure, and FP32 V-cycle from
+    the learned guess (network inference included in the time).  Also the
+    per-field difference of the FP32-V-cycle step from the FP64 one, both
+    taken from the same state, and the network forward's matrix-core rate."""
+    import numpy as np
+    import torch
+
+    from paper_2206_07732_amd import inputs as I
+    from paper_2206_07732_amd import ns
+
+    wl = I.workload(name)
+    f0 = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f0)
+    net = None
+    if weights and os.path.exists(weights):
+        net = ns.Net(wl.nx, wl.ny, wl.nz)
+        net.set_params(np.load(weights, allow_pickle=False))
+    out = {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "steps_timed": steps, "rtol": 1e-10,
+           "weights": os.path.relpath(weights, ROOT) if net is not None else None}
+    variants = [("fp64", "zero"), ("fp64", "prev"), ("mixed", "prev")]
+    if net is not None:
+        variants.append(("mixed", "learned"))
+    for prec, x0 in variants:
+        dev = ns.device_fields(f0)
+        S = ns.Solver(ns.params(wl, prec=ns.PREC_FP64 if prec == "fp64" else ns.PREC_MIXED,
+                                x0={"zero": ns.X0_ZERO, "prev": ns.X0_PREV, "learned": ns.X0_LEARNED}[x0]), dev)
+        if x0 == "learned":
+            S.attach_net(net)
+        t = 0.0
+        for _ in range(warmup):
+            S.step(dt, t)
+            t += dt
+        ms, its, r0, res = [], [], [], []
+        for _ in range(steps):
+            S.levelset_advect_reinit(dt)
+            S.momentum_step(dt, t + dt)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = S.projection_solve(dt)
+            ms.append(1e3 * (time.perf_counter() - a))
+            its.append(st["iters"])
+            r0.append(st["rel_resid0"])
+            res.append(st["true_rel_resid"])
+            t += dt
+        out[f"{prec}+{x0}"] = {"ms_median": round(statistics.median(ms), 4), "iters": its,
+                               "mean_rel_resid0": float(np.mean(r0)), "max_true_rel_resid": max(res)}
+        log(f"[bench] {wl.name[:3]} projection {prec}+{x0}: {statistics.median(ms):.3f} ms, iters {its}")
+        S.close()
+    base = out["fp64+prev"]["ms_median"]
+    for k in ("mixed+prev", "mixed+learned"):
+        if k in out:
+            out[k]["speedup_vs_fp64_prev"] = round(base / out[k]["ms_median"], 3)
+    # per-field difference of one step with the FP32 V-cycle from the FP64 one
+    fields = {}
+    for prec in (ns.PREC_FP64, ns.PREC_MIXED):
+        dev = ns.device_fields(f0)
+        S = ns.Solver(ns.params(wl, prec=prec), dev)
+        S.step(dt, 0.0)
+        torch.cuda.synchronize()
+        fields[prec] = {k: v.clone() for k, v in dev.items()}
+        S.close()
+    err = {}
+    for k in ("p", "u", "v", "w", "sigma"):
+        a, b = fields[ns.PREC_MIXED][k], fields[ns.PREC_FP64][k]
+        nrm = float(torch.linalg.vector_norm(b))
+        err[k] = {"rel_l2": float(torch.linalg.vector_norm(a - b)) / nrm if nrm > 0 else 0.0,
+                  "max_abs": float((a - b).abs().max())}
+    out["mixed_vs_fp64_one_step"] = err
+    if net is not None:
+        feat = torch.randn((4, wl.nz, wl.ny, wl.nx), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            net.forward(feat)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        with torch.cuda.stream(net.stream):
+            e0.record()
+            for _ in range(reps):
+                net.forward(feat)
+            e1.record()
+        torch.cuda.synchronize()
+        fwd_ms = e0.elapsed_time(e1) / reps
+        tflops = NET_FLOP_PER_VOXEL * wl.ncells / (fwd_ms * 1e-3) / 1e12
+        out["net_forward"] = {"ms": round(fwd_ms, 4), "flop_per_voxel": NET_FLOP_PER_VOXEL,
+                              "achieved_tflops": round(tflops, 1), "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                              "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4)}
+        log(f"[bench] network forward {fwd_ms:.3f} ms ({tflops:.0f} TFLOP/s BF16)")
+    return out
+
+
 def run_cpu_baseline(wl, f0, dt, seconds: float):
     """The oracle as it stands, single-threaded, for about `seconds`."""
     from oracle import oracle as O
@@ -175,6 +284,11 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--projection-workload", default="c3,c4eval",
+                    help="comma-separated workloads of the projection study (FP64 vs FP32 V-cycle vs learned "
+                         "guess); 'none' skips it")
+    ap.add_argument("--projection-steps", type=int, default=8)
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2206_07732_amd", "weights", "guess_c4.npy"))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -193,6 +307,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 x {args.copy_calibration_mib} MiB device copies")
+    study = None
+    if args.projection_workload != "none":
+        study = [projection_study(w, args.projection_steps, 2, args.weights)
+                 for w in args.projection_workload.split(",")]
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(r["wl"], r["f0"], r["dt"], args.cpu_seconds)
@@ -213,6 +331,7 @@ def main():
         "config": r["config"],
         "cg_iters": r["iters"],
         "projection": r["projection"],
+        "projection_study": study,
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }

@@ -156,6 +156,18 @@ def _cyl(xc=2.0, yc=1.0, **kw) -> Body:
     return Body(1, (xc, yc, 0.0), (0.25, 0.7, 1.5), **kw)
 
 
+def harvest_draw(seed: int):
+    """Wave and buoy of one seeded learned-guess run: amplitude U[0.01, 0.08] m,
+    period U[0.8, 2] s, buoy centre (x, y) in U([1.5, 2.5] x [0.75, 1.25]) m,
+    phase U[0, 2 pi).  Returns (a, T, phase, x, y)."""
+    rng = np.random.default_rng(1000 + seed)
+    a = float(rng.uniform(0.01, 0.08))
+    T = float(rng.uniform(0.8, 2.0))
+    bx, by = float(rng.uniform(1.5, 2.5)), float(rng.uniform(0.75, 1.25))
+    phase = float(rng.uniform(0, 2 * math.pi))
+    return a, T, phase, bx, by
+
+
 def workload(name: str, **over) -> Workload:
     """Named synthetic tanks.  'c1'..'c5' are the five measured configurations;
     'tiny2d'/'tiny3d' are small variants for quick parity tests."""
@@ -176,6 +188,11 @@ def workload(name: str, **over) -> Workload:
         wl = Workload("c4-train: 3-D tank 128x64x64, seeded Airy wave and buoy position",
                       128, 64, 64, 4.0 / 128, 1.0, {"kind": "airy", "a": 0.04, "T": 1.2, "phase": 0.0},
                       [_cyl()], steps=50, seed=4)
+    elif name == "c4eval":
+        a, T, phase, bx, by = harvest_draw(40)
+        wl = Workload("c4-eval: 3-D tank 256x128x128 (h=1/64), held-out seeded Airy wave and buoy (draw 40)",
+                      256, 128, 128, 4.0 / 256, 1.0, {"kind": "airy", "a": a, "T": T, "phase": phase},
+                      [_cyl(bx, by)], steps=20, seed=40)
     elif name == "c5":
         wl = Workload("c5: 3-D tank 512x256x256 (4x2x2 m, h=1/128), JONSWAP Hs=0.2 m Tp=2 s, two heaving cylinders",
                       512, 256, 256, 4.0 / 512, 1.0, {"kind": "jonswap", "hs": 0.2, "tp": 2.0, "n": 64},

@@ -54,12 +54,9 @@ LAYERS = [(4, 16, 3), (16, 32, 3), (32, 64, 3), (96, 32, 3), (48, 16, 3), (16, 1
 
 def run_workload(seed: int, nx=128, ny=64, nz=64):
     """One seeded harvest tank."""
-    rng = np.random.default_rng(1000 + seed)
-    a = float(rng.uniform(0.01, 0.08))
-    T = float(rng.uniform(0.8, 2.0))
-    bx, by = float(rng.uniform(1.5, 2.5)), float(rng.uniform(0.75, 1.25))
+    a, T, phase, bx, by = I.harvest_draw(seed)
     wl = I.workload("c4train", nx=nx, ny=ny, nz=nz, h=4.0 / nx, seed=seed,
-                    wave={"kind": "airy", "a": a, "T": T, "phase": float(rng.uniform(0, 2 * math.pi))},
+                    wave={"kind": "airy", "a": a, "T": T, "phase": phase},
                     bodies=[I.Body(1, (bx, by, 0.0), (0.25, 0.7, 1.5))])
     return wl
 
