@@ -1,0 +1,146 @@
+"""Full-size checks at the largest tank, 512x256x256 (33.5 M cells), where the
+oracle cannot run whole: one FP64 step through the C ABI is checked
+
+  * stage by stage on sampled windows: the oracle runs the level-set,
+    property, momentum and face-coefficient stages on a window of the same
+    inputs (body coordinates shifted to the window's origin), and every value
+    at least MARGIN cells inside the window's artificial edges, where the
+    window's own boundary treatment cannot reach, must agree to the stage
+    tolerances of the whole-grid parity tests;
+  * for the projection, which is global, by properties that hold at any
+    size: the true residual meets the 1e-10 bar, and the corrected velocity's
+    discrete divergence obeys div u = -dt (b - A p), so
+    max|div u| <= dt * ||b - A p||_2 <= dt * 1e-10 * sqrt(N) * max|b|;
+  * and the FP32-V-cycle step against the FP64 one from the same state.
+"""
+import numpy as np
+import pytest
+
+from paper_2206_07732_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HALF = 12     # window half-width (cells)
+MARGIN = 8    # stencil reach of advection + 5 reinitialisation sweeps is 7
+
+
+def _ns():
+    from paper_2206_07732_amd import ns
+    return ns
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / (nb if nb > 0 else 1.0))
+
+
+def window(n, c):
+    """[lo, hi) of a window around c, clipped to [0, n), and the [lo, hi) of
+    its trusted core: cells at least MARGIN from an edge inside the grid."""
+    lo, hi = max(0, c - HALF), min(n, c + HALF + 1)
+    return (lo, hi), (lo if lo == 0 else lo + MARGIN, hi if hi == n else hi - MARGIN)
+
+
+def sub(a, w, face_axis=None):
+    """a[z, y, x] restricted to window w = ((x0, x1), (y0, y1), (z0, z1)); along
+    face_axis (0 x, 1 y, 2 z) the faces of the window's cells (one more)."""
+    (x0, x1), (y0, y1), (z0, z1) = w
+    return np.ascontiguousarray(a[z0:z1 + (face_axis == 2), y0:y1 + (face_axis == 1), x0:x1 + (face_axis == 0)])
+
+
+def core(a, w, cw, face_axis=None):
+    """The core of a window array (window-local indices)."""
+    (x0, _), (y0, _), (z0, _) = w
+    (cx0, cx1), (cy0, cy1), (cz0, cz1) = cw
+    fx, fy, fz = face_axis == 0, face_axis == 1, face_axis == 2
+    # a face is trusted when both of its cells are (interior faces of the core)
+    return a[cz0 - z0 + fz:cz1 - z0, cy0 - y0 + fy:cy1 - y0, cx0 - x0 + fx:cx1 - x0]
+
+
+def window_workload(wl, w):
+    (x0, x1), (y0, y1), (z0, z1) = w
+    h = wl.h
+    bodies = []
+    for b in wl.bodies:   # cylinders: c = (xc, yc, -), half = (R, z_bot, z_top)
+        bodies.append(I.Body(b.kind, (b.c[0] - x0 * h, b.c[1] - y0 * h, 0.0),
+                             (b.half[0], b.half[1] - z0 * h, b.half[2] - z0 * h),
+                             b.heave_amp, b.heave_omega, b.heave_phase))
+    return I.workload(wl.name.split(":")[0], nx=x1 - x0, ny=y1 - y0, nz=z1 - z0, h=h, bodies=bodies)
+
+
+def sample_centres(wl, seed=5):
+    """Three windows: on the free surface, on the first buoy's waterline, and
+    one drawn at random."""
+    rng = np.random.default_rng(seed)
+    kd = int(wl.depth / wl.h)
+    b = wl.bodies[0]
+    return [(int(rng.integers(HALF, wl.nx - HALF)), int(rng.integers(HALF, wl.ny - HALF)), kd),
+            (int(b.c[0] / wl.h) + int(b.half[0] / wl.h), int(b.c[1] / wl.h), kd),
+            (int(rng.integers(0, wl.nx)), int(rng.integers(0, wl.ny)), int(rng.integers(0, wl.nz)))]
+
+
+def test_c5_one_step_windows_and_properties(orc):
+    ns = _ns()
+    wl = I.workload("c5")
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    t1 = dt
+    print(f"[fullsize] {wl.nx}x{wl.ny}x{wl.nz} dt={dt:.5f}", flush=True)
+    dev = ns.device_fields(f)
+    S = ns.Solver(ns.params(wl), dev)
+    S.levelset_advect_reinit(dt)
+    torch.cuda.synchronize()
+    sig1 = dev["sigma"].cpu().numpy()
+    S.momentum_step(dt, t1)
+    torch.cuda.synchronize()
+    gpu = {k: S.buffer(k).cpu().numpy() for k in ("us", "vs", "ws", "rho", "rho_flow", "mu", "chi", "bx", "by", "bz")}
+    print("[fullsize] stages done, checking windows", flush=True)
+    for (ci, cj, ck) in sample_centres(wl):
+        wx, cx = window(wl.nx, ci)
+        wy, cy = window(wl.ny, cj)
+        wz, cz = window(wl.nz, ck)
+        w, cw = (wx, wy, wz), (cx, cy, cz)
+        Pw = orc.params(window_workload(wl, w))
+        s_o = orc.reinit(Pw, orc.levelset_advect(Pw, sub(f["sigma"], w), sub(f["u"], w, 0), sub(f["v"], w, 1),
+                                                 sub(f["w"], w, 2), dt))
+        r = rel(core(sub(sig1, w), w, cw), core(s_o, w, cw))
+        print(f"[fullsize] window at {(ci, cj, ck)} sigma rel={r:.2e}", flush=True)
+        assert r < 1e-13
+        # properties, momentum and beta from the GPU's sigma^{n+1} on both sides
+        sg = sub(sig1, w)
+        props = dict(zip(("rho", "rho_flow", "mu", "chi"), orc.properties(Pw, sg, t1)))
+        for k, ref in props.items():
+            a, b = core(sub(gpu[k], w), w, cw), core(ref, w, cw)
+            assert (rel(a, b) < 1e-14) if np.linalg.norm(b) > 0 else np.max(np.abs(a)) < 1e-14, k
+        mom = orc.momentum(Pw, sub(f["u"], w, 0), sub(f["v"], w, 1), sub(f["w"], w, 2), sg, t1, dt)
+        for ax, (k, ref) in enumerate(zip(("us", "vs", "ws"), mom)):
+            a, b = core(sub(gpu[k], w, ax), w, cw, ax), core(ref, w, cw, ax)
+            assert (rel(a, b) < 1e-13) if np.linalg.norm(b) > 0 else np.max(np.abs(a)) == 0.0, k
+        beta = orc.face_beta(Pw, sg, t1, dt)
+        for ax, (k, ref) in enumerate(zip(("bx", "by", "bz"), beta)):
+            a, b = core(sub(gpu[k], w, ax), w, cw, ax), core(ref, w, cw, ax)
+            assert rel(a, b) < 1e-14, k
+    # projection: global, checked by properties
+    st = S.projection_solve(dt)
+    torch.cuda.synchronize()
+    print(f"[fullsize] projection iters={st['iters']} true_rel_resid={st['true_rel_resid']:.2e}", flush=True)
+    assert st["converged"] == 1 and st["true_rel_resid"] <= 1e-10
+    bmax = float(S.buffer("rhs").abs().max())
+    div = S.diagnostics()[0]
+    bound = dt * 1e-10 * np.sqrt(wl.ncells) * bmax
+    print(f"[fullsize] max|div u| = {div:.3e} (bound {bound:.3e}, dt max|b| = {dt * bmax:.3e})", flush=True)
+    assert div <= bound
+    p64 = {k: v.clone() for k, v in dev.items()}
+    S.close()
+    # the FP32 V-cycle inside FP64 CG, one step from the same state
+    dev32 = ns.device_fields(f)
+    S32 = ns.Solver(ns.params(wl, prec=ns.PREC_MIXED), dev32)
+    st32 = S32.step(dt, 0.0)
+    torch.cuda.synchronize()
+    assert st32["converged"] == 1 and st32["true_rel_resid"] <= 1e-10
+    for k in ("p", "u", "v", "w"):
+        d = float(torch.linalg.vector_norm(dev32[k] - p64[k]) / torch.linalg.vector_norm(p64[k]))
+        print(f"[fullsize] mixed vs fp64 {k}: rel {d:.2e}", flush=True)
+        assert d < 1e-8, k
+    S32.close()

@@ -47,7 +47,7 @@ def case(name):
     return I.workload(name)
 
 
-STAGE_CASES = ["tiny2d", "tiny3d", "ragged3d", "heave3d", "c1", "c2"]
+STAGE_CASES = ["tiny2d", "tiny3d", "ragged3d", "heave3d", "c1", "c2", "c3"]
 
 
 def make_solver(wl, fields, **opts):
