@@ -227,6 +227,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     const size_t fu = (size_t)(V.n.nx + 1) * V.n.ny * V.n.nz;
     const size_t fv = (size_t)V.n.nx * (V.n.ny + 1) * V.n.nz;
     const size_t fw = (size_t)V.n.nx * V.n.ny * (V.n.nz + 1);
+    const size_t c2 = 2 * (size_t)((V.n.nx + 1) / 2) * V.n.ny * V.n.nz;   // colour-split size
     if (l >= t32) {
       V.bxf = from32(fu);
       V.byf = from32(fv);
@@ -236,7 +237,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       V.bxf = cv.take<float>(fu);
       V.byf = cv.take<float>(fv);
       V.bzf = cv.take<float>(fw);
-      V.invdf = cv.take<float>(c);
+      V.invdf = cv.take<float>(c2);
     }
     if (l >= t64) {
       V.bx = from64(fu);
@@ -247,15 +248,24 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       V.bx = cv.take<double>(fu);
       V.by = cv.take<double>(fv);
       V.bz = cv.take<double>(fw);
-      V.invd = cv.take<double>(c);
+      V.invd = cv.take<double>(c2);
     }
-    V.bf = cv.take<float>(c);
-    V.ef = cv.take<float>(c);
+    // b and e: colour-split (2 ceil(nx/2) ny nz entries) above the tail,
+    // natural on tail levels; level 0 keeps its own split pair (its natural
+    // b and e are the CG vectors, and for FP32 the bfn/efn interface)
+    const size_t cs = 2 * (size_t)((V.n.nx + 1) / 2) * V.n.ny * V.n.nz;
+    V.bf = cv.take<float>(l < t32 ? cs : c);
+    V.ef = cv.take<float>(l < t32 ? cs : c);
+    V.bfn = V.efn = nullptr;
     if (l == 0) {
-      V.b = V.e = nullptr;   // level 0's b and e are CG vectors
+      V.bfn = t32 > 0 ? cv.take<float>(c) : V.bf;
+      V.efn = t32 > 0 ? cv.take<float>(c) : V.ef;
+    }
+    if (l == 0 && t64 == 0) {
+      V.b = V.e = nullptr;   // a tail-only hierarchy works on the CG vectors directly
     } else {
-      V.b = cv.take<double>(c);
-      V.e = cv.take<double>(c);
+      V.b = cv.take<double>(l < t64 ? cs : c);
+      V.e = cv.take<double>(l < t64 ? cs : c);
     }
   }
   if (X) {
@@ -362,7 +372,7 @@ void build_hierarchy(ns_ctx* X) {
   }
   for (int l = 0; l < X->L; ++l) {
     const Level& V = X->lev[l];
-    launch_invdiag<T>(V, LV<T>::bx(V), LV<T>::by(V), LV<T>::bz(V), LV<T>::invd(V), X->st);
+    launch_invdiag<T>(V, LV<T>::bx(V), LV<T>::by(V), LV<T>::bz(V), LV<T>::invd(V), l < tail_start<T>(X), X->st);
   }
 }
 
@@ -403,43 +413,51 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
   launch_vcycle_tail<T>(D, bytes, X->st);
 }
 
-// e_l = V(l, b_l); level 0 uses the given b0, e0
+// e_l = V(l, b_l); level 0 takes b0 and returns e0 in natural order.  Levels
+// above the tail work on colour-split b and e; the first sweep of level 0
+// reads b0 in natural order and writes its split copy, and the last red pass
+// of level 0 writes e0 in natural order.
 template <typename T>
 void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   const ns_params& P = X->P;
   const Level& L = X->lev[l];
-  const T* b = (l == 0) ? b0 : LV<T>::b(L);
-  T* e = (l == 0) ? e0 : LV<T>::e(L);
-  const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
   hipStream_t st = X->st;
   if (l == tail_start<T>(X)) {
-    launch_tail<T>(X, l, b, e, tail_bytes<T>(X));
+    launch_tail<T>(X, l, l == 0 ? b0 : LV<T>::b(L), l == 0 ? e0 : LV<T>::e(L), tail_bytes<T>(X));
     return;
   }
+  T* b = LV<T>::b(L);   // split
+  T* e = LV<T>::e(L);   // split
+  const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
   KTimer* kt = (l == 0 && X->timed_kernel == NS_TIME_SMOOTH0) ? &X->kt : nullptr;
+  const size_t nsplit = 2 * (size_t)((L.n.nx + 1) / 2) * L.n.ny * L.n.nz;
   // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
-    launch_gs_first<T>(L, bx, by, bz, b, LV<T>::invd(L), e, st);
+    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st);
     for (int s = 1; s < P.nu_pre; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
     }
   } else {
-    launch_fill<T>(e, (size_t)L.n.nx * L.n.ny * L.n.nz, st);
+    if (l == 0) launch_split_copy<T>(L, b0, b, true, st);
+    launch_fill<T>(e, nsplit, st);
   }
   const Level& C = X->lev[l + 1];
-  launch_resid_restrict<T>(L, bx, by, bz, b, e, C, LV<T>::b(C), st);
+  const bool csplit = (l + 1) < tail_start<T>(X);
+  launch_resid_restrict<T>(L, bx, by, bz, b, e, C, LV<T>::b(C), csplit, st);
   vcycle<T>(X, l + 1, nullptr, nullptr);
-  // post-smoothing: (prolongation + black) fused, then red, then black, red pairs
+  // post-smoothing: (prolongation + black) fused, then red, then black, red
+  // pairs; at level 0 the last red pass writes e0
   if (P.nu_post > 0) {
-    launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), st);
-    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+    launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), csplit, st);
+    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, (l == 0 && P.nu_post == 1) ? e0 : nullptr);
     for (int s = 1; s < P.nu_post; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
-      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, (l == 0 && s == P.nu_post - 1) ? e0 : nullptr);
     }
   } else {
-    launch_prolong<T>(L, e, C, LV<T>::e(C), st);
+    launch_prolong<T>(L, e, C, LV<T>::e(C), csplit, st);
+    if (l == 0) launch_split_copy<T>(L, e, e0, false, st);
   }
 }
 
@@ -449,9 +467,9 @@ void precond(ns_ctx* X, const double* r, double* z) {
     vcycle<double>(X, 0, r, z);
   } else {
     Level& L0 = X->lev[0];
-    launch_d2f(r, L0.bf, X->nc, X->st);
-    vcycle<float>(X, 0, L0.bf, L0.ef);
-    launch_f2d(L0.ef, z, X->nc, X->st);
+    launch_d2f(r, L0.bfn, X->nc, X->st);
+    vcycle<float>(X, 0, L0.bfn, L0.efn);
+    launch_f2d(L0.efn, z, X->nc, X->st);
   }
 }
 
@@ -701,6 +719,8 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
   if (kernel != NS_TIME_SMOOTH0 && kernel != NS_TIME_SPMV)
     return fail(X, NS_EINVAL, "unknown timed kernel %d", kernel);
   if (!X->have_beta) return fail(X, NS_ESTATE, "no coefficients yet: call momentum_step first");
+  if (kernel == NS_TIME_SMOOTH0 && (X->P.prec == NS_PREC_FP64 ? X->tail64 : X->tail32) == 0)
+    return fail(X, NS_EINVAL, "the whole hierarchy runs in the coarse-level tail: no finest smoother pass");
   hipEvent_t a, b;
   HIPCHK(X, hipEventCreate(&a));
   if (hipEventCreate(&b) != hipSuccess) {
@@ -714,10 +734,10 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
   (void)hipEventRecord(a, X->st);
   for (int q = 0; q < reps; ++q) {
     if (kernel == NS_TIME_SMOOTH0) {
-      // the finest smoother pass of the configured precision, on scratch
-      // vectors that are dead between steps (r read as b, zn or ef written)
+      // the finest smoother pass of the configured precision, on the
+      // level's colour-split b and e, which are dead between V-cycles
       if (X->P.prec == NS_PREC_FP64)
-        launch_gs<double>(L0, L0.bx, L0.by, L0.bz, X->r, X->zn, q & 1, X->st);
+        launch_gs<double>(L0, L0.bx, L0.by, L0.bz, L0.b, L0.e, q & 1, X->st);
       else
         launch_gs<float>(L0, L0.bxf, L0.byf, L0.bzf, L0.bf, L0.ef, q & 1, X->st);
     } else {

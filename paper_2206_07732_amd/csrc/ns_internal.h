@@ -43,8 +43,9 @@ struct Level {
   int f[3];                     // coarsening factor towards level + 1
   double *bx, *by, *bz;         // FP64 face coefficients (walls = 0)
   float *bxf, *byf, *bzf;       // FP32 copies
-  double *b, *e;                // FP64 right-hand side and correction
+  double *b, *e;                // FP64 right-hand side and correction (split above the tail)
   float *bf, *ef;               // FP32
+  float *bfn, *efn;             // level 0, FP32: natural-order b and e of the mixed V-cycle
   double* invd;                 // 1 / diagonal (h^2 scaled), FP64
   float* invdf;                 // FP32
 };
@@ -123,22 +124,31 @@ void launch_diag_finalize(const double* partials, int nparts, double* scal, hipS
 int diag_blocks(const Phys& P);
 
 // multigrid and CG kernels (ns_mg.hip)
+// Multigrid kernels.  On levels above the tail b, e and 1/D are colour-split
+// (cell (i,j,k) at ((i+j+k)&1) P + (i>>1) + ceil(nx/2) (j + ny k)); tail
+// levels keep the natural layout.
+// one colour pass (nat: also write the pair, both colours, to nat in natural order)
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
-               hipStream_t st, KTimer* kt = nullptr);
+               hipStream_t st, KTimer* kt = nullptr, T* nat = nullptr);
+// red from zero + black; b natural (b_natural, its split copy written to bs) or split
 template <typename T>
-void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, const T* invd,
-                     T* e, hipStream_t st);
+void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, bool b_natural,
+                     const T* invd, T* e, T* bs, hipStream_t st);
+// prolongation of the next level's correction ec (split or natural) + black
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
-                       const Level& C, const T* ec, hipStream_t st);
+                       const Level& C, const T* ec, bool ec_split, hipStream_t st);
+// coarse b = restricted residual (coarse layout split or natural)
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
-                           const T* e, const Level& C, T* bc, hipStream_t st);
+                           const T* e, const Level& C, T* bc, bool c_split, hipStream_t st);
 template <typename T>
-void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, hipStream_t st);
+void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, bool ec_split, hipStream_t st);
 template <typename T>
-void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, hipStream_t st);
+void launch_split_copy(const Level& L, const T* src, T* dst, bool to_split, hipStream_t st);
+template <typename T>
+void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, bool split, hipStream_t st);
 template <typename T>
 void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C,
                          T* cbx, T* cby, T* cbz, hipStream_t st);

@@ -102,141 +102,246 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* __restri
 }
 
 // --------------------------------------------------------------- smoothers
+// Levels above the coarse-level tail keep b, e and 1/D colour-split: cell
+// (i, j, k) of colour c = (i + j + k) & 1 lives at c P + p with the pair index
+// p = (i >> 1) + hx (j + ny k), hx = ceil(nx / 2), P = hx ny nz.  A colour pass
+// then reads and writes only its own colour's entries (and the other
+// colour's as neighbours), instead of whole lines of both.  The face
+// coefficients stay in their natural layout.
+struct SplitGeo {
+  int hx;
+  size_t P;
+};
+__host__ __device__ inline SplitGeo split_geo(const Dims& n) {
+  const int hx = (n.nx + 1) >> 1;
+  return SplitGeo{hx, (size_t)hx * n.ny * n.nz};
+}
+__device__ __forceinline__ size_t sidx(const Dims& n, const SplitGeo& g, int i, int j, int k) {
+  return (size_t)((i + j + k) & 1) * g.P + (size_t)(i >> 1) + (size_t)g.hx * (j + (size_t)n.ny * k);
+}
+// index of cell (i, j, k) of a level's correction, split or natural
+__device__ __forceinline__ size_t lidx(const Dims& n, const SplitGeo& g, bool split, int i, int j, int k) {
+  return split ? sidx(n, g, i, j, k) : (size_t)i + (size_t)n.nx * (j + (size_t)n.ny * k);
+}
+
 // Threads own cell pairs (2ti, 2ti+1) of a row; the red cell of the pair is
-// 2ti + ((j+k) & 1), the black one the other.
+// 2ti + ((j+k) & 1), the black one the other; pos is the pair index.
 #define PAIR_INDEX                                           \
   const int ti = blockIdx.x * blockDim.x + threadIdx.x;      \
   const int j = blockIdx.y * blockDim.y + threadIdx.y;       \
   const int k = blockIdx.z * blockDim.z + threadIdx.z;       \
   if (j >= n.ny || k >= n.nz) return;                        \
+  const SplitGeo sg = split_geo(n);                          \
+  if (ti >= sg.hx) return;                                   \
   const size_t sxy = (size_t)n.nx * n.ny;                    \
-  const size_t row = (size_t)n.nx * j + sxy * k
+  const size_t row = (size_t)n.nx * j + sxy * k;             \
+  const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k)
 
-// one colour of Gauss-Seidel (FINE: finest-level instance, own symbol)
-template <typename T, bool FINE>
-__global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx,
-                                            const T* __restrict__ by, const T* __restrict__ bz,
-                                            const T* __restrict__ b, T* __restrict__ e, int colour) {
-  PAIR_INDEX;
-  const int i = 2 * ti + ((j + k + colour) & 1);
-  if (i >= n.nx) return;
-  const size_t c = row + i;
+// Gauss-Seidel value of cell (i, j, k) with pair index pos: (h^2 b + sum over
+// non-wall faces of beta_f x_nb) / D, the neighbour values o(q) taken from the
+// other colour at the neighbours' pair indices.  Wall terms are dropped by
+// selects and every load goes through an in-range index (a wall neighbour
+// through the cell's own pair index), so all of a thread's loads are in
+// flight together and a 0 * garbage product never enters a sum.
+template <typename T, typename O>
+__device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T h2, const T* __restrict__ bx,
+                                           const T* __restrict__ by, const T* __restrict__ bz, T bc, int i, int j,
+                                           int k, size_t pos, O o) {
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const size_t c = i + (size_t)n.nx * j + sxy * k;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
   const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
   const bool top = (k == n.nz - 1);
+  const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0;
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  // every neighbour is loaded unconditionally (a wall neighbour through the
-  // cell's own index, so all loads are in flight together) and a wall term is
-  // then dropped by a select, never multiplied in: the cell's own entry may
-  // still be unset, and 0 * garbage need not be 0
-  const T ew = e[i > 0 ? c - 1 : c], ee = e[i < n.nx - 1 ? c + 1 : c];
-  const T es = e[j > 0 ? c - n.nx : c], en = e[j < n.ny - 1 ? c + n.nx : c];
-  const T ed = e[k > 0 ? c - sxy : c], eu = e[top ? c : c + sxy];
-  const T num = h2 * b[c] + (i > 0 ? bw * ew : (T)0) + (i < n.nx - 1 ? be * ee : (T)0) +
-                (j > 0 ? bs * es : (T)0) + (j < n.ny - 1 ? bn * en : (T)0) + (k > 0 ? bd * ed : (T)0) +
-                (top ? (T)0 : bu * eu);
-  e[c] = num / diag;
+  // x neighbours: cell i - 1 is in pair (i - 1) >> 1, cell i + 1 in pair (i + 1) >> 1
+  const size_t sz = (size_t)sg.hx * n.ny;
+  const size_t pw = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos;
+  const size_t pe = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
+  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos;
+  const size_t pd = D ? pos - sz : pos, pu = top ? pos : pos + sz;
+  const T vw = o(pw), ve = o(pe), vs = o(ps), vn = o(pn), vd = o(pd), vu = o(pu);
+  const T num = h2 * bc + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
+                (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
+  return num / diag;
 }
 
-// red pass from a zero guess followed by the black pass, in one launch
+// one colour of Gauss-Seidel on colour-split b, e (FINE: finest-level
+// instance, own symbol).  With nat set (the last pass of the finest level's
+// V-cycle) the pair is written, both colours, to nat in natural order
+// instead of back into e.
 template <typename T, bool FINE>
-__global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx,
-                                                  const T* __restrict__ by, const T* __restrict__ bz,
-                                                  const T* __restrict__ b, const T* __restrict__ invd,
-                                                  T* __restrict__ e) {
+__global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                            const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
+                                            int colour, T* __restrict__ nat) {
+  PAIR_INDEX;
+  const int par = (j + k + colour) & 1;
+  const int i = 2 * ti + par, io = 2 * ti + 1 - par;
+  const T* eo = e + (size_t)(1 - colour) * sg.P;
+  if (i < n.nx) {
+    const T v = gs_split_value<T>(n, sg, h2, bx, by, bz, b[(size_t)colour * sg.P + pos], i, j, k, pos,
+                                  [&](size_t q) { return eo[q]; });
+    if (nat)
+      nat[row + i] = v;
+    else
+      e[(size_t)colour * sg.P + pos] = v;
+  }
+  if (nat && io < n.nx) nat[row + io] = eo[pos];
+}
+
+// red pass from a zero guess followed by the black pass, in one launch: the
+// red values the black cells need are recomputed from b and 1/D.  NAT: b is
+// read in natural order (the finest level, whose b is a CG vector) and its
+// colour-split copy is written to bs for the later passes.
+template <typename T, bool FINE, bool NAT>
+__global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                                  const T* __restrict__ bz, const T* __restrict__ b,
+                                                  const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs) {
   PAIR_INDEX;
   const int par = (j + k) & 1;
   const int ir = 2 * ti + par, ib = 2 * ti + 1 - par;
-  if (ir < n.nx) e[row + ir] = h2 * b[row + ir] * invd[row + ir];
+  const size_t sz = (size_t)sg.hx * n.ny;
+  // b of the cell (ii, jj, kk) of colour c with pair index q
+  auto bval = [&](int c, size_t q, int ii, int jj, int kk) -> T {
+    if constexpr (NAT)
+      return b[(size_t)ii + (size_t)n.nx * jj + sxy * kk];
+    else
+      return b[(size_t)c * sg.P + q];
+  };
+  if (ir < n.nx) {
+    const T br = bval(0, pos, ir, j, k);
+    e[pos] = h2 * br * invd[pos];
+    if constexpr (NAT) bs[pos] = br;
+  }
   if (ib >= n.nx) return;
-  const int i = ib;
-  const size_t c = row + i;
-  auto red = [&](size_t q) { return h2 * b[q] * invd[q]; };
-  const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
-  const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
-  const bool top = (k == n.nz - 1);
-  const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  const T num = h2 * b[c] + bw * red(i > 0 ? c - 1 : c) + be * red(i < n.nx - 1 ? c + 1 : c) +
-                bs * red(j > 0 ? c - n.nx : c) + bn * red(j < n.ny - 1 ? c + n.nx : c) +
-                bd * red(k > 0 ? c - sxy : c) + (top ? (T)0 : bu * red(top ? c : c + sxy));
-  e[c] = num / diag;
+  const T bb = bval(1, pos, ib, j, k);
+  if constexpr (NAT) bs[sg.P + pos] = bb;
+  // red neighbour values h2 b / D through in-range indices (walls: own pair)
+  const bool W = ib > 0, E = ib < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
+  const size_t pw = W ? pos - (size_t)((ib & 1) ? 0 : 1) : pos, pe = E ? pos + (size_t)((ib & 1) ? 1 : 0) : pos;
+  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
+  const int iw = W ? ib - 1 : ib, ie = E ? ib + 1 : ib, js = S ? j - 1 : j, jn = N ? j + 1 : j;
+  const int kd = D ? k - 1 : k, ku = U ? k + 1 : k;
+  auto red = [&](size_t q, int ii, int jj, int kk) { return h2 * bval(0, q, ii, jj, kk) * invd[q]; };
+  const T vw = red(pw, iw, j, k), ve = red(pe, ie, j, k), vs = red(ps, ib, js, k), vn = red(pn, ib, jn, k),
+          vd = red(pd, ib, j, kd), vu = red(pu, ib, j, ku);
+  const size_t c = row + ib;
+  const size_t fx = ib + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+  const size_t fy = ib + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+  const T bw = bx[fx], be = bx[fx + 1], bsy = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  const bool top = !U;
+  const T diag = bw + be + bsy + bn + bd + (top ? (T)2 * bu : bu);
+  const T num = h2 * bb + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bsy * vs : (T)0) +
+                (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
+  e[sg.P + pos] = num / diag;
 }
 
 // prolongation e += P ec followed by the black pass, in one launch; only the
 // black cells are written (the red pass that follows overwrites the red ones
-// without reading them)
+// without reading them).  ec is the next level's correction, colour-split
+// (csplit) or natural (a tail level).
 template <typename T, bool FINE>
-__global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx,
-                                                    const T* __restrict__ by, const T* __restrict__ bz,
-                                                    const T* __restrict__ b, T* __restrict__ e, Dims nc,
-                                                    int fxc, int fyc, int fzc, const T* __restrict__ ec) {
+__global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                                    const T* __restrict__ bz, const T* __restrict__ b,
+                                                    T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
+                                                    const T* __restrict__ ec) {
   PAIR_INDEX;
   const int i = 2 * ti + 1 - ((j + k) & 1);   // the black cell
   if (i >= n.nx) return;
-  const size_t c = row + i;
-  auto up = [&](int ii, int jj, int kk) {
-    const size_t q = ii + (size_t)n.nx * jj + sxy * kk;
-    return e[q] + ec[(ii / fxc) + (size_t)nc.nx * ((jj / fyc) + (size_t)nc.ny * (kk / fzc))];
+  const SplitGeo cg = split_geo(nc);
+  auto up = [&](size_t q, int ii, int jj, int kk) {
+    return e[q] + ec[lidx(nc, cg, csplit != 0, ii >> sxc, jj >> syc, kk >> szc)];
   };
+  const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
+  const size_t sz = (size_t)sg.hx * n.ny;
+  const size_t pw = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos, pe = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
+  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
+  const T vw = up(pw, W ? i - 1 : i, j, k), ve = up(pe, E ? i + 1 : i, j, k), vs = up(ps, i, S ? j - 1 : j, k),
+          vn = up(pn, i, N ? j + 1 : j, k), vd = up(pd, i, j, D ? k - 1 : k), vu = up(pu, i, j, U ? k + 1 : k);
+  const size_t c = row + i;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
   const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
-  const bool top = (k == n.nz - 1);
+  const bool top = !U;
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  // neighbours loaded unconditionally through clamped indices, wall terms
-  // dropped by a select (as in k_gs)
-  const T uw = up(i > 0 ? i - 1 : i, j, k), ue = up(i < n.nx - 1 ? i + 1 : i, j, k);
-  const T us = up(i, j > 0 ? j - 1 : j, k), un = up(i, j < n.ny - 1 ? j + 1 : j, k);
-  const T ud = up(i, j, k > 0 ? k - 1 : k), uu = up(i, j, top ? k : k + 1);
-  const T num = h2 * b[c] + (i > 0 ? bw * uw : (T)0) + (i < n.nx - 1 ? be * ue : (T)0) +
-                (j > 0 ? bs * us : (T)0) + (j < n.ny - 1 ? bn * un : (T)0) + (k > 0 ? bd * ud : (T)0) +
-                (top ? (T)0 : bu * uu);
-  e[c] = num / diag;
+  const T num = h2 * b[sg.P + pos] + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
+                (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
+  e[sg.P + pos] = num / diag;
 }
 
-// coarse rhs = mean over the children of the fine residual b - A e
+// coarse rhs = mean over the children of the fine residual b - A e (fine b,
+// e colour-split; the coarse b colour-split when csplit, else natural)
 template <typename T>
 __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy, int fz, T ih2,
-                                                        const T* __restrict__ bx,
-                                                        const T* __restrict__ by,
-                                                        const T* __restrict__ bz,
-                                                        const T* __restrict__ b,
-                                                        const T* __restrict__ e, Dims nc, T inv,
+                                                        const T* __restrict__ bx, const T* __restrict__ by,
+                                                        const T* __restrict__ bz, const T* __restrict__ b,
+                                                        const T* __restrict__ e, Dims nc, int csplit, T inv,
                                                         T* __restrict__ bc) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   const int J = blockIdx.y * blockDim.y + threadIdx.y;
   const int K = blockIdx.z * blockDim.z + threadIdx.z;
   if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
+  const SplitGeo sg = split_geo(nf);
+  const size_t sxy = (size_t)nf.nx * nf.ny;
   T sum = 0;
   for (int dk = 0; dk < fz; ++dk)
     for (int dj = 0; dj < fy; ++dj)
       for (int di = 0; di < fx; ++di) {
         const int i = fx * I + di, j = fy * J + dj, k = fz * K + dk;
-        const size_t c = i + (size_t)nf.nx * (j + (size_t)nf.ny * k);
-        sum += b[c] - ih2 * stencil<T>(nf, bx, by, bz, e, i, j, k, c);
+        const size_t c = i + (size_t)nf.nx * j + sxy * k;
+        const size_t fxi = i + (size_t)(nf.nx + 1) * (j + (size_t)nf.ny * k);
+        const size_t fyi = i + (size_t)nf.nx * (j + (size_t)(nf.ny + 1) * k);
+        const T xc = e[sidx(nf, sg, i, j, k)];
+        const T xw = e[sidx(nf, sg, i > 0 ? i - 1 : i, j, k)];
+        const T xe = e[sidx(nf, sg, i < nf.nx - 1 ? i + 1 : i, j, k)];
+        const T xs = e[sidx(nf, sg, i, j > 0 ? j - 1 : j, k)];
+        const T xn = e[sidx(nf, sg, i, j < nf.ny - 1 ? j + 1 : j, k)];
+        const T xd = e[sidx(nf, sg, i, j, k > 0 ? k - 1 : k)];
+        const T xu = e[sidx(nf, sg, i, j, k < nf.nz - 1 ? k + 1 : k)];
+        const T bu = bz[c + sxy];
+        T acc = bx[fxi] * (xc - xw) + bx[fxi + 1] * (xc - xe) + by[fyi] * (xc - xs) + by[fyi + nf.nx] * (xc - xn) +
+                bz[c] * (xc - xd);
+        acc += (k < nf.nz - 1) ? bu * (xc - xu) : (T)2 * bu * xc;
+        sum += b[sidx(nf, sg, i, j, k)] - ih2 * acc;
       }
-  bc[I + (size_t)nc.nx * (J + (size_t)nc.ny * K)] = sum * inv;
+  const SplitGeo cg = split_geo(nc);
+  bc[lidx(nc, cg, csplit != 0, I, J, K)] = sum * inv;
 }
 
-// fine correction += parent's coarse correction (used when nu_post == 0)
+// colour-split fine correction += parent's coarse correction (nu_post == 0)
 template <typename T>
-__global__ void __launch_bounds__(256) k_prolong(Dims nf, int fx, int fy, int fz, T* __restrict__ e,
-                                                 Dims nc, const T* __restrict__ ec) {
+__global__ void __launch_bounds__(256) k_prolong(Dims nf, int sx, int sy, int sz, T* __restrict__ e, Dims nc,
+                                                 int csplit, const T* __restrict__ ec) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z * blockDim.z + threadIdx.z;
   if (i >= nf.nx || j >= nf.ny || k >= nf.nz) return;
-  e[i + (size_t)nf.nx * (j + (size_t)nf.ny * k)] +=
-      ec[(i / fx) + (size_t)nc.nx * ((j / fy) + (size_t)nc.ny * (k / fz))];
+  const SplitGeo sg = split_geo(nf), cg = split_geo(nc);
+  e[sidx(nf, sg, i, j, k)] += ec[lidx(nc, cg, csplit != 0, i >> sx, j >> sy, k >> sz)];
 }
 
-// 1 / (sum of the cell's face coefficients, top face counted twice)
+// natural <-> colour-split copies (the finest level's edge cases)
 template <typename T>
-__global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ bx,
-                                                 const T* __restrict__ by, const T* __restrict__ bz,
-                                                 T* __restrict__ invd) {
+__global__ void __launch_bounds__(256) k_split_copy(Dims n, const T* __restrict__ src, T* __restrict__ dst,
+                                                    int to_split) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  if (i >= n.nx || j >= n.ny || k >= n.nz) return;
+  const SplitGeo sg = split_geo(n);
+  const size_t c = i + (size_t)n.nx * (j + (size_t)n.ny * k), s = sidx(n, sg, i, j, k);
+  if (to_split)
+    dst[s] = src[c];
+  else
+    dst[c] = src[s];
+}
+
+// 1 / (sum of the cell's face coefficients, top face counted twice), stored
+// colour-split (levels above the tail) or natural (tail levels)
+template <typename T>
+__global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ bx, const T* __restrict__ by,
+                                                 const T* __restrict__ bz, int split, T* __restrict__ invd) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z * blockDim.z + threadIdx.z;
@@ -247,7 +352,7 @@ __global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ b
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
   const T bu = bz[c + sxy];
   const T diag = bx[fx] + bx[fx + 1] + by[fy] + by[fy + n.nx] + bz[c] + (k == n.nz - 1 ? (T)2 * bu : bu);
-  invd[c] = (T)1 / diag;
+  invd[lidx(n, split_geo(n), split != 0, i, j, k)] = (T)1 / diag;
 }
 
 // coarse face coefficient = mean of the fine faces covering it
@@ -702,56 +807,68 @@ __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ pa
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
-               hipStream_t st, KTimer* kt) {
+               hipStream_t st, KTimer* kt, T* nat) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
   auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
   if (kt && kt->n < kt->cap) {
     hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
-                          (T)(L.h * L.h), bx, by, bz, b, e, colour);
+                          (T)(L.h * L.h), bx, by, bz, b, e, colour, nat);
     ++kt->n;
     return;
   }
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, nat);
 }
 
 template <typename T>
-void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, const T* invd,
-                     T* e, hipStream_t st) {
+void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, bool b_natural,
+                     const T* invd, T* e, T* bs, hipStream_t st) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
-  auto kern = (L.h == L.h0) ? k_gs_first<T, true> : k_gs_first<T, false>;
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e);
+  const bool fine = (L.h == L.h0);
+  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*);
+  if (b_natural)
+    kern = fine ? k_gs_first<T, true, true> : k_gs_first<T, false, true>;
+  else
+    kern = fine ? k_gs_first<T, true, false> : k_gs_first<T, false, false>;
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs);
 }
 
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
-                       const Level& C, const T* ec, hipStream_t st) {
+                       const Level& C, const T* ec, bool ec_split, hipStream_t st) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0],
-                     L.f[1], L.f[2], ec);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0] >> 1,
+                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec);
 }
 
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
-                           const T* e, const Level& C, T* bc, hipStream_t st) {
+                           const T* e, const Level& C, T* bc, bool c_split, hipStream_t st) {
   Geo g = geo3(C.n.nx, C.n.ny, C.n.nz);
   const T ih2 = (T)(1.0 / (F.h * F.h));
   const T inv = (T)(1.0 / (F.f[0] * F.f[1] * F.f[2]));
   hipLaunchKernelGGL(k_resid_restrict<T>, g.grid, g.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], ih2, bx,
-                     by, bz, b, e, C.n, inv, bc);
+                     by, bz, b, e, C.n, c_split ? 1 : 0, inv, bc);
 }
 
 template <typename T>
-void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, hipStream_t st) {
+void launch_prolong(const Level& F, T* e, const Level& C, const T* ec, bool ec_split, hipStream_t st) {
   Geo g = geo3(F.n.nx, F.n.ny, F.n.nz);
-  hipLaunchKernelGGL(k_prolong<T>, g.grid, g.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], e, C.n, ec);
+  hipLaunchKernelGGL(k_prolong<T>, g.grid, g.block, 0, st, F.n, F.f[0] >> 1, F.f[1] >> 1, F.f[2] >> 1, e, C.n,
+                     ec_split ? 1 : 0, ec);
 }
 
 template <typename T>
-void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, hipStream_t st) {
+void launch_split_copy(const Level& L, const T* src, T* dst, bool to_split, hipStream_t st) {
   Geo g = geo3(L.n.nx, L.n.ny, L.n.nz);
-  hipLaunchKernelGGL(k_invdiag<T>, g.grid, g.block, 0, st, L.n, bx, by, bz, invd);
+  hipLaunchKernelGGL(k_split_copy<T>, g.grid, g.block, 0, st, L.n, src, dst, to_split ? 1 : 0);
+}
+
+template <typename T>
+void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, bool split, hipStream_t st) {
+  Geo g = geo3(L.n.nx, L.n.ny, L.n.nz);
+  hipLaunchKernelGGL(k_invdiag<T>, g.grid, g.block, 0, st, L.n, bx, by, bz, split ? 1 : 0, invd);
 }
 
 template <typename T>
@@ -852,16 +969,17 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
 }
 
 #define NSK_INST(T)                                                                                   \
-  template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int,          \
-                             hipStream_t, KTimer*);                                                   \
-  template void launch_gs_first<T>(const Level&, const T*, const T*, const T*, const T*, const T*,   \
-                                   T*, hipStream_t);                                                  \
-  template void launch_gs_prolong<T>(const Level&, const T*, const T*, const T*, const T*, T*,       \
-                                     const Level&, const T*, hipStream_t);                            \
-  template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*,        \
-                                         const T*, const Level&, T*, hipStream_t);                    \
-  template void launch_prolong<T>(const Level&, T*, const Level&, const T*, hipStream_t);             \
-  template void launch_invdiag<T>(const Level&, const T*, const T*, const T*, T*, hipStream_t);       \
+  template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int, hipStream_t,   \
+                             KTimer*, T*);                                                                \
+  template void launch_gs_first<T>(const Level&, const T*, const T*, const T*, const T*, bool, const T*,  \
+                                   T*, T*, hipStream_t);                                                  \
+  template void launch_gs_prolong<T>(const Level&, const T*, const T*, const T*, const T*, T*,           \
+                                     const Level&, const T*, bool, hipStream_t);                          \
+  template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*, const T*,  \
+                                         const Level&, T*, bool, hipStream_t);                            \
+  template void launch_prolong<T>(const Level&, T*, const Level&, const T*, bool, hipStream_t);           \
+  template void launch_split_copy<T>(const Level&, const T*, T*, bool, hipStream_t);                     \
+  template void launch_invdiag<T>(const Level&, const T*, const T*, const T*, T*, bool, hipStream_t);    \
   template void launch_coarsen_beta<T>(const Level&, const T*, const T*, const T*, const Level&, T*,  \
                                        T*, T*, hipStream_t);                                          \
   template void launch_fill<T>(T*, size_t, hipStream_t);                                              \
