@@ -271,40 +271,55 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
 }
 
 // coarse rhs = mean over the children of the fine residual b - A e (fine b,
-// e colour-split; the coarse b colour-split when csplit, else natural)
+// e colour-split; the coarse b colour-split when csplit, else natural).  A
+// block takes a tile of fine cells (32 x 4 x 2; 64 x 1 x 4 in 2-D), one
+// thread per cell: each computes its cell's residual into LDS, then one
+// thread per coarse cell of the tile sums its children from LDS in the
+// order (dk, dj, di).  Tile extents are even, so a coarse cell's children
+// never straddle two tiles.
 template <typename T>
 __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy, int fz, T ih2,
                                                         const T* __restrict__ bx, const T* __restrict__ by,
                                                         const T* __restrict__ bz, const T* __restrict__ b,
                                                         const T* __restrict__ e, Dims nc, int csplit, T inv,
                                                         T* __restrict__ bc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
-  const int K = blockIdx.z * blockDim.z + threadIdx.z;
-  if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
+  __shared__ T sr[256];
+  const int TX = blockDim.x, TY = blockDim.y;
+  const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
+  const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty, k = blockIdx.z * blockDim.z + tz;
   const SplitGeo sg = split_geo(nf);
   const size_t sxy = (size_t)nf.nx * nf.ny;
+  T r = 0;
+  if (i < nf.nx && j < nf.ny && k < nf.nz) {
+    const size_t c = i + (size_t)nf.nx * j + sxy * k;
+    const size_t fxi = i + (size_t)(nf.nx + 1) * (j + (size_t)nf.ny * k);
+    const size_t fyi = i + (size_t)nf.nx * (j + (size_t)(nf.ny + 1) * k);
+    const T xc = e[sidx(nf, sg, i, j, k)];
+    const T xw = e[sidx(nf, sg, i > 0 ? i - 1 : i, j, k)];
+    const T xe = e[sidx(nf, sg, i < nf.nx - 1 ? i + 1 : i, j, k)];
+    const T xs = e[sidx(nf, sg, i, j > 0 ? j - 1 : j, k)];
+    const T xn = e[sidx(nf, sg, i, j < nf.ny - 1 ? j + 1 : j, k)];
+    const T xd = e[sidx(nf, sg, i, j, k > 0 ? k - 1 : k)];
+    const T xu = e[sidx(nf, sg, i, j, k < nf.nz - 1 ? k + 1 : k)];
+    const T bu = bz[c + sxy];
+    T acc = bx[fxi] * (xc - xw) + bx[fxi + 1] * (xc - xe) + by[fyi] * (xc - xs) + by[fyi + nf.nx] * (xc - xn) +
+            bz[c] * (xc - xd);
+    acc += (k < nf.nz - 1) ? bu * (xc - xu) : (T)2 * bu * xc;
+    r = b[sidx(nf, sg, i, j, k)] - ih2 * acc;
+  }
+  const int t = (tz * TY + ty) * TX + tx;
+  sr[t] = r;
+  __syncthreads();
+  // coarse cells of the tile
+  const int CX = TX / fx, CY = TY / fy, CZ = (int)blockDim.z / fz;
+  if (t >= CX * CY * CZ) return;
+  const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
+  const int I = blockIdx.x * CX + cx, J = blockIdx.y * CY + cy, K = blockIdx.z * CZ + cz;
+  if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
   T sum = 0;
   for (int dk = 0; dk < fz; ++dk)
     for (int dj = 0; dj < fy; ++dj)
-      for (int di = 0; di < fx; ++di) {
-        const int i = fx * I + di, j = fy * J + dj, k = fz * K + dk;
-        const size_t c = i + (size_t)nf.nx * j + sxy * k;
-        const size_t fxi = i + (size_t)(nf.nx + 1) * (j + (size_t)nf.ny * k);
-        const size_t fyi = i + (size_t)nf.nx * (j + (size_t)(nf.ny + 1) * k);
-        const T xc = e[sidx(nf, sg, i, j, k)];
-        const T xw = e[sidx(nf, sg, i > 0 ? i - 1 : i, j, k)];
-        const T xe = e[sidx(nf, sg, i < nf.nx - 1 ? i + 1 : i, j, k)];
-        const T xs = e[sidx(nf, sg, i, j > 0 ? j - 1 : j, k)];
-        const T xn = e[sidx(nf, sg, i, j < nf.ny - 1 ? j + 1 : j, k)];
-        const T xd = e[sidx(nf, sg, i, j, k > 0 ? k - 1 : k)];
-        const T xu = e[sidx(nf, sg, i, j, k < nf.nz - 1 ? k + 1 : k)];
-        const T bu = bz[c + sxy];
-        T acc = bx[fxi] * (xc - xw) + bx[fxi + 1] * (xc - xe) + by[fyi] * (xc - xs) + by[fyi + nf.nx] * (xc - xn) +
-                bz[c] * (xc - xd);
-        acc += (k < nf.nz - 1) ? bu * (xc - xu) : (T)2 * bu * xc;
-        sum += b[sidx(nf, sg, i, j, k)] - ih2 * acc;
-      }
+      for (int di = 0; di < fx; ++di) sum += sr[((cz * fz + dk) * TY + cy * fy + dj) * TX + cx * fx + di];
   const SplitGeo cg = split_geo(nc);
   bc[lidx(nc, cg, csplit != 0, I, J, K)] = sum * inv;
 }
@@ -737,13 +752,11 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
     const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
     const double dc = D(c);
     const double bu = bz[c + sxy];
+    const double du = D(k < n.nz - 1 ? c + sxy : c);   // unconditional: all loads in flight together
     double acc = bx[fx] * (dc - D(i > 0 ? c - 1 : c)) + bx[fx + 1] * (dc - D(i < n.nx - 1 ? c + 1 : c)) +
                  by[fy] * (dc - D(j > 0 ? c - n.nx : c)) + by[fy + n.nx] * (dc - D(j < n.ny - 1 ? c + n.nx : c)) +
                  bz[c] * (dc - D(k > 0 ? c - sxy : c));
-    if (k < n.nz - 1)
-      acc += bu * (dc - D(c + sxy));
-    else
-      acc += 2.0 * bu * dc;
+    acc += (k < n.nz - 1) ? bu * (dc - du) : 2.0 * bu * dc;
     const double qc = ih2 * acc;
     dnew[c] = dc;
     q[c] = qc;
@@ -782,10 +795,25 @@ __global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const doubl
 // fixed-order sum of the per-block partials and the CG scalar recurrences
 __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ partials, int nparts,
                                                    int nv, int mode, double* __restrict__ scal) {
+  // thread t sums partials t, t + 1024, t + 2048, ... in that order; each
+  // batch of 16 is loaded (clamped, unconditional) before it is added, so
+  // the loads are in flight together
   double v[2] = {0.0, 0.0};
-  for (int q = threadIdx.x; q < nparts; q += 1024) {
-    v[0] += partials[nv * q];
-    if (nv > 1) v[1] += partials[nv * q + 1];
+  constexpr int B = 16;
+  for (int base = threadIdx.x; base < nparts; base += 1024 * B) {
+    double a[B], c[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int q = min(base + 1024 * u, nparts - 1);
+      a[u] = partials[nv * q];
+      c[u] = nv > 1 ? partials[nv * q + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (base + 1024 * u < nparts) {
+        v[0] += a[u];
+        if (nv > 1) v[1] += c[u];
+      }
   }
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -845,7 +873,9 @@ void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, co
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
                            const T* e, const Level& C, T* bc, bool c_split, hipStream_t st) {
-  Geo g = geo3(C.n.nx, C.n.ny, C.n.nz);
+  // fine-cell tiles with even extents (a coarse cell's children in one tile)
+  const dim3 blk = (F.n.ny > 1) ? dim3(32, 4, 2) : dim3(64, 1, 4);
+  const Geo g{dim3((F.n.nx + blk.x - 1) / blk.x, (F.n.ny + blk.y - 1) / blk.y, (F.n.nz + blk.z - 1) / blk.z), blk};
   const T ih2 = (T)(1.0 / (F.h * F.h));
   const T inv = (T)(1.0 / (F.f[0] * F.f[1] * F.f[2]));
   hipLaunchKernelGGL(k_resid_restrict<T>, g.grid, g.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], ih2, bx,
