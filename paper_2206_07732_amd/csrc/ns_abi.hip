@@ -130,14 +130,16 @@ size_t tail_pack_elems(const Level* lev, int L, int l) {
   return tot;
 }
 
-// LDS elements of the tail from level l down: the pack, then b and e per level
+// LDS elements of the tail from level l down: the pack, then b and e per
+// level, then (when the tail restricts, i.e. has more than one level) a
+// residual scratch of level l's size
 size_t tail_elems(const Level* lev, int L, int l) {
   size_t tot = tail_pack_elems(lev, L, l);
   for (int q = l; q < L; ++q) {
     const Dims n = lev[q].n;
     tot += 2 * pad4((size_t)n.nx * n.ny * n.nz);
   }
-  return tot;
+  return tot + (l < L - 1 ? pad4((size_t)lev[l].n.nx * lev[l].n.ny * lev[l].n.nz) : 0);
 }
 
 // first level whose tail fits the LDS budget and the workgroup (L: none)
@@ -407,6 +409,7 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
     D.ob[q] = take(mc);
     D.oe[q] = take(mc);
   }
+  D.ors = D.nl > 1 ? take((size_t)D.n[0].nx * D.n[0].ny * D.n[0].nz) : 0;
   D.pack = LV<T>::bx(X->lev[l0]);   // the pack starts with the first tail level's bx
   D.b0 = b;
   D.ge = e;
@@ -431,6 +434,29 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
   KTimer* kt = (l == 0 && X->timed_kernel == NS_TIME_SMOOTH0) ? &X->kt : nullptr;
   const size_t nsplit = 2 * (size_t)((L.n.nx + 1) / 2) * L.n.ny * L.n.nz;
+  if (l == X->L - 1) {
+    // a coarsest level too large for the tail: its sweeps with the
+    // multi-block kernels, forward (red, black) then backward (black, red)
+    // from zero; at level 0 the last red pass writes e0
+    const int S = P.coarse_sweeps;
+    if (S == 0) {
+      if (l == 0)
+        launch_fill<T>(e0, (size_t)L.n.nx * L.n.ny * L.n.nz, st);
+      else
+        launch_fill<T>(e, nsplit, st);
+      return;
+    }
+    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st);
+    for (int s = 1; s < S; ++s) {
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
+    }
+    for (int s = 0; s < S; ++s) {
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, (l == 0 && s == S - 1) ? e0 : nullptr);
+    }
+    return;
+  }
   // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
     launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st);

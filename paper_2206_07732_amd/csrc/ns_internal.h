@@ -73,7 +73,7 @@ struct KTimer {
 // Coarse-level tail of the V-cycle run by one workgroup from LDS.
 constexpr int kTailMaxLevels = 12;
 constexpr int kTailThreads = 512;
-constexpr size_t kTailLdsBytes = 64 * 1024;
+constexpr size_t kTailLdsBytes = 160 * 1024;   // gfx950: 160 KB of LDS per workgroup
 
 template <typename T>
 struct TailDesc {
@@ -84,6 +84,7 @@ struct TailDesc {
   T h2[kTailMaxLevels];
   int obx[kTailMaxLevels], oby[kTailMaxLevels], obz[kTailMaxLevels];  // LDS offsets (elements)
   int ob[kTailMaxLevels], oe[kTailMaxLevels], oid[kTailMaxLevels];
+  int ors;                                  // LDS scratch: one value per cell of the first level
   // staging: the first npack LDS elements are a flat copy of pack (the tail
   // levels' bx, by, bz, 1/D), then the first level's b goes to ob[0]
   const T* pack;

@@ -514,35 +514,39 @@ struct TailLevel {
     const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l], *b = sm + D.ob[l];
     const T* e = sm + D.oe[l];
     T* bc = sm + D.ob[l + 1];
+    T* rs = sm + D.ors;   // scratch: the fine residual
     const T ih2 = (T)1 / D.h2[l];
     const T inv = (T)1 / (T)(fx * fy * fz);
-    const int Nc = nc.nx * nc.ny * nc.nz;
+    const int N = nf.nx * nf.ny * nf.nz, Nc = nc.nx * nc.ny * nc.nz;
     const int sxy = nf.nx * nf.ny;
+    // every fine cell's residual b - A e, one thread per cell ...
+    for (int c = tid; c < N; c += nthr) {
+      const int i = c % nf.nx, j = (c / nf.nx) % nf.ny, k = c / sxy;
+      const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
+      const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
+      const T xc = e[c];
+      const bool w = i > 0, E = i < nf.nx - 1, S = j > 0, N2 = j < nf.ny - 1, d = k > 0, u = k < nf.nz - 1;
+      const T tw = bx[ix] * (xc - e[w ? c - 1 : c]), te = bx[ix + 1] * (xc - e[E ? c + 1 : c]);
+      const T ts = by[iy] * (xc - e[S ? c - nf.nx : c]), tn = by[iy + nf.nx] * (xc - e[N2 ? c + nf.nx : c]);
+      const T td = bz[c] * (xc - e[d ? c - sxy : c]);
+      const T tu = u ? bz[c + sxy] * (xc - e[u ? c + sxy : c]) : (T)2 * bz[c + sxy] * xc;
+      T acc = 0;
+      if (w) acc += tw;
+      if (E) acc += te;
+      if (S) acc += ts;
+      if (N2) acc += tn;
+      if (d) acc += td;
+      acc += tu;
+      rs[c] = b[c] - ih2 * acc;
+    }
+    tail_sync<WAVE>();
+    // ... then each coarse cell's mean of its children, summed in the order (dk, dj, di)
     for (int C = tid; C < Nc; C += nthr) {
       const int I = C % nc.nx, J = (C / nc.nx) % nc.ny, K = C / (nc.nx * nc.ny);
       T sum = 0;
       for (int dk = 0; dk < fz; ++dk)
         for (int dj = 0; dj < fy; ++dj)
-          for (int di = 0; di < fx; ++di) {
-            const int i = fx * I + di, j = fy * J + dj, k = fz * K + dk;
-            const int c = i + nf.nx * (j + nf.ny * k);
-            const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
-            const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
-            const T xc = e[c];
-            const bool w = i > 0, E = i < nf.nx - 1, S = j > 0, N = j < nf.ny - 1, d = k > 0, u = k < nf.nz - 1;
-            const T tw = bx[ix] * (xc - e[w ? c - 1 : c]), te = bx[ix + 1] * (xc - e[E ? c + 1 : c]);
-            const T ts = by[iy] * (xc - e[S ? c - nf.nx : c]), tn = by[iy + nf.nx] * (xc - e[N ? c + nf.nx : c]);
-            const T td = bz[c] * (xc - e[d ? c - sxy : c]);
-            const T tu = u ? bz[c + sxy] * (xc - e[u ? c + sxy : c]) : (T)2 * bz[c + sxy] * xc;
-            T acc = 0;
-            if (w) acc += tw;
-            if (E) acc += te;
-            if (S) acc += ts;
-            if (N) acc += tn;
-            if (d) acc += td;
-            acc += tu;
-            sum += b[c] - ih2 * acc;
-          }
+          for (int di = 0; di < fx; ++di) sum += rs[(fx * I + di) + nf.nx * ((fy * J + dj) + nf.ny * (fz * K + dk))];
       bc[C] = sum * inv;
     }
     tail_sync<WAVE>();
@@ -917,6 +921,13 @@ void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fb
 
 template <typename T>
 void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st) {
+  // dynamic LDS above 64 KB needs the kernel's limit raised (once per process)
+  static bool raised = false;
+  if (lds_bytes > 64 * 1024 && !raised) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_vcycle_tail<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsBytes);
+    raised = true;
+  }
   hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(1), dim3(kTailThreads), lds_bytes, st, D);
 }
 
