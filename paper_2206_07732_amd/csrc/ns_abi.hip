@@ -32,7 +32,8 @@ struct ns_ctx {
   int nparts;
   int L;
   Level lev[32];
-  double* host;   // pinned host scalars
+  double* host;       // pinned, coherent host mirror of the scalars
+  double* host_dev;   // its device address
   bool have_beta;
   int timed_kernel;   // -1 or an ns_timed_kernel id
   KTimer kt;
@@ -506,6 +507,13 @@ void prepare_hierarchy(ns_ctx* X) {
     build_hierarchy<float>(X);
 }
 
+// wait until the work queued so far has stored its scalars to the host mirror
+ns_status wait_host(ns_ctx* X) {
+  HIPCHK(X, hipEventRecord(X->ev_rr, X->st));
+  HIPCHK(X, hipEventSynchronize(X->ev_rr));
+  return NS_OK;
+}
+
 ns_status read_scal(ns_ctx* X) {
   HIPCHK(X, hipMemcpyAsync(X->host, X->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, X->st));
   HIPCHK(X, hipStreamSynchronize(X->st));
@@ -527,7 +535,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   const Level& L0 = X->lev[0];
   hipStream_t st = X->st;
   double* x = X->F.p;
-  const CgScratch cs{X->partials, X->scal};
+  const CgScratch cs{X->partials, X->scal, X->host_dev};
   ns_stats S{};
   double* z = X->z;
   double* zn = X->zn;
@@ -535,7 +543,6 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   double* dn = X->d2;
   prepare_hierarchy(X);
   launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
-  HIPCHK(X, hipMemcpyAsync(X->host, X->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(X, hipEventRecord(X->ev_rr, st));
   // first direction d = z = M r, rho = <r, z>, queued before the host has
   // seen ||b|| and ||r||; unused if b = 0 or the guess already converges
@@ -567,7 +574,6 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     first = false;
     launch_cg_update(n, d, X->q, x, X->r, cs, st);
     ++it;
-    HIPCHK(X, hipMemcpyAsync(X->host, X->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(X, hipEventRecord(X->ev_rr, st));
     // the residual this iteration is expected to reach, at the rate of the last one
     const bool likely_done = rr_prev > 0.0 && rr * (rr / rr_prev) <= tol2;
@@ -588,7 +594,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     if (rr <= tol2) {
       // confirm on the true residual; restart from it when it fails
       launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
-      ns_status s = read_scal(X);
+      ns_status s = wait_host(X);
       if (s != NS_OK) return s;
       rr = true_rr = X->host[S_RR];
       S.rel_resid = std::sqrt(rr) / bnorm;
@@ -613,7 +619,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   if (!conv) {
     // true residual at exit (into q, leaving r as the recursion left it)
     launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st);
-    ns_status s = read_scal(X);
+    ns_status s = wait_host(X);
     if (s != NS_OK) return s;
     true_rr = X->host[S_TRR];
   }
@@ -702,7 +708,15 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
   X->st = (hipStream_t)hip_stream;
   X->phys = make_phys(*params);
   carve(params, X, (char*)workspace);
-  if (hipHostMalloc((void**)&X->host, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  // coherent and mapped: the reduction kernels store the values the host
+  // tests straight into it, so reading them needs no copy
+  if (hipHostMalloc((void**)&X->host, S_COUNT * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped) !=
+      hipSuccess) {
+    delete X;
+    return NS_EHIP;
+  }
+  if (hipHostGetDevicePointer((void**)&X->host_dev, X->host, 0) != hipSuccess) {
+    (void)hipHostFree(X->host);
     delete X;
     return NS_EHIP;
   }
@@ -775,7 +789,7 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
   }
   Level& L0 = X->lev[0];
   const Dims n = L0.n;
-  const CgScratch cs{X->partials, X->scal};
+  const CgScratch cs{X->partials, X->scal, X->host_dev};
   (void)hipStreamSynchronize(X->st);
   (void)hipEventRecord(a, X->st);
   for (int q = 0; q < reps; ++q) {

@@ -99,6 +99,8 @@ enum FinMode { FIN_RESID0 = 0, FIN_RHO = 1, FIN_ALPHA = 2, FIN_RR = 3, FIN_BETA 
 struct CgScratch {
   double* partials;
   double* scal;
+  double* hscal;   // device address of the pinned host mirror of scal (the
+                   // values the host tests: S_BB, S_RR, S_TRR)
 };
 
 // ---------------------------------------------------------------- launchers

@@ -796,14 +796,17 @@ __global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const doubl
 }
 
 
-// fixed-order sum of the per-block partials and the CG scalar recurrences
+// fixed-order sum of the per-block partials and the CG scalar recurrences;
+// the values the host tests are also stored to its pinned mirror
+template <int B>
 __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ partials, int nparts,
-                                                   int nv, int mode, double* __restrict__ scal) {
+                                                   int nv, int mode, double* __restrict__ scal,
+                                                   double* __restrict__ hscal) {
   // thread t sums partials t, t + 1024, t + 2048, ... in that order; each
-  // batch of 16 is loaded (clamped, unconditional) before it is added, so
-  // the loads are in flight together
+  // batch of B is loaded (clamped, unconditional) before it is added, so the
+  // loads are in flight together.  B only sets how many loads one batch
+  // issues, never the order of the additions.
   double v[2] = {0.0, 0.0};
-  constexpr int B = 16;
   for (int base = threadIdx.x; base < nparts; base += 1024 * B) {
     double a[B], c[B];
 #pragma unroll
@@ -823,12 +826,23 @@ __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ pa
   if (threadIdx.x == 0) {
     const double a = v[0], b = v[1];
     switch (mode) {
-      case FIN_RESID0: scal[S_RR] = a; scal[S_BB] = b; break;
-      case FIN_TRR: scal[S_TRR] = a; break;
+      case FIN_RESID0:
+        scal[S_RR] = a;
+        scal[S_BB] = b;
+        hscal[S_RR] = a;
+        hscal[S_BB] = b;
+        break;
+      case FIN_TRR:
+        scal[S_TRR] = a;
+        hscal[S_TRR] = a;
+        break;
       case FIN_RHO: scal[S_RHO] = a; break;
       case FIN_BETA: scal[S_BETA] = (a - b) / scal[S_RHO]; scal[S_RHO] = a; break;
       case FIN_ALPHA: scal[S_DQ] = a; scal[S_ALPHA] = scal[S_RHO] / a; break;
-      case FIN_RR: scal[S_RR] = a; break;
+      case FIN_RR:
+        scal[S_RR] = a;
+        hscal[S_RR] = a;
+        break;
     }
   }
 }
@@ -953,7 +967,17 @@ int cg_blocks(const Dims& n) {
 
 static void finalize(const CgScratch& cs, int nparts, int mode, hipStream_t st) {
   const int nv = (mode == FIN_RESID0 || mode == FIN_TRR || mode == FIN_BETA) ? 2 : 1;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, cs.partials, nparts, nv, mode, cs.scal);
+  // loads per thread per batch: as many as the partials need, at most 16
+  const int per = (nparts + 1023) / 1024;
+  const dim3 g(1), b(1024);
+  if (per <= 1)
+    hipLaunchKernelGGL(k_finalize<1>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+  else if (per <= 2)
+    hipLaunchKernelGGL(k_finalize<2>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+  else if (per <= 4)
+    hipLaunchKernelGGL(k_finalize<4>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+  else
+    hipLaunchKernelGGL(k_finalize<16>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
 }
 
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
