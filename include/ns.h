@@ -183,6 +183,22 @@ ns_status ns_buffer(ns_ctx* ctx, int which, void** dev_ptr, size_t* count);
  * out is host memory; synchronises the stream. */
 ns_status ns_diagnostics(ns_ctx* ctx, double out[4]);
 
+/* How the CG loop issues its preconditioner (one V-cycle per iteration).
+ * NS_LAUNCH_GRAPH (the default): the V-cycle's kernels are recorded once per
+ * context into a HIP graph for each vector pair the loop uses, and each
+ * application is one graph launch on the context's stream; the kernels and
+ * their arguments are those of NS_LAUNCH_STREAM, which launches them one by
+ * one.  Results are bitwise the same either way; the graph saves host time
+ * per kernel.  Recording happens on the first solve after the mode is set
+ * (it runs nothing); the graphs live until ns_destroy.  While kernel timing
+ * is enabled the loop launches kernel by kernel.  NS_EINVAL for another
+ * value. */
+typedef enum {
+  NS_LAUNCH_STREAM = 0,
+  NS_LAUNCH_GRAPH = 1
+} ns_launch_mode;
+ns_status ns_set_launch_mode(ns_ctx* ctx, int mode);
+
 /* Kernel timing, a profiling aid.  While enabled for a kernel, each of its
  * next max_launches dispatches on the context's stream carries a start and
  * stop HIP event recorded by the dispatch itself (hipExtLaunchKernelGGL),

@@ -38,6 +38,14 @@ struct ns_ctx {
   int timed_kernel;   // -1 or an ns_timed_kernel id
   KTimer kt;
   hipEvent_t ev_rr;   // marks the residual read-back of a CG iteration
+  int launch_mode;    // ns_launch_mode
+  hipStream_t cap_st; // capture-only stream: the V-cycle graphs are recorded on it
+  struct {
+    const double* r;
+    double* z;
+    hipGraphExec_t exec;
+  } pg[2];            // V-cycle graphs, one per (r, z) pair the CG loop uses
+  int npg;
   ns_net* net;        // learned guess (not owned)
   int tail64, tail32; // first level of the LDS tail per precision (L: none)
   size_t lds64, lds32;
@@ -488,8 +496,8 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   }
 }
 
-// z = M r
-void precond(ns_ctx* X, const double* r, double* z) {
+// z = M r, one kernel launch at a time on the context's stream
+void precond_launch(ns_ctx* X, const double* r, double* z) {
   if (X->P.prec == NS_PREC_FP64) {
     vcycle<double>(X, 0, r, z);
   } else {
@@ -498,6 +506,49 @@ void precond(ns_ctx* X, const double* r, double* z) {
     vcycle<float>(X, 0, L0.bfn, L0.efn);
     launch_f2d(L0.efn, z, X->nc, X->st);
   }
+}
+
+// Record precond_launch(r, z) as a graph. Nothing runs: the kernels are
+// captured on the context's capture-only stream, with every argument
+// (level buffers, tail descriptor, r and z) fixed for the context's life.
+ns_status capture_precond(ns_ctx* X, const double* r, double* z, hipGraphExec_t* exec) {
+  hipStream_t run = X->st;
+  X->st = X->cap_st;
+  hipError_t e = hipStreamBeginCapture(X->cap_st, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    precond_launch(X, r, z);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(X->cap_st, &g);
+    if (e == hipSuccess) {
+      e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+    }
+  }
+  X->st = run;
+  if (e != hipSuccess) return fail(X, NS_EHIP, "V-cycle graph capture: %s", hipGetErrorString(e));
+  return NS_OK;
+}
+
+// z = M r: a replay of the recorded V-cycle for this (r, z) in graph mode,
+// else (stream mode, or while a kernel is being timed) the kernels one by one
+ns_status precond(ns_ctx* X, const double* r, double* z) {
+  if (X->launch_mode == NS_LAUNCH_GRAPH && X->timed_kernel < 0) {
+    hipGraphExec_t exec = nullptr;
+    for (int q = 0; q < X->npg; ++q)
+      if (X->pg[q].r == r && X->pg[q].z == z) exec = X->pg[q].exec;
+    if (!exec && X->npg < 2) {
+      ns_status s = capture_precond(X, r, z, &exec);
+      if (s != NS_OK) return s;
+      X->pg[X->npg++] = {r, z, exec};
+    }
+    if (exec) {
+      HIPCHK(X, hipGraphLaunch(exec, X->st));
+      return NS_OK;
+    }
+  }
+  precond_launch(X, r, z);
+  HIPCHK(X, hipGetLastError());
+  return NS_OK;
 }
 
 void prepare_hierarchy(ns_ctx* X) {
@@ -546,7 +597,8 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   HIPCHK(X, hipEventRecord(X->ev_rr, st));
   // first direction d = z = M r, rho = <r, z>, queued before the host has
   // seen ||b|| and ||r||; unused if b = 0 or the guess already converges
-  precond(X, X->r, z);
+  ns_status s = precond(X, X->r, z);
+  if (s != NS_OK) return s;
   launch_dot_rho(n, X->r, z, cs, st);
   HIPCHK(X, hipEventSynchronize(X->ev_rr));
   const double bb = X->host[S_BB];
@@ -579,7 +631,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     const bool likely_done = rr_prev > 0.0 && rr * (rr / rr_prev) <= tol2;
     const bool ahead = it < P.max_iters && !likely_done;
     if (ahead) {
-      precond(X, X->r, zn);
+      if ((s = precond(X, X->r, zn)) != NS_OK) return s;
       launch_dots_beta(n, X->r, zn, z, cs, st);
     }
     HIPCHK(X, hipEventSynchronize(X->ev_rr));
@@ -594,8 +646,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     if (rr <= tol2) {
       // confirm on the true residual; restart from it when it fails
       launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
-      ns_status s = wait_host(X);
-      if (s != NS_OK) return s;
+      if ((s = wait_host(X)) != NS_OK) return s;
       rr = true_rr = X->host[S_RR];
       S.rel_resid = std::sqrt(rr) / bnorm;
       if (rr <= tol2) {
@@ -603,7 +654,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
         break;
       }
       if (it >= P.max_iters) break;
-      precond(X, X->r, z);
+      if ((s = precond(X, X->r, z)) != NS_OK) return s;
       launch_dot_rho(n, X->r, z, cs, st);
       first = true;
       rr_prev = 0.0;
@@ -611,7 +662,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     }
     if (it >= P.max_iters) break;
     if (!ahead) {
-      precond(X, X->r, zn);
+      if ((s = precond(X, X->r, zn)) != NS_OK) return s;
       launch_dots_beta(n, X->r, zn, z, cs, st);
     }
     std::swap(z, zn);
@@ -619,8 +670,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   if (!conv) {
     // true residual at exit (into q, leaving r as the recursion left it)
     launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st);
-    ns_status s = wait_host(X);
-    if (s != NS_OK) return s;
+    if ((s = wait_host(X)) != NS_OK) return s;
     true_rr = X->host[S_TRR];
   }
   S.iters = it;
@@ -725,6 +775,14 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     delete X;
     return NS_EHIP;
   }
+  if (hipStreamCreateWithFlags(&X->cap_st, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipEventDestroy(X->ev_rr);
+    (void)hipHostFree(X->host);
+    delete X;
+    return NS_EHIP;
+  }
+  X->launch_mode = NS_LAUNCH_GRAPH;
+  X->npg = 0;
   X->have_beta = false;
   X->timed_kernel = -1;
   X->kt = KTimer{nullptr, 0, 0};
@@ -745,9 +803,18 @@ static void free_timer(ns_ctx* X) {
 void ns_destroy(ns_ctx* X) {
   if (!X) return;
   free_timer(X);
+  for (int q = 0; q < X->npg; ++q) (void)hipGraphExecDestroy(X->pg[q].exec);
+  if (X->cap_st) (void)hipStreamDestroy(X->cap_st);
   if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
   if (X->host) (void)hipHostFree(X->host);
   delete X;
+}
+
+ns_status ns_set_launch_mode(ns_ctx* X, int mode) {
+  if (!X) return NS_EINVAL;
+  if (mode != NS_LAUNCH_STREAM && mode != NS_LAUNCH_GRAPH) return fail(X, NS_EINVAL, "unknown launch mode %d", mode);
+  X->launch_mode = mode;
+  return NS_OK;
 }
 
 ns_status ns_timing_enable(ns_ctx* X, int kernel, int max_launches) {
@@ -958,7 +1025,7 @@ ns_status ns_vcycle(ns_ctx* X, const double* r, double* z) {
   launch_d2f(L0.by, L0.byf, X->nv, X->st);
   launch_d2f(L0.bz, L0.bzf, X->nw, X->st);
   prepare_hierarchy(X);
-  precond(X, r, z);
+  precond_launch(X, r, z);   // caller pointers: launched, never recorded
   HIPCHK(X, hipGetLastError());
   return NS_OK;
 }

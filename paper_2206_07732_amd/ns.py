@@ -87,6 +87,7 @@ def lib() -> C.CDLL:
             "ns_buffer": ([vp, i, C.POINTER(vp), C.POINTER(C.c_size_t)], i),
             "ns_diagnostics": ([vp, C.POINTER(C.c_double)], i),
             "ns_num_levels": ([i, i, i], i),
+            "ns_set_launch_mode": ([vp, i], i),
             "ns_timing_enable": ([vp, i, i], i),
             "ns_timing_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int)], i),
             "ns_time_kernel": ([vp, i, i, C.POINTER(C.c_double)], i),
@@ -117,12 +118,13 @@ def lib() -> C.CDLL:
 
 EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
             "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
-            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_timing_enable",
+            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_set_launch_mode", "ns_timing_enable",
             "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
             "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
+LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 
 SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2, coarse_sweeps=10,
                        max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV, p_scale=0.0)
@@ -266,6 +268,11 @@ class Solver:
                  "by": (nz, ny + 1, nx), "ws": (nz + 1, ny, nx), "bz": (nz + 1, ny, nx)}.get(
             key, (nz, ny, nx))
         return flat.view(shape)
+
+    def set_launch_mode(self, mode: int):
+        """LAUNCH_GRAPH (default): each V-cycle of the CG loop is one replay of
+        a recorded HIP graph; LAUNCH_STREAM: its kernels launched one by one."""
+        self._chk("ns_set_launch_mode", lib().ns_set_launch_mode(self.ctx, mode))
 
     def timing_enable(self, kernel: int, max_launches: int):
         self._chk("ns_timing_enable", lib().ns_timing_enable(self.ctx, kernel, max_launches))
