@@ -183,16 +183,18 @@ ns_status ns_buffer(ns_ctx* ctx, int which, void** dev_ptr, size_t* count);
  * out is host memory; synchronises the stream. */
 ns_status ns_diagnostics(ns_ctx* ctx, double out[4]);
 
-/* How the CG loop issues its preconditioner (one V-cycle per iteration).
- * NS_LAUNCH_GRAPH (the default): the V-cycle's kernels are recorded once per
- * context into a HIP graph for each vector pair the loop uses, and each
- * application is one graph launch on the context's stream; the kernels and
- * their arguments are those of NS_LAUNCH_STREAM, which launches them one by
- * one.  Results are bitwise the same either way; the graph saves host time
- * per kernel.  Recording happens on the first solve after the mode is set
- * (it runs nothing); the graphs live until ns_destroy.  While kernel timing
- * is enabled the loop launches kernel by kernel.  NS_EINVAL for another
- * value. */
+/* How the CG loop issues its preconditioner.  Each V-cycle, with the dot
+ * product that follows it, is a segment of some thirty kernels.
+ * NS_LAUNCH_GRAPH (the default): each segment is recorded once per context
+ * into a HIP graph for each set of vectors the loop uses it with (at most
+ * 16 graphs; recording runs nothing, and the graphs live until ns_destroy),
+ * and every later use is one graph launch on the context's stream.
+ * NS_LAUNCH_STREAM: the same kernels with the same arguments launched one by
+ * one, so results are bitwise the same in both modes.  A graph launch saves
+ * the host some thirty kernel launches for a fixed device-side cost of a few
+ * microseconds, which keeps the device fed on slow hosts.  While kernel
+ * timing is enabled the loop launches kernel by kernel.  NS_EINVAL for
+ * another value. */
 typedef enum {
   NS_LAUNCH_STREAM = 0,
   NS_LAUNCH_GRAPH = 1

@@ -41,11 +41,14 @@ struct ns_ctx {
   int launch_mode;    // ns_launch_mode
   hipStream_t cap_st; // capture-only stream: the V-cycle graphs are recorded on it
   struct {
-    const double* r;
-    double* z;
+    int kind;
+    const void* a;
+    const void* b;
+    const void* c;
+    int flag;
     hipGraphExec_t exec;
-  } pg[2];            // V-cycle graphs, one per (r, z) pair the CG loop uses
-  int npg;
+  } gs[16];           // recorded CG segments, keyed by kind and vectors
+  int ngs;
   ns_net* net;        // learned guess (not owned)
   int tail64, tail32; // first level of the LDS tail per precision (L: none)
   size_t lds64, lds32;
@@ -508,45 +511,49 @@ void precond_launch(ns_ctx* X, const double* r, double* z) {
   }
 }
 
-// Record precond_launch(r, z) as a graph. Nothing runs: the kernels are
-// captured on the context's capture-only stream, with every argument
-// (level buffers, tail descriptor, r and z) fixed for the context's life.
-ns_status capture_precond(ns_ctx* X, const double* r, double* z, hipGraphExec_t* exec) {
-  hipStream_t run = X->st;
-  X->st = X->cap_st;
-  hipError_t e = hipStreamBeginCapture(X->cap_st, hipStreamCaptureModeRelaxed);
-  if (e == hipSuccess) {
-    precond_launch(X, r, z);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(X->cap_st, &g);
-    if (e == hipSuccess) {
-      e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-    }
-  }
-  X->st = run;
-  if (e != hipSuccess) return fail(X, NS_EHIP, "V-cycle graph capture: %s", hipGetErrorString(e));
-  return NS_OK;
-}
+// The CG loop's V-cycles, each with the dot product that follows it, are
+// issued as segments. In graph mode a segment is recorded once per context
+// and key (kind, the vectors it works on, a flag) and replayed with one
+// hipGraphLaunch: one host call instead of some thirty kernel launches, for
+// a fixed device-side cost per graph launch of a few microseconds. Recording
+// runs nothing, on the context's capture-only stream, and every other
+// argument is fixed for the context's life. In stream mode, or while a kernel
+// is being timed, the segment's kernels are launched one by one. `launch`
+// issues them on X->st.
+enum SegKind { SEG_PRECOND_RHO = 1, SEG_PRECOND_BETA = 2 };
 
-// z = M r: a replay of the recorded V-cycle for this (r, z) in graph mode,
-// else (stream mode, or while a kernel is being timed) the kernels one by one
-ns_status precond(ns_ctx* X, const double* r, double* z) {
+template <class F>
+ns_status issue(ns_ctx* X, int kind, const void* a, const void* b, const void* c, int flag, F&& launch) {
   if (X->launch_mode == NS_LAUNCH_GRAPH && X->timed_kernel < 0) {
-    hipGraphExec_t exec = nullptr;
-    for (int q = 0; q < X->npg; ++q)
-      if (X->pg[q].r == r && X->pg[q].z == z) exec = X->pg[q].exec;
-    if (!exec && X->npg < 2) {
-      ns_status s = capture_precond(X, r, z, &exec);
-      if (s != NS_OK) return s;
-      X->pg[X->npg++] = {r, z, exec};
+    for (int q = 0; q < X->ngs; ++q) {
+      const auto& g = X->gs[q];
+      if (g.kind == kind && g.a == a && g.b == b && g.c == c && g.flag == flag) {
+        HIPCHK(X, hipGraphLaunch(g.exec, X->st));
+        return NS_OK;
+      }
     }
-    if (exec) {
+    if (X->ngs < (int)(sizeof(X->gs) / sizeof(X->gs[0]))) {
+      hipStream_t run = X->st;
+      X->st = X->cap_st;
+      hipGraphExec_t exec = nullptr;
+      hipError_t e = hipStreamBeginCapture(X->cap_st, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        launch();
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(X->cap_st, &g);
+        if (e == hipSuccess) {
+          e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+        }
+      }
+      X->st = run;
+      if (e != hipSuccess) return fail(X, NS_EHIP, "CG segment graph capture: %s", hipGetErrorString(e));
+      X->gs[X->ngs++] = {kind, a, b, c, flag, exec};
       HIPCHK(X, hipGraphLaunch(exec, X->st));
       return NS_OK;
     }
   }
-  precond_launch(X, r, z);
+  launch();
   HIPCHK(X, hipGetLastError());
   return NS_OK;
 }
@@ -571,6 +578,11 @@ ns_status read_scal(ns_ctx* X) {
   return NS_OK;
 }
 
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
 // flexible PCG on A p = b with x = fields.p as the initial guess.
 //
 // The host reads ||r||^2 once per iteration. While it waits, the device is
@@ -592,14 +604,36 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   double* zn = X->zn;
   double* d = X->d;
   double* dn = X->d2;
+  // segments: z = M r then rho = <r, z>; zn = M r then beta and rho;
+  // then d = z + beta d, q = A d, alpha, x += alpha d, r -= alpha q, ||r||^2
+  auto precond_rho = [&](double* zz) {
+    return issue(X, SEG_PRECOND_RHO, zz, nullptr, nullptr, 0, [&] {
+      precond_launch(X, X->r, zz);
+      launch_dot_rho(n, X->r, zz, cs, X->st);
+    });
+  };
+  auto precond_beta = [&](double* znew, const double* zold) {
+    return issue(X, SEG_PRECOND_BETA, znew, zold, nullptr, 0, [&] {
+      precond_launch(X, X->r, znew);
+      launch_dots_beta(n, X->r, znew, zold, cs, X->st);
+    });
+  };
+  // (four kernels: launched directly, a graph launch would cost the device
+  // more than it saves the host)
+  auto dir_update = [&](const double* zz, const double* dold, double* dnew, int first) {
+    launch_dir_spmv(n, h, L0.bx, L0.by, L0.bz, zz, dold, dnew, X->q, first, cs, X->st,
+                    X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr);
+    launch_cg_update(n, dnew, X->q, x, X->r, cs, X->st);
+    HIPCHK(X, hipGetLastError());
+    return NS_OK;
+  };
   prepare_hierarchy(X);
   launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
   HIPCHK(X, hipEventRecord(X->ev_rr, st));
   // first direction d = z = M r, rho = <r, z>, queued before the host has
   // seen ||b|| and ||r||; unused if b = 0 or the guess already converges
-  ns_status s = precond(X, X->r, z);
+  ns_status s = precond_rho(z);
   if (s != NS_OK) return s;
-  launch_dot_rho(n, X->r, z, cs, st);
   HIPCHK(X, hipEventSynchronize(X->ev_rr));
   const double bb = X->host[S_BB];
   double rr = X->host[S_RR];
@@ -619,21 +653,16 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   int it = 0;
   bool first = true;
   while (!conv && it < P.max_iters) {
-    // d = z + beta d (or z), q = A d, alpha = rho / <d, q>
-    launch_dir_spmv(n, h, L0.bx, L0.by, L0.bz, z, d, dn, X->q, first ? 1 : 0, cs, st,
-                    X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr);
+    // d = z + beta d (or z), q = A d, alpha = rho / <d, q>, then x and r
+    if ((s = dir_update(z, d, dn, first ? 1 : 0)) != NS_OK) return s;
     std::swap(d, dn);
     first = false;
-    launch_cg_update(n, d, X->q, x, X->r, cs, st);
     ++it;
     HIPCHK(X, hipEventRecord(X->ev_rr, st));
     // the residual this iteration is expected to reach, at the rate of the last one
     const bool likely_done = rr_prev > 0.0 && rr * (rr / rr_prev) <= tol2;
     const bool ahead = it < P.max_iters && !likely_done;
-    if (ahead) {
-      if ((s = precond(X, X->r, zn)) != NS_OK) return s;
-      launch_dots_beta(n, X->r, zn, z, cs, st);
-    }
+    if (ahead && (s = precond_beta(zn, z)) != NS_OK) return s;
     HIPCHK(X, hipEventSynchronize(X->ev_rr));
     rr_prev = rr;
     rr = X->host[S_RR];
@@ -654,17 +683,13 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
         break;
       }
       if (it >= P.max_iters) break;
-      if ((s = precond(X, X->r, z)) != NS_OK) return s;
-      launch_dot_rho(n, X->r, z, cs, st);
+      if ((s = precond_rho(z)) != NS_OK) return s;
       first = true;
       rr_prev = 0.0;
       continue;
     }
     if (it >= P.max_iters) break;
-    if (!ahead) {
-      if ((s = precond(X, X->r, zn)) != NS_OK) return s;
-      launch_dots_beta(n, X->r, zn, z, cs, st);
-    }
+    if (!ahead && (s = precond_beta(zn, z)) != NS_OK) return s;
     std::swap(z, zn);
   }
   if (!conv) {
@@ -682,10 +707,6 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   return NS_OK;
 }
 
-double now_ms() {
-  using namespace std::chrono;
-  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
 
 bool aligned8(const void* p) { return p && ((uintptr_t)p & 7) == 0; }
 
@@ -782,7 +803,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     return NS_EHIP;
   }
   X->launch_mode = NS_LAUNCH_GRAPH;
-  X->npg = 0;
+  X->ngs = 0;
   X->have_beta = false;
   X->timed_kernel = -1;
   X->kt = KTimer{nullptr, 0, 0};
@@ -803,7 +824,7 @@ static void free_timer(ns_ctx* X) {
 void ns_destroy(ns_ctx* X) {
   if (!X) return;
   free_timer(X);
-  for (int q = 0; q < X->npg; ++q) (void)hipGraphExecDestroy(X->pg[q].exec);
+  for (int q = 0; q < X->ngs; ++q) (void)hipGraphExecDestroy(X->gs[q].exec);
   if (X->cap_st) (void)hipStreamDestroy(X->cap_st);
   if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
   if (X->host) (void)hipHostFree(X->host);

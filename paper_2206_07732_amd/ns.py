@@ -118,8 +118,8 @@ def lib() -> C.CDLL:
 
 EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
             "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
-            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_set_launch_mode", "ns_timing_enable",
-            "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
+            "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_set_launch_mode",
+            "ns_timing_enable", "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
             "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target"]
@@ -270,8 +270,9 @@ class Solver:
         return flat.view(shape)
 
     def set_launch_mode(self, mode: int):
-        """LAUNCH_GRAPH (default): each V-cycle of the CG loop is one replay of
-        a recorded HIP graph; LAUNCH_STREAM: its kernels launched one by one."""
+        """LAUNCH_GRAPH (default): each V-cycle of the CG loop, with the dot
+        product after it, is one replay of a recorded HIP graph;
+        LAUNCH_STREAM: the same kernels launched one by one."""
         self._chk("ns_set_launch_mode", lib().ns_set_launch_mode(self.ctx, mode))
 
     def timing_enable(self, kernel: int, max_launches: int):

@@ -275,17 +275,18 @@ def test_bitwise_deterministic(name, prec):
 
 @pytest.mark.parametrize("name,prec", [("ragged3d", 0), ("odd1level", 0), ("c2", 0), ("c2", 1)])
 def test_graph_replays_match_stream_launches(name, prec):
-    """The V-cycle replayed from a recorded HIP graph leaves, step after step,
-    bit for bit the state that the same kernels launched one by one leave.
-    Each step replays each graph about a dozen times, with the CG loop's own
-    kernels and host waits between the replays; the modes are then swapped
-    on the live contexts."""
+    """The CG loop's V-cycles replayed from recorded HIP graphs leave, step
+    after step, bit for bit the state that the same kernels launched one by
+    one leave. Each step replays each graph about a dozen times, with the
+    step's other kernels and host waits between the replays; the modes are
+    then swapped on the live contexts."""
     ns = _ns()
     wl = case(name)
     f = I.make_fields(wl)
     dt = I.cfl_dt(wl, f)
     Sg, dg = make_solver(wl, f, prec=prec)
     Ss, ds = make_solver(wl, f, prec=prec)
+    Sg.set_launch_mode(ns.LAUNCH_GRAPH)
     Ss.set_launch_mode(ns.LAUNCH_STREAM)
     for s in range(5):
         if s == 4:
