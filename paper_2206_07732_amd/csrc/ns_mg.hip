@@ -517,37 +517,58 @@ struct TailLevel {
     T* rs = sm + D.ors;   // scratch: the fine residual
     const T ih2 = (T)1 / D.h2[l];
     const T inv = (T)1 / (T)(fx * fy * fz);
-    const int N = nf.nx * nf.ny * nf.nz, Nc = nc.nx * nc.ny * nc.nz;
     const int sxy = nf.nx * nf.ny;
-    // every fine cell's residual b - A e, one thread per cell ...
-    for (int c = tid; c < N; c += nthr) {
-      const int i = c % nf.nx, j = (c / nf.nx) % nf.ny, k = c / sxy;
-      const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
-      const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
-      const T xc = e[c];
-      const bool w = i > 0, E = i < nf.nx - 1, S = j > 0, N2 = j < nf.ny - 1, d = k > 0, u = k < nf.nz - 1;
-      const T tw = bx[ix] * (xc - e[w ? c - 1 : c]), te = bx[ix + 1] * (xc - e[E ? c + 1 : c]);
-      const T ts = by[iy] * (xc - e[S ? c - nf.nx : c]), tn = by[iy + nf.nx] * (xc - e[N2 ? c + nf.nx : c]);
-      const T td = bz[c] * (xc - e[d ? c - sxy : c]);
-      const T tu = u ? bz[c + sxy] * (xc - e[u ? c + sxy : c]) : (T)2 * bz[c + sxy] * xc;
-      T acc = 0;
-      if (w) acc += tw;
-      if (E) acc += te;
-      if (S) acc += ts;
-      if (N2) acc += tn;
-      if (d) acc += td;
-      acc += tu;
-      rs[c] = b[c] - ih2 * acc;
+    // every fine cell's residual b - A e, each thread for both cells of its
+    // pairs ...
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= tp.np) break;
+      const int j = tp.j[q], k = tp.k[q];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 2 * tp.ti[q] + h;
+        if (i < nf.nx) {
+          const int c = i + nf.nx * j + sxy * k;
+          const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
+          const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
+          const T xc = e[c];
+          const bool w = i > 0, E = i < nf.nx - 1, S = j > 0, N2 = j < nf.ny - 1, d = k > 0, u = k < nf.nz - 1;
+          const T tw = bx[ix] * (xc - e[w ? c - 1 : c]), te = bx[ix + 1] * (xc - e[E ? c + 1 : c]);
+          const T ts = by[iy] * (xc - e[S ? c - nf.nx : c]), tn = by[iy + nf.nx] * (xc - e[N2 ? c + nf.nx : c]);
+          const T td = bz[c] * (xc - e[d ? c - sxy : c]);
+          const T tu = u ? bz[c + sxy] * (xc - e[u ? c + sxy : c]) : (T)2 * bz[c + sxy] * xc;
+          T acc = 0;
+          if (w) acc += tw;
+          if (E) acc += te;
+          if (S) acc += ts;
+          if (N2) acc += tn;
+          if (d) acc += td;
+          acc += tu;
+          rs[c] = b[c] - ih2 * acc;
+        }
+      }
     }
     tail_sync<WAVE>();
-    // ... then each coarse cell's mean of its children, summed in the order (dk, dj, di)
-    for (int C = tid; C < Nc; C += nthr) {
-      const int I = C % nc.nx, J = (C / nc.nx) % nc.ny, K = C / (nc.nx * nc.ny);
-      T sum = 0;
-      for (int dk = 0; dk < fz; ++dk)
-        for (int dj = 0; dj < fy; ++dj)
-          for (int di = 0; di < fx; ++di) sum += rs[(fx * I + di) + nf.nx * ((fy * J + dj) + nf.ny * (fz * K + dk))];
-      bc[C] = sum * inv;
+    // ... then each coarse cell's mean of its children, summed in the order
+    // (dk, dj, di) by the thread whose pair is the cell's (dj, dk) = (0, 0)
+    // corner: a level that is restricted has an even nx, so a pair (ti, j, k)
+    // is exactly the two x-children of coarse column ti (fx = 2; fy, fz are
+    // 1 along a dimension of one cell, else 2)
+    const int sy = fy - 1, sz = fz - 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= tp.np) break;
+      const int ti = tp.ti[q], j = tp.j[q], k = tp.k[q];
+      if ((j & sy) == 0 && (k & sz) == 0) {
+        T sum = 0;
+        for (int dk = 0; dk < fz; ++dk)
+          for (int dj = 0; dj < fy; ++dj) {
+            const int f = 2 * ti + nf.nx * (j + dj) + sxy * (k + dk);
+            sum += rs[f];
+            sum += rs[f + 1];
+          }
+        bc[ti + nc.nx * ((j >> sy) + nc.ny * (k >> sz))] = sum * inv;
+      }
     }
     tail_sync<WAVE>();
   }
@@ -604,20 +625,25 @@ struct TailLevel {
     tail_sync<WAVE>();
   }
 
-  // prolongation of the next level's correction, then post-smoothing
+  // prolongation of the next level's correction (both cells of a pair share
+  // one coarse cell: fx = 2), then post-smoothing
   __device__ void up(int l) const {
     const Dims nf = D.n[l], nc = D.n[l + 1];
-    const int fx = D.f[l][0], fy = D.f[l][1], fz = D.f[l][2];
+    const int sy = D.f[l][1] - 1, sz = D.f[l][2] - 1;
     T* e = sm + D.oe[l];
     const T* ec = sm + D.oe[l + 1];
-    const int N = nf.nx * nf.ny * nf.nz;
-    for (int c = tid; c < N; c += nthr) {
-      const int i = c % nf.nx, j = (c / nf.nx) % nf.ny, k = c / (nf.nx * nf.ny);
-      e[c] += ec[(i / fx) + nc.nx * ((j / fy) + nc.ny * (k / fz))];
-    }
-    tail_sync<WAVE>();
     TailPairs tp;
     tail_decode(nf, tid, nthr, tp);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= tp.np) break;
+      const int ti = tp.ti[q], j = tp.j[q], k = tp.k[q];
+      const T add = ec[ti + nc.nx * ((j >> sy) + nc.ny * (k >> sz))];
+      const int c = 2 * ti + nf.nx * (j + nf.ny * k);
+      e[c] += add;
+      if (2 * ti + 1 < nf.nx) e[c + 1] += add;
+    }
+    tail_sync<WAVE>();
     smooth(l, tp, 1, D.nu_post, false);
   }
 };
