@@ -99,9 +99,10 @@ __global__ void __launch_bounds__(256) k_advect(Phys P, const double* __restrict
                                                 const double* __restrict__ w, double dt,
                                                 double* __restrict__ out) {
   const Dims n = P.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
@@ -141,9 +142,10 @@ __global__ void __launch_bounds__(256) k_reinit(Phys P, const double* __restrict
                                                 const double* __restrict__ cur,
                                                 double* __restrict__ nxt, double dtau) {
   const Dims n = P.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
@@ -193,9 +195,10 @@ __global__ void __launch_bounds__(256) k_props(Phys P, const double* __restrict_
                                                double* __restrict__ rho, double* __restrict__ rfl,
                                                double* __restrict__ mu, double* __restrict__ chi) {
   const Dims n = P.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t c = i + (size_t)n.nx * (j + (size_t)n.ny * k);
   double zd;
@@ -272,9 +275,10 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
   const Dims n = P.n;
   constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
   const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= mx || j >= my || k >= mz) return;
   const size_t f = i + (size_t)mx * (j + (size_t)my * k);
   const bool wall = (C == 0) ? (i == 0 || i == n.nx) : (C == 1) ? (j == 0 || j == n.ny) : (k == 0);
@@ -311,9 +315,10 @@ __global__ void __launch_bounds__(256) k_rhs(Phys P, const double* __restrict__ 
                                              const double* __restrict__ ws, double scale,
                                              double* __restrict__ b) {
   const Dims n = P.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
@@ -332,9 +337,10 @@ __global__ void __launch_bounds__(256) k_correct(Phys P, const double* __restric
   const Dims n = P.n;
   constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
   const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= mx || j >= my || k >= mz) return;
   const size_t f = i + (size_t)mx * (j + (size_t)my * k);
   const bool wall = (C == 0) ? (i == 0 || i == n.nx) : (C == 1) ? (j == 0 || j == n.ny) : (k == 0);
@@ -359,9 +365,10 @@ __global__ void __launch_bounds__(256) k_diag(Phys P, const double* __restrict__
                                               const double* __restrict__ w,
                                               double* __restrict__ partials) {
   const Dims n = P.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   double vals[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < n.nx && j < n.ny && k < n.nz) {
     const size_t sxy = (size_t)n.nx * n.ny;
@@ -394,7 +401,7 @@ __global__ void __launch_bounds__(256) k_diag(Phys P, const double* __restrict__
     for (int q = 0; q < 4; ++q) sm[wid][q] = vals[q];
   __syncthreads();
   if (tid == 0) {
-    const size_t blk = blockIdx.x + gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+    const size_t blk = tl.lin;
     partials[4 * blk + 0] = fmax(fmax(sm[0][0], sm[1][0]), fmax(sm[2][0], sm[3][0]));
     partials[4 * blk + 1] = (sm[0][1] + sm[1][1]) + (sm[2][1] + sm[3][1]);
     partials[4 * blk + 2] = (sm[0][2] + sm[1][2]) + (sm[2][2] + sm[3][2]);

@@ -11,6 +11,30 @@
 
 namespace nsk {
 
+// The tile (block coordinates in the launch grid) a workgroup works on.
+// Workgroups are handed to the eight XCDs round-robin by linear id, and each
+// XCD has its own L2; this gives XCD x the contiguous run of tiles
+// [start(x), start(x + 1)) in x-fastest tile order, so that tiles sharing
+// halo rows and planes mostly share an L2.  It is a bijection for any grid,
+// so no result depends on the dispatch order.  lin is the tile's linear
+// index, which also numbers its reduction partial.
+struct Tile {
+  int x, y, z, lin;
+};
+__device__ __forceinline__ Tile xcd_tile() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nb = gx * gy * (int)gridDim.z;
+  const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  Tile t;
+  t.lin = x * q + (x < r ? x : r) + (b >> 3);
+  t.x = t.lin % gx;
+  const int yz = t.lin / gx;
+  t.y = yz % gy;
+  t.z = yz / gy;
+  return t;
+}
+
 struct Dims {
   int nx, ny, nz;
 };

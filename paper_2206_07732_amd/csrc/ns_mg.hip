@@ -90,14 +90,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   __syncthreads();
 }
 
-// write the block's NV sums to partials[NV * block + q] (thread 0)
+// write the block's NV sums to partials[NV * slot + q] (thread 0); slot is
+// the block's tile index, so the partials lie in tile order
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ partials) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ partials, int slot) {
   block_sum<NV>(v);
   if (block_tid() == 0) {
-    const size_t blk = blockIdx.x + gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) partials[NV * blk + q] = v[q];
+    for (int q = 0; q < NV; ++q) partials[NV * (size_t)slot + q] = v[q];
   }
 }
 
@@ -126,15 +126,16 @@ __device__ __forceinline__ size_t lidx(const Dims& n, const SplitGeo& g, bool sp
 
 // Threads own cell pairs (2ti, 2ti+1) of a row; the red cell of the pair is
 // 2ti + ((j+k) & 1), the black one the other; pos is the pair index.
-#define PAIR_INDEX                                           \
-  const int ti = blockIdx.x * blockDim.x + threadIdx.x;      \
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;       \
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;       \
-  if (j >= n.ny || k >= n.nz) return;                        \
-  const SplitGeo sg = split_geo(n);                          \
-  if (ti >= sg.hx) return;                                   \
-  const size_t sxy = (size_t)n.nx * n.ny;                    \
-  const size_t row = (size_t)n.nx * j + sxy * k;             \
+#define PAIR_INDEX                                                        \
+  const Tile tl = xcd_tile();                                             \
+  const int ti = tl.x * blockDim.x + threadIdx.x;                         \
+  const int j = tl.y * blockDim.y + threadIdx.y;                          \
+  const int k = tl.z * blockDim.z + threadIdx.z;                          \
+  if (j >= n.ny || k >= n.nz) return;                                     \
+  const SplitGeo sg = split_geo(n);                                       \
+  if (ti >= sg.hx) return;                                                \
+  const size_t sxy = (size_t)n.nx * n.ny;                                 \
+  const size_t row = (size_t)n.nx * j + sxy * k;                          \
   const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k)
 
 // Gauss-Seidel value of cell (i, j, k) with pair index pos: (h^2 b + sum over
@@ -286,7 +287,8 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
   __shared__ T sr[256];
   const int TX = blockDim.x, TY = blockDim.y;
   const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
-  const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty, k = blockIdx.z * blockDim.z + tz;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * TX + tx, j = tl.y * TY + ty, k = tl.z * blockDim.z + tz;
   const SplitGeo sg = split_geo(nf);
   const size_t sxy = (size_t)nf.nx * nf.ny;
   T r = 0;
@@ -314,7 +316,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
   const int CX = TX / fx, CY = TY / fy, CZ = (int)blockDim.z / fz;
   if (t >= CX * CY * CZ) return;
   const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
-  const int I = blockIdx.x * CX + cx, J = blockIdx.y * CY + cy, K = blockIdx.z * CZ + cz;
+  const int I = tl.x * CX + cx, J = tl.y * CY + cy, K = tl.z * CZ + cz;
   if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
   T sum = 0;
   for (int dk = 0; dk < fz; ++dk)
@@ -328,9 +330,10 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong(Dims nf, int sx, int sy, int sz, T* __restrict__ e, Dims nc,
                                                  int csplit, const T* __restrict__ ec) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= nf.nx || j >= nf.ny || k >= nf.nz) return;
   const SplitGeo sg = split_geo(nf), cg = split_geo(nc);
   e[sidx(nf, sg, i, j, k)] += ec[lidx(nc, cg, csplit != 0, i >> sx, j >> sy, k >> sz)];
@@ -340,9 +343,10 @@ __global__ void __launch_bounds__(256) k_prolong(Dims nf, int sx, int sy, int sz
 template <typename T>
 __global__ void __launch_bounds__(256) k_split_copy(Dims n, const T* __restrict__ src, T* __restrict__ dst,
                                                     int to_split) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const SplitGeo sg = split_geo(n);
   const size_t c = i + (size_t)n.nx * (j + (size_t)n.ny * k), s = sidx(n, sg, i, j, k);
@@ -357,9 +361,10 @@ __global__ void __launch_bounds__(256) k_split_copy(Dims n, const T* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ bx, const T* __restrict__ by,
                                                  const T* __restrict__ bz, int split, T* __restrict__ invd) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
@@ -376,9 +381,10 @@ __global__ void __launch_bounds__(256) k_coarsen_beta(Dims nf, int fx, int fy, i
                                                       const T* __restrict__ fb, Dims nc,
                                                       T* __restrict__ cb) {
   const int mx = nc.nx + (C == 0), my = nc.ny + (C == 1), mz = nc.nz + (C == 2);
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
-  const int K = blockIdx.z * blockDim.z + threadIdx.z;
+  const Tile tl = xcd_tile();
+  const int I = tl.x * blockDim.x + threadIdx.x;
+  const int J = tl.y * blockDim.y + threadIdx.y;
+  const int K = tl.z * blockDim.z + threadIdx.z;
   if (I >= mx || J >= my || K >= mz) return;
   const int fmx = nf.nx + (C == 0), fmy = nf.ny + (C == 1);
   const int ni = (C == 0) ? 1 : fx, nj = (C == 1) ? 1 : fy, nk = (C == 2) ? 1 : fz;
@@ -713,11 +719,12 @@ __global__ void k_f2d(const float* __restrict__ a, double* __restrict__ b, size_
 }
 
 // ------------------------------------------------------------------ CG (FP64)
-#define CELL_INDEX                                              \
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;          \
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;          \
-  const int k = blockIdx.z * blockDim.z + threadIdx.z;          \
-  const bool inside = (i < n.nx && j < n.ny && k < n.nz);       \
+#define CELL_INDEX                                                         \
+  const Tile tl = xcd_tile();                                              \
+  const int i = tl.x * blockDim.x + threadIdx.x;                           \
+  const int j = tl.y * blockDim.y + threadIdx.y;                           \
+  const int k = tl.z * blockDim.z + threadIdx.z;                           \
+  const bool inside = (i < n.nx && j < n.ny && k < n.nz);                  \
   const size_t c = inside ? i + (size_t)n.nx * (j + (size_t)n.ny * k) : 0
 
 // r = b - A x; totals (r.r, b.b) -> scal (RESID0: S_RR, S_BB; TRR: S_TRR)
@@ -737,7 +744,7 @@ __global__ void __launch_bounds__(256) k_resid_norm(Dims n, double ih2, const do
     v[0] = rc * rc;
     v[1] = bc * bc;
   }
-  block_partials<2>(v, partials);
+  block_partials<2>(v, partials, tl.lin);
 }
 
 // rho = <r, z>
@@ -745,7 +752,7 @@ __global__ void __launch_bounds__(256) k_dot_rho(Dims n, const double* __restric
                                                  const double* __restrict__ z, double* __restrict__ partials) {
   CELL_INDEX;
   double v[1] = {inside ? r[c] * z[c] : 0.0};
-  block_partials<1>(v, partials);
+  block_partials<1>(v, partials, tl.lin);
 }
 
 // flexible (Polak-Ribiere) beta = (<r, zn> - <r, z>) / rho, then rho = <r, zn>
@@ -760,7 +767,7 @@ __global__ void __launch_bounds__(256) k_dots_beta(Dims n, const double* __restr
     v[0] = rc * zn[c];
     v[1] = rc * z[c];
   }
-  block_partials<2>(v, partials);
+  block_partials<2>(v, partials, tl.lin);
 }
 
 // d = zn + beta d_old (first: d = zn); q = A d; alpha = rho / <d, q>
@@ -792,7 +799,7 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
     q[c] = qc;
     v[0] = dc * qc;
   }
-  block_partials<1>(v, partials);
+  block_partials<1>(v, partials, tl.lin);
 }
 
 // x += alpha d; r -= alpha q; ||r||^2
@@ -809,7 +816,7 @@ __global__ void __launch_bounds__(256) k_cg_update(Dims n, const double* __restr
     r[c] = rc;
     v[0] = rc * rc;
   }
-  block_partials<1>(v, partials);
+  block_partials<1>(v, partials, tl.lin);
 }
 
 __global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const double* __restrict__ bx,
