@@ -34,6 +34,8 @@ struct ns_ctx {
   Level lev[32];
   double* host;       // pinned, coherent host mirror of the scalars
   double* host_dev;   // its device address
+  double* hpart;      // pinned, coherent host partials (nparts <= kHostPartsMax), or null
+  double* hpart_dev;  // their device address
   bool have_beta;
   int timed_kernel;   // -1 or an ns_timed_kernel id
   KTimer kt;
@@ -565,6 +567,17 @@ void prepare_hierarchy(ns_ctx* X) {
     build_hierarchy<float>(X);
 }
 
+// Totals of a reduction the host reads: summed here, in block order, from the
+// host partials when the grid is small enough to have them, else as the
+// finalize kernel stored them to the mirror. q selects the value (0 or 1) of
+// an nv-valued reduction; mirror_slot is its S_* index.
+double host_total(const ns_ctx* X, int nv, int q, int mirror_slot) {
+  if (!X->hpart) return X->host[mirror_slot];
+  double s = 0.0;
+  for (int b = 0; b < X->nparts; ++b) s += X->hpart[(size_t)nv * b + q];
+  return s;
+}
+
 // wait until the work queued so far has stored its scalars to the host mirror
 ns_status wait_host(ns_ctx* X) {
   HIPCHK(X, hipEventRecord(X->ev_rr, X->st));
@@ -598,7 +611,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   const Level& L0 = X->lev[0];
   hipStream_t st = X->st;
   double* x = X->F.p;
-  const CgScratch cs{X->partials, X->scal, X->host_dev};
+  const CgScratch cs{X->partials, X->scal, X->host_dev, X->hpart_dev};
   ns_stats S{};
   double* z = X->z;
   double* zn = X->zn;
@@ -635,8 +648,8 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   ns_status s = precond_rho(z);
   if (s != NS_OK) return s;
   HIPCHK(X, hipEventSynchronize(X->ev_rr));
-  const double bb = X->host[S_BB];
-  double rr = X->host[S_RR];
+  const double bb = host_total(X, 2, 1, S_BB);
+  double rr = host_total(X, 2, 0, S_RR);
   if (!std::isfinite(bb) || !std::isfinite(rr)) return fail(X, NS_ENAN, "non-finite right-hand side or guess");
   if (bb == 0.0) {
     launch_fill<double>(x, X->nc, st);
@@ -665,7 +678,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     if (ahead && (s = precond_beta(zn, z)) != NS_OK) return s;
     HIPCHK(X, hipEventSynchronize(X->ev_rr));
     rr_prev = rr;
-    rr = X->host[S_RR];
+    rr = host_total(X, 1, 0, S_RR);
     if (!std::isfinite(rr)) {
       S.iters = it;
       if (stats) *stats = S;
@@ -676,7 +689,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
       // confirm on the true residual; restart from it when it fails
       launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
       if ((s = wait_host(X)) != NS_OK) return s;
-      rr = true_rr = X->host[S_RR];
+      rr = true_rr = host_total(X, 2, 0, S_RR);
       S.rel_resid = std::sqrt(rr) / bnorm;
       if (rr <= tol2) {
         conv = true;
@@ -696,7 +709,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     // true residual at exit (into q, leaving r as the recursion left it)
     launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st);
     if ((s = wait_host(X)) != NS_OK) return s;
-    true_rr = X->host[S_TRR];
+    true_rr = host_total(X, 2, 0, S_TRR);
   }
   S.iters = it;
   S.true_rel_resid = std::sqrt(true_rr) / bnorm;
@@ -791,6 +804,19 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     delete X;
     return NS_EHIP;
   }
+  // small grids: the reductions the host alone reads leave their per-block
+  // partials in host memory, and the host sums them (no finalize launch)
+  X->hpart = X->hpart_dev = nullptr;
+  if (X->nparts <= kHostPartsMax) {
+    if (hipHostMalloc((void**)&X->hpart, (size_t)2 * X->nparts * sizeof(double),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&X->hpart_dev, X->hpart, 0) != hipSuccess) {
+      if (X->hpart) (void)hipHostFree(X->hpart);
+      (void)hipHostFree(X->host);
+      delete X;
+      return NS_EHIP;
+    }
+  }
   if (hipEventCreateWithFlags(&X->ev_rr, hipEventDisableTiming) != hipSuccess) {
     (void)hipHostFree(X->host);
     delete X;
@@ -828,6 +854,7 @@ void ns_destroy(ns_ctx* X) {
   if (X->cap_st) (void)hipStreamDestroy(X->cap_st);
   if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
   if (X->host) (void)hipHostFree(X->host);
+  if (X->hpart) (void)hipHostFree(X->hpart);
   delete X;
 }
 

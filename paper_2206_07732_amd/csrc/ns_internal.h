@@ -125,7 +125,14 @@ struct CgScratch {
   double* scal;
   double* hscal;   // device address of the pinned host mirror of scal (the
                    // values the host tests: S_BB, S_RR, S_TRR)
+  double* hpart;   // device address of pinned host partials, or null: when
+                   // set, the reductions only the host reads (||r||^2,
+                   // ||b||^2, the true residual) leave their per-block
+                   // partials there for the host to sum, with no finalize
 };
+
+// the host sums the partials of its own reductions up to this many blocks
+constexpr int kHostPartsMax = 8192;
 
 // ---------------------------------------------------------------- launchers
 // grid step kernels (ns_grid.hip)

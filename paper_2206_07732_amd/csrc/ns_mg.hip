@@ -1018,8 +1018,8 @@ void launch_resid_norm(const Dims& n, double h, const double* bx, const double* 
                        hipStream_t st) {
   Geo g = geo3(n.nx, n.ny, n.nz);
   hipLaunchKernelGGL(k_resid_norm, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, b, x, r,
-                     cs.partials);
-  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), mode, st);
+                     cs.hpart ? cs.hpart : cs.partials);
+  if (!cs.hpart) finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), mode, st);
 }
 
 void launch_dot_rho(const Dims& n, const double* r, const double* z, const CgScratch& cs, hipStream_t st) {
@@ -1056,8 +1056,8 @@ void launch_cg_update(const Dims& n, const double* d, const double* q, double* x
                       const CgScratch& cs, hipStream_t st) {
   Geo g = geo3(n.nx, n.ny, n.nz);
   hipLaunchKernelGGL(k_cg_update, g.grid, g.block, 0, st, n, d, q, x, r, (const double*)cs.scal,
-                     cs.partials);
-  finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_RR, st);
+                     cs.hpart ? cs.hpart : cs.partials);
+  if (!cs.hpart) finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_RR, st);
 }
 
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
