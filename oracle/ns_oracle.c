@@ -77,6 +77,10 @@ static double heaviside(double phi, double eps) {
 static double body_psi_one(const orc_body* b, double x, double y, double z, double t, double* zdot) {
   double zeta = b->heave_amp * sin(b->heave_omega * t + b->heave_phase);
   *zdot = b->heave_amp * b->heave_omega * cos(b->heave_omega * t + b->heave_phase);
+  if (b->free_heave) {  /* heave from the body's own state (eqn_newton_u) */
+    zeta = b->zeta;
+    *zdot = b->zdot;
+  }
   if (b->kind == 0) {
     double dx = fabs(x - b->c[0]) - b->half[0];
     double dz = fabs(z - (b->c[2] + zeta)) - b->half[2];
@@ -670,4 +674,86 @@ void orc_diagnostics(const orc_params* P, const double* sigma, const double* u, 
   out4[1] = wv;
   out4[2] = ke;
   out4[3] = mu;
+}
+
+/* --------------------------------------------------------------------------
+ * Hydrodynamic force on body m, eqn_int_fh (Sec. "Fluid-structure coupling"):
+ *   F = sum over f of ( -p_f n_f + mu_f (grad u + grad u^T)_f . n_f ) dA_f
+ * over the faces of the stair-step body surface (Sec. "NLFK calculation",
+ * eqn_NLFK_p): a face belongs to it when the body's level set psi has
+ * opposite signs in the two cells the face separates.
+ *   n_f   unit normal out of the body: from the cell with psi < 0 to the other
+ *   p_f   the two cell pressures interpolated linearly to psi = 0, i.e.
+ *         weighted by the other cell's |psi|
+ *   mu_f  mean of the two cells' viscosity
+ *   grad  central differences at the face centre (MAC grid): a velocity
+ *         component's derivative across the face from the cell-centred means
+ *         of the two cells, a derivative of the face's own normal velocity
+ *         along the face from its two neighbours; indices clamp to the grid
+ *   dA_f  h^2 in 3-D, h in 2-D (per unit depth)
+ * In 2-D (ny == 1) the y-direction carries no faces and no derivatives.
+ * ------------------------------------------------------------------------ */
+
+/* cell-centred mean of velocity component c at cell (i,j,k) */
+static double vel_cell(const orc_params* P, int c, const double* vel, int i, int j, int k) {
+  int di = (c == 0), dj = (c == 1), dk = (c == 2);
+  return 0.5 * (facev(P, c, vel, i, j, k) + facev(P, c, vel, i + di, j + dj, k + dk));
+}
+
+void orc_hydro_force(const orc_params* P, int m, const double* p, const double* u, const double* v,
+                     const double* w, const double* mu, double t, double* F) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
+  const double h = P->h;
+  const double dA = (ny == 1) ? h : h * h;
+  const double* vel[3] = {u, v, w};
+  const orc_body* B = &P->body[m];
+  F[0] = F[1] = F[2] = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    if (d == 1 && ny == 1) continue;
+    const int di = (d == 0), dj = (d == 1), dk = (d == 2);
+    /* interior faces normal to d: between cell a = (i,j,k) - e_d and b = (i,j,k) */
+    for (int k = dk; k < nz; ++k)
+      for (int j = dj; j < ny; ++j)
+        for (int i = di; i < nx; ++i) {
+          const int ia = i - di, ja = j - dj, ka = k - dk;
+          double zd;
+          const double psa = body_psi_one(B, (ia + 0.5) * h, (ja + 0.5) * h, (ka + 0.5) * h, t, &zd);
+          const double psb = body_psi_one(B, (i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h, t, &zd);
+          if ((psa < 0.0) == (psb < 0.0)) continue;
+          const double nd = (psa < 0.0) ? 1.0 : -1.0;   /* out of the body along d */
+          const double pa = cellv(P, p, ia, ja, ka), pb = cellv(P, p, i, j, k);
+          const double pf = (fabs(psb) * pa + fabs(psa) * pb) / (fabs(psa) + fabs(psb));
+          const double muf = 0.5 * (cellv(P, mu, ia, ja, ka) + cellv(P, mu, i, j, k));
+          F[d] += -pf * nd * dA;
+          for (int c = 0; c < 3; ++c) {
+            if (c == 1 && ny == 1) continue;
+            double G;
+            if (c == d) {
+              /* 2 d(u_d)/dx_d at the face: neighbours of the face along d */
+              G = 2.0 * (facev(P, d, vel[d], i + di, j + dj, k + dk) - facev(P, d, vel[d], i - di, j - dj, k - dk)) /
+                  (2.0 * h);
+            } else {
+              const int ci = (c == 0), cj = (c == 1), ck = (c == 2);
+              /* d(u_c)/dx_d across the face, from the cell-centred means */
+              const double dcd = (vel_cell(P, c, vel[c], i, j, k) - vel_cell(P, c, vel[c], ia, ja, ka)) / h;
+              /* d(u_d)/dx_c along the face, from the face's neighbours along c */
+              const double ddc = (facev(P, d, vel[d], i + ci, j + cj, k + ck) -
+                                  facev(P, d, vel[d], i - ci, j - cj, k - ck)) / (2.0 * h);
+              G = dcd + ddc;
+            }
+            F[c] += muf * G * nd * dA;
+          }
+        }
+  }
+}
+
+/* Heave of a free body, eqn_newton_u with the linear-damper PTO force
+ * F_PTO = -c zdot^{n+1} taken at the new time level:
+ *   m (zdot^{n+1} - zdot^n) / dt = Fz - m g - c zdot^{n+1},
+ * then zeta^{n+1} = zeta^n + dt zdot^{n+1}. */
+void orc_heave_update(double mass, double pto_damping, double g, double dt, double fz, double* zeta,
+                      double* zdot) {
+  const double zn = (*zdot + dt * (fz - mass * g) / mass) / (1.0 + dt * pto_damping / mass);
+  *zdot = zn;
+  *zeta += dt * zn;
 }

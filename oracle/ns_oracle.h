@@ -25,6 +25,10 @@ typedef struct {
   double c[3];         /* box: (xc, -, zc); cylinder: (xc, yc, -)                  */
   double half[3];      /* box: (a, -, b) half-widths; cylinder: (R, z_bot, z_top)  */
   double heave_amp, heave_omega, heave_phase;  /* zeta(t) = A sin(w t + phi)     */
+  int free_heave;      /* 1: heave follows eqn_newton_u; zeta, zdot are its state  */
+  double mass;         /* m of eqn_newton_u (per unit depth in 2-D)                */
+  double pto_damping;  /* c of the linear-damper PTO force F_PTO = -c zdot         */
+  double zeta, zdot;   /* heave offset and velocity of a free body                 */
 } orc_body;
 
 typedef struct {
@@ -74,6 +78,12 @@ int  orc_step(const orc_params* P, double* sigma, double* u, double* v, double* 
               double dt, double t_n, int x0_prev, orc_stats* st);
 void orc_diagnostics(const orc_params* P, const double* sigma, const double* u, const double* v,
                      const double* w, double* out4);
+/* hydrodynamic force on body m (eqn_int_fh); mu: cell viscosity; F: (Fx, Fy, Fz) */
+void orc_hydro_force(const orc_params* P, int m, const double* p, const double* u, const double* v,
+                     const double* w, const double* mu, double t, double* F);
+/* heave update of a free body (eqn_newton_u, linear-damper PTO, implicit) */
+void orc_heave_update(double mass, double pto_damping, double g, double dt, double fz, double* zeta,
+                      double* zdot);
 
 #ifdef __cplusplus
 }

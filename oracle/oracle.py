@@ -30,7 +30,9 @@ def build(force: bool = True) -> str:
 
 class _Body(C.Structure):
     _fields_ = [("kind", C.c_int), ("c", C.c_double * 3), ("half", C.c_double * 3),
-                ("heave_amp", C.c_double), ("heave_omega", C.c_double), ("heave_phase", C.c_double)]
+                ("heave_amp", C.c_double), ("heave_omega", C.c_double), ("heave_phase", C.c_double),
+                ("free_heave", C.c_int), ("mass", C.c_double), ("pto_damping", C.c_double),
+                ("zeta", C.c_double), ("zdot", C.c_double)]
 
 
 class Params(C.Structure):
@@ -79,6 +81,8 @@ def lib():
             "orc_correct": [P, dp, dp, dp, dp, dp, dp, dp, d, dp, dp, dp],
             "orc_step": [P, dp, dp, dp, dp, dp, d, d, C.c_int, S],
             "orc_diagnostics": [P, dp, dp, dp, dp, dp],
+            "orc_hydro_force": [P, C.c_int, dp, dp, dp, dp, dp, d, dp],
+            "orc_heave_update": [d, d, d, d, d, dp, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -116,6 +120,9 @@ def params(wl, **solver) -> Params:
             P.body[m].half[q] = b.half[q]
         P.body[m].heave_amp, P.body[m].heave_omega, P.body[m].heave_phase = \
             b.heave_amp, b.heave_omega, b.heave_phase
+        P.body[m].free_heave, P.body[m].mass, P.body[m].pto_damping = \
+            int(b.free_heave), b.mass, b.pto_damping
+        P.body[m].zeta, P.body[m].zdot = b.zeta0, b.zdot0
     opts = dict(SOLVER_DEFAULTS)
     opts.update(solver)
     for k, v in opts.items():
@@ -219,3 +226,38 @@ def diagnostics(P, sigma, u, v, w):
     out = np.empty(4)
     lib().orc_diagnostics(C.byref(P), _p(sigma), _p(u), _p(v), _p(w), _p(out))
     return out   # max|div|, water volume, kinetic energy, max|u|
+
+
+def hydro_force(P, m, p, u, v, w, mu, t):
+    """(Fx, Fy, Fz) on body m (eqn_int_fh) from cell pressure p, face velocities
+    and cell viscosity mu; the body's heave as P holds it (or prescribed at t)."""
+    p, u, v, w, mu = map(_arr, (p, u, v, w, mu))
+    out = np.zeros(3)
+    lib().orc_hydro_force(C.byref(P), m, _p(p), _p(u), _p(v), _p(w), _p(mu), t, _p(out))
+    return out
+
+
+def heave_update(mass, pto_damping, g, dt, fz, zeta, zdot):
+    """One heave update of a free body (eqn_newton_u); returns (zeta, zdot)."""
+    z, zd = C.c_double(zeta), C.c_double(zdot)
+    lib().orc_heave_update(mass, pto_damping, g, dt, fz, C.byref(z), C.byref(zd))
+    return z.value, zd.value
+
+
+def step_fsi(P, fields, dt, t_n, x0_prev=True):
+    """One coupled step (Sec. "Fluid-structure coupling", one cycle): for every
+    free body, the force from the current state (viscosity from the properties
+    at t_n and the body's current heave), then its heave update; then the step
+    with psi and u_b from the new heave.  P's body states advance in place.
+    Returns (fields, stats, rc, {body: (Fx, Fy, Fz)})."""
+    forces = {}
+    free = [m for m in range(P.n_bodies) if P.body[m].free_heave]
+    if free:
+        _, _, mu, _ = properties(P, fields["sigma"], t_n)
+        for m in free:
+            F = hydro_force(P, m, fields["p"], fields["u"], fields["v"], fields["w"], mu, t_n)
+            forces[m] = F
+            B = P.body[m]
+            B.zeta, B.zdot = heave_update(B.mass, B.pto_damping, P.g, dt, F[2], B.zeta, B.zdot)
+    f, st, rc = step(P, fields, dt, t_n, x0_prev)
+    return f, st, rc, forces

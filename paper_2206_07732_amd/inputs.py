@@ -111,6 +111,11 @@ class Body:
     heave_amp: float = 0.0          # prescribed heave zeta(t) = A sin(w t + phi)
     heave_omega: float = 0.0
     heave_phase: float = 0.0
+    free_heave: int = 0             # 1: heave follows Newton's law under the hydrodynamic force
+    mass: float = 0.0               # kg (per metre of depth in 2-D)
+    pto_damping: float = 0.0        # linear-damper PTO force F_PTO = -c zdot, N s/m
+    zeta0: float = 0.0              # initial heave offset (m) and velocity (m/s) of a free body
+    zdot0: float = 0.0
 
 
 @dataclasses.dataclass

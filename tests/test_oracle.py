@@ -547,3 +547,97 @@ def test_c1_volume_and_convergence(orc):
     d = orc.diagnostics(P, f["sigma"], f["u"], f["v"], f["w"])
     assert abs(d[1] - v0) / v0 < 1e-3
     assert d[0] < 1e-7                       # max |div u| after projection
+
+
+# ---------------------------------------------------------------------------
+# Hydrodynamic force on a body (eqn_int_fh) and the heave update (eqn_newton_u)
+# ---------------------------------------------------------------------------
+def box_on_faces(h, i0, i1, k0, k1):
+    """2-D box whose sides lie on grid faces: x in [i0 h, i1 h], z in [k0 h, k1 h]."""
+    return I.Body(0, ((i0 + i1) * h / 2, 0.0, (k0 + k1) * h / 2), ((i1 - i0) * h / 2, 0.0, (k1 - k0) * h / 2))
+
+
+@pytest.mark.parametrize("k_bot", [5.0, 5.3])
+def test_hydro_force_is_archimedes_buoyancy_on_a_box(orc, k_bot):
+    """Still water, p = rho_w g (d - z) below the surface and 0 above, and a
+    box whose sides lie on grid faces: the stair-step surface feels exactly
+    rho_w g times the submerged area (per unit depth), and no side force.
+    With the bottom off the grid (5.3 h) the two cells across a bottom face
+    are 0.2 h and 0.8 h from it, and only interpolation of the pressure to
+    psi = 0 (each cell weighted by the other's |psi|) lands on p(z_bottom)."""
+    h, d = 0.125, 12 * 0.125
+    body = I.Body(0, (11 * h, 0.0, (k_bot + 16.4) * h / 2), (3 * h, 0.0, (16.4 - k_bot) * h / 2))
+    wl = flat_wl(nx=24, nz=24, h=h, depth=d, bodies=[body])
+    P = orc.params(wl)
+    x, y, z = cell_centres(wl)
+    p = np.where(z < d, FL["rho_w"] * wl.g * (d - z), 0.0)
+    _, u, v, w = zeros(wl)
+    mu = np.full(p.shape, FL["mu_w"])
+    F = orc.hydro_force(P, 0, p, u, v, w, mu, 0.0)
+    submerged = (6 * h) * (d - k_bot * h)
+    assert abs(F[2] / (FL["rho_w"] * wl.g * submerged) - 1.0) < 1e-13
+    assert abs(F[0]) < 1e-12 * F[2] and F[1] == 0.0
+
+
+def test_hydro_force_viscous_shear_closed_form(orc):
+    """p = 0, u = 0, w = gamma x^2: on the box's sides the z-traction
+    mu (dw/dx + du/dz) n_x = 2 mu gamma x n_x (exact for a quadratic), so
+    Fz = 2 mu gamma W H; the top and bottom faces carry 2 mu dw/dz = 0 in z
+    and cancel in x."""
+    h, gamma, mu0 = 0.125, 0.37, 1.7e-3
+    wl = flat_wl(nx=24, nz=20, h=h, bodies=[box_on_faces(h, 6, 15, 7, 12)])
+    P = orc.params(wl)
+    _, u, v, w = zeros(wl)
+    xw = (np.arange(wl.nx) + 0.5) * h
+    w[:] = gamma * xw[None, None, :] ** 2
+    p = np.zeros((wl.nz, 1, wl.nx))
+    mu = np.full(p.shape, mu0)
+    F = orc.hydro_force(P, 0, p, u, v, w, mu, 0.0)
+    W, H = 9 * h, 5 * h
+    assert abs(F[2] / (2 * mu0 * gamma * W * H) - 1.0) < 1e-12
+    assert abs(F[0]) < 1e-12 * abs(F[2])
+
+
+def test_hydro_force_constant_pressure_closes_on_a_cylinder(orc):
+    """A constant pressure integrates to zero over any closed stair-step
+    surface (every face of a column or row has an opposite twin): this pins
+    the face set and the normals of the 3-D loop for an off-grid cylinder."""
+    h = 0.125
+    cyl = I.Body(1, (8.0 * h, 8.3 * h, 0.0), (3.3 * h, 4.2 * h, 11.7 * h))
+    wl = flat_wl(nx=16, ny=16, nz=16, h=h, bodies=[cyl])
+    P = orc.params(wl)
+    p0 = 1234.5
+    p = np.full((16, 16, 16), p0)
+    _, u, v, w = zeros(wl)
+    mu = np.full(p.shape, FL["mu_w"])
+    F = orc.hydro_force(P, 0, p, u, v, w, mu, 0.0)
+    area = 2 * math.pi * 3.3 * h * 7.5 * h + 2 * math.pi * (3.3 * h) ** 2
+    assert np.max(np.abs(F)) < 1e-13 * p0 * area
+    # the same body in still water is buoyed, with no force along x: its axis
+    # lies on the grid plane x = 8 h, so the stair-step is mirror-symmetric in
+    # x (off-centre in y it need not be in y)
+    d = 8 * h
+    x, y, z = cell_centres(wl)
+    p = np.where(z < d, FL["rho_w"] * wl.g * (d - z), 0.0)
+    F = orc.hydro_force(P, 0, p, u, v, w, mu, 0.0)
+    buoy = FL["rho_w"] * wl.g * math.pi * (3.3 * h) ** 2 * (d - 4.2 * h)
+    assert abs(F[0]) < 1e-12 * F[2]
+    assert 0.8 < F[2] / buoy < 1.2
+
+
+def test_heave_update_free_fall_and_damped_decay(orc):
+    """No force: zdot^n = -g n dt and zeta^n = -g dt^2 n (n + 1) / 2 (the
+    update is backward Euler).  Weightless (Fz = m g) with a damper c:
+    zdot^n = zdot^0 (1 + c dt / m)^-n."""
+    m, g, dt = 3.0, 9.81, 0.01
+    z, zd = 0.0, 0.0
+    for n in range(1, 41):
+        z, zd = orc.heave_update(m, 0.0, g, dt, 0.0, z, zd)
+        assert abs(zd / (-g * n * dt) - 1) < 1e-13
+        assert abs(z / (-g * dt * dt * n * (n + 1) / 2) - 1) < 1e-12
+    c, z, zd = 7.0, 0.1, 0.5
+    for n in range(1, 41):
+        z, zd = orc.heave_update(m, c, g, dt, m * g, z, zd)
+        assert abs(zd / (0.5 * (1 + c * dt / m) ** -n) - 1) < 1e-12
+    z, zd = orc.heave_update(m, c, g, dt, m * g, 0.25, 0.0)
+    assert (z, zd) == (0.25, 0.0)
