@@ -58,15 +58,32 @@ typedef enum { NS_X0_ZERO = 0, NS_X0_PREV = 1, NS_X0_LEARNED = 2 } ns_x0;   /* p
 
 /* A rigid body given by an analytic level set psi (negative inside), built
  * from primitive distance functions with min/max (Sec. "Interface tracking":
- * psi is reset directly from the geometry each step).  Prescribed heave
- * zeta(t) = A sin(omega t + phase) shifts it along z; its velocity
- * u_b = dzeta/dt e_z (eq_ub_velocity restricted to heave). */
+ * psi is reset directly from the geometry each step).  A heave offset zeta
+ * shifts it along z; its velocity is u_b = dzeta/dt e_z (eq_ub_velocity
+ * restricted to heave).
+ *   Prescribed heave (free_heave = 0): zeta(t) = A sin(omega t + phase).
+ *   Free heave (free_heave = 1, Sec. "Fluid-structure coupling"): zeta and
+ *   zdot start at zeta0, zdot0 and follow eqn_newton_u,
+ *     m (zdot^{n+1} - zdot^n) / dt = F_hydro,z - m g + F_PTO,
+ *   with a linear-damper power take-off F_PTO = -c zdot^{n+1} and
+ *   zeta^{n+1} = zeta^n + dt zdot^{n+1}.  F_hydro is eqn_int_fh summed over
+ *   the body's stair-step surface (faces across which its psi changes sign)
+ *   from the pressure, velocity and viscosity that the previous step left;
+ *   on the first ns_step, from the fields it starts from (a caller driving
+ *   the three stages alone gets, on its first momentum_step, the force with
+ *   the viscosity of the level set as that call finds it).  momentum_step
+ *   advances the heave once per call; projection_solve computes the next
+ *   force.  mass is per metre of depth in a 2-D tank. */
 typedef struct {
   int kind;           /* 0: box in the (x,z) plane, psi = max(|x-xc|-a, |z-zc|-b)
                          1: vertical cylinder, psi = max(r - R, z_bot - z, z - z_top) */
   double c[3];        /* kind 0: (xc, unused, zc); kind 1: (xc, yc, unused)            */
   double half[3];     /* kind 0: (a, unused, b);  kind 1: (R, z_bot, z_top)            */
-  double heave_amp, heave_omega, heave_phase;
+  double heave_amp, heave_omega, heave_phase;   /* prescribed heave                    */
+  int free_heave;     /* 0: prescribed heave; 1: free heave                           */
+  double mass;        /* m (kg), > 0 for a free body                                  */
+  double pto_damping; /* c (N s/m), >= 0                                              */
+  double zeta0, zdot0;/* initial heave offset (m) and velocity (m/s) of a free body   */
 } ns_body;
 
 typedef struct {
@@ -177,6 +194,12 @@ ns_status ns_vcycle(ns_ctx* ctx, const double* r, double* z);
 
 /* Device pointer and element count of an internal array. */
 ns_status ns_buffer(ns_ctx* ctx, int which, void** dev_ptr, size_t* count);
+
+/* State of body m (host memory, no device work): out[0] zeta, out[1] zdot,
+ * out[2..4] the last hydrodynamic force (Fx, Fy, Fz) of eqn_int_fh, out[5]
+ * the last F_PTO.  For a prescribed body zeta and zdot are those of the last
+ * momentum_step and the force entries are 0.  NS_EINVAL for a bad m. */
+ns_status ns_body_state(ns_ctx* ctx, int body, double out[6]);
 
 /* out[0] max|div_h u|, out[1] water volume sum (1 - H(sigma)) h^d,
  * out[2] kinetic energy 1/2 sum rho^flow |u_c|^2 h^d, out[3] max|u_face|.

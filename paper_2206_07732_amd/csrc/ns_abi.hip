@@ -41,6 +41,15 @@ struct ns_ctx {
   KTimer kt;
   hipEvent_t ev_rr;   // marks the residual read-back of a CG iteration
   int launch_mode;    // ns_launch_mode
+  struct {
+    double F[3];      // last hydrodynamic force (eqn_int_fh)
+    double fpto;      // last power take-off force
+  } bs[4];            // free-body state beside the heave kept in phys.body
+  int nfree;          // number of free bodies
+  bool force_ready;   // bs[].F belongs to the current fields
+  double t_props;     // time of the last property evaluation
+  double* fpart;      // pinned host copy of the force partials (3 per block per free body)
+  int fcap;           // its capacity in blocks per body
   hipStream_t cap_st; // capture-only stream: the V-cycle graphs are recorded on it
   struct {
     int kind;
@@ -125,8 +134,16 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
     return snprintf(why, nwhy, "bad x0"), false;
   if (P->x0 == NS_X0_LEARNED && !(P->p_scale > 0.0))
     return snprintf(why, nwhy, "p_scale must be > 0 for the learned guess"), false;
-  for (int m = 0; m < P->n_bodies; ++m)
-    if (P->body[m].kind != 0 && P->body[m].kind != 1) return snprintf(why, nwhy, "bad body kind"), false;
+  for (int m = 0; m < P->n_bodies; ++m) {
+    const ns_body& B = P->body[m];
+    if (B.kind != 0 && B.kind != 1) return snprintf(why, nwhy, "bad body kind"), false;
+    if (B.free_heave != 0 && B.free_heave != 1) return snprintf(why, nwhy, "free_heave must be 0 or 1"), false;
+    if (B.free_heave && !(B.mass > 0.0 && std::isfinite(B.mass)))
+      return snprintf(why, nwhy, "body %d: a free body needs mass > 0", m), false;
+    if (B.free_heave && !(B.pto_damping >= 0.0 && std::isfinite(B.pto_damping) && std::isfinite(B.zeta0) &&
+                          std::isfinite(B.zdot0)))
+      return snprintf(why, nwhy, "body %d: pto_damping must be >= 0 and zeta0, zdot0 finite", m), false;
+  }
   return true;
 }
 
@@ -339,8 +356,9 @@ Phys make_phys(const ns_params& P) {
   ph.nb = P.n_bodies;
   for (int m = 0; m < P.n_bodies; ++m) {
     const ns_body& B = P.body[m];
-    ph.body[m] = BodyK{B.kind, B.c[0], B.c[1], B.c[2], B.half[0], B.half[1], B.half[2],
-                       B.heave_amp, B.heave_omega, B.heave_phase};
+    ph.body[m] = BodyK{B.kind,          B.c[0],          B.c[1],      B.c[2],  B.half[0],
+                       B.half[1],       B.half[2],       B.heave_amp, B.heave_omega,
+                       B.heave_phase,   B.free_heave,    B.zeta0,     B.zdot0};
   }
   return ph;
 }
@@ -806,6 +824,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
   }
   // small grids: the reductions the host alone reads leave their per-block
   // partials in host memory, and the host sums them (no finalize launch)
+  X->fpart = nullptr;
   X->hpart = X->hpart_dev = nullptr;
   if (X->nparts <= kHostPartsMax) {
     if (hipHostMalloc((void**)&X->hpart, (size_t)2 * X->nparts * sizeof(double),
@@ -816,6 +835,23 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
       delete X;
       return NS_EHIP;
     }
+  }
+  // free bodies: heave state, and pinned host room for the force partials;
+  // a force launch writes three partials per block into the device partials
+  // (4 nparts doubles), so it may use at most 4 nparts / 3 blocks, which a
+  // body's box within the grid does not exceed (a bigger one is refused)
+  X->nfree = 0;
+  for (int m = 0; m < params->n_bodies; ++m) X->nfree += params->body[m].free_heave ? 1 : 0;
+  for (int m = 0; m < 4; ++m) X->bs[m] = {{0.0, 0.0, 0.0}, 0.0};
+  X->force_ready = false;
+  X->t_props = 0.0;
+  X->fcap = (4 * X->nparts) / 3;
+  if (X->nfree > 0 &&
+      hipHostMalloc((void**)&X->fpart, (size_t)3 * 4 * X->fcap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (X->hpart) (void)hipHostFree(X->hpart);
+    (void)hipHostFree(X->host);
+    delete X;
+    return NS_EHIP;
   }
   if (hipEventCreateWithFlags(&X->ev_rr, hipEventDisableTiming) != hipSuccess) {
     (void)hipHostFree(X->host);
@@ -855,6 +891,7 @@ void ns_destroy(ns_ctx* X) {
   if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
   if (X->host) (void)hipHostFree(X->host);
   if (X->hpart) (void)hipHostFree(X->hpart);
+  if (X->fpart) (void)hipHostFree(X->fpart);
   delete X;
 }
 
@@ -947,6 +984,65 @@ ns_status ns_timing_read(ns_ctx* X, double* total_ms, int* launches) {
 
 const char* ns_last_error(ns_ctx* X) { return X ? X->err : "null context"; }
 
+// Force on every free body from the current pressure, velocity and the
+// viscosity in the workspace: the kernels and the copies of their partials
+// into pinned host memory are queued; free_forces_sum, after the stream has
+// been synchronised, sums each body's partials in block order.
+int free_forces_queue(ns_ctx* X, int nb[4]) {
+  for (int m = 0; m < X->phys.nb; ++m) {
+    nb[m] = 0;
+    if (!X->phys.body[m].fh) continue;
+    nb[m] = launch_hydro_force(X->phys, m, X->t_props, X->F.p, X->F.u, X->F.v, X->F.w, X->mu, X->partials,
+                               X->fcap, X->st);
+    if (nb[m] < 0) return -1;
+    if (nb[m] > 0 &&
+        hipMemcpyAsync(X->fpart + (size_t)3 * X->fcap * m, X->partials, (size_t)3 * nb[m] * sizeof(double),
+                       hipMemcpyDeviceToHost, X->st) != hipSuccess)
+      return -1;
+  }
+  return 0;
+}
+
+void free_forces_sum(ns_ctx* X, const int nb[4]) {
+  for (int m = 0; m < X->phys.nb; ++m) {
+    if (!X->phys.body[m].fh) continue;
+    const double* q = X->fpart + (size_t)3 * X->fcap * m;
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nb[m]; ++b)
+      for (int c = 0; c < 3; ++c) F[c] += q[3 * b + c];
+    for (int c = 0; c < 3; ++c) X->bs[m].F[c] = F[c];
+  }
+  X->force_ready = true;
+}
+
+// The force of the current fields when none is at hand (the first step):
+// the viscosity of the current level set and heave at time t, then the force.
+ns_status ensure_free_forces(ns_ctx* X, double t) {
+  if (X->nfree == 0 || X->force_ready) return NS_OK;
+  X->t_props = t;
+  launch_props(X->phys, X->F.sigma, t, X->rho, X->rfl, X->mu, X->chi, X->st);
+  int nb[4];
+  if (free_forces_queue(X, nb) != 0) return fail(X, NS_EHIP, "hydrodynamic force: launch or copy failed");
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  free_forces_sum(X, nb);
+  return NS_OK;
+}
+
+// eqn_newton_u for every free body with the force of the current fields:
+// m (zdot' - zdot) / dt = Fz - m g - c zdot', zeta' = zeta + dt zdot'
+void free_heave_update(ns_ctx* X, double dt) {
+  for (int m = 0; m < X->phys.nb; ++m) {
+    BodyK& B = X->phys.body[m];
+    if (!B.fh) continue;
+    const ns_body& Q = X->P.body[m];
+    const double zd = (B.zdot + dt * (X->bs[m].F[2] - Q.mass * X->P.g) / Q.mass) / (1.0 + dt * Q.pto_damping / Q.mass);
+    B.zdot = zd;
+    B.zeta += dt * zd;
+    X->bs[m].fpto = -Q.pto_damping * zd;
+  }
+  X->force_ready = false;
+}
+
 ns_status levelset_advect_reinit(ns_ctx* X, double dt) {
   if (!X) return NS_EINVAL;
   if (!(dt > 0.0)) return fail(X, NS_EINVAL, "dt must be > 0");
@@ -974,8 +1070,16 @@ ns_status levelset_advect_reinit(ns_ctx* X, double dt) {
 ns_status momentum_step(ns_ctx* X, double dt, double t_np1) {
   if (!X) return NS_EINVAL;
   if (!(dt > 0.0)) return fail(X, NS_EINVAL, "dt must be > 0");
-  const Phys& ph = X->phys;
   hipStream_t st = X->st;
+  if (X->nfree > 0) {
+    // ns_step has already taken the force of the state the step starts from;
+    // a caller driving the stages alone gets that of the current fields
+    ns_status s = ensure_free_forces(X, t_np1 - dt);
+    if (s != NS_OK) return s;
+    free_heave_update(X, dt);
+  }
+  const Phys& ph = X->phys;
+  X->t_props = t_np1;
   launch_props(ph, X->F.sigma, t_np1, X->rho, X->rfl, X->mu, X->chi, st);
   Level& L0 = X->lev[0];
   launch_momentum(ph, X->F.u, X->F.v, X->F.w, X->rho, X->rfl, X->mu, X->chi, dt, t_np1, X->us, X->vs,
@@ -1020,8 +1124,13 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   }
   const Level& L0 = X->lev[0];
   launch_correct(ph, X->us, X->vs, X->ws, X->F.p, L0.bx, L0.by, L0.bz, dt, X->F.u, X->F.v, X->F.w, st);
+  // the hydrodynamic force of the new fields, for the next heave update
+  int nb[4];
+  if (X->nfree > 0 && free_forces_queue(X, nb) != 0)
+    return fail(X, NS_EHIP, "hydrodynamic force: launch or copy failed");
   HIPCHK(X, hipGetLastError());
   HIPCHK(X, hipStreamSynchronize(st));
+  if (X->nfree > 0) free_forces_sum(X, nb);
   S.ms = now_ms() - t0;
   if (stats) *stats = S;
   return s;
@@ -1030,7 +1139,10 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
 ns_status ns_step(ns_ctx* X, double dt, double t_n, ns_stats* stats) {
   if (!X) return NS_EINVAL;
   const double t0 = now_ms();
-  ns_status s = levelset_advect_reinit(X, dt);
+  // free bodies: on the first step, the force of the state the step starts from
+  ns_status s = ensure_free_forces(X, t_n);
+  if (s != NS_OK) return s;
+  s = levelset_advect_reinit(X, dt);
   if (s != NS_OK) return s;
   if ((s = momentum_step(X, dt, t_n + dt)) != NS_OK) return s;
   ns_stats S{};
@@ -1104,6 +1216,17 @@ ns_status ns_buffer(ns_ctx* X, int which, void** dev_ptr, size_t* count) {
   if (count) *count = c;
   if (which == NS_BUF_BX || which == NS_BUF_BY || which == NS_BUF_BZ || which == NS_BUF_RHS)
     X->have_beta = true;   // the caller may fill the projection inputs directly
+  return NS_OK;
+}
+
+ns_status ns_body_state(ns_ctx* X, int body, double out[6]) {
+  if (!X || !out) return NS_EINVAL;
+  if (body < 0 || body >= X->phys.nb) return fail(X, NS_EINVAL, "no body %d", body);
+  const BodyK& B = X->phys.body[body];
+  out[0] = B.fh ? B.zeta : B.amp * std::sin(B.om * X->t_props + B.ph);
+  out[1] = B.fh ? B.zdot : B.amp * B.om * std::cos(B.om * X->t_props + B.ph);
+  for (int c = 0; c < 3; ++c) out[2 + c] = B.fh ? X->bs[body].F[c] : 0.0;
+  out[5] = B.fh ? X->bs[body].fpto : 0.0;
   return NS_OK;
 }
 

@@ -7,6 +7,7 @@
 // along z for a 2-D tank).  Out-of-grid neighbours are the nearest interior
 // value: zero normal gradient for scalars, free slip for tangential
 // velocity, zero for wall-normal velocity (whose faces hold 0).
+#include <algorithm>
 #include <cmath>
 
 #include "ns_internal.h"
@@ -64,23 +65,32 @@ __device__ __forceinline__ double heaviside(double phi, double eps) {
   return 0.5 * (1.0 + phi / eps + sin(kPi * phi / eps) * (1.0 / kPi));
 }
 
+// level set of one body at (x,y,z,t) and its heave velocity: prescribed
+// heave A sin(w t + phi), or the free body's own state
+__device__ double body_psi_one(const BodyK& B, double x, double y, double z, double t, double* zdot) {
+  double zeta, zd;
+  if (B.fh) {
+    zeta = B.zeta;
+    zd = B.zdot;
+  } else {
+    const double arg = B.om * t + B.ph;
+    zeta = B.amp * sin(arg);
+    zd = B.amp * B.om * cos(arg);
+  }
+  *zdot = zd;
+  if (B.kind == 0) return fmax(fabs(x - B.c0) - B.h0, fabs(z - (B.c2 + zeta)) - B.h2);
+  const double dx = x - B.c0, dy = y - B.c1;
+  const double r = sqrt(dx * dx + dy * dy);
+  return fmax(r - B.h0, fmax((B.h1 + zeta) - z, z - (B.h2 + zeta)));
+}
+
 // union of the analytic bodies at (x,y,z,t); zdot of the nearest one
 __device__ double body_psi(const Phys& P, double x, double y, double z, double t, double* zdot) {
   double best = INFINITY;
   double zd_best = 0.0;
   for (int m = 0; m < P.nb; ++m) {
-    const BodyK& B = P.body[m];
-    double arg = B.om * t + B.ph;
-    double zeta = B.amp * sin(arg);
-    double zd = B.amp * B.om * cos(arg);
-    double s;
-    if (B.kind == 0) {
-      s = fmax(fabs(x - B.c0) - B.h0, fabs(z - (B.c2 + zeta)) - B.h2);
-    } else {
-      double dx = x - B.c0, dy = y - B.c1;
-      double r = sqrt(dx * dx + dy * dy);
-      s = fmax(r - B.h0, fmax((B.h1 + zeta) - z, z - (B.h2 + zeta)));
-    }
+    double zd;
+    const double s = body_psi_one(P.body[m], x, y, z, t, &zd);
     if (s < best) {
       best = s;
       zd_best = zd;
@@ -358,6 +368,94 @@ __global__ void __launch_bounds__(256) k_correct(Phys P, const double* __restric
   u[f] = us[f] - dt * beta[f] * grad;
 }
 
+// Hydrodynamic force on body m, eqn_int_fh (Sec. "Fluid-structure
+// coupling"): the sum over its stair-step surface (the faces across which the
+// body's level set changes sign, Sec. "NLFK calculation") of
+// (-p_f n_f + mu_f (grad u + grad u^T) . n_f) dA_f, with n_f out of the body,
+// p_f the two cell pressures interpolated linearly to psi = 0, mu_f their
+// mean viscosity, central differences at the face centre, dA_f = h^2 (h in
+// 2-D).  One thread per cell of the box [lo, lo + ext), for the three faces
+// below it; the box holds every cell within two of the body, so no face of
+// the surface lies on its edge.  Per-block partials (Fx, Fy, Fz) in tile
+// order.
+__global__ void __launch_bounds__(256) k_hydro_force(Phys P, int m, int i0, int j0, int k0, int ex, int ey,
+                                                     int ez, double t, const double* __restrict__ p,
+                                                     const double* __restrict__ u,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ w,
+                                                     const double* __restrict__ mu,
+                                                     double* __restrict__ partials) {
+  const Dims n = P.n;
+  const Tile tl = xcd_tile();
+  const int li = tl.x * blockDim.x + threadIdx.x;
+  const int lj = tl.y * blockDim.y + threadIdx.y;
+  const int lk = tl.z * blockDim.z + threadIdx.z;
+  double F[3] = {0.0, 0.0, 0.0};
+  if (li < ex && lj < ey && lk < ez) {
+    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+    const BodyK B = P.body[m];
+    const double h = P.h, ih = 1.0 / h;
+    const bool two_d = (n.ny == 1);
+    const double dA = two_d ? h : h * h;
+    double zd;
+    const double psb = body_psi_one(B, (i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h, t, &zd);
+    // cell-centred mean of component c at a cell
+    auto cmean = [&](int c, int a, int b2, int c2) {
+      switch (c) {
+        case 0: return 0.5 * (fv<0>(u, n, a, b2, c2) + fv<0>(u, n, a + 1, b2, c2));
+        case 1: return 0.5 * (fv<1>(v, n, a, b2, c2) + fv<1>(v, n, a, b2 + 1, c2));
+        default: return 0.5 * (fv<2>(w, n, a, b2, c2) + fv<2>(w, n, a, b2, c2 + 1));
+      }
+    };
+    // face value of component d at face index (a, b2, c2)
+    auto face = [&](int d, int a, int b2, int c2) {
+      return d == 0 ? fv<0>(u, n, a, b2, c2) : (d == 1 ? fv<1>(v, n, a, b2, c2) : fv<2>(w, n, a, b2, c2));
+    };
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d == 1 && two_d) continue;
+      const int di = (d == 0), dj = (d == 1), dk = (d == 2);
+      if ((d == 0 && i < 1) || (d == 1 && j < 1) || (d == 2 && k < 1)) continue;
+      const int ia = i - di, ja = j - dj, ka = k - dk;
+      const double psa = body_psi_one(B, (ia + 0.5) * h, (ja + 0.5) * h, (ka + 0.5) * h, t, &zd);
+      if ((psa < 0.0) == (psb < 0.0)) continue;
+      const double nd = (psa < 0.0) ? 1.0 : -1.0;
+      const double pa = cv(p, n, ia, ja, ka), pb = cv(p, n, i, j, k);
+      const double wa = fabs(psa), wb = fabs(psb);
+      const double pf = (wb * pa + wa * pb) / (wa + wb);
+      const double muf = 0.5 * (cv(mu, n, ia, ja, ka) + cv(mu, n, i, j, k));
+      F[d] -= pf * nd * dA;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c == 1 && two_d) continue;
+        double G;
+        if (c == d) {
+          G = (face(d, i + di, j + dj, k + dk) - face(d, i - di, j - dj, k - dk)) * ih;
+        } else {
+          const int ci = (c == 0), cj = (c == 1), ck = (c == 2);
+          G = (cmean(c, i, j, k) - cmean(c, ia, ja, ka)) * ih +
+              (face(d, i + ci, j + cj, k + ck) - face(d, i - ci, j - cj, k - ck)) * (0.5 * ih);
+        }
+        F[c] += muf * G * nd * dA;
+      }
+    }
+  }
+  // fixed-order block sum
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) F[q] += __shfl_down(F[q], off, 64);
+  __shared__ double sm[4][3];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sm[tid >> 6][q] = F[q];
+  __syncthreads();
+  if (tid == 0)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) partials[3 * (size_t)tl.lin + q] = (sm[0][q] + sm[1][q]) + (sm[2][q] + sm[3][q]);
+}
+
 // per-block partial diagnostics: max|div|, water volume, kinetic energy, max|u_c|
 __global__ void __launch_bounds__(256) k_diag(Phys P, const double* __restrict__ sigma,
                                               const double* __restrict__ u,
@@ -515,6 +613,39 @@ int launch_diag_partials(const Phys& P, const double* sigma, const double* u, co
 
 void launch_diag_finalize(const double* partials, int nparts, double* scal, hipStream_t st) {
   hipLaunchKernelGGL(k_diag_finalize, dim3(1), dim3(1024), 0, st, partials, nparts, scal);
+}
+
+int launch_hydro_force(const Phys& P, int m, double t, const double* p, const double* u, const double* v,
+                       const double* w, const double* mu, double* partials, int max_blocks, hipStream_t st) {
+  const BodyK& B = P.body[m];
+  const double zeta = B.fh ? B.zeta : B.amp * sin(B.om * t + B.ph);
+  // the body's extent, then every cell within two of it
+  double lo[3], hi[3];
+  if (B.kind == 0) {
+    lo[0] = B.c0 - B.h0, hi[0] = B.c0 + B.h0;
+    lo[1] = 0.0, hi[1] = P.n.ny * P.h;
+    lo[2] = B.c2 + zeta - B.h2, hi[2] = B.c2 + zeta + B.h2;
+  } else {
+    lo[0] = B.c0 - B.h0, hi[0] = B.c0 + B.h0;
+    lo[1] = B.c1 - B.h0, hi[1] = B.c1 + B.h0;
+    lo[2] = B.h1 + zeta, hi[2] = B.h2 + zeta;
+  }
+  const int nn[3] = {P.n.nx, P.n.ny, P.n.nz};
+  int a[3], e[3];
+  for (int d = 0; d < 3; ++d) {
+    const double L = std::floor(lo[d] / P.h) - 2.0, H = std::ceil(hi[d] / P.h) + 2.0;
+    const int a0 = (int)std::max(0.0, std::min(L, (double)nn[d]));
+    const int a1 = (int)std::max(0.0, std::min(H, (double)nn[d]));
+    a[d] = a0;
+    e[d] = a1 - a0;
+  }
+  if (e[0] <= 0 || e[1] <= 0 || e[2] <= 0) return 0;
+  Geo g = geo3(e[0], e[1], e[2]);
+  const long long blocks = (long long)g.grid.x * g.grid.y * g.grid.z;
+  if (blocks > max_blocks) return -1;
+  hipLaunchKernelGGL(k_hydro_force, g.grid, g.block, 0, st, P, m, a[0], a[1], a[2], e[0], e[1], e[2], t, p, u, v,
+                     w, mu, partials);
+  return (int)blocks;
 }
 
 }  // namespace nsk

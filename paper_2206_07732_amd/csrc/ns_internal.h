@@ -44,6 +44,8 @@ struct BodyK {
   double c0, c1, c2;
   double h0, h1, h2;
   double amp, om, ph;
+  int fh;              // free heave: zeta, zdot below are the body's state
+  double zeta, zdot;
 };
 
 // Physical constants and geometry passed by value to the grid kernels.
@@ -155,6 +157,11 @@ void launch_correct(const Phys& P, const double* us, const double* vs, const dou
 int launch_diag_partials(const Phys& P, const double* sigma, const double* u, const double* v,
                          const double* w, double* partials, hipStream_t st);
 void launch_diag_finalize(const double* partials, int nparts, double* scal, hipStream_t st);
+// hydrodynamic force on body m over the cells of its bounding box: three
+// per-block partials (Fx, Fy, Fz) in tile order; returns the block count, or
+// -1 without launching when it would exceed max_blocks
+int launch_hydro_force(const Phys& P, int m, double t, const double* p, const double* u, const double* v,
+                       const double* w, const double* mu, double* partials, int max_blocks, hipStream_t st);
 int diag_blocks(const Phys& P);
 
 // multigrid and CG kernels (ns_mg.hip)

@@ -142,6 +142,7 @@ class Workload:
     inv_kappa_p: float = 1.0e8      # Brinkman 1/kappa_p
     proj_penalty_weight: float = 1.0
     dt_max: float = 0.05
+    p_init: str = "zero"            # initial pressure: "zero", or "hydrostatic" under the initial surface
 
     @property
     def dim(self) -> int:
@@ -159,6 +160,10 @@ class Workload:
 def _cyl(xc=2.0, yc=1.0, **kw) -> Body:
     # radius 0.25 m, length 0.8 m, draft 0.3 m in 1 m of water: z in [0.7, 1.5]
     return Body(1, (xc, yc, 0.0), (0.25, 0.7, 1.5), **kw)
+
+
+# mass of the water the cylinder displaces at rest (floats in equilibrium)
+_CYL_MASS = RHO_W * math.pi * 0.25 ** 2 * 0.3
 
 
 def harvest_draw(seed: int):
@@ -212,6 +217,26 @@ def workload(name: str, **over) -> Workload:
         wl = Workload("tiny3d: 3-D tank 32x16x16 (4x2x2 m), Stokes-2 a=0.08 T=1.2, fixed cylinder",
                       32, 16, 16, 4.0 / 32, 1.0, {"kind": "stokes2", "a": 0.08, "T": 1.2}, [_cyl()],
                       steps=3, seed=12)
+    elif name == "fsi2d":
+        # a spar-like box 0.25 m wide and 0.75 m tall floating at a 0.5 m draft
+        # (mass of the displaced water, per metre of depth), released 2 cm
+        # above its rest position
+        wl = Workload("fsi2d: 2-D tank 128x32 (8x2 m, h=1/16), Airy a=0.03 T=1.5, free-heave box 0.25x0.75 m, "
+                      "PTO 20 N s/m",
+                      128, 1, 32, 8.0 / 128, 1.0, {"kind": "airy", "a": 0.03, "T": 1.5, "phase": 0.3},
+                      [Body(0, (4.0, 0.0, 0.875), (0.125, 0.0, 0.375), free_heave=1, mass=RHO_W * 0.25 * 0.5,
+                            pto_damping=20.0, zeta0=0.02)], steps=5, seed=13, p_init="hydrostatic")
+    elif name == "fsi3d":
+        wl = Workload("fsi3d: 3-D tank 32x16x16 (4x2x2 m), Stokes-2 a=0.08 T=1.2, free-heave cylinder, PTO 50 N s/m",
+                      32, 16, 16, 4.0 / 32, 1.0, {"kind": "stokes2", "a": 0.08, "T": 1.2},
+                      [_cyl(free_heave=1, mass=_CYL_MASS, pto_damping=50.0)], steps=5, seed=14,
+                      p_init="hydrostatic")
+    elif name == "c2fsi":
+        wl = Workload("c2fsi: 3-D tank 128x64x64 (4x2x2 m, h=1/32), Stokes-2 a=0.05 m T=1.2 s, "
+                      "free-heave cylinder, PTO 200 N s/m",
+                      128, 64, 64, 4.0 / 128, 1.0, {"kind": "stokes2", "a": 0.05, "T": 1.2},
+                      [_cyl(free_heave=1, mass=_CYL_MASS, pto_damping=200.0)], steps=20, seed=2,
+                      p_init="hydrostatic")
     else:
         raise KeyError(name)
     for k, v in over.items():
@@ -285,7 +310,9 @@ def _velocity(wl: Workload, x, z):
 
 
 def make_fields(wl: Workload):
-    """Initial sigma (cells), u/v/w (faces) and p = 0.
+    """Initial sigma (cells), u/v/w (faces) and p: 0, or with p_init =
+    "hydrostatic" rho_w g (d + eta(x) - z) under the initial surface and 0
+    above it.
 
     sigma = z - (d + eta(x)): negative in water, not an exact signed distance.
     Faces below the initial surface carry the potential-flow velocity, faces
@@ -316,6 +343,10 @@ def make_fields(wl: Workload):
     ww[0, :] = 0.0
     w = np.repeat(ww[:, None, :], ny, axis=1).copy()
     p = np.zeros((nz, ny, nx))
+    if wl.p_init == "hydrostatic":
+        p[:] = np.maximum(-sigma, 0.0) * wl.rho_w * wl.g
+    elif wl.p_init != "zero":
+        raise ValueError(wl.p_init)
     return {"sigma": np.ascontiguousarray(sigma), "u": u, "v": v, "w": w, "p": p}
 
 

@@ -26,7 +26,9 @@ BUF = {"us": 0, "vs": 1, "ws": 2, "bx": 3, "by": 4, "bz": 5, "rhs": 6, "rho": 7,
 
 class NSBody(C.Structure):
     _fields_ = [("kind", C.c_int), ("c", C.c_double * 3), ("half", C.c_double * 3),
-                ("heave_amp", C.c_double), ("heave_omega", C.c_double), ("heave_phase", C.c_double)]
+                ("heave_amp", C.c_double), ("heave_omega", C.c_double), ("heave_phase", C.c_double),
+                ("free_heave", C.c_int), ("mass", C.c_double), ("pto_damping", C.c_double),
+                ("zeta0", C.c_double), ("zdot0", C.c_double)]
 
 
 class NSParams(C.Structure):
@@ -88,6 +90,7 @@ def lib() -> C.CDLL:
             "ns_diagnostics": ([vp, C.POINTER(C.c_double)], i),
             "ns_num_levels": ([i, i, i], i),
             "ns_set_launch_mode": ([vp, i], i),
+            "ns_body_state": ([vp, i, C.POINTER(C.c_double)], i),
             "ns_timing_enable": ([vp, i, i], i),
             "ns_timing_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int)], i),
             "ns_time_kernel": ([vp, i, i, C.POINTER(C.c_double)], i),
@@ -119,7 +122,7 @@ def lib() -> C.CDLL:
 EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum_step",
             "projection_solve", "ns_step", "ns_pcg_solve", "ns_apply_A", "ns_vcycle", "ns_buffer",
             "ns_diagnostics", "ns_num_levels", "ns_last_error", "ns_destroy", "ns_set_launch_mode",
-            "ns_timing_enable", "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
+            "ns_body_state", "ns_timing_enable", "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
             "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target"]
@@ -145,6 +148,8 @@ def params(wl, **opts) -> NSParams:
             P.body[m].half[q] = b.half[q]
         P.body[m].heave_amp, P.body[m].heave_omega, P.body[m].heave_phase = (
             b.heave_amp, b.heave_omega, b.heave_phase)
+        P.body[m].free_heave, P.body[m].mass, P.body[m].pto_damping = int(b.free_heave), b.mass, b.pto_damping
+        P.body[m].zeta0, P.body[m].zdot0 = b.zeta0, b.zdot0
     o = dict(SOLVER_DEFAULTS)
     o["p_scale"] = wl.rho_w * wl.g * wl.depth      # P0 = rho_w g d
     o.update(opts)
@@ -301,6 +306,13 @@ class Solver:
 
     def target(self, p_prev: torch.Tensor, t: torch.Tensor):
         self._chk("ns_target", lib().ns_target(self.ctx, _dev_f64(p_prev, "p_prev"), t.data_ptr()))
+
+    def body_state(self, m: int) -> dict:
+        """Heave offset and velocity of body m, the last hydrodynamic force
+        (Fx, Fy, Fz) and power take-off force (free bodies)."""
+        out = (C.c_double * 6)()
+        self._chk("ns_body_state", lib().ns_body_state(self.ctx, m, out))
+        return {"zeta": out[0], "zdot": out[1], "F": (out[2], out[3], out[4]), "f_pto": out[5]}
 
     def diagnostics(self):
         out = (C.c_double * 4)()

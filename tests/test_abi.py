@@ -61,6 +61,13 @@ def test_workspace_size_and_validation(nslib):
     assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
     bad = nslib.params(wl, prec=7)
     assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+    # a free-heave body needs a positive mass and a non-negative PTO damping
+    fsi = I.workload("fsi3d")
+    assert L.ns_workspace_bytes(ctypes.byref(nslib.params(fsi))) > 0
+    for field, value in (("mass", 0.0), ("pto_damping", -1.0), ("free_heave", 2)):
+        bad = nslib.params(fsi)
+        setattr(bad.body[0], field, value)
+        assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0, field
 
 
 def test_level_count_matches_oracle(nslib, orc):
