@@ -23,6 +23,10 @@ Printed: ONE JSON line with
                inference included), the per-field difference of the
                FP32-V-cycle step from the FP64 one, and the network forward's
                BF16 rate
+  fsi_study    free heave (force of eqn_int_fh, heave of eqn_newton_u) on the
+               same tank with the cylinder free: whole ns_step calls timed the
+               same way, against the fixed-body step, with the heave range and
+               the force over the body's weight
   roofline     the finest-level smoother pass (the dominant kernel): its
                algorithmic bytes per launch over its average duration, the
                duration taken from HIP events recorded with each dispatch
@@ -257,6 +261,52 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
     return out
 
 
+def fsi_study(name: str, steps: int, warmup: int, fixed: dict):
+    """Free heave on `name`: K whole ns_step calls after W warm-up steps, each
+    with the force on the free body and its heave update; fixed is the
+    fixed-body run of the same tank for comparison."""
+    import torch
+    from paper_2206_07732_amd import inputs as I, ns
+    wl = I.workload(name)
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    S = ns.Solver(ns.params(wl), ns.device_fields(f))
+    t = 0.0
+    for _ in range(warmup):
+        S.step(dt, t)
+        t += dt
+    torch.cuda.synchronize()
+    zeta, fz, iters = [], [], []
+    a = time.perf_counter()
+    for _ in range(steps):
+        st = S.step(dt, t)
+        t += dt
+        iters.append(st["iters"])
+        b = S.body_state(0)           # host state: no device work
+        zeta.append(b["zeta"])
+        fz.append(b["F"][2])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - a) / steps
+    S.close()
+    mg = wl.bodies[0].mass * wl.g
+    ncell = wl.nx * wl.ny * wl.nz
+    out = {
+        "workload": wl.name,
+        "steps": steps,
+        "ms_per_step": round(ms, 4),
+        "mcell_steps_per_s": round(ncell * steps / (ms * steps * 1e-3) / 1e6, 3),
+        "cg_iters": iters,
+        "ms_per_cg_iter": round(ms / statistics.mean(iters), 4),
+        "fixed_body_ms_per_step": round(fixed["ms_per_step"], 4),
+        "fixed_body_ms_per_cg_iter": round(fixed["ms_per_step"] / statistics.mean(fixed["iters"]), 4),
+        "zeta_range_m": [round(min(zeta), 6), round(max(zeta), 6)],
+        "fz_over_mg_range": [round(min(fz) / mg, 4), round(max(fz) / mg, 4)],
+    }
+    log(f"[bench] free heave {name}: {ms:.3f} ms/step ({out['ms_per_cg_iter']} ms per CG iteration; fixed body "
+        f"{out['fixed_body_ms_per_cg_iter']}), zeta in {out['zeta_range_m']} m, Fz/mg in {out['fz_over_mg_range']}")
+    return out
+
+
 def run_cpu_baseline(wl, f0, dt, seconds: float):
     """The oracle as it stands, single-threaded, for about `seconds`."""
     from oracle import oracle as O
@@ -288,6 +338,8 @@ def main():
                     help="comma-separated workloads of the projection study (FP64 vs FP32 V-cycle vs learned "
                          "guess); 'none' skips it")
     ap.add_argument("--projection-steps", type=int, default=8)
+    ap.add_argument("--fsi-workload", default="c2fsi",
+                    help="workload of the free-heave study (a free body on the main tank); 'none' skips it")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2206_07732_amd", "weights", "guess_c4.npy"))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -311,6 +363,9 @@ def main():
     if args.projection_workload != "none":
         study = [projection_study(w, args.projection_steps, 2, args.weights)
                  for w in args.projection_workload.split(",")]
+    fsi = None
+    if args.fsi_workload != "none":
+        fsi = fsi_study(args.fsi_workload, args.steps, args.warmup, r)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(r["wl"], r["f0"], r["dt"], args.cpu_seconds)
@@ -332,6 +387,7 @@ def main():
         "cg_iters": r["iters"],
         "projection": r["projection"],
         "projection_study": study,
+        "fsi_study": fsi,
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }
