@@ -238,6 +238,92 @@ static int is_wall_face(const orc_params* P, int c, int i, int j, int k) {
 }
 
 /* --------------------------------------------------------------------------
+ * Numerical wave tank (Sec. "Numerical wave tank").
+ * Target wave: the superposition of linear components (Sec. "Regular waves"
+ * and "Irregular waves") a_i cos(k_i x - om_i t + ph_i), with potential-flow
+ * velocity under the surface (z from the bed) and none above it.
+ * ------------------------------------------------------------------------ */
+static double wave_eta(const orc_params* P, double x, double t) {
+  double eta = 0.0;
+  for (int q = 0; q < P->n_waves; ++q) eta += P->wave_a[q] * cos(P->wave_k[q] * x - P->wave_om[q] * t + P->wave_ph[q]);
+  return eta;
+}
+
+/* horizontal (c = 0) or vertical (c = 2) target velocity at (x, z, t); v = 0 */
+static double wave_vel(const orc_params* P, int c, double x, double z, double t) {
+  if (c == 1 || z >= P->depth + wave_eta(P, x, t)) return 0.0;
+  double s = 0.0;
+  for (int q = 0; q < P->n_waves; ++q) {
+    double k = P->wave_k[q], th = k * x - P->wave_om[q] * t + P->wave_ph[q];
+    double amp = P->wave_a[q] * P->wave_om[q] / sinh(k * P->depth);
+    s += (c == 0) ? amp * cosh(k * z) * cos(th) : amp * sinh(k * z) * sin(th);
+  }
+  return s;
+}
+
+/* relaxation weight of the relaxation-zone method the tank uses (Jacobsen et
+ * al.): 1 at the zone's inner edge (chi = 0), 0 at the tank end (chi = 1) */
+static double relax_alpha(double chi) { return 1.0 - (exp(pow(chi, 3.5)) - 1.0) / (exp(1.0) - 1.0); }
+
+/* vorticity damping coefficient g(z~) = rho_a (cos(pi z~) + 1) / (4 dt),
+ * z~ = (z - z_top) / width over the top `width` of the tank, 0 below it */
+static double vort_damp(const orc_params* P, double z, double dt) {
+  if (P->vort_width <= 0.0) return 0.0;
+  double zt = (z - P->nz * P->h) / P->vort_width;
+  if (zt < -1.0) return 0.0;
+  return P->rho_a * (cos(M_PI * zt) + 1.0) / (4.0 * dt);
+}
+
+/* The zones after each step: every field phi in them becomes
+ * alpha phi + (1 - alpha) phi_target, with the target wave in the
+ * generation zone [0, gen_len] (chi = 1 - x / gen_len) and still water in
+ * the damping zone [L - damp_len, L] (chi = (x - L + damp_len) / damp_len). */
+static int relax_weight(const orc_params* P, double x, int* gen, double* alpha) {
+  double L = P->nx * P->h;
+  if (P->gen_len > 0.0 && x <= P->gen_len) {
+    *gen = 1;
+    *alpha = relax_alpha(1.0 - x / P->gen_len);
+    return 1;
+  }
+  if (P->damp_len > 0.0 && x >= L - P->damp_len) {
+    *gen = 0;
+    *alpha = relax_alpha((x - (L - P->damp_len)) / P->damp_len);
+    return 1;
+  }
+  return 0;
+}
+
+void orc_relax(const orc_params* P, double t, double* sigma, double* u, double* v, double* w) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
+  const double h = P->h;
+  double* vel[3] = {u, v, w};
+  int gen;
+  double al;
+  for (int c = 0; c < 3; ++c) {
+    int mx = nx + (c == 0), my = ny + (c == 1), mz = nz + (c == 2);
+    for (int k = 0; k < mz; ++k)
+      for (int j = 0; j < my; ++j)
+        for (int i = 0; i < mx; ++i) {
+          double x = (c == 0) ? i * h : (i + 0.5) * h;
+          double z = (c == 2) ? k * h : (k + 0.5) * h;
+          if (!relax_weight(P, x, &gen, &al)) continue;
+          size_t f = i + (size_t)mx * (j + (size_t)my * k);
+          double target = gen ? wave_vel(P, c, x, z, t) : 0.0;
+          vel[c][f] = al * vel[c][f] + (1.0 - al) * target;
+        }
+  }
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double x = (i + 0.5) * h, z = (k + 0.5) * h;
+        if (!relax_weight(P, x, &gen, &al)) continue;
+        size_t c = i + (size_t)nx * (j + (size_t)ny * k);
+        double target = z - (P->depth + (gen ? wave_eta(P, x, t) : 0.0));
+        sigma[c] = al * sigma[c] + (1.0 - al) * target;
+      }
+}
+
+/* --------------------------------------------------------------------------
  * Momentum predictor (eqn_c_discrete_momentum with the Brinkman term
  * eqn_bp_discrete taken implicitly, gravity on the flowing density; the
  * pressure gradient is left to the projection):
@@ -267,6 +353,11 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
       for (int j = 0; j < my; ++j)
         for (int i = 0; i < mx; ++i) {
           size_t f = i + (size_t)mx * (j + (size_t)my * k);
+          if (c == 0 && i == 0 && P->gen_len > 0.0) {
+            /* the inlet of the wave tank: the target wave's velocity */
+            out[c][f] = wave_vel(P, 0, 0.0, (k + 0.5) * h, t_np1);
+            continue;
+          }
           if (is_wall_face(P, c, i, j, k)) {
             out[c][f] = 0.0;
             continue;
@@ -329,8 +420,10 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
             body_psi(P, (i + 0.5) * h, (j + 0.5) * h, k * h, t_np1, &ub);
           }
           double pen = chif * P->inv_kappa_p;
+          /* vorticity damping force -g(z~) u, taken implicitly like the penalty */
+          double damp = vort_damp(P, (c == 2) ? k * h : (k + 0.5) * h, dt);
           double num = rhof * (uf / dt - adv) + visc + grav + pen * ub;
-          out[c][f] = num / (rhof / dt + pen);
+          out[c][f] = num / (rhof / dt + pen + damp);
         }
   }
   free(rho);
@@ -588,6 +681,10 @@ void orc_correct(const orc_params* P, const double* us, const double* vs, const 
       for (int j = 0; j < my; ++j)
         for (int i = 0; i < mx; ++i) {
           size_t f = i + (size_t)mx * (j + (size_t)my * k);
+          if (c == 0 && i == 0 && P->gen_len > 0.0) {
+            out[c][f] = S[c][f];   /* the inlet keeps its prescribed velocity */
+            continue;
+          }
           if (is_wall_face(P, c, i, j, k)) {
             out[c][f] = 0.0;
             continue;
@@ -631,6 +728,7 @@ int orc_step(const orc_params* P, double* sigma, double* u, double* v, double* w
   if (!x0_prev) memset(p, 0, n * sizeof(double));
   int rc = orc_pcg(P, bx, by, bz, b, p, st);
   orc_correct(P, us, vs, ws, p, bx, by, bz, dt, u, v, w);
+  if (P->gen_len > 0.0 || P->damp_len > 0.0) orc_relax(P, t1, sigma, u, v, w);
   free(us);
   free(vs);
   free(ws);

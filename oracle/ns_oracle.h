@@ -45,6 +45,13 @@ typedef struct {
   int nu_pre, nu_post, coarse_sweeps, max_iters;
   double rtol;
   int prec;                    /* 0: FP64 V-cycle, 1: FP32 V-cycle               */
+  /* numerical wave tank (Sec. "Numerical wave tank"); zeros: a closed tank */
+  double depth;                /* still-water depth d                            */
+  double gen_len;              /* wave generation zone x in [0, gen_len]         */
+  double damp_len;             /* wave damping zone x in [L - damp_len, L]       */
+  double vort_width;           /* vorticity damping zone width below the top     */
+  int n_waves;                 /* generated linear components (<= 64)            */
+  double wave_a[64], wave_k[64], wave_om[64], wave_ph[64];
 } orc_params;
 
 typedef struct {
@@ -81,6 +88,8 @@ void orc_diagnostics(const orc_params* P, const double* sigma, const double* u, 
 /* hydrodynamic force on body m (eqn_int_fh); mu: cell viscosity; F: (Fx, Fy, Fz) */
 void orc_hydro_force(const orc_params* P, int m, const double* p, const double* u, const double* v,
                      const double* w, const double* mu, double t, double* F);
+/* relaxation zones of the numerical wave tank at time t, in place */
+void orc_relax(const orc_params* P, double t, double* sigma, double* u, double* v, double* w);
 /* heave update of a free body (eqn_newton_u, linear-damper PTO, implicit) */
 void orc_heave_update(double mass, double pto_damping, double g, double dt, double fz, double* zeta,
                       double* zdot);

@@ -43,7 +43,11 @@ class Params(C.Structure):
                 ("proj_penalty_weight", C.c_double), ("n_bodies", C.c_int), ("body", _Body * 4),
                 ("reinit_iters", C.c_int), ("reinit_dtau_over_h", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_sweeps", C.c_int),
-                ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int)]
+                ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int),
+                ("depth", C.c_double), ("gen_len", C.c_double), ("damp_len", C.c_double),
+                ("vort_width", C.c_double), ("n_waves", C.c_int),
+                ("wave_a", C.c_double * 64), ("wave_k", C.c_double * 64), ("wave_om", C.c_double * 64),
+                ("wave_ph", C.c_double * 64)]
 
 
 class Stats(C.Structure):
@@ -83,6 +87,7 @@ def lib():
             "orc_diagnostics": [P, dp, dp, dp, dp, dp],
             "orc_hydro_force": [P, C.c_int, dp, dp, dp, dp, dp, d, dp],
             "orc_heave_update": [d, d, d, d, d, dp, dp],
+            "orc_relax": [P, d, dp, dp, dp, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -123,6 +128,14 @@ def params(wl, **solver) -> Params:
         P.body[m].free_heave, P.body[m].mass, P.body[m].pto_damping = \
             int(b.free_heave), b.mass, b.pto_damping
         P.body[m].zeta, P.body[m].zdot = b.zeta0, b.zdot0
+    P.depth = wl.depth
+    if wl.nwt:
+        from paper_2206_07732_amd.inputs import wave_components
+        P.gen_len, P.damp_len, P.vort_width = wl.nwt.get("gen", 0.0), wl.nwt.get("damp", 0.0), wl.nwt.get("vort", 0.0)
+        a, k, om, ph = wave_components(wl)
+        P.n_waves = len(a)
+        for q in range(len(a)):
+            P.wave_a[q], P.wave_k[q], P.wave_om[q], P.wave_ph[q] = a[q], k[q], om[q], ph[q]
     opts = dict(SOLVER_DEFAULTS)
     opts.update(solver)
     for k, v in opts.items():
@@ -261,3 +274,10 @@ def step_fsi(P, fields, dt, t_n, x0_prev=True):
             B.zeta, B.zdot = heave_update(B.mass, B.pto_damping, P.g, dt, F[2], B.zeta, B.zdot)
     f, st, rc = step(P, fields, dt, t_n, x0_prev)
     return f, st, rc, forces
+
+
+def relax(P, t, fields):
+    """The wave tank's relaxation zones at time t, on copies of the fields."""
+    f = {k: _arr(fields[k]).copy() for k in ("sigma", "u", "v", "w")}
+    lib().orc_relax(C.byref(P), t, _p(f["sigma"]), _p(f["u"]), _p(f["v"]), _p(f["w"]))
+    return f

@@ -143,6 +143,7 @@ class Workload:
     proj_penalty_weight: float = 1.0
     dt_max: float = 0.05
     p_init: str = "zero"            # initial pressure: "zero", or "hydrostatic" under the initial surface
+    nwt: Optional[dict] = None      # numerical wave tank: {"gen": m, "damp": m, "vort": m} zone sizes
 
     @property
     def dim(self) -> int:
@@ -217,6 +218,22 @@ def workload(name: str, **over) -> Workload:
         wl = Workload("tiny3d: 3-D tank 32x16x16 (4x2x2 m), Stokes-2 a=0.08 T=1.2, fixed cylinder",
                       32, 16, 16, 4.0 / 32, 1.0, {"kind": "stokes2", "a": 0.08, "T": 1.2}, [_cyl()],
                       steps=3, seed=12)
+    elif name == "c1nwt":
+        # C1's tank as a numerical wave tank: generation zone of one
+        # wavelength at the inlet, damping zone of 1.5 wavelengths at the far
+        # end, vorticity damping over the top four cells
+        lam = 2.0 * math.pi / wavenumber(2.0 * math.pi / 1.0, 1.0, G)
+        wl = Workload("c1nwt: 2-D wave tank 256x64 (8x2 m, h=1/32), Airy a=0.02 m T=1 s generated at x=0, "
+                      "zones 1 and 1.5 wavelengths, fixed box 0.4x0.2 m",
+                      256, 1, 64, 8.0 / 256, 1.0, {"kind": "airy", "a": 0.02, "T": 1.0, "phase": 0.0},
+                      [Body(0, (4.0, 0.0, 1.0), (0.2, 0.0, 0.1))], steps=10, seed=1,
+                      nwt={"gen": lam, "damp": 1.5 * lam, "vort": 4 * 8.0 / 256})
+    elif name == "nwt3d":
+        lam = 2.0 * math.pi / wavenumber(2.0 * math.pi / 1.2, 1.0, G)
+        wl = Workload("nwt3d: 3-D wave tank 32x16x16 (4x2x2 m), Airy a=0.05 T=1.2 s generated at x=0, "
+                      "zones 1 and 1.5 m, fixed cylinder",
+                      32, 16, 16, 4.0 / 32, 1.0, {"kind": "airy", "a": 0.05, "T": 1.2, "phase": 0.4}, [_cyl()],
+                      steps=3, seed=15, nwt={"gen": 1.0, "damp": 1.5, "vort": 4 * 4.0 / 32})
     elif name == "fsi2d":
         # a spar-like box 0.25 m wide and 0.75 m tall floating at a 0.5 m draft
         # (mass of the displaced water, per metre of depth), released 2 cm
@@ -274,6 +291,22 @@ def _wave_terms(wl: Workload):
     if kind == "flat":
         return kind, []
     raise KeyError(kind)
+
+
+def wave_components(wl: Workload):
+    """The linear components (a, kappa, omega, phase) of the workload's wave,
+    as arrays: the waves a numerical wave tank generates, a cos(kappa x -
+    omega t + phase).  Only linear kinds (Airy, JONSWAP, flat) qualify."""
+    kind, comps = _wave_terms(wl)
+    if kind not in ("airy", "jonswap", "flat"):
+        raise ValueError(f"a wave tank generates linear waves only, not {kind}")
+    if len(comps) > 64:
+        raise ValueError("at most 64 components")
+    a = np.array([c[0] for c in comps], dtype=np.float64)
+    om = np.array([c[1] for c in comps], dtype=np.float64)
+    k = np.array([c[2] for c in comps], dtype=np.float64)
+    ph = np.array([c[3] for c in comps], dtype=np.float64)
+    return a, k, om, ph
 
 
 def elevation(wl: Workload, x):

@@ -641,3 +641,88 @@ def test_heave_update_free_fall_and_damped_decay(orc):
         assert abs(zd / (0.5 * (1 + c * dt / m) ** -n) - 1) < 1e-12
     z, zd = orc.heave_update(m, c, g, dt, m * g, 0.25, 0.0)
     assert (z, zd) == (0.25, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Numerical wave tank (Sec. "Numerical wave tank"): relaxation zones, inlet,
+# vorticity damping
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t", [0.0, 0.37])
+def test_generation_zone_holds_the_target_wave(orc, t):
+    """The initial fields of a linear wave (built by the input generator's own
+    numpy kinematics) are the generation zone's target at t = 0, so relaxing
+    them there changes nothing: this pins the oracle's wave kinematics.  At
+    t > 0 the target is the same wave with its phase moved back by omega t,
+    whose initial fields are built the same way."""
+    wl = I.workload("c1nwt")
+    om = 2.0 * math.pi / wl.wave["T"]
+    shifted = I.workload("c1nwt")
+    shifted.wave = dict(wl.wave, phase=wl.wave["phase"] - om * t)
+    f = I.make_fields(shifted)
+    P = orc.params(wl)
+    r = orc.relax(P, t, f)
+    gen = wl.nwt["gen"]
+    ncol = {"sigma": int(gen / wl.h - 0.5) + 1, "u": int(gen / wl.h) + 1, "w": int(gen / wl.h - 0.5) + 1}
+    for k in ("sigma", "u", "w"):
+        lo = 1 if k == "u" else 0        # the initial fields treat x = 0 as a wall
+        a, b = r[k][..., lo:ncol[k]], f[k][..., lo:ncol[k]]
+        assert np.max(np.abs(a - b)) < 1e-13 * max(1.0, np.max(np.abs(b))), k
+    # the damping zone at the far end (1.5 wavelengths) does change the wave
+    ndamp = int(wl.nwt["damp"] / wl.h)
+    assert np.max(np.abs(r["sigma"][..., -ndamp:] - f["sigma"][..., -ndamp:])) > 0.2 * wl.wave["a"]
+
+
+def test_damping_zone_blends_to_still_water(orc):
+    """Still water is a fixed point; a uniform velocity U is blended to
+    exactly 0 at the tank end (weight 0 there), left untouched up to the
+    zone's inner edge, and decreases monotonically in between."""
+    wl = flat_wl(nx=64, nz=16, h=0.125, depth=1.0)
+    wl.nwt = {"gen": 0.0, "damp": 2.0, "vort": 0.0}
+    P = orc.params(wl)
+    x, y, z = cell_centres(wl)
+    _, u, v, w = zeros(wl)
+    still = {"sigma": z - 1.0, "u": u, "v": v, "w": w}
+    r = orc.relax(P, 0.3, still)
+    for k in still:
+        assert np.array_equal(r[k], still[k]), k
+    U = 0.7
+    moving = dict(still, u=np.full_like(u, U))
+    r = orc.relax(P, 0.3, moving)["u"][5, 0, :]
+    xf = np.arange(wl.nx + 1) * wl.h
+    inside = xf >= 8.0 - 2.0
+    assert np.all(r[~inside] == U)
+    assert r[-1] == 0.0 and abs(r[inside][0] - U) < 1e-15
+    assert np.all(np.diff(r[inside]) < 0)
+
+
+def test_inlet_face_carries_the_wave_velocity(orc):
+    """With a generation zone the predictor puts the target wave's horizontal
+    velocity on the inlet face (the input generator's potential flow at the
+    same time)."""
+    wl = I.workload("c1nwt")
+    f = I.make_fields(wl)
+    P = orc.params(wl)
+    us, vs, ws = orc.momentum(P, f["u"], f["v"], f["w"], f["sigma"], 0.0, 0.01)
+    zc = (np.arange(wl.nz) + 0.5) * wl.h
+    uu, _ = I._velocity(wl, np.zeros(1)[None, :], zc[:, None])
+    wet = zc < wl.depth + I.elevation(wl, np.zeros(1))[0]
+    assert np.max(np.abs(us[:, 0, 0] - np.where(wet, uu[:, 0], 0.0))) < 1e-13
+
+
+def test_vorticity_damping_in_the_predictor(orc):
+    """A uniform horizontal velocity U has no advection or viscous stress, so
+    the predictor leaves it alone below the damping zone and divides it by
+    1 + dt g / rho_f inside, g = rho_a (cos(pi z~) + 1) / (4 dt): in the top
+    row of an all-air tank z~ = -1/8 and u* = U / (1 + (cos(pi/8) + 1) / 4)."""
+    wl = flat_wl(nx=16, nz=16, h=0.125, depth=-1.0)     # all air
+    wl.nwt = {"gen": 0.0, "damp": 0.0, "vort": 4 * 0.125}
+    P = orc.params(wl)
+    x, y, z = cell_centres(wl)
+    _, u, v, w = zeros(wl)
+    U = 0.3
+    u[:] = U
+    us, _, _ = orc.momentum(P, u, v, w, z + 1.0, 0.0, 0.01)
+    interior = us[:, 0, 2:-2]
+    assert np.all(interior[:12] == U)
+    assert np.max(np.abs(interior[15] / (U / (1 + (math.cos(math.pi / 8) + 1) / 4)) - 1)) < 1e-14
+    assert np.all(np.diff(interior[11:, 0]) < 0)
