@@ -108,6 +108,26 @@ typedef struct {
   int x0;                      /* ns_x0                                             */
   double p_scale;              /* P0 of the learned guess p0 = p_prev + P0 delta,
                                   e.g. rho_w g depth; > 0 when x0 = NS_X0_LEARNED  */
+  /* Numerical wave tank (Sec. "Numerical wave tank"); all zero: a closed
+   * tank.  The tank generates the linear waves listed in waves[]:
+   * eta = sum a cos(kappa x - omega t + phase), with potential-flow velocity
+   * u = sum a omega cosh(kappa z)/sinh(kappa d) cos(.), w = sum a omega
+   * sinh(kappa z)/sinh(kappa d) sin(.) under the surface (z from the bed),
+   * none above it, v = 0.
+   *   gen_len > 0: the inlet face x = 0 carries that u (in place of a wall),
+   *     and after each step a generation zone x in [0, gen_len] relaxes u, v,
+   *     w and sigma toward the wave at t^{n+1}: phi <- a phi + (1 - a) phi_t,
+   *     a = 1 - (exp(chi^3.5) - 1)/(e - 1), chi = 1 - x / gen_len.
+   *   damp_len > 0: a damping zone x in [L - damp_len, L] relaxes them toward
+   *     still water (u = v = w = 0, sigma = z - depth), chi = (x - L +
+   *     damp_len) / damp_len.
+   *   vort_width > 0: the predictor adds the damping force -g u, g = rho_a
+   *     (cos(pi z~) + 1)/(4 dt), z~ = (z - z_top)/vort_width >= -1, implicitly. */
+  double depth;                /* still-water depth d (m), > 0 with zones       */
+  double gen_len, damp_len;    /* relaxation zone lengths (m), >= 0             */
+  double vort_width;           /* vorticity damping zone width (m), >= 0        */
+  int n_waves;                 /* 0..64                                         */
+  struct { double a, kappa, omega, phase; } waves[64];
 } ns_params;
 
 /* The caller's state arrays (device, FP64, layouts above); read and written

@@ -134,6 +134,18 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
     return snprintf(why, nwhy, "bad x0"), false;
   if (P->x0 == NS_X0_LEARNED && !(P->p_scale > 0.0))
     return snprintf(why, nwhy, "p_scale must be > 0 for the learned guess"), false;
+  if (!(P->gen_len >= 0.0 && P->damp_len >= 0.0 && P->vort_width >= 0.0) || !std::isfinite(P->gen_len) ||
+      !std::isfinite(P->damp_len) || !std::isfinite(P->vort_width))
+    return snprintf(why, nwhy, "wave tank zone sizes must be finite and >= 0"), false;
+  if (P->n_waves < 0 || P->n_waves > 64) return snprintf(why, nwhy, "n_waves must be 0..64"), false;
+  if ((P->gen_len > 0.0 || P->damp_len > 0.0) && !(P->depth > 0.0 && std::isfinite(P->depth)))
+    return snprintf(why, nwhy, "a wave tank with relaxation zones needs depth > 0"), false;
+  for (int q = 0; q < P->n_waves; ++q) {
+    const auto& W = P->waves[q];
+    if (!(std::isfinite(W.a) && std::isfinite(W.omega) && std::isfinite(W.phase) && W.kappa > 0.0 &&
+          std::isfinite(W.kappa)))
+      return snprintf(why, nwhy, "wave component %d: finite a, omega, phase and kappa > 0 needed", q), false;
+  }
   for (int m = 0; m < P->n_bodies; ++m) {
     const ns_body& B = P->body[m];
     if (B.kind != 0 && B.kind != 1) return snprintf(why, nwhy, "bad body kind"), false;
@@ -217,6 +229,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
   double* q = cv.take<double>(nc);
   double* part = cv.take<double>((size_t)4 * nparts);
   double* scal = cv.take<double>(S_COUNT);
+  double* waves = cv.take<double>(4 * 64);   // the wave tank's components
   const int L = count_levels(P->nx, P->ny, P->nz);
   Level lev[32];
   bool act[3] = {P->nx > 1, P->ny > 1, P->nz > 1};
@@ -324,6 +337,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     X->q = q;
     X->partials = part;
     X->scal = scal;
+    X->phys.waves = waves;
     X->nparts = nparts;
     X->L = L;
     for (int l = 0; l < L; ++l) X->lev[l] = lev[l];
@@ -354,6 +368,12 @@ Phys make_phys(const ns_params& P) {
   ph.inv_kp = P.inv_kappa_p;
   ph.pen_w = P.proj_penalty_weight;
   ph.nb = P.n_bodies;
+  ph.depth = P.depth;
+  ph.gen_len = P.gen_len;
+  ph.damp_len = P.damp_len;
+  ph.vort_w = P.vort_width;
+  ph.nwave = P.n_waves;
+  ph.waves = nullptr;   // set when the workspace is carved
   for (int m = 0; m < P.n_bodies; ++m) {
     const ns_body& B = P.body[m];
     ph.body[m] = BodyK{B.kind,          B.c[0],          B.c[1],      B.c[2],  B.half[0],
@@ -810,6 +830,13 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
   X->st = (hipStream_t)hip_stream;
   X->phys = make_phys(*params);
   carve(params, X, (char*)workspace);
+  if (params->n_waves > 0 &&
+      (hipMemcpyAsync(const_cast<double*>(X->phys.waves), params->waves, sizeof(double) * 4 * params->n_waves,
+                      hipMemcpyHostToDevice, X->st) != hipSuccess ||
+       hipStreamSynchronize(X->st) != hipSuccess)) {
+    delete X;
+    return NS_EHIP;
+  }
   // coherent and mapped: the reduction kernels store the values the host
   // tests straight into it, so reading them needs no copy
   if (hipHostMalloc((void**)&X->host, S_COUNT * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped) !=
@@ -1124,6 +1151,8 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   }
   const Level& L0 = X->lev[0];
   launch_correct(ph, X->us, X->vs, X->ws, X->F.p, L0.bx, L0.by, L0.bz, dt, X->F.u, X->F.v, X->F.w, st);
+  // the wave tank's relaxation zones, at the time of the step's properties
+  launch_relax(ph, X->t_props, X->F.sigma, X->F.u, X->F.v, X->F.w, st);
   // the hydrodynamic force of the new fields, for the next heave update
   int nb[4];
   if (X->nfree > 0 && free_forces_queue(X, nb) != 0)

@@ -27,6 +27,8 @@ inline Geo geo3(int mx, int my, int mz) {
   return {dim3((mx + 63) / 64, (my + b.y - 1) / b.y, (mz + b.z - 1) / b.z), b};
 }
 
+constexpr double kE = 2.718281828459045235360287471352662;   // e
+
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
 // cell value with clamped indices
@@ -98,6 +100,44 @@ __device__ double body_psi(const Phys& P, double x, double y, double z, double t
   }
   *zdot = zd_best;
   return best;
+}
+
+// --------------------------------------------------------------------------
+// numerical wave tank (Sec. "Numerical wave tank")
+// --------------------------------------------------------------------------
+// the generated wave: elevation, and horizontal (c = 0) or vertical (c = 2)
+// potential-flow velocity under the surface at (x, z from the bed, t)
+__device__ double tank_eta(const Phys& P, double x, double t) {
+  double eta = 0.0;
+  for (int q = 0; q < P.nwave; ++q) {
+    const double* W = P.waves + 4 * q;
+    eta += W[0] * cos(W[1] * x - W[2] * t + W[3]);
+  }
+  return eta;
+}
+
+__device__ double tank_vel(const Phys& P, int c, double x, double z, double t) {
+  if (c == 1 || z >= P.depth + tank_eta(P, x, t)) return 0.0;
+  double s = 0.0;
+  for (int q = 0; q < P.nwave; ++q) {
+    const double* W = P.waves + 4 * q;
+    const double th = W[1] * x - W[2] * t + W[3];
+    const double amp = W[0] * W[2] / sinh(W[1] * P.depth);
+    s += (c == 0) ? amp * cosh(W[1] * z) * cos(th) : amp * sinh(W[1] * z) * sin(th);
+  }
+  return s;
+}
+
+// relaxation weight (the relaxation-zone method): 1 at the inner edge, 0 at the end
+__device__ __forceinline__ double relax_weight(double chi) {
+  return 1.0 - (exp(pow(chi, 3.5)) - 1.0) / (kE - 1.0);
+}
+
+// vorticity damping coefficient over the top vort_w of the tank
+__device__ __forceinline__ double vort_coeff(const Phys& P, double z, double dt) {
+  if (P.vort_w <= 0.0) return 0.0;
+  const double zt = (z - P.n.nz * P.h) / P.vort_w;
+  return zt < -1.0 ? 0.0 : P.rho_a * (cos(kPi * zt) + 1.0) / (4.0 * dt);
 }
 
 // --------------------------------------------------------------------------
@@ -293,7 +333,8 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
   const size_t f = i + (size_t)mx * (j + (size_t)my * k);
   const bool wall = (C == 0) ? (i == 0 || i == n.nx) : (C == 1) ? (j == 0 || j == n.ny) : (k == 0);
   if (wall) {
-    out[f] = 0.0;
+    // the inlet of a wave tank carries the generated wave's velocity
+    out[f] = (C == 0 && i == 0 && P.gen_len > 0.0) ? tank_vel(P, 0, 0.0, (k + 0.5) * P.h, t1) : 0.0;
     beta[f] = 0.0;
     betaf[f] = 0.0f;
     return;
@@ -313,7 +354,8 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
   if (C == 2 && P.nb > 0) body_psi(P, (i + 0.5) * P.h, (j + 0.5) * P.h, k * P.h, t1, &ub);
   const double grav = (C == 2) ? -P.g * rff : 0.0;
   const double pen = xf * P.inv_kp;
-  out[f] = (rf * (uf / dt - adv) + visc + grav + pen * ub) / (rf / dt + pen);
+  const double damp = vort_coeff(P, (C == 2) ? k * P.h : (k + 0.5) * P.h, dt);   // -g u, implicit
+  out[f] = (rf * (uf / dt - adv) + visc + grav + pen * ub) / (rf / dt + pen + damp);
   const double bt = 1.0 / (rf + P.pen_w * dt * pen);
   beta[f] = bt;
   betaf[f] = (float)bt;
@@ -355,7 +397,7 @@ __global__ void __launch_bounds__(256) k_correct(Phys P, const double* __restric
   const size_t f = i + (size_t)mx * (j + (size_t)my * k);
   const bool wall = (C == 0) ? (i == 0 || i == n.nx) : (C == 1) ? (j == 0 || j == n.ny) : (k == 0);
   if (wall) {
-    u[f] = 0.0;
+    u[f] = (C == 0 && i == 0 && P.gen_len > 0.0) ? us[f] : 0.0;   // a tank's inlet keeps its wave
     return;
   }
   const double ih = 1.0 / P.h;
@@ -366,6 +408,47 @@ __global__ void __launch_bounds__(256) k_correct(Phys P, const double* __restric
     grad = (cv(p, n, i, j, k) - cv(p, n, i - ci, j - cj, k - ck)) * ih;
   }
   u[f] = us[f] - dt * beta[f] * grad;
+}
+
+// The wave tank's relaxation zones after a step: phi <- a phi + (1 - a) target
+// over the columns of the generation zone [0, gen_len] (target: the wave at
+// t) and of the damping zone [L - damp_len, L] (still water).  The launch
+// covers only those columns: column q < ng is x-index q, the others
+// x-index i_damp + (q - ng).  C = 0, 1, 2: the velocity faces; C = 3: sigma.
+template <int C>
+__global__ void __launch_bounds__(256) k_relax(Phys P, double t, int ng, int i_damp, int ncol,
+                                               double* __restrict__ a) {
+  const Dims n = P.n;
+  const int my = n.ny + (C == 1), mz = n.nz + (C == 2), mx = n.nx + (C == 0);
+  const Tile tl = xcd_tile();
+  const int q = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
+  if (q >= ncol || j >= my || k >= mz) return;
+  const int i = q < ng ? q : i_damp + (q - ng);
+  if (i >= mx) return;
+  const double h = P.h;
+  const double x = (C == 0) ? i * h : (i + 0.5) * h;
+  const double z = (C == 2) ? k * h : (k + 0.5) * h;
+  const double L = n.nx * h;
+  bool gen;
+  double al;
+  if (P.gen_len > 0.0 && x <= P.gen_len) {
+    gen = true;
+    al = relax_weight(1.0 - x / P.gen_len);
+  } else if (P.damp_len > 0.0 && x >= L - P.damp_len) {
+    gen = false;
+    al = relax_weight((x - (L - P.damp_len)) / P.damp_len);
+  } else {
+    return;
+  }
+  double target;
+  if constexpr (C == 3)
+    target = z - (P.depth + (gen ? tank_eta(P, x, t) : 0.0));
+  else
+    target = gen ? tank_vel(P, C, x, z, t) : 0.0;
+  const size_t f = i + (size_t)mx * (j + (size_t)my * k);
+  a[f] = al * a[f] + (1.0 - al) * target;
 }
 
 // Hydrodynamic force on body m, eqn_int_fh (Sec. "Fluid-structure
@@ -646,6 +729,27 @@ int launch_hydro_force(const Phys& P, int m, double t, const double* p, const do
   hipLaunchKernelGGL(k_hydro_force, g.grid, g.block, 0, st, P, m, a[0], a[1], a[2], e[0], e[1], e[2], t, p, u, v,
                      w, mu, partials);
   return (int)blocks;
+}
+
+void launch_relax(const Phys& P, double t, double* sigma, double* u, double* v, double* w, hipStream_t st) {
+  if (!(P.gen_len > 0.0) && !(P.damp_len > 0.0)) return;
+  // columns that can lie in a zone: x-index 0..ng-1 (generation) and
+  // i_damp..nx (damping), one spare column each way for the face arrays
+  const double h = P.h;
+  const int nx = P.n.nx;
+  const int ng = P.gen_len > 0.0 ? std::min(nx + 1, (int)std::floor(P.gen_len / h) + 2) : 0;
+  const int i_damp = P.damp_len > 0.0 ? std::max(ng, (int)std::floor((nx * h - P.damp_len) / h) - 1) : nx + 1;
+  const int ncol = ng + std::max(0, nx + 1 - i_damp);
+  if (ncol <= 0) return;
+  Geo gu = geo3(ncol, P.n.ny, P.n.nz);
+  hipLaunchKernelGGL(k_relax<0>, gu.grid, gu.block, 0, st, P, t, ng, i_damp, ncol, u);
+  if (P.n.ny > 1) {
+    Geo gv = geo3(ncol, P.n.ny + 1, P.n.nz);
+    hipLaunchKernelGGL(k_relax<1>, gv.grid, gv.block, 0, st, P, t, ng, i_damp, ncol, v);
+  }
+  Geo gw = geo3(ncol, P.n.ny, P.n.nz + 1);
+  hipLaunchKernelGGL(k_relax<2>, gw.grid, gw.block, 0, st, P, t, ng, i_damp, ncol, w);
+  hipLaunchKernelGGL(k_relax<3>, gu.grid, gu.block, 0, st, P, t, ng, i_damp, ncol, sigma);
 }
 
 }  // namespace nsk

@@ -58,6 +58,11 @@ struct Phys {
   double pen_w;    // projection penalty weight
   int nb;
   BodyK body[4];
+  // numerical wave tank: zones (0: none), still-water depth, the generated
+  // wave's components (device array: a, kappa, omega, phase per component)
+  double depth, gen_len, damp_len, vort_w;
+  int nwave;
+  const double* waves;
 };
 
 // One multigrid level.  Level 0 of the FP64 hierarchy aliases the CG
@@ -157,6 +162,8 @@ void launch_correct(const Phys& P, const double* us, const double* vs, const dou
 int launch_diag_partials(const Phys& P, const double* sigma, const double* u, const double* v,
                          const double* w, double* partials, hipStream_t st);
 void launch_diag_finalize(const double* partials, int nparts, double* scal, hipStream_t st);
+// relaxation zones of the wave tank at time t, in place (no-op without zones)
+void launch_relax(const Phys& P, double t, double* sigma, double* u, double* v, double* w, hipStream_t st);
 // hydrodynamic force on body m over the cells of its bounding box: three
 // per-block partials (Fx, Fy, Fz) in tile order; returns the block count, or
 // -1 without launching when it would exceed max_blocks

@@ -31,6 +31,10 @@ class NSBody(C.Structure):
                 ("zeta0", C.c_double), ("zdot0", C.c_double)]
 
 
+class NSWave(C.Structure):
+    _fields_ = [("a", C.c_double), ("kappa", C.c_double), ("omega", C.c_double), ("phase", C.c_double)]
+
+
 class NSParams(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
                 ("rho_w", C.c_double), ("mu_w", C.c_double), ("rho_a", C.c_double), ("mu_a", C.c_double),
@@ -40,7 +44,9 @@ class NSParams(C.Structure):
                 ("reinit_iters", C.c_int), ("reinit_dtau_over_h", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_sweeps", C.c_int),
                 ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int), ("x0", C.c_int),
-                ("p_scale", C.c_double)]
+                ("p_scale", C.c_double),
+                ("depth", C.c_double), ("gen_len", C.c_double), ("damp_len", C.c_double),
+                ("vort_width", C.c_double), ("n_waves", C.c_int), ("waves", NSWave * 64)]
 
 
 class NSFields(C.Structure):
@@ -150,6 +156,14 @@ def params(wl, **opts) -> NSParams:
             b.heave_amp, b.heave_omega, b.heave_phase)
         P.body[m].free_heave, P.body[m].mass, P.body[m].pto_damping = int(b.free_heave), b.mass, b.pto_damping
         P.body[m].zeta0, P.body[m].zdot0 = b.zeta0, b.zdot0
+    P.depth = wl.depth
+    if wl.nwt:                                      # numerical wave tank
+        from . import inputs as I
+        P.gen_len, P.damp_len, P.vort_width = wl.nwt.get("gen", 0.0), wl.nwt.get("damp", 0.0), wl.nwt.get("vort", 0.0)
+        a, k, om, ph = I.wave_components(wl)
+        P.n_waves = len(a)
+        for q in range(len(a)):
+            P.waves[q].a, P.waves[q].kappa, P.waves[q].omega, P.waves[q].phase = a[q], k[q], om[q], ph[q]
     o = dict(SOLVER_DEFAULTS)
     o["p_scale"] = wl.rho_w * wl.g * wl.depth      # P0 = rho_w g d
     o.update(opts)
