@@ -228,6 +228,13 @@ def workload(name: str, **over) -> Workload:
                       256, 1, 64, 8.0 / 256, 1.0, {"kind": "airy", "a": 0.02, "T": 1.0, "phase": 0.0},
                       [Body(0, (4.0, 0.0, 1.0), (0.2, 0.0, 0.1))], steps=10, seed=1,
                       nwt={"gen": lam, "damp": 1.5 * lam, "vort": 4 * 8.0 / 256})
+    elif name == "c2nwt":
+        # the C2 tank as a wave tank: Airy waves generated at x = 0 (the tank is
+        # 1.8 wavelengths long, so the zones are 0.8 and 1.2 m)
+        wl = Workload("c2nwt: 3-D wave tank 128x64x64 (4x2x2 m, h=1/32), Airy a=0.05 m T=1.2 s generated at x=0, "
+                      "zones 0.8 and 1.2 m, vorticity damping 4 cells, fixed cylinder",
+                      128, 64, 64, 4.0 / 128, 1.0, {"kind": "airy", "a": 0.05, "T": 1.2, "phase": 0.0}, [_cyl()],
+                      steps=20, seed=2, nwt={"gen": 0.8, "damp": 1.2, "vort": 4 * 4.0 / 128})
     elif name == "nwt3d":
         lam = 2.0 * math.pi / wavenumber(2.0 * math.pi / 1.2, 1.0, G)
         wl = Workload("nwt3d: 3-D wave tank 32x16x16 (4x2x2 m), Airy a=0.05 T=1.2 s generated at x=0, "
