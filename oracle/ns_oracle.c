@@ -334,8 +334,35 @@ void orc_relax(const orc_params* P, double t, double* sigma, double* u, double* 
  * viscous stress use u^n.  Face values of rho, rho^flow and chi are the
  * mean of the two adjacent cells; edge viscosities the mean of four.
  * ------------------------------------------------------------------------ */
+/* With rho_n (cell density at t^n) the predictor takes the conservative form
+ * of eqn_c_discrete_momentum with consistent mass/momentum transport (Sec.
+ * "Multiphase incompressible Navier-Stokes solution"): the face density is
+ * carried over the step by the same mass fluxes that carry momentum,
+ *   rb_f = rho^n_f - dt/h sum (m_+ - m_-),  m = a rho_upwind(rho^n_f),
+ *   (rb_f u*_f - rho^n_f u^n_f)/dt + 1/h sum (m_+ v_+ - m_- v_-) = forces,
+ * with the Koren-limited upwind face density and velocity of the advective
+ * form; rb (face arrays, may be NULL) receives rb_f.  Without rho_n it is
+ * the advective form above. */
+static void momentum_impl(const orc_params* P, const double* u, const double* v, const double* w,
+                          const double* sigma, double t_np1, double dt, const double* rho_n, double* us,
+                          double* vs, double* ws, double* const rb[3]);
+
 void orc_momentum(const orc_params* P, const double* u, const double* v, const double* w,
                   const double* sigma, double t_np1, double dt, double* us, double* vs, double* ws) {
+  double* const none[3] = {NULL, NULL, NULL};
+  momentum_impl(P, u, v, w, sigma, t_np1, dt, NULL, us, vs, ws, none);
+}
+
+void orc_momentum_cons(const orc_params* P, const double* u, const double* v, const double* w,
+                       const double* sigma, double t_np1, double dt, const double* rho_n, double* us, double* vs,
+                       double* ws, double* rbx, double* rby, double* rbz) {
+  double* const rb[3] = {rbx, rby, rbz};
+  momentum_impl(P, u, v, w, sigma, t_np1, dt, rho_n, us, vs, ws, rb);
+}
+
+static void momentum_impl(const orc_params* P, const double* u, const double* v, const double* w,
+                          const double* sigma, double t_np1, double dt, const double* rho_n, double* us,
+                          double* vs, double* ws, double* const rb[3]) {
   const size_t n = ncell(P);
   const double h = P->h;
   double* rho = (double*)malloc(n * sizeof(double));
@@ -360,13 +387,18 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
           }
           if (is_wall_face(P, c, i, j, k)) {
             out[c][f] = 0.0;
+            if (rho_n && rb[c]) rb[c][f] = 0.0;
             continue;
           }
           double uf = F[c][f];
-          double adv = 0.0, visc = 0.0;
+          double adv = 0.0, visc = 0.0, conv = 0.0, mflux = 0.0;
           for (int d = 0; d < 3; ++d) {
             int ed[3] = {d == 0, d == 1, d == 2};
 #define FC(o) facev(P, c, F[c], i + (o) * ed[0], j + (o) * ed[1], k + (o) * ed[2])
+/* face density at t^n of the face o steps along d: mean of its two cells */
+#define RF(o)                                                                                        \
+  (0.5 * (cellv(P, rho_n, i - ec[0] + (o) * ed[0], j - ec[1] + (o) * ed[1], k - ec[2] + (o) * ed[2]) + \
+          cellv(P, rho_n, i + (o) * ed[0], j + (o) * ed[1], k + (o) * ed[2])))
             /* advecting velocities on the + and - sides of the control volume */
             double ap, am;
             if (d == c) {
@@ -381,6 +413,14 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
             double vp = ap >= 0.0 ? koren(FC(-1), FC(0), FC(1)) : koren(FC(2), FC(1), FC(0));
             double vm = am >= 0.0 ? koren(FC(-2), FC(-1), FC(0)) : koren(FC(1), FC(0), FC(-1));
             adv += ap * (vp - uf) - am * (vm - uf);
+            if (rho_n) {
+              /* mass fluxes with the same upwinding, and the momentum they carry */
+              double rp = ap >= 0.0 ? koren(RF(-1), RF(0), RF(1)) : koren(RF(2), RF(1), RF(0));
+              double rm = am >= 0.0 ? koren(RF(-2), RF(-1), RF(0)) : koren(RF(1), RF(0), RF(-1));
+              double mp = ap * rp, mm = am * rm;
+              conv += mp * vp - mm * vm;
+              mflux += mp - mm;
+            }
 
             /* viscous stress on the + and - sides */
             double tp, tm;
@@ -422,6 +462,14 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
           double pen = chif * P->inv_kappa_p;
           /* vorticity damping force -g(z~) u, taken implicitly like the penalty */
           double damp = vort_damp(P, (c == 2) ? k * h : (k + 0.5) * h, dt);
+          if (rho_n) {
+            double r0 = 0.5 * (cellv(P, rho_n, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, rho_n, i, j, k));
+            double rbf = r0 - dt * mflux / h;
+            double num = r0 * uf / dt - conv / h + visc + grav + pen * ub;
+            out[c][f] = num / (rbf / dt + pen + damp);
+            if (rb[c]) rb[c][f] = rbf;
+            continue;
+          }
           double num = rhof * (uf / dt - adv) + visc + grav + pen * ub;
           out[c][f] = num / (rhof / dt + pen + damp);
         }
@@ -431,6 +479,7 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
   free(mu);
   free(chi);
 }
+#undef RF
 
 /* --------------------------------------------------------------------------
  * Projection coefficient on faces: beta_f = 1/(rho_f + w dt chi_f/kappa_p),
@@ -458,6 +507,35 @@ void orc_face_beta(const orc_params* P, const double* sigma, double t_np1, doubl
           double rhof = 0.5 * (cellv(P, rho, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, rho, i, j, k));
           double chif = 0.5 * (cellv(P, chi, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, chi, i, j, k));
           out[c][f] = 1.0 / (rhof + P->proj_penalty_weight * dt * chif * P->inv_kappa_p);
+        }
+  }
+  free(rho);
+  free(chi);
+}
+
+/* beta_f = 1/(rb_f + w dt chi_f/kappa_p) with the transported face density
+ * rb_f of the consistent form (walls 0) */
+void orc_face_beta_rho(const orc_params* P, const double* rbx, const double* rby, const double* rbz,
+                       const double* sigma, double t_np1, double dt, double* bx, double* by, double* bz) {
+  const size_t n = ncell(P);
+  double* rho = (double*)malloc(n * sizeof(double));
+  double* chi = (double*)malloc(n * sizeof(double));
+  orc_properties(P, sigma, t_np1, rho, NULL, NULL, chi);
+  const double* rb[3] = {rbx, rby, rbz};
+  double* out[3] = {bx, by, bz};
+  for (int c = 0; c < 3; ++c) {
+    int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
+    int ec[3] = {c == 0, c == 1, c == 2};
+    for (int k = 0; k < mz; ++k)
+      for (int j = 0; j < my; ++j)
+        for (int i = 0; i < mx; ++i) {
+          size_t f = i + (size_t)mx * (j + (size_t)my * k);
+          if (is_wall_face(P, c, i, j, k)) {
+            out[c][f] = 0.0;
+            continue;
+          }
+          double chif = 0.5 * (cellv(P, chi, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, chi, i, j, k));
+          out[c][f] = 1.0 / (rb[c][f] + P->proj_penalty_weight * dt * chif * P->inv_kappa_p);
         }
   }
   free(rho);
@@ -709,6 +787,11 @@ void orc_correct(const orc_params* P, const double* us, const double* vs, const 
 int orc_step(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,
              double dt, double t_n, int x0_prev, orc_stats* st) {
   const size_t n = ncell(P);
+  double* rho_n = NULL;
+  if (P->consistent) {  /* the density the step starts from */
+    rho_n = (double*)malloc(n * sizeof(double));
+    orc_properties(P, sigma, t_n, rho_n, NULL, NULL, NULL);
+  }
   double* s1 = (double*)malloc(n * sizeof(double));
   orc_levelset_advect(P, sigma, u, v, w, dt, s1);
   orc_reinit(P, s1, sigma);
@@ -722,8 +805,20 @@ int orc_step(const orc_params* P, double* sigma, double* u, double* v, double* w
   double* by = (double*)malloc(nv * sizeof(double));
   double* bz = (double*)malloc(nw * sizeof(double));
   double* b = (double*)malloc(n * sizeof(double));
-  orc_momentum(P, u, v, w, sigma, t1, dt, us, vs, ws);
-  orc_face_beta(P, sigma, t1, dt, bx, by, bz);
+  if (P->consistent) {
+    double* rbx = (double*)malloc(nu * sizeof(double));
+    double* rby = (double*)malloc(nv * sizeof(double));
+    double* rbz = (double*)malloc(nw * sizeof(double));
+    orc_momentum_cons(P, u, v, w, sigma, t1, dt, rho_n, us, vs, ws, rbx, rby, rbz);
+    orc_face_beta_rho(P, rbx, rby, rbz, sigma, t1, dt, bx, by, bz);
+    free(rbx);
+    free(rby);
+    free(rbz);
+    free(rho_n);
+  } else {
+    orc_momentum(P, u, v, w, sigma, t1, dt, us, vs, ws);
+    orc_face_beta(P, sigma, t1, dt, bx, by, bz);
+  }
   orc_rhs(P, us, vs, ws, dt, b);
   if (!x0_prev) memset(p, 0, n * sizeof(double));
   int rc = orc_pcg(P, bx, by, bz, b, p, st);

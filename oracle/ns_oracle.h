@@ -52,6 +52,8 @@ typedef struct {
   double vort_width;           /* vorticity damping zone width below the top     */
   int n_waves;                 /* generated linear components (<= 64)            */
   double wave_a[64], wave_k[64], wave_om[64], wave_ph[64];
+  int consistent;              /* 1: conservative predictor with consistent       */
+                               /*    mass/momentum transport                     */
 } orc_params;
 
 typedef struct {
@@ -69,6 +71,13 @@ void orc_momentum(const orc_params* P, const double* u, const double* v, const d
                   const double* sigma, double t_np1, double dt, double* us, double* vs, double* ws);
 void orc_face_beta(const orc_params* P, const double* sigma, double t_np1, double dt, double* bx,
                    double* by, double* bz);
+/* the conservative predictor with consistent transport: u* and the face
+ * density rb carried over the step (rho_n: cell density at t^n) */
+void orc_momentum_cons(const orc_params* P, const double* u, const double* v, const double* w,
+                       const double* sigma, double t_np1, double dt, const double* rho_n, double* us, double* vs,
+                       double* ws, double* rbx, double* rby, double* rbz);
+void orc_face_beta_rho(const orc_params* P, const double* rbx, const double* rby, const double* rbz,
+                       const double* sigma, double t_np1, double dt, double* bx, double* by, double* bz);
 void orc_rhs(const orc_params* P, const double* us, const double* vs, const double* ws, double dt,
              double* b);
 void orc_apply_A(int nx, int ny, int nz, double h, const double* bx, const double* by,

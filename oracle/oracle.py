@@ -47,7 +47,7 @@ class Params(C.Structure):
                 ("depth", C.c_double), ("gen_len", C.c_double), ("damp_len", C.c_double),
                 ("vort_width", C.c_double), ("n_waves", C.c_int),
                 ("wave_a", C.c_double * 64), ("wave_k", C.c_double * 64), ("wave_om", C.c_double * 64),
-                ("wave_ph", C.c_double * 64)]
+                ("wave_ph", C.c_double * 64), ("consistent", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -88,6 +88,8 @@ def lib():
             "orc_hydro_force": [P, C.c_int, dp, dp, dp, dp, dp, d, dp],
             "orc_heave_update": [d, d, d, d, d, dp, dp],
             "orc_relax": [P, d, dp, dp, dp, dp],
+            "orc_momentum_cons": [P, dp, dp, dp, dp, d, d, dp, dp, dp, dp, dp, dp, dp],
+            "orc_face_beta_rho": [P, dp, dp, dp, dp, d, d, dp, dp, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -129,6 +131,7 @@ def params(wl, **solver) -> Params:
             int(b.free_heave), b.mass, b.pto_damping
         P.body[m].zeta, P.body[m].zdot = b.zeta0, b.zdot0
     P.depth = wl.depth
+    P.consistent = int(wl.consistent)
     if wl.nwt:
         from paper_2206_07732_amd.inputs import wave_components
         P.gen_len, P.damp_len, P.vort_width = wl.nwt.get("gen", 0.0), wl.nwt.get("damp", 0.0), wl.nwt.get("vort", 0.0)
@@ -281,3 +284,21 @@ def relax(P, t, fields):
     f = {k: _arr(fields[k]).copy() for k in ("sigma", "u", "v", "w")}
     lib().orc_relax(C.byref(P), t, _p(f["sigma"]), _p(f["u"]), _p(f["v"]), _p(f["w"]))
     return f
+
+
+def momentum_cons(P, u, v, w, sigma, t_np1, dt, rho_n):
+    """Conservative predictor with consistent transport: (u*, v*, w*) and the
+    transported face densities (rbx, rby, rbz)."""
+    sigma, u, v, w, rho_n = map(_arr, (sigma, u, v, w, rho_n))
+    us, vs, ws = np.empty_like(u), np.empty_like(v), np.empty_like(w)
+    rb = [np.empty_like(u), np.empty_like(v), np.empty_like(w)]
+    lib().orc_momentum_cons(C.byref(P), _p(u), _p(v), _p(w), _p(sigma), t_np1, dt, _p(rho_n), _p(us), _p(vs),
+                            _p(ws), *[_p(a) for a in rb])
+    return (us, vs, ws), tuple(rb)
+
+
+def face_beta_rho(P, rb, sigma, t_np1, dt):
+    rb = [_arr(a) for a in rb]
+    out = [np.empty_like(a) for a in rb]
+    lib().orc_face_beta_rho(C.byref(P), *[_p(a) for a in rb], _p(_arr(sigma)), t_np1, dt, *[_p(a) for a in out])
+    return tuple(out)

@@ -144,6 +144,7 @@ class Workload:
     dt_max: float = 0.05
     p_init: str = "zero"            # initial pressure: "zero", or "hydrostatic" under the initial surface
     nwt: Optional[dict] = None      # numerical wave tank: {"gen": m, "damp": m, "vort": m} zone sizes
+    consistent: int = 0             # 1: conservative predictor with consistent mass/momentum transport
 
     @property
     def dim(self) -> int:

@@ -726,3 +726,60 @@ def test_vorticity_damping_in_the_predictor(orc):
     assert np.all(interior[:12] == U)
     assert np.max(np.abs(interior[15] / (U / (1 + (math.cos(math.pi / 8) + 1) / 4)) - 1)) < 1e-14
     assert np.all(np.diff(interior[11:, 0]) < 0)
+
+
+# ---------------------------------------------------------------------------
+# Consistent mass/momentum transport (Sec. "Multiphase incompressible
+# Navier-Stokes solution", conservative eqn_c_discrete_momentum)
+# ---------------------------------------------------------------------------
+def _tilted_tank(orc, n=16):
+    """2-D n x n tank (h = 1/8) with a tilted water surface and a velocity
+    blob that vanishes within four cells of every wall, so that no mass or
+    momentum flux crosses the walls."""
+    h = 0.125
+    wl = flat_wl(nx=n, nz=n, h=h, depth=1.0, consistent=1)
+    P = orc.params(wl)
+    x, y, z = cell_centres(wl)
+    sigma = z - (0.9 + 0.15 * (x - 1.0))
+    _, u, v, w = zeros(wl)
+    L = n * h
+    def bump(s):
+        a, b = 4 * h, L - 4 * h
+        t = np.clip((s - a) / (b - a), 0.0, 1.0)
+        return np.sin(np.pi * t) ** 2
+    xf, zc = np.arange(n + 1) * h, (np.arange(n) + 0.5) * h
+    u[:, 0, :] = 0.4 * bump(xf)[None, :] * bump(zc)[:, None]
+    xc, zf = (np.arange(n) + 0.5) * h, np.arange(n + 1) * h
+    w[:, 0, :] = -0.3 * bump(xc)[None, :] * bump(zf)[:, None] * np.cos(3 * xc)[None, :]
+    return wl, P, sigma, u, v, w
+
+
+def test_consistent_transport_conserves_face_mass_and_momentum(orc):
+    """With no flux through the walls and no force along x, the transported
+    face densities keep their sum and the x-momentum sum rb u* equals the
+    starting sum rho^n_f u^n (the fluxes and the viscous stresses telescope).
+    The advective form, with the same state, does not conserve momentum."""
+    wl, P, sigma, u, v, w = _tilted_tank(orc)
+    dt = 0.01
+    rho_n = orc.properties(P, sigma, 0.0)[0]
+    (us, vs, ws), (rbx, rby, rbz) = orc.momentum_cons(P, u, v, w, sigma, dt, dt, rho_n)
+    rho_f = 0.5 * (rho_n[:, :, :-1] + rho_n[:, :, 1:])          # interior x-faces
+    assert abs(rbx[:, :, 1:-1].sum() / rho_f.sum() - 1) < 1e-14
+    mom0 = (rho_f * u[:, :, 1:-1]).sum()
+    mom1 = (rbx[:, :, 1:-1] * us[:, :, 1:-1]).sum()
+    scale = (rho_f * np.abs(u[:, :, 1:-1])).sum()
+    assert abs(mom1 - mom0) < 1e-13 * scale
+    us_adv, _, _ = orc.momentum(P, u, v, w, sigma, dt, dt)
+    assert abs((rho_f * us_adv[:, :, 1:-1]).sum() - mom0) > 1e-6 * scale
+
+
+def test_consistent_transport_keeps_a_uniform_velocity_across_the_interface(orc):
+    """A uniform horizontal velocity U across the water-air interface (837:1)
+    stays U on every face away from the walls: the momentum it carries is the
+    mass flux times U."""
+    wl, P, sigma, u, v, w = _tilted_tank(orc)
+    u[:] = 0.25
+    w[:] = 0.0
+    rho_n = orc.properties(P, sigma, 0.0)[0]
+    (us, _, _), _ = orc.momentum_cons(P, u, v, w, sigma, 0.01, 0.01, rho_n)
+    assert np.max(np.abs(us[3:-3, :, 4:-4] - 0.25)) < 1e-14
