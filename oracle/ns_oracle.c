@@ -334,6 +334,100 @@ void orc_relax(const orc_params* P, double t, double* sigma, double* u, double* 
  * viscous stress use u^n.  Face values of rho, rho^flow and chi are the
  * mean of the two adjacent cells; edge viscosities the mean of four.
  * ------------------------------------------------------------------------ */
+/* Viscous stress of component c along direction d at face (i, j, k),
+ * ((tau_+) - (tau_-))/h with tau = mu (du_c/dx_d + du_d/dx_c) on the edges
+ * (mean of four cell viscosities) or 2 mu du_c/dx_c at the cell centres
+ * (d = c).  diag (may be NULL) receives the magnitude of the coefficient of
+ * the face's own value in the interior stencil. */
+static double visc_dir(const orc_params* P, const double* mu, const double* const F[3], int c, int d, int i, int j,
+                       int k, double* diag) {
+  const double h = P->h;
+  int ec[3] = {c == 0, c == 1, c == 2};
+  int ed[3] = {d == 0, d == 1, d == 2};
+#define FV(o) facev(P, c, F[c], i + (o) * ed[0], j + (o) * ed[1], k + (o) * ed[2])
+  double tp, tm;
+  if (d == c) {
+    /* normal stress 2 mu du_c/dx_c at the cell centres either side */
+    double mup = cellv(P, mu, i, j, k);
+    double mum = cellv(P, mu, i - ec[0], j - ec[1], k - ec[2]);
+    tp = 2.0 * mup * (FV(1) - FV(0)) / h;
+    tm = 2.0 * mum * (FV(0) - FV(-1)) / h;
+    if (diag) *diag = 2.0 * (mup + mum) / (h * h);
+  } else {
+    /* shear stress mu (du_c/dx_d + du_d/dx_c) on the edges either side */
+    double mep = 0.25 * (cellv(P, mu, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, mu, i, j, k) +
+                         cellv(P, mu, i - ec[0] + ed[0], j - ec[1] + ed[1], k - ec[2] + ed[2]) +
+                         cellv(P, mu, i + ed[0], j + ed[1], k + ed[2]));
+    double mem = 0.25 * (cellv(P, mu, i - ec[0] - ed[0], j - ec[1] - ed[1], k - ec[2] - ed[2]) +
+                         cellv(P, mu, i - ed[0], j - ed[1], k - ed[2]) +
+                         cellv(P, mu, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, mu, i, j, k));
+    double dudp = (FV(1) - FV(0)) / h;
+    double dudm = (FV(0) - FV(-1)) / h;
+    double dvp = (facev(P, d, F[d], i + ed[0], j + ed[1], k + ed[2]) -
+                  facev(P, d, F[d], i + ed[0] - ec[0], j + ed[1] - ec[1], k + ed[2] - ec[2])) / h;
+    double dvm = (facev(P, d, F[d], i, j, k) - facev(P, d, F[d], i - ec[0], j - ec[1], k - ec[2])) / h;
+    tp = mep * (dudp + dvp);
+    tm = mem * (dudm + dvm);
+    if (diag) *diag = (mep + mem) / (h * h);
+  }
+#undef FV
+  return (tp - tm) / h;
+}
+
+/* Crank-Nicolson viscous term (Sec. "Time stepping scheme"): each face that
+ * is not a wall or the inlet solves
+ *   D_f u*_f - 1/2 L(u*)_f = rhs_f,
+ * rhs_f holding the explicit terms and 1/2 L(u^n)_f, D_f the implicit
+ * diagonal (D_f = 0 marks a fixed face).  The system is solved by point-Jacobi
+ * sweeps from the iterate in out, each
+ *   u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f)) / (D_f + 1/2 a_f),
+ * every component from the previous iterate, with a_f the magnitude of the
+ * interior diagonal of L; fixed faces keep their values. */
+static void cn_sweeps(const orc_params* P, const double* mu, double* const rhs[3], double* const D[3],
+                      double* const out[3]) {
+  double* cur[3];
+  double* nxt[3];
+  for (int c = 0; c < 3; ++c) {
+    cur[c] = out[c];
+    nxt[c] = (double*)malloc(face_count(P, c) * sizeof(double));
+  }
+  for (int s = 0; s < P->cn_sweeps; ++s) {
+    const double* F[3] = {cur[0], cur[1], cur[2]};
+    for (int c = 0; c < 3; ++c) {
+      int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
+      for (int k = 0; k < mz; ++k)
+        for (int j = 0; j < my; ++j)
+          for (int i = 0; i < mx; ++i) {
+            size_t f = i + (size_t)mx * (j + (size_t)my * k);
+            if (D[c][f] == 0.0) {
+              nxt[c][f] = cur[c][f];
+              continue;
+            }
+            double L = 0.0, a = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              double ad;
+              L += visc_dir(P, mu, F, c, d, i, j, k, &ad);
+              a += ad;
+            }
+            nxt[c][f] = (rhs[c][f] + 0.5 * (L + a * cur[c][f])) / (D[c][f] + 0.5 * a);
+          }
+    }
+    for (int c = 0; c < 3; ++c) {
+      double* t = cur[c];
+      cur[c] = nxt[c];
+      nxt[c] = t;
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    if (cur[c] != out[c]) {
+      memcpy(out[c], cur[c], face_count(P, c) * sizeof(double));
+      free(cur[c]);
+    } else {
+      free(nxt[c]);
+    }
+  }
+}
+
 /* With rho_n (cell density at t^n) the predictor takes the conservative form
  * of eqn_c_discrete_momentum with consistent mass/momentum transport (Sec.
  * "Multiphase incompressible Navier-Stokes solution"): the face density is
@@ -372,6 +466,16 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
   orc_properties(P, sigma, t_np1, rho, rfl, mu, chi);
   const double* F[3] = {u, v, w};
   double* out[3] = {us, vs, ws};
+  /* Crank-Nicolson: half the viscous term at t^n goes to the right-hand side */
+  const int cn = P->cn_sweeps > 0;
+  const double wv = cn ? 0.5 : 1.0;
+  double* rhsA[3] = {NULL, NULL, NULL};
+  double* DA[3] = {NULL, NULL, NULL};
+  if (cn)
+    for (int c = 0; c < 3; ++c) {
+      rhsA[c] = (double*)calloc(face_count(P, c), sizeof(double));
+      DA[c] = (double*)calloc(face_count(P, c), sizeof(double));
+    }
 
   for (int c = 0; c < 3; ++c) {
     int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
@@ -383,6 +487,7 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
           if (c == 0 && i == 0 && P->gen_len > 0.0) {
             /* the inlet of the wave tank: the target wave's velocity */
             out[c][f] = wave_vel(P, 0, 0.0, (k + 0.5) * h, t_np1);
+            if (rho_n && rb[c]) rb[c][f] = 0.0;
             continue;
           }
           if (is_wall_face(P, c, i, j, k)) {
@@ -422,31 +527,7 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
               mflux += mp - mm;
             }
 
-            /* viscous stress on the + and - sides */
-            double tp, tm;
-            if (d == c) {
-              /* normal stress 2 mu du_c/dx_c at the cell centres either side */
-              double mup = cellv(P, mu, i, j, k);
-              double mum = cellv(P, mu, i - ec[0], j - ec[1], k - ec[2]);
-              tp = 2.0 * mup * (FC(1) - FC(0)) / h;
-              tm = 2.0 * mum * (FC(0) - FC(-1)) / h;
-            } else {
-              /* shear stress mu (du_c/dx_d + du_d/dx_c) on the edges either side */
-              double mep = 0.25 * (cellv(P, mu, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, mu, i, j, k) +
-                                   cellv(P, mu, i - ec[0] + ed[0], j - ec[1] + ed[1], k - ec[2] + ed[2]) +
-                                   cellv(P, mu, i + ed[0], j + ed[1], k + ed[2]));
-              double mem = 0.25 * (cellv(P, mu, i - ec[0] - ed[0], j - ec[1] - ed[1], k - ec[2] - ed[2]) +
-                                   cellv(P, mu, i - ed[0], j - ed[1], k - ed[2]) +
-                                   cellv(P, mu, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, mu, i, j, k));
-              double dudp = (FC(1) - FC(0)) / h;
-              double dudm = (FC(0) - FC(-1)) / h;
-              double dvp = (facev(P, d, F[d], i + ed[0], j + ed[1], k + ed[2]) -
-                            facev(P, d, F[d], i + ed[0] - ec[0], j + ed[1] - ec[1], k + ed[2] - ec[2])) / h;
-              double dvm = (facev(P, d, F[d], i, j, k) - facev(P, d, F[d], i - ec[0], j - ec[1], k - ec[2])) / h;
-              tp = mep * (dudp + dvp);
-              tm = mem * (dudm + dvm);
-            }
-            visc += (tp - tm) / h;
+            visc += visc_dir(P, mu, F, c, d, i, j, k, NULL);
 #undef FC
           }
           adv /= h;
@@ -465,14 +546,25 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
           if (rho_n) {
             double r0 = 0.5 * (cellv(P, rho_n, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, rho_n, i, j, k));
             double rbf = r0 - dt * mflux / h;
-            double num = r0 * uf / dt - conv / h + visc + grav + pen * ub;
-            out[c][f] = num / (rbf / dt + pen + damp);
+            double num = r0 * uf / dt - conv / h + wv * visc + grav + pen * ub;
+            double den = rbf / dt + pen + damp;
+            out[c][f] = cn ? (num + 0.5 * visc) / den : num / den;
             if (rb[c]) rb[c][f] = rbf;
+            if (cn) rhsA[c][f] = num, DA[c][f] = den;
             continue;
           }
-          double num = rhof * (uf / dt - adv) + visc + grav + pen * ub;
-          out[c][f] = num / (rhof / dt + pen + damp);
+          double num = rhof * (uf / dt - adv) + wv * visc + grav + pen * ub;
+          double den = rhof / dt + pen + damp;
+          out[c][f] = cn ? (num + 0.5 * visc) / den : num / den;
+          if (cn) rhsA[c][f] = num, DA[c][f] = den;
         }
+  }
+  if (cn) {
+    cn_sweeps(P, mu, rhsA, DA, out);
+    for (int c = 0; c < 3; ++c) {
+      free(rhsA[c]);
+      free(DA[c]);
+    }
   }
   free(rho);
   free(rfl);

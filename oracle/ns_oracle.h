@@ -54,6 +54,8 @@ typedef struct {
   double wave_a[64], wave_k[64], wave_om[64], wave_ph[64];
   int consistent;              /* 1: conservative predictor with consistent       */
                                /*    mass/momentum transport                     */
+  int cn_sweeps;               /* > 0: Crank-Nicolson viscous term, solved by     */
+                               /*    this many Jacobi sweeps; 0: explicit         */
 } orc_params;
 
 typedef struct {

@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("depth", C.c_double), ("gen_len", C.c_double), ("damp_len", C.c_double),
                 ("vort_width", C.c_double), ("n_waves", C.c_int),
                 ("wave_a", C.c_double * 64), ("wave_k", C.c_double * 64), ("wave_om", C.c_double * 64),
-                ("wave_ph", C.c_double * 64), ("consistent", C.c_int)]
+                ("wave_ph", C.c_double * 64), ("consistent", C.c_int),
+                ("cn_sweeps", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -132,6 +133,7 @@ def params(wl, **solver) -> Params:
         P.body[m].zeta, P.body[m].zdot = b.zeta0, b.zdot0
     P.depth = wl.depth
     P.consistent = int(wl.consistent)
+    P.cn_sweeps = int(wl.cn_sweeps)
     if wl.nwt:
         from paper_2206_07732_amd.inputs import wave_components
         P.gen_len, P.damp_len, P.vort_width = wl.nwt.get("gen", 0.0), wl.nwt.get("damp", 0.0), wl.nwt.get("vort", 0.0)

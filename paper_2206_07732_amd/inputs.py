@@ -145,6 +145,7 @@ class Workload:
     p_init: str = "zero"            # initial pressure: "zero", or "hydrostatic" under the initial surface
     nwt: Optional[dict] = None      # numerical wave tank: {"gen": m, "damp": m, "vort": m} zone sizes
     consistent: int = 0             # 1: conservative predictor with consistent mass/momentum transport
+    cn_sweeps: int = 0              # > 0: Crank-Nicolson viscous term by this many Jacobi sweeps
 
     @property
     def dim(self) -> int:

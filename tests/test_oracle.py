@@ -783,3 +783,77 @@ def test_consistent_transport_keeps_a_uniform_velocity_across_the_interface(orc)
     rho_n = orc.properties(P, sigma, 0.0)[0]
     (us, _, _), _ = orc.momentum_cons(P, u, v, w, sigma, 0.01, 0.01, rho_n)
     assert np.max(np.abs(us[3:-3, :, 4:-4] - 0.25)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson viscous term (Sec. "Time stepping scheme")
+# ---------------------------------------------------------------------------
+def test_cn_viscous_amplification_of_a_column_eigenmode(orc):
+    """One water column (nx = ny = 1, no gravity): only w moves and the
+    viscous operator is the normal stress 2 mu w_zz with w = 0 on the bed and a
+    zero gradient at the top.  w_k = sin(theta k), theta = pi (2m+1)/(2nz+1),
+    is an eigenvector with eigenvalue -8 mu sin^2(theta/2)/h^2, so one step
+    multiplies it by (1 - x/2)/(1 + x/2) with Crank-Nicolson, 1 - x explicitly
+    (x = 8 nu dt sin^2(theta/2)/h^2).  The amplitude is 1e-60, so the
+    advection term, quadratic in w, vanishes."""
+    nz, m, h, dt = 16, 8, 0.1, 0.05
+    theta = np.pi * (2 * m + 1) / (2 * nz + 1)
+    rho = FL["rho_w"]
+    x = 0.8
+    mu = x * rho * h * h / (8.0 * np.sin(theta / 2) ** 2 * dt)
+    eps = 1e-60
+    for sweeps, factor in ((40, (1 - x / 2) / (1 + x / 2)), (0, 1 - x)):
+        wl = flat_wl(nx=1, nz=nz, h=h, depth=0.5, g=0.0, mu_w=mu, cn_sweeps=sweeps)
+        P = orc.params(wl)
+        sigma, u, v, w = zeros(wl)
+        sigma[:] = -5.0                                   # all water
+        w[:, 0, 0] = eps * np.sin(theta * np.arange(nz + 1))
+        _, _, ws = orc.momentum(P, u, v, w, sigma, dt, dt)
+        assert np.max(np.abs(ws - factor * w)) < 1e-13 * eps, sweeps
+
+
+def test_cn_viscous_matches_a_dense_solve_in_a_two_phase_box(orc):
+    """A 4x3x4 box with a sloping interface (rho and mu vary, nu = 0.05 in both
+    phases) and no gravity.  The explicit predictor is linear in a velocity
+    of amplitude 1e-60 (advection, quadratic, vanishes): u* = J u^n with
+    J = I + D^-1 L on the faces that are not walls, J read off column by
+    column.  Crank-Nicolson, (D - L/2) u* = (D + L/2) u^n, is then
+    (3I - J) u* = (I + J) u^n, solved densely; the Jacobi iterate after 80
+    sweeps must match it, and differ from the explicit step."""
+    h, dt, nu = 0.25, 0.05, 0.05
+    kw = dict(nx=4, ny=3, nz=4, h=h, depth=0.5, g=0.0, mu_w=nu * FL["rho_w"], mu_a=nu * FL["rho_a"])
+    wl0, wl1 = flat_wl(**kw), flat_wl(cn_sweeps=80, **kw)
+    P0, P1 = orc.params(wl0), orc.params(wl1)
+    x, y, z = cell_centres(wl0)
+    sigma = z - (0.45 + 0.2 * (x - 0.5) + 0.1 * (y - 0.375))
+    _, u, v, w = zeros(wl0)
+    masks = [np.ones(u.shape, bool), np.ones(v.shape, bool), np.ones(w.shape, bool)]
+    masks[0][:, :, [0, -1]] = False                       # walls
+    masks[1][:, [0, -1], :] = False
+    masks[2][0] = False
+    shapes = [a.shape for a in (u, v, w)]
+    sizes = [int(np.prod(s)) for s in shapes]
+    idx = np.concatenate([np.flatnonzero(mk.ravel()) + sum(sizes[:c]) for c, mk in enumerate(masks)])
+    eps = 1e-60
+
+    def split(vec):
+        out, o = [], 0
+        for s, n in zip(shapes, sizes):
+            out.append(vec[o:o + n].reshape(s))
+            o += n
+        return out
+
+    def predictor(P, vec):
+        full = np.zeros(sum(sizes))
+        full[idx] = vec
+        r = orc.momentum(P, *split(full * eps), sigma, dt, dt)
+        return np.concatenate([a.ravel() for a in r])[idx] / eps
+
+    n = len(idx)
+    J = np.stack([predictor(P0, e) for e in np.eye(n)], axis=1)
+    rng = np.random.default_rng(7)
+    un = rng.standard_normal(n)
+    exact = np.linalg.solve(3 * np.eye(n) - J, (np.eye(n) + J) @ un)
+    got = predictor(P1, un)
+    assert np.linalg.norm(got - exact) < 1e-12 * np.linalg.norm(exact)
+    assert np.linalg.norm(J @ un - exact) > 1e-3 * np.linalg.norm(exact)
