@@ -878,11 +878,22 @@ void orc_correct(const orc_params* P, const double* us, const double* vs, const 
  * ------------------------------------------------------------------------ */
 int orc_step(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,
              double dt, double t_n, int x0_prev, orc_stats* st) {
+  return orc_step_from(P, sigma, u, v, w, p, dt, t_n, x0_prev, NULL, st);
+}
+
+/* As orc_step; with consistent transport rho_n_in (may be NULL: the
+ * properties of sigma and the bodies as P holds them, at t_n) is the density
+ * the step starts from. */
+int orc_step_from(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,
+                  double dt, double t_n, int x0_prev, const double* rho_n_in, orc_stats* st) {
   const size_t n = ncell(P);
   double* rho_n = NULL;
   if (P->consistent) {  /* the density the step starts from */
     rho_n = (double*)malloc(n * sizeof(double));
-    orc_properties(P, sigma, t_n, rho_n, NULL, NULL, NULL);
+    if (rho_n_in)
+      memcpy(rho_n, rho_n_in, n * sizeof(double));
+    else
+      orc_properties(P, sigma, t_n, rho_n, NULL, NULL, NULL);
   }
   double* s1 = (double*)malloc(n * sizeof(double));
   orc_levelset_advect(P, sigma, u, v, w, dt, s1);

@@ -94,6 +94,8 @@ void orc_correct(const orc_params* P, const double* us, const double* vs, const 
                  double* u, double* v, double* w);
 int  orc_step(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,
               double dt, double t_n, int x0_prev, orc_stats* st);
+int  orc_step_from(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,
+                   double dt, double t_n, int x0_prev, const double* rho_n, orc_stats* st);
 void orc_diagnostics(const orc_params* P, const double* sigma, const double* u, const double* v,
                      const double* w, double* out4);
 /* hydrodynamic force on body m (eqn_int_fh); mu: cell viscosity; F: (Fx, Fy, Fz) */

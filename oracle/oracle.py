@@ -85,6 +85,7 @@ def lib():
             "orc_pcg": [P, dp, dp, dp, dp, dp, S],
             "orc_correct": [P, dp, dp, dp, dp, dp, dp, dp, d, dp, dp, dp],
             "orc_step": [P, dp, dp, dp, dp, dp, d, d, C.c_int, S],
+            "orc_step_from": [P, dp, dp, dp, dp, dp, d, d, C.c_int, dp, S],
             "orc_diagnostics": [P, dp, dp, dp, dp, dp],
             "orc_hydro_force": [P, C.c_int, dp, dp, dp, dp, dp, d, dp],
             "orc_heave_update": [d, d, d, d, d, dp, dp],
@@ -95,7 +96,7 @@ def lib():
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
-            fn.restype = C.c_int if name in ("orc_num_levels", "orc_pcg", "orc_step") else None
+            fn.restype = C.c_int if name in ("orc_num_levels", "orc_pcg", "orc_step", "orc_step_from") else None
         _lib = L
     return _lib
 
@@ -230,12 +231,15 @@ def correct(P, us, vs, ws, p, bx, by, bz, dt):
     return u, v, w
 
 
-def step(P, fields, dt, t_n, x0_prev=True):
-    """One time step on copies of the fields; returns (fields, stats, rc)."""
+def step(P, fields, dt, t_n, x0_prev=True, rho_n=None):
+    """One time step on copies of the fields; returns (fields, stats, rc).
+    With consistent transport, rho_n (default: the properties of the fields
+    and bodies as they are, at t_n) is the density the step starts from."""
     f = {k: _arr(fields[k]).copy() for k in ("sigma", "u", "v", "w", "p")}
     st = Stats()
-    rc = lib().orc_step(C.byref(P), _p(f["sigma"]), _p(f["u"]), _p(f["v"]), _p(f["w"]), _p(f["p"]),
-                        dt, t_n, 1 if x0_prev else 0, C.byref(st))
+    rn = None if rho_n is None else _arr(rho_n)
+    rc = lib().orc_step_from(C.byref(P), _p(f["sigma"]), _p(f["u"]), _p(f["v"]), _p(f["w"]), _p(f["p"]),
+                             dt, t_n, 1 if x0_prev else 0, None if rn is None else _p(rn), C.byref(st))
     return f, st.as_dict(), rc
 
 
@@ -266,18 +270,22 @@ def step_fsi(P, fields, dt, t_n, x0_prev=True):
     """One coupled step (Sec. "Fluid-structure coupling", one cycle): for every
     free body, the force from the current state (viscosity from the properties
     at t_n and the body's current heave), then its heave update; then the step
-    with psi and u_b from the new heave.  P's body states advance in place.
+    with psi and u_b from the new heave (with consistent transport, from the
+    density of the state at t_n).  P's body states advance in place.
     Returns (fields, stats, rc, {body: (Fx, Fy, Fz)})."""
     forces = {}
     free = [m for m in range(P.n_bodies) if P.body[m].free_heave]
+    rho_n = None
     if free:
-        _, _, mu, _ = properties(P, fields["sigma"], t_n)
+        rho_n, _, mu, _ = properties(P, fields["sigma"], t_n)
         for m in free:
             F = hydro_force(P, m, fields["p"], fields["u"], fields["v"], fields["w"], mu, t_n)
             forces[m] = F
             B = P.body[m]
             B.zeta, B.zdot = heave_update(B.mass, B.pto_damping, P.g, dt, F[2], B.zeta, B.zdot)
-    f, st, rc = step(P, fields, dt, t_n, x0_prev)
+    # consistent transport starts from the density of the state at t_n (the
+    # body before its heave update)
+    f, st, rc = step(P, fields, dt, t_n, x0_prev, rho_n if P.consistent else None)
     return f, st, rc, forces
 
 
