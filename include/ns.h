@@ -128,6 +128,26 @@ typedef struct {
   double vort_width;           /* vorticity damping zone width (m), >= 0        */
   int n_waves;                 /* 0..64                                         */
   struct { double a, kappa, omega, phase; } waves[64];
+  /* 1: the predictor takes the conservative form of eqn_c_discrete_momentum
+   * with consistent mass/momentum transport (Sec. "Multiphase incompressible
+   * Navier-Stokes solution"): the face density starts from the density of
+   * the level set the step starts from and is carried over the step by the
+   * same limited upwind mass fluxes that carry momentum, rb = rho^n_f -
+   * dt/h sum m, (rb u* - rho^n_f u^n)/dt + sum(m v)/h = forces, and beta
+   * uses rb.  ns_step takes rho^n from the fields it starts from; a caller
+   * driving the stages alone gets, on its first momentum_step, the density
+   * of the level set as that call finds it.  0: the advective form. */
+  int consistent;
+  /* > 0: the viscous term is Crank-Nicolson (Sec. "Time stepping scheme"):
+   * half of it at t^n, half at the predicted velocity, each face solving
+   *   D_f u*_f - 1/2 L(u*)_f = rhs_f
+   * with D_f the implicit diagonal of the predictor and L the viscous
+   * operator.  The system is solved by this many point-Jacobi sweeps from the
+   * explicit predictor, u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f))/(D_f + 1/2 a_f),
+   * a_f the magnitude of L's diagonal; each sweep contracts the error by a
+   * factor of order nu dt/h^2.  Walls and the inlet keep their values.
+   * 0: explicit viscous term.  At most 64. */
+  int cn_sweeps;
 } ns_params;
 
 /* The caller's state arrays (device, FP64, layouts above); read and written

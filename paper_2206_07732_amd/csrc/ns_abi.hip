@@ -26,6 +26,11 @@ struct ns_ctx {
   double *us, *vs, *ws;
   double *sig_a, *sig_b;
   double *rho, *rfl, *mu, *chi;
+  double* rho_prev;   // consistent transport: the density of the level set the step starts from
+  bool have_rho_n;    // rho holds the density at the start of the next momentum_step
+  double* cn_rhs[3];  // Crank-Nicolson viscous term: right-hand side per face,
+  double* cn_diag[3]; // implicit diagonal (0 on walls and the inlet),
+  double* cn_tmp[3];  // and the second iterate of the Jacobi sweeps
   double *b, *r, *z, *zn, *d, *d2, *q;
   double *partials;
   double *scal;
@@ -138,6 +143,8 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
       !std::isfinite(P->damp_len) || !std::isfinite(P->vort_width))
     return snprintf(why, nwhy, "wave tank zone sizes must be finite and >= 0"), false;
   if (P->n_waves < 0 || P->n_waves > 64) return snprintf(why, nwhy, "n_waves must be 0..64"), false;
+  if (P->consistent != 0 && P->consistent != 1) return snprintf(why, nwhy, "consistent must be 0 or 1"), false;
+  if (P->cn_sweeps < 0 || P->cn_sweeps > 64) return snprintf(why, nwhy, "cn_sweeps must be 0..64"), false;
   if ((P->gen_len > 0.0 || P->damp_len > 0.0) && !(P->depth > 0.0 && std::isfinite(P->depth)))
     return snprintf(why, nwhy, "a wave tank with relaxation zones needs depth > 0"), false;
   for (int q = 0; q < P->n_waves; ++q) {
@@ -219,6 +226,10 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
   double* rho = cv.take<double>(nc);
   double* rfl = cv.take<double>(nc);
   double* mu = cv.take<double>(nc);
+  double* rho_prev = P->consistent ? cv.take<double>(nc) : nullptr;   // rho at t^n
+  double* cn[9] = {};   // Crank-Nicolson: rhs, diagonal and second iterate of u, v, w
+  if (P->cn_sweeps > 0)
+    for (int q = 0; q < 9; ++q) cn[q] = cv.take<double>(q % 3 == 0 ? nu : q % 3 == 1 ? nv : nw);
   double* chi = cv.take<double>(nc);
   double* b = cv.take<double>(nc);
   double* r = cv.take<double>(nc);
@@ -327,6 +338,12 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     X->rho = rho;
     X->rfl = rfl;
     X->mu = mu;
+    X->rho_prev = rho_prev;
+    for (int c = 0; c < 3; ++c) {
+      X->cn_rhs[c] = cn[c];
+      X->cn_diag[c] = cn[3 + c];
+      X->cn_tmp[c] = cn[6 + c];
+    }
     X->chi = chi;
     X->b = b;
     X->r = r;
@@ -472,8 +489,17 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
 // above the tail work on colour-split b and e; the first sweep of level 0
 // reads b0 in natural order and writes its split copy, and the last red pass
 // of level 0 writes e0 in natural order.
+// The flexible CG's next two products (r z, r z_old) requested of an FP64
+// V-cycle: its last kernel computes them when it is the finest level's last
+// red pass (nparts: the partials it left; 0 when the cycle had no such pass).
+struct DotsReq {
+  const double* r;
+  const double* zold;
+  int nparts;
+};
+
 template <typename T>
-void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
+void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
   const ns_params& P = X->P;
   const Level& L = X->lev[l];
   hipStream_t st = X->st;
@@ -486,6 +512,17 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
   KTimer* kt = (l == 0 && X->timed_kernel == NS_TIME_SMOOTH0) ? &X->kt : nullptr;
   const size_t nsplit = 2 * (size_t)((L.n.nx + 1) / 2) * L.n.ny * L.n.nz;
+  // the red pass that writes the cycle's result e0 (level 0): with the
+  // products fused when they are requested (FP64, no kernel timer on it)
+  auto last_red = [&]() {
+    if constexpr (sizeof(T) == 8) {
+      if (dq && !kt) {
+        dq->nparts = launch_gs_last_dots(L, bx, by, bz, b, e, e0, dq->r, dq->zold, X->partials, st);
+        return;
+      }
+    }
+    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, e0);
+  };
   if (l == X->L - 1) {
     // a coarsest level too large for the tail: its sweeps with the
     // multi-block kernels, forward (red, black) then backward (black, red)
@@ -505,7 +542,10 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
     }
     for (int s = 0; s < S; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
-      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, (l == 0 && s == S - 1) ? e0 : nullptr);
+      if (l == 0 && s == S - 1)
+        last_red();
+      else
+        launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
     }
     return;
   }
@@ -528,10 +568,16 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   // pairs; at level 0 the last red pass writes e0
   if (P.nu_post > 0) {
     launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), csplit, st);
-    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, (l == 0 && P.nu_post == 1) ? e0 : nullptr);
+    if (l == 0 && P.nu_post == 1)
+      last_red();
+    else
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
     for (int s = 1; s < P.nu_post; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
-      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, (l == 0 && s == P.nu_post - 1) ? e0 : nullptr);
+      if (l == 0 && s == P.nu_post - 1)
+        last_red();
+      else
+        launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
     }
   } else {
     launch_prolong<T>(L, e, C, LV<T>::e(C), csplit, st);
@@ -539,16 +585,21 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0) {
   }
 }
 
-// z = M r, one kernel launch at a time on the context's stream
-void precond_launch(ns_ctx* X, const double* r, double* z) {
+// z = M r, one kernel launch at a time on the context's stream.  With zold
+// the cycle's last kernel also leaves the partials of r z and r z_old in
+// X->partials when it can; returns how many (0: not fused, or not asked).
+int precond_launch(ns_ctx* X, const double* r, double* z, const double* zold = nullptr) {
   if (X->P.prec == NS_PREC_FP64) {
-    vcycle<double>(X, 0, r, z);
-  } else {
-    Level& L0 = X->lev[0];
-    launch_d2f(r, L0.bfn, X->nc, X->st);
-    vcycle<float>(X, 0, L0.bfn, L0.efn);
-    launch_f2d(L0.efn, z, X->nc, X->st);
+    DotsReq dq{r, zold, 0};
+    vcycle<double>(X, 0, r, z, zold ? &dq : nullptr);
+    return dq.nparts;
   }
+  Level& L0 = X->lev[0];
+  launch_d2f(r, L0.bfn, X->nc, X->st);
+  vcycle<float>(X, 0, L0.bfn, L0.efn);
+  if (zold) return launch_f2d_dots(L0.efn, z, X->nc, r, zold, X->partials, X->st);
+  launch_f2d(L0.efn, z, X->nc, X->st);
+  return 0;
 }
 
 // The CG loop's V-cycles, each with the dot product that follows it, are
@@ -665,8 +716,12 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   };
   auto precond_beta = [&](double* znew, const double* zold) {
     return issue(X, SEG_PRECOND_BETA, znew, zold, nullptr, 0, [&] {
-      precond_launch(X, X->r, znew);
-      launch_dots_beta(n, X->r, znew, zold, cs, X->st);
+      // the products come with the cycle's last kernel when it can give them
+      const int np = precond_launch(X, X->r, znew, zold);
+      if (np > 0)
+        launch_finalize_beta(cs, np, X->st);
+      else
+        launch_dots_beta(n, X->r, znew, zold, cs, X->st);
     });
   };
   // (four kernels: launched directly, a graph launch would cost the device
@@ -867,6 +922,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
   // a force launch writes three partials per block into the device partials
   // (4 nparts doubles), so it may use at most 4 nparts / 3 blocks, which a
   // body's box within the grid does not exceed (a bigger one is refused)
+  X->have_rho_n = false;
   X->nfree = 0;
   for (int m = 0; m < params->n_bodies; ++m) X->nfree += params->body[m].free_heave ? 1 : 0;
   for (int m = 0; m < 4; ++m) X->bs[m] = {{0.0, 0.0, 0.0}, 0.0};
@@ -1106,11 +1162,30 @@ ns_status momentum_step(ns_ctx* X, double dt, double t_np1) {
     free_heave_update(X, dt);
   }
   const Phys& ph = X->phys;
+  if (X->P.consistent) {
+    // the density at t^n: the last properties (ns_step fills them on its
+    // first step; a caller driving the stages alone gets the current level set's)
+    if (!X->have_rho_n) launch_props(ph, X->F.sigma, t_np1 - dt, X->rho, X->rfl, X->mu, X->chi, st);
+    std::swap(X->rho, X->rho_prev);
+  }
   X->t_props = t_np1;
   launch_props(ph, X->F.sigma, t_np1, X->rho, X->rfl, X->mu, X->chi, st);
   Level& L0 = X->lev[0];
-  launch_momentum(ph, X->F.u, X->F.v, X->F.w, X->rho, X->rfl, X->mu, X->chi, dt, t_np1, X->us, X->vs,
-                  X->ws, L0.bx, L0.by, L0.bz, L0.bxf, L0.byf, L0.bzf, st);
+  // Crank-Nicolson: the predictor writes the first iterate and the sweeps
+  // alternate between u* and a second set, starting in the one that leaves
+  // the last iterate in u*
+  const int S = X->P.cn_sweeps;
+  double* us3[3] = {X->us, X->vs, X->ws};
+  double** cur = (S % 2) ? X->cn_tmp : us3;
+  double** nxt = (S % 2) ? us3 : X->cn_tmp;
+  launch_momentum(ph, X->F.u, X->F.v, X->F.w, X->rho, X->rfl, X->mu, X->chi, X->P.consistent ? X->rho_prev : nullptr,
+                  dt, t_np1, cur[0], cur[1], cur[2], L0.bx, L0.by, L0.bz, L0.bxf, L0.byf, L0.bzf,
+                  S > 0 ? X->cn_rhs : nullptr, S > 0 ? X->cn_diag : nullptr, st);
+  for (int s = 0; s < S; ++s) {
+    launch_cn_sweep(ph, cur[0], cur[1], cur[2], X->mu, X->cn_rhs, X->cn_diag, nxt[0], nxt[1], nxt[2], st);
+    std::swap(cur, nxt);
+  }
+  X->have_rho_n = X->P.consistent != 0;
   HIPCHK(X, hipGetLastError());
   X->have_beta = true;
   return NS_OK;
@@ -1171,6 +1246,11 @@ ns_status ns_step(ns_ctx* X, double dt, double t_n, ns_stats* stats) {
   // free bodies: on the first step, the force of the state the step starts from
   ns_status s = ensure_free_forces(X, t_n);
   if (s != NS_OK) return s;
+  // consistent transport: on the first step, the density the step starts from
+  if (X->P.consistent && !X->have_rho_n) {
+    launch_props(X->phys, X->F.sigma, t_n, X->rho, X->rfl, X->mu, X->chi, X->st);
+    X->have_rho_n = true;
+  }
   s = levelset_advect_reinit(X, dt);
   if (s != NS_OK) return s;
   if ((s = momentum_step(X, dt, t_n + dt)) != NS_OK) return s;

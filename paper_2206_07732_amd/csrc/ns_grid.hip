@@ -266,11 +266,47 @@ __global__ void __launch_bounds__(256) k_props(Phys P, const double* __restrict_
 // --------------------------------------------------------------------------
 // momentum predictor for velocity component C (faces normal to C)
 // --------------------------------------------------------------------------
-// contribution of direction D to advection and viscous stress of component C
+// Viscous stress of component C along direction D at a face,
+// ((tau_+) - (tau_-))/h: tau = 2 mu du_C/dx_C at the cell centres either side
+// (D = C), else mu (du_C/dx_D + du_D/dx_C) on the edges either side with the
+// mean of their four cell viscosities.  m1, p1: the face's neighbours along D;
+// dvp, dvm: du_D/dx_C on the two edges.  *a (if not null) receives the
+// magnitude of the coefficient of the face's own value.
 template <int C, int D>
+__device__ __forceinline__ double visc_stress(const double* __restrict__ mu, const Dims& n, int i, int j, int k,
+                                              double uf, double m1, double p1, double dvp, double dvm, double ih,
+                                              double* a) {
+  constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
+  constexpr int di = (D == 0), dj = (D == 1), dk = (D == 2);
+  double tp, tm;
+  if constexpr (C == D) {
+    const double mup = cv(mu, n, i, j, k), mum = cv(mu, n, i - ci, j - cj, k - ck);
+    tp = 2.0 * mup * (p1 - uf) * ih;
+    tm = 2.0 * mum * (uf - m1) * ih;
+    if (a) *a = 2.0 * (mup + mum) * ih * ih;
+  } else {
+    const double mep = 0.25 * (cv(mu, n, i - ci, j - cj, k - ck) + cv(mu, n, i, j, k) +
+                               cv(mu, n, i - ci + di, j - cj + dj, k - ck + dk) +
+                               cv(mu, n, i + di, j + dj, k + dk));
+    const double mem = 0.25 * (cv(mu, n, i - ci - di, j - cj - dj, k - ck - dk) +
+                               cv(mu, n, i - di, j - dj, k - dk) + cv(mu, n, i - ci, j - cj, k - ck) +
+                               cv(mu, n, i, j, k));
+    tp = mep * ((p1 - uf) * ih + dvp);
+    tm = mem * ((uf - m1) * ih + dvm);
+    if (a) *a = (mep + mem) * ih * ih;
+  }
+  return (tp - tm) * ih;
+}
+
+// One direction D of the predictor of component C: advection (advective
+// form), viscous stress, and with CONS the consistent transport's mass flux
+// (Koren-limited upwind face density at t^n times the advecting velocity)
+// and the momentum it carries (times the same upwind velocity).
+template <int C, int D, bool CONS>
 __device__ __forceinline__ void mom_dir(const double* __restrict__ uc, const double* __restrict__ ud,
-                                        const double* __restrict__ mu, const Dims& n, int i, int j,
-                                        int k, double uf, double ih, double& adv, double& visc) {
+                                        const double* __restrict__ mu, const double* __restrict__ rho_n,
+                                        const Dims& n, int i, int j, int k, double uf, double ih, double& adv,
+                                        double& visc, double& conv, double& mflux) {
   constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
   constexpr int di = (D == 0), dj = (D == 1), dk = (D == 2);
   const double m2 = fv<C>(uc, n, i - 2 * di, j - 2 * dj, k - 2 * dk);
@@ -295,33 +331,37 @@ __device__ __forceinline__ void mom_dir(const double* __restrict__ uc, const dou
   const double vp = ap >= 0.0 ? koren(m1, uf, p1) : koren(p2, p1, uf);
   const double vm = am >= 0.0 ? koren(m2, m1, uf) : koren(p1, uf, m1);
   adv += ap * (vp - uf) - am * (vm - uf);
-  double tp, tm;
-  if constexpr (C == D) {
-    tp = 2.0 * cv(mu, n, i, j, k) * (p1 - uf) * ih;
-    tm = 2.0 * cv(mu, n, i - ci, j - cj, k - ck) * (uf - m1) * ih;
-  } else {
-    const double mep = 0.25 * (cv(mu, n, i - ci, j - cj, k - ck) + cv(mu, n, i, j, k) +
-                               cv(mu, n, i - ci + di, j - cj + dj, k - ck + dk) +
-                               cv(mu, n, i + di, j + dj, k + dk));
-    const double mem = 0.25 * (cv(mu, n, i - ci - di, j - cj - dj, k - ck - dk) +
-                               cv(mu, n, i - di, j - dj, k - dk) + cv(mu, n, i - ci, j - cj, k - ck) +
-                               cv(mu, n, i, j, k));
-    tp = mep * ((p1 - uf) * ih + dvp);
-    tm = mem * ((uf - m1) * ih + dvm);
+  if constexpr (CONS) {
+    // face density at t^n of the face o steps along D: mean of its two cells
+    auto rf = [&](int o) {
+      return 0.5 * (cv(rho_n, n, i - ci + o * di, j - cj + o * dj, k - ck + o * dk) +
+                    cv(rho_n, n, i + o * di, j + o * dj, k + o * dk));
+    };
+    const double rm2 = rf(-2), rm1 = rf(-1), r0 = rf(0), rp1 = rf(1), rp2 = rf(2);
+    const double mp = ap * (ap >= 0.0 ? koren(rm1, r0, rp1) : koren(rp2, rp1, r0));
+    const double mm = am * (am >= 0.0 ? koren(rm2, rm1, r0) : koren(rp1, r0, rm1));
+    conv += mp * vp - mm * vm;
+    mflux += mp - mm;
   }
-  visc += (tp - tm) * ih;
+  visc += visc_stress<C, D>(mu, n, i, j, k, uf, m1, p1, dvp, dvm, ih, nullptr);
 }
 
-template <int C>
+// The predictor of component C.  CONS: the conservative form with
+// consistent mass/momentum transport, from the cell density rho_n at t^n:
+// (rb u* - rho^n_f u^n)/dt + conv/h = forces, rb = rho^n_f - dt mflux/h, and
+// beta from rb; otherwise the advective form with rho_f at t^{n+1}.
+template <int C, bool CONS>
 __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restrict__ u,
                                                   const double* __restrict__ v,
                                                   const double* __restrict__ w,
                                                   const double* __restrict__ rho,
                                                   const double* __restrict__ rfl,
                                                   const double* __restrict__ mu,
-                                                  const double* __restrict__ chi, double dt, double t1,
+                                                  const double* __restrict__ chi,
+                                                  const double* __restrict__ rho_n, double dt, double t1,
                                                   double* __restrict__ out, double* __restrict__ beta,
-                                                  float* __restrict__ betaf) {
+                                                  float* __restrict__ betaf, double* __restrict__ cn_rhs,
+                                                  double* __restrict__ cn_diag) {
   const Dims n = P.n;
   constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
   const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
@@ -337,15 +377,19 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
     out[f] = (C == 0 && i == 0 && P.gen_len > 0.0) ? tank_vel(P, 0, 0.0, (k + 0.5) * P.h, t1) : 0.0;
     beta[f] = 0.0;
     betaf[f] = 0.0f;
+    if (cn_rhs) {
+      cn_rhs[f] = 0.0;
+      cn_diag[f] = 0.0;   // marks a face the Crank-Nicolson sweeps keep
+    }
     return;
   }
   const double* uc = (C == 0) ? u : (C == 1) ? v : w;
   const double uf = uc[f];
   const double ih = 1.0 / P.h;
-  double adv = 0.0, visc = 0.0;
-  mom_dir<C, 0>(uc, u, mu, n, i, j, k, uf, ih, adv, visc);
-  mom_dir<C, 1>(uc, v, mu, n, i, j, k, uf, ih, adv, visc);
-  mom_dir<C, 2>(uc, w, mu, n, i, j, k, uf, ih, adv, visc);
+  double adv = 0.0, visc = 0.0, conv = 0.0, mflux = 0.0;
+  mom_dir<C, 0, CONS>(uc, u, mu, rho_n, n, i, j, k, uf, ih, adv, visc, conv, mflux);
+  mom_dir<C, 1, CONS>(uc, v, mu, rho_n, n, i, j, k, uf, ih, adv, visc, conv, mflux);
+  mom_dir<C, 2, CONS>(uc, w, mu, rho_n, n, i, j, k, uf, ih, adv, visc, conv, mflux);
   adv *= ih;
   const double rf = 0.5 * (cv(rho, n, i - ci, j - cj, k - ck) + cv(rho, n, i, j, k));
   const double rff = 0.5 * (cv(rfl, n, i - ci, j - cj, k - ck) + cv(rfl, n, i, j, k));
@@ -355,10 +399,89 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
   const double grav = (C == 2) ? -P.g * rff : 0.0;
   const double pen = xf * P.inv_kp;
   const double damp = vort_coeff(P, (C == 2) ? k * P.h : (k + 0.5) * P.h, dt);   // -g u, implicit
-  out[f] = (rf * (uf / dt - adv) + visc + grav + pen * ub) / (rf / dt + pen + damp);
+  // Crank-Nicolson keeps half the viscous term at t^n on the right-hand side
+  // and writes the first iterate of its sweeps (the explicit value)
+  const double wv = cn_rhs ? 0.5 : 1.0;
+  if constexpr (CONS) {
+    const double r0 = 0.5 * (cv(rho_n, n, i - ci, j - cj, k - ck) + cv(rho_n, n, i, j, k));
+    const double rb = r0 - dt * mflux * ih;
+    const double num = r0 * uf / dt - conv * ih + wv * visc + grav + pen * ub;
+    const double den = rb / dt + pen + damp;
+    out[f] = cn_rhs ? (num + 0.5 * visc) / den : num / den;
+    if (cn_rhs) {
+      cn_rhs[f] = num;
+      cn_diag[f] = den;
+    }
+    const double bt = 1.0 / (rb + P.pen_w * dt * pen);
+    beta[f] = bt;
+    betaf[f] = (float)bt;
+    return;
+  }
+  const double num = rf * (uf / dt - adv) + wv * visc + grav + pen * ub;
+  const double den = rf / dt + pen + damp;
+  out[f] = cn_rhs ? (num + 0.5 * visc) / den : num / den;
+  if (cn_rhs) {
+    cn_rhs[f] = num;
+    cn_diag[f] = den;
+  }
   const double bt = 1.0 / (rf + P.pen_w * dt * pen);
   beta[f] = bt;
   betaf[f] = (float)bt;
+}
+
+// Viscous stress of component C along D from the iterate, with its diagonal.
+template <int C, int D>
+__device__ __forceinline__ void sweep_dir(const double* __restrict__ uc, const double* __restrict__ ud,
+                                          const double* __restrict__ mu, const Dims& n, int i, int j, int k,
+                                          double uf, double ih, double& L, double& a) {
+  constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
+  constexpr int di = (D == 0), dj = (D == 1), dk = (D == 2);
+  const double m1 = fv<C>(uc, n, i - di, j - dj, k - dk);
+  const double p1 = fv<C>(uc, n, i + di, j + dj, k + dk);
+  double dvp = 0.0, dvm = 0.0;
+  if constexpr (C != D) {
+    dvp = (fv<D>(ud, n, i + di, j + dj, k + dk) - fv<D>(ud, n, i + di - ci, j + dj - cj, k + dk - ck)) * ih;
+    dvm = (fv<D>(ud, n, i, j, k) - fv<D>(ud, n, i - ci, j - cj, k - ck)) * ih;
+  }
+  double ad;
+  L += visc_stress<C, D>(mu, n, i, j, k, uf, m1, p1, dvp, dvm, ih, &ad);
+  a += ad;
+}
+
+// One point-Jacobi sweep of the Crank-Nicolson viscous system of component C,
+//   D_f u_f - 1/2 L(u)_f = rhs_f,
+// from the iterate (u, v, w): u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f)) / (D_f + 1/2 a_f),
+// a_f the magnitude of L's diagonal; a face with D_f = 0 (a wall or the
+// inlet) keeps its value.
+template <int C>
+__global__ void __launch_bounds__(256) k_cn_sweep(Phys P, const double* __restrict__ u,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ w,
+                                                  const double* __restrict__ mu,
+                                                  const double* __restrict__ rhs,
+                                                  const double* __restrict__ diag, double* __restrict__ out) {
+  const Dims n = P.n;
+  constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
+  const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
+  if (i >= mx || j >= my || k >= mz) return;
+  const size_t f = i + (size_t)mx * (j + (size_t)my * k);
+  const double* uc = (C == 0) ? u : (C == 1) ? v : w;
+  const double uf = uc[f];
+  const double dg = diag[f];
+  if (dg == 0.0) {
+    out[f] = uf;
+    return;
+  }
+  const double ih = 1.0 / P.h;
+  double L = 0.0, a = 0.0;
+  sweep_dir<C, 0>(uc, u, mu, n, i, j, k, uf, ih, L, a);
+  sweep_dir<C, 1>(uc, v, mu, n, i, j, k, uf, ih, L, a);
+  sweep_dir<C, 2>(uc, w, mu, n, i, j, k, uf, ih, L, a);
+  out[f] = (rhs[f] + 0.5 * (L + a * uf)) / (dg + 0.5 * a);
 }
 
 // b = -div_h(u*) / dt
@@ -650,18 +773,43 @@ void launch_props(const Phys& P, const double* sigma, double t, double* rho, dou
 
 void launch_momentum(const Phys& P, const double* u, const double* v, const double* w,
                      const double* rho, const double* rfl, const double* mu, const double* chi,
-                     double dt, double t1, double* us, double* vs, double* ws, double* bx, double* by,
-                     double* bz, float* bxf, float* byf, float* bzf, hipStream_t st) {
+                     const double* rho_n, double dt, double t1, double* us, double* vs, double* ws, double* bx,
+                     double* by, double* bz, float* bxf, float* byf, float* bzf, double* const* cn_rhs,
+                     double* const* cn_diag, hipStream_t st) {
   const Dims n = P.n;
   Geo gx = geo3(n.nx + 1, n.ny, n.nz);
-  hipLaunchKernelGGL(k_momentum<0>, gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, dt, t1,
-                     us, bx, bxf);
   Geo gy = geo3(n.nx, n.ny + 1, n.nz);
-  hipLaunchKernelGGL(k_momentum<1>, gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, dt, t1,
-                     vs, by, byf);
   Geo gz = geo3(n.nx, n.ny, n.nz + 1);
-  hipLaunchKernelGGL(k_momentum<2>, gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, dt, t1,
-                     ws, bz, bzf);
+  double* r[3] = {nullptr, nullptr, nullptr};
+  double* dg[3] = {nullptr, nullptr, nullptr};
+  if (cn_rhs)
+    for (int c = 0; c < 3; ++c) r[c] = cn_rhs[c], dg[c] = cn_diag[c];
+  if (rho_n) {
+    hipLaunchKernelGGL((k_momentum<0, true>), gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+                       t1, us, bx, bxf, r[0], dg[0]);
+    hipLaunchKernelGGL((k_momentum<1, true>), gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+                       t1, vs, by, byf, r[1], dg[1]);
+    hipLaunchKernelGGL((k_momentum<2, true>), gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+                       t1, ws, bz, bzf, r[2], dg[2]);
+    return;
+  }
+  hipLaunchKernelGGL((k_momentum<0, false>), gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+                     t1, us, bx, bxf, r[0], dg[0]);
+  hipLaunchKernelGGL((k_momentum<1, false>), gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+                     t1, vs, by, byf, r[1], dg[1]);
+  hipLaunchKernelGGL((k_momentum<2, false>), gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+                     t1, ws, bz, bzf, r[2], dg[2]);
+}
+
+void launch_cn_sweep(const Phys& P, const double* u, const double* v, const double* w, const double* mu,
+                     double* const* rhs, double* const* diag, double* uo, double* vo, double* wo, hipStream_t st) {
+  const Dims n = P.n;
+  Geo gx = geo3(n.nx + 1, n.ny, n.nz);
+  Geo gy = geo3(n.nx, n.ny + 1, n.nz);
+  Geo gz = geo3(n.nx, n.ny, n.nz + 1);
+  hipLaunchKernelGGL(k_cn_sweep<0>, gx.grid, gx.block, 0, st, P, u, v, w, mu, rhs[0], diag[0], uo);
+  hipLaunchKernelGGL(k_cn_sweep<1>, gy.grid, gy.block, 0, st, P, u, v, w, mu, rhs[1], diag[1], vo);
+  hipLaunchKernelGGL(k_cn_sweep<2>, gz.grid, gz.block, 0, st, P, u, v, w, mu, rhs[2], diag[2], wo);
 }
 
 void launch_rhs(const Phys& P, const double* us, const double* vs, const double* ws, double dt,

@@ -152,8 +152,12 @@ void launch_props(const Phys& P, const double* sigma, double t, double* rho, dou
                   double* chi, hipStream_t st);
 void launch_momentum(const Phys& P, const double* u, const double* v, const double* w,
                      const double* rho, const double* rfl, const double* mu, const double* chi,
-                     double dt, double t1, double* us, double* vs, double* ws, double* bx, double* by,
-                     double* bz, float* bxf, float* byf, float* bzf, hipStream_t st);
+                     const double* rho_n, double dt, double t1, double* us, double* vs, double* ws, double* bx,
+                     double* by, double* bz, float* bxf, float* byf, float* bzf, double* const* cn_rhs,
+                     double* const* cn_diag, hipStream_t st);
+// one Jacobi sweep of the Crank-Nicolson viscous system: (u, v, w) -> (uo, vo, wo)
+void launch_cn_sweep(const Phys& P, const double* u, const double* v, const double* w, const double* mu,
+                     double* const* rhs, double* const* diag, double* uo, double* vo, double* wo, hipStream_t st);
 void launch_rhs(const Phys& P, const double* us, const double* vs, const double* ws, double dt,
                 double* b, hipStream_t st);
 void launch_correct(const Phys& P, const double* us, const double* vs, const double* ws,
@@ -206,12 +210,21 @@ template <typename T>
 void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st);
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st);
 void launch_f2d(const float* a, double* b, size_t n, hipStream_t st);
+// the V-cycle's last kernel fused with the flexible CG's two products (r z,
+// r z_old): per-block partials, two per block; each returns the block count
+int launch_gs_last_dots(const Level& L, const double* bx, const double* by, const double* bz, const double* b,
+                        const double* e, double* nat, const double* r, const double* zold, double* partials,
+                        hipStream_t st);
+int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
+                    hipStream_t st);
 
 int cg_blocks(const Dims& n);
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                        const double* b, const double* x, double* r, const CgScratch& cs, int mode,
                        hipStream_t st);
 void launch_dot_rho(const Dims& n, const double* r, const double* z, const CgScratch& cs, hipStream_t st);
+// beta and rho from two-valued partials already in cs.partials
+void launch_finalize_beta(const CgScratch& cs, int nparts, hipStream_t st);
 void launch_dots_beta(const Dims& n, const double* r, const double* zn, const double* z,
                       const CgScratch& cs, hipStream_t st);
 void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,

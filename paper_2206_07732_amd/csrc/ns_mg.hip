@@ -191,6 +191,51 @@ __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ 
   if (nat && io < n.nx) nat[row + io] = eo[pos];
 }
 
+// The last red pass of the finest level in FP64, writing the V-cycle's
+// result z in natural order (as k_gs with nat), fused with the two products
+// the flexible CG needs next: per block, sum over its cells of r z and
+// r z_old, red cell then black cell of each pair, in tile order.  Every
+// thread reaches the block reduction (no early return).
+__global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const double* __restrict__ bx,
+                                                      const double* __restrict__ by,
+                                                      const double* __restrict__ bz,
+                                                      const double* __restrict__ b,
+                                                      const double* __restrict__ e, double* __restrict__ nat,
+                                                      const double* __restrict__ r,
+                                                      const double* __restrict__ zold,
+                                                      double* __restrict__ partials) {
+  const Tile tl = xcd_tile();
+  const int ti = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
+  const SplitGeo sg = split_geo(n);
+  double v[2] = {0.0, 0.0};
+  if (j < n.ny && k < n.nz && ti < sg.hx) {
+    const size_t sxy = (size_t)n.nx * n.ny;
+    const size_t row = (size_t)n.nx * j + sxy * k;
+    const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k);
+    const int par = (j + k) & 1;
+    const int i = 2 * ti + par, io = 2 * ti + 1 - par;
+    const double* eo = e + sg.P;   // the black plane
+    if (i < n.nx) {
+      const double z = gs_split_value<double>(n, sg, h2, bx, by, bz, b[pos], i, j, k, pos,
+                                              [&](size_t q) { return eo[q]; });
+      nat[row + i] = z;
+      const double rv = r[row + i];
+      v[0] += rv * z;
+      v[1] += rv * zold[row + i];
+    }
+    if (io < n.nx) {
+      const double z = eo[pos];
+      nat[row + io] = z;
+      const double rv = r[row + io];
+      v[0] += rv * z;
+      v[1] += rv * zold[row + io];
+    }
+  }
+  block_partials<2>(v, partials, tl.lin);
+}
+
 // red pass from a zero guess followed by the black pass, in one launch: the
 // red values the black cells need are recomputed from b and 1/D.  NAT: b is
 // read in natural order (the finest level, whose b is a CG vector) and its
@@ -718,6 +763,23 @@ __global__ void k_f2d(const float* __restrict__ a, double* __restrict__ b, size_
   if (q < n) b[q] = (double)a[q];
 }
 
+// the FP32 V-cycle's result to FP64 z, fused with the per-block sums of r z
+// and r z_old (block order); every thread reaches the reduction
+__global__ void __launch_bounds__(256) k_f2d_dots(const float* __restrict__ a, double* __restrict__ z, size_t n,
+                                                  const double* __restrict__ r, const double* __restrict__ zold,
+                                                  double* __restrict__ partials) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (q < n) {
+    const double zq = (double)a[q];
+    z[q] = zq;
+    const double rv = r[q];
+    v[0] = rv * zq;
+    v[1] = rv * zold[q];
+  }
+  block_partials<2>(v, partials, (int)blockIdx.x);
+}
+
 // ------------------------------------------------------------------ CG (FP64)
 #define CELL_INDEX                                                         \
   const Tile tl = xcd_tile();                                              \
@@ -989,6 +1051,22 @@ void launch_d2f(const double* a, float* b, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
 }
 
+int launch_gs_last_dots(const Level& L, const double* bx, const double* by, const double* bz, const double* b,
+                        const double* e, double* nat, const double* r, const double* zold, double* partials,
+                        hipStream_t st) {
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
+  hipLaunchKernelGGL(k_gs_last_dots, g.grid, g.block, 0, st, L.n, L.h * L.h, bx, by, bz, b, e, nat, r, zold,
+                     partials);
+  return (int)(g.grid.x * g.grid.y * g.grid.z);
+}
+
+int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
+                    hipStream_t st) {
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_f2d_dots, dim3(nb), dim3(256), 0, st, a, z, n, r, zold, partials);
+  return nb;
+}
+
 void launch_f2d(const float* a, double* b, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_f2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
 }
@@ -1012,6 +1090,8 @@ static void finalize(const CgScratch& cs, int nparts, int mode, hipStream_t st) 
   else
     hipLaunchKernelGGL(k_finalize<16>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
 }
+
+void launch_finalize_beta(const CgScratch& cs, int nparts, hipStream_t st) { finalize(cs, nparts, FIN_BETA, st); }
 
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                        const double* b, const double* x, double* r, const CgScratch& cs, int mode,

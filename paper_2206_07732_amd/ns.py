@@ -46,7 +46,8 @@ class NSParams(C.Structure):
                 ("max_iters", C.c_int), ("rtol", C.c_double), ("prec", C.c_int), ("x0", C.c_int),
                 ("p_scale", C.c_double),
                 ("depth", C.c_double), ("gen_len", C.c_double), ("damp_len", C.c_double),
-                ("vort_width", C.c_double), ("n_waves", C.c_int), ("waves", NSWave * 64)]
+                ("vort_width", C.c_double), ("n_waves", C.c_int), ("waves", NSWave * 64),
+                ("consistent", C.c_int), ("cn_sweeps", C.c_int)]
 
 
 class NSFields(C.Structure):
@@ -157,6 +158,8 @@ def params(wl, **opts) -> NSParams:
         P.body[m].free_heave, P.body[m].mass, P.body[m].pto_damping = int(b.free_heave), b.mass, b.pto_damping
         P.body[m].zeta0, P.body[m].zdot0 = b.zeta0, b.zdot0
     P.depth = wl.depth
+    P.consistent = int(wl.consistent)
+    P.cn_sweeps = int(wl.cn_sweeps)
     if wl.nwt:                                      # numerical wave tank
         from . import inputs as I
         P.gen_len, P.damp_len, P.vort_width = wl.nwt.get("gen", 0.0), wl.nwt.get("damp", 0.0), wl.nwt.get("vort", 0.0)

@@ -76,3 +76,21 @@ def test_level_count_matches_oracle(nslib, orc):
     assert nslib.num_levels(256, 1, 64) == 7
     assert nslib.num_levels(128, 64, 64) == 7
     assert nslib.num_levels(512, 256, 256) == 9
+
+
+def test_workspace_options_consistent_and_cn(nslib):
+    """The consistent predictor adds one cell array (the density at t^n),
+    Crank-Nicolson nine face arrays (rhs, diagonal, second iterate); values
+    out of range are refused."""
+    from paper_2206_07732_amd import inputs as I
+    L = nslib.lib()
+    wl = I.workload("c2")
+    nb0 = L.ns_workspace_bytes(ctypes.byref(nslib.params(wl)))
+    nc = wl.nx * wl.ny * wl.nz
+    nf = (wl.nx + 1) * wl.ny * wl.nz + wl.nx * (wl.ny + 1) * wl.nz + wl.nx * wl.ny * (wl.nz + 1)
+    nbc = L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, consistent=1)))
+    assert 8 * nc <= nbc - nb0 <= 8 * nc + 256
+    nbn = L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, cn_sweeps=3)))
+    assert 3 * 8 * nf <= nbn - nb0 <= 3 * 8 * nf + 9 * 256
+    for field, value in (("consistent", 2), ("cn_sweeps", -1), ("cn_sweeps", 65)):
+        assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, **{field: value}))) == 0, (field, value)
