@@ -27,6 +27,12 @@ Printed: ONE JSON line with
                same tank with the cylinder free: whole ns_step calls timed the
                same way, against the fixed-body step, with the heave range and
                the force over the body's weight
+  nwt_study    the same grid as a numerical wave tank (Airy waves generated at
+               the inlet, generation and damping zones, vorticity damping),
+               timed the same way
+  option_study the main workload with the predictor's options: consistent
+               mass/momentum transport, and the Crank-Nicolson viscous term
+               (N Jacobi sweeps), timed the same way
   roofline     the finest-level smoother pass (the dominant kernel): its
                algorithmic bytes per launch over its average duration, the
                duration taken from HIP events recorded with each dispatch
@@ -261,13 +267,27 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
     return out
 
 
-def fsi_study(name: str, steps: int, warmup: int, fixed: dict):
-    """Free heave on `name`: K whole ns_step calls after W warm-up steps, each
-    with the force on the free body and its heave update; fixed is the
-    fixed-body run of the same tank for comparison."""
+def option_overrides(opt: str) -> dict:
+    """'consistent', 'cnN' or both joined by '+' -> workload overrides."""
+    over = {}
+    for o in opt.split("+"):
+        if o == "consistent":
+            over["consistent"] = 1
+        elif o.startswith("cn") and o[2:].isdigit():
+            over["cn_sweeps"] = int(o[2:])
+        else:
+            raise SystemExit(f"unknown predictor option {o!r} (consistent, cnN)")
+    return over
+
+
+def variant_study(name: str, steps: int, warmup: int, fixed: dict, label: str = "", **over):
+    """A variant of the main tank (free heave, a numerical wave tank, or an
+    option of the predictor): K whole ns_step calls after W warm-up steps;
+    fixed is the main run on the same grid for comparison.  For a free body
+    also its heave range and its force over its weight."""
     import torch
     from paper_2206_07732_amd import inputs as I, ns
-    wl = I.workload(name)
+    wl = I.workload(name, **over)
     f = I.make_fields(wl)
     dt = I.cfl_dt(wl, f)
     S = ns.Solver(ns.params(wl), ns.device_fields(f))
@@ -276,34 +296,38 @@ def fsi_study(name: str, steps: int, warmup: int, fixed: dict):
         S.step(dt, t)
         t += dt
     torch.cuda.synchronize()
+    free = any(b.free_heave for b in wl.bodies)
     zeta, fz, iters = [], [], []
     a = time.perf_counter()
     for _ in range(steps):
         st = S.step(dt, t)
         t += dt
         iters.append(st["iters"])
-        b = S.body_state(0)           # host state: no device work
-        zeta.append(b["zeta"])
-        fz.append(b["F"][2])
+        if free:
+            b = S.body_state(0)       # host state: no device work
+            zeta.append(b["zeta"])
+            fz.append(b["F"][2])
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - a) / steps
     S.close()
-    mg = wl.bodies[0].mass * wl.g
     ncell = wl.nx * wl.ny * wl.nz
     out = {
-        "workload": wl.name,
+        "workload": wl.name + (f" [{label}]" if label else ""),
         "steps": steps,
         "ms_per_step": round(ms, 4),
         "mcell_steps_per_s": round(ncell * steps / (ms * steps * 1e-3) / 1e6, 3),
         "cg_iters": iters,
         "ms_per_cg_iter": round(ms / statistics.mean(iters), 4),
-        "fixed_body_ms_per_step": round(fixed["ms_per_step"], 4),
-        "fixed_body_ms_per_cg_iter": round(fixed["ms_per_step"] / statistics.mean(fixed["iters"]), 4),
-        "zeta_range_m": [round(min(zeta), 6), round(max(zeta), 6)],
-        "fz_over_mg_range": [round(min(fz) / mg, 4), round(max(fz) / mg, 4)],
+        "main_ms_per_step": round(fixed["ms_per_step"], 4),
+        "main_ms_per_cg_iter": round(fixed["ms_per_step"] / statistics.mean(fixed["iters"]), 4),
     }
-    log(f"[bench] free heave {name}: {ms:.3f} ms/step ({out['ms_per_cg_iter']} ms per CG iteration; fixed body "
-        f"{out['fixed_body_ms_per_cg_iter']}), zeta in {out['zeta_range_m']} m, Fz/mg in {out['fz_over_mg_range']}")
+    if free:
+        mg = wl.bodies[0].mass * wl.g
+        out["zeta_range_m"] = [round(min(zeta), 6), round(max(zeta), 6)]
+        out["fz_over_mg_range"] = [round(min(fz) / mg, 4), round(max(fz) / mg, 4)]
+    log(f"[bench] {name}{' ' + label if label else ''}: {ms:.3f} ms/step ({out['ms_per_cg_iter']} ms per CG iteration; main tank "
+        f"{out['main_ms_per_cg_iter']})" + (f", zeta in {out['zeta_range_m']} m, Fz/mg in {out['fz_over_mg_range']}"
+                                             if free else ""))
     return out
 
 
@@ -340,6 +364,13 @@ def main():
     ap.add_argument("--projection-steps", type=int, default=8)
     ap.add_argument("--fsi-workload", default="c2fsi",
                     help="workload of the free-heave study (a free body on the main tank); 'none' skips it")
+    ap.add_argument("--nwt-workload", default="c2nwt",
+                    help="workload of the wave-tank study (the main grid with generation and damping zones); "
+                         "'none' skips it")
+    ap.add_argument("--option-studies", default="consistent,cn3",
+                    help="comma-separated predictor options timed on the main workload: 'consistent' "
+                         "(consistent mass/momentum transport), 'cnN' (Crank-Nicolson viscous term by N "
+                         "Jacobi sweeps), or both joined by '+'; 'none' skips them")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2206_07732_amd", "weights", "guess_c4.npy"))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -365,7 +396,14 @@ def main():
                  for w in args.projection_workload.split(",")]
     fsi = None
     if args.fsi_workload != "none":
-        fsi = fsi_study(args.fsi_workload, args.steps, args.warmup, r)
+        fsi = variant_study(args.fsi_workload, args.steps, args.warmup, r)
+    nwt = None
+    if args.nwt_workload != "none":
+        nwt = variant_study(args.nwt_workload, args.steps, args.warmup, r)
+    opts = None
+    if args.option_studies != "none":
+        opts = [variant_study(args.workload, args.steps, args.warmup, r, label=o, **option_overrides(o))
+                for o in args.option_studies.split(",")]
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(r["wl"], r["f0"], r["dt"], args.cpu_seconds)
@@ -388,6 +426,8 @@ def main():
         "projection": r["projection"],
         "projection_study": study,
         "fsi_study": fsi,
+        "nwt_study": nwt,
+        "option_study": opts,
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }
