@@ -1228,6 +1228,11 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   launch_correct(ph, X->us, X->vs, X->ws, X->F.p, L0.bx, L0.by, L0.bz, dt, X->F.u, X->F.v, X->F.w, st);
   // the wave tank's relaxation zones, at the time of the step's properties
   launch_relax(ph, X->t_props, X->F.sigma, X->F.u, X->F.v, X->F.w, st);
+  // the zones changed sigma: the density consistent transport starts the next
+  // step from, and the viscosity of the force below, are those of the
+  // relaxed level set
+  if ((ph.gen_len > 0.0 || ph.damp_len > 0.0) && (X->nfree > 0 || X->P.consistent))
+    launch_props(ph, X->F.sigma, X->t_props, X->rho, X->rfl, X->mu, X->chi, st);
   // the hydrodynamic force of the new fields, for the next heave update
   int nb[4];
   if (X->nfree > 0 && free_forces_queue(X, nb) != 0)

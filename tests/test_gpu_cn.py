@@ -141,3 +141,90 @@ def test_cn_c2_predictor_parity_and_convergence(orc):
         print(f"[cn c2 convergence] {k} max|u3-u8|/max|u*|={d:.2e}", flush=True)
         assert d < 1e-12, k
     S8.close()
+
+
+def rel_flow(a, b, fields):
+    """Relative error judged on the flow's own velocity scale (a component
+    that is zero up to round-off is not divided by its own norm)."""
+    U = max(float(np.max(np.abs(fields[k]))) for k in ("u", "v", "w"))
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), U * np.sqrt(b.size), 1e-300))
+
+
+SHAPES = [("ragged3d", 3, 1), ("odd1level", 2, 0), ("odd1level", 3, 1)]
+
+
+@pytest.mark.parametrize("name,sweeps,consistent", SHAPES)
+def test_options_on_ragged_and_single_level_grids(orc, name, sweeps, consistent):
+    """70x6x22 (not a multiple of the tiles, two MG levels) and 129x8x8 (odd
+    nx: one level solved by the multi-block sweeps) with the Crank-Nicolson
+    term, alone or with consistent transport: the predictor, then a step with
+    the CG count forced to the oracle's."""
+    from test_gpu_parity import case
+    wl = case(name)
+    wl.cn_sweeps, wl.consistent = sweeps, consistent
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    P = orc.params(wl)
+    S, dev = make_solver(wl, f)
+    S.momentum_step(dt, dt)
+    torch.cuda.synchronize()
+    if consistent:
+        ref = orc.momentum_cons(P, f["u"], f["v"], f["w"], f["sigma"], dt, dt,
+                                orc.properties(P, f["sigma"], 0.0)[0])[0]
+    else:
+        ref = orc.momentum(P, f["u"], f["v"], f["w"], f["sigma"], dt, dt)
+    for k, r in zip(("us", "vs", "ws"), ref):
+        e = rel_flow(host(S.buffer(k)), r, f)
+        print(f"[options shape] {name} sweeps={sweeps} cons={consistent} {k} rel={e:.2e}", flush=True)
+        assert e < 1e-13, k
+    S.close()
+    _, st, rc = orc.step(P, f, dt, 0.0)
+    assert rc == 0
+    it = st["iters"]
+    ref, _, _ = orc.step(orc.params(wl, max_iters=it, rtol=0.0), f, dt, 0.0)
+    S, dev = make_solver(wl, f, max_iters=it, rtol=0.0)
+    sg = S.step(dt, 0.0, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert sg["iters"] == it
+    for key in ("sigma", "u", "v", "w", "p"):
+        e = rel_flow(host(dev[key]), ref[key], f) if key in ("u", "v", "w") else rel(host(dev[key]), ref[key])
+        print(f"[options shape step] {name} field={key} rel={e:.2e}", flush=True)
+        assert e < 1e-10, key
+    S.close()
+
+
+def test_wave_tank_with_both_options_step_parity(orc):
+    """The 2-D wave tank (inlet, relaxation zones, vorticity damping) with
+    consistent transport and the Crank-Nicolson term: a step with the CG
+    count forced to the oracle's, then two free-running steps."""
+    wl = workload("c1nwt", 3, consistent=1)
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    P = orc.params(wl)
+    _, st, rc = orc.step(P, f, dt, 0.0)
+    assert rc == 0
+    it = st["iters"]
+    ref, _, _ = orc.step(orc.params(wl, max_iters=it, rtol=0.0), f, dt, 0.0)
+    S, dev = make_solver(wl, f, max_iters=it, rtol=0.0)
+    sg = S.step(dt, 0.0, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert sg["iters"] == it
+    for key in ("sigma", "u", "w", "p"):
+        r = rel(host(dev[key]), ref[key])
+        print(f"[nwt options step] field={key} rel={r:.2e}", flush=True)
+        assert r < 1e-10, key
+    S.close()
+    S, dev = make_solver(wl, f)
+    ref, t = f, 0.0
+    for s in range(3):
+        ref, _, rc = orc.step(P, ref, dt, t)
+        assert rc == 0
+        S.step(dt, t)
+        t += dt
+    torch.cuda.synchronize()
+    for key in ("sigma", "u", "w", "p"):
+        r = rel(host(dev[key]), ref[key])
+        print(f"[nwt options free run] field={key} rel={r:.2e}", flush=True)
+        assert r < 1e-8, key
+    S.close()
