@@ -35,7 +35,10 @@ Printed: ONE JSON line with
                (N Jacobi sweeps), timed the same way
   roofline     the finest-level smoother pass (the dominant kernel): its
                algorithmic bytes per launch over its average duration, the
-               duration taken from HIP events recorded with each dispatch
+               duration taken from HIP events recorded with each dispatch;
+               against the published 8 TB/s and a measured device copy
+  measured_ceilings  a 1 GiB device copy and an 8192^3 BF16 matrix product
+               timed on the device, beside the published peaks
   cpu_baseline the FP64 CPU oracle, single-threaded, on a bounded sample of
                the same workload
 """
@@ -132,6 +135,11 @@ def run_gpu(args):
     log(f"[bench] smoother pass: avg {avg_ms*1e3:.2f} us over {reps} back-to-back launches "
         f"({achieved:.0f} GB/s); in-step per-dispatch events {kms/max(kn,1)*1e3:.2f} us over {kn}")
     S.close()
+    ceil = measured_ceilings()
+    roofline["copy_ceiling_gbs"] = ceil["copy_gbs"]
+    roofline["frac_of_copy"] = round(achieved / ceil["copy_gbs"], 4)
+    log(f"[bench] measured ceilings: device copy {ceil['copy_gbs']:.0f} GB/s, BF16 GEMM "
+        f"{ceil['bf16_gemm_tflops']:.0f} TFLOP/s; smoother pass at {100 * achieved / ceil['copy_gbs']:.0f}% of the copy")
 
     # ---- projection time to 1e-10, FP64 V-cycle vs FP32 V-cycle in FP64 CG
     proj = {}
@@ -163,7 +171,42 @@ def run_gpu(args):
               "dt": dt, "cfl": wl.cfl, "solver": "flexible PCG, V(2,2) red-black GS, FP64",
               "rtol": 1e-10, "mg_levels": ns.num_levels(wl.nx, wl.ny, wl.nz)}
     return {"value": value, "ms_per_step": ms_per_step, "iters": iters, "roofline": roofline,
-            "projection": proj, "config": config, "wl": wl, "f0": f0, "dt": dt}
+            "projection": proj, "config": config, "wl": wl, "f0": f0, "dt": dt, "ceilings": ceil}
+
+
+def measured_ceilings():
+    """What the device reaches on plain work, as context for the published
+    peaks: a 1 GiB device-to-device copy (bytes read + written per second)
+    and an 8192^3 BF16 matrix product (torch, i.e. the vendor library)."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 8 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    m = 8192
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(m, m, device="cuda", dtype=torch.bfloat16, generator=g)
+    y = torch.randn(m, m, device="cuda", dtype=torch.bfloat16, generator=g)
+    for _ in range(2):
+        z = torch.matmul(x, y)
+    e0.record()
+    for _ in range(5):
+        z = torch.matmul(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    gemm = 2.0 * m ** 3 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del x, y, z
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(copy_gbs, 1), "bf16_gemm_tflops": round(gemm, 1)}
 
 
 # FLOPs of one inference of the learned-guess network per voxel of the full
@@ -361,7 +404,7 @@ def main():
     ap.add_argument("--projection-workload", default="c3,c4eval",
                     help="comma-separated workloads of the projection study (FP64 vs FP32 V-cycle vs learned "
                          "guess); 'none' skips it")
-    ap.add_argument("--projection-steps", type=int, default=8)
+    ap.add_argument("--projection-steps", type=int, default=20)
     ap.add_argument("--fsi-workload", default="c2fsi",
                     help="workload of the free-heave study (a free body on the main tank); 'none' skips it")
     ap.add_argument("--nwt-workload", default="c2nwt",
@@ -429,6 +472,7 @@ def main():
         "nwt_study": nwt,
         "option_study": opts,
         "roofline": r["roofline"],
+        "measured_ceilings": r["ceilings"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
