@@ -379,10 +379,11 @@ def run_cpu_baseline(wl, f0, dt, seconds: float):
     from oracle import oracle as O
     O.lib()
     P = O.params(wl)
-    f, t, n = f0, 0.0, 0
+    f, t, n, iters = f0, 0.0, 0, []
     t0 = time.perf_counter()
     while True:
         f, st, rc = O.step(P, f, dt, t)
+        iters.append(st["iters"])
         t += dt
         n += 1
         el = time.perf_counter() - t0
@@ -390,7 +391,22 @@ def run_cpu_baseline(wl, f0, dt, seconds: float):
             break
     return {"value": round(wl.ncells * n / el / 1e6, 4), "unit": "Mcell-steps/s", "cores": 1,
             "kind": "oracle", "sample": f"first {n} step(s) of the same workload from its initial "
-                                        f"condition, {el:.1f} s, one thread"}
+                                        f"condition, {el:.1f} s, one thread",
+            "cg_iters": iters, "host": host_cpu()}
+
+
+def host_cpu() -> str:
+    """CPU model and logical core count of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores"
 
 
 def main():
