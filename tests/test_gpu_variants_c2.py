@@ -1,0 +1,91 @@
+"""The variants the benchmark times on the 128x64x64 tank, at that full size
+and in that configuration, against the FP64 CPU oracle: the free cylinder
+(c2fsi), the wave tank (c2nwt), consistent transport, and the Crank-Nicolson
+term by 3 sweeps.  One step with the CG count forced to the oracle's agrees
+to 1e-10 relative per field; three free-running steps agree to 1e-8."""
+import numpy as np
+import pytest
+
+from paper_2206_07732_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+VARIANTS = {
+    "c2fsi": ("c2fsi", {}),
+    "c2nwt": ("c2nwt", {}),
+    "c2-consistent": ("c2", {"consistent": 1}),
+    "c2-cn3": ("c2", {"cn_sweeps": 3}),
+}
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_flow(a, b, fields):
+    """Relative error on the flow's velocity scale for velocities (a
+    component that is nearly zero is not divided by its own norm)."""
+    U = max(float(np.max(np.abs(fields[k]))) for k in ("u", "v", "w"))
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), U * np.sqrt(b.size), 1e-300))
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / (nb if nb > 0 else 1.0))
+
+
+def err(key, a, b, f):
+    return rel_flow(a, b, f) if key in ("u", "v", "w") else rel(a, b)
+
+
+def oracle_step(orc, P, f, dt, t, free):
+    if free:
+        r, st, rc, _ = orc.step_fsi(P, f, dt, t)
+    else:
+        r, st, rc = orc.step(P, f, dt, t)
+    return r, st, rc
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_c2_variant_forced_and_free_running(orc, variant):
+    from paper_2206_07732_amd import ns
+    name, over = VARIANTS[variant]
+    wl = I.workload(name, **over)
+    free = any(b.free_heave for b in wl.bodies)
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    _, st, rc = oracle_step(orc, orc.params(wl), f, dt, 0.0, free)
+    assert rc == 0
+    k = st["iters"]
+    ref, _, _ = oracle_step(orc, orc.params(wl, max_iters=k, rtol=0.0), f, dt, 0.0, free)
+    dev = ns.device_fields(f)
+    S = ns.Solver(ns.params(wl, max_iters=k, rtol=0.0), dev)
+    sg = S.step(dt, 0.0, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert sg["iters"] == k
+    for key in ("sigma", "u", "v", "w", "p"):
+        e = err(key, host(dev[key]), ref[key], f)
+        print(f"[c2 variant] {variant} forced {k} it: {key} rel={e:.2e}", flush=True)
+        assert e < 1e-10, key
+    S.close()
+    P = orc.params(wl)
+    dev = ns.device_fields(f)
+    S = ns.Solver(ns.params(wl), dev)
+    ref, t = f, 0.0
+    for s in range(3):
+        ref, _, rc = oracle_step(orc, P, ref, dt, t, free)
+        assert rc == 0
+        S.step(dt, t)
+        t += dt
+    torch.cuda.synchronize()
+    for key in ("sigma", "u", "v", "w", "p"):
+        e = err(key, host(dev[key]), ref[key], f)
+        print(f"[c2 variant] {variant} 3 free steps: {key} rel={e:.2e}", flush=True)
+        assert e < 1e-8, key
+    if free:
+        b = S.body_state(0)
+        print(f"[c2 variant] {variant} heave {b['zeta']:+.6e} oracle {P.body[0].zeta:+.6e}", flush=True)
+        assert abs(b["zeta"] - P.body[0].zeta) <= 1e-9 * abs(P.body[0].zeta) + 1e-15
+    S.close()
