@@ -19,8 +19,9 @@
 //   * all levels from about a thousand cells down run in one workgroup out of
 //     LDS;
 //   * the direction update d = z + beta d is folded into the operator
-//     application; every CG reduction ends in one fixed-order pass over the
-//     per-block partials, so results are bitwise reproducible.
+//     application, which carries q = A d by its recurrence A z + beta q;
+//     every CG reduction ends in one fixed-order pass over the per-block
+//     partials, so results are bitwise reproducible.
 #include <hip/hip_ext.h>
 
 #include "ns_internal.h"
@@ -832,7 +833,13 @@ __global__ void __launch_bounds__(256) k_dots_beta(Dims n, const double* __restr
   block_partials<2>(v, partials, tl.lin);
 }
 
-// d = zn + beta d_old (first: d = zn); q = A d; alpha = rho / <d, q>
+// d = zn + beta d_old, q = A d = A zn + beta q_old (first: d = zn, q = A zn);
+// alpha = rho / <d, q>.  Carrying q = A d by its recurrence keeps the
+// stencil on zn alone, and d_old and q_old are read pointwise: the stencil's
+// load count, not its bytes, limits this kernel.  A wavefront is one x-row of
+// 64 cells (blockDim.x == 64), so the x neighbours of zn come from the
+// adjacent lanes and only a row's end lanes load them; every lane takes part
+// in the shuffles (c is 0 outside the grid).
 __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const double* __restrict__ bx,
                                                   const double* __restrict__ by,
                                                   const double* __restrict__ bz,
@@ -843,20 +850,28 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
                                                   double* __restrict__ partials) {
   CELL_INDEX;
   double v[1] = {0.0};
+  const double zc = zn[c];
+  const double zl = __shfl_up(zc, 1, 64), zr = __shfl_down(zc, 1, 64);
   if (inside) {
-    const double beta = first ? 0.0 : scal[S_BETA];
-    auto D = [&](size_t p) { return first ? zn[p] : zn[p] + beta * dold[p]; };
+    const int lane = threadIdx.x;
     const size_t sxy = (size_t)n.nx * n.ny;
     const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
     const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-    const double dc = D(c);
+    double zw = zc, ze = zc;
+    if (i > 0) zw = lane > 0 ? zl : zn[c - 1];
+    if (i < n.nx - 1) ze = lane < 63 ? zr : zn[c + 1];
     const double bu = bz[c + sxy];
-    const double du = D(k < n.nz - 1 ? c + sxy : c);   // unconditional: all loads in flight together
-    double acc = bx[fx] * (dc - D(i > 0 ? c - 1 : c)) + bx[fx + 1] * (dc - D(i < n.nx - 1 ? c + 1 : c)) +
-                 by[fy] * (dc - D(j > 0 ? c - n.nx : c)) + by[fy + n.nx] * (dc - D(j < n.ny - 1 ? c + n.nx : c)) +
-                 bz[c] * (dc - D(k > 0 ? c - sxy : c));
-    acc += (k < n.nz - 1) ? bu * (dc - du) : 2.0 * bu * dc;
-    const double qc = ih2 * acc;
+    const double zu = zn[k < n.nz - 1 ? c + sxy : c];   // unconditional: all loads in flight together
+    double acc = bx[fx] * (zc - zw) + bx[fx + 1] * (zc - ze) + by[fy] * (zc - zn[j > 0 ? c - n.nx : c]) +
+                 by[fy + n.nx] * (zc - zn[j < n.ny - 1 ? c + n.nx : c]) + bz[c] * (zc - zn[k > 0 ? c - sxy : c]);
+    acc += (k < n.nz - 1) ? bu * (zc - zu) : 2.0 * bu * zc;
+    const double qz = ih2 * acc;
+    double dc = zc, qc = qz;
+    if (!first) {
+      const double beta = scal[S_BETA];
+      dc = zc + beta * dold[c];
+      qc = qz + beta * q[c];
+    }
     dnew[c] = dc;
     q[c] = qc;
     v[0] = dc * qc;
