@@ -146,9 +146,9 @@ __device__ __forceinline__ size_t lidx(const Dims& n, const SplitGeo& g, bool sp
 // through the cell's own pair index), so all of a thread's loads are in
 // flight together and a 0 * garbage product never enters a sum.
 template <typename T, typename O>
-__device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T h2, const T* __restrict__ bx,
-                                           const T* __restrict__ by, const T* __restrict__ bz, T bc, int i, int j,
-                                           int k, size_t pos, O o) {
+__device__ __forceinline__ T gs_split_value_x(const Dims& n, const SplitGeo& sg, T h2, const T* __restrict__ bx,
+                                             const T* __restrict__ by, const T* __restrict__ bz, T bc, int i,
+                                             int j, int k, size_t pos, T vw, T ve, O o) {
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
@@ -157,16 +157,25 @@ __device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T
   const bool top = (k == n.nz - 1);
   const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0;
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  // x neighbours: cell i - 1 is in pair (i - 1) >> 1, cell i + 1 in pair (i + 1) >> 1
   const size_t sz = (size_t)sg.hx * n.ny;
-  const size_t pw = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos;
-  const size_t pe = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
   const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos;
   const size_t pd = D ? pos - sz : pos, pu = top ? pos : pos + sz;
-  const T vw = o(pw), ve = o(pe), vs = o(ps), vn = o(pn), vd = o(pd), vu = o(pu);
+  const T vs = o(ps), vn = o(pn), vd = o(pd), vu = o(pu);
   const T num = h2 * bc + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
                 (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
   return num / diag;
+}
+
+// the same with the x neighbours loaded: cell i - 1 is in pair (i - 1) >> 1,
+// cell i + 1 in pair (i + 1) >> 1
+template <typename T, typename O>
+__device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T h2, const T* __restrict__ bx,
+                                           const T* __restrict__ by, const T* __restrict__ bz, T bc, int i, int j,
+                                           int k, size_t pos, O o) {
+  const bool W = i > 0, E = i < n.nx - 1;
+  const size_t pw = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos;
+  const size_t pe = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
+  return gs_split_value_x<T>(n, sg, h2, bx, by, bz, bc, i, j, k, pos, o(pw), o(pe), o);
 }
 
 // one colour of Gauss-Seidel on colour-split b, e (FINE: finest-level
@@ -211,26 +220,36 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const d
   const int k = tl.z * blockDim.z + threadIdx.z;
   const SplitGeo sg = split_geo(n);
   double v[2] = {0.0, 0.0};
-  if (j < n.ny && k < n.nz && ti < sg.hx) {
+  const bool live = j < n.ny && k < n.nz && ti < sg.hx;
+  const size_t pos = live ? (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k) : 0;
+  const double* eo = e + sg.P;   // the black plane
+  // This pair's black value.  The red cell's x neighbours are this pair's
+  // black cell and the adjacent pair's, which the adjacent lane holds (a
+  // wavefront is 64 consecutive pairs of one row); every lane takes part in
+  // the shuffles, and only a row's end lanes load their neighbour.
+  const double eb = eo[pos];
+  const double ebl = __shfl_up(eb, 1, 64), ebr = __shfl_down(eb, 1, 64);
+  if (live) {
     const size_t sxy = (size_t)n.nx * n.ny;
     const size_t row = (size_t)n.nx * j + sxy * k;
-    const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k);
     const int par = (j + k) & 1;
     const int i = 2 * ti + par, io = 2 * ti + 1 - par;
-    const double* eo = e + sg.P;   // the black plane
+    const int lane = threadIdx.x;
     if (i < n.nx) {
-      const double z = gs_split_value<double>(n, sg, h2, bx, by, bz, b[pos], i, j, k, pos,
-                                              [&](size_t q) { return eo[q]; });
+      double vw = eb, ve = eb;   // par 1: west is this pair's black; par 0: east is
+      if (par == 0 && i > 0) vw = lane > 0 ? ebl : eo[pos - 1];
+      if (par == 1 && i < n.nx - 1) ve = lane < 63 ? ebr : eo[pos + 1];
+      const double z = gs_split_value_x<double>(n, sg, h2, bx, by, bz, b[pos], i, j, k, pos, vw, ve,
+                                                [&](size_t q) { return eo[q]; });
       nat[row + i] = z;
       const double rv = r[row + i];
       v[0] += rv * z;
       v[1] += rv * zold[row + i];
     }
     if (io < n.nx) {
-      const double z = eo[pos];
-      nat[row + io] = z;
+      nat[row + io] = eb;
       const double rv = r[row + io];
-      v[0] += rv * z;
+      v[0] += rv * eb;
       v[1] += rv * zold[row + io];
     }
   }
@@ -256,23 +275,32 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
     else
       return b[(size_t)c * sg.P + q];
   };
+  // This pair's red value h2 b / D, formed also where the red cell lies past
+  // the row's end (b clamped into the row, an unused 1/D entry), since the
+  // adjacent lane reads it: the black cell's x neighbours are this pair's red
+  // cell and the adjacent pair's (a wavefront is 64 consecutive pairs of one
+  // row), and only a row's end lanes load theirs.
+  const T br = bval(0, pos, ir < n.nx ? ir : n.nx - 1, j, k);
+  const T rv = h2 * br * invd[pos];
   if (ir < n.nx) {
-    const T br = bval(0, pos, ir, j, k);
-    e[pos] = h2 * br * invd[pos];
+    e[pos] = rv;
     if constexpr (NAT) bs[pos] = br;
   }
+  const T rl = __shfl_up(rv, 1, 64), rr = __shfl_down(rv, 1, 64);
   if (ib >= n.nx) return;
   const T bb = bval(1, pos, ib, j, k);
   if constexpr (NAT) bs[sg.P + pos] = bb;
   // red neighbour values h2 b / D through in-range indices (walls: own pair)
   const bool W = ib > 0, E = ib < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
-  const size_t pw = W ? pos - (size_t)((ib & 1) ? 0 : 1) : pos, pe = E ? pos + (size_t)((ib & 1) ? 1 : 0) : pos;
   const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
-  const int iw = W ? ib - 1 : ib, ie = E ? ib + 1 : ib, js = S ? j - 1 : j, jn = N ? j + 1 : j;
+  const int js = S ? j - 1 : j, jn = N ? j + 1 : j;
   const int kd = D ? k - 1 : k, ku = U ? k + 1 : k;
   auto red = [&](size_t q, int ii, int jj, int kk) { return h2 * bval(0, q, ii, jj, kk) * invd[q]; };
-  const T vw = red(pw, iw, j, k), ve = red(pe, ie, j, k), vs = red(ps, ib, js, k), vn = red(pn, ib, jn, k),
-          vd = red(pd, ib, j, kd), vu = red(pu, ib, j, ku);
+  const int lane = threadIdx.x;
+  T vw = rv, ve = rv;   // par 0: west is this pair's red cell; par 1: east is
+  if (par == 0 && E) ve = lane < 63 ? rr : red(pos + 1, ib + 1, j, k);
+  if (par == 1 && W) vw = lane > 0 ? rl : red(pos - 1, ib - 1, j, k);
+  const T vs = red(ps, ib, js, k), vn = red(pn, ib, jn, k), vd = red(pd, ib, j, kd), vu = red(pu, ib, j, ku);
   const size_t c = row + ib;
   const size_t fx = ib + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = ib + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
