@@ -993,7 +993,8 @@ void backward(ns_net* N) {
   wgrad<16, 16>(N, N->res0, N->v0, N->x0, N->d1, 0);
 }
 
-// canonical index (oracle layout) <-> internal index
+// canonical parameter index (the flat order of ns_net_set_params and
+// ns_net_get_params) <-> internal index
 // conv layer l: canonical w[co][ci][kz][ky][kx] (ci < true C_in) then b[co];
 // internal W[co][tap][ci_pad], tap = (kz * 3 + ky) * 3 + kx
 template <typename F>
