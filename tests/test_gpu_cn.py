@@ -228,3 +228,27 @@ def test_wave_tank_with_both_options_step_parity(orc):
         print(f"[nwt options free run] field={key} rel={r:.2e}", flush=True)
         assert r < 1e-8, key
     S.close()
+
+
+def test_long_free_run_wave_tank_with_both_options(orc):
+    """60 free-running steps of the 2-D wave tank (about two wave periods)
+    with consistent transport and the Crank-Nicolson term, checked against
+    the oracle every 20 steps: the two stay together to 1e-8."""
+    wl = workload("c1nwt", 3, consistent=1)
+    f = I.make_fields(wl)
+    dt = I.cfl_dt(wl, f)
+    P = orc.params(wl)
+    S, dev = make_solver(wl, f)
+    ref, t = f, 0.0
+    for s in range(60):
+        ref, _, rc = orc.step(P, ref, dt, t)
+        assert rc == 0
+        S.step(dt, t)
+        t += dt
+        if (s + 1) % 20 == 0:
+            torch.cuda.synchronize()
+            for key in ("sigma", "u", "w", "p"):
+                r = rel(host(dev[key]), ref[key])
+                print(f"[nwt long run] step {s + 1} {key} rel={r:.2e}", flush=True)
+                assert r < 1e-8, (s, key)
+    S.close()
