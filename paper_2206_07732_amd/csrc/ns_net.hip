@@ -71,10 +71,12 @@ __device__ __forceinline__ long vox_count(const VDims& d) { return (long)d.nx * 
 // activation only when Y is given.
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHV = kHX * kHY * kHZ;
-// the two 8-channel halves of a staged chunk live in separate planes (16-byte
-// entries), the second shifted by 64 bytes, so eight consecutive lanes of an
-// A-fragment read touch 128 contiguous bytes
-constexpr int kPlane = kHV + 4;
+// The two 8-channel halves of a staged chunk live in separate planes
+// (16-byte entries).  Adjacent 16-lane groups of an A-fragment read take the
+// two halves of the same voxels; the LDS serves half of one group with half
+// of the next, which is free of bank conflicts only when their entries are a
+// multiple of 16 apart, so the plane stride is a multiple of 16 entries.
+constexpr int kPlane = (kHV + 15) / 16 * 16;
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 u) { return __builtin_bit_cast(bf16x8, u); }
 
