@@ -96,10 +96,9 @@ __global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restric
   static_assert(EPI != 2 || COUT == 16, "the fused head takes 16 channels");
   constexpr int NT = COUT / 16, NC = CIN / 16;
   constexpr int NE = (2 * kHV + 255) / 256;   // 16-byte tile pieces per thread
-  // Up to two output-channel tiles the chunk's weight fragments are loaded
-  // ahead of the next chunk's tile (kept in registers), so waiting for the
-  // weights never waits for that prefetch; wider layers load per tap pair.
-  constexpr bool AHEAD = NT <= 2;
+  // Weight fragments are loaded per tap pair (they stay in the caches):
+  // holding a chunk's fourteen ahead in registers cost two of the wide
+  // layers a wave per SIMD of occupancy, and the forward 9%.
   __shared__ u32x4 tile[2][2 * kPlane];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, kg = lane >> 4;
@@ -160,13 +159,6 @@ __global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restric
   __syncthreads();
 #pragma unroll 1
   for (int c = 0; c < NC; ++c) {
-    bf16x8 bw[AHEAD ? 14 : 1][NT];
-    if constexpr (AHEAD) {
-#pragma unroll
-      for (int p = 0; p < 14; ++p)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) bw[p][t] = wfrag(p, t, c);
-    }
     if (c + 1 < NC) fetch(c + 1);
     const u32x4* T = tile[c & 1] + lbase;
 #pragma unroll
@@ -175,7 +167,7 @@ __global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restric
       const int o = (kg >> 1) ? tap_off(2 * p + 1) : tap_off(2 * p);
       bf16x8 b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = AHEAD ? bw[AHEAD ? p : 0][t] : wfrag(p, t, c);
+      for (int t = 0; t < NT; ++t) b[t] = wfrag(p, t, c);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const bf16x8 a = as_bf16x8(tv ? T[o + m * kHX] : zero);
