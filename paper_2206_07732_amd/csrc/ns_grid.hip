@@ -158,27 +158,32 @@ __global__ void __launch_bounds__(256) k_advect(Phys P, const double* __restrict
   const size_t c = i + (size_t)n.nx * j + sxy * k;
   const double sc = s[c];
   double acc = 0.0;
+  // each direction's four neighbours are loaded before the upwind side is
+  // chosen, so no load waits on the velocity's sign
   {  // x
     const size_t fm = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
     const double am = u[fm], ap = u[fm + 1];
     auto S = [&](int o) { return s[c + (clampi(i + o, 0, n.nx - 1) - i)]; };
-    const double sp = ap >= 0.0 ? koren(S(-1), sc, S(1)) : koren(S(2), S(1), sc);
-    const double sm = am >= 0.0 ? koren(S(-2), S(-1), sc) : koren(S(1), sc, S(-1));
+    const double m2 = S(-2), m1 = S(-1), p1 = S(1), p2 = S(2);
+    const double sp = ap >= 0.0 ? koren(m1, sc, p1) : koren(p2, p1, sc);
+    const double sm = am >= 0.0 ? koren(m2, m1, sc) : koren(p1, sc, m1);
     acc += ap * (sp - sc) - am * (sm - sc);
   }
   {  // y
     const size_t fm = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
     const double am = v[fm], ap = v[fm + n.nx];
     auto S = [&](int o) { return s[c + (ptrdiff_t)(clampi(j + o, 0, n.ny - 1) - j) * n.nx]; };
-    const double sp = ap >= 0.0 ? koren(S(-1), sc, S(1)) : koren(S(2), S(1), sc);
-    const double sm = am >= 0.0 ? koren(S(-2), S(-1), sc) : koren(S(1), sc, S(-1));
+    const double m2 = S(-2), m1 = S(-1), p1 = S(1), p2 = S(2);
+    const double sp = ap >= 0.0 ? koren(m1, sc, p1) : koren(p2, p1, sc);
+    const double sm = am >= 0.0 ? koren(m2, m1, sc) : koren(p1, sc, m1);
     acc += ap * (sp - sc) - am * (sm - sc);
   }
   {  // z
     const double am = w[c], ap = w[c + sxy];
     auto S = [&](int o) { return s[c + (ptrdiff_t)(clampi(k + o, 0, n.nz - 1) - k) * (ptrdiff_t)sxy]; };
-    const double sp = ap >= 0.0 ? koren(S(-1), sc, S(1)) : koren(S(2), S(1), sc);
-    const double sm = am >= 0.0 ? koren(S(-2), S(-1), sc) : koren(S(1), sc, S(-1));
+    const double m2 = S(-2), m1 = S(-1), p1 = S(1), p2 = S(2);
+    const double sp = ap >= 0.0 ? koren(m1, sc, p1) : koren(p2, p1, sc);
+    const double sm = am >= 0.0 ? koren(m2, m1, sc) : koren(p1, sc, m1);
     acc += ap * (sp - sc) - am * (sm - sc);
   }
   out[c] = sc - (dt / P.h) * acc;
@@ -199,21 +204,22 @@ __global__ void __launch_bounds__(256) k_reinit(Phys P, const double* __restrict
   if (i >= n.nx || j >= n.ny || k >= n.nz) return;
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
+  // every load is issued before the sign test, so none waits on it
   const double a0 = s0[c];
-  const double h = P.h;
-  const double sg = a0 / sqrt(a0 * a0 + h * h);
   const double sc = cur[c];
-  if (sg == 0.0) {
-    nxt[c] = sc;
-    return;
-  }
-  const double ih = 1.0 / h;
   const double nb[6] = {cur[i > 0 ? c - 1 : c],
                         cur[i < n.nx - 1 ? c + 1 : c],
                         cur[j > 0 ? c - n.nx : c],
                         cur[j < n.ny - 1 ? c + n.nx : c],
                         cur[k > 0 ? c - sxy : c],
                         cur[k < n.nz - 1 ? c + sxy : c]};
+  const double h = P.h;
+  const double sg = a0 / sqrt(a0 * a0 + h * h);
+  if (sg == 0.0) {
+    nxt[c] = sc;
+    return;
+  }
+  const double ih = 1.0 / h;
   double g2 = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
