@@ -892,7 +892,9 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     delete X;
     return NS_EHIP;
   }
-  // coherent and mapped: the reduction kernels store the values the host
+  // From here on a failure releases what was acquired through ns_destroy,
+  // which accepts a partly built context (its fields start null).
+  // Coherent and mapped: the reduction kernels store the values the host
   // tests straight into it, so reading them needs no copy
   if (hipHostMalloc((void**)&X->host, S_COUNT * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped) !=
       hipSuccess) {
@@ -900,8 +902,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     return NS_EHIP;
   }
   if (hipHostGetDevicePointer((void**)&X->host_dev, X->host, 0) != hipSuccess) {
-    (void)hipHostFree(X->host);
-    delete X;
+    ns_destroy(X);
     return NS_EHIP;
   }
   // small grids: the reductions the host alone reads leave their per-block
@@ -912,9 +913,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     if (hipHostMalloc((void**)&X->hpart, (size_t)2 * X->nparts * sizeof(double),
                       hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer((void**)&X->hpart_dev, X->hpart, 0) != hipSuccess) {
-      if (X->hpart) (void)hipHostFree(X->hpart);
-      (void)hipHostFree(X->host);
-      delete X;
+      ns_destroy(X);
       return NS_EHIP;
     }
   }
@@ -931,20 +930,15 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
   X->fcap = (4 * X->nparts) / 3;
   if (X->nfree > 0 &&
       hipHostMalloc((void**)&X->fpart, (size_t)3 * 4 * X->fcap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    if (X->hpart) (void)hipHostFree(X->hpart);
-    (void)hipHostFree(X->host);
-    delete X;
+    ns_destroy(X);
     return NS_EHIP;
   }
   if (hipEventCreateWithFlags(&X->ev_rr, hipEventDisableTiming) != hipSuccess) {
-    (void)hipHostFree(X->host);
-    delete X;
+    ns_destroy(X);
     return NS_EHIP;
   }
   if (hipStreamCreateWithFlags(&X->cap_st, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipEventDestroy(X->ev_rr);
-    (void)hipHostFree(X->host);
-    delete X;
+    ns_destroy(X);
     return NS_EHIP;
   }
   X->launch_mode = NS_LAUNCH_GRAPH;

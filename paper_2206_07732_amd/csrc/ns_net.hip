@@ -1045,10 +1045,11 @@ ns_status ns_net_create(int nx, int ny, int nz, int training, void* ws, size_t b
     delete N;
     return NS_EHIP;
   }
-  if (training) {
-    (void)hipMemsetAsync(N->m, 0, N->np * sizeof(float), N->st);
-    (void)hipMemsetAsync(N->v, 0, N->np * sizeof(float), N->st);
-    (void)hipMemsetAsync(N->g, 0, N->np * sizeof(float), N->st);
+  if (training && (hipMemsetAsync(N->m, 0, N->np * sizeof(float), N->st) != hipSuccess ||
+                   hipMemsetAsync(N->v, 0, N->np * sizeof(float), N->st) != hipSuccess ||
+                   hipMemsetAsync(N->g, 0, N->np * sizeof(float), N->st) != hipSuccess)) {
+    ns_net_destroy(N);
+    return NS_EHIP;
   }
   *out = N;
   return NS_OK;
