@@ -27,9 +27,11 @@
  *
  * Memory and streams.  Every array pointer is a DEVICE pointer owned by the
  * caller.  ns_init borrows the field arrays and the workspace for the life of
- * the context; the library never allocates device memory (it allocates only
- * a small host context and a few bytes of pinned host memory for scalar
- * read-back).  All device work is enqueued on the stream given to ns_init;
+ * the context; the library never calls hipMalloc.  It allocates a host
+ * context, pinned host memory for the values the host tests (the CG scalars,
+ * the per-block partials of grids of at most 8192 blocks, up to 128 KB, and
+ * free bodies' force partials), one event and one capture-only stream, and
+ * the recorded V-cycle graphs; ns_destroy releases them.  All device work is enqueued on the stream given to ns_init;
  * calls that return solver statistics or diagnostics synchronise that stream.
  * A context must not be used from two host threads at once.
  *
