@@ -205,6 +205,8 @@ class Solver:
         for k, s in shapes.items():
             if tuple(fields[k].shape) != s:
                 raise ValueError(f"{k} has shape {tuple(fields[k].shape)}, expected {s}")
+            if fields[k].device != self.device:
+                raise ValueError(f"{k} is on {fields[k].device}, the others on {self.device}")
         F = NSFields(*[_dev_f64(fields[k], k) for k in ("sigma", "u", "v", "w", "p")])
         nbytes = L.ns_workspace_bytes(C.byref(P))
         if nbytes == 0:
