@@ -258,8 +258,9 @@ ns_status ns_diagnostics(ns_ctx* ctx, double out[4]);
  * one, so results are bitwise the same in both modes.  A graph launch saves
  * the host some thirty kernel launches for a fixed device-side cost of a few
  * microseconds, which keeps the device fed on slow hosts.  While kernel
- * timing is enabled the loop launches kernel by kernel.  NS_EINVAL for
- * another value. */
+ * timing is enabled the loop launches kernel by kernel.  If recording a
+ * graph fails, the context falls back to NS_LAUNCH_STREAM for the rest of
+ * its life and the solve continues.  NS_EINVAL for another value. */
 typedef enum {
   NS_LAUNCH_STREAM = 0,
   NS_LAUNCH_GRAPH = 1

@@ -638,10 +638,15 @@ ns_status issue(ns_ctx* X, int kind, const void* a, const void* b, const void* c
         }
       }
       X->st = run;
-      if (e != hipSuccess) return fail(X, NS_EHIP, "CG segment graph capture: %s", hipGetErrorString(e));
-      X->gs[X->ngs++] = {kind, a, b, c, flag, exec};
-      HIPCHK(X, hipGraphLaunch(exec, X->st));
-      return NS_OK;
+      if (e == hipSuccess) {
+        X->gs[X->ngs++] = {kind, a, b, c, flag, exec};
+        HIPCHK(X, hipGraphLaunch(exec, X->st));
+        return NS_OK;
+      }
+      // Recording failed (nothing recorded ran): this context launches one
+      // by one from now on, with bitwise the same results.
+      (void)hipGetLastError();
+      X->launch_mode = NS_LAUNCH_STREAM;
     }
   }
   launch();
