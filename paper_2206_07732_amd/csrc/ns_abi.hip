@@ -432,18 +432,16 @@ size_t tail_bytes(const ns_ctx* X) {
 }
 
 // coarse coefficients of every level from level 0, and 1/D of every level
-// (the tail stages it), in precision T
+// (the tail stages it), in precision T: one launch per level
 template <typename T>
 void build_hierarchy(ns_ctx* X) {
+  const Level& V0 = X->lev[0];
+  launch_invdiag<T>(V0, LV<T>::bx(V0), LV<T>::by(V0), LV<T>::bz(V0), LV<T>::invd(V0), 0 < tail_start<T>(X), X->st);
   for (int l = 1; l < X->L; ++l) {
     const Level& F = X->lev[l - 1];
     const Level& C = X->lev[l];
-    launch_coarsen_beta<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
-                           LV<T>::bz(C), X->st);
-  }
-  for (int l = 0; l < X->L; ++l) {
-    const Level& V = X->lev[l];
-    launch_invdiag<T>(V, LV<T>::bx(V), LV<T>::by(V), LV<T>::bz(V), LV<T>::invd(V), l < tail_start<T>(X), X->st);
+    launch_coarsen_level<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
+                            LV<T>::bz(C), LV<T>::invd(C), l < tail_start<T>(X), X->st);
   }
 }
 

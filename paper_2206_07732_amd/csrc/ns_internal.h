@@ -202,8 +202,8 @@ void launch_split_copy(const Level& L, const T* src, T* dst, bool to_split, hipS
 template <typename T>
 void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* invd, bool split, hipStream_t st);
 template <typename T>
-void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C,
-                         T* cbx, T* cby, T* cbz, hipStream_t st);
+void launch_coarsen_level(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C, T* cbx,
+                          T* cby, T* cbz, T* invd, bool split, hipStream_t st);
 template <typename T>
 void launch_fill(T* a, size_t n, hipStream_t st);
 template <typename T>

@@ -449,17 +449,11 @@ __global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ b
   invd[lidx(n, split_geo(n), split != 0, i, j, k)] = (T)1 / diag;
 }
 
-// coarse face coefficient = mean of the fine faces covering it
+// Coarse face coefficient of component C at coarse face (I, J, K): the mean
+// of the fine faces covering it, summed in the order (dk, dj, di).
 template <typename T, int C>
-__global__ void __launch_bounds__(256) k_coarsen_beta(Dims nf, int fx, int fy, int fz,
-                                                      const T* __restrict__ fb, Dims nc,
-                                                      T* __restrict__ cb) {
-  const int mx = nc.nx + (C == 0), my = nc.ny + (C == 1), mz = nc.nz + (C == 2);
-  const Tile tl = xcd_tile();
-  const int I = tl.x * blockDim.x + threadIdx.x;
-  const int J = tl.y * blockDim.y + threadIdx.y;
-  const int K = tl.z * blockDim.z + threadIdx.z;
-  if (I >= mx || J >= my || K >= mz) return;
+__device__ __forceinline__ T coarse_face(const Dims& nf, int fx, int fy, int fz, const T* __restrict__ fb, int I,
+                                         int J, int K) {
   const int fmx = nf.nx + (C == 0), fmy = nf.ny + (C == 1);
   const int ni = (C == 0) ? 1 : fx, nj = (C == 1) ? 1 : fy, nk = (C == 2) ? 1 : fz;
   T sum = 0;
@@ -469,7 +463,43 @@ __global__ void __launch_bounds__(256) k_coarsen_beta(Dims nf, int fx, int fy, i
         const int i = I * fx + di, j = J * fy + dj, k = K * fz + dk;
         sum += fb[i + (size_t)fmx * (j + (size_t)fmy * k)];
       }
-  cb[I + (size_t)mx * (J + (size_t)my * K)] = sum / (T)(ni * nj * nk);
+  return sum / (T)(ni * nj * nk);
+}
+
+// One coarse level of the hierarchy in one launch: each coarse cell forms its
+// six face coefficients from the fine level, writes the faces it owns (its
+// lower faces, and its upper ones on the grid's upper edges) and its 1/D
+// (the sum of its faces, the top face twice, as in k_invdiag), colour-split
+// (split) or natural.  A face shared by two cells is formed by both with the
+// same arithmetic, and written once.
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarsen_level(Dims nf, int fx, int fy, int fz, const T* __restrict__ fbx,
+                                                       const T* __restrict__ fby, const T* __restrict__ fbz,
+                                                       Dims nc, T* __restrict__ cbx, T* __restrict__ cby,
+                                                       T* __restrict__ cbz, int split, T* __restrict__ invd) {
+  const Tile tl = xcd_tile();
+  const int I = tl.x * blockDim.x + threadIdx.x;
+  const int J = tl.y * blockDim.y + threadIdx.y;
+  const int K = tl.z * blockDim.z + threadIdx.z;
+  if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
+  const T bw = coarse_face<T, 0>(nf, fx, fy, fz, fbx, I, J, K);
+  const T be = coarse_face<T, 0>(nf, fx, fy, fz, fbx, I + 1, J, K);
+  const T bs = coarse_face<T, 1>(nf, fx, fy, fz, fby, I, J, K);
+  const T bn = coarse_face<T, 1>(nf, fx, fy, fz, fby, I, J + 1, K);
+  const T bd = coarse_face<T, 2>(nf, fx, fy, fz, fbz, I, J, K);
+  const T bu = coarse_face<T, 2>(nf, fx, fy, fz, fbz, I, J, K + 1);
+  const size_t fxi = I + (size_t)(nc.nx + 1) * (J + (size_t)nc.ny * K);
+  const size_t fyi = I + (size_t)nc.nx * (J + (size_t)(nc.ny + 1) * K);
+  const size_t c = I + (size_t)nc.nx * (J + (size_t)nc.ny * K);
+  const size_t sxy = (size_t)nc.nx * nc.ny;
+  cbx[fxi] = bw;
+  if (I == nc.nx - 1) cbx[fxi + 1] = be;
+  cby[fyi] = bs;
+  if (J == nc.ny - 1) cby[fyi + nc.nx] = bn;
+  cbz[c] = bd;
+  if (K == nc.nz - 1) cbz[c + sxy] = bu;
+  const T diag = bw + be + bs + bn + bd + (K == nc.nz - 1 ? (T)2 * bu : bu);
+  invd[lidx(nc, split_geo(nc), split != 0, I, J, K)] = (T)1 / diag;
 }
 
 // ------------------------------------------------------- coarse-level tail
@@ -1058,17 +1088,11 @@ void launch_invdiag(const Level& L, const T* bx, const T* by, const T* bz, T* in
 }
 
 template <typename T>
-void launch_coarsen_beta(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C,
-                         T* cbx, T* cby, T* cbz, hipStream_t st) {
-  Geo gx = geo3(C.n.nx + 1, C.n.ny, C.n.nz);
-  hipLaunchKernelGGL((k_coarsen_beta<T, 0>), gx.grid, gx.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], fbx,
-                     C.n, cbx);
-  Geo gy = geo3(C.n.nx, C.n.ny + 1, C.n.nz);
-  hipLaunchKernelGGL((k_coarsen_beta<T, 1>), gy.grid, gy.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], fby,
-                     C.n, cby);
-  Geo gz = geo3(C.n.nx, C.n.ny, C.n.nz + 1);
-  hipLaunchKernelGGL((k_coarsen_beta<T, 2>), gz.grid, gz.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], fbz,
-                     C.n, cbz);
+void launch_coarsen_level(const Level& F, const T* fbx, const T* fby, const T* fbz, const Level& C, T* cbx,
+                          T* cby, T* cbz, T* invd, bool split, hipStream_t st) {
+  Geo g = geo3(C.n.nx, C.n.ny, C.n.nz);
+  hipLaunchKernelGGL(k_coarsen_level<T>, g.grid, g.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], fbx, fby, fbz, C.n,
+                     cbx, cby, cbz, split ? 1 : 0, invd);
 }
 
 template <typename T>
@@ -1201,8 +1225,8 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
   template void launch_prolong<T>(const Level&, T*, const Level&, const T*, bool, hipStream_t);           \
   template void launch_split_copy<T>(const Level&, const T*, T*, bool, hipStream_t);                     \
   template void launch_invdiag<T>(const Level&, const T*, const T*, const T*, T*, bool, hipStream_t);    \
-  template void launch_coarsen_beta<T>(const Level&, const T*, const T*, const T*, const Level&, T*,  \
-                                       T*, T*, hipStream_t);                                          \
+  template void launch_coarsen_level<T>(const Level&, const T*, const T*, const T*, const Level&, T*, \
+                                        T*, T*, T*, bool, hipStream_t);                               \
   template void launch_fill<T>(T*, size_t, hipStream_t);                                              \
   template void launch_vcycle_tail<T>(const TailDesc<T>&, size_t, hipStream_t);
 NSK_INST(double)
