@@ -89,7 +89,9 @@ typedef struct {
 } ns_body;
 
 typedef struct {
-  int nx, ny, nz;              /* cells; ny == 1 for a 2-D (x,z) tank; each >= 1      */
+  int nx, ny, nz;              /* cells; ny == 1 for a 2-D (x,z) tank; nx >= 2,      */
+                               /* ny >= 1, nz >= 2, and no face array (nx+1) ny nz,  */
+                               /* nx (ny+1) nz, nx ny (nz+1) above 2e9 entries       */
   double h;                    /* uniform spacing (m), > 0                           */
   double rho_w, mu_w;          /* water (liquid) density and viscosity              */
   double rho_a, mu_a;          /* air (gas)                                         */

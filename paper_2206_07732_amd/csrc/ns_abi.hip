@@ -126,7 +126,13 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
   if (!P) return snprintf(why, nwhy, "params is NULL"), false;
   if (P->nx < 2 || P->ny < 1 || P->nz < 2)
     return snprintf(why, nwhy, "grid %dx%dx%d: need nx >= 2, ny >= 1, nz >= 2", P->nx, P->ny, P->nz), false;
-  if ((double)P->nx * P->ny * P->nz > 2.0e9) return snprintf(why, nwhy, "grid too large"), false;
+  {
+    // cells and faces are indexed in 32-bit arithmetic: the largest face
+    // array, (nx+1) ny nz or one of its two siblings, must stay below 2^31
+    const double x = P->nx, y = P->ny, z = P->nz;
+    const double faces = std::max(std::max((x + 1) * y * z, x * (y + 1) * z), x * y * (z + 1));
+    if (faces > 2.0e9) return snprintf(why, nwhy, "grid %dx%dx%d too large: more than 2e9 faces", P->nx, P->ny, P->nz), false;
+  }
   if (!(P->h > 0.0)) return snprintf(why, nwhy, "h must be > 0"), false;
   if (P->n_bodies < 0 || P->n_bodies > 4) return snprintf(why, nwhy, "n_bodies must be 0..4"), false;
   if (!(P->rho_w > 0 && P->rho_a > 0 && P->rho_s > 0))

@@ -61,6 +61,11 @@ def test_workspace_size_and_validation(nslib):
     assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
     bad = nslib.params(wl, prec=7)
     assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+    # indices are 32-bit: the largest face array must stay under 2e9 entries
+    # (here nx (ny+1) nz = 2.002e9 while the cell count is 1.992e9)
+    bad = nslib.params(wl)
+    bad.nx, bad.ny, bad.nz = 1000, 199, 10010
+    assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
     # a free-heave body needs a positive mass and a non-negative PTO damping
     fsi = I.workload("fsi3d")
     assert L.ns_workspace_bytes(ctypes.byref(nslib.params(fsi))) > 0
