@@ -508,16 +508,30 @@ __global__ void __launch_bounds__(256) k_coarsen_level(Dims nf, int fx, int fy, 
 // LDS, so a smoothing pass costs a barrier instead of a launch.  Levels whose
 // cell pairs fit one wavefront run in wavefront 0 alone, ordered by
 // wavefront-level fences instead of workgroup barriers.  Each thread decodes
-// its cell pairs once per level visit.
+// its cell pairs once per level visit, with every LDS index a pass of either
+// colour needs, so that a pass is its loads and its arithmetic.
+//
+// Walls carry beta = 0 and every correction in LDS is finite (the tail zeroes
+// them all before its first level), so a wall term beta_f e_nb is an exact
+// zero and the passes add it unconditionally; only the open top face, whose
+// coefficient is not zero, is dropped by a select.
+struct TailCell {
+  int c;          // cell index (b, e, 1/D, bz of the lower face)
+  int fx, fy;     // west x-face and south y-face
+  int w, e, s, n, d, u;   // neighbour cells; the cell itself through a wall or the top
+  bool ok, top;   // the cell exists (i < nx); it lies in the top row
+};
 struct TailPairs {
   int ti[2], j[2], k[2];
   int np;
+  TailCell cell[2][2];   // [pair][colour]: the pair's red cell, then its black one
 };
 
 // lanes 0..nthr-1 take pairs t and t + nthr
 __device__ __forceinline__ void tail_decode(const Dims& n, int tid, int nthr, TailPairs& tp) {
   const int hx = (n.nx + 1) >> 1;
   const int NP = hx * n.ny * n.nz;
+  const int sxy = n.nx * n.ny;
   tp.np = 0;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -528,6 +542,23 @@ __device__ __forceinline__ void tail_decode(const Dims& n, int tid, int nthr, Ta
       tp.j[q] = r % n.ny;
       tp.k[q] = r / n.ny;
       tp.np = q + 1;
+      const int j = tp.j[q], k = tp.k[q];
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const int i = 2 * tp.ti[q] + ((j + k + col) & 1);
+        TailCell& x = tp.cell[q][col];
+        x.ok = i < n.nx;
+        x.top = k == n.nz - 1;
+        x.c = i + n.nx * j + sxy * k;
+        x.fx = i + (n.nx + 1) * (j + n.ny * k);
+        x.fy = i + n.nx * (j + (n.ny + 1) * k);
+        x.w = i > 0 ? x.c - 1 : x.c;
+        x.e = i < n.nx - 1 ? x.c + 1 : x.c;
+        x.s = j > 0 ? x.c - n.nx : x.c;
+        x.n = j < n.ny - 1 ? x.c + n.nx : x.c;
+        x.d = k > 0 ? x.c - sxy : x.c;
+        x.u = x.top ? x.c : x.c + sxy;
+      }
     }
   }
 }
@@ -545,37 +576,37 @@ __device__ __forceinline__ void tail_sync() {
   }
 }
 
-template <typename T, bool WAVE>
+template <typename T, bool WAVE, int COLOUR>
 __device__ __forceinline__ void tail_pass(const Dims& n, const TailPairs& tp, T h2, const T* bx, const T* by,
-                                          const T* bz, const T* invd, const T* b, T* e, int colour,
-                                          bool from_zero) {
+                                          const T* bz, const T* invd, const T* b, T* e, bool from_zero) {
   const int sxy = n.nx * n.ny;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {   // compile-time index: the pairs stay in registers
+  for (int q = 0; q < 2; ++q) {   // compile-time indices: the cells stay in registers
     if (q >= tp.np) break;
-    const int j = tp.j[q], k = tp.k[q];
-    const int i = 2 * tp.ti[q] + ((j + k + colour) & 1);
-    if (i < n.nx) {
-      const int c = i + n.nx * j + sxy * k;
-      T num = h2 * b[c];
-      if (!from_zero) {
-        // all loads unconditional (walls through the cell's own index), wall
-        // terms dropped by a select: a cell's own entry may still be unset
-        // after a red pass from zero, and 0 * garbage need not be 0
-        const int fx = i + (n.nx + 1) * (j + n.ny * k);
-        const int fy = i + n.nx * (j + (n.ny + 1) * k);
-        const bool w = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, d = k > 0, u = k < n.nz - 1;
-        const T tw = bx[fx] * e[w ? c - 1 : c], te = bx[fx + 1] * e[E ? c + 1 : c];
-        const T ts = by[fy] * e[S ? c - n.nx : c], tn = by[fy + n.nx] * e[N ? c + n.nx : c];
-        const T td = bz[c] * e[d ? c - sxy : c], tu = bz[c + sxy] * e[u ? c + sxy : c];
-        if (w) num += tw;
-        if (E) num += te;
-        if (S) num += ts;
-        if (N) num += tn;
-        if (d) num += td;
-        if (u) num += tu;
+    const TailCell& x = tp.cell[q][COLOUR];
+    if (x.ok) {
+      const T id = invd[x.c], bc = b[x.c];
+      if (from_zero) {
+        e[x.c] = (h2 * bc) * id;
+      } else {
+        // every load is issued before the arithmetic starts (the scheduling
+        // barrier keeps the compiler from interleaving them with the sums,
+        // which would wait on each pair in turn); the up term is formed and
+        // then selected, so that its loads do not sit behind a branch
+        const T cw = bx[x.fx], ce = bx[x.fx + 1], cs = by[x.fy], cn = by[x.fy + n.nx];
+        const T cd = bz[x.c], cu = bz[x.c + sxy];
+        const T ew = e[x.w], ee = e[x.e], es = e[x.s], en = e[x.n], ed = e[x.d], eu = e[x.u];
+        __builtin_amdgcn_sched_barrier(0);
+        T num = h2 * bc;
+        num += cw * ew;   // west, east, south, north, down, up
+        num += ce * ee;
+        num += cs * es;
+        num += cn * en;
+        num += cd * ed;
+        const T with_up = num + cu * eu;
+        num = x.top ? num : with_up;
+        e[x.c] = num * id;
       }
-      e[c] = num * invd[c];
     }
   }
   tail_sync<WAVE>();
@@ -589,16 +620,25 @@ struct TailLevel {
   T* sm;
   int tid, nthr;
 
-  __device__ void smooth(int l, const TailPairs& tp, int first_colour, int pairs, bool from_zero) const {
+  template <int C0>
+  __device__ void smooth_from(int l, const TailPairs& tp, int pairs, bool from_zero) const {
     const Dims n = D.n[l];
     const T *bx = sm + D.obx[l], *by = sm + D.oby[l], *bz = sm + D.obz[l], *b = sm + D.ob[l];
     const T* invd = sm + D.oid[l];
     T* e = sm + D.oe[l];
     const T h2 = D.h2[l];
     for (int s = 0; s < pairs; ++s) {
-      tail_pass<T, WAVE>(n, tp, h2, bx, by, bz, invd, b, e, first_colour, from_zero && s == 0);
-      tail_pass<T, WAVE>(n, tp, h2, bx, by, bz, invd, b, e, 1 - first_colour, false);
+      tail_pass<T, WAVE, C0>(n, tp, h2, bx, by, bz, invd, b, e, from_zero && s == 0);
+      tail_pass<T, WAVE, 1 - C0>(n, tp, h2, bx, by, bz, invd, b, e, false);
     }
+  }
+
+  // `pairs` (red, black) or (black, red) sweeps
+  __device__ void smooth(int l, const TailPairs& tp, int first_colour, int pairs, bool from_zero) const {
+    if (first_colour == 0)
+      smooth_from<0>(l, tp, pairs, from_zero);
+    else
+      smooth_from<1>(l, tp, pairs, from_zero);
   }
 
   __device__ void zero(int l) const {
@@ -613,8 +653,8 @@ struct TailLevel {
     TailPairs tp;
     tail_decode(D.n[l], tid, nthr, tp);
     if (D.nu_pre > 0) {
-      // the red pass from zero leaves the black cells unset; the black pass
-      // that follows writes every one of them before anything reads them
+      // the red pass from zero writes the red cells without reading e; the
+      // black pass after it reads them (and its own zeroed entries at walls)
       smooth(l, tp, 0, D.nu_pre, true);
     } else {
       zero(l);
@@ -629,33 +669,49 @@ struct TailLevel {
     const T inv = (T)1 / (T)(fx * fy * fz);
     const int sxy = nf.nx * nf.ny;
     // every fine cell's residual b - A e, each thread for both cells of its
-    // pairs ...
+    // pairs (a wall term is an exact zero) ...
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (q >= tp.np) break;
-      const int j = tp.j[q], k = tp.k[q];
+      // both cells' loads first (a cell past the row's end reads the
+      // pair's other cell, and is not stored), then their sums
+      T v[2][14];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = 2 * tp.ti[q] + h;
-        if (i < nf.nx) {
-          const int c = i + nf.nx * j + sxy * k;
-          const int ix = i + (nf.nx + 1) * (j + nf.ny * k);
-          const int iy = i + nf.nx * (j + (nf.ny + 1) * k);
-          const T xc = e[c];
-          const bool w = i > 0, E = i < nf.nx - 1, S = j > 0, N2 = j < nf.ny - 1, d = k > 0, u = k < nf.nz - 1;
-          const T tw = bx[ix] * (xc - e[w ? c - 1 : c]), te = bx[ix + 1] * (xc - e[E ? c + 1 : c]);
-          const T ts = by[iy] * (xc - e[S ? c - nf.nx : c]), tn = by[iy + nf.nx] * (xc - e[N2 ? c + nf.nx : c]);
-          const T td = bz[c] * (xc - e[d ? c - sxy : c]);
-          const T tu = u ? bz[c + sxy] * (xc - e[u ? c + sxy : c]) : (T)2 * bz[c + sxy] * xc;
-          T acc = 0;
-          if (w) acc += tw;
-          if (E) acc += te;
-          if (S) acc += ts;
-          if (N2) acc += tn;
-          if (d) acc += td;
-          acc += tu;
-          rs[c] = b[c] - ih2 * acc;
-        }
+      for (int col = 0; col < 2; ++col) {
+        const TailCell& x = tp.cell[q][col];
+        const int c = x.ok ? x.c : tp.cell[q][1 - col].c;
+        const int w = x.ok ? x.w : c, ea = x.ok ? x.e : c, so = x.ok ? x.s : c, no = x.ok ? x.n : c;
+        const int d = x.ok ? x.d : c, u = x.ok ? x.u : c;
+        const int ix = x.ok ? x.fx : tp.cell[q][1 - col].fx, iy = x.ok ? x.fy : tp.cell[q][1 - col].fy;
+        v[col][0] = e[c];
+        v[col][1] = bx[ix];
+        v[col][2] = bx[ix + 1];
+        v[col][3] = by[iy];
+        v[col][4] = by[iy + nf.nx];
+        v[col][5] = bz[c];
+        v[col][6] = bz[c + sxy];
+        v[col][7] = e[w];
+        v[col][8] = e[ea];
+        v[col][9] = e[so];
+        v[col][10] = e[no];
+        v[col][11] = e[d];
+        v[col][12] = e[u];
+        v[col][13] = b[c];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const TailCell& x = tp.cell[q][col];
+        const T* a = v[col];
+        const T xc = a[0];
+        T acc = 0;
+        acc += a[1] * (xc - a[7]);    // west, east, south, north, down, up
+        acc += a[2] * (xc - a[8]);
+        acc += a[3] * (xc - a[9]);
+        acc += a[4] * (xc - a[10]);
+        acc += a[5] * (xc - a[11]);
+        acc += x.top ? (T)2 * a[6] * xc : a[6] * (xc - a[12]);
+        if (x.ok) rs[x.c] = a[13] - ih2 * acc;
       }
     }
     tail_sync<WAVE>();
@@ -768,19 +824,28 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailDesc<T> D) {
   // right-hand side: one flat loop, sixteen independent loads in flight per
   // thread
   {
+    // each load from one address chosen by a select (past the end: the last
+    // entry of b0, not stored), so no load waits behind a branch
     const int np = D.npack, n0 = D.n[0].nx * D.n[0].ny * D.n[0].nz, total = np + n0;
     for (int base = tid; base < total; base += 16 * kTailThreads) {
       T v[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int q = base + u * kTailThreads;
-        v[u] = q < np ? D.pack[q] : (q < total ? D.b0[q - np] : (T)0);
+        const T* src = q < np ? D.pack + q : D.b0 + min(max(q - np, 0), n0 - 1);
+        v[u] = *src;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int q = base + u * kTailThreads;
         if (q < total) sm[q < np ? q : D.ob[0] + (q - np)] = v[u];
       }
+    }
+    // every level's correction starts at zero: the passes read a cell's own
+    // entry through a wall before it is first written
+    for (int l = 0; l < nl; ++l) {
+      const int N = D.n[l].nx * D.n[l].ny * D.n[l].nz;
+      for (int c = tid; c < N; c += kTailThreads) sm[D.oe[l] + c] = (T)0;
     }
   }
   __syncthreads();
