@@ -145,25 +145,44 @@ __device__ __forceinline__ size_t lidx(const Dims& n, const SplitGeo& g, bool sp
 // selects and every load goes through an in-range index (a wall neighbour
 // through the cell's own pair index), so all of a thread's loads are in
 // flight together and a 0 * garbage product never enters a sum.
+// The loads of that value (faces; y and z neighbours), gathered apart from
+// its arithmetic so that a kernel can issue them with its other loads,
+// before anything waits on one.
+template <typename T>
+struct GsIn {
+  T bw, be, bs, bn, bd, bu;   // faces: west, east, south, north, down, up
+  T vs, vn, vd, vu;           // neighbour values: south, north, down, up
+};
 template <typename T, typename O>
-__device__ __forceinline__ T gs_split_value_x(const Dims& n, const SplitGeo& sg, T h2, const T* __restrict__ bx,
-                                             const T* __restrict__ by, const T* __restrict__ bz, T bc, int i,
-                                             int j, int k, size_t pos, T vw, T ve, O o) {
+__device__ __forceinline__ GsIn<T> gs_gather(const Dims& n, const SplitGeo& sg, const T* __restrict__ bx,
+                                             const T* __restrict__ by, const T* __restrict__ bz, int i, int j,
+                                             int k, size_t pos, O o) {
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t c = i + (size_t)n.nx * j + sxy * k;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
   const bool top = (k == n.nz - 1);
-  const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0;
-  const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
+  const bool S = j > 0, N = j < n.ny - 1, D = k > 0;
   const size_t sz = (size_t)sg.hx * n.ny;
   const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos;
   const size_t pd = D ? pos - sz : pos, pu = top ? pos : pos + sz;
-  const T vs = o(ps), vn = o(pn), vd = o(pd), vu = o(pu);
-  const T num = h2 * bc + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
-                (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
+  return GsIn<T>{bx[fx], bx[fx + 1], by[fy], by[fy + n.nx], bz[c], bz[c + sxy], o(ps), o(pn), o(pd), o(pu)};
+}
+template <typename T>
+__device__ __forceinline__ T gs_combine(const Dims& n, const GsIn<T>& g, T h2, T bc, int i, int j, int k, T vw,
+                                        T ve) {
+  const bool top = (k == n.nz - 1);
+  const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0;
+  const T diag = g.bw + g.be + g.bs + g.bn + g.bd + (top ? (T)2 * g.bu : g.bu);
+  const T num = h2 * bc + (W ? g.bw * vw : (T)0) + (E ? g.be * ve : (T)0) + (S ? g.bs * g.vs : (T)0) +
+                (N ? g.bn * g.vn : (T)0) + (D ? g.bd * g.vd : (T)0) + (top ? (T)0 : g.bu * g.vu);
   return num / diag;
+}
+template <typename T, typename O>
+__device__ __forceinline__ T gs_split_value_x(const Dims& n, const SplitGeo& sg, T h2, const T* __restrict__ bx,
+                                             const T* __restrict__ by, const T* __restrict__ bz, T bc, int i,
+                                             int j, int k, size_t pos, T vw, T ve, O o) {
+  return gs_combine<T>(n, gs_gather<T>(n, sg, bx, by, bz, i, j, k, pos, o), h2, bc, i, j, k, vw, ve);
 }
 
 // the same with the x neighbours loaded: cell i - 1 is in pair (i - 1) >> 1,
@@ -226,33 +245,38 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const d
   // This pair's black value.  The red cell's x neighbours are this pair's
   // black cell and the adjacent pair's, which the adjacent lane holds (a
   // wavefront is 64 consecutive pairs of one row); every lane takes part in
-  // the shuffles, and only a row's end lanes load their neighbour.
+  // the shuffles, and only a row's end lanes load their neighbour.  Every
+  // load is issued before the shuffles wait for eb, through in-range indices
+  // (a lane outside the grid, or a red cell past the row's end, reads cells
+  // of the grid and stores nothing).
+  const int par = (j + k) & 1;
+  const int i = 2 * ti + par, io = 2 * ti + 1 - par;
+  const int jj = live ? j : 0, kk = live ? k : 0;
+  const int ir = live ? min(i, n.nx - 1) : 0, iq = live ? min(io, n.nx - 1) : 0;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const size_t row = (size_t)n.nx * jj + sxy * kk;
+  const int lane = threadIdx.x;
   const double eb = eo[pos];
+  const GsIn<double> g = gs_gather<double>(n, sg, bx, by, bz, ir, jj, kk, pos, [&](size_t q) { return eo[q]; });
+  const double bc = b[pos];
+  double ex = 0.0;   // the row-end lanes' x neighbour from outside the wavefront
+  if (live && lane == 0 && par == 0 && ir > 0) ex = eo[pos - 1];
+  if (live && lane == 63 && par == 1 && ir < n.nx - 1) ex = eo[pos + 1];
+  const double rr = r[row + ir], zr = zold[row + ir], rq = r[row + iq], zq = zold[row + iq];
+  __builtin_amdgcn_sched_barrier(0);
   const double ebl = __shfl_up(eb, 1, 64), ebr = __shfl_down(eb, 1, 64);
-  if (live) {
-    const size_t sxy = (size_t)n.nx * n.ny;
-    const size_t row = (size_t)n.nx * j + sxy * k;
-    const int par = (j + k) & 1;
-    const int i = 2 * ti + par, io = 2 * ti + 1 - par;
-    const int lane = threadIdx.x;
-    if (i < n.nx) {
-      double vw = eb, ve = eb;   // par 1: west is this pair's black; par 0: east is
-      if (par == 0 && i > 0) vw = lane > 0 ? ebl : eo[pos - 1];
-      if (par == 1 && i < n.nx - 1) ve = lane < 63 ? ebr : eo[pos + 1];
-      const double z = gs_split_value_x<double>(n, sg, h2, bx, by, bz, b[pos], i, j, k, pos, vw, ve,
-                                                [&](size_t q) { return eo[q]; });
-      nat[row + i] = z;
-      const double rv = r[row + i];
-      v[0] += rv * z;
-      v[1] += rv * zold[row + i];
-    }
-    if (io < n.nx) {
-      nat[row + io] = eb;
-      const double rv = r[row + io];
-      v[0] += rv * eb;
-      v[1] += rv * zold[row + io];
-    }
-  }
+  // formed on every lane from in-grid values, then kept by selects: a use
+  // under a branch would let the compiler sink r's and z_old's loads past
+  // the shuffles
+  double vw = eb, ve = eb;   // par 1: west is this pair's black; par 0: east is
+  if (par == 0 && ir > 0) vw = lane > 0 ? ebl : ex;
+  if (par == 1 && ir < n.nx - 1) ve = lane < 63 ? ebr : ex;
+  const double z = gs_combine<double>(n, g, h2, bc, ir, jj, kk, vw, ve);
+  const bool red_ok = live && i < n.nx, black_ok = live && io < n.nx;
+  if (red_ok) nat[row + i] = z;
+  if (black_ok) nat[row + io] = eb;
+  v[0] = (red_ok ? rr * z : 0.0) + (black_ok ? rq * eb : 0.0);
+  v[1] = (red_ok ? rr * zr : 0.0) + (black_ok ? rq * zq : 0.0);
   block_partials<2>(v, partials, tl.lin);
 }
 
@@ -279,32 +303,46 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   // the row's end (b clamped into the row, an unused 1/D entry), since the
   // adjacent lane reads it: the black cell's x neighbours are this pair's red
   // cell and the adjacent pair's (a wavefront is 64 consecutive pairs of one
-  // row), and only a row's end lanes load theirs.
-  const T br = bval(0, pos, ir < n.nx ? ir : n.nx - 1, j, k);
-  const T rv = h2 * br * invd[pos];
+  // row), and only a row's end lanes load theirs.  Every load is issued
+  // before the shuffles wait for that value; a black cell past the row's end
+  // gathers through the row's last cell and stores nothing.
+  const int lane = threadIdx.x;
+  const int irc = ir < n.nx ? ir : n.nx - 1, ibc = ib < n.nx ? ib : n.nx - 1;
+  const T br = bval(0, pos, irc, j, k), idr = invd[pos];
+  const T bb = bval(1, pos, ibc, j, k);
+  // the red neighbours' b and 1/D through in-range indices (walls: own pair)
+  const bool W = ibc > 0, E = ibc < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
+  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
+  const int js = S ? j - 1 : j, jn = N ? j + 1 : j;
+  const int kd = D ? k - 1 : k, ku = U ? k + 1 : k;
+  const T bS = bval(0, ps, ibc, js, k), iS = invd[ps], bN = bval(0, pn, ibc, jn, k), iN = invd[pn];
+  const T bD = bval(0, pd, ibc, j, kd), iD = invd[pd], bU = bval(0, pu, ibc, j, ku), iU = invd[pu];
+  T bX = 0, iX = 0;   // lane 63's east or lane 0's west red neighbour, outside the wavefront
+  if (lane == 63 && par == 0 && E) {
+    bX = bval(0, pos + 1, ibc + 1, j, k);
+    iX = invd[pos + 1];
+  }
+  if (lane == 0 && par == 1 && W) {
+    bX = bval(0, pos - 1, ibc - 1, j, k);
+    iX = invd[pos - 1];
+  }
+  const size_t c = row + ibc;
+  const size_t fx = ibc + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+  const size_t fy = ibc + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+  const T bw = bx[fx], be = bx[fx + 1], bsy = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  __builtin_amdgcn_sched_barrier(0);
+  const T rv = h2 * br * idr;
   if (ir < n.nx) {
     e[pos] = rv;
     if constexpr (NAT) bs[pos] = br;
   }
   const T rl = __shfl_up(rv, 1, 64), rr = __shfl_down(rv, 1, 64);
   if (ib >= n.nx) return;
-  const T bb = bval(1, pos, ib, j, k);
   if constexpr (NAT) bs[sg.P + pos] = bb;
-  // red neighbour values h2 b / D through in-range indices (walls: own pair)
-  const bool W = ib > 0, E = ib < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
-  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
-  const int js = S ? j - 1 : j, jn = N ? j + 1 : j;
-  const int kd = D ? k - 1 : k, ku = U ? k + 1 : k;
-  auto red = [&](size_t q, int ii, int jj, int kk) { return h2 * bval(0, q, ii, jj, kk) * invd[q]; };
-  const int lane = threadIdx.x;
   T vw = rv, ve = rv;   // par 0: west is this pair's red cell; par 1: east is
-  if (par == 0 && E) ve = lane < 63 ? rr : red(pos + 1, ib + 1, j, k);
-  if (par == 1 && W) vw = lane > 0 ? rl : red(pos - 1, ib - 1, j, k);
-  const T vs = red(ps, ib, js, k), vn = red(pn, ib, jn, k), vd = red(pd, ib, j, kd), vu = red(pu, ib, j, ku);
-  const size_t c = row + ib;
-  const size_t fx = ib + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
-  const size_t fy = ib + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  const T bw = bx[fx], be = bx[fx + 1], bsy = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  if (par == 0 && E) ve = lane < 63 ? rr : h2 * bX * iX;
+  if (par == 1 && W) vw = lane > 0 ? rl : h2 * bX * iX;
+  const T vs = h2 * bS * iS, vn = h2 * bN * iN, vd = h2 * bD * iD, vu = h2 * bU * iU;
   const bool top = !U;
   const T diag = bw + be + bsy + bn + bd + (top ? (T)2 * bu : bu);
   const T num = h2 * bb + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bsy * vs : (T)0) +
@@ -377,11 +415,14 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
     const T xn = e[sidx(nf, sg, i, j < nf.ny - 1 ? j + 1 : j, k)];
     const T xd = e[sidx(nf, sg, i, j, k > 0 ? k - 1 : k)];
     const T xu = e[sidx(nf, sg, i, j, k < nf.nz - 1 ? k + 1 : k)];
-    const T bu = bz[c + sxy];
-    T acc = bx[fxi] * (xc - xw) + bx[fxi + 1] * (xc - xe) + by[fyi] * (xc - xs) + by[fyi + nf.nx] * (xc - xn) +
-            bz[c] * (xc - xd);
+    const T cw = bx[fxi], ce = bx[fxi + 1], cs = by[fyi], cn = by[fyi + nf.nx], cd = bz[c], bu = bz[c + sxy];
+    const T bcell = b[sidx(nf, sg, i, j, k)];
+    // all loads above are in flight together: the compiler may not sink the
+    // up neighbour's load into the branch that uses it
+    __builtin_amdgcn_sched_barrier(0);
+    T acc = cw * (xc - xw) + ce * (xc - xe) + cs * (xc - xs) + cn * (xc - xn) + cd * (xc - xd);
     acc += (k < nf.nz - 1) ? bu * (xc - xu) : (T)2 * bu * xc;
-    r = b[sidx(nf, sg, i, j, k)] - ih2 * acc;
+    r = bcell - ih2 * acc;
   }
   const int t = (tz * TY + ty) * TX + tx;
   sr[t] = r;
@@ -973,27 +1014,37 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
                                                   double* __restrict__ partials) {
   CELL_INDEX;
   double v[1] = {0.0};
+  // Every load is issued before the shuffles wait for zc: the faces and the
+  // y and z neighbours through in-range indices (a lane outside the grid
+  // reads around cell 0), the row-end lanes' x neighbour, and d_old, q_old
+  // (also on a first iteration, which does not use them).
+  const int lane = threadIdx.x;
+  const int ii = inside ? i : 0, jj = inside ? j : 0, kk = inside ? k : 0;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const size_t fx = ii + (size_t)(n.nx + 1) * (jj + (size_t)n.ny * kk);
+  const size_t fy = ii + (size_t)n.nx * (jj + (size_t)(n.ny + 1) * kk);
   const double zc = zn[c];
+  const double cw = bx[fx], ce = bx[fx + 1], cs = by[fy], cn = by[fy + n.nx], cd = bz[c], cu = bz[c + sxy];
+  const double zs = zn[jj > 0 ? c - n.nx : c], zno = zn[jj < n.ny - 1 ? c + n.nx : c];
+  const double zd = zn[kk > 0 ? c - sxy : c], zu = zn[kk < n.nz - 1 ? c + sxy : c];
+  double zx = 0.0;   // lane 0's west and lane 63's east neighbour lie outside the wavefront
+  if (lane == 0 && ii > 0) zx = zn[c - 1];
+  if (lane == 63 && ii < n.nx - 1) zx = zn[c + 1];
+  const double dol = dold[c], qol = q[c];
+  __builtin_amdgcn_sched_barrier(0);
   const double zl = __shfl_up(zc, 1, 64), zr = __shfl_down(zc, 1, 64);
   if (inside) {
-    const int lane = threadIdx.x;
-    const size_t sxy = (size_t)n.nx * n.ny;
-    const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
-    const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
     double zw = zc, ze = zc;
-    if (i > 0) zw = lane > 0 ? zl : zn[c - 1];
-    if (i < n.nx - 1) ze = lane < 63 ? zr : zn[c + 1];
-    const double bu = bz[c + sxy];
-    const double zu = zn[k < n.nz - 1 ? c + sxy : c];   // unconditional: all loads in flight together
-    double acc = bx[fx] * (zc - zw) + bx[fx + 1] * (zc - ze) + by[fy] * (zc - zn[j > 0 ? c - n.nx : c]) +
-                 by[fy + n.nx] * (zc - zn[j < n.ny - 1 ? c + n.nx : c]) + bz[c] * (zc - zn[k > 0 ? c - sxy : c]);
-    acc += (k < n.nz - 1) ? bu * (zc - zu) : 2.0 * bu * zc;
+    if (i > 0) zw = lane > 0 ? zl : zx;
+    if (i < n.nx - 1) ze = lane < 63 ? zr : zx;
+    double acc = cw * (zc - zw) + ce * (zc - ze) + cs * (zc - zs) + cn * (zc - zno) + cd * (zc - zd);
+    acc += (k < n.nz - 1) ? cu * (zc - zu) : 2.0 * cu * zc;
     const double qz = ih2 * acc;
     double dc = zc, qc = qz;
     if (!first) {
       const double beta = scal[S_BETA];
-      dc = zc + beta * dold[c];
-      qc = qz + beta * q[c];
+      dc = zc + beta * dol;
+      qc = qz + beta * qol;
     }
     dnew[c] = dc;
     q[c] = qc;
