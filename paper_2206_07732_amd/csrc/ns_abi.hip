@@ -315,10 +315,13 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     }
     // b and e: colour-split (2 ceil(nx/2) ny nz entries) above the tail,
     // natural on tail levels; level 0 keeps its own split pair (its natural
-    // b and e are the CG vectors, and for FP32 the bfn/efn interface)
+    // b and e are the CG vectors, and for FP32 the bfn/efn interface).  A
+    // coarse split level's e has a third plane, the black plane's copy that
+    // its fused red-black passes read.
     const size_t cs = 2 * (size_t)((V.n.nx + 1) / 2) * V.n.ny * V.n.nz;
+    const size_t ces = l >= 1 ? cs + cs / 2 : cs;
     V.bf = cv.take<float>(l < t32 ? cs : c);
-    V.ef = cv.take<float>(l < t32 ? cs : c);
+    V.ef = cv.take<float>(l < t32 ? ces : c);
     V.bfn = V.efn = nullptr;
     if (l == 0) {
       V.bfn = t32 > 0 ? cv.take<float>(c) : V.bf;
@@ -328,7 +331,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       V.b = V.e = nullptr;   // a tail-only hierarchy works on the CG vectors directly
     } else {
       V.b = cv.take<double>(l < t64 ? cs : c);
-      V.e = cv.take<double>(l < t64 ? cs : c);
+      V.e = cv.take<double>(l < t64 ? ces : c);
     }
   }
   if (X) {
@@ -553,10 +556,21 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
     }
     return;
   }
+  // On a coarse level whose rows fit one tile, the first (red, black) pair
+  // after a kernel that leaves the black plane's copy is one fused launch.
+  const bool rb = l >= 1 && gs_rb_fits(L.n);
+  T* ecopy = rb ? e + nsplit : nullptr;
   // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
-    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st);
-    for (int s = 1; s < P.nu_pre; ++s) {
+    const bool rb_pre = rb && P.nu_pre >= 2;
+    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st,
+                       rb_pre ? ecopy : nullptr);
+    int s = 1;
+    if (rb_pre) {
+      launch_gs_rb<T>(L, bx, by, bz, b, e, ecopy, st);
+      s = 2;
+    }
+    for (; s < P.nu_pre; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
     }
@@ -570,7 +584,16 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
   vcycle<T>(X, l + 1, nullptr, nullptr);
   // post-smoothing: (prolongation + black) fused, then red, then black, red
   // pairs; at level 0 the last red pass writes e0
-  if (P.nu_post > 0) {
+  if (P.nu_post > 0 && rb && P.nu_post >= 2) {
+    // (prolongation + black), then (red, black) fused, red, then black, red
+    launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), csplit, st, ecopy);
+    launch_gs_rb<T>(L, bx, by, bz, b, e, ecopy, st);
+    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+    for (int s = 2; s < P.nu_post; ++s) {
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+    }
+  } else if (P.nu_post > 0) {
     launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), csplit, st);
     if (l == 0 && P.nu_post == 1)
       last_red();

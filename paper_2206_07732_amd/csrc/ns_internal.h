@@ -184,13 +184,20 @@ template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
                hipStream_t st, KTimer* kt = nullptr, T* nat = nullptr);
 // red from zero + black; b natural (b_natural, its split copy written to bs) or split
+// (bcopy, when set: a copy of the black plane, for a fused pass to read)
 template <typename T>
 void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, bool b_natural,
-                     const T* invd, T* e, T* bs, hipStream_t st);
+                     const T* invd, T* e, T* bs, hipStream_t st, T* bcopy = nullptr);
 // prolongation of the next level's correction ec (split or natural) + black
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
-                       const Level& C, const T* ec, bool ec_split, hipStream_t st);
+                       const Level& C, const T* ec, bool ec_split, hipStream_t st, T* bcopy = nullptr);
+// a red then a black pass in one launch, reading the black plane's copy
+// bold; only where gs_rb_fits (rows of at most 32 pairs)
+bool gs_rb_fits(const Dims& n);
+template <typename T>
+void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
+                  hipStream_t st);
 // coarse b = restricted residual (coarse layout split or natural)
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,

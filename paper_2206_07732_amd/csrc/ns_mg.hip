@@ -287,7 +287,8 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const d
 template <typename T, bool FINE, bool NAT>
 __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                                   const T* __restrict__ bz, const T* __restrict__ b,
-                                                  const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs) {
+                                                  const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
+                                                  T* __restrict__ bcopy) {
   PAIR_INDEX;
   const int par = (j + k) & 1;
   const int ir = 2 * ti + par, ib = 2 * ti + 1 - par;
@@ -347,7 +348,9 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   const T diag = bw + be + bsy + bn + bd + (top ? (T)2 * bu : bu);
   const T num = h2 * bb + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bsy * vs : (T)0) +
                 (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
-  e[sg.P + pos] = num / diag;
+  const T vb = num / diag;
+  e[sg.P + pos] = vb;
+  if (bcopy) bcopy[pos] = vb;   // the black plane as a fused red-black pass will read it
 }
 
 // prolongation e += P ec followed by the black pass, in one launch; only the
@@ -358,7 +361,7 @@ template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                                     const T* __restrict__ bz, const T* __restrict__ b,
                                                     T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
-                                                    const T* __restrict__ ec) {
+                                                    const T* __restrict__ ec, T* __restrict__ bcopy) {
   PAIR_INDEX;
   const int i = 2 * ti + 1 - ((j + k) & 1);   // the black cell
   if (i >= n.nx) return;
@@ -380,7 +383,103 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
   const T num = h2 * b[sg.P + pos] + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
                 (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
-  e[sg.P + pos] = num / diag;
+  const T vb = num / diag;
+  e[sg.P + pos] = vb;
+  if (bcopy) bcopy[pos] = vb;   // the black plane as a fused red-black pass will read it
+}
+
+// A red pass then a black pass of Gauss-Seidel in one launch, on a level
+// whose rows are at most 32 pairs (ceil(nx/2) <= 32), where launch latency,
+// not bytes, bounds a pass.  A block takes whole rows: TY rows by TZ planes
+// of pairs (TX >= ceil(nx/2) lanes per row).  It forms the red values of its
+// tile and of a ring one row wide in y and z around it (the red cells its
+// black cells read) from the black plane as it stood before the launch,
+// which the previous kernel copied to bold (this launch overwrites the
+// black plane while other blocks still read it).  It then forms its black
+// values from those red values, held in LDS.  Each value comes from the same
+// arithmetic, on the same inputs, as in the two separate passes, so the
+// results are theirs bit for bit.  Every global load of a thread is issued
+// before it waits on any.
+constexpr int kRbThreads = 256;
+constexpr int kRbMaxIter = 3;   // ring-extended tile entries per thread
+constexpr int kRbMaxExt = kRbThreads * kRbMaxIter;
+
+template <typename T>
+__global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __restrict__ bx,
+                                                      const T* __restrict__ by, const T* __restrict__ bz,
+                                                      const T* __restrict__ b, T* __restrict__ e,
+                                                      const T* __restrict__ bold, int TX, int TY, int TZ) {
+  __shared__ T R[kRbMaxExt];
+  const SplitGeo sg = split_geo(n);
+  const Tile tl = xcd_tile();
+  const int ty0 = tl.y * TY, tz0 = tl.z * TZ;
+  const int ry = n.ny > 1 ? 1 : 0;   // ring width in y (none in a 2-D tank)
+  const int EY = TY + 2 * ry, NE = TX * EY * (TZ + 2);
+  const int t = threadIdx.x;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  auto ob = [&](size_t q) { return bold[q]; };
+  // red entries of the ring-extended tile: entry q is pair q % TX of row
+  // (ty0 + ey - ry, tz0 + ez - 1); an entry outside the grid gathers through
+  // red cell (parity, 0, 0) and is stored as 0
+  GsIn<T> gr[kRbMaxIter];
+  T br[kRbMaxIter], rw[kRbMaxIter], re[kRbMaxIter];
+  int ri[kRbMaxIter], rj[kRbMaxIter], rk[kRbMaxIter];
+  size_t rp[kRbMaxIter];
+  bool rok[kRbMaxIter];
+#pragma unroll
+  for (int u = 0; u < kRbMaxIter; ++u) {
+    const int q = t + u * kRbThreads;
+    const int ex = q % TX, ey = (q / TX) % EY, ez = q / (TX * EY);
+    const int j = ty0 + ey - ry, k = tz0 + ez - 1;
+    const int i = 2 * ex + ((j + k) & 1);
+    rok[u] = q < NE && j >= 0 && j < n.ny && k >= 0 && k < n.nz && i < n.nx;
+    rj[u] = rok[u] ? j : 0;
+    rk[u] = rok[u] ? k : 0;
+    ri[u] = rok[u] ? i : 0;
+    rp[u] = (size_t)(ri[u] >> 1) + (size_t)sg.hx * (rj[u] + (size_t)n.ny * rk[u]);
+    gr[u] = gs_gather<T>(n, sg, bx, by, bz, ri[u], rj[u], rk[u], rp[u], ob);
+    br[u] = b[rp[u]];
+    const bool W = ri[u] > 0, E = ri[u] < n.nx - 1;
+    rw[u] = bold[W ? rp[u] - (size_t)((ri[u] & 1) ? 0 : 1) : rp[u]];
+    re[u] = bold[E ? rp[u] + (size_t)((ri[u] & 1) ? 1 : 0) : rp[u]];
+  }
+  // this thread's black cell: pair px of row (ty0 + py, tz0 + pz)
+  const int px = t % TX, py = (t / TX) % TY, pz = t / (TX * TY);
+  const int jb = ty0 + py, kb = tz0 + pz;
+  const int ib = 2 * px + 1 - ((jb + kb) & 1);
+  const bool bok = jb < n.ny && kb < n.nz && ib < n.nx;
+  const int jc = bok ? jb : 0, kc = bok ? kb : 0, ic = bok ? ib : 1;
+  const size_t pb = (size_t)(ic >> 1) + (size_t)sg.hx * (jc + (size_t)n.ny * kc);
+  const size_t cb = ic + (size_t)n.nx * jc + sxy * kc;
+  const size_t fxb = ic + (size_t)(n.nx + 1) * (jc + (size_t)n.ny * kc);
+  const size_t fyb = ic + (size_t)n.nx * (jc + (size_t)(n.ny + 1) * kc);
+  const T bw = bx[fxb], be = bx[fxb + 1], bs = by[fyb], bn = by[fyb + n.nx], bd = bz[cb], bu = bz[cb + sxy];
+  const T bb = b[sg.P + pb];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kRbMaxIter; ++u) {
+    const int q = t + u * kRbThreads;
+    if (q < NE) {
+      T v = (T)0;
+      if (rok[u]) {
+        v = gs_combine<T>(n, gr[u], h2, br[u], ri[u], rj[u], rk[u], rw[u], re[u]);
+        const int ey = (q / TX) % EY, ez = q / (TX * EY);
+        if (ey >= ry && ey < ry + TY && ez >= 1 && ez <= TZ) e[rp[u]] = v;
+      }
+      R[q] = v;
+    }
+  }
+  __syncthreads();
+  if (bok) {
+    const int ey = py + ry, ez = pz + 1;
+    const int row = TX * (ey + EY * ez);
+    const int L = px + row;
+    const bool W = ib > 0, E = ib < n.nx - 1, S = jb > 0, N = jb < n.ny - 1, D = kb > 0, U = kb < n.nz - 1;
+    const T vw = R[W ? ((ib - 1) >> 1) + row : L], ve = R[E ? ((ib + 1) >> 1) + row : L];
+    const GsIn<T> g{bw, be, bs, bn, bd, bu, R[S ? L - TX : L], R[N ? L + TX : L], R[D ? L - TX * EY : L],
+                    R[U ? L + TX * EY : L]};
+    e[sg.P + pb] = gs_combine<T>(n, g, h2, bb, ib, jb, kb, vw, ve);
+  }
 }
 
 // coarse rhs = mean over the children of the fine residual b - A e (fine b,
@@ -1152,24 +1251,50 @@ void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b
 
 template <typename T>
 void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, bool b_natural,
-                     const T* invd, T* e, T* bs, hipStream_t st) {
+                     const T* invd, T* e, T* bs, hipStream_t st, T* bcopy) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
-  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*);
+  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*, T*);
   if (b_natural)
     kern = fine ? k_gs_first<T, true, true> : k_gs_first<T, false, true>;
   else
     kern = fine ? k_gs_first<T, true, false> : k_gs_first<T, false, false>;
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy);
 }
 
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
-                       const Level& C, const T* ec, bool ec_split, hipStream_t st) {
+                       const Level& C, const T* ec, bool ec_split, hipStream_t st, T* bcopy) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
   hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0] >> 1,
-                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec);
+                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy);
+}
+
+// the fused red-black pass's tile (TX lanes per row, TY rows, TZ planes), or
+// false where a row does not fit one tile
+static bool gs_rb_tile(const Dims& n, int& TX, int& TY, int& TZ) {
+  const int hx = (n.nx + 1) / 2;
+  if (hx > 32) return false;
+  TX = hx > 16 ? 32 : hx > 8 ? 16 : 8;
+  TY = n.ny > 1 ? 4 : 1;
+  TZ = kRbThreads / (TX * TY);
+  return TX * (TY + (n.ny > 1 ? 2 : 0)) * (TZ + 2) <= kRbMaxExt;
+}
+
+bool gs_rb_fits(const Dims& n) {
+  int TX, TY, TZ;
+  return gs_rb_tile(n, TX, TY, TZ);
+}
+
+template <typename T>
+void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
+                  hipStream_t st) {
+  int TX, TY, TZ;
+  if (!gs_rb_tile(L.n, TX, TY, TZ)) return;   // callers check gs_rb_fits first
+  const dim3 grid(1, (L.n.ny + TY - 1) / TY, (L.n.nz + TZ - 1) / TZ);
+  hipLaunchKernelGGL(k_gs_rb<T>, grid, dim3(kRbThreads), 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, bold, TX,
+                     TY, TZ);
 }
 
 template <typename T>
@@ -1333,9 +1458,11 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
   template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int, hipStream_t,   \
                              KTimer*, T*);                                                                \
   template void launch_gs_first<T>(const Level&, const T*, const T*, const T*, const T*, bool, const T*,  \
-                                   T*, T*, hipStream_t);                                                  \
+                                   T*, T*, hipStream_t, T*);                                              \
   template void launch_gs_prolong<T>(const Level&, const T*, const T*, const T*, const T*, T*,           \
-                                     const Level&, const T*, bool, hipStream_t);                          \
+                                     const Level&, const T*, bool, hipStream_t, T*);                      \
+  template void launch_gs_rb<T>(const Level&, const T*, const T*, const T*, const T*, T*, const T*,     \
+                                hipStream_t);                                                             \
   template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*, const T*,  \
                                          const Level&, T*, bool, hipStream_t);                            \
   template void launch_prolong<T>(const Level&, T*, const Level&, const T*, bool, hipStream_t);           \

@@ -55,6 +55,14 @@ def case(name):
         # so the coarsest-level sweeps run with the multi-block kernels
         return I.workload("tiny3d", nx=129, ny=8, nz=8, h=4.0 / 129, seed=22,
                           bodies=[I.Body(1, (2.0, 0.15, 0.0), (0.1, 0.7, 1.5))])
+    if name == "rbragged":
+        # a coarse level (48x20x12) whose rows fit the fused red-black pass,
+        # with ragged row and plane tiles
+        return I.workload("tiny3d", nx=96, ny=40, nz=24, h=4.0 / 96, seed=23,
+                          bodies=[I.Body(1, (2.0, 0.8, 0.0), (0.3, 0.7, 1.5))])
+    if name == "rb2d":
+        # a 2-D tank whose second level (64x1x128) takes the fused pass
+        return I.workload("tiny2d", nx=128, ny=1, nz=256, h=8.0 / 128, seed=24)
     if name == "heave3d":
         return I.workload("tiny3d", nx=32, ny=16, nz=16,
                           bodies=[I.Body(1, (2.0, 1.0, 0.0), (0.25, 0.7, 1.5), heave_amp=0.05,
@@ -184,7 +192,8 @@ def test_c1_ten_steps_free_running(orc):
 
 
 def test_operator_and_vcycle_parity(orc):
-    for name in ("tiny3d", "ragged3d", "odd1level", "c1"):
+    # rbragged, rb2d and c2 have coarse levels on the fused red-black pass
+    for name in ("tiny3d", "ragged3d", "odd1level", "c1", "rbragged", "rb2d", "c2"):
         wl = case(name)
         f = I.make_fields(wl)
         dt = I.cfl_dt(wl, f)
