@@ -60,7 +60,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # HBM bytes per launch of the finest smoother pass from rocprofv3 counters
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors from a 256 MiB device
 # copy measured in the same runs); None until taken for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = 20002269   # profiles/c2_smoother_hbm_counters.md
+TRAFFIC_BYTES_PER_LAUNCH = 19988958   # profiles/c2_smoother_hbm_counters.md
 
 
 def log(*a):
