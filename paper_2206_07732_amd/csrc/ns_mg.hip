@@ -591,18 +591,42 @@ __global__ void __launch_bounds__(256) k_invdiag(Dims n, const T* __restrict__ b
 
 // Coarse face coefficient of component C at coarse face (I, J, K): the mean
 // of the fine faces covering it, summed in the order (dk, dj, di).
+// (the coarsening factors fx, fy, fz are 1 or 2).  The candidate fine faces
+// are loaded through indices clamped into the array (coarse_face_load), and
+// those within the factors summed in the order (dk, dj, di)
+// (coarse_face_sum); a kernel loads all six faces before it sums any, so
+// that every load is in flight before the first wait.
+template <typename T>
+struct FaceIn {
+  T v[2][2][2];   // [dk][dj][di]
+};
 template <typename T, int C>
-__device__ __forceinline__ T coarse_face(const Dims& nf, int fx, int fy, int fz, const T* __restrict__ fb, int I,
-                                         int J, int K) {
-  const int fmx = nf.nx + (C == 0), fmy = nf.ny + (C == 1);
+__device__ __forceinline__ FaceIn<T> coarse_face_load(const Dims& nf, int fx, int fy, int fz,
+                                                      const T* __restrict__ fb, int I, int J, int K) {
+  const int fmx = nf.nx + (C == 0), fmy = nf.ny + (C == 1), fmz = nf.nz + (C == 2);
+  FaceIn<T> f;
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int i = min(I * fx + di, fmx - 1), j = min(J * fy + dj, fmy - 1), k = min(K * fz + dk, fmz - 1);
+        f.v[dk][dj][di] = fb[i + (size_t)fmx * (j + (size_t)fmy * k)];
+      }
+  return f;
+}
+template <typename T, int C>
+__device__ __forceinline__ T coarse_face_sum(int fx, int fy, int fz, const FaceIn<T>& f) {
   const int ni = (C == 0) ? 1 : fx, nj = (C == 1) ? 1 : fy, nk = (C == 2) ? 1 : fz;
   T sum = 0;
-  for (int dk = 0; dk < nk; ++dk)
-    for (int dj = 0; dj < nj; ++dj)
-      for (int di = 0; di < ni; ++di) {
-        const int i = I * fx + di, j = J * fy + dj, k = K * fz + dk;
-        sum += fb[i + (size_t)fmx * (j + (size_t)fmy * k)];
-      }
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di)
+        if (dk < nk && dj < nj && di < ni) sum += f.v[dk][dj][di];
   return sum / (T)(ni * nj * nk);
 }
 
@@ -622,12 +646,18 @@ __global__ void __launch_bounds__(256) k_coarsen_level(Dims nf, int fx, int fy, 
   const int J = tl.y * blockDim.y + threadIdx.y;
   const int K = tl.z * blockDim.z + threadIdx.z;
   if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
-  const T bw = coarse_face<T, 0>(nf, fx, fy, fz, fbx, I, J, K);
-  const T be = coarse_face<T, 0>(nf, fx, fy, fz, fbx, I + 1, J, K);
-  const T bs = coarse_face<T, 1>(nf, fx, fy, fz, fby, I, J, K);
-  const T bn = coarse_face<T, 1>(nf, fx, fy, fz, fby, I, J + 1, K);
-  const T bd = coarse_face<T, 2>(nf, fx, fy, fz, fbz, I, J, K);
-  const T bu = coarse_face<T, 2>(nf, fx, fy, fz, fbz, I, J, K + 1);
+  const FaceIn<T> fw = coarse_face_load<T, 0>(nf, fx, fy, fz, fbx, I, J, K);
+  const FaceIn<T> fe = coarse_face_load<T, 0>(nf, fx, fy, fz, fbx, I + 1, J, K);
+  const FaceIn<T> fs = coarse_face_load<T, 1>(nf, fx, fy, fz, fby, I, J, K);
+  const FaceIn<T> fn = coarse_face_load<T, 1>(nf, fx, fy, fz, fby, I, J + 1, K);
+  const FaceIn<T> fd = coarse_face_load<T, 2>(nf, fx, fy, fz, fbz, I, J, K);
+  const FaceIn<T> fu = coarse_face_load<T, 2>(nf, fx, fy, fz, fbz, I, J, K + 1);
+  // (the barrier keeps the compiler from sinking a load into the branch of
+  // the sum that uses it)
+  __builtin_amdgcn_sched_barrier(0);
+  const T bw = coarse_face_sum<T, 0>(fx, fy, fz, fw), be = coarse_face_sum<T, 0>(fx, fy, fz, fe);
+  const T bs = coarse_face_sum<T, 1>(fx, fy, fz, fs), bn = coarse_face_sum<T, 1>(fx, fy, fz, fn);
+  const T bd = coarse_face_sum<T, 2>(fx, fy, fz, fd), bu = coarse_face_sum<T, 2>(fx, fy, fz, fu);
   const size_t fxi = I + (size_t)(nc.nx + 1) * (J + (size_t)nc.ny * K);
   const size_t fyi = I + (size_t)nc.nx * (J + (size_t)(nc.ny + 1) * K);
   const size_t c = I + (size_t)nc.nx * (J + (size_t)nc.ny * K);
