@@ -215,10 +215,9 @@ __global__ void __launch_bounds__(256) k_reinit(Phys P, const double* __restrict
                         cur[k < n.nz - 1 ? c + sxy : c]};
   const double h = P.h;
   const double sg = a0 / sqrt(a0 * a0 + h * h);
-  if (sg == 0.0) {
-    nxt[c] = sc;
-    return;
-  }
+  // (a cell on the interface, sg = 0, keeps its value: selected at the end
+  // rather than returned early, so the neighbour loads are not sunk behind
+  // the wait for a0)
   const double ih = 1.0 / h;
   double g2 = 0.0;
 #pragma unroll
@@ -235,7 +234,8 @@ __global__ void __launch_bounds__(256) k_reinit(Phys P, const double* __restrict
     }
     g2 += fmax(t1 * t1, t2 * t2);
   }
-  nxt[c] = sc - dtau * sg * (sqrt(g2) - 1.0);
+  const double upd = sc - dtau * sg * (sqrt(g2) - 1.0);
+  nxt[c] = sg == 0.0 ? sc : upd;
 }
 
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t n) {
