@@ -365,23 +365,32 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
   PAIR_INDEX;
   const int i = 2 * ti + 1 - ((j + k) & 1);   // the black cell
   if (i >= n.nx) return;
-  const SplitGeo cg = split_geo(nc);
-  auto up = [&](size_t q, int ii, int jj, int kk) {
-    return e[q] + ec[lidx(nc, cg, csplit != 0, ii >> sxc, jj >> syc, kk >> szc)];
+  // the parent's entry in 32-bit arithmetic (a level's arrays have fewer
+  // than 2^31 entries; six of these per thread dominated its instruction count)
+  const int chx = (nc.nx + 1) >> 1, cP = chx * nc.ny * nc.nz;
+  auto cidx = [&](int ii, int jj, int kk) {
+    const int I = ii >> sxc, J = jj >> syc, K = kk >> szc;
+    return csplit ? ((I + J + K) & 1) * cP + (I >> 1) + chx * (J + nc.ny * K) : I + nc.nx * (J + nc.ny * K);
   };
   const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
   const size_t sz = (size_t)sg.hx * n.ny;
   const size_t pw = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos, pe = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
   const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
-  const T vw = up(pw, W ? i - 1 : i, j, k), ve = up(pe, E ? i + 1 : i, j, k), vs = up(ps, i, S ? j - 1 : j, k),
-          vn = up(pn, i, N ? j + 1 : j, k), vd = up(pd, i, j, D ? k - 1 : k), vu = up(pu, i, j, U ? k + 1 : k);
+  // the red neighbours' values and their parents' corrections, the faces and
+  // b: every load before the first wait
+  const T ew = e[pw], ee = e[pe], es = e[ps], en = e[pn], ed = e[pd], eu = e[pu];
+  const T qw = ec[cidx(W ? i - 1 : i, j, k)], qe = ec[cidx(E ? i + 1 : i, j, k)], qs = ec[cidx(i, S ? j - 1 : j, k)];
+  const T qn = ec[cidx(i, N ? j + 1 : j, k)], qd = ec[cidx(i, j, D ? k - 1 : k)], qu = ec[cidx(i, j, U ? k + 1 : k)];
   const size_t c = row + i;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
   const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  const T bcell = b[sg.P + pos];
+  __builtin_amdgcn_sched_barrier(0);
+  const T vw = ew + qw, ve = ee + qe, vs = es + qs, vn = en + qn, vd = ed + qd, vu = eu + qu;
   const bool top = !U;
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  const T num = h2 * b[sg.P + pos] + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
+  const T num = h2 * bcell + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
                 (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
   const T vb = num / diag;
   e[sg.P + pos] = vb;
@@ -500,22 +509,31 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
   const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
   const Tile tl = xcd_tile();
   const int i = tl.x * TX + tx, j = tl.y * TY + ty, k = tl.z * blockDim.z + tz;
-  const SplitGeo sg = split_geo(nf);
-  const size_t sxy = (size_t)nf.nx * nf.ny;
+  // Index arithmetic in 32 bits (every array of a level has fewer than 2^31
+  // entries): the kernel issues more integer instructions than loads, and
+  // 64-bit products cost several each.
+  const int hx = (nf.nx + 1) >> 1, P = hx * nf.ny * nf.nz;
+  const int sxy = nf.nx * nf.ny, sz = hx * nf.ny;
   T r = 0;
   if (i < nf.nx && j < nf.ny && k < nf.nz) {
-    const size_t c = i + (size_t)nf.nx * j + sxy * k;
-    const size_t fxi = i + (size_t)(nf.nx + 1) * (j + (size_t)nf.ny * k);
-    const size_t fyi = i + (size_t)nf.nx * (j + (size_t)(nf.ny + 1) * k);
-    const T xc = e[sidx(nf, sg, i, j, k)];
-    const T xw = e[sidx(nf, sg, i > 0 ? i - 1 : i, j, k)];
-    const T xe = e[sidx(nf, sg, i < nf.nx - 1 ? i + 1 : i, j, k)];
-    const T xs = e[sidx(nf, sg, i, j > 0 ? j - 1 : j, k)];
-    const T xn = e[sidx(nf, sg, i, j < nf.ny - 1 ? j + 1 : j, k)];
-    const T xd = e[sidx(nf, sg, i, j, k > 0 ? k - 1 : k)];
-    const T xu = e[sidx(nf, sg, i, j, k < nf.nz - 1 ? k + 1 : k)];
+    const int c = i + nf.nx * j + sxy * k;
+    const int fxi = i + (nf.nx + 1) * (j + nf.ny * k);
+    const int fyi = i + nf.nx * (j + (nf.ny + 1) * k);
+    const int par = (i + j + k) & 1;
+    const int rowp = hx * (j + nf.ny * k);          // first pair of the cell's row
+    const int own = par * P + (i >> 1) + rowp;      // the cell's own entry
+    const int oth = (1 - par) * P + rowp;           // the other colour's row (all six neighbours)
+    const int pc = oth + (i >> 1);
+    // walls read the cell's own entry, so their (x_c - x_nb) is zero
+    const T xc = e[own];
+    const T xw = e[i > 0 ? oth + ((i - 1) >> 1) : own];
+    const T xe = e[i < nf.nx - 1 ? oth + ((i + 1) >> 1) : own];
+    const T xs = e[j > 0 ? pc - hx : own];
+    const T xn = e[j < nf.ny - 1 ? pc + hx : own];
+    const T xd = e[k > 0 ? pc - sz : own];
+    const T xu = e[k < nf.nz - 1 ? pc + sz : own];
     const T cw = bx[fxi], ce = bx[fxi + 1], cs = by[fyi], cn = by[fyi + nf.nx], cd = bz[c], bu = bz[c + sxy];
-    const T bcell = b[sidx(nf, sg, i, j, k)];
+    const T bcell = b[own];
     // all loads above are in flight together: the compiler may not sink the
     // up neighbour's load into the branch that uses it
     __builtin_amdgcn_sched_barrier(0);
@@ -526,18 +544,21 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
   const int t = (tz * TY + ty) * TX + tx;
   sr[t] = r;
   __syncthreads();
-  // coarse cells of the tile
-  const int CX = TX / fx, CY = TY / fy, CZ = (int)blockDim.z / fz;
-  if (t >= CX * CY * CZ) return;
-  const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
-  const int I = tl.x * CX + cx, J = tl.y * CY + cy, K = tl.z * CZ + cz;
+  // each coarse cell of the tile is summed by the thread of its corner child
+  // (the factors are 1 or 2 and the tile's extents even, so shifts replace
+  // divisions)
+  const int sx = fx - 1, sy = fy - 1, sz2 = fz - 1;
+  if ((tx & sx) | (ty & sy) | (tz & sz2)) return;
+  const int CX = TX >> sx, CY = TY >> sy, CZ = (int)blockDim.z >> sz2;
+  const int I = tl.x * CX + (tx >> sx), J = tl.y * CY + (ty >> sy), K = tl.z * CZ + (tz >> sz2);
   if (I >= nc.nx || J >= nc.ny || K >= nc.nz) return;
   T sum = 0;
   for (int dk = 0; dk < fz; ++dk)
     for (int dj = 0; dj < fy; ++dj)
-      for (int di = 0; di < fx; ++di) sum += sr[((cz * fz + dk) * TY + cy * fy + dj) * TX + cx * fx + di];
-  const SplitGeo cg = split_geo(nc);
-  bc[lidx(nc, cg, csplit != 0, I, J, K)] = sum * inv;
+      for (int di = 0; di < fx; ++di) sum += sr[((tz + dk) * TY + ty + dj) * TX + tx + di];
+  const int chx = (nc.nx + 1) >> 1, cP = chx * nc.ny * nc.nz;
+  const int ci = csplit ? ((I + J + K) & 1) * cP + (I >> 1) + chx * (J + nc.ny * K) : I + nc.nx * (J + nc.ny * K);
+  bc[ci] = sum * inv;
 }
 
 // colour-split fine correction += parent's coarse correction (nu_post == 0)
