@@ -1050,7 +1050,7 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
   }
   Level& L0 = X->lev[0];
   const Dims n = L0.n;
-  const CgScratch cs{X->partials, X->scal, X->host_dev};
+  const CgScratch cs{X->partials, X->scal, X->host_dev, nullptr};
   (void)hipStreamSynchronize(X->st);
   (void)hipEventRecord(a, X->st);
   for (int q = 0; q < reps; ++q) {

@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(256) k_bias_part(long nv, int C, const uint16_
     for (long v = v0 + r; v < v1; v += lanes) s += bf2f(dY[v * C + c]);
   sm[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x < C) {
+  if ((int)threadIdx.x < C) {
     float t = 0.f;
     for (int q = 0; q < lanes; ++q) t += sm[q * C + threadIdx.x];
     part[(size_t)blockIdx.x * C + threadIdx.x] = t;
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(256) k_loss_part(long nv, const float* __restr
   sb[threadIdx.x] = b;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
       sa[threadIdx.x] += sa[threadIdx.x + s];
       sb[threadIdx.x] += sb[threadIdx.x + s];
     }
