@@ -60,6 +60,10 @@ def case(name):
         # with ragged row and plane tiles
         return I.workload("tiny3d", nx=96, ny=40, nz=24, h=4.0 / 96, seed=23,
                           bodies=[I.Body(1, (2.0, 0.8, 0.0), (0.3, 0.7, 1.5))])
+    if name == "rbnarrow":
+        # a tall narrow tank: its second level (16x8x128) takes the fused pass
+        # with 8-lane rows
+        return I.workload("tiny3d", nx=32, ny=16, nz=256, h=4.0 / 32, seed=25)
     if name == "rb2d":
         # a 2-D tank whose second level (64x1x128) takes the fused pass
         return I.workload("tiny2d", nx=128, ny=1, nz=256, h=8.0 / 128, seed=24)
@@ -192,8 +196,9 @@ def test_c1_ten_steps_free_running(orc):
 
 
 def test_operator_and_vcycle_parity(orc):
-    # rbragged, rb2d and c2 have coarse levels on the fused red-black pass
-    for name in ("tiny3d", "ragged3d", "odd1level", "c1", "rbragged", "rb2d", "c2"):
+    # rbragged, rbnarrow, rb2d and c2 have coarse levels on the fused
+    # red-black pass (rows of 32, 8, 32 and 32/16 lanes)
+    for name in ("tiny3d", "ragged3d", "odd1level", "c1", "rbragged", "rbnarrow", "rb2d", "c2"):
         wl = case(name)
         f = I.make_fields(wl)
         dt = I.cfl_dt(wl, f)
