@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
   const int px = t % TX, py = (t / TX) % TY, pz = t / (TX * TY);
   const int jb = ty0 + py, kb = tz0 + pz;
   const int ib = 2 * px + 1 - ((jb + kb) & 1);
-  const bool bok = jb < n.ny && kb < n.nz && ib < n.nx;
+  const bool bok = pz < TZ && jb < n.ny && kb < n.nz && ib < n.nx;
   const int jc = bok ? jb : 0, kc = bok ? kb : 0, ic = bok ? ib : 1;
   const size_t pb = (size_t)(ic >> 1) + (size_t)sg.hx * (jc + (size_t)n.ny * kc);
   const size_t cb = ic + (size_t)n.nx * jc + sxy * kc;
@@ -1330,7 +1330,9 @@ static bool gs_rb_tile(const Dims& n, int& TX, int& TY, int& TZ) {
   TX = hx > 16 ? 32 : hx > 8 ? 16 : 8;
   TY = n.ny > 1 ? 4 : 1;
   TZ = kRbThreads / (TX * TY);
-  return TX * (TY + (n.ny > 1 ? 2 : 0)) * (TZ + 2) <= kRbMaxExt;
+  // every thread's black cell inside the tile, and the ring-extended tile
+  // within the kernel's LDS and its unrolled loads
+  return TX * TY * TZ == kRbThreads && TX * (TY + (n.ny > 1 ? 2 : 0)) * (TZ + 2) <= kRbMaxExt;
 }
 
 bool gs_rb_fits(const Dims& n) {
