@@ -374,58 +374,51 @@ static double visc_dir(const orc_params* P, const double* mu, const double* cons
   return (tp - tm) / h;
 }
 
+/* Status of the last predictor call: bit 0 set when a transported face
+ * density came out non-positive, bit 1 when the Crank-Nicolson system did
+ * not converge. */
+static int g_flags = 0;
+int orc_last_flags(void) { return g_flags; }
+
 /* Crank-Nicolson viscous term (Sec. "Time stepping scheme"): each face that
  * is not a wall or the inlet solves
  *   D_f u*_f - 1/2 L(u*)_f = rhs_f,
  * rhs_f holding the explicit terms and 1/2 L(u^n)_f, D_f the implicit
- * diagonal (D_f = 0 marks a fixed face).  The system is solved by point-Jacobi
- * sweeps from the iterate in out, each
+ * diagonal (D_f = 0 marks a fixed face).  The system is solved to
+ * convergence by Gauss-Seidel sweeps in place over u, then v, then w, each
+ * face from the latest values of every component:
  *   u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f)) / (D_f + 1/2 a_f),
- * every component from the previous iterate, with a_f the magnitude of the
- * interior diagonal of L; fixed faces keep their values. */
-static void cn_sweeps(const orc_params* P, const double* mu, double* const rhs[3], double* const D[3],
-                      double* const out[3]) {
-  double* cur[3];
-  double* nxt[3];
-  for (int c = 0; c < 3; ++c) {
-    cur[c] = out[c];
-    nxt[c] = (double*)malloc(face_count(P, c) * sizeof(double));
-  }
-  for (int s = 0; s < P->cn_sweeps; ++s) {
-    const double* F[3] = {cur[0], cur[1], cur[2]};
+ * a_f the magnitude of the interior diagonal of L; any fixed point of this
+ * update solves the system above.  Sweeps stop once a sweep changes no face
+ * by more than 1e-15 of the largest |u*|; 500 sweeps without that set bit 1
+ * of the status. */
+static void cn_solve(const orc_params* P, const double* mu, double* const rhs[3], double* const D[3],
+                     double* const out[3]) {
+  for (int s = 0; s < 500; ++s) {
+    const double* F[3] = {out[0], out[1], out[2]};
+    double dmax = 0.0, umax = 0.0;
     for (int c = 0; c < 3; ++c) {
       int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
       for (int k = 0; k < mz; ++k)
         for (int j = 0; j < my; ++j)
           for (int i = 0; i < mx; ++i) {
             size_t f = i + (size_t)mx * (j + (size_t)my * k);
-            if (D[c][f] == 0.0) {
-              nxt[c][f] = cur[c][f];
-              continue;
-            }
+            if (D[c][f] == 0.0) continue;
             double L = 0.0, a = 0.0;
             for (int d = 0; d < 3; ++d) {
               double ad;
               L += visc_dir(P, mu, F, c, d, i, j, k, &ad);
               a += ad;
             }
-            nxt[c][f] = (rhs[c][f] + 0.5 * (L + a * cur[c][f])) / (D[c][f] + 0.5 * a);
+            double nv = (rhs[c][f] + 0.5 * (L + a * out[c][f])) / (D[c][f] + 0.5 * a);
+            dmax = fmax(dmax, fabs(nv - out[c][f]));
+            umax = fmax(umax, fabs(nv));
+            out[c][f] = nv;
           }
     }
-    for (int c = 0; c < 3; ++c) {
-      double* t = cur[c];
-      cur[c] = nxt[c];
-      nxt[c] = t;
-    }
+    if (dmax <= 1e-15 * umax) return;
   }
-  for (int c = 0; c < 3; ++c) {
-    if (cur[c] != out[c]) {
-      memcpy(out[c], cur[c], face_count(P, c) * sizeof(double));
-      free(cur[c]);
-    } else {
-      free(nxt[c]);
-    }
-  }
+  g_flags |= 2;
 }
 
 /* With rho_n (cell density at t^n) the predictor takes the conservative form
@@ -467,7 +460,8 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
   const double* F[3] = {u, v, w};
   double* out[3] = {us, vs, ws};
   /* Crank-Nicolson: half the viscous term at t^n goes to the right-hand side */
-  const int cn = P->cn_sweeps > 0;
+  const int cn = P->crank_nicolson != 0;
+  g_flags = 0;
   const double wv = cn ? 0.5 : 1.0;
   double* rhsA[3] = {NULL, NULL, NULL};
   double* DA[3] = {NULL, NULL, NULL};
@@ -546,6 +540,9 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
           if (rho_n) {
             double r0 = 0.5 * (cellv(P, rho_n, i - ec[0], j - ec[1], k - ec[2]) + cellv(P, rho_n, i, j, k));
             double rbf = r0 - dt * mflux / h;
+            /* a transported density at or below zero leaves the projection
+             * operator indefinite: the step is outside the scheme's bound */
+            if (!(rbf > 0.0)) g_flags |= 1;
             double num = r0 * uf / dt - conv / h + wv * visc + grav + pen * ub;
             double den = rbf / dt + pen + damp;
             out[c][f] = cn ? (num + 0.5 * visc) / den : num / den;
@@ -560,7 +557,7 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
         }
   }
   if (cn) {
-    cn_sweeps(P, mu, rhsA, DA, out);
+    cn_solve(P, mu, rhsA, DA, out);
     for (int c = 0; c < 3; ++c) {
       free(rhsA[c]);
       free(DA[c]);
@@ -922,11 +919,14 @@ int orc_step_from(const orc_params* P, double* sigma, double* u, double* v, doub
     orc_momentum(P, u, v, w, sigma, t1, dt, us, vs, ws);
     orc_face_beta(P, sigma, t1, dt, bx, by, bz);
   }
-  orc_rhs(P, us, vs, ws, dt, b);
-  if (!x0_prev) memset(p, 0, n * sizeof(double));
-  int rc = orc_pcg(P, bx, by, bz, b, p, st);
-  orc_correct(P, us, vs, ws, p, bx, by, bz, dt, u, v, w);
-  if (P->gen_len > 0.0 || P->damp_len > 0.0) orc_relax(P, t1, sigma, u, v, w);
+  int rc = (g_flags & 1) ? 2 : (g_flags & 2) ? 3 : 0;
+  if (rc == 0) {
+    orc_rhs(P, us, vs, ws, dt, b);
+    if (!x0_prev) memset(p, 0, n * sizeof(double));
+    rc = orc_pcg(P, bx, by, bz, b, p, st);
+    orc_correct(P, us, vs, ws, p, bx, by, bz, dt, u, v, w);
+    if (P->gen_len > 0.0 || P->damp_len > 0.0) orc_relax(P, t1, sigma, u, v, w);
+  }
   free(us);
   free(vs);
   free(ws);
@@ -935,6 +935,28 @@ int orc_step_from(const orc_params* P, double* sigma, double* u, double* v, doub
   free(bz);
   free(b);
   return rc;
+}
+
+/* Time step of the CFL rule (Sec. "Time stepping scheme"; the paper keeps
+ * the Courant number at or below 0.5): dt = cfl h / m with m the largest
+ * cell value of |u_c| + |v_c| + |w_c|, each cell velocity the mean of its two
+ * faces, capped at dt_max (dt_max for a fluid at rest). */
+double orc_cfl_dt(const orc_params* P, const double* u, const double* v, const double* w, double cfl,
+                  double dt_max) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
+  double m = 0.0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double uc = 0.5 * fabs(facev(P, 0, u, i, j, k) + facev(P, 0, u, i + 1, j, k));
+        double vc = 0.5 * fabs(facev(P, 1, v, i, j, k) + facev(P, 1, v, i, j + 1, k));
+        double wc = 0.5 * fabs(facev(P, 2, w, i, j, k) + facev(P, 2, w, i, j, k + 1));
+        double s = uc + vc + wc;
+        if (s > m) m = s;
+      }
+  if (!(m > 0.0)) return dt_max;
+  double dt = cfl * P->h / m;
+  return dt < dt_max ? dt : dt_max;
 }
 
 /* max |div_h u|, water volume sum (1 - H(sigma)) h^d, kinetic energy

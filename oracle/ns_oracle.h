@@ -54,8 +54,8 @@ typedef struct {
   double wave_a[64], wave_k[64], wave_om[64], wave_ph[64];
   int consistent;              /* 1: conservative predictor with consistent       */
                                /*    mass/momentum transport                     */
-  int cn_sweeps;               /* > 0: Crank-Nicolson viscous term, solved by     */
-                               /*    this many Jacobi sweeps; 0: explicit         */
+  int crank_nicolson;          /* 1: Crank-Nicolson viscous term, its system      */
+                               /*    solved to convergence; 0: explicit           */
 } orc_params;
 
 typedef struct {
@@ -92,6 +92,15 @@ int  orc_pcg(const orc_params* P, const double* bx, const double* by, const doub
 void orc_correct(const orc_params* P, const double* us, const double* vs, const double* ws,
                  const double* p, const double* bx, const double* by, const double* bz, double dt,
                  double* u, double* v, double* w);
+/* time step of the CFL rule on the current face velocities */
+double orc_cfl_dt(const orc_params* P, const double* u, const double* v, const double* w, double cfl,
+                  double dt_max);
+/* status of the last predictor: bit 0 a non-positive transported density,
+ * bit 1 a Crank-Nicolson solve that did not converge */
+int  orc_last_flags(void);
+/* orc_step / orc_step_from return 0, 1 when CG did not converge, 2 when the
+ * consistent transport's face density came out non-positive (the step stops
+ * after the predictor), 3 when the Crank-Nicolson solve did not converge */
 int  orc_step(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,
               double dt, double t_n, int x0_prev, orc_stats* st);
 int  orc_step_from(const orc_params* P, double* sigma, double* u, double* v, double* w, double* p,

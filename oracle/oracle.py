@@ -48,7 +48,7 @@ class Params(C.Structure):
                 ("vort_width", C.c_double), ("n_waves", C.c_int),
                 ("wave_a", C.c_double * 64), ("wave_k", C.c_double * 64), ("wave_om", C.c_double * 64),
                 ("wave_ph", C.c_double * 64), ("consistent", C.c_int),
-                ("cn_sweeps", C.c_int)]
+                ("crank_nicolson", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -92,11 +92,15 @@ def lib():
             "orc_relax": [P, d, dp, dp, dp, dp],
             "orc_momentum_cons": [P, dp, dp, dp, dp, d, d, dp, dp, dp, dp, dp, dp, dp],
             "orc_face_beta_rho": [P, dp, dp, dp, dp, d, d, dp, dp, dp],
+            "orc_cfl_dt": [P, dp, dp, dp, d, d],
+            "orc_last_flags": [],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
-            fn.restype = C.c_int if name in ("orc_num_levels", "orc_pcg", "orc_step", "orc_step_from") else None
+            fn.restype = C.c_int if name in ("orc_num_levels", "orc_pcg", "orc_step", "orc_step_from",
+                                             "orc_last_flags") else None
+        L.orc_cfl_dt.restype = C.c_double
         _lib = L
     return _lib
 
@@ -134,7 +138,7 @@ def params(wl, **solver) -> Params:
         P.body[m].zeta, P.body[m].zdot = b.zeta0, b.zdot0
     P.depth = wl.depth
     P.consistent = int(wl.consistent)
-    P.cn_sweeps = int(wl.cn_sweeps)
+    P.crank_nicolson = 1 if wl.cn_sweeps > 0 else 0
     if wl.nwt:
         from paper_2206_07732_amd.inputs import wave_components
         P.gen_len, P.damp_len, P.vort_width = wl.nwt.get("gen", 0.0), wl.nwt.get("damp", 0.0), wl.nwt.get("vort", 0.0)
@@ -241,6 +245,19 @@ def step(P, fields, dt, t_n, x0_prev=True, rho_n=None):
     rc = lib().orc_step_from(C.byref(P), _p(f["sigma"]), _p(f["u"]), _p(f["v"]), _p(f["w"]), _p(f["p"]),
                              dt, t_n, 1 if x0_prev else 0, None if rn is None else _p(rn), C.byref(st))
     return f, st.as_dict(), rc
+
+
+def cfl_dt(P, fields, cfl: float, dt_max: float = 0.05) -> float:
+    """Time step of the CFL rule on the fields' face velocities: cfl h over
+    the largest cell |u_c| + |v_c| + |w_c|, capped at dt_max."""
+    u, v, w = (_arr(fields[k]) for k in ("u", "v", "w"))
+    return lib().orc_cfl_dt(C.byref(P), _p(u), _p(v), _p(w), cfl, dt_max)
+
+
+def last_flags() -> int:
+    """Status of the last predictor: bit 0 a non-positive transported face
+    density, bit 1 an unconverged Crank-Nicolson solve."""
+    return lib().orc_last_flags()
 
 
 def diagnostics(P, sigma, u, v, w):

@@ -193,6 +193,13 @@ def workload(name: str, **over) -> Workload:
         wl = Workload("c2: 3-D tank 128x64x64 (4x2x2 m, h=1/32), Stokes-2 a=0.05 m T=1.2 s, fixed cylinder",
                       128, 64, 64, 4.0 / 128, 1.0, {"kind": "stokes2", "a": 0.05, "T": 1.2}, [_cyl()],
                       steps=20, seed=2)
+    elif name == "c2half":
+        # C2's tank and wave at half the resolution: the smallest tank on which
+        # the cylinder's waterline drives the local Courant number past 0.5
+        # within a dozen steps of the fixed initial-field time step
+        wl = Workload("c2half: 3-D tank 64x32x32 (4x2x2 m, h=1/16), Stokes-2 a=0.05 m T=1.2 s, fixed cylinder",
+                      64, 32, 32, 4.0 / 64, 1.0, {"kind": "stokes2", "a": 0.05, "T": 1.2}, [_cyl()],
+                      steps=40, seed=2)
     elif name == "c3":
         wl = Workload("c3: 3-D tank 256x128x128 (4x2x2 m, h=1/64), JONSWAP Hs=0.1 m Tp=1.5 s 64 comps, fixed cylinder",
                       256, 128, 128, 4.0 / 256, 1.0, {"kind": "jonswap", "hs": 0.1, "tp": 1.5, "n": 64},
