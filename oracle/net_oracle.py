@@ -12,9 +12,13 @@ and the previous pressure to a correction delta, and the initial guess is
 p0 = p_prev + P0 delta with P0 = rho_w g d.
 
 Arrays are channel-first (C, Z, Y, X) here.  With bf16=True every value the
-GPU stores in bfloat16 (features, weights, activations) is rounded to
-bfloat16 (round to nearest even) at the same points; products and sums stay
-in FP64 (the GPU sums in FP32).
+GPU stores in bfloat16 is rounded to bfloat16 (round to nearest even) at the
+same point: the features, the weights of the 3x3x3 convolutions, every
+activation, and in the backward pass every activation gradient (after its
+ReLU mask, after the input-gradient convolution, after the upsampling's
+adjoint, after a skip connection's sum).  The 1x1x1 head keeps its weights
+and its output in FP32 on the GPU, so they are not rounded.  Products and
+sums stay in FP64 here (the GPU sums in FP32).
 """
 from __future__ import annotations
 
@@ -123,7 +127,8 @@ def up_backward(dy):
 def forward(P, feat, bf16=False):
     """delta and the cache for backward.  feat: (4, Z, Y, X)."""
     q = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    W = {k: (q(v) if k.endswith(".w") else np.asarray(v, dtype=np.float64)) for k, v in P.items()}
+    W = {k: (q(v) if k.endswith(".w") and k != "head.w" else np.asarray(v, dtype=np.float64))
+         for k, v in P.items()}
     x0 = q(feat)
     a1 = q(np.maximum(conv(x0, W["c1.w"], W["c1.b"]), 0.0))
     p1 = q(pool(a1))
@@ -135,28 +140,33 @@ def forward(P, feat, bf16=False):
     c1 = np.concatenate([a1, up(a4)], axis=0)
     a5 = q(np.maximum(conv(c1, W["c5.w"], W["c5.b"]), 0.0))
     out = conv(a5, W["head.w"], W["head.b"])[0]
-    cache = dict(W=W, x0=x0, a1=a1, p1=p1, a2=a2, p2=p2, a3=a3, c2=c2, a4=a4, c1=c1, a5=a5)
+    cache = dict(W=W, x0=x0, a1=a1, p1=p1, a2=a2, p2=p2, a3=a3, c2=c2, a4=a4, c1=c1, a5=a5, bf16=bf16)
     return out, cache
 
 
 def backward(cache, dout):
     """Parameter gradients (dict) for d(loss)/d(out) = dout (Z, Y, X)."""
     W = cache["W"]
+    q = bf16_round if cache.get("bf16") else (lambda a: a)
     g = {}
     d5, g["head.w"], g["head.b"] = conv_backward(cache["a5"], W["head.w"], dout[None])
-    d5 = d5 * (cache["a5"] > 0)
+    d5 = q(d5 * (cache["a5"] > 0))
     dc1, g["c5.w"], g["c5.b"] = conv_backward(cache["c1"], W["c5.w"], d5)
+    dc1 = q(dc1)
     da1 = dc1[:16].copy()
-    d4 = up_backward(dc1[16:]) * (cache["a4"] > 0)
+    d4 = q(up_backward(dc1[16:]) * (cache["a4"] > 0))
     dc2, g["c4.w"], g["c4.b"] = conv_backward(cache["c2"], W["c4.w"], d4)
+    dc2 = q(dc2)
     da2 = dc2[:32].copy()
-    d3 = up_backward(dc2[32:]) * (cache["a3"] > 0)
+    d3 = q(up_backward(dc2[32:]) * (cache["a3"] > 0))
     dp2, g["c3.w"], g["c3.b"] = conv_backward(cache["p2"], W["c3.w"], d3)
+    dp2 = q(dp2)
     da2 += pool_backward(dp2)
-    d2 = da2 * (cache["a2"] > 0)
+    d2 = q(da2 * (cache["a2"] > 0))
     dp1, g["c2.w"], g["c2.b"] = conv_backward(cache["p1"], W["c2.w"], d2)
+    dp1 = q(dp1)
     da1 += pool_backward(dp1)
-    d1 = da1 * (cache["a1"] > 0)
+    d1 = q(da1 * (cache["a1"] > 0))
     _, g["c1.w"], g["c1.b"] = conv_backward(cache["x0"], W["c1.w"], d1)
     return g
 

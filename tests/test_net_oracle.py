@@ -120,3 +120,34 @@ def test_energy_loss_gradient_and_special_values():
         dm[idx] -= eps
         fd = (N.energy_loss_and_grad(dp, t, op)[0] - N.energy_loss_and_grad(dm, t, op)[0]) / (2 * eps)
         assert abs(fd - g[idx]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_bf16_emulation_stays_within_rounding_of_the_exact_network():
+    """The bfloat16 emulation rounds (features, 3x3x3 weights, activations and
+    activation gradients) but keeps the head in full precision: with inputs
+    and weights that are already bfloat16 numbers, its output and gradients
+    stay within a few bfloat16 roundings (2^-8 relative each, compounded over
+    the layers) of the FP64 network's, and differ from them (something is
+    rounded).  A head whose weights are bfloat16 numbers and a loss gradient
+    that is one make the two heads' arithmetic identical, so any difference
+    comes from the emulated storage."""
+    rng = np.random.default_rng(31)
+    theta = N.bf16_round(N.he_init(5))
+    theta[-17:] = N.bf16_round(rng.standard_normal(17) * 0.3)
+    P = N.unflatten(theta)
+    feat = N.bf16_round(rng.standard_normal((4, 8, 8, 8)))
+    out64, c64 = N.forward(P, feat)
+    out16, c16 = N.forward(P, feat, bf16=True)
+    r_out = np.linalg.norm(out16 - out64) / np.linalg.norm(out64)
+    assert 1e-5 < r_out < 3e-2
+    dout = N.bf16_round(rng.standard_normal(out64.shape))
+    g64 = N.backward(c64, dout)
+    g16 = N.backward(c16, dout)
+    for k in g64:
+        r = np.linalg.norm(g16[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert r < 6e-2, k
+    # the head's weight gradient sees only a5, rounded the same way on both
+    # paths up to the activations' own rounding; the deepest gradient (c1)
+    # has passed through every rounded tensor
+    r_c1 = np.linalg.norm(g16["c1.w"] - g64["c1.w"]) / np.linalg.norm(g64["c1.w"])
+    assert r_c1 > 1e-4
