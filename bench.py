@@ -1,46 +1,44 @@
 #!/usr/bin/env python3
 """Throughput of the two-phase Navier-Stokes time step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload c5] [--no-cpu-baseline]
 
-A step is one whole pass of the hot path: level-set advection and
+A step is one whole pass of the hot path: the time step of the CFL rule on
+the current velocity (ns_cfl_dt), level-set advection and
 reinitialisation, properties, the momentum predictor, and the projection
 solved by MG-preconditioned CG to ||b - A p|| <= 1e-10 ||b||.  The default
-workload is the 3-D tank of 128x64x64 cells (4 x 2 x 2 m, 1 m water,
-second-order Stokes wave a = 0.05 m, T = 1.2 s, fixed cylinder buoy) in
-plain FP64, with synthetic seeded inputs already resident in device memory
-when the timed region starts.
+workload is the largest single-GPU tank, 512x256x256 cells (4 x 2 x 2 m,
+33.5 M cells, 1 m water, JONSWAP waves Hs 0.2 m Tp 2 s, two cylinders
+heaving at a prescribed velocity), in plain FP64, with synthetic seeded
+inputs already resident in device memory when the timed region starts.
 
 Printed: ONE JSON line with
   value        Mcell-steps/s over the K timed steps (cells x K / seconds)
-  projection   projection wall time and CG iterations on the same workload,
-               FP64 V-cycle vs FP32 V-cycle inside FP64 CG, both to the same
-               1e-10 residual
-  projection_study  the same on the 256x128x128 tanks (JONSWAP waves, and a
-               held-out draw of the learned guess's Airy-wave training runs)
-               for the FP64 V-cycle (zero and previous-pressure guesses) and
-               the FP32 V-cycle (previous-pressure and learned guesses,
+  roofline     the dominant kernel (the finest-level red-black smoothing):
+               its algorithmic bytes per launch (24 B per cell per colour
+               pass: beta on the three face arrays once, b, e read and e
+               written once per sweep, halved over the two colours) over its
+               average duration from HIP events on the library's stream,
+               against the published 8 TB/s; traffic from rocprofv3 counters
+  step_roofline  the whole step's algorithmic bytes (380 B per cell outside
+               the solve, 387 B per cell per FP64 CG iteration) over the
+               measured step time
+  phases       device time of each phase of a step (level set, predictor,
+               projection set-up, CG, correction)
+  configs      the FP64 step on the other tanks: 256x64 (2-D), 128x64x64,
+               256x128x128
+  projection_study  projection wall time and CG iterations to the same
+               1e-10 true residual: FP64 V-cycle (zero and previous-pressure
+               guesses), FP32 V-cycle (previous-pressure and learned guesses,
                inference included), the per-field difference of the
-               FP32-V-cycle step from the FP64 one, and the network forward's
-               BF16 rate
-  fsi_study    free heave (force of eqn_int_fh, heave of eqn_newton_u) on the
-               same tank with the cylinder free: whole ns_step calls timed the
-               same way, against the fixed-body step, with the heave range and
-               the force over the body's weight
-  nwt_study    the same grid as a numerical wave tank (Airy waves generated at
-               the inlet, generation and damping zones, vorticity damping),
-               timed the same way
-  option_study the main workload with the predictor's options: consistent
-               mass/momentum transport, and the Crank-Nicolson viscous term
-               (N Jacobi sweeps), timed the same way
-  roofline     the finest-level smoother pass (the dominant kernel): its
-               algorithmic bytes per launch over its average duration, the
-               duration taken from HIP events recorded with each dispatch;
-               against the published 8 TB/s and a measured device copy
+               FP32-V-cycle step from the FP64 one, the network forward's
+               BF16 rate; on 512x256x256 and the two 256x128x128 tanks
+  fsi_study, nwt_study, option_study  free heave, the numerical wave tank
+               and the predictor's options on the 128x64x64 tank
   measured_ceilings  a 1 GiB device copy and an 8192^3 BF16 matrix product
-               timed on the device, beside the published peaks
-  cpu_baseline the FP64 CPU oracle, single-threaded, on a bounded sample of
-               the same workload
+  cpu_baseline the FP64 CPU oracle on the host's cores (OpenMP, static
+               schedule) and on one thread, each on the first step of the
+               same workload
 """
 from __future__ import annotations
 
@@ -56,24 +54,42 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 
-# HBM bytes per launch of the finest smoother pass from rocprofv3 counters
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors from a 256 MiB device
-# copy measured in the same runs); None until taken for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = 19988958   # profiles/c2_smoother_hbm_counters.md
+# HBM bytes per launch of the dominant kernel at 512x256x256 from two
+# rocprofv3 --pmc passes (FETCH_SIZE x its copy-calibrated factor +
+# WRITE_SIZE), taken for the kernel as it is now; None until taken.
+TRAFFIC_BYTES_PER_LAUNCH = None
+
+# Algorithmic bytes per cell (FP64, 3-D; each array read or written once per
+# pass): the passes outside the solve, and one FP64 CG iteration (vector work
+# 120 + the V(2,2) cycle 267 over all levels).
+STEP_BYTES_PER_CELL = 380.0
+ITER_BYTES_PER_CELL_FP64 = 387.0
+# one red-black sweep of the smoother reads the three face arrays of beta,
+# b and e once and writes e once: 48 B per cell, 24 per colour pass
+SWEEP_BYTES_PER_CELL_FP64 = 48.0
+# the kernel the library's smoother timer measures (ns.TIME_SMOOTH0) and the
+# part of one red-black sweep of the finest level that one launch does
+SMOOTHER_KERNEL = "k_gs<double, true> (one red-black colour pass, finest level)"
+SWEEPS_PER_LAUNCH = 0.5
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def smoother_bytes_per_cell(prec: int) -> float:
-    """Algorithmic bytes per cell of one colour pass of red-black Gauss-Seidel:
-    beta on the three face arrays (every face touches a cell of each colour),
-    b and the new e of that colour's half of the cells, and the old e of the
-    other colour's half (its neighbours).  FP64: 24 + 4 + 4 + 4 = 36 B."""
-    w = 8 if prec == 0 else 4
-    return 3 * w + 0.5 * w + 0.5 * w + 0.5 * w
+def timed_steps(S, wl, steps: int, t0: float = 0.0):
+    """`steps` whole steps, each with the time step of the CFL rule taken on
+    the device from the current velocity; returns (t, iters, dts)."""
+    t, iters, dts = t0, [], []
+    for _ in range(steps):
+        dt = S.cfl_dt(wl.cfl, wl.dt_max)
+        st = S.step(dt, t)
+        iters.append(st["iters"])
+        dts.append(dt)
+        t += dt
+    return t, iters, dts
 
 
 def run_gpu(args):
@@ -89,89 +105,82 @@ def run_gpu(args):
         build.build()
     wl = I.workload(args.workload)
     f0 = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f0)
     ncell = wl.ncells
 
     # ---- main timed region: K whole FP64 steps
     dev = ns.device_fields(f0)
     S = ns.Solver(ns.params(wl, prec=ns.PREC_FP64), dev)
-    t = 0.0
-    for _ in range(args.warmup):
-        S.step(dt, t)
-        t += dt
+    t, _, _ = timed_steps(S, wl, args.warmup)
     torch.cuda.synchronize()
-    iters = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = S.step(dt, t)
-        iters.append(st["iters"])
-        t += dt
+    t, iters, dts = timed_steps(S, wl, args.steps, t)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = ncell * args.steps / elapsed / 1e6
     log(f"[bench] {args.workload}: {ms_per_step:.3f} ms/step, {value:.1f} Mcell-steps/s, CG iters {iters}")
 
-    # ---- dominant kernel: the finest-level smoother pass.  Its average
-    # duration is taken from HIP events around a batch of back-to-back
-    # dispatches (amortising the events' own cost); the per-dispatch event
-    # figure from inside real steps is reported beside it.
-    reps = 200
+    # ---- where a step's time goes (device time per phase, three steps)
+    S.phase_timing(True)
+    ph = []
+    for _ in range(3):
+        dt = S.cfl_dt(wl.cfl, wl.dt_max)
+        ph.append(S.step(dt, t)["t_ms"])
+        t += dt
+    S.phase_timing(False)
+    names = ["level_set", "predictor", "projection_setup", "cg_solve", "correction", "step"]
+    phases = {n: round(statistics.mean(p[q] for p in ph), 4) for q, n in enumerate(names)}
+    log(f"[bench] phases (ms): {phases}")
+
+    # ---- the dominant kernel: the finest-level red-black smoothing pass.
+    # Its average duration from HIP events around a batch of back-to-back
+    # dispatches, and from events recorded with each dispatch inside steps.
+    reps = 100
     avg_ms = S.time_kernel(ns.TIME_SMOOTH0, reps)
     S.timing_enable(ns.TIME_SMOOTH0, 4096)
     for _ in range(2):
+        dt = S.cfl_dt(wl.cfl, wl.dt_max)
         S.step(dt, t)
         t += dt
     kms, kn = S.timing_read()
     S.timing_enable(ns.TIME_SMOOTH0, 0)
-    kbytes = smoother_bytes_per_cell(0) * ncell
-    achieved = kbytes / (avg_ms * 1e-3) / 1e9
-    roofline = {"kernel": "k_gs<double, true> (one red-black colour pass, finest level)",
-                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES_PER_LAUNCH,
-                "avg_us": round(avg_ms * 1e3, 3), "timed_launches": reps,
-                "bytes_per_launch": int(kbytes),
-                "in_step_event_avg_us": round(kms / max(kn, 1) * 1e3, 3), "in_step_launches": kn}
-    log(f"[bench] smoother pass: avg {avg_ms*1e3:.2f} us over {reps} back-to-back launches "
-        f"({achieved:.0f} GB/s); in-step per-dispatch events {kms/max(kn,1)*1e3:.2f} us over {kn}")
     S.close()
+    kbytes = SWEEP_BYTES_PER_CELL_FP64 * SWEEPS_PER_LAUNCH * ncell
+    in_step_ms = kms / max(kn, 1)
+    achieved = kbytes / (in_step_ms * 1e-3) / 1e9
+    achieved_batch = kbytes / (avg_ms * 1e-3) / 1e9
+    roofline = {"kernel": SMOOTHER_KERNEL, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                "bytes_per_launch": int(kbytes), "sweeps_per_launch": SWEEPS_PER_LAUNCH,
+                "bytes_per_cell_per_sweep": SWEEP_BYTES_PER_CELL_FP64,
+                "avg_us": round(in_step_ms * 1e3, 3), "launches": kn, "timing": "HIP events with each "
+                "dispatch inside two whole steps, on the library's stream",
+                "batch_avg_us": round(avg_ms * 1e3, 3), "batch_launches": reps,
+                "batch_frac": round(achieved_batch / HBM_PEAK_GBS, 4)}
+    log(f"[bench] smoother: {in_step_ms * 1e3:.2f} us per launch in steps ({achieved:.0f} GB/s, "
+        f"{100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s); {avg_ms * 1e3:.2f} us back to back")
+    mean_it = statistics.mean(iters)
+    step_bytes = (STEP_BYTES_PER_CELL + mean_it * ITER_BYTES_PER_CELL_FP64) * ncell
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
+    step_roofline = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": int(step_bytes),
+                     "bytes_per_cell": STEP_BYTES_PER_CELL + mean_it * ITER_BYTES_PER_CELL_FP64,
+                     "mean_cg_iters": mean_it}
+    log(f"[bench] whole step: {step_gbs:.0f} GB/s algorithmic ({100 * step_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     ceil = measured_ceilings()
     roofline["copy_ceiling_gbs"] = ceil["copy_gbs"]
     roofline["frac_of_copy"] = round(achieved / ceil["copy_gbs"], 4)
     log(f"[bench] measured ceilings: device copy {ceil['copy_gbs']:.0f} GB/s, BF16 GEMM "
-        f"{ceil['bf16_gemm_tflops']:.0f} TFLOP/s; smoother pass at {100 * achieved / ceil['copy_gbs']:.0f}% of the copy")
-
-    # ---- projection time to 1e-10, FP64 V-cycle vs FP32 V-cycle in FP64 CG
-    proj = {}
-    for name, prec in (("fp64", ns.PREC_FP64), ("mixed", ns.PREC_MIXED)):
-        d = ns.device_fields(f0)
-        Sp = ns.Solver(ns.params(wl, prec=prec), d)
-        tt = 0.0
-        for _ in range(args.warmup):
-            Sp.step(dt, tt)
-            tt += dt
-        ms, its, res = [], [], []
-        for _ in range(max(3, min(args.steps, 10))):
-            Sp.levelset_advect_reinit(dt)
-            Sp.momentum_step(dt, tt + dt)
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            st = Sp.projection_solve(dt)
-            ms.append(1e3 * (time.perf_counter() - a))
-            its.append(st["iters"])
-            res.append(st["true_rel_resid"])
-            tt += dt
-        proj[name] = {"ms_median": round(statistics.median(ms), 4), "iters": its,
-                      "max_true_rel_resid": max(res)}
-        Sp.close()
-    proj["speedup_mixed_vs_fp64"] = round(proj["fp64"]["ms_median"] / proj["mixed"]["ms_median"], 3)
-    log(f"[bench] projection fp64 {proj['fp64']['ms_median']:.3f} ms, mixed {proj['mixed']['ms_median']:.3f} ms")
-
+        f"{ceil['bf16_gemm_tflops']:.0f} TFLOP/s")
     config = {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "cells": ncell, "h": wl.h,
-              "dt": dt, "cfl": wl.cfl, "solver": "flexible PCG, V(2,2) red-black GS, FP64",
-              "rtol": 1e-10, "mg_levels": ns.num_levels(wl.nx, wl.ny, wl.nz)}
+              "dt": "CFL rule on the current velocity each step", "cfl": wl.cfl,
+              "dt_range": [min(dts), max(dts)],
+              "solver": "flexible PCG, V(2,2) red-black GS, FP64", "rtol": 1e-10,
+              "mg_levels": ns.num_levels(wl.nx, wl.ny, wl.nz)}
     return {"value": value, "ms_per_step": ms_per_step, "iters": iters, "roofline": roofline,
-            "projection": proj, "config": config, "wl": wl, "f0": f0, "dt": dt, "ceilings": ceil}
+            "step_roofline": step_roofline, "phases": phases, "config": config, "wl": wl, "f0": f0,
+            "ceilings": ceil}
 
 
 def measured_ceilings():
@@ -209,13 +218,33 @@ def measured_ceilings():
     return {"copy_gbs": round(copy_gbs, 1), "bf16_gemm_tflops": round(gemm, 1)}
 
 
+def config_line(name: str, steps: int, warmup: int):
+    """The FP64 step on another tank, timed like the main one."""
+    import torch
+
+    from paper_2206_07732_amd import inputs as I
+    from paper_2206_07732_amd import ns
+    wl = I.workload(name)
+    S = ns.Solver(ns.params(wl), ns.device_fields(I.make_fields(wl)))
+    t, _, _ = timed_steps(S, wl, warmup)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    t, iters, _ = timed_steps(S, wl, steps, t)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - a) / steps
+    S.close()
+    out = {"workload": wl.name, "cells": wl.ncells, "steps": steps, "ms_per_step": round(ms, 4),
+           "mcell_steps_per_s": round(wl.ncells / (ms * 1e-3) / 1e6, 3), "cg_iters": iters}
+    log(f"[bench] {name}: {ms:.3f} ms/step, {out['mcell_steps_per_s']} Mcell-steps/s, iters {iters}")
+    return out
+
+
 # FLOPs of one inference of the learned-guess network per voxel of the full
 # grid: 2 * 27 * C_in * C_out per output voxel and layer (first layer with its
 # 4 real input channels; levels 2 and 3 hold 1/8 and 1/64 of the voxels), plus
 # the 1x1x1 head.
 NET_FLOP_PER_VOXEL = (2 * 27 * 4 * 16 + 2 * 27 * 48 * 16 + 2 * 16) + (2 * 27 * 16 * 32 + 2 * 27 * 96 * 32) / 8 + \
     (2 * 27 * 32 * 64) / 64
-MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak, published
 
 
 def projection_study(name: str, steps: int, warmup: int, weights: str):
@@ -233,7 +262,6 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
 
     wl = I.workload(name)
     f0 = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f0)
     net = None
     if weights and os.path.exists(weights):
         net = ns.Net(wl.nx, wl.ny, wl.nz)
@@ -249,12 +277,10 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
                                 x0={"zero": ns.X0_ZERO, "prev": ns.X0_PREV, "learned": ns.X0_LEARNED}[x0]), dev)
         if x0 == "learned":
             S.attach_net(net)
-        t = 0.0
-        for _ in range(warmup):
-            S.step(dt, t)
-            t += dt
+        t, _, _ = timed_steps(S, wl, warmup)
         ms, its, r0, res = [], [], [], []
         for _ in range(steps):
+            dt = S.cfl_dt(wl.cfl, wl.dt_max)
             S.levelset_advect_reinit(dt)
             S.momentum_step(dt, t + dt)
             torch.cuda.synchronize()
@@ -267,7 +293,7 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
             t += dt
         out[f"{prec}+{x0}"] = {"ms_median": round(statistics.median(ms), 4), "iters": its,
                                "mean_rel_resid0": float(np.mean(r0)), "max_true_rel_resid": max(res)}
-        log(f"[bench] {wl.name[:3]} projection {prec}+{x0}: {statistics.median(ms):.3f} ms, iters {its}")
+        log(f"[bench] {wl.name[:6]} projection {prec}+{x0}: {statistics.median(ms):.3f} ms, iters {its}")
         S.close()
     base = out["fp64+prev"]["ms_median"]
     for k in ("mixed+prev", "mixed+learned"):
@@ -278,6 +304,7 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
     for prec in (ns.PREC_FP64, ns.PREC_MIXED):
         dev = ns.device_fields(f0)
         S = ns.Solver(ns.params(wl, prec=prec), dev)
+        dt = S.cfl_dt(wl.cfl, wl.dt_max)
         S.step(dt, 0.0)
         torch.cuda.synchronize()
         fields[prec] = {k: v.clone() for k, v in dev.items()}
@@ -288,6 +315,7 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
         nrm = float(torch.linalg.vector_norm(b))
         err[k] = {"rel_l2": float(torch.linalg.vector_norm(a - b)) / nrm if nrm > 0 else 0.0,
                   "max_abs": float((a - b).abs().max())}
+    del fields
     out["mixed_vs_fp64_one_step"] = err
     if net is not None:
         feat = torch.randn((4, wl.nz, wl.ny, wl.nx), dtype=torch.float32, device="cuda")
@@ -307,6 +335,8 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
                               "achieved_tflops": round(tflops, 1), "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
                               "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4)}
         log(f"[bench] network forward {fwd_ms:.3f} ms ({tflops:.0f} TFLOP/s BF16)")
+        net.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -323,29 +353,26 @@ def option_overrides(opt: str) -> dict:
     return over
 
 
-def variant_study(name: str, steps: int, warmup: int, fixed: dict, label: str = "", **over):
-    """A variant of the main tank (free heave, a numerical wave tank, or an
-    option of the predictor): K whole ns_step calls after W warm-up steps;
-    fixed is the main run on the same grid for comparison.  For a free body
-    also its heave range and its force over its weight."""
+def variant_study(name: str, steps: int, warmup: int, base: dict, label: str = "", **over):
+    """A variant of a tank (free heave, a numerical wave tank, or an option
+    of the predictor): K whole steps after W warm-up steps, timed like the
+    main run; base is the same grid's plain run for comparison.  For a free
+    body also its heave range and its force over its weight."""
     import torch
     from paper_2206_07732_amd import inputs as I, ns
     wl = I.workload(name, **over)
-    f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
-    S = ns.Solver(ns.params(wl), ns.device_fields(f))
-    t = 0.0
-    for _ in range(warmup):
-        S.step(dt, t)
-        t += dt
+    S = ns.Solver(ns.params(wl), ns.device_fields(I.make_fields(wl)))
+    t, _, _ = timed_steps(S, wl, warmup)
     torch.cuda.synchronize()
     free = any(b.free_heave for b in wl.bodies)
-    zeta, fz, iters = [], [], []
+    zeta, fz, iters, cn = [], [], [], []
     a = time.perf_counter()
     for _ in range(steps):
+        dt = S.cfl_dt(wl.cfl, wl.dt_max)
         st = S.step(dt, t)
         t += dt
         iters.append(st["iters"])
+        cn.append(st["cn_sweeps"])
         if free:
             b = S.body_state(0)       # host state: no device work
             zeta.append(b["zeta"])
@@ -353,46 +380,57 @@ def variant_study(name: str, steps: int, warmup: int, fixed: dict, label: str = 
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - a) / steps
     S.close()
-    ncell = wl.nx * wl.ny * wl.nz
     out = {
         "workload": wl.name + (f" [{label}]" if label else ""),
         "steps": steps,
         "ms_per_step": round(ms, 4),
-        "mcell_steps_per_s": round(ncell * steps / (ms * steps * 1e-3) / 1e6, 3),
+        "mcell_steps_per_s": round(wl.ncells / (ms * 1e-3) / 1e6, 3),
         "cg_iters": iters,
         "ms_per_cg_iter": round(ms / statistics.mean(iters), 4),
-        "main_ms_per_step": round(fixed["ms_per_step"], 4),
-        "main_ms_per_cg_iter": round(fixed["ms_per_step"] / statistics.mean(fixed["iters"]), 4),
+        "base_ms_per_step": base["ms_per_step"],
+        "base_ms_per_cg_iter": round(base["ms_per_step"] / statistics.mean(base["cg_iters"]), 4),
     }
+    if wl.cn_sweeps:
+        out["cn_sweeps"] = cn
     if free:
         mg = wl.bodies[0].mass * wl.g
         out["zeta_range_m"] = [round(min(zeta), 6), round(max(zeta), 6)]
         out["fz_over_mg_range"] = [round(min(fz) / mg, 4), round(max(fz) / mg, 4)]
-    log(f"[bench] {name}{' ' + label if label else ''}: {ms:.3f} ms/step ({out['ms_per_cg_iter']} ms per CG iteration; main tank "
-        f"{out['main_ms_per_cg_iter']})" + (f", zeta in {out['zeta_range_m']} m, Fz/mg in {out['fz_over_mg_range']}"
-                                             if free else ""))
+    log(f"[bench] {name}{' ' + label if label else ''}: {ms:.3f} ms/step ({out['ms_per_cg_iter']} ms per CG "
+        f"iteration; plain tank {out['base_ms_per_cg_iter']}), iters {iters}"
+        + (f", zeta in {out['zeta_range_m']} m, Fz/mg in {out['fz_over_mg_range']}" if free else ""))
     return out
 
 
-def run_cpu_baseline(wl, f0, dt, seconds: float):
-    """The oracle as it stands, single-threaded, for about `seconds`."""
+def run_cpu_baseline(wl, f0, steps: int):
+    """The oracle as it stands on the first `steps` steps of the workload from
+    its initial condition (each with the oracle's own CFL rule): on all host
+    cores (OpenMP build, static schedule), then on one thread."""
     from oracle import oracle as O
-    O.lib()
-    P = O.params(wl)
-    f, t, n, iters = f0, 0.0, 0, []
-    t0 = time.perf_counter()
-    while True:
-        f, st, rc = O.step(P, f, dt, t)
-        iters.append(st["iters"])
-        t += dt
-        n += 1
+    out = {}
+    for label, omp in (("all_cores", True), ("one_thread", False)):
+        O.use_openmp(omp)
+        O.lib()
+        P = O.params(wl)
+        f, t = f0, 0.0
+        iters = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dt = O.cfl_dt(P, f, wl.cfl, wl.dt_max)
+            f, st, rc = O.step(P, f, dt, t)
+            iters.append(st["iters"])
+            t += dt
         el = time.perf_counter() - t0
-        if el >= seconds or n >= wl.steps:
-            break
-    return {"value": round(wl.ncells * n / el / 1e6, 4), "unit": "Mcell-steps/s", "cores": 1,
-            "kind": "oracle", "sample": f"first {n} step(s) of the same workload from its initial "
-                                        f"condition, {el:.1f} s, one thread",
-            "cg_iters": iters, "host": host_cpu()}
+        out[label] = {"value": round(wl.ncells * steps / el / 1e6, 4), "seconds": round(el, 2),
+                      "cg_iters": iters}
+        log(f"[bench] cpu oracle ({label}): {out[label]['value']} Mcell-steps/s, {el:.1f} s for {steps} step(s)")
+    O.use_openmp(False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": out["all_cores"]["value"], "unit": "Mcell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {steps} step(s) of the same workload ({wl.nx}x{wl.ny}x{wl.nz}) from its "
+                      f"initial condition, FP64, OpenMP static schedule on {threads} threads; "
+                      f"{out['all_cores']['seconds']} s",
+            "one_thread": {**out["one_thread"], "cores": 1}, "all_cores": out["all_cores"], "host": host_cpu()}
 
 
 def host_cpu() -> str:
@@ -414,22 +452,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--projection-workload", default="c3,c4eval",
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--configs", default="c1,c2,c3",
+                    help="comma-separated tanks whose FP64 step is also timed; 'none' skips them")
+    ap.add_argument("--projection-workload", default="c5,c3,c4eval",
                     help="comma-separated workloads of the projection study (FP64 vs FP32 V-cycle vs learned "
                          "guess); 'none' skips it")
-    ap.add_argument("--projection-steps", type=int, default=20)
+    ap.add_argument("--projection-steps", type=int, default=10)
+    ap.add_argument("--side-workload", default="c2", help="tank of the free-heave, wave-tank and option studies")
     ap.add_argument("--fsi-workload", default="c2fsi",
-                    help="workload of the free-heave study (a free body on the main tank); 'none' skips it")
+                    help="workload of the free-heave study (a free body on the side tank); 'none' skips it")
     ap.add_argument("--nwt-workload", default="c2nwt",
-                    help="workload of the wave-tank study (the main grid with generation and damping zones); "
+                    help="workload of the wave-tank study (the side grid with generation and damping zones); "
                          "'none' skips it")
     ap.add_argument("--option-studies", default="consistent,cn3",
-                    help="comma-separated predictor options timed on the main workload: 'consistent' "
-                         "(consistent mass/momentum transport), 'cnN' (Crank-Nicolson viscous term by N "
-                         "Jacobi sweeps), or both joined by '+'; 'none' skips them")
+                    help="comma-separated predictor options timed on the side tank: 'consistent' "
+                         "(consistent mass/momentum transport), 'cnN' (Crank-Nicolson viscous term, N Jacobi "
+                         "sweeps per convergence check), or both joined by '+'; 'none' skips them")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2206_07732_amd", "weights", "guess_c4.npy"))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -448,25 +489,29 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
         log(f"[bench] copy calibration: 3 x {args.copy_calibration_mib} MiB device copies")
+    configs = None
+    if args.configs != "none":
+        steps = {"c1": 10, "c2": 20, "c3": 10}
+        configs = [config_line(c, steps.get(c, 10), 3) for c in args.configs.split(",")]
     study = None
     if args.projection_workload != "none":
         study = [projection_study(w, args.projection_steps, 2, args.weights)
                  for w in args.projection_workload.split(",")]
-    fsi = None
-    if args.fsi_workload != "none":
-        fsi = variant_study(args.fsi_workload, args.steps, args.warmup, r)
-    nwt = None
-    if args.nwt_workload != "none":
-        nwt = variant_study(args.nwt_workload, args.steps, args.warmup, r)
+    side = None
+    if args.fsi_workload != "none" or args.nwt_workload != "none" or args.option_studies != "none":
+        side = next((c for c in configs or [] if c["workload"].startswith(args.side_workload + ":")), None) \
+            or config_line(args.side_workload, 20, 3)
+    fsi = variant_study(args.fsi_workload, 20, 3, side) if args.fsi_workload != "none" else None
+    nwt = variant_study(args.nwt_workload, 20, 3, side) if args.nwt_workload != "none" else None
     opts = None
     if args.option_studies != "none":
-        opts = [variant_study(args.workload, args.steps, args.warmup, r, label=o, **option_overrides(o))
+        opts = [variant_study(args.side_workload, 20, 3, side, label=o, **option_overrides(o))
                 for o in args.option_studies.split(",")]
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(r["wl"], r["f0"], r["dt"], args.cpu_seconds)
-        log(f"[bench] cpu oracle {cpu['value']} Mcell-steps/s ({cpu['sample']})")
+        cpu = run_cpu_baseline(r["wl"], r["f0"], args.cpu_steps)
     out = {
         "metric": "Mcell-steps/s + projection time @1e-10 resid: FP64 MG-CG vs mixed-prec+learned",
         "value": round(r["value"], 3),
@@ -482,12 +527,14 @@ def main():
         "data": "synthetic",
         "config": r["config"],
         "cg_iters": r["iters"],
-        "projection": r["projection"],
+        "roofline": r["roofline"],
+        "step_roofline": r["step_roofline"],
+        "phases_ms": r["phases"],
+        "configs": configs,
         "projection_study": study,
         "fsi_study": fsi,
         "nwt_study": nwt,
         "option_study": opts,
-        "roofline": r["roofline"],
         "measured_ceilings": r["ceilings"],
         "cpu_baseline": cpu,
     }

@@ -52,7 +52,11 @@ typedef enum {
   NS_ENOCONV = -2,  /* projection hit max_iters before rtol; u and p hold the last iterate */
   NS_ENAN = -3,     /* a non-finite value appeared in the solve */
   NS_EHIP = -4,     /* a HIP runtime call failed */
-  NS_ESTATE = -5    /* call out of order (e.g. projection before momentum) */
+  NS_ESTATE = -5,   /* call out of order (e.g. projection before momentum) */
+  NS_EUNSTABLE = -6 /* the step left the scheme's stability bound: with consistent
+                       transport a carried face density came out <= 0, which
+                       happens once the outflow Courant number passes 1/2 (take
+                       dt from ns_cfl_dt); u and p are not updated */
 } ns_status;
 
 typedef enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 } ns_prec;   /* V-cycle precision   */
@@ -146,12 +150,17 @@ typedef struct {
    * half of it at t^n, half at the predicted velocity, each face solving
    *   D_f u*_f - 1/2 L(u*)_f = rhs_f
    * with D_f the implicit diagonal of the predictor and L the viscous
-   * operator.  The system is solved by this many point-Jacobi sweeps from the
-   * explicit predictor, u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f))/(D_f + 1/2 a_f),
-   * a_f the magnitude of L's diagonal; each sweep contracts the error by a
-   * factor of order nu dt/h^2.  Walls and the inlet keep their values.
-   * 0: explicit viscous term.  At most 64. */
+   * operator.  The system is solved by point-Jacobi sweeps from the explicit
+   * predictor, u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f))/(D_f + 1/2 a_f), a_f
+   * the magnitude of L's diagonal; walls and the inlet keep their values.
+   * cn_sweeps sweeps run between convergence checks: after each batch the
+   * largest change of the batch's last sweep over all faces is compared with
+   * cn_tol times the largest |u*|, and batches continue until it is below,
+   * at most 64 sweeps in all (then momentum_step returns NS_ENOCONV).  Each
+   * sweep contracts the error by a factor of order nu dt/h^2.  A check
+   * synchronises the stream once.  0: explicit viscous term.  At most 64. */
   int cn_sweeps;
+  double cn_tol;               /* > 0 when cn_sweeps > 0, e.g. 1e-10            */
 } ns_params;
 
 /* The caller's state arrays (device, FP64, layouts above); read and written
@@ -173,6 +182,14 @@ typedef struct {
   double true_rel_resid;   /* ||b - A p|| / ||b|| recomputed at exit                  */
   double ms;               /* wall time of the call, stream-synchronised (ms)         */
   int x0_fallback;         /* 1 if the learned guess was non-finite and p_prev was used */
+  int cn_sweeps;           /* Crank-Nicolson sweeps of the step's predictor (0: explicit) */
+  /* Device time per phase (ms) while ns_phase_timing is on, else zeros:
+   * [0] level set (advection + reinitialisation), [1] properties and
+   * predictor, [2] projection set-up (right-hand side, initial guess with
+   * any network inference), [3] the CG solve, [4] velocity correction (with
+   * the wave tank's zones and free bodies' forces), [5] the whole step;
+   * [0], [1] and [5] are filled by ns_step only; [6], [7] are 0. */
+  double t_ms[8];
 } ns_stats;
 
 /* Internal arrays a caller may inspect or fill through ns_buffer (device
@@ -358,6 +375,21 @@ ns_status ns_features(ns_ctx* ctx, double dt, const double* p_prev, float* feat4
 /* Training target t = (p - p_prev) / P0 of the solved pressure fields.p
  * (device FP64 p_prev, device FP32 t). */
 ns_status ns_target(ns_ctx* ctx, const double* p_prev, float* t);
+
+/* Time step of the CFL rule (Sec. "Time stepping scheme": the paper's runs
+ * keep the Courant number at or below 0.5) on the current fields:
+ *   *dt_out = min(cfl h / m, dt_max),  m = max over cells of |u_c| + |v_c| + |w_c|,
+ * each cell velocity the mean of its two faces (dt_max when m = 0).  The
+ * maximum is taken on the device by an order-independent reduction, so the
+ * result does not depend on the launch.  dt_out is host memory; synchronises
+ * the stream.  NS_EINVAL unless cfl > 0 and dt_max > 0; NS_ENAN if a
+ * velocity is not finite. */
+ns_status ns_cfl_dt(ns_ctx* ctx, double cfl, double dt_max, double* dt_out);
+
+/* Per-phase device timing of the steps (ns_stats.t_ms): on != 0 records HIP
+ * events between the phases of every later call (host-API objects, created
+ * on the first use; no device memory); 0 stops it. */
+ns_status ns_phase_timing(ns_ctx* ctx, int on);
 
 /* Number of multigrid levels for these sizes. */
 int ns_num_levels(int nx, int ny, int nz);

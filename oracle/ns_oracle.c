@@ -31,6 +31,16 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Built with -fopenmp (the CPU-baseline timing build only) the outer loops of
+ * the grid passes are split over the host's cores, each thread a contiguous
+ * block of planes; the dot products then sum per thread.  The build the tests
+ * use has no OpenMP and runs every loop in order on one thread. */
+#ifdef _OPENMP
+#define ORC_PAR _Pragma("omp parallel for schedule(static)")
+#else
+#define ORC_PAR
+#endif
+
 /* --------------------------------------------------------------------------
  * indexing with clamped (nearest-interior) ghosts
  * ------------------------------------------------------------------------ */
@@ -134,6 +144,7 @@ void orc_levelset_advect(const orc_params* P, const double* sigma, const double*
                          const double* w, double dt, double* sigma_out) {
   const double* vel[3] = {u, v, w};
   const int nx = P->nx, ny = P->ny, nz = P->nz;
+  ORC_PAR
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -170,6 +181,7 @@ void orc_reinit(const orc_params* P, const double* sigma0, double* sigma_out) {
   double* nxt = (double*)malloc(n * sizeof(double));
   memcpy(cur, sigma0, n * sizeof(double));
   for (int it = 0; it < P->reinit_iters; ++it) {
+    ORC_PAR
     for (int k = 0; k < nz; ++k)
       for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -212,6 +224,7 @@ void orc_properties(const orc_params* P, const double* sigma, double t, double* 
                     double* mu, double* chi) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
   const double h = P->h, eps = P->n_cells * h;
+  ORC_PAR
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -461,7 +474,7 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
   double* out[3] = {us, vs, ws};
   /* Crank-Nicolson: half the viscous term at t^n goes to the right-hand side */
   const int cn = P->crank_nicolson != 0;
-  g_flags = 0;
+  int flags = 0;
   const double wv = cn ? 0.5 : 1.0;
   double* rhsA[3] = {NULL, NULL, NULL};
   double* DA[3] = {NULL, NULL, NULL};
@@ -474,6 +487,9 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
   for (int c = 0; c < 3; ++c) {
     int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
     int ec[3] = {c == 0, c == 1, c == 2};
+    #ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : flags)
+#endif
     for (int k = 0; k < mz; ++k)
       for (int j = 0; j < my; ++j)
         for (int i = 0; i < mx; ++i) {
@@ -542,7 +558,7 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
             double rbf = r0 - dt * mflux / h;
             /* a transported density at or below zero leaves the projection
              * operator indefinite: the step is outside the scheme's bound */
-            if (!(rbf > 0.0)) g_flags |= 1;
+            if (!(rbf > 0.0)) flags |= 1;
             double num = r0 * uf / dt - conv / h + wv * visc + grav + pen * ub;
             double den = rbf / dt + pen + damp;
             out[c][f] = cn ? (num + 0.5 * visc) / den : num / den;
@@ -556,6 +572,7 @@ static void momentum_impl(const orc_params* P, const double* u, const double* v,
           if (cn) rhsA[c][f] = num, DA[c][f] = den;
         }
   }
+  g_flags = flags;
   if (cn) {
     cn_solve(P, mu, rhsA, DA, out);
     for (int c = 0; c < 3; ++c) {
@@ -585,6 +602,7 @@ void orc_face_beta(const orc_params* P, const double* sigma, double t_np1, doubl
   for (int c = 0; c < 3; ++c) {
     int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
     int ec[3] = {c == 0, c == 1, c == 2};
+    ORC_PAR
     for (int k = 0; k < mz; ++k)
       for (int j = 0; j < my; ++j)
         for (int i = 0; i < mx; ++i) {
@@ -615,6 +633,7 @@ void orc_face_beta_rho(const orc_params* P, const double* rbx, const double* rby
   for (int c = 0; c < 3; ++c) {
     int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
     int ec[3] = {c == 0, c == 1, c == 2};
+    ORC_PAR
     for (int k = 0; k < mz; ++k)
       for (int j = 0; j < my; ++j)
         for (int i = 0; i < mx; ++i) {
@@ -635,6 +654,7 @@ void orc_face_beta_rho(const orc_params* P, const double* rbx, const double* rby
 void orc_rhs(const orc_params* P, const double* us, const double* vs, const double* ws, double dt,
              double* b) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
+  ORC_PAR
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -736,6 +756,9 @@ void orc_vcycle(const orc_params* P, const double* bx, const double* by, const d
 
 static double dot(const double* a, const double* b, size_t n) {
   double s = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(+ : s)
+#endif
   for (size_t c = 0; c < n; ++c) s += a[c] * b[c];
   return s;
 }
@@ -782,6 +805,7 @@ int orc_pcg(const orc_params* P, const double* bx, const double* by, const doubl
     while (it < P->max_iters) {
       orc_apply_A(nx, ny, nz, h, bx, by, bz, d, q);
       double alpha = rho / dot(d, q, n);
+      ORC_PAR
       for (size_t c = 0; c < n; ++c) {
         x[c] += alpha * d[c];
         r[c] -= alpha * q[c];
@@ -808,6 +832,7 @@ int orc_pcg(const orc_params* P, const double* bx, const double* by, const doubl
       double rzn = dot(r, zn, n);
       double rzo = dot(r, z, n);
       double beta = (rzn - rzo) / rho;
+      ORC_PAR
       for (size_t c = 0; c < n; ++c) d[c] = zn[c] + beta * d[c];
       rho = rzn;
       double* t = z;
@@ -844,6 +869,7 @@ void orc_correct(const orc_params* P, const double* us, const double* vs, const 
   for (int c = 0; c < 3; ++c) {
     int mx = P->nx + (c == 0), my = P->ny + (c == 1), mz = P->nz + (c == 2);
     int ec[3] = {c == 0, c == 1, c == 2};
+    ORC_PAR
     for (int k = 0; k < mz; ++k)
       for (int j = 0; j < my; ++j)
         for (int i = 0; i < mx; ++i) {
@@ -945,6 +971,9 @@ double orc_cfl_dt(const orc_params* P, const double* u, const double* v, const d
                   double dt_max) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
   double m = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(max : m)
+#endif
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -952,7 +981,7 @@ double orc_cfl_dt(const orc_params* P, const double* u, const double* v, const d
         double vc = 0.5 * fabs(facev(P, 1, v, i, j, k) + facev(P, 1, v, i, j + 1, k));
         double wc = 0.5 * fabs(facev(P, 2, w, i, j, k) + facev(P, 2, w, i, j, k + 1));
         double s = uc + vc + wc;
-        if (s > m) m = s;
+        if (s > m) m = s;   /* a maximum: the same in any order */
       }
   if (!(m > 0.0)) return dt_max;
   double dt = cfl * P->h / m;

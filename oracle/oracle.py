@@ -15,16 +15,20 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libns_oracle.so")
+LIB_OMP = os.path.join(HERE, "libns_oracle_omp.so")
 SRC = os.path.join(HERE, "ns_oracle.c")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-ffp-contract=off",
-               SRC, "-o", LIB + ".tmp", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
+    """Compile the oracle with gcc (no FMA contraction, no fast-math): the
+    single-threaded library the tests use, and beside it the same source with
+    OpenMP for timing the oracle on all host cores."""
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-ffp-contract=off", *extra,
+                   SRC, "-o", out + ".tmp", "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(out + ".tmp", out)
     return LIB
 
 
@@ -60,14 +64,25 @@ class Stats(C.Structure):
 
 
 _lib = None
+_path = LIB
+
+
+def use_openmp(on: bool) -> None:
+    """Run the wrappers below on the OpenMP build (all host cores; dot
+    products then sum per thread, so results differ from the single-threaded
+    build in the last bits) or on the single-threaded one (the default)."""
+    global _lib, _path
+    path = LIB_OMP if on else LIB
+    if path != _path:
+        _path, _lib = path, None
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        if not os.path.exists(_path):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(_path)
         dp = C.POINTER(C.c_double)
         P = C.POINTER(Params)
         S = C.POINTER(Stats)

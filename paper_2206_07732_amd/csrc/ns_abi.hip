@@ -31,6 +31,11 @@ struct ns_ctx {
   double* cn_rhs[3];  // Crank-Nicolson viscous term: right-hand side per face,
   double* cn_diag[3]; // implicit diagonal (0 on walls and the inlet),
   double* cn_tmp[3];  // and the second iterate of the Jacobi sweeps
+  double* cnpart;     // per-block (largest change, largest |u*|) of a checked sweep
+  int last_cn;        // sweeps the last predictor ran
+  bool phase_on;      // ns_phase_timing
+  bool ph_step;       // ns_step recorded the events of its first two phases
+  hipEvent_t ph_ev[6];
   double *b, *r, *z, *zn, *d, *d2, *q;
   double *partials;
   double *scal;
@@ -151,6 +156,8 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
   if (P->n_waves < 0 || P->n_waves > 64) return snprintf(why, nwhy, "n_waves must be 0..64"), false;
   if (P->consistent != 0 && P->consistent != 1) return snprintf(why, nwhy, "consistent must be 0 or 1"), false;
   if (P->cn_sweeps < 0 || P->cn_sweeps > 64) return snprintf(why, nwhy, "cn_sweeps must be 0..64"), false;
+  if (P->cn_sweeps > 0 && !(P->cn_tol > 0.0 && std::isfinite(P->cn_tol)))
+    return snprintf(why, nwhy, "cn_tol must be finite and > 0 with cn_sweeps > 0"), false;
   if ((P->gen_len > 0.0 || P->damp_len > 0.0) && !(P->depth > 0.0 && std::isfinite(P->depth)))
     return snprintf(why, nwhy, "a wave tank with relaxation zones needs depth > 0"), false;
   for (int q = 0; q < P->n_waves; ++q) {
@@ -236,6 +243,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
   double* cn[9] = {};   // Crank-Nicolson: rhs, diagonal and second iterate of u, v, w
   if (P->cn_sweeps > 0)
     for (int q = 0; q < 9; ++q) cn[q] = cv.take<double>(q % 3 == 0 ? nu : q % 3 == 1 ? nv : nw);
+  double* cnpart = P->cn_sweeps > 0 ? cv.take<double>(2 * (size_t)cn_part_blocks(n0)) : nullptr;
   double* chi = cv.take<double>(nc);
   double* b = cv.take<double>(nc);
   double* r = cv.take<double>(nc);
@@ -353,6 +361,7 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       X->cn_diag[c] = cn[3 + c];
       X->cn_tmp[c] = cn[6 + c];
     }
+    X->cnpart = cnpart;
     X->chi = chi;
     X->b = b;
     X->r = r;
@@ -773,6 +782,9 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   ns_status s = precond_rho(z);
   if (s != NS_OK) return s;
   HIPCHK(X, hipEventSynchronize(X->ev_rr));
+  if (X->host[S_FLAGS] != 0.0)
+    return fail(X, NS_EUNSTABLE, "a carried face density came out <= 0: the step's outflow Courant number is "
+                "above the limited transport's bound of 1/2 (take dt from the CFL rule)");
   const double bb = host_total(X, 2, 1, S_BB);
   double rr = host_total(X, 2, 0, S_RR);
   if (!std::isfinite(bb) || !std::isfinite(rr)) return fail(X, NS_ENAN, "non-finite right-hand side or guess");
@@ -937,6 +949,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     ns_destroy(X);
     return NS_EHIP;
   }
+  for (int q = 0; q < S_COUNT; ++q) X->host[q] = 0.0;
   // small grids: the reductions the host alone reads leave their per-block
   // partials in host memory, and the host sums them (no finalize launch)
   X->fpart = nullptr;
@@ -998,10 +1011,38 @@ void ns_destroy(ns_ctx* X) {
   for (int q = 0; q < X->ngs; ++q) (void)hipGraphExecDestroy(X->gs[q].exec);
   if (X->cap_st) (void)hipStreamDestroy(X->cap_st);
   if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
+  for (int q = 0; q < 6; ++q)
+    if (X->ph_ev[q]) (void)hipEventDestroy(X->ph_ev[q]);
   if (X->host) (void)hipHostFree(X->host);
   if (X->hpart) (void)hipHostFree(X->hpart);
   if (X->fpart) (void)hipHostFree(X->fpart);
   delete X;
+}
+
+ns_status ns_phase_timing(ns_ctx* X, int on) {
+  if (!X) return NS_EINVAL;
+  if (on && !X->ph_ev[0])
+    for (int q = 0; q < 6; ++q) HIPCHK(X, hipEventCreate(&X->ph_ev[q]));
+  X->phase_on = on != 0;
+  return NS_OK;
+}
+
+ns_status ns_cfl_dt(ns_ctx* X, double cfl, double dt_max, double* dt_out) {
+  if (!X || !dt_out) return NS_EINVAL;
+  if (!(cfl > 0.0) || !(dt_max > 0.0)) return fail(X, NS_EINVAL, "cfl and dt_max must be > 0");
+  launch_cfl_max(X->phys, X->F.u, X->F.v, X->F.w, X->partials, X->host_dev + S_CFL, X->st);
+  HIPCHK(X, hipGetLastError());
+  ns_status s = wait_host(X);
+  if (s != NS_OK) return s;
+  const double m = X->host[S_CFL];
+  if (!std::isfinite(m)) return fail(X, NS_ENAN, "non-finite velocity in the CFL rule");
+  if (!(m > 0.0)) {
+    *dt_out = dt_max;
+    return NS_OK;
+  }
+  const double dt = cfl * X->P.h / m;
+  *dt_out = dt < dt_max ? dt : dt_max;
+  return NS_OK;
 }
 
 ns_status ns_set_launch_mode(ns_ctx* X, int mode) {
@@ -1199,17 +1240,44 @@ ns_status momentum_step(ns_ctx* X, double dt, double t_np1) {
   Level& L0 = X->lev[0];
   // Crank-Nicolson: the predictor writes the first iterate and the sweeps
   // alternate between u* and a second set, starting in the one that leaves
-  // the last iterate in u*
+  // the first batch's last iterate in u*
   const int S = X->P.cn_sweeps;
   double* us3[3] = {X->us, X->vs, X->ws};
   double** cur = (S % 2) ? X->cn_tmp : us3;
   double** nxt = (S % 2) ? us3 : X->cn_tmp;
+  X->host[S_FLAGS] = 0.0;   // the consistent predictor stores 1 here on a density <= 0
   launch_momentum(ph, X->F.u, X->F.v, X->F.w, X->rho, X->rfl, X->mu, X->chi, X->P.consistent ? X->rho_prev : nullptr,
                   dt, t_np1, cur[0], cur[1], cur[2], L0.bx, L0.by, L0.bz, L0.bxf, L0.byf, L0.bzf,
-                  S > 0 ? X->cn_rhs : nullptr, S > 0 ? X->cn_diag : nullptr, st);
-  for (int s = 0; s < S; ++s) {
-    launch_cn_sweep(ph, cur[0], cur[1], cur[2], X->mu, X->cn_rhs, X->cn_diag, nxt[0], nxt[1], nxt[2], st);
-    std::swap(cur, nxt);
+                  S > 0 ? X->cn_rhs : nullptr, S > 0 ? X->cn_diag : nullptr, X->host_dev + S_FLAGS, st);
+  X->last_cn = 0;
+  X->have_beta = false;
+  if (S > 0) {
+    // batches of S sweeps, the last of each measuring its largest change,
+    // until that change is below cn_tol of the largest |u*|
+    constexpr int kCnMaxSweeps = 64;
+    for (;;) {
+      for (int q = 0; q < S; ++q) {
+        const bool last = q == S - 1;
+        launch_cn_sweep(ph, cur[0], cur[1], cur[2], X->mu, X->cn_rhs, X->cn_diag, nxt[0], nxt[1], nxt[2],
+                        last ? X->cnpart : nullptr, last ? X->host_dev + S_CNDU : nullptr, st);
+        std::swap(cur, nxt);
+      }
+      X->last_cn += S;
+      HIPCHK(X, hipGetLastError());
+      ns_status s = wait_host(X);
+      if (s != NS_OK) return s;
+      const double du = X->host[S_CNDU], um = X->host[S_CNU];
+      if (!std::isfinite(du) || !std::isfinite(um)) return fail(X, NS_ENAN, "non-finite Crank-Nicolson iterate");
+      if (du <= X->P.cn_tol * um) break;
+      if (X->last_cn + S > kCnMaxSweeps)
+        return fail(X, NS_ENOCONV, "Crank-Nicolson sweeps did not converge: last change %.3e of max |u*| %.3e "
+                    "after %d sweeps", du, um, X->last_cn);
+    }
+    if (cur != us3) {   // an odd number of extra batches left the iterate in the second set
+      launch_copy(cur[0], X->us, X->nu, st);
+      launch_copy(cur[1], X->vs, X->nv, st);
+      launch_copy(cur[2], X->ws, X->nw, st);
+    }
   }
   X->have_rho_n = X->P.consistent != 0;
   HIPCHK(X, hipGetLastError());
@@ -1224,6 +1292,10 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   const double t0 = now_ms();
   const Phys& ph = X->phys;
   hipStream_t st = X->st;
+  const bool timed = X->phase_on;
+  const bool whole = timed && X->ph_step;
+  X->ph_step = false;
+  if (timed) HIPCHK(X, hipEventRecord(X->ph_ev[2], st));
   launch_rhs(ph, X->us, X->vs, X->ws, dt, X->b, st);
   int fallback = 0;
   if (X->P.x0 == NS_X0_ZERO) {
@@ -1244,13 +1316,16 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
     }
   }
   ns_stats S{};
+  if (timed) HIPCHK(X, hipEventRecord(X->ph_ev[3], st));
   ns_status s = pcg(X, &S);
   S.x0_fallback = fallback;
+  S.cn_sweeps = X->last_cn;
   if (s != NS_OK && s != NS_ENOCONV) {
     if (stats) *stats = S;
     return s;
   }
   const Level& L0 = X->lev[0];
+  if (timed) HIPCHK(X, hipEventRecord(X->ph_ev[4], st));
   launch_correct(ph, X->us, X->vs, X->ws, X->F.p, L0.bx, L0.by, L0.bz, dt, X->F.u, X->F.v, X->F.w, st);
   // the wave tank's relaxation zones, at the time of the step's properties
   launch_relax(ph, X->t_props, X->F.sigma, X->F.u, X->F.v, X->F.w, st);
@@ -1264,8 +1339,21 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   if (X->nfree > 0 && free_forces_queue(X, nb) != 0)
     return fail(X, NS_EHIP, "hydrodynamic force: launch or copy failed");
   HIPCHK(X, hipGetLastError());
+  if (timed) HIPCHK(X, hipEventRecord(X->ph_ev[5], st));
   HIPCHK(X, hipStreamSynchronize(st));
   if (X->nfree > 0) free_forces_sum(X, nb);
+  if (timed) {
+    // [2] set-up, [3] CG, [4] correction; from ns_step also [0], [1] and the whole step
+    float ms;
+    for (int q = whole ? 0 : 2; q < 5; ++q) {
+      HIPCHK(X, hipEventElapsedTime(&ms, X->ph_ev[q], X->ph_ev[q + 1]));
+      S.t_ms[q] = ms;
+    }
+    if (whole) {
+      HIPCHK(X, hipEventElapsedTime(&ms, X->ph_ev[0], X->ph_ev[5]));
+      S.t_ms[5] = ms;
+    }
+  }
   S.ms = now_ms() - t0;
   if (stats) *stats = S;
   return s;
@@ -1282,9 +1370,12 @@ ns_status ns_step(ns_ctx* X, double dt, double t_n, ns_stats* stats) {
     launch_props(X->phys, X->F.sigma, t_n, X->rho, X->rfl, X->mu, X->chi, X->st);
     X->have_rho_n = true;
   }
+  if (X->phase_on) HIPCHK(X, hipEventRecord(X->ph_ev[0], X->st));
   s = levelset_advect_reinit(X, dt);
   if (s != NS_OK) return s;
+  if (X->phase_on) HIPCHK(X, hipEventRecord(X->ph_ev[1], X->st));
   if ((s = momentum_step(X, dt, t_n + dt)) != NS_OK) return s;
+  X->ph_step = X->phase_on;
   ns_stats S{};
   s = projection_solve(X, dt, &S);
   S.ms = now_ms() - t0;

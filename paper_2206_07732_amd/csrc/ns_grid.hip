@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
                                                   const double* __restrict__ rho_n, double dt, double t1,
                                                   double* __restrict__ out, double* __restrict__ beta,
                                                   float* __restrict__ betaf, double* __restrict__ cn_rhs,
-                                                  double* __restrict__ cn_diag) {
+                                                  double* __restrict__ cn_diag, double* __restrict__ flag) {
   const Dims n = P.n;
   constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
   const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
@@ -411,6 +411,9 @@ __global__ void __launch_bounds__(256) k_momentum(Phys P, const double* __restri
   if constexpr (CONS) {
     const double r0 = 0.5 * (cv(rho_n, n, i - ci, j - cj, k - ck) + cv(rho_n, n, i, j, k));
     const double rb = r0 - dt * mflux * ih;
+    // a carried density at or below zero makes the projection operator
+    // indefinite: the step is past the transport's Courant bound
+    if (!(rb > 0.0)) *flag = 1.0;
     const double num = r0 * uf / dt - conv * ih + wv * visc + grav + pen * ub;
     const double den = rb / dt + pen + damp;
     out[f] = cn_rhs ? (num + 0.5 * visc) / den : num / den;
@@ -454,18 +457,40 @@ __device__ __forceinline__ void sweep_dir(const double* __restrict__ uc, const d
   a += ad;
 }
 
+// Largest value over a 256-thread block (64 x 4 or 64 x 1 x 4), two
+// quantities at once; thread 0 returns them.
+__device__ __forceinline__ void block_max2(double& a, double& b) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a = fmax(a, __shfl_down(a, off, 64));
+    b = fmax(b, __shfl_down(b, off, 64));
+  }
+  __shared__ double sm[4][2];
+  const int tid = threadIdx.x + 64 * (threadIdx.y + blockDim.y * threadIdx.z);
+  if ((tid & 63) == 0) {
+    sm[tid >> 6][0] = a;
+    sm[tid >> 6][1] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a = fmax(fmax(sm[0][0], sm[1][0]), fmax(sm[2][0], sm[3][0]));
+    b = fmax(fmax(sm[0][1], sm[1][1]), fmax(sm[2][1], sm[3][1]));
+  }
+}
+
 // One point-Jacobi sweep of the Crank-Nicolson viscous system of component C,
 //   D_f u_f - 1/2 L(u)_f = rhs_f,
 // from the iterate (u, v, w): u_f <- (rhs_f + 1/2 (L(u)_f + a_f u_f)) / (D_f + 1/2 a_f),
 // a_f the magnitude of L's diagonal; a face with D_f = 0 (a wall or the
-// inlet) keeps its value.
+// inlet) keeps its value.  With part, the block's largest |u_new - u| and
+// largest |u_new| over the faces it updates go to part[2 lin], part[2 lin + 1].
 template <int C>
 __global__ void __launch_bounds__(256) k_cn_sweep(Phys P, const double* __restrict__ u,
                                                   const double* __restrict__ v,
                                                   const double* __restrict__ w,
                                                   const double* __restrict__ mu,
                                                   const double* __restrict__ rhs,
-                                                  const double* __restrict__ diag, double* __restrict__ out) {
+                                                  const double* __restrict__ diag, double* __restrict__ out,
+                                                  double* __restrict__ part) {
   const Dims n = P.n;
   constexpr int ci = (C == 0), cj = (C == 1), ck = (C == 2);
   const int mx = n.nx + ci, my = n.ny + cj, mz = n.nz + ck;
@@ -473,21 +498,85 @@ __global__ void __launch_bounds__(256) k_cn_sweep(Phys P, const double* __restri
   const int i = tl.x * blockDim.x + threadIdx.x;
   const int j = tl.y * blockDim.y + threadIdx.y;
   const int k = tl.z * blockDim.z + threadIdx.z;
-  if (i >= mx || j >= my || k >= mz) return;
-  const size_t f = i + (size_t)mx * (j + (size_t)my * k);
-  const double* uc = (C == 0) ? u : (C == 1) ? v : w;
-  const double uf = uc[f];
-  const double dg = diag[f];
-  if (dg == 0.0) {
-    out[f] = uf;
-    return;
+  double du = 0.0, um = 0.0;
+  if (i < mx && j < my && k < mz) {
+    const size_t f = i + (size_t)mx * (j + (size_t)my * k);
+    const double* uc = (C == 0) ? u : (C == 1) ? v : w;
+    const double uf = uc[f];
+    const double dg = diag[f];
+    double nv = uf;
+    if (dg != 0.0) {
+      const double ih = 1.0 / P.h;
+      double L = 0.0, a = 0.0;
+      sweep_dir<C, 0>(uc, u, mu, n, i, j, k, uf, ih, L, a);
+      sweep_dir<C, 1>(uc, v, mu, n, i, j, k, uf, ih, L, a);
+      sweep_dir<C, 2>(uc, w, mu, n, i, j, k, uf, ih, L, a);
+      nv = (rhs[f] + 0.5 * (L + a * uf)) / (dg + 0.5 * a);
+      du = fabs(nv - uf);
+      um = fabs(nv);
+    }
+    out[f] = nv;
   }
-  const double ih = 1.0 / P.h;
-  double L = 0.0, a = 0.0;
-  sweep_dir<C, 0>(uc, u, mu, n, i, j, k, uf, ih, L, a);
-  sweep_dir<C, 1>(uc, v, mu, n, i, j, k, uf, ih, L, a);
-  sweep_dir<C, 2>(uc, w, mu, n, i, j, k, uf, ih, L, a);
-  out[f] = (rhs[f] + 0.5 * (L + a * uf)) / (dg + 0.5 * a);
+  if (part) {   // uniform over the grid
+    block_max2(du, um);
+    if (threadIdx.x + threadIdx.y + threadIdx.z == 0) {
+      part[2 * (size_t)tl.lin] = du;
+      part[2 * (size_t)tl.lin + 1] = um;
+    }
+  }
+}
+
+// The CFL rule's per-block maximum of |u_c| + |v_c| + |w_c|, each cell
+// velocity the mean of its two faces; a value that is not finite counts as
+// infinite (a maximum would otherwise drop a NaN).
+__global__ void __launch_bounds__(256) k_cfl(Phys P, const double* __restrict__ u, const double* __restrict__ v,
+                                             const double* __restrict__ w, double* __restrict__ partials) {
+  const Dims n = P.n;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k = tl.z * blockDim.z + threadIdx.z;
+  double m = 0.0, unused = 0.0;
+  if (i < n.nx && j < n.ny && k < n.nz) {
+    const size_t sxy = (size_t)n.nx * n.ny;
+    const size_t c = i + (size_t)n.nx * j + sxy * k;
+    const size_t fu = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+    const size_t fvv = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+    const double uc = 0.5 * fabs(u[fu] + u[fu + 1]);
+    const double vc = 0.5 * fabs(v[fvv] + v[fvv + n.nx]);
+    const double wc = 0.5 * fabs(w[c] + w[c + sxy]);
+    const double sum = (uc + vc) + wc;
+    m = isfinite(sum) ? sum : INFINITY;
+  }
+  block_max2(m, unused);
+  if (threadIdx.x + threadIdx.y + threadIdx.z == 0) partials[tl.lin] = m;
+}
+
+// out[q] = max over p of partials[K p + q], q < K (one 1024-thread block)
+template <int K>
+__global__ void __launch_bounds__(1024) k_max_finalize(const double* __restrict__ partials, int nparts,
+                                                       double* __restrict__ out) {
+  double m[2] = {0.0, 0.0};
+  for (int p = threadIdx.x; p < nparts; p += 1024)
+#pragma unroll
+    for (int q = 0; q < K; ++q) m[q] = fmax(m[q], partials[(size_t)K * p + q]);
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < K; ++q) m[q] = fmax(m[q], __shfl_down(m[q], off, 64));
+  __shared__ double sm[16][2];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < K; ++q) sm[wid][q] = m[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[2] = {0.0, 0.0};
+    for (int w = 0; w < 16; ++w)
+#pragma unroll
+      for (int q = 0; q < K; ++q) r[q] = fmax(r[q], sm[w][q]);
+#pragma unroll
+    for (int q = 0; q < K; ++q) out[q] = r[q];
+  }
 }
 
 // b = -div_h(u*) / dt
@@ -781,7 +870,7 @@ void launch_momentum(const Phys& P, const double* u, const double* v, const doub
                      const double* rho, const double* rfl, const double* mu, const double* chi,
                      const double* rho_n, double dt, double t1, double* us, double* vs, double* ws, double* bx,
                      double* by, double* bz, float* bxf, float* byf, float* bzf, double* const* cn_rhs,
-                     double* const* cn_diag, hipStream_t st) {
+                     double* const* cn_diag, double* flag, hipStream_t st) {
   const Dims n = P.n;
   Geo gx = geo3(n.nx + 1, n.ny, n.nz);
   Geo gy = geo3(n.nx, n.ny + 1, n.nz);
@@ -792,30 +881,53 @@ void launch_momentum(const Phys& P, const double* u, const double* v, const doub
     for (int c = 0; c < 3; ++c) r[c] = cn_rhs[c], dg[c] = cn_diag[c];
   if (rho_n) {
     hipLaunchKernelGGL((k_momentum<0, true>), gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
-                       t1, us, bx, bxf, r[0], dg[0]);
+                       t1, us, bx, bxf, r[0], dg[0], flag);
     hipLaunchKernelGGL((k_momentum<1, true>), gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
-                       t1, vs, by, byf, r[1], dg[1]);
+                       t1, vs, by, byf, r[1], dg[1], flag);
     hipLaunchKernelGGL((k_momentum<2, true>), gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
-                       t1, ws, bz, bzf, r[2], dg[2]);
+                       t1, ws, bz, bzf, r[2], dg[2], flag);
     return;
   }
   hipLaunchKernelGGL((k_momentum<0, false>), gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
-                     t1, us, bx, bxf, r[0], dg[0]);
+                     t1, us, bx, bxf, r[0], dg[0], flag);
   hipLaunchKernelGGL((k_momentum<1, false>), gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
-                     t1, vs, by, byf, r[1], dg[1]);
+                     t1, vs, by, byf, r[1], dg[1], flag);
   hipLaunchKernelGGL((k_momentum<2, false>), gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
-                     t1, ws, bz, bzf, r[2], dg[2]);
+                     t1, ws, bz, bzf, r[2], dg[2], flag);
 }
 
 void launch_cn_sweep(const Phys& P, const double* u, const double* v, const double* w, const double* mu,
-                     double* const* rhs, double* const* diag, double* uo, double* vo, double* wo, hipStream_t st) {
+                     double* const* rhs, double* const* diag, double* uo, double* vo, double* wo, double* part,
+                     double* out2, hipStream_t st) {
   const Dims n = P.n;
   Geo gx = geo3(n.nx + 1, n.ny, n.nz);
   Geo gy = geo3(n.nx, n.ny + 1, n.nz);
   Geo gz = geo3(n.nx, n.ny, n.nz + 1);
-  hipLaunchKernelGGL(k_cn_sweep<0>, gx.grid, gx.block, 0, st, P, u, v, w, mu, rhs[0], diag[0], uo);
-  hipLaunchKernelGGL(k_cn_sweep<1>, gy.grid, gy.block, 0, st, P, u, v, w, mu, rhs[1], diag[1], vo);
-  hipLaunchKernelGGL(k_cn_sweep<2>, gz.grid, gz.block, 0, st, P, u, v, w, mu, rhs[2], diag[2], wo);
+  const size_t bx = (size_t)gx.grid.x * gx.grid.y * gx.grid.z, by = (size_t)gy.grid.x * gy.grid.y * gy.grid.z;
+  const size_t bz = (size_t)gz.grid.x * gz.grid.y * gz.grid.z;
+  hipLaunchKernelGGL(k_cn_sweep<0>, gx.grid, gx.block, 0, st, P, u, v, w, mu, rhs[0], diag[0], uo, part);
+  hipLaunchKernelGGL(k_cn_sweep<1>, gy.grid, gy.block, 0, st, P, u, v, w, mu, rhs[1], diag[1], vo,
+                     part ? part + 2 * bx : nullptr);
+  hipLaunchKernelGGL(k_cn_sweep<2>, gz.grid, gz.block, 0, st, P, u, v, w, mu, rhs[2], diag[2], wo,
+                     part ? part + 2 * (bx + by) : nullptr);
+  if (part)
+    hipLaunchKernelGGL(k_max_finalize<2>, dim3(1), dim3(1024), 0, st, part, (int)(bx + by + bz), out2);
+}
+
+int cn_part_blocks(const Dims& n) {
+  Geo gx = geo3(n.nx + 1, n.ny, n.nz);
+  Geo gy = geo3(n.nx, n.ny + 1, n.nz);
+  Geo gz = geo3(n.nx, n.ny, n.nz + 1);
+  return (int)((size_t)gx.grid.x * gx.grid.y * gx.grid.z + (size_t)gy.grid.x * gy.grid.y * gy.grid.z +
+               (size_t)gz.grid.x * gz.grid.y * gz.grid.z);
+}
+
+void launch_cfl_max(const Phys& P, const double* u, const double* v, const double* w, double* partials,
+                    double* out, hipStream_t st) {
+  Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
+  const int nb = (int)(g.grid.x * g.grid.y * g.grid.z);
+  hipLaunchKernelGGL(k_cfl, g.grid, g.block, 0, st, P, u, v, w, partials);
+  hipLaunchKernelGGL(k_max_finalize<1>, dim3(1), dim3(1024), 0, st, partials, nb, out);
 }
 
 void launch_rhs(const Phys& P, const double* us, const double* vs, const double* ws, double dt,

@@ -90,7 +90,11 @@ enum ScalIdx {
   S_BETA = 4,
   S_DQ = 5,     // <d, A d>
   S_TRR = 6,    // ||b - A x||^2 recomputed
+  S_CFL = 7,    // max over cells of |u_c| + |v_c| + |w_c| (the CFL rule)
   S_DIAG = 8,   // 4 diagnostics
+  S_FLAGS = 12, // set to 1 by the predictor when a carried face density is <= 0
+  S_CNDU = 13,  // Crank-Nicolson: largest change of the last sweep
+  S_CNU = 14,   //   and the largest |u*| it produced
   S_COUNT = 16
 };
 
@@ -150,14 +154,25 @@ void launch_reinit(const Phys& P, const double* s0, const double* cur, double* n
 void launch_copy(const double* src, double* dst, size_t n, hipStream_t st);
 void launch_props(const Phys& P, const double* sigma, double t, double* rho, double* rfl, double* mu,
                   double* chi, hipStream_t st);
+// rho_n set: the consistent form, which stores 1.0 to *flag (device address of
+// host-mapped memory) when a carried face density comes out <= 0
 void launch_momentum(const Phys& P, const double* u, const double* v, const double* w,
                      const double* rho, const double* rfl, const double* mu, const double* chi,
                      const double* rho_n, double dt, double t1, double* us, double* vs, double* ws, double* bx,
                      double* by, double* bz, float* bxf, float* byf, float* bzf, double* const* cn_rhs,
-                     double* const* cn_diag, hipStream_t st);
-// one Jacobi sweep of the Crank-Nicolson viscous system: (u, v, w) -> (uo, vo, wo)
+                     double* const* cn_diag, double* flag, hipStream_t st);
+// one Jacobi sweep of the Crank-Nicolson viscous system: (u, v, w) -> (uo, vo, wo);
+// with part (2 cn_part_blocks values), also each block's largest change and
+// largest |new value| over the faces it updates, then their maxima to out2
+// (two doubles, e.g. the host mirror)
 void launch_cn_sweep(const Phys& P, const double* u, const double* v, const double* w, const double* mu,
-                     double* const* rhs, double* const* diag, double* uo, double* vo, double* wo, hipStream_t st);
+                     double* const* rhs, double* const* diag, double* uo, double* vo, double* wo, double* part,
+                     double* out2, hipStream_t st);
+int cn_part_blocks(const Dims& n);
+// the CFL rule's maximum over cells of |u_c| + |v_c| + |w_c| (infinite if any
+// is not finite) into *out; partials holds one value per diag_blocks block
+void launch_cfl_max(const Phys& P, const double* u, const double* v, const double* w, double* partials,
+                    double* out, hipStream_t st);
 void launch_rhs(const Phys& P, const double* us, const double* vs, const double* ws, double dt,
                 double* b, hipStream_t st);
 void launch_correct(const Phys& P, const double* us, const double* vs, const double* ws,

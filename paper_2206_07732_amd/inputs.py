@@ -399,20 +399,6 @@ def make_fields(wl: Workload):
     return {"sigma": np.ascontiguousarray(sigma), "u": u, "v": v, "w": w, "p": p}
 
 
-def cfl_dt(wl: Workload, fields, cfl: Optional[float] = None) -> float:
-    """Fixed time step dt = CFL h / max_cells(|u_c| + |v_c| + |w_c|) of the
-    initial field (cell-centred face averages), capped at wl.dt_max."""
-    cfl = wl.cfl if cfl is None else cfl
-    u, v, w = fields["u"], fields["v"], fields["w"]
-    uc = 0.5 * (np.abs(u[:, :, 1:] + u[:, :, :-1]))
-    vc = 0.5 * (np.abs(v[:, 1:, :] + v[:, :-1, :]))
-    wc = 0.5 * (np.abs(w[1:, :, :] + w[:-1, :, :]))
-    m = float(np.max(uc + vc + wc))
-    if m <= 0.0:
-        return wl.dt_max
-    return min(cfl * wl.h / m, wl.dt_max)
-
-
 def random_fields(nx: int, ny: int, nz: int, seed: int, scale: float = 1.0):
     """Random cell/face arrays (for operator-level parity tests)."""
     rng = np.random.default_rng(seed)

@@ -71,12 +71,12 @@ def harvest(seeds, steps: int, log=print):
     for sd in seeds:
         wl = run_workload(sd)
         f = I.make_fields(wl)
-        dt = I.cfl_dt(wl, f)
         dev = ns.device_fields(f)
         S = ns.Solver(ns.params(wl), dev)
         shp = f["p"].shape
         t = 0.0
         for s in range(steps):
+            dt = S.cfl_dt(wl.cfl, wl.dt_max)      # the CFL rule on the current velocity
             S.levelset_advect_reinit(dt)
             S.momentum_step(dt, t + dt)
             pprev = dev["p"].clone()
@@ -90,7 +90,7 @@ def harvest(seeds, steps: int, log=print):
                 out.append((feat, tgt, beta))
             t += dt
         S.close()
-        log(f"[harvest] seed {sd}: {steps} steps, dt {dt:.4f}, total samples {len(out)}")
+        log(f"[harvest] seed {sd}: {steps} steps to t = {t:.3f} s, total samples {len(out)}")
     return out
 
 
@@ -133,7 +133,6 @@ def evaluate(params, steps: int, wl_name="c3", log=print, precs=("fp64", "mixed"
     from paper_2206_07732_amd import ns
     wl = I.workload(wl_name)
     f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
     res = {"workload": wl.name, "steps": steps}
     net = None
     if params is not None:
@@ -151,6 +150,7 @@ def evaluate(params, steps: int, wl_name="c3", log=print, precs=("fp64", "mixed"
                 S.attach_net(net)
             t, its, ms, r0 = 0.0, [], [], []
             for s in range(steps):
+                dt = S.cfl_dt(wl.cfl, wl.dt_max)
                 S.levelset_advect_reinit(dt)
                 S.momentum_step(dt, t + dt)
                 torch.cuda.synchronize()

@@ -16,8 +16,9 @@ import torch
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libns.so")
 
-NS_OK, NS_EINVAL, NS_ENOCONV, NS_ENAN, NS_EHIP, NS_ESTATE = 0, -1, -2, -3, -4, -5
-STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_ENOCONV", -3: "NS_ENAN", -4: "NS_EHIP", -5: "NS_ESTATE"}
+NS_OK, NS_EINVAL, NS_ENOCONV, NS_ENAN, NS_EHIP, NS_ESTATE, NS_EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
+STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_ENOCONV", -3: "NS_ENAN", -4: "NS_EHIP", -5: "NS_ESTATE",
+          -6: "NS_EUNSTABLE"}
 PREC_FP64, PREC_MIXED = 0, 1
 X0_ZERO, X0_PREV, X0_LEARNED = 0, 1, 2
 BUF = {"us": 0, "vs": 1, "ws": 2, "bx": 3, "by": 4, "bz": 5, "rhs": 6, "rho": 7, "mu": 8, "chi": 9,
@@ -47,7 +48,7 @@ class NSParams(C.Structure):
                 ("p_scale", C.c_double),
                 ("depth", C.c_double), ("gen_len", C.c_double), ("damp_len", C.c_double),
                 ("vort_width", C.c_double), ("n_waves", C.c_int), ("waves", NSWave * 64),
-                ("consistent", C.c_int), ("cn_sweeps", C.c_int)]
+                ("consistent", C.c_int), ("cn_sweeps", C.c_int), ("cn_tol", C.c_double)]
 
 
 class NSFields(C.Structure):
@@ -58,10 +59,12 @@ class NSFields(C.Structure):
 class NSStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_resid0", C.c_double),
                 ("rel_resid", C.c_double), ("true_rel_resid", C.c_double), ("ms", C.c_double),
-                ("x0_fallback", C.c_int)]
+                ("x0_fallback", C.c_int), ("cn_sweeps", C.c_int), ("t_ms", C.c_double * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["t_ms"] = list(self.t_ms)
+        return d
 
 
 class NSError(RuntimeError):
@@ -115,6 +118,8 @@ def lib() -> C.CDLL:
             "ns_attach_net": ([vp, vp], i),
             "ns_features": ([vp, d, vp, vp], i),
             "ns_target": ([vp, vp, vp], i),
+            "ns_cfl_dt": ([vp, d, d, C.POINTER(C.c_double)], i),
+            "ns_phase_timing": ([vp, i], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
         }
@@ -132,12 +137,12 @@ EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum
             "ns_body_state", "ns_timing_enable", "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
-            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target"]
+            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target", "ns_cfl_dt", "ns_phase_timing"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
 LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 
 SOLVER_DEFAULTS = dict(reinit_iters=5, reinit_dtau_over_h=0.25, nu_pre=2, nu_post=2, coarse_sweeps=10,
-                       max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV, p_scale=0.0)
+                       max_iters=200, rtol=1e-10, prec=PREC_FP64, x0=X0_PREV, p_scale=0.0, cn_tol=1e-10)
 
 
 def params(wl, **opts) -> NSParams:
@@ -332,6 +337,16 @@ class Solver:
         out = (C.c_double * 6)()
         self._chk("ns_body_state", lib().ns_body_state(self.ctx, m, out))
         return {"zeta": out[0], "zdot": out[1], "F": (out[2], out[3], out[4]), "f_pto": out[5]}
+
+    def cfl_dt(self, cfl: float, dt_max: float = 0.05) -> float:
+        """Time step of the CFL rule on the current fields (ns_cfl_dt)."""
+        dt = C.c_double()
+        self._chk("ns_cfl_dt", lib().ns_cfl_dt(self.ctx, cfl, dt_max, C.byref(dt)))
+        return dt.value
+
+    def phase_timing(self, on: bool):
+        """Per-phase device times in the stats' t_ms while on."""
+        self._chk("ns_phase_timing", lib().ns_phase_timing(self.ctx, 1 if on else 0))
 
     def diagnostics(self):
         out = (C.c_double * 4)()

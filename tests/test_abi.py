@@ -85,8 +85,9 @@ def test_level_count_matches_oracle(nslib, orc):
 
 def test_workspace_options_consistent_and_cn(nslib):
     """The consistent predictor adds one cell array (the density at t^n),
-    Crank-Nicolson nine face arrays (rhs, diagonal, second iterate); values
-    out of range are refused."""
+    Crank-Nicolson nine face arrays (rhs, diagonal, second iterate) and two
+    values per block of its convergence check; values out of range are
+    refused."""
     from paper_2206_07732_amd import inputs as I
     L = nslib.lib()
     wl = I.workload("c2")
@@ -96,6 +97,12 @@ def test_workspace_options_consistent_and_cn(nslib):
     nbc = L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, consistent=1)))
     assert 8 * nc <= nbc - nb0 <= 8 * nc + 256
     nbn = L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, cn_sweeps=3)))
-    assert 3 * 8 * nf <= nbn - nb0 <= 3 * 8 * nf + 9 * 256
+    def blocks(mx, my, mz):                        # 64 x 4 x 1 tiles of a face array
+        return -(-mx // 64) * -(-my // 4) * mz
+    nblk = blocks(wl.nx + 1, wl.ny, wl.nz) + blocks(wl.nx, wl.ny + 1, wl.nz) + blocks(wl.nx, wl.ny, wl.nz + 1)
+    checks = 2 * 8 * nblk                          # (largest change, largest |u*|) per block
+    assert 3 * 8 * nf <= nbn - nb0 <= 3 * 8 * nf + checks + 10 * 256
     for field, value in (("consistent", 2), ("cn_sweeps", -1), ("cn_sweeps", 65)):
         assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, **{field: value}))) == 0, (field, value)
+    for tol in (0.0, -1e-10, float("nan")):
+        assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, cn_sweeps=3, cn_tol=tol))) == 0, tol

@@ -3,12 +3,15 @@ the oracle's bfloat16 emulation, training, feature construction and the
 learned guess inside the projection.
 
 Tolerances: the GPU stores activations and activation gradients in bfloat16
-(relative rounding 2^-9) and sums in FP32, the oracle rounds the same
-activations but keeps gradients in FP64, so outputs agree to about 1e-2 and
-weight gradients to a few 1e-2 (relative L2)."""
+and sums in FP32; the oracle's bfloat16 emulation rounds the same tensors at
+the same points and sums in FP64.  What differs is the FP32 summation order
+and the rare bfloat16 rounding it flips, so the output and every gradient
+must agree to 5e-3 (relative L2, and the largest elementwise difference over
+the tensor's largest value)."""
 import numpy as np
 import pytest
 
+from gates import gate
 from oracle import net_oracle as N
 from paper_2206_07732_amd import inputs as I
 
@@ -42,7 +45,8 @@ def test_param_count_matches_oracle():
     assert _ns().net_param_count() == N.param_count()
 
 
-@pytest.mark.parametrize("dims", [(16, 8, 8), (24, 12, 8)])
+# (64, 32, 32): every level (64x32x32, 32x16x16, 16x8x8) fills whole tiles
+@pytest.mark.parametrize("dims", [(16, 8, 8), (24, 12, 8), (64, 32, 32)])
 def test_forward_matches_oracle_bf16(dims):
     ns = _ns()
     nx, ny, nz = dims
@@ -55,14 +59,13 @@ def test_forward_matches_oracle_bf16(dims):
     assert np.array_equal(net.get_params(), theta.astype(np.float32))
     out = net.forward(torch.from_numpy(feat).cuda()).cpu().numpy()
     ref, _ = N.forward(N.unflatten(theta.astype(np.float32).astype(np.float64)), feat.astype(np.float64), bf16=True)
-    r = rel(out, ref)
-    print(f"[net fwd] dims={dims} rel={r:.2e}", flush=True)
-    assert r < 1e-2
+    gate(f"net forward {dims}", out, ref, 5e-3, float(np.max(np.abs(ref))))
 
 
-def test_gradients_match_oracle(orc):
+@pytest.mark.parametrize("dims", [(16, 8, 8), (32, 16, 16)])
+def test_gradients_match_oracle(orc, dims):
     ns = _ns()
-    nx, ny, nz = 16, 8, 8
+    nx, ny, nz = dims
     rng = np.random.default_rng(3)
     theta = N.he_init(11)
     theta[-161:] = rng.standard_normal(161) * 0.05
@@ -79,13 +82,48 @@ def test_gradients_match_oracle(orc):
                                bz.astype(np.float64), x)
     L, dout = N.energy_loss_and_grad(out, target.astype(np.float64), op)
     gr = N.backward(cache, dout)
-    print(f"[net grad] loss gpu={loss:.6f} oracle={L:.6f}", flush=True)
-    assert abs(loss - L) < 1e-2 * L
+    print(f"[net grad] {dims} loss gpu={loss:.8f} oracle={L:.8f}", flush=True)
+    assert abs(loss - L) < 5e-3 * L
     G = N.unflatten(g.astype(np.float64))
     for k in gr:
-        r = rel(G[k], gr[k])
-        print(f"[net grad] {k} rel={r:.2e}", flush=True)
-        assert r < 5e-2, k
+        gate(f"net grad {dims} {k}", G[k], gr[k], 5e-3, float(np.max(np.abs(gr[k]))))
+
+
+def test_adam_steps_match_oracle():
+    """Two training steps with the update on: each step's parameters against
+    the oracle's Adam (bias-corrected, betas 0.9/0.999, eps 1e-8) applied to
+    the previous parameters and the GPU's own gradients of that step, element
+    by element.  The GPU updates in FP32 (its constants 0.9f, 0.999f), the
+    oracle in FP64."""
+    ns = _ns()
+    nx, ny, nz = 16, 8, 8
+    rng = np.random.default_rng(13)
+    theta = N.he_init(17)
+    theta[-161:] = rng.standard_normal(161) * 0.05
+    feat = torch.from_numpy(rng.standard_normal((4, nz, ny, nx)).astype(np.float32)).cuda()
+    target = torch.from_numpy((rng.standard_normal((nz, ny, nx)) * 0.3).astype(np.float32)).cuda()
+    _, beta = random_beta(nx, ny, nz, 14)
+    net = ns.Net(nx, ny, nz, training=True)
+    net.set_params(theta)
+    th = net.get_params().astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    lr = 1e-3
+    for t in (1, 2):
+        net.train_step(feat, target, beta, lr, update=True)
+        g = net.get_grads().astype(np.float64)
+        ref, m, v = N.adam_step(th, g, m, v, t, lr=lr)
+        got = net.get_params().astype(np.float64)
+        err = np.abs(got - ref)
+        # FP32 on the GPU: the parameter's own rounding (4e-7 relative), and
+        # the update's, whose bias corrections 1 - 0.999f^t differ from the
+        # exact ones by up to 1.5e-5 (the FP32 constant 0.999f)
+        bound = 4e-7 * np.abs(ref) + 5e-5 * lr
+        print(f"[adam] step {t}: max |err| {err.max():.3e}, max err/bound {np.max(err / bound):.3f}, "
+              f"moved {np.mean(got != th):.3f} of the parameters", flush=True)
+        assert np.all(err <= bound)
+        assert np.mean(np.abs(got - th) > 0.5 * lr) > 0.5      # the first steps move by ~lr
+        th = got
 
 
 def test_training_reduces_loss():
@@ -116,7 +154,7 @@ def test_features_match_oracle(orc):
     ns = _ns()
     wl = I.workload("tiny3d")
     f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl)
     dev = ns.device_fields(f)
     S = ns.Solver(ns.params(wl), dev)
     S.levelset_advect_reinit(dt)
@@ -136,14 +174,14 @@ def test_features_match_oracle(orc):
     ref = N.features(b, rho, pp, r0, wl.h, wl.rho_w, wl.rho_a, P0)
     got = feat.cpu().numpy()
     for c in range(4):
-        assert rel(got[c], ref[c]) < 1e-6, c
+        gate(f"features channel {c}", got[c], ref[c], 1e-6, float(np.max(np.abs(ref[c]))))
 
 
-def test_learned_guess_in_projection():
+def test_learned_guess_in_projection(orc):
     ns = _ns()
     wl = I.workload("tiny3d")
     f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl)
     net = ns.Net(wl.nx, wl.ny, wl.nz)
     net.set_params(N.he_init(3) * 0.1)
     dev = ns.device_fields(f)

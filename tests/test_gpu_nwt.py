@@ -8,6 +8,7 @@ elementwise on top of that)."""
 import numpy as np
 import pytest
 
+from gates import Scales, gate, gate_fields, gate_velocity
 from paper_2206_07732_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -40,22 +41,20 @@ def make_solver(wl, fields, **opts):
 def test_predictor_with_inlet_and_vorticity_damping(orc, name):
     wl = I.workload(name)
     f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
     P = orc.params(wl)
     S, dev = make_solver(wl, f)
     S.momentum_step(dt, dt)
     torch.cuda.synchronize()
     ref = orc.momentum(P, f["u"], f["v"], f["w"], f["sigma"], dt, dt)
-    for k, r in zip(("us", "vs", "ws"), ref):
-        g = host(S.buffer(k))
-        print(f"[nwt predictor] {name} {k} rel={rel(g, r):.2e}", flush=True)
-        if np.linalg.norm(r) > 0:
-            assert rel(g, r) < 1e-13, k
+    sc = Scales(wl, f, dt)
+    gate_velocity(f"nwt predictor {name}", [S.buffer(k) for k in ("us", "vs", "ws")], ref, ("us", "vs", "ws"),
+                  1e-13, sc)
     # the inlet face carries the generated wave, and the top rows are damped
     us = host(S.buffer("us"))
     assert np.max(np.abs(us[..., 0])) > 0.1 * wl.wave["a"]
     bx, by, bz = orc.face_beta(P, f["sigma"], dt, dt)
-    assert rel(host(S.buffer("bx")), bx) < 1e-14
+    gate(f"nwt beta {name}", S.buffer("bx"), bx, 1e-13, sc.of("bx", bx))   # see the stage parity
     S.close()
 
 
@@ -64,7 +63,7 @@ def test_step_parity_forced_iterations(orc, name):
     """A whole step (inlet, damping force, projection, relaxation zones)."""
     wl = I.workload(name)
     f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
     _, st, rc = orc.step(orc.params(wl), f, dt, 0.0)
     assert rc == 0
     k = st["iters"]
@@ -73,11 +72,7 @@ def test_step_parity_forced_iterations(orc, name):
     sg = S.step(dt, 0.0, allow_noconv=True)
     torch.cuda.synchronize()
     assert sg["iters"] == k
-    for key in ("sigma", "u", "v", "w", "p"):
-        r = rel(host(dev[key]), ref[key])
-        print(f"[nwt step parity] case={name} field={key} rel={r:.2e}", flush=True)
-        if np.linalg.norm(ref[key]) > 0:
-            assert r < 1e-10, key
+    gate_fields(f"nwt step {name}", dev, ref, ("sigma", "u", "v", "w", "p"), 1e-10, Scales(wl, f, dt))
     S.close()
 
 
@@ -85,7 +80,7 @@ def test_c1nwt_free_running_steps(orc):
     """Five free-running steps of the 2-D wave tank stay with the oracle's."""
     wl = I.workload("c1nwt")
     f = I.make_fields(wl)
-    dt = I.cfl_dt(wl, f)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
     P = orc.params(wl)
     S, dev = make_solver(wl, f)
     ref = f
@@ -96,8 +91,5 @@ def test_c1nwt_free_running_steps(orc):
         S.step(dt, t)
         t += dt
     torch.cuda.synchronize()
-    for key in ("sigma", "u", "w", "p"):
-        r = rel(host(dev[key]), ref[key])
-        print(f"[nwt free run] field={key} rel={r:.2e}", flush=True)
-        assert r < 1e-8, key
+    gate_fields("nwt free run", dev, ref, ("sigma", "u", "w", "p"), 1e-8, Scales(wl, f, dt))
     S.close()

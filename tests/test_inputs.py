@@ -76,8 +76,6 @@ def test_fields_shapes_and_walls():
     assert np.all(f["w"][0] == 0)
     # sigma is negative in water below the still level
     assert f["sigma"][0].max() < 0 and f["sigma"][-1].min() > 0
-    dt = I.cfl_dt(wl, f)
-    assert 0 < dt <= wl.dt_max
 
 
 def test_seeded_inputs_are_reproducible():
