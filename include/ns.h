@@ -386,6 +386,23 @@ ns_status ns_target(ns_ctx* ctx, const double* p_prev, float* t);
  * velocity is not finite. */
 ns_status ns_cfl_dt(ns_ctx* ctx, double cfl, double dt_max, double* dt_out);
 
+/* The CFL rule of ns_cfl_dt for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It needs no context and allocates nothing: u, v, w are the
+ * face velocities of an nx*ny*nz grid of spacing h (device, FP64, the
+ * layouts above, same limits on the sizes as ns_params), and the time step
+ * min(cfl h / m, dt_max) (dt_max when m = 0; NaN when a velocity is not
+ * finite) is stored to dt_dev, one caller-owned device double, in stream
+ * order on hip_stream; the call does not wait for it.  Its scratch (the
+ * per-block maxima, 16 KiB, every grid size fits) is a device array of the
+ * library's own, one per GPU, held until the process ends: calls that
+ * overlap on one GPU (other streams or threads) race on it.  The result is
+ * bit for bit that of ns_cfl_dt.  NS_EINVAL for bad sizes, a non-positive h,
+ * cfl or dt_max, or a null or misaligned pointer; NS_EHIP if the current
+ * device cannot be queried or the launch fails. */
+ns_status ns_cfl_dt_noalloc(int nx, int ny, int nz, double h, const double* u, const double* v, const double* w,
+                            double cfl, double dt_max, double* dt_dev, void* hip_stream);
+
 /* Per-phase device timing of the steps (ns_stats.t_ms): on != 0 records HIP
  * events between the phases of every later call (host-API objects, created
  * on the first use; no device memory); 0 stops it. */

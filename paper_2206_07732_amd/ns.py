@@ -119,6 +119,7 @@ def lib() -> C.CDLL:
             "ns_features": ([vp, d, vp, vp], i),
             "ns_target": ([vp, vp, vp], i),
             "ns_cfl_dt": ([vp, d, d, C.POINTER(C.c_double)], i),
+            "ns_cfl_dt_noalloc": ([i, i, i, d, vp, vp, vp, d, d, vp, vp], i),
             "ns_phase_timing": ([vp, i], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
@@ -137,7 +138,7 @@ EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum
             "ns_body_state", "ns_timing_enable", "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
-            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target", "ns_cfl_dt", "ns_phase_timing"]
+            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target", "ns_cfl_dt", "ns_phase_timing", "ns_cfl_dt_noalloc"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
 LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 
@@ -352,6 +353,19 @@ class Solver:
         out = (C.c_double * 4)()
         self._chk("ns_diagnostics", lib().ns_diagnostics(self.ctx, out))
         return list(out)
+
+
+def cfl_dt_noalloc(nx: int, ny: int, nz: int, h: float, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+                   cfl: float, dt_max: float, dt_out: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    """ns_cfl_dt_noalloc: the CFL rule's time step into dt_out (one float64
+    CUDA element), stream-ordered, without a context or any allocation."""
+    if not (dt_out.is_cuda and dt_out.dtype == torch.float64 and dt_out.numel() >= 1):
+        raise TypeError("dt_out must be a float64 CUDA tensor")
+    st = stream if stream is not None else torch.cuda.current_stream(dt_out.device)
+    s = lib().ns_cfl_dt_noalloc(nx, ny, nz, h, _dev_f64(u, "u"), _dev_f64(v, "v"), _dev_f64(w, "w"), cfl, dt_max,
+                                dt_out.data_ptr(), C.c_void_p(st.cuda_stream))
+    if s != NS_OK:
+        raise NSError("ns_cfl_dt_noalloc", s, "invalid sizes, pointers or values, or a HIP failure")
 
 
 def device_fields(host_fields: dict, device="cuda") -> dict:
