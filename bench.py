@@ -14,12 +14,14 @@ inputs already resident in device memory when the timed region starts.
 
 Printed: ONE JSON line with
   value        Mcell-steps/s over the K timed steps (cells x K / seconds)
-  roofline     the dominant kernel (the finest-level red-black smoothing):
-               its algorithmic bytes per launch (24 B per cell per colour
-               pass: beta on the three face arrays once, b, e read and e
-               written once per sweep, halved over the two colours) over its
-               average duration from HIP events on the library's stream,
-               against the published 8 TB/s; traffic from rocprofv3 counters
+  roofline     the dominant kernel (the finest-level red-black smoothing:
+               on 512x256x256 the fused sweep, one launch per red-black
+               sweep): its algorithmic bytes per launch (48 B per cell per
+               sweep: beta on the three face arrays once, b, e read and e
+               written once; 24 B per cell for a single colour pass) over
+               its average duration from HIP events on the library's
+               stream, against the published 8 TB/s; traffic from rocprofv3
+               counters
   step_roofline  the whole step's algorithmic bytes (380 B per cell outside
                the solve, 387 B per cell per FP64 CG iteration) over the
                measured step time
@@ -70,9 +72,11 @@ ITER_BYTES_PER_CELL_FP64 = 387.0
 # b and e once and writes e once: 48 B per cell, 24 per colour pass
 SWEEP_BYTES_PER_CELL_FP64 = 48.0
 # the kernel the library's smoother timer measures (ns.TIME_SMOOTH0) and the
-# part of one red-black sweep of the finest level that one launch does
-SMOOTHER_KERNEL = "k_gs<double, true> (one red-black colour pass, finest level)"
-SWEEPS_PER_LAUNCH = 0.5
+# part of one red-black sweep of the finest level that one launch does: the
+# fused sweep where the library uses it (large 3-D grids), else one colour
+# pass
+SMOOTHER_KERNELS = {True: ("k_gs_rb_fine<double, 14> (one red-black sweep, finest level)", 1.0),
+                    False: ("k_gs<double, true> (one red-black colour pass, finest level)", 0.5)}
 
 
 def log(*a):
@@ -136,6 +140,8 @@ def run_gpu(args):
     # Its average duration from HIP events around a batch of back-to-back
     # dispatches, and from events recorded with each dispatch inside steps.
     reps = 100
+    fused = S.fine_sweep()
+    smoother_kernel, sweeps_per_launch = SMOOTHER_KERNELS[fused]
     avg_ms = S.time_kernel(ns.TIME_SMOOTH0, reps)
     S.timing_enable(ns.TIME_SMOOTH0, 4096)
     for _ in range(2):
@@ -145,14 +151,14 @@ def run_gpu(args):
     kms, kn = S.timing_read()
     S.timing_enable(ns.TIME_SMOOTH0, 0)
     S.close()
-    kbytes = SWEEP_BYTES_PER_CELL_FP64 * SWEEPS_PER_LAUNCH * ncell
+    kbytes = SWEEP_BYTES_PER_CELL_FP64 * sweeps_per_launch * ncell
     in_step_ms = kms / max(kn, 1)
     achieved = kbytes / (in_step_ms * 1e-3) / 1e9
     achieved_batch = kbytes / (avg_ms * 1e-3) / 1e9
-    roofline = {"kernel": SMOOTHER_KERNEL, "bound": "hbm", "achieved": round(achieved, 1),
+    roofline = {"kernel": smoother_kernel, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": TRAFFIC_BYTES_PER_LAUNCH,
-                "bytes_per_launch": int(kbytes), "sweeps_per_launch": SWEEPS_PER_LAUNCH,
+                "bytes_per_launch": int(kbytes), "sweeps_per_launch": sweeps_per_launch,
                 "bytes_per_cell_per_sweep": SWEEP_BYTES_PER_CELL_FP64,
                 "avg_us": round(in_step_ms * 1e3, 3), "launches": kn, "timing": "HIP events with each "
                 "dispatch inside two whole steps, on the library's stream",

@@ -286,13 +286,30 @@ typedef enum {
 } ns_launch_mode;
 ns_status ns_set_launch_mode(ns_ctx* ctx, int mode);
 
+/* How the finest level runs the red-black sweeps that follow the first pass
+ * of each smoothing (the red pass of one sweep and the black pass after it):
+ * fused = 1 as one launch that reads each face coefficient once, the black
+ * values taking theirs from the red values' loads; fused = 0 as two colour
+ * passes.  The fused launch applies to 3-D levels with ny, nz >= 4 and at
+ * least 32 cell pairs per row; ns_create picks it where it applies and its
+ * launch has at least 512 workgroups (a finest level of about 16M cells
+ * and up), the two passes elsewhere.  Results are bitwise the same either
+ * way.  Recorded V-cycle graphs are released and recorded again on their
+ * next use (synchronises the stream).  NS_EINVAL for another value, or
+ * fused = 1 on a grid it does not apply to. */
+ns_status ns_set_fine_sweep(ns_ctx* ctx, int fused);
+/* *fused = 1 if the finest level's sweeps run as one launch, else 0.
+ * NS_EINVAL for a null argument. */
+ns_status ns_get_fine_sweep(const ns_ctx* ctx, int* fused);
+
 /* Kernel timing, a profiling aid.  While enabled for a kernel, each of its
  * next max_launches dispatches on the context's stream carries a start and
  * stop HIP event recorded by the dispatch itself (hipExtLaunchKernelGGL),
  * so the elapsed time is the kernel's own execution.  max_launches <= 0
  * disables.  Events are host-API objects; no device memory is allocated. */
 typedef enum {
-  NS_TIME_SMOOTH0 = 0,   /* the finest-level smoother pass (one colour)            */
+  NS_TIME_SMOOTH0 = 0,   /* the finest-level smoother: the fused red-black sweep where it
+                            is used (ns_set_fine_sweep), else one colour pass      */
   NS_TIME_SPMV = 1       /* the CG operator application with its dot product       */
 } ns_timed_kernel;
 ns_status ns_timing_enable(ns_ctx* ctx, int kernel, int max_launches);

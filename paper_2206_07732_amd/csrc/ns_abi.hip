@@ -51,6 +51,7 @@ struct ns_ctx {
   KTimer kt;
   hipEvent_t ev_rr;   // marks the residual read-back of a CG iteration
   int launch_mode;    // ns_launch_mode
+  bool fine_rb;       // the finest level's red-black sweeps as one launch each
   struct {
     double F[3];      // last hydrodynamic force (eqn_int_fh)
     double fpto;      // last power take-off force
@@ -327,7 +328,9 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
     // coarse split level's e has a third plane, the black plane's copy that
     // its fused red-black passes read.
     const size_t cs = 2 * (size_t)((V.n.nx + 1) / 2) * V.n.ny * V.n.nz;
-    const size_t ces = l >= 1 ? cs + cs / 2 : cs;
+    // a third plane for the black plane's copy that a fused red-black pass
+    // reads: on the coarse levels, and on the finest where its fused sweep applies
+    const size_t ces = (l >= 1 || gs_rb_fine_fits(V.n)) ? cs + cs / 2 : cs;
     V.bf = cv.take<float>(l < t32 ? cs : c);
     V.ef = cv.take<float>(l < t32 ? ces : c);
     V.bfn = V.efn = nullptr;
@@ -566,9 +569,20 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
     return;
   }
   // On a coarse level whose rows fit one tile, the first (red, black) pair
-  // after a kernel that leaves the black plane's copy is one fused launch.
-  const bool rb = l >= 1 && gs_rb_fits(L.n);
+  // after a kernel that leaves the black plane's copy is one fused launch;
+  // on the finest level the same pair is the fused sweep that reads each
+  // face coefficient once.
+  const bool fine = l == 0 && X->fine_rb;
+  const bool rb = (l >= 1 && gs_rb_fits(L.n)) || fine;
   T* ecopy = rb ? e + nsplit : nullptr;
+  auto fused = [&]() {
+    if (fine)
+      launch_gs_rb_fine<T>(L, bx, by, bz, b, e, ecopy, st, kt);
+    else
+      launch_gs_rb<T>(L, bx, by, bz, b, e, ecopy, st);
+  };
+  // with the fused sweep on the finest level, the timer follows it
+  KTimer* kgs = fine ? nullptr : kt;
   // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
     const bool rb_pre = rb && P.nu_pre >= 2;
@@ -576,12 +590,12 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
                        rb_pre ? ecopy : nullptr);
     int s = 1;
     if (rb_pre) {
-      launch_gs_rb<T>(L, bx, by, bz, b, e, ecopy, st);
+      fused();
       s = 2;
     }
     for (; s < P.nu_pre; ++s) {
-      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
-      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kgs);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kgs);
     }
   } else {
     if (l == 0) launch_split_copy<T>(L, b0, b, true, st);
@@ -594,26 +608,30 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
   // post-smoothing: (prolongation + black) fused, then red, then black, red
   // pairs; at level 0 the last red pass writes e0
   if (P.nu_post > 0 && rb && P.nu_post >= 2) {
-    // (prolongation + black), then (red, black) fused, red, then black, red
+    // (prolongation + black), then (red, black) fused, then red, black
+    // pairs and the last red (at level 0 writing e0)
     launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), csplit, st, ecopy);
-    launch_gs_rb<T>(L, bx, by, bz, b, e, ecopy, st);
-    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+    fused();
     for (int s = 2; s < P.nu_post; ++s) {
-      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
-      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kgs);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kgs);
     }
+    if (l == 0)
+      last_red();
+    else
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kgs);
   } else if (P.nu_post > 0) {
     launch_gs_prolong<T>(L, bx, by, bz, b, e, C, LV<T>::e(C), csplit, st);
     if (l == 0 && P.nu_post == 1)
       last_red();
     else
-      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 0, st, kgs);
     for (int s = 1; s < P.nu_post; ++s) {
-      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
+      launch_gs<T>(L, bx, by, bz, b, e, 1, st, kgs);
       if (l == 0 && s == P.nu_post - 1)
         last_red();
       else
-        launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
+        launch_gs<T>(L, bx, by, bz, b, e, 0, st, kgs);
     }
   } else {
     launch_prolong<T>(L, e, C, LV<T>::e(C), csplit, st);
@@ -987,6 +1005,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     return NS_EHIP;
   }
   X->launch_mode = NS_LAUNCH_GRAPH;
+  X->fine_rb = gs_rb_fine_pays(X->lev[0].n);
   X->ngs = 0;
   X->have_beta = false;
   X->timed_kernel = -1;
@@ -1045,6 +1064,24 @@ ns_status ns_cfl_dt(ns_ctx* X, double cfl, double dt_max, double* dt_out) {
   return NS_OK;
 }
 
+ns_status ns_set_fine_sweep(ns_ctx* X, int fused) {
+  if (!X) return NS_EINVAL;
+  if (fused != 0 && fused != 1) return fail(X, NS_EINVAL, "fused must be 0 or 1");
+  if (fused && !gs_rb_fine_fits(X->lev[0].n)) return fail(X, NS_EINVAL, "the fused sweep does not apply to this grid");
+  X->fine_rb = fused != 0;
+  // the recorded V-cycle graphs hold the old schedule: record them again
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  for (int q = 0; q < X->ngs; ++q) (void)hipGraphExecDestroy(X->gs[q].exec);
+  X->ngs = 0;
+  return NS_OK;
+}
+
+ns_status ns_get_fine_sweep(const ns_ctx* X, int* fused) {
+  if (!X || !fused) return NS_EINVAL;
+  *fused = X->fine_rb ? 1 : 0;
+  return NS_OK;
+}
+
 ns_status ns_set_launch_mode(ns_ctx* X, int mode) {
   if (!X) return NS_EINVAL;
   if (mode != NS_LAUNCH_STREAM && mode != NS_LAUNCH_GRAPH) return fail(X, NS_EINVAL, "unknown launch mode %d", mode);
@@ -1096,12 +1133,21 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
   (void)hipEventRecord(a, X->st);
   for (int q = 0; q < reps; ++q) {
     if (kernel == NS_TIME_SMOOTH0) {
-      // the finest smoother pass of the configured precision, on the
+      // the finest smoother pass of the configured precision (the fused
+      // red-black sweep where it is used, else one colour pass), on the
       // level's colour-split b and e, which are dead between V-cycles
-      if (X->P.prec == NS_PREC_FP64)
-        launch_gs<double>(L0, L0.bx, L0.by, L0.bz, L0.b, L0.e, q & 1, X->st);
-      else
-        launch_gs<float>(L0, L0.bxf, L0.byf, L0.bzf, L0.bf, L0.ef, q & 1, X->st);
+      const size_t ns = 2 * (size_t)((n.nx + 1) / 2) * n.ny * n.nz;
+      if (X->P.prec == NS_PREC_FP64) {
+        if (X->fine_rb)
+          launch_gs_rb_fine<double>(L0, L0.bx, L0.by, L0.bz, L0.b, L0.e, L0.e + ns, X->st);
+        else
+          launch_gs<double>(L0, L0.bx, L0.by, L0.bz, L0.b, L0.e, q & 1, X->st);
+      } else {
+        if (X->fine_rb)
+          launch_gs_rb_fine<float>(L0, L0.bxf, L0.byf, L0.bzf, L0.bf, L0.ef, L0.ef + ns, X->st);
+        else
+          launch_gs<float>(L0, L0.bxf, L0.byf, L0.bzf, L0.bf, L0.ef, q & 1, X->st);
+      }
     } else {
       launch_dir_spmv(n, X->P.h, L0.bx, L0.by, L0.bz, X->zn, X->d, X->d2, X->q, 1, cs, X->st);
     }

@@ -213,6 +213,14 @@ bool gs_rb_fits(const Dims& n);
 template <typename T>
 void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
                   hipStream_t st);
+// the finest level's red then black pass in one launch, each face coefficient
+// read once (3-D levels where gs_rb_fine_fits; the default where
+// gs_rb_fine_pays); bold: the black plane's copy
+bool gs_rb_fine_fits(const Dims& n);
+bool gs_rb_fine_pays(const Dims& n);
+template <typename T>
+void launch_gs_rb_fine(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
+                       hipStream_t st, KTimer* kt = nullptr);
 // coarse b = restricted residual (coarse layout split or natural)
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,

@@ -491,6 +491,174 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
   }
 }
 
+// A red pass then a black pass of Gauss-Seidel in one launch on the finest
+// level, reading each face coefficient once.  Every face borders one red and
+// one black cell, so the black update takes its six coefficients from the
+// red updates beside it instead of loading them again:
+//   * its z-faces are the down face of the red cell above it and the up face
+//     of the red cell below it, both in the same pair column, which the same
+//     thread computes on the planes above and below;
+//   * its x-faces are the faces of the red cell of its own pair and of the
+//     adjacent pair (the adjacent lane: a wave is 64 consecutive pairs of a
+//     row);
+//   * its y-faces are those of the red cells of the rows beside it (LDS).
+// A block is 64 lanes by TY + 2 rows of pairs and marches up a chunk of KZ
+// planes: at plane m it forms the red values of plane m, then the black
+// values of plane m - 1, whose red neighbours are then all known.  The first
+// and last rows form a ring whose red values the block's own black cells
+// read; so do lanes 0 and 63 when a row has more than 64 pairs.  Ring values
+// are recomputed (the neighbouring block forms and stores them too) and
+// only the inner lanes and rows store.  Red values are formed from the
+// black plane as it stood before the launch, which the previous kernel
+// copied to bold (this launch overwrites the black plane while other blocks
+// still read it).  Each value comes from the same arithmetic on the same
+// inputs as in the two separate passes, so the results are theirs bit for
+// bit.
+//
+// The march is bound by memory latency, not bandwidth: a plane's work is a
+// few dozen instructions per thread against one trip to HBM.  So every load
+// of plane m + 1 is issued, unconditionally from clamped addresses, before
+// plane m is computed, and waits only at its first use one plane later; the
+// loop is unrolled by two so that the two planes' registers alternate
+// without copies.
+constexpr int kRbfLanes = 64;
+
+template <typename T>
+struct RbfLoads {
+  T fw, fe, fs, fn, fd, fu;  // the faces of the red cell of plane m
+  T bc;                      // its right-hand side
+  T bo_u;                    // this pair's black value (before the launch) on plane m + 1
+  T xo, yo;                  // black values beside the ring (row ends, ring rows) on plane m
+  T bb;                      // the right-hand side of this pair's black cell on plane m - 1
+  T xf;                      // that cell's outer x-face, for a row's end lanes
+};
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(kRbfLanes * (TY + 2)) k_gs_rb_fine(Dims n, T h2, const T* __restrict__ bx,
+                                                                     const T* __restrict__ by,
+                                                                     const T* __restrict__ bz,
+                                                                     const T* __restrict__ b, T* __restrict__ e,
+                                                                     const T* __restrict__ bold, int KZ) {
+  constexpr int R = TY + 2;
+  __shared__ T BO[2][R][kRbfLanes];    // black values (as before the launch) of a plane
+  __shared__ T RN[2][R][kRbfLanes];    // red values of a plane
+  __shared__ T RYS[2][R][kRbfLanes];   // their south and north faces
+  __shared__ T RYN[2][R][kRbfLanes];
+  const SplitGeo sg = split_geo(n);
+  const Tile tl = xcd_tile();
+  const int lane = threadIdx.x, r = threadIdx.y;
+  const int xr = sg.hx > kRbfLanes ? 1 : 0;   // ring lanes only where a row spans several blocks
+  const int ti = tl.x * (kRbfLanes - 2 * xr) - xr + lane, j = tl.y * TY - 1 + r;
+  const bool ok = ti >= 0 && ti < sg.hx && j >= 0 && j < n.ny;
+  const bool inner = ok && lane >= xr && lane < kRbfLanes - xr && r >= 1 && r <= TY;
+  const int tic = min(max(ti, 0), sg.hx - 1), jc = min(max(j, 0), n.ny - 1);
+  const int k0 = tl.z * KZ, kz1 = min(k0 + KZ, n.nz);
+  const size_t sz = (size_t)sg.hx * n.ny;                 // pairs per plane
+  const size_t prow = (size_t)tic + (size_t)sg.hx * jc;   // this pair in plane 0
+  // the pairs whose black values the ring reads: the adjacent pair for a
+  // row's end lanes, the adjacent row for the ring rows (others: their own)
+  const size_t xrow = (size_t)(lane == 0 ? max(tic - 1, 0) : lane == kRbfLanes - 1 ? min(tic + 1, sg.hx - 1) : tic) +
+                      (size_t)sg.hx * jc;
+  const size_t yrow = (size_t)tic + (size_t)sg.hx * (r == 0 ? max(jc - 1, 0) : r == R - 1 ? min(jc + 1, n.ny - 1) : jc);
+  // the outer x-face of a black cell on a row's end lane: the west face of
+  // an even column on lane 0, the east face of an odd one on lane 63 (a
+  // shuffle there would return the lane's own face)
+  const int xfi = lane == 0 ? 2 * ti : 2 * ti + 2;
+  const size_t fxs = (size_t)(n.nx + 1) * n.ny, fys = (size_t)n.nx * (n.ny + 1), fzs = (size_t)n.nx * n.ny;
+  const auto clampz = [&](int m) { return (size_t)min(max(m, 0), n.nz - 1); };
+  // face indices from the unclamped cell, kept in the face range: a ring
+  // cell outside the grid holds the wall face it shares with the grid; at
+  // m = -1 the up face is the bed, at m = nz the down face is the open top
+  const auto load = [&](int m, RbfLoads<T>& L) {
+    const size_t mc = clampz(m);
+    const int iru = 2 * ti + ((j + m) & 1);
+    const int irc = min(max(iru, 0), n.nx - 1);
+    const size_t xf = (size_t)(n.nx + 1) * jc + fxs * mc;
+    L.fw = bx[(size_t)min(max(iru, 0), n.nx) + xf];
+    L.fe = bx[(size_t)min(max(iru + 1, 0), n.nx) + xf];
+    L.fs = by[(size_t)irc + (size_t)n.nx * min(max(j, 0), n.ny) + fys * mc];
+    L.fn = by[(size_t)irc + (size_t)n.nx * min(max(j + 1, 0), n.ny) + fys * mc];
+    L.fd = bz[(size_t)irc + (size_t)n.nx * jc + fzs * (size_t)min(max(m, 0), n.nz)];
+    L.fu = bz[(size_t)irc + (size_t)n.nx * jc + fzs * (size_t)min(max(m + 1, 0), n.nz)];
+    L.bc = b[prow + sz * mc];
+    L.bo_u = bold[prow + sz * clampz(m + 1)];
+    L.xo = bold[xrow + sz * mc];
+    L.yo = bold[yrow + sz * mc];
+    L.bb = b[sg.P + prow + sz * clampz(m - 1)];
+    L.xf = bx[(size_t)min(max(xfi, 0), n.nx) + (size_t)(n.nx + 1) * jc + fxs * clampz(m - 1)];
+  };
+  T bo_d = bold[prow + sz * clampz(k0 - 2)], bo_c = bold[prow + sz * clampz(k0 - 1)];
+  if (!(ok && k0 - 2 >= 0)) bo_d = (T)0;
+  if (!(ok && k0 - 1 >= 0)) bo_c = (T)0;
+  T rv1 = 0, rv2 = 0, fu1 = 0, fu2 = 0, fw1 = 0, fe1 = 0;
+  const auto plane = [&](int m, const RbfLoads<T>& L) {
+    // ---- the red cell of this pair on plane m (ring included)
+    const int mc = (int)clampz(m);
+    const int par = (j + m) & 1;
+    const int iru = 2 * ti + par;                     // possibly outside the grid
+    const int irc = min(max(iru, 0), n.nx - 1);
+    const bool live = ok && m >= 0 && m < n.nz;
+    const T bo_u = (ok && m + 1 >= 0 && m + 1 < n.nz) ? L.bo_u : (T)0;
+    // x neighbours: this pair's black cell and the adjacent pair's (the
+    // adjacent lane; the row's end lanes loaded theirs)
+    const T bl = __shfl_up(bo_c, 1, kRbfLanes), br = __shfl_down(bo_c, 1, kRbfLanes);
+    const T xo = live ? L.xo : (T)0, yo = live ? L.yo : (T)0;
+    const T vw = par == 0 ? (lane > 0 ? bl : xo) : bo_c;
+    const T ve = par == 1 ? (lane < kRbfLanes - 1 ? br : xo) : bo_c;
+    const T vs = r > 0 ? BO[m & 1][r - 1][lane] : yo;
+    const T vn = r < R - 1 ? BO[m & 1][r + 1][lane] : yo;
+    T rv = (T)0;
+    if (live && iru < n.nx) {
+      const GsIn<T> g{L.fw, L.fe, L.fs, L.fn, L.fd, L.fu, vs, vn, bo_d, bo_u};
+      rv = gs_combine<T>(n, g, h2, L.bc, irc, jc, mc, vw, ve);
+      if (inner && m >= k0 && m < kz1) e[prow + sz * mc] = rv;
+    }
+    RN[m & 1][r][lane] = rv;
+    RYS[m & 1][r][lane] = L.fs;
+    RYN[m & 1][r][lane] = L.fn;
+    BO[(m + 1) & 1][r][lane] = bo_u;
+    // the adjacent lanes' red values and x-faces of plane m - 1 (every lane
+    // takes part in the shuffles)
+    const T xfe = __shfl_up(fe1, 1, kRbfLanes), xrl = __shfl_up(rv1, 1, kRbfLanes);
+    const T xfw = __shfl_down(fw1, 1, kRbfLanes), xrr = __shfl_down(rv1, 1, kRbfLanes);
+    __syncthreads();
+    // ---- the black cell of this pair on plane m - 1 (inner threads)
+    const int mb = m - 1;
+    if (inner && mb >= k0 && mb < kz1) {
+      const int ib = iru;      // the black cell of plane m - 1 shares the column of plane m's red cell
+      if (ib < n.nx) {
+        const bool even = (ib & 1) == 0;
+        const T bw = lane > 0 ? xfe : L.xf, be = lane < kRbfLanes - 1 ? xfw : L.xf;
+        const GsIn<T> g{even ? bw : fe1, even ? fw1 : be, RYN[mb & 1][r - 1][lane], RYS[mb & 1][r + 1][lane],
+                        fu2, L.fd, RN[mb & 1][r - 1][lane], RN[mb & 1][r + 1][lane], rv2, rv};
+        e[sg.P + prow + sz * (size_t)mb] = gs_combine<T>(n, g, h2, L.bb, ib, j, mb, even ? xrl : rv1, even ? rv1 : xrr);
+      }
+    }
+    __syncthreads();
+    rv2 = rv1;
+    rv1 = rv;
+    fu2 = fu1;
+    fu1 = L.fu;
+    fw1 = L.fw;
+    fe1 = L.fe;
+    bo_d = bo_c;
+    bo_c = bo_u;
+  };
+  RbfLoads<T> A, B;
+  load(k0 - 1, A);
+  BO[(k0 - 1) & 1][r][lane] = bo_c;
+  __syncthreads();
+  for (int m = k0 - 1; m <= kz1; m += 2) {
+    load(m + 1, B);
+    __builtin_amdgcn_sched_barrier(0);
+    plane(m, A);
+    if (m + 1 > kz1) break;
+    load(m + 2, A);
+    __builtin_amdgcn_sched_barrier(0);
+    plane(m + 1, B);
+  }
+}
+
 // coarse rhs = mean over the children of the fine residual b - A e (fine b,
 // e colour-split; the coarse b colour-split when csplit, else natural).  A
 // block takes a tile of fine cells (32 x 4 x 2; 64 x 1 x 4 in 2-D), one
@@ -1350,6 +1518,53 @@ void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T
                      TY, TZ);
 }
 
+// the finest level's fused red-black sweep: where it applies (a 3-D level
+// whose rows fill at least half a wave), where it pays, and its launch.  A
+// block runs TY + 2 rows of 64 lanes (1024 threads) up KZ planes.
+constexpr int kRbfRows = 14;    // inner rows of a block (TY)
+constexpr int kRbfPlanes = 32;  // planes a block marches (KZ)
+
+static dim3 rbf_grid(const Dims& n, int TY, int KZ) {
+  const int hx = (n.nx + 1) / 2;
+  const int step = hx > kRbfLanes ? kRbfLanes - 2 : kRbfLanes;   // inner lanes of a block
+  return dim3((hx + step - 1) / step, (n.ny + TY - 1) / TY, (n.nz + KZ - 1) / KZ);
+}
+
+bool gs_rb_fine_fits(const Dims& n) {
+  return n.ny >= 4 && n.nz >= 4 && (n.nx + 1) / 2 >= 32;
+}
+
+// A block's march is a chain of dependent planes, so the launch wins over
+// two colour passes only where its blocks fill every compute unit at least
+// twice (measured: 760 blocks on 512 x 256 x 256 beat the two passes by a
+// sixth; 120 on 256 x 128 x 128 lose by a tenth).
+bool gs_rb_fine_pays(const Dims& n) {
+  if (!gs_rb_fine_fits(n)) return false;
+  const dim3 g = rbf_grid(n, kRbfRows, kRbfPlanes);
+  return (long)g.x * g.y * g.z >= 512;
+}
+
+template <typename T, int TY>
+void launch_gs_rb_fine_tile(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
+                            hipStream_t st, KTimer* kt, int KZ) {
+  const dim3 grid = rbf_grid(L.n, TY, KZ);
+  const dim3 blk(kRbfLanes, TY + 2);
+  const T h2 = (T)(L.h * L.h);
+  if (kt && kt->n < kt->cap) {
+    hipExtLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
+                          h2, bx, by, bz, b, e, bold, KZ);
+    ++kt->n;
+    return;
+  }
+  hipLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, L.n, h2, bx, by, bz, b, e, bold, KZ);
+}
+
+template <typename T>
+void launch_gs_rb_fine(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
+                       hipStream_t st, KTimer* kt) {
+  launch_gs_rb_fine_tile<T, kRbfRows>(L, bx, by, bz, b, e, bold, st, kt, kRbfPlanes);
+}
+
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
                            const T* e, const Level& C, T* bc, bool c_split, hipStream_t st) {
@@ -1516,6 +1731,8 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
                                      const Level&, const T*, bool, hipStream_t, T*);                      \
   template void launch_gs_rb<T>(const Level&, const T*, const T*, const T*, const T*, T*, const T*,     \
                                 hipStream_t);                                                             \
+  template void launch_gs_rb_fine<T>(const Level&, const T*, const T*, const T*, const T*, T*, const T*,  \
+                                     hipStream_t, KTimer*);                                               \
   template void launch_resid_restrict<T>(const Level&, const T*, const T*, const T*, const T*, const T*,  \
                                          const Level&, T*, bool, hipStream_t);                            \
   template void launch_prolong<T>(const Level&, T*, const Level&, const T*, bool, hipStream_t);           \

@@ -121,6 +121,8 @@ def lib() -> C.CDLL:
             "ns_cfl_dt": ([vp, d, d, C.POINTER(C.c_double)], i),
             "ns_cfl_dt_noalloc": ([i, i, i, d, vp, vp, vp, d, d, vp, vp], i),
             "ns_phase_timing": ([vp, i], i),
+            "ns_set_fine_sweep": ([vp, i], i),
+            "ns_get_fine_sweep": ([vp, C.POINTER(i)], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
         }
@@ -138,7 +140,8 @@ EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum
             "ns_body_state", "ns_timing_enable", "ns_timing_read", "ns_time_kernel", "ns_net_param_count", "ns_net_workspace_bytes",
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
-            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target", "ns_cfl_dt", "ns_phase_timing", "ns_cfl_dt_noalloc"]
+            "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target", "ns_cfl_dt", "ns_phase_timing", "ns_cfl_dt_noalloc",
+            "ns_set_fine_sweep", "ns_get_fine_sweep"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
 LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 
@@ -304,6 +307,18 @@ class Solver:
         product after it, is one replay of a recorded HIP graph;
         LAUNCH_STREAM: the same kernels launched one by one."""
         self._chk("ns_set_launch_mode", lib().ns_set_launch_mode(self.ctx, mode))
+
+    def set_fine_sweep(self, fused: bool):
+        """The finest level's red-black sweeps as one launch each (True) or
+        as two colour passes (False); the library's default is the fused
+        launch on large 3-D grids."""
+        self._chk("ns_set_fine_sweep", lib().ns_set_fine_sweep(self.ctx, 1 if fused else 0))
+
+    def fine_sweep(self) -> bool:
+        """Whether the finest level's red-black sweeps run as one launch each."""
+        v = C.c_int()
+        self._chk("ns_get_fine_sweep", lib().ns_get_fine_sweep(self.ctx, C.byref(v)))
+        return bool(v.value)
 
     def timing_enable(self, kernel: int, max_launches: int):
         self._chk("ns_timing_enable", lib().ns_timing_enable(self.ctx, kernel, max_launches))
