@@ -32,7 +32,9 @@ Printed: ONE JSON line with
   projection_study  projection wall time and CG iterations to the same
                1e-10 true residual: FP64 V-cycle (zero and previous-pressure
                guesses), FP32 V-cycle (previous-pressure and learned guesses,
-               inference included), the per-field difference of the
+               inference included, and the per-step choice that runs the
+               network only where it is measured to pay), the learned guess's
+               break-even in CG iterations, the per-field difference of the
                FP32-V-cycle step from the FP64 one, the network forward's
                BF16 rate; on 512x256x256 and the two 256x128x128 tanks
   fsi_study, nwt_study, option_study  free heave, the numerical wave tank
@@ -263,10 +265,14 @@ NET_FLOP_PER_VOXEL = (2 * 27 * 4 * 16 + 2 * 27 * 48 * 16 + 2 * 16) + (2 * 27 * 1
 def projection_study(name: str, steps: int, warmup: int, weights: str):
     """Projection wall time and CG iterations to the same 1e-10 true residual
     on one workload for: FP64 V-cycle from zero and from the previous
-    pressure, FP32 V-cycle from the previous pressure, and FP32 V-cycle from
-    the learned guess (network inference included in the time).  Also the
-    per-field difference of the FP32-V-cycle step from the FP64 one, both
-    taken from the same state, and the network forward's matrix-core rate."""
+    pressure, FP32 V-cycle from the previous pressure, FP32 V-cycle from the
+    learned guess (network inference included in the time), and FP32 V-cycle
+    with the guess chosen per step (NS_X0_AUTO: inference only where it is
+    measured to pay).  The learned guess's break-even: the CG iterations its
+    inference costs at the FP32 V-cycle's time per iteration, against the
+    iterations it saves.  Also the per-field difference of the FP32-V-cycle
+    step from the FP64 one, both taken from the same state, and the network
+    forward's matrix-core rate."""
     import numpy as np
     import torch
 
@@ -283,15 +289,16 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
            "weights": os.path.relpath(weights, ROOT) if net is not None else None}
     variants = [("fp64", "zero"), ("fp64", "prev"), ("mixed", "prev")]
     if net is not None:
-        variants.append(("mixed", "learned"))
+        variants += [("mixed", "learned"), ("mixed", "auto")]
     for prec, x0 in variants:
         dev = ns.device_fields(f0)
         S = ns.Solver(ns.params(wl, prec=ns.PREC_FP64 if prec == "fp64" else ns.PREC_MIXED,
-                                x0={"zero": ns.X0_ZERO, "prev": ns.X0_PREV, "learned": ns.X0_LEARNED}[x0]), dev)
-        if x0 == "learned":
+                                x0={"zero": ns.X0_ZERO, "prev": ns.X0_PREV, "learned": ns.X0_LEARNED,
+                                    "auto": ns.X0_AUTO}[x0]), dev)
+        if x0 in ("learned", "auto"):
             S.attach_net(net)
         t, _, _ = timed_steps(S, wl, warmup)
-        ms, its, r0, res = [], [], [], []
+        ms, its, r0, res, used = [], [], [], [], []
         for _ in range(steps):
             dt = S.cfl_dt(wl.cfl, wl.dt_max)
             S.levelset_advect_reinit(dt)
@@ -303,15 +310,29 @@ def projection_study(name: str, steps: int, warmup: int, weights: str):
             its.append(st["iters"])
             r0.append(st["rel_resid0"])
             res.append(st["true_rel_resid"])
+            used.append(st["x0_used"])
             t += dt
         out[f"{prec}+{x0}"] = {"ms_median": round(statistics.median(ms), 4), "iters": its,
                                "mean_rel_resid0": float(np.mean(r0)), "max_true_rel_resid": max(res)}
+        if x0 == "auto":
+            out[f"{prec}+{x0}"].update({"ms_mean": round(statistics.mean(ms), 4), "x0_used": used,
+                                        "gain_iters": round(st["x0_gain"], 3)})
         log(f"[bench] {wl.name[:6]} projection {prec}+{x0}: {statistics.median(ms):.3f} ms, iters {its}")
         S.close()
     base = out["fp64+prev"]["ms_median"]
-    for k in ("mixed+prev", "mixed+learned"):
+    for k in ("mixed+prev", "mixed+learned", "mixed+auto"):
         if k in out:
             out[k]["speedup_vs_fp64_prev"] = round(base / out[k]["ms_median"], 3)
+    if "mixed+learned" in out:
+        # what inference costs in CG iterations of the FP32 V-cycle, and what it saves
+        mp, ml = out["mixed+prev"], out["mixed+learned"]
+        t_it = mp["ms_median"] / statistics.mean(mp["iters"])
+        saved = statistics.mean(mp["iters"]) - statistics.mean(ml["iters"])
+        cost_ms = ml["ms_median"] - mp["ms_median"] + saved * t_it
+        out["learned_break_even"] = {"ms_per_cg_iter": round(t_it, 4), "inference_ms": round(cost_ms, 4),
+                                     "break_even_iters": round(cost_ms / t_it, 2), "saved_iters": round(saved, 2)}
+        log(f"[bench] {wl.name[:6]} learned guess: inference {cost_ms:.3f} ms = {cost_ms / t_it:.2f} CG "
+            f"iterations, saves {saved:.2f}")
     # per-field difference of one step with the FP32 V-cycle from the FP64 one
     fields = {}
     for prec in (ns.PREC_FP64, ns.PREC_MIXED):

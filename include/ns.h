@@ -60,7 +60,15 @@ typedef enum {
 } ns_status;
 
 typedef enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 } ns_prec;   /* V-cycle precision   */
-typedef enum { NS_X0_ZERO = 0, NS_X0_PREV = 1, NS_X0_LEARNED = 2 } ns_x0;   /* projection guess */
+/* Projection guess.  NS_X0_AUTO: the learned guess only where it pays.  A
+ * step runs the network (a trial) on the first projection, whenever the
+ * iterations the learned guess saved on its trials, at the last solve's time
+ * per CG iteration, outweigh the inference's device time, and otherwise on
+ * every 8th step; the other steps start from p_prev without inference.  On a
+ * trial the residual of p_prev is measured beside the learned guess's, and
+ * the iterations saved are their log ratio over the last solve's log
+ * contraction per iteration (averaged over trials, the latest weighted 1/2). */
+typedef enum { NS_X0_ZERO = 0, NS_X0_PREV = 1, NS_X0_LEARNED = 2, NS_X0_AUTO = 3 } ns_x0;
 
 /* A rigid body given by an analytic level set psi (negative inside), built
  * from primitive distance functions with min/max (Sec. "Interface tracking":
@@ -115,7 +123,8 @@ typedef struct {
   int prec;                    /* ns_prec                                           */
   int x0;                      /* ns_x0                                             */
   double p_scale;              /* P0 of the learned guess p0 = p_prev + P0 delta,
-                                  e.g. rho_w g depth; > 0 when x0 = NS_X0_LEARNED  */
+                                  e.g. rho_w g depth; > 0 when x0 = NS_X0_LEARNED
+                                  or NS_X0_AUTO                                    */
   /* Numerical wave tank (Sec. "Numerical wave tank"); all zero: a closed
    * tank.  The tank generates the linear waves listed in waves[]:
    * eta = sum a cos(kappa x - omega t + phase), with potential-flow velocity
@@ -190,6 +199,10 @@ typedef struct {
    * the wave tank's zones and free bodies' forces), [5] the whole step;
    * [0], [1] and [5] are filled by ns_step only; [6], [7] are 0. */
   double t_ms[8];
+  int x0_used;             /* the guess the solve started from: NS_X0_ZERO, _PREV or
+                              _LEARNED (a non-finite learned guess counts as _PREV) */
+  double x0_gain;          /* NS_X0_AUTO: CG iterations the learned guess is estimated
+                              to save over p_prev after this step's update; else 0 */
 } ns_stats;
 
 /* Internal arrays a caller may inspect or fill through ns_buffer (device
@@ -381,7 +394,7 @@ ns_status ns_net_forward(ns_net* net, float* delta_out);
 ns_status ns_net_train_step(ns_net* net, const float* feat4, const float* target, const float* beta_x,
                             const float* beta_y, const float* beta_z, float lr, int update, double* loss);
 
-/* Use `net` (same grid) for x0 = NS_X0_LEARNED in this context. */
+/* Use `net` (same grid) for x0 = NS_X0_LEARNED or NS_X0_AUTO in this context. */
 ns_status ns_attach_net(ns_ctx* ctx, ns_net* net);
 
 /* The four features of the projection about to be solved (after

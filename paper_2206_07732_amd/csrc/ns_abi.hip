@@ -72,6 +72,14 @@ struct ns_ctx {
   } gs[16];           // recorded CG segments, keyed by kind and vectors
   int ngs;
   ns_net* net;        // learned guess (not owned)
+  struct {
+    double gain;      // CG iterations the learned guess saves over p_prev (trial average)
+    double t_inf;     // device time of the last inference (ms)
+    double t_it;      // wall time per CG iteration of the last solve (ms)
+    int trials;       // steps that ran the network so far
+    int since;        // steps since the last trial
+    hipEvent_t ev[2]; // around the last inference
+  } ax;               // x0 = NS_X0_AUTO
   int tail64, tail32; // first level of the LDS tail per precision (L: none)
   size_t lds64, lds32;
   double* pack64;     // the tail levels' bx, by, bz, 1/D (tail kernel's LDS image)
@@ -147,9 +155,9 @@ bool valid_params(const ns_params* P, char* why, size_t nwhy) {
   if (P->reinit_iters < 0 || P->nu_pre < 0 || P->nu_post < 0 || P->coarse_sweeps < 0 || P->max_iters < 0)
     return snprintf(why, nwhy, "iteration counts must be >= 0"), false;
   if (P->prec != NS_PREC_FP64 && P->prec != NS_PREC_MIXED) return snprintf(why, nwhy, "bad prec"), false;
-  if (P->x0 != NS_X0_ZERO && P->x0 != NS_X0_PREV && P->x0 != NS_X0_LEARNED)
+  if (P->x0 != NS_X0_ZERO && P->x0 != NS_X0_PREV && P->x0 != NS_X0_LEARNED && P->x0 != NS_X0_AUTO)
     return snprintf(why, nwhy, "bad x0"), false;
-  if (P->x0 == NS_X0_LEARNED && !(P->p_scale > 0.0))
+  if ((P->x0 == NS_X0_LEARNED || P->x0 == NS_X0_AUTO) && !(P->p_scale > 0.0))
     return snprintf(why, nwhy, "p_scale must be > 0 for the learned guess"), false;
   if (!(P->gen_len >= 0.0 && P->damp_len >= 0.0 && P->vort_width >= 0.0) || !std::isfinite(P->gen_len) ||
       !std::isfinite(P->damp_len) || !std::isfinite(P->vort_width))
@@ -996,7 +1004,8 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     ns_destroy(X);
     return NS_EHIP;
   }
-  if (hipEventCreateWithFlags(&X->ev_rr, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&X->ev_rr, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&X->ax.ev[0]) != hipSuccess || hipEventCreate(&X->ax.ev[1]) != hipSuccess) {
     ns_destroy(X);
     return NS_EHIP;
   }
@@ -1030,6 +1039,8 @@ void ns_destroy(ns_ctx* X) {
   for (int q = 0; q < X->ngs; ++q) (void)hipGraphExecDestroy(X->gs[q].exec);
   if (X->cap_st) (void)hipStreamDestroy(X->cap_st);
   if (X->ev_rr) (void)hipEventDestroy(X->ev_rr);
+  for (int q = 0; q < 2; ++q)
+    if (X->ax.ev[q]) (void)hipEventDestroy(X->ax.ev[q]);
   for (int q = 0; q < 6; ++q)
     if (X->ph_ev[q]) (void)hipEventDestroy(X->ph_ev[q]);
   if (X->host) (void)hipHostFree(X->host);
@@ -1343,29 +1354,69 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
   X->ph_step = false;
   if (timed) HIPCHK(X, hipEventRecord(X->ph_ev[2], st));
   launch_rhs(ph, X->us, X->vs, X->ws, dt, X->b, st);
-  int fallback = 0;
-  if (X->P.x0 == NS_X0_ZERO) {
+  int fallback = 0, used = X->P.x0;
+  bool trial = false;
+  double rel_prev = 0.0;
+  if (X->P.x0 == NS_X0_AUTO) {
+    if (!X->net) return fail(X, NS_ESTATE, "x0 = NS_X0_AUTO needs ns_attach_net");
+    constexpr int kAutoRetry = 8;
+    trial = X->ax.trials == 0 || X->ax.since + 1 >= kAutoRetry || X->ax.gain * X->ax.t_it > X->ax.t_inf;
+    used = trial ? NS_X0_LEARNED : NS_X0_PREV;
+  }
+  if (used == NS_X0_ZERO) {
     launch_fill<double>(X->F.p, X->nc, st);
-  } else if (X->P.x0 == NS_X0_LEARNED) {
+  } else if (used == NS_X0_LEARNED) {
     // p0 = p_prev + P0 delta(features of b, rho, p_prev); p_prev if not finite
     ns_net* N = X->net;
     if (!N) return fail(X, NS_ESTATE, "x0 = NS_X0_LEARNED needs ns_attach_net");
     const Level& L0 = X->lev[0];
     double* pprev = net_pprev(N);
     launch_copy(X->F.p, pprev, X->nc, st);
+    if (trial) {
+      // ||b - A p_prev||: the residual the step would start from without the network
+      const CgScratch cs{X->partials, X->scal, X->host_dev, X->hpart_dev};
+      launch_resid_norm(L0.n, X->P.h, L0.bx, L0.by, L0.bz, X->b, pprev, X->r, cs, FIN_RESID0, st);
+      HIPCHK(X, hipEventRecord(X->ax.ev[0], st));
+    }
     launch_apply_A(L0.n, X->P.h, L0.bx, L0.by, L0.bz, pprev, net_Ap(N), st);
     net_features(N, L0.n, X->P.h, X->P.rho_w, X->P.rho_a, X->P.p_scale, X->b, X->rho, pprev, net_Ap(N),
                  net_feat(N), st);
-    if (net_guess(N, X->P.p_scale, X->F.p, st) != 0) {
+    if (net_guess(N, X->P.p_scale, X->F.p, st, trial ? X->ax.ev[1] : nullptr) != 0) {
       launch_copy(pprev, X->F.p, X->nc, st);
       fallback = 1;
+      used = NS_X0_PREV;
+    }
+    if (trial) {   // net_guess synchronised the stream
+      const double bb = host_total(X, 2, 1, S_BB), rr = host_total(X, 2, 0, S_RR);
+      rel_prev = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+      float ms = 0.f;
+      HIPCHK(X, hipEventElapsedTime(&ms, X->ax.ev[0], X->ax.ev[1]));
+      X->ax.t_inf = ms;
     }
   }
   ns_stats S{};
   if (timed) HIPCHK(X, hipEventRecord(X->ph_ev[3], st));
+  const double tc = now_ms();
   ns_status s = pcg(X, &S);
   S.x0_fallback = fallback;
+  S.x0_used = used;
   S.cn_sweeps = X->last_cn;
+  if (X->P.x0 == NS_X0_AUTO && (s == NS_OK || s == NS_ENOCONV)) {
+    X->ax.t_it = (now_ms() - tc) / (S.iters > 0 ? S.iters : 1);
+    if (trial) {
+      // iterations saved: log(r_prev / r_learned) over the solve's log contraction per iteration
+      double saved = 0.0;
+      const double q = S.iters > 0 && S.rel_resid0 > 0.0 ? std::pow(S.rel_resid / S.rel_resid0, 1.0 / S.iters) : 0.0;
+      if (!fallback && q > 0.0 && q < 1.0 && rel_prev > 0.0 && S.rel_resid0 > 0.0)
+        saved = std::log(rel_prev / S.rel_resid0) / -std::log(q);
+      if (std::isfinite(saved)) X->ax.gain = X->ax.trials == 0 ? saved : 0.5 * (X->ax.gain + saved);
+      ++X->ax.trials;
+      X->ax.since = 0;
+    } else {
+      ++X->ax.since;
+    }
+    S.x0_gain = X->ax.gain;
+  }
   if (s != NS_OK && s != NS_ENOCONV) {
     if (stats) *stats = S;
     return s;

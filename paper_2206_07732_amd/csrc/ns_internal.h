@@ -272,7 +272,7 @@ int net_matches(const ns_net* N, const Dims& n);
 double* net_pprev(ns_net* N);
 double* net_Ap(ns_net* N);
 float* net_feat(ns_net* N);
-int net_guess(ns_net* N, double P0, double* p, hipStream_t st);
+int net_guess(ns_net* N, double P0, double* p, hipStream_t st, hipEvent_t done = nullptr);
 void net_target(long nv, const double* p, const double* pprev, double P0, float* t, hipStream_t st);
 
 }  // namespace nsk

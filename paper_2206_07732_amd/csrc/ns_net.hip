@@ -1171,8 +1171,9 @@ double* net_Ap(ns_net* N) { return N->Ap; }
 float* net_feat(ns_net* N) { return N->feat; }
 
 // p = p_prev + P0 delta from the current features; returns the number of
-// non-finite outputs (device counter read back synchronously)
-int net_guess(ns_net* N, double P0, double* p, hipStream_t st) {
+// non-finite outputs (device counter read back synchronously); done, if
+// given, is recorded once p is written
+int net_guess(ns_net* N, double P0, double* p, hipStream_t st, hipEvent_t done) {
   hipStream_t keep = N->st;
   N->st = st;
   if (N->training) hipLaunchKernelGGL(k_set_input, g1(N->v0), dim3(256), 0, st, N->v0, N->feat, N->x0);
@@ -1180,6 +1181,7 @@ int net_guess(ns_net* N, double P0, double* p, hipStream_t st) {
   (void)hipMemsetAsync(N->bad, 0, sizeof(int), st);
   hipLaunchKernelGGL(k_finite_count, g1(N->v0), dim3(256), 0, st, N->v0, N->delta, N->bad);
   hipLaunchKernelGGL(k_apply_delta, g1(N->v0), dim3(256), 0, st, N->v0, N->pprev, N->delta, P0, p);
+  if (done) (void)hipEventRecord(done, st);
   int bad = 0;
   (void)hipMemcpyAsync(N->host, N->bad, sizeof(int), hipMemcpyDeviceToHost, st);
   (void)hipStreamSynchronize(st);

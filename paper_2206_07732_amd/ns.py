@@ -20,7 +20,7 @@ NS_OK, NS_EINVAL, NS_ENOCONV, NS_ENAN, NS_EHIP, NS_ESTATE, NS_EUNSTABLE = 0, -1,
 STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_ENOCONV", -3: "NS_ENAN", -4: "NS_EHIP", -5: "NS_ESTATE",
           -6: "NS_EUNSTABLE"}
 PREC_FP64, PREC_MIXED = 0, 1
-X0_ZERO, X0_PREV, X0_LEARNED = 0, 1, 2
+X0_ZERO, X0_PREV, X0_LEARNED, X0_AUTO = 0, 1, 2, 3
 BUF = {"us": 0, "vs": 1, "ws": 2, "bx": 3, "by": 4, "bz": 5, "rhs": 6, "rho": 7, "mu": 8, "chi": 9,
        "rho_flow": 10, "bxf": 11, "byf": 12, "bzf": 13}
 
@@ -59,7 +59,8 @@ class NSFields(C.Structure):
 class NSStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_resid0", C.c_double),
                 ("rel_resid", C.c_double), ("true_rel_resid", C.c_double), ("ms", C.c_double),
-                ("x0_fallback", C.c_int), ("cn_sweeps", C.c_int), ("t_ms", C.c_double * 8)]
+                ("x0_fallback", C.c_int), ("cn_sweeps", C.c_int), ("t_ms", C.c_double * 8),
+                ("x0_used", C.c_int), ("x0_gain", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

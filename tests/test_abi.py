@@ -61,6 +61,13 @@ def test_workspace_size_and_validation(nslib):
     assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
     bad = nslib.params(wl, prec=7)
     assert L.ns_workspace_bytes(ctypes.byref(bad)) == 0
+    # the guess modes: 0..3, and the two that run the network need P0 > 0
+    for x0 in (nslib.X0_ZERO, nslib.X0_PREV, nslib.X0_LEARNED, nslib.X0_AUTO):
+        assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, x0=x0))) == nb
+    assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, x0=4))) == 0
+    for x0 in (nslib.X0_LEARNED, nslib.X0_AUTO):
+        assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, x0=x0, p_scale=0.0))) == 0
+    assert L.ns_workspace_bytes(ctypes.byref(nslib.params(wl, x0=nslib.X0_PREV, p_scale=0.0))) == nb
     # indices are 32-bit: the largest face array must stay under 2e9 entries
     # (here nx (ny+1) nz = 2.002e9 while the cell count is 1.992e9)
     bad = nslib.params(wl)

@@ -204,3 +204,40 @@ def test_learned_guess_in_projection(orc):
     S2.momentum_step(dt, dt)
     with pytest.raises(ns.NSError):
         S2.projection_solve(dt)
+
+
+def test_auto_guess_skips_a_network_that_cannot_win(orc):
+    """x0 = NS_X0_AUTO with a network whose weights are all zero: its guess is
+    p_prev bit for bit, so its trials measure no saving and the solver runs
+    it only on the first step and on every 8th step after; every step is
+    bitwise the one of x0 = NS_X0_PREV, with the same CG count."""
+    ns = _ns()
+    wl = I.workload("tiny3d")
+    f = I.make_fields(wl)
+    net = ns.Net(wl.nx, wl.ny, wl.nz)
+    net.set_params(np.zeros(N.param_count(), dtype=np.float32))
+    dev_a, dev_p = ns.device_fields(f), ns.device_fields(f)
+    SA = ns.Solver(ns.params(wl, x0=ns.X0_AUTO), dev_a)
+    SA.attach_net(net)
+    SP = ns.Solver(ns.params(wl, x0=ns.X0_PREV), dev_p)
+    used, t = [], 0.0
+    for s in range(18):
+        dt = SP.cfl_dt(wl.cfl, wl.dt_max)
+        assert SA.cfl_dt(wl.cfl, wl.dt_max) == dt
+        a, b = SA.step(dt, t), SP.step(dt, t)
+        t += dt
+        used.append(a["x0_used"])
+        assert b["x0_used"] == ns.X0_PREV and b["x0_gain"] == 0.0
+        assert a["x0_gain"] == 0.0 and a["x0_fallback"] == 0
+        assert a["iters"] == b["iters"] and a["converged"] == 1
+    print(f"[auto guess] guesses used: {used}", flush=True)
+    assert used == [2] + [1] * 7 + [2] + [1] * 7 + [2, 1]
+    for k in dev_a:
+        assert torch.equal(dev_a[k], dev_p[k]), k
+    # without an attached network the mode is refused at the projection
+    S2 = ns.Solver(ns.params(wl, x0=ns.X0_AUTO), ns.device_fields(f))
+    S2.levelset_advect_reinit(dt)
+    S2.momentum_step(dt, dt)
+    with pytest.raises(ns.NSError) as e:
+        S2.projection_solve(dt)
+    assert e.value.status == ns.NS_ESTATE
