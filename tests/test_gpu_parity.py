@@ -39,9 +39,11 @@ def case(name):
                           bodies=[I.Body(1, (2.0, 0.17, 0.0), (0.3, 0.7, 1.5))])
     if name == "odd1level":
         # odd nx: a single level, too large for the single-workgroup tail,
-        # so the coarsest-level sweeps run with the multi-block kernels
-        return I.workload("tiny3d", nx=129, ny=8, nz=8, h=4.0 / 129, seed=22,
-                          bodies=[I.Body(1, (2.0, 0.15, 0.0), (0.1, 0.7, 1.5))])
+        # so the coarsest-level sweeps run with the multi-block kernels; the
+        # 0.25 m-tall tank is half water, and the cylinder pierces the surface
+        return I.workload("tiny3d", nx=129, ny=8, nz=8, h=4.0 / 129, seed=22, depth=0.124,
+                          wave={"kind": "airy", "a": 0.01, "T": 1.2, "phase": 0.0},
+                          bodies=[I.Body(1, (2.0, 0.124, 0.0), (0.08, 0.05, 0.2))])
     if name == "rbragged":
         # a coarse level (48x20x12) whose rows fit the fused red-black pass,
         # with ragged row and plane tiles
@@ -201,8 +203,9 @@ def test_operator_and_vcycle_parity(orc):
         torch.cuda.synchronize()
         zo32 = orc.vcycle(orc.params(wl, prec=1), bx, by, bz, x)
         # both sides run the cycle in FP32; only the order of FP32 roundings
-        # differs (observed ~6e-8 relative)
-        gate(f"{name} V-cycle fp32", y, zo32, 1e-6, float(np.max(np.abs(zo32))))
+        # differs (observed on these eight grids: relative L2 4e-8 to 8.5e-8,
+        # largest elementwise difference 0.7e-7 to 2.1e-7 of the largest value)
+        gate(f"{name} V-cycle fp32", y, zo32, 5e-7, float(np.max(np.abs(zo32))))
 
 
 def test_mixed_precision_projection_meets_fp64_tolerance(orc):

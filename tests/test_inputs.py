@@ -85,3 +85,23 @@ def test_seeded_inputs_are_reproducible():
         assert np.array_equal(a[k], b[k])
     c = I.make_fields(I.workload("tiny3d", seed=99))
     assert not np.array_equal(a["sigma"], c["sigma"])
+
+
+def test_parity_cases_hold_an_interface_and_a_body_crossing_it():
+    """Every 3-D stage-parity case has water and air, and each body reaches
+    from the water into the air (a case whose body sits outside the water, or
+    whose tank is all water, would leave the interface and penalisation terms
+    untested)."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_gpu_parity import STAGE_CASES, case
+    for name in STAGE_CASES:
+        wl = case(name)
+        f = I.make_fields(wl)
+        assert f["sigma"].min() < 0.0 < f["sigma"].max(), name
+        top = wl.nz * wl.h
+        for b in wl.bodies:
+            if b.kind == 1:                      # cylinder: half = (R, z_bottom, z_top)
+                assert b.half[1] < wl.depth < b.half[2] and b.half[1] < top, name
+                assert 0.0 < b.c[0] < wl.nx * wl.h and (wl.ny == 1 or 0.0 < b.c[1] < wl.ny * wl.h), name
