@@ -1398,6 +1398,34 @@ __global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const doubl
 }
 
 
+// first stage of a large reduction: block g sums partials [g W, (g + 1) W),
+// W = 4 x 1024, thread t the four consecutive ones from g W + 4 t in order,
+// then the block's fixed tree; out[nv g + q] gets the block's sums
+constexpr int kFinChunk = 4 * 1024;
+__global__ void __launch_bounds__(1024) k_finalize_chunks(const double* __restrict__ partials, int nparts, int nv,
+                                                          double* __restrict__ out) {
+  const int q0 = (int)blockIdx.x * kFinChunk + 4 * (int)threadIdx.x;
+  double a[4], c[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = min(q0 + u, nparts - 1);
+    a[u] = partials[nv * q];
+    c[u] = nv > 1 ? partials[nv * q + 1] : 0.0;
+  }
+  double v[2] = {0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (q0 + u < nparts) {
+      v[0] += a[u];
+      v[1] += c[u];
+    }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    out[nv * (size_t)blockIdx.x] = v[0];
+    if (nv > 1) out[nv * (size_t)blockIdx.x + 1] = v[1];
+  }
+}
+
 // fixed-order sum of the per-block partials and the CG scalar recurrences;
 // the values the host tests are also stored to its pinned mirror
 template <int B>
@@ -1654,17 +1682,31 @@ int cg_blocks(const Dims& n) {
 
 static void finalize(const CgScratch& cs, int nparts, int mode, hipStream_t st) {
   const int nv = (mode == FIN_RESID0 || mode == FIN_TRR || mode == FIN_BETA) ? 2 : 1;
+  const double* src = cs.partials;
+  // Beyond one batch of 16 loads per thread, one workgroup walking every
+  // partial waits on a chain of batches (27 us for the 131072 blocks of a
+  // 512 x 256 x 256 level): the chunks are summed first, one workgroup
+  // each, into the partials buffer's free room after the nv * nparts values
+  // (the buffer holds 4 per block of the finest level; nv <= 2), and their
+  // sums finalized.  Up to one batch a single launch is cheaper.
+  if (nparts > 16 * 1024) {
+    const int G = (nparts + kFinChunk - 1) / kFinChunk;
+    double* mid = cs.partials + (size_t)nv * nparts;
+    hipLaunchKernelGGL(k_finalize_chunks, dim3(G), dim3(1024), 0, st, cs.partials, nparts, nv, mid);
+    src = mid;
+    nparts = G;
+  }
   // loads per thread per batch: as many as the partials need, at most 16
   const int per = (nparts + 1023) / 1024;
   const dim3 g(1), b(1024);
   if (per <= 1)
-    hipLaunchKernelGGL(k_finalize<1>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+    hipLaunchKernelGGL(k_finalize<1>, g, b, 0, st, src, nparts, nv, mode, cs.scal, cs.hscal);
   else if (per <= 2)
-    hipLaunchKernelGGL(k_finalize<2>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+    hipLaunchKernelGGL(k_finalize<2>, g, b, 0, st, src, nparts, nv, mode, cs.scal, cs.hscal);
   else if (per <= 4)
-    hipLaunchKernelGGL(k_finalize<4>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+    hipLaunchKernelGGL(k_finalize<4>, g, b, 0, st, src, nparts, nv, mode, cs.scal, cs.hscal);
   else
-    hipLaunchKernelGGL(k_finalize<16>, g, b, 0, st, cs.partials, nparts, nv, mode, cs.scal, cs.hscal);
+    hipLaunchKernelGGL(k_finalize<16>, g, b, 0, st, src, nparts, nv, mode, cs.scal, cs.hscal);
 }
 
 void launch_finalize_beta(const CgScratch& cs, int nparts, hipStream_t st) { finalize(cs, nparts, FIN_BETA, st); }
