@@ -452,11 +452,12 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
     rw[u] = bold[W ? rp[u] - (size_t)((ri[u] & 1) ? 0 : 1) : rp[u]];
     re[u] = bold[E ? rp[u] + (size_t)((ri[u] & 1) ? 1 : 0) : rp[u]];
   }
-  // this thread's black cell: pair px of row (ty0 + py, tz0 + pz)
+  // this thread's black cell: pair px of row (ty0 + py, tz0 + pz); the tile
+  // has exactly kRbThreads cells (TX TY TZ = kRbThreads), so pz < TZ
   const int px = t % TX, py = (t / TX) % TY, pz = t / (TX * TY);
   const int jb = ty0 + py, kb = tz0 + pz;
   const int ib = 2 * px + 1 - ((jb + kb) & 1);
-  const bool bok = pz < TZ && jb < n.ny && kb < n.nz && ib < n.nx;
+  const bool bok = jb < n.ny && kb < n.nz && ib < n.nx;
   const int jc = bok ? jb : 0, kc = bok ? kb : 0, ic = bok ? ib : 1;
   const size_t pb = (size_t)(ic >> 1) + (size_t)sg.hx * (jc + (size_t)n.ny * kc);
   const size_t cb = ic + (size_t)n.nx * jc + sxy * kc;
@@ -499,14 +500,14 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
 //     of the red cell below it, both in the same pair column, which the same
 //     thread computes on the planes above and below;
 //   * its x-faces are the faces of the red cell of its own pair and of the
-//     adjacent pair (the adjacent lane: a wave is 64 consecutive pairs of a
-//     row);
+//     adjacent pair (the adjacent lane: a row of the block is LN consecutive
+//     pairs, one wave for LN = 64);
 //   * its y-faces are those of the red cells of the rows beside it (LDS).
-// A block is 64 lanes by TY + 2 rows of pairs and marches up a chunk of KZ
+// A block is LN lanes by TY + 2 rows of pairs and marches up a chunk of KZ
 // planes: at plane m it forms the red values of plane m, then the black
 // values of plane m - 1, whose red neighbours are then all known.  The first
 // and last rows form a ring whose red values the block's own black cells
-// read; so do lanes 0 and 63 when a row has more than 64 pairs.  Ring values
+// read; so do lanes 0 and LN - 1 when a row has more than LN pairs.  Ring values
 // are recomputed (the neighbouring block forms and stores them too) and
 // only the inner lanes and rows store.  Red values are formed from the
 // black plane as it stood before the launch, which the previous kernel
@@ -521,8 +522,6 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
 // plane m is computed, and waits only at its first use one plane later; the
 // loop is unrolled by two so that the two planes' registers alternate
 // without copies.
-constexpr int kRbfLanes = 64;
-
 template <typename T>
 struct RbfLoads {
   T fw, fe, fs, fn, fd, fu;  // the faces of the red cell of plane m
@@ -530,39 +529,39 @@ struct RbfLoads {
   T bo_u;                    // this pair's black value (before the launch) on plane m + 1
   T xo, yo;                  // black values beside the ring (row ends, ring rows) on plane m
   T bb;                      // the right-hand side of this pair's black cell on plane m - 1
-  T xf;                      // that cell's outer x-face, for a row's end lanes
+  T xf;                      // that cell's outer x-face, for a block row's end lanes
 };
 
-template <typename T, int TY>
-__global__ void __launch_bounds__(kRbfLanes * (TY + 2)) k_gs_rb_fine(Dims n, T h2, const T* __restrict__ bx,
+template <typename T, int TY, int LN>
+__global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, const T* __restrict__ bx,
                                                                      const T* __restrict__ by,
                                                                      const T* __restrict__ bz,
                                                                      const T* __restrict__ b, T* __restrict__ e,
                                                                      const T* __restrict__ bold, int KZ) {
   constexpr int R = TY + 2;
-  __shared__ T BO[2][R][kRbfLanes];    // black values (as before the launch) of a plane
-  __shared__ T RN[2][R][kRbfLanes];    // red values of a plane
-  __shared__ T RYS[2][R][kRbfLanes];   // their south and north faces
-  __shared__ T RYN[2][R][kRbfLanes];
+  __shared__ T BO[2][R][LN];    // black values (as before the launch) of a plane
+  __shared__ T RN[2][R][LN];    // red values of a plane
+  __shared__ T RYS[2][R][LN];   // their south and north faces
+  __shared__ T RYN[2][R][LN];
   const SplitGeo sg = split_geo(n);
   const Tile tl = xcd_tile();
   const int lane = threadIdx.x, r = threadIdx.y;
-  const int xr = sg.hx > kRbfLanes ? 1 : 0;   // ring lanes only where a row spans several blocks
-  const int ti = tl.x * (kRbfLanes - 2 * xr) - xr + lane, j = tl.y * TY - 1 + r;
+  const int xr = sg.hx > LN ? 1 : 0;   // ring lanes only where a row spans several blocks
+  const int ti = tl.x * (LN - 2 * xr) - xr + lane, j = tl.y * TY - 1 + r;
   const bool ok = ti >= 0 && ti < sg.hx && j >= 0 && j < n.ny;
-  const bool inner = ok && lane >= xr && lane < kRbfLanes - xr && r >= 1 && r <= TY;
+  const bool inner = ok && lane >= xr && lane < LN - xr && r >= 1 && r <= TY;
   const int tic = min(max(ti, 0), sg.hx - 1), jc = min(max(j, 0), n.ny - 1);
   const int k0 = tl.z * KZ, kz1 = min(k0 + KZ, n.nz);
   const size_t sz = (size_t)sg.hx * n.ny;                 // pairs per plane
   const size_t prow = (size_t)tic + (size_t)sg.hx * jc;   // this pair in plane 0
   // the pairs whose black values the ring reads: the adjacent pair for a
   // row's end lanes, the adjacent row for the ring rows (others: their own)
-  const size_t xrow = (size_t)(lane == 0 ? max(tic - 1, 0) : lane == kRbfLanes - 1 ? min(tic + 1, sg.hx - 1) : tic) +
+  const size_t xrow = (size_t)(lane == 0 ? max(tic - 1, 0) : lane == LN - 1 ? min(tic + 1, sg.hx - 1) : tic) +
                       (size_t)sg.hx * jc;
   const size_t yrow = (size_t)tic + (size_t)sg.hx * (r == 0 ? max(jc - 1, 0) : r == R - 1 ? min(jc + 1, n.ny - 1) : jc);
-  // the outer x-face of a black cell on a row's end lane: the west face of
-  // an even column on lane 0, the east face of an odd one on lane 63 (a
-  // shuffle there would return the lane's own face)
+  // the outer x-face of a black cell on a block row's end lane: the west
+  // face of an even column on lane 0, the east face of an odd one on lane
+  // LN - 1 (a shuffle there would return the lane's own face)
   const int xfi = lane == 0 ? 2 * ti : 2 * ti + 2;
   const size_t fxs = (size_t)(n.nx + 1) * n.ny, fys = (size_t)n.nx * (n.ny + 1), fzs = (size_t)n.nx * n.ny;
   const auto clampz = [&](int m) { return (size_t)min(max(m, 0), n.nz - 1); };
@@ -601,10 +600,10 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 2)) k_gs_rb_fine(Dims n, T h
     const T bo_u = (ok && m + 1 >= 0 && m + 1 < n.nz) ? L.bo_u : (T)0;
     // x neighbours: this pair's black cell and the adjacent pair's (the
     // adjacent lane; the row's end lanes loaded theirs)
-    const T bl = __shfl_up(bo_c, 1, kRbfLanes), br = __shfl_down(bo_c, 1, kRbfLanes);
+    const T bl = __shfl_up(bo_c, 1, LN), br = __shfl_down(bo_c, 1, LN);
     const T xo = live ? L.xo : (T)0, yo = live ? L.yo : (T)0;
     const T vw = par == 0 ? (lane > 0 ? bl : xo) : bo_c;
-    const T ve = par == 1 ? (lane < kRbfLanes - 1 ? br : xo) : bo_c;
+    const T ve = par == 1 ? (lane < LN - 1 ? br : xo) : bo_c;
     const T vs = r > 0 ? BO[m & 1][r - 1][lane] : yo;
     const T vn = r < R - 1 ? BO[m & 1][r + 1][lane] : yo;
     T rv = (T)0;
@@ -619,8 +618,8 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 2)) k_gs_rb_fine(Dims n, T h
     BO[(m + 1) & 1][r][lane] = bo_u;
     // the adjacent lanes' red values and x-faces of plane m - 1 (every lane
     // takes part in the shuffles)
-    const T xfe = __shfl_up(fe1, 1, kRbfLanes), xrl = __shfl_up(rv1, 1, kRbfLanes);
-    const T xfw = __shfl_down(fw1, 1, kRbfLanes), xrr = __shfl_down(rv1, 1, kRbfLanes);
+    const T xfe = __shfl_up(fe1, 1, LN), xrl = __shfl_up(rv1, 1, LN);
+    const T xfw = __shfl_down(fw1, 1, LN), xrr = __shfl_down(rv1, 1, LN);
     __syncthreads();
     // ---- the black cell of this pair on plane m - 1 (inner threads)
     const int mb = m - 1;
@@ -628,7 +627,7 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 2)) k_gs_rb_fine(Dims n, T h
       const int ib = iru;      // the black cell of plane m - 1 shares the column of plane m's red cell
       if (ib < n.nx) {
         const bool even = (ib & 1) == 0;
-        const T bw = lane > 0 ? xfe : L.xf, be = lane < kRbfLanes - 1 ? xfw : L.xf;
+        const T bw = lane > 0 ? xfe : L.xf, be = lane < LN - 1 ? xfw : L.xf;
         const GsIn<T> g{even ? bw : fe1, even ? fw1 : be, RYN[mb & 1][r - 1][lane], RYS[mb & 1][r + 1][lane],
                         fu2, L.fd, RN[mb & 1][r - 1][lane], RN[mb & 1][r + 1][lane], rv2, rv};
         e[sg.P + prow + sz * (size_t)mb] = gs_combine<T>(n, g, h2, L.bb, ib, j, mb, even ? xrl : rv1, even ? rv1 : xrr);
@@ -1525,10 +1524,12 @@ static bool gs_rb_tile(const Dims& n, int& TX, int& TY, int& TZ) {
   if (hx > 32) return false;
   TX = hx > 16 ? 32 : hx > 8 ? 16 : 8;
   TY = n.ny > 1 ? 4 : 1;
+  // TX TY is 8 to 128, a divisor of kRbThreads: the tile has one black cell
+  // per thread
+  static_assert(kRbThreads % (32 * 4) == 0, "every TX TY divides the block");
   TZ = kRbThreads / (TX * TY);
-  // every thread's black cell inside the tile, and the ring-extended tile
-  // within the kernel's LDS and its unrolled loads
-  return TX * TY * TZ == kRbThreads && TX * (TY + (n.ny > 1 ? 2 : 0)) * (TZ + 2) <= kRbMaxExt;
+  // the ring-extended tile within the kernel's LDS and its unrolled loads
+  return TX * (TY + (n.ny > 1 ? 2 : 0)) * (TZ + 2) <= kRbMaxExt;
 }
 
 bool gs_rb_fits(const Dims& n) {
@@ -1548,13 +1549,19 @@ void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T
 
 // the finest level's fused red-black sweep: where it applies (a 3-D level
 // whose rows fill at least half a wave), where it pays, and its launch.  A
-// block runs TY + 2 rows of 64 lanes (1024 threads) up KZ planes.
+// block runs TY + 2 rows of LN lanes (1024 threads) up KZ planes.  A block
+// holds its compute unit for its whole march, so whole rounds of blocks
+// matter: on 512 x 256 x 256, 64 x 16 blocks up 32 planes (760 blocks, 2.97
+// rounds of 256) took 412 us a sweep, 32 x 32 blocks (648, of which the
+// third round is half empty) 431 us though they re-read fewer ring rows,
+// and 16 x 64 blocks 498 us.
+constexpr int kRbfLanes = 64;   // lanes of a block row (LN)
 constexpr int kRbfRows = 14;    // inner rows of a block (TY)
 constexpr int kRbfPlanes = 32;  // planes a block marches (KZ)
 
-static dim3 rbf_grid(const Dims& n, int TY, int KZ) {
+static dim3 rbf_grid(const Dims& n, int TY, int KZ, int LN) {
   const int hx = (n.nx + 1) / 2;
-  const int step = hx > kRbfLanes ? kRbfLanes - 2 : kRbfLanes;   // inner lanes of a block
+  const int step = hx > LN ? LN - 2 : LN;   // inner lanes of a block
   return dim3((hx + step - 1) / step, (n.ny + TY - 1) / TY, (n.nz + KZ - 1) / KZ);
 }
 
@@ -1564,33 +1571,34 @@ bool gs_rb_fine_fits(const Dims& n) {
 
 // A block's march is a chain of dependent planes, so the launch wins over
 // two colour passes only where its blocks fill every compute unit at least
-// twice (measured: 760 blocks on 512 x 256 x 256 beat the two passes by a
-// sixth; 120 on 256 x 128 x 128 lose by a tenth).
+// twice (measured: 760 blocks of 64 x 16 on 512 x 256 x 256 beat the two
+// passes by a sixth; 120 on 256 x 128 x 128 lose by a tenth).
 bool gs_rb_fine_pays(const Dims& n) {
   if (!gs_rb_fine_fits(n)) return false;
-  const dim3 g = rbf_grid(n, kRbfRows, kRbfPlanes);
+  const dim3 g = rbf_grid(n, kRbfRows, kRbfPlanes, kRbfLanes);
   return (long)g.x * g.y * g.z >= 512;
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int LN>
 void launch_gs_rb_fine_tile(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
                             hipStream_t st, KTimer* kt, int KZ) {
-  const dim3 grid = rbf_grid(L.n, TY, KZ);
-  const dim3 blk(kRbfLanes, TY + 2);
+  static_assert(LN * (TY + 2) == 1024, "a block of 1024 threads");
+  const dim3 grid = rbf_grid(L.n, TY, KZ, LN);
+  const dim3 blk(LN, TY + 2);
   const T h2 = (T)(L.h * L.h);
   if (kt && kt->n < kt->cap) {
-    hipExtLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
-                          h2, bx, by, bz, b, e, bold, KZ);
+    hipExtLaunchKernelGGL((k_gs_rb_fine<T, TY, LN>), grid, blk, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0,
+                          L.n, h2, bx, by, bz, b, e, bold, KZ);
     ++kt->n;
     return;
   }
-  hipLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, L.n, h2, bx, by, bz, b, e, bold, KZ);
+  hipLaunchKernelGGL((k_gs_rb_fine<T, TY, LN>), grid, blk, 0, st, L.n, h2, bx, by, bz, b, e, bold, KZ);
 }
 
 template <typename T>
 void launch_gs_rb_fine(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
                        hipStream_t st, KTimer* kt) {
-  launch_gs_rb_fine_tile<T, kRbfRows>(L, bx, by, bz, b, e, bold, st, kt, kRbfPlanes);
+  launch_gs_rb_fine_tile<T, kRbfRows, kRbfLanes>(L, bx, by, bz, b, e, bold, st, kt, kRbfPlanes);
 }
 
 template <typename T>

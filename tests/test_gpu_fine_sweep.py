@@ -1,13 +1,18 @@
 """The finest level's fused red-black sweep (one launch per sweep, each face
 coefficient read once) against the same sweep as two colour passes, through
 the C ABI: V-cycles and whole steps must agree bit for bit, in FP64 and
-with the FP32 V-cycle.  Rows of at most 64 pairs run without ring lanes
-(lanes 0 and 63 are cells of the grid): the C2 tank (64 pairs), a 127-cell
-row (64 pairs, the last a single cell), the half-resolution tank (32
-pairs), a ragged 70-cell row (35 pairs).  Longer rows take ring lanes: a
-132-cell row (two blocks, the second with 4 of its 62 inner pairs).  Rows
-and planes are not multiples of the block's 14 rows and 32 planes, and one
-grid has several plane chunks (100 planes: three of 32 and one of 4)."""
+with the FP32 V-cycle.  A block is 64 lanes by 16 rows of cell pairs (14
+inner) marching up 32 planes.  Rows of at most 64 pairs run without ring
+lanes (lanes 0 and 63 are cells of the grid when the row has 64 pairs):
+C2's 64, a 127-cell row (64 pairs, the last a single cell), the
+half-resolution tank (32 pairs), a 63-cell row (32 pairs, the last single)
+and a ragged 35 pairs.  Longer rows take ring lanes: 66 pairs (two blocks,
+the second with 4 of its 62 inner pairs).  The grids' rows and planes are
+not multiples of the block's 14 rows and 32 planes, several span more than
+one row block, and one has several plane chunks (100 planes: three of 32
+and one of 4)."""
+
+
 import numpy as np
 import pytest
 
@@ -24,6 +29,9 @@ def _ns():
 
 def case(name):
     from test_gpu_parity import case as parity_case
+    if name == "g63":
+        return I.workload("tiny3d", nx=63, ny=40, nz=20, h=4.0 / 63, seed=33,
+                          bodies=[I.Body(1, (2.0, 0.8, 0.0), (0.3, 0.7, 1.5))])
     if name == "g127":
         return I.workload("tiny3d", nx=127, ny=20, nz=40, h=4.0 / 127, seed=32,
                           bodies=[I.Body(1, (2.0, 0.3, 0.0), (0.3, 0.7, 1.5))])
@@ -35,7 +43,7 @@ def case(name):
     return parity_case(name)
 
 
-CASES = ["c2", "g127", "c2half", "ragged3d", "rbragged", "g132"]
+CASES = ["c2", "g63", "g127", "c2half", "ragged3d", "rbragged", "g132"]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -62,7 +70,7 @@ def test_fused_sweep_vcycle_is_bitwise_the_two_passes(orc, name, prec):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["c2", "g127", "g132"])
+@pytest.mark.parametrize("name", ["c2", "g63", "g127", "g132"])
 def test_fused_sweep_steps_are_bitwise_the_two_passes(orc, name):
     """Three whole steps (graph-replayed V-cycles inside CG) with the fused
     sweep and three with the two colour passes, from the same state."""
