@@ -36,7 +36,11 @@ __device__ __forceinline__ double cv(const double* __restrict__ a, const Dims& n
   i = clampi(i, 0, n.nx - 1);
   j = clampi(j, 0, n.ny - 1);
   k = clampi(k, 0, n.nz - 1);
-  return a[i + (size_t)n.nx * (j + (size_t)n.ny * k)];
+  // 32-bit index arithmetic: every array has fewer than 2^31 entries (the
+  // context refuses grids with more than 2e9 faces), and the predictor's
+  // ~35 clamped loads per face made 64-bit products a large share of its
+  // instructions
+  return a[i + n.nx * (j + n.ny * k)];
 }
 
 // face value of component C with clamped indices
@@ -46,7 +50,7 @@ __device__ __forceinline__ double fv(const double* __restrict__ a, const Dims& n
   i = clampi(i, 0, mx - 1);
   j = clampi(j, 0, my - 1);
   k = clampi(k, 0, mz - 1);
-  return a[i + (size_t)mx * (j + (size_t)my * k)];
+  return a[i + mx * (j + my * k)];
 }
 
 // Koren-limited upwind face value; up2 is the cell behind the upwind cell up,
@@ -59,6 +63,15 @@ __device__ __forceinline__ double koren(double up2, double up, double dn) {
   const double fa = fabs(a), fb = fabs(b);
   const double lim = fmin(fmin(2.0 * fa, (2.0 * fb + fa) * (1.0 / 3.0)), 2.0 * fb);
   return up + copysign(0.5 * lim, b);
+}
+
+// The Koren value at a face between m (its negative side) and p, with mm
+// behind m and pp beyond p, upwind of the advecting velocity a.  The upwind
+// side's three values are selected first, so one limiter is evaluated
+// instead of both sides' and a select of the two.
+__device__ __forceinline__ double koren_face(double a, double mm, double m, double p, double pp) {
+  const bool pos = a >= 0.0;
+  return koren(pos ? mm : pp, pos ? m : p, pos ? p : m);
 }
 
 __device__ __forceinline__ double heaviside(double phi, double eps) {
@@ -165,8 +178,8 @@ __global__ void __launch_bounds__(256) k_advect(Phys P, const double* __restrict
     const double am = u[fm], ap = u[fm + 1];
     auto S = [&](int o) { return s[c + (clampi(i + o, 0, n.nx - 1) - i)]; };
     const double m2 = S(-2), m1 = S(-1), p1 = S(1), p2 = S(2);
-    const double sp = ap >= 0.0 ? koren(m1, sc, p1) : koren(p2, p1, sc);
-    const double sm = am >= 0.0 ? koren(m2, m1, sc) : koren(p1, sc, m1);
+    const double sp = koren_face(ap, m1, sc, p1, p2);
+    const double sm = koren_face(am, m2, m1, sc, p1);
     acc += ap * (sp - sc) - am * (sm - sc);
   }
   {  // y
@@ -174,16 +187,16 @@ __global__ void __launch_bounds__(256) k_advect(Phys P, const double* __restrict
     const double am = v[fm], ap = v[fm + n.nx];
     auto S = [&](int o) { return s[c + (ptrdiff_t)(clampi(j + o, 0, n.ny - 1) - j) * n.nx]; };
     const double m2 = S(-2), m1 = S(-1), p1 = S(1), p2 = S(2);
-    const double sp = ap >= 0.0 ? koren(m1, sc, p1) : koren(p2, p1, sc);
-    const double sm = am >= 0.0 ? koren(m2, m1, sc) : koren(p1, sc, m1);
+    const double sp = koren_face(ap, m1, sc, p1, p2);
+    const double sm = koren_face(am, m2, m1, sc, p1);
     acc += ap * (sp - sc) - am * (sm - sc);
   }
   {  // z
     const double am = w[c], ap = w[c + sxy];
     auto S = [&](int o) { return s[c + (ptrdiff_t)(clampi(k + o, 0, n.nz - 1) - k) * (ptrdiff_t)sxy]; };
     const double m2 = S(-2), m1 = S(-1), p1 = S(1), p2 = S(2);
-    const double sp = ap >= 0.0 ? koren(m1, sc, p1) : koren(p2, p1, sc);
-    const double sm = am >= 0.0 ? koren(m2, m1, sc) : koren(p1, sc, m1);
+    const double sp = koren_face(ap, m1, sc, p1, p2);
+    const double sm = koren_face(am, m2, m1, sc, p1);
     acc += ap * (sp - sc) - am * (sm - sc);
   }
   out[c] = sc - (dt / P.h) * acc;
@@ -334,8 +347,8 @@ __device__ __forceinline__ void mom_dir(const double* __restrict__ uc, const dou
     dvp = (vpp - vpm) * ih;
     dvm = (vmp - vmm) * ih;
   }
-  const double vp = ap >= 0.0 ? koren(m1, uf, p1) : koren(p2, p1, uf);
-  const double vm = am >= 0.0 ? koren(m2, m1, uf) : koren(p1, uf, m1);
+  const double vp = koren_face(ap, m1, uf, p1, p2);
+  const double vm = koren_face(am, m2, m1, uf, p1);
   adv += ap * (vp - uf) - am * (vm - uf);
   if constexpr (CONS) {
     // face density at t^n of the face o steps along D: mean of its two cells
@@ -344,8 +357,8 @@ __device__ __forceinline__ void mom_dir(const double* __restrict__ uc, const dou
                     cv(rho_n, n, i + o * di, j + o * dj, k + o * dk));
     };
     const double rm2 = rf(-2), rm1 = rf(-1), r0 = rf(0), rp1 = rf(1), rp2 = rf(2);
-    const double mp = ap * (ap >= 0.0 ? koren(rm1, r0, rp1) : koren(rp2, rp1, r0));
-    const double mm = am * (am >= 0.0 ? koren(rm2, rm1, r0) : koren(rp1, r0, rm1));
+    const double mp = ap * koren_face(ap, rm1, r0, rp1, rp2);
+    const double mm = am * koren_face(am, rm2, rm1, r0, rp1);
     conv += mp * vp - mm * vm;
     mflux += mp - mm;
   }
@@ -860,10 +873,28 @@ void launch_copy(const double* src, double* dst, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
 }
 
+// A launch evaluates the bodies at one time: a prescribed heave's sine and
+// cosine are taken here, once, and the kernels receive those bodies with
+// zeta, zdot set and fh = 1, as for a free body's state (fh is read on the
+// device only to choose between the stored heave and the formula).  The
+// kernels had evaluated both per cell or face.
+static Phys heave_at(const Phys& P, double t) {
+  Phys Q = P;
+  for (int m = 0; m < Q.nb; ++m) {
+    BodyK& B = Q.body[m];
+    if (B.fh) continue;
+    const double arg = B.om * t + B.ph;
+    B.zeta = B.amp * std::sin(arg);
+    B.zdot = B.amp * B.om * std::cos(arg);
+    B.fh = 1;
+  }
+  return Q;
+}
+
 void launch_props(const Phys& P, const double* sigma, double t, double* rho, double* rfl, double* mu,
                   double* chi, hipStream_t st) {
   Geo g = geo3(P.n.nx, P.n.ny, P.n.nz);
-  hipLaunchKernelGGL(k_props, g.grid, g.block, 0, st, P, sigma, t, rho, rfl, mu, chi);
+  hipLaunchKernelGGL(k_props, g.grid, g.block, 0, st, heave_at(P, t), sigma, t, rho, rfl, mu, chi);
 }
 
 void launch_momentum(const Phys& P, const double* u, const double* v, const double* w,
@@ -872,6 +903,7 @@ void launch_momentum(const Phys& P, const double* u, const double* v, const doub
                      double* by, double* bz, float* bxf, float* byf, float* bzf, double* const* cn_rhs,
                      double* const* cn_diag, double* flag, hipStream_t st) {
   const Dims n = P.n;
+  const Phys Pt = heave_at(P, t1);
   Geo gx = geo3(n.nx + 1, n.ny, n.nz);
   Geo gy = geo3(n.nx, n.ny + 1, n.nz);
   Geo gz = geo3(n.nx, n.ny, n.nz + 1);
@@ -880,19 +912,19 @@ void launch_momentum(const Phys& P, const double* u, const double* v, const doub
   if (cn_rhs)
     for (int c = 0; c < 3; ++c) r[c] = cn_rhs[c], dg[c] = cn_diag[c];
   if (rho_n) {
-    hipLaunchKernelGGL((k_momentum<0, true>), gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+    hipLaunchKernelGGL((k_momentum<0, true>), gx.grid, gx.block, 0, st, Pt, u, v, w, rho, rfl, mu, chi, rho_n, dt,
                        t1, us, bx, bxf, r[0], dg[0], flag);
-    hipLaunchKernelGGL((k_momentum<1, true>), gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+    hipLaunchKernelGGL((k_momentum<1, true>), gy.grid, gy.block, 0, st, Pt, u, v, w, rho, rfl, mu, chi, rho_n, dt,
                        t1, vs, by, byf, r[1], dg[1], flag);
-    hipLaunchKernelGGL((k_momentum<2, true>), gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+    hipLaunchKernelGGL((k_momentum<2, true>), gz.grid, gz.block, 0, st, Pt, u, v, w, rho, rfl, mu, chi, rho_n, dt,
                        t1, ws, bz, bzf, r[2], dg[2], flag);
     return;
   }
-  hipLaunchKernelGGL((k_momentum<0, false>), gx.grid, gx.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+  hipLaunchKernelGGL((k_momentum<0, false>), gx.grid, gx.block, 0, st, Pt, u, v, w, rho, rfl, mu, chi, rho_n, dt,
                      t1, us, bx, bxf, r[0], dg[0], flag);
-  hipLaunchKernelGGL((k_momentum<1, false>), gy.grid, gy.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+  hipLaunchKernelGGL((k_momentum<1, false>), gy.grid, gy.block, 0, st, Pt, u, v, w, rho, rfl, mu, chi, rho_n, dt,
                      t1, vs, by, byf, r[1], dg[1], flag);
-  hipLaunchKernelGGL((k_momentum<2, false>), gz.grid, gz.block, 0, st, P, u, v, w, rho, rfl, mu, chi, rho_n, dt,
+  hipLaunchKernelGGL((k_momentum<2, false>), gz.grid, gz.block, 0, st, Pt, u, v, w, rho, rfl, mu, chi, rho_n, dt,
                      t1, ws, bz, bzf, r[2], dg[2], flag);
 }
 
@@ -992,7 +1024,7 @@ int launch_hydro_force(const Phys& P, int m, double t, const double* p, const do
   Geo g = geo3(e[0], e[1], e[2]);
   const long long blocks = (long long)g.grid.x * g.grid.y * g.grid.z;
   if (blocks > max_blocks) return -1;
-  hipLaunchKernelGGL(k_hydro_force, g.grid, g.block, 0, st, P, m, a[0], a[1], a[2], e[0], e[1], e[2], t, p, u, v,
+  hipLaunchKernelGGL(k_hydro_force, g.grid, g.block, 0, st, heave_at(P, t), m, a[0], a[1], a[2], e[0], e[1], e[2], t, p, u, v,
                      w, mu, partials);
   return (int)blocks;
 }
