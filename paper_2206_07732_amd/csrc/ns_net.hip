@@ -239,6 +239,164 @@ __global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restric
   }
 }
 
+// The same convolution with K running over 32 input channels of one tap
+// (channel-major), for the half-resolution decoder layer at inference (96
+// input channels).  With the K of an MFMA inside one tap, the activation
+// fragment of halo row y serves the output rows y - dy for all three dy taps
+// of a (dz, dx) pair: a wave reads its ten halo rows once per (dz, dx) and
+// issues 24 NT MFMAs from them, where the tap-pair form reads one fragment
+// per MFMA row group.  A block computes a 16 x 8 x 4 tile of output voxels;
+// wave w owns the eight x-rows of z-plane w, so each weight fragment feeds
+// eight MFMAs.  Input channels are staged 32 at a time into LDS as four
+// planes of 8 channels (16-byte entries; the plane stride a multiple of 16
+// entries, so a 16-lane group's reads stay free of bank conflicts).
+// Epilogues as k_conv.  At 256 x 128 x 128 it runs the 96 -> 32 layer in
+// 108 us against k_conv's 155; for the 48 -> 16 layer (a 16-channel
+// remainder chunk, run half empty or as tap pairs) it measured 348 and
+// 328 us against k_conv's 321, and for 32 -> 64 (an eighth of the voxels)
+// 23.5 against 21 us, so those stay on k_conv.  Its single-buffered 68 KB
+// tile leaves two blocks per compute unit; a chunk's staging is hidden only
+// by the other block.
+constexpr int kCX = 16, kCY = 8, kCZ = 4;
+constexpr int kCHX = kCX + 2, kCHY = kCY + 2, kCHZ = kCZ + 2, kCHV = kCHX * kCHY * kCHZ;
+constexpr int kCPlane = (kCHV + 15) / 16 * 16;
+
+template <int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(256) k_conv_cm(VDims d, const uint16_t* __restrict__ XA, int sa, int ca,
+                                                 const uint16_t* __restrict__ XB, int sb,
+                                                 const uint16_t* __restrict__ W, const float* __restrict__ bias,
+                                                 uint16_t* __restrict__ Y, int ys, int yo,
+                                                 const float* __restrict__ hw, const float* __restrict__ hb,
+                                                 float* __restrict__ delta) {
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
+  static_assert(EPI != 1, "the gradient w.r.t. the input runs on k_conv");
+  static_assert(EPI != 2 || COUT == 16, "the fused head takes 16 channels");
+  static_assert(CIN % 32 == 0, "whole chunks of 32 input channels");
+  constexpr int NT = COUT / 16, NC = CIN / 32;
+  __shared__ u32x4 tile[4 * kCPlane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  const int x0 = blockIdx.x * kCX, y0 = blockIdx.y * kCY, z0 = blockIdx.z * kCZ;
+  const int cnx = d.nx >> 1, cny = d.ny >> 1;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  f32x4 acc[kCY][NT];
+#pragma unroll
+  for (int m = 0; m < kCY; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // weight fragment: output column r of tile t, channels 32 c + 8 kg .. + 7 of tap
+  const uint16_t* wl = W + (long)r * 27 * CIN + 8 * kg;
+  auto wfrag = [&](int tap, int t, int c) -> bf16x8 {
+    return as_bf16x8(*reinterpret_cast<const u32x4*>(wl + (long)t * 16 * 27 * CIN + (long)tap * CIN + 32 * c));
+  };
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    if (c > 0) __syncthreads();   // every wave is done with the previous chunk
+    // stage channels [32 c, 32 c + 32): lanes 16 g .. 16 g + 15 take group g
+    // (8 channels) of 16 consecutive halo voxels, so a wave reads 16 whole
+    // 64-byte voxel slices and writes 16 consecutive entries of each plane.
+    // Every load is issued (from a clamped address) before the first write.
+    constexpr int NS = (kCHV + 63) / 64;
+    const int ch = 32 * c + 8 * kg;
+    u32x4 v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int hv = 64 * s + 16 * wave + r;
+      const int hx = hv % kCHX, hy = (hv / kCHX) % kCHY, hz = hv / (kCHX * kCHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      const bool in = hv < kCHV && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz;
+      const int cx = in ? gx : 0, cy = in ? gy : 0, cz = in ? gz : 0;
+      const uint16_t* src = ch < ca ? XA + (long)(cx + d.nx * (cy + d.ny * cz)) * sa + ch
+                                    : XB + (long)((cx >> 1) + cnx * ((cy >> 1) + cny * (cz >> 1))) * sb + (ch - ca);
+      const u32x4 w = *reinterpret_cast<const u32x4*>(src);
+      v[s] = in ? w : zero;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int hv = 64 * s + 16 * wave + r;
+      if (hv < kCHV) tile[kg * kCPlane + hv] = v[s];
+    }
+    __syncthreads();
+    const u32x4* T = tile + kg * kCPlane + r;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        bf16x8 b[3][NT];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) b[dy][t] = wfrag(9 * dz + 3 * dy + dx, t, c);
+        bf16x8 a[kCHY];
+#pragma unroll
+        for (int hy = 0; hy < kCHY; ++hy) a[hy] = as_bf16x8(T[((wave + dz) * kCHY + hy) * kCHX + dx]);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int m = 0; m < kCY; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m + dy], b[dy][t], acc[m][t], 0, 0, 0);
+      }
+    }
+  }
+  // Epilogue: + bias, ReLU, BF16; the wave's 128 voxels x COUT results are
+  // transposed through its own slice of the tile memory and stored as
+  // 16-byte pieces of 8 channels.
+  static_assert(kCY * 16 * COUT * 2 * 4 <= (int)sizeof(tile), "staging fits in the tile");
+  const bool store = (EPI != 2) || (Y != nullptr);
+  __syncthreads();
+  uint16_t* stg = reinterpret_cast<uint16_t*>(&tile[0]) + wave * kCY * 16 * COUT;
+  const int z = z0 + wave;
+#pragma unroll
+  for (int m = 0; m < kCY; ++m) {
+    const int y = y0 + m;
+    const long row = (long)d.nx * (y + (long)d.ny * z);
+    float hs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + r;
+      const float bb = bias[co];
+      const float wh = (EPI == 2) ? hw[co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float val = fmaxf(acc[m][t][i] + bb, 0.f);
+        const uint16_t q = f2bf(val);
+        stg[(m * 16 + 4 * kg + i) * COUT + co] = q;
+        if (EPI == 2) hs[i] = wh * bf2f(q);
+      }
+    }
+    if (EPI == 2) {
+      // sum the 16 channels: the 16 lanes of one row group
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) hs[i] += __shfl_xor(hs[i], o, 16);
+      if (r == 0 && y < d.ny && z < d.nz) {
+        const float b0 = hb[0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int x = x0 + 4 * kg + i;
+          if (x < d.nx) delta[row + x] = hs[i] + b0;
+        }
+      }
+    }
+  }
+  if (store) {
+    __syncthreads();
+    constexpr int G = COUT / 8;   // 16-byte pieces per voxel
+#pragma unroll
+    for (int j = 0; j < 2 * G; ++j) {
+      const int q = lane + 64 * j, vl = q / G, cg = q % G;
+      const int x = x0 + (vl & 15), y = y0 + (vl >> 4);
+      if (x < d.nx && y < d.ny && z < d.nz)
+        *reinterpret_cast<u32x4*>(Y + ((long)x + (long)d.nx * (y + (long)d.ny * z)) * ys + yo + 8 * cg) =
+            *reinterpret_cast<const u32x4*>(stg + vl * COUT + 8 * cg);
+    }
+  }
+}
+
 // First layer at inference: the four FP32 feature channels (channel-first,
 // feat[c nv + v]) are converted to bfloat16 while staged in LDS (8 bytes per
 // halo voxel), and K runs over (tap, channel) compactly, k = 4 tap + ci with
@@ -890,6 +1048,15 @@ void conv(const ns_net* N, VDims d, const uint16_t* XA, int sa, int ca, const ui
                      yo, hw, hb, delta);
 }
 
+template <int CIN, int COUT, int EPI>
+void conv_cm(const ns_net* N, VDims d, const uint16_t* XA, int sa, int ca, const uint16_t* XB, int sb,
+             const uint16_t* W, const float* bias, uint16_t* Y, int ys, int yo, const float* hw = nullptr,
+             const float* hb = nullptr, float* delta = nullptr) {
+  const dim3 grid((d.nx + kCX - 1) / kCX, (d.ny + kCY - 1) / kCY, (d.nz + kCZ - 1) / kCZ);
+  hipLaunchKernelGGL((k_conv_cm<CIN, COUT, EPI>), grid, dim3(256), 0, N->st, d, XA, sa, ca, XB, sb, W, bias, Y,
+                     ys, yo, hw, hb, delta);
+}
+
 // bf16 copies (forward and flipped-transposed) of the FP32 master weights
 void refresh_weights(ns_net* N) {
   hipLaunchKernelGGL(k_compact_w0, dim3(8), dim3(256), 0, N->st, N->theta + N->ow[0], N->wc0);
@@ -935,7 +1102,7 @@ void forward_infer(ns_net* N) {
   conv<16, 32, 0>(N, N->res1, N->p1, 16, 16, nullptr, 0, N->wf[1], th + N->ob[1], a2, 32, 0);
   hipLaunchKernelGGL(k_pool, g1(N->v2 * 4), dim3(256), 0, N->st, N->res1, a2, 32, 0, 32, N->p2);
   conv<32, 64, 0>(N, N->res2, N->p2, 32, 32, nullptr, 0, N->wf[2], th + N->ob[2], N->a3, 64, 0);
-  conv<96, 32, 0>(N, N->res1, a2, 32, 32, N->a3, 64, N->wf[3], th + N->ob[3], N->a4, 32, 0);
+  conv_cm<96, 32, 0>(N, N->res1, a2, 32, 32, N->a3, 64, N->wf[3], th + N->ob[3], N->a4, 32, 0);
   conv<48, 16, 2>(N, N->res0, a1, 16, 16, N->a4, 32, N->wf[4], th + N->ob[4], nullptr, 16, 0, th + N->ohw,
                   th + N->ohb, N->delta);
 }
