@@ -61,11 +61,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 
 # HBM bytes per launch of the dominant kernel (the fused finest-level sweep
-# k_gs_rb_fine<double, 14, 64>) at 512x256x256 from two rocprofv3 --pmc passes:
+# k_gs_rb_fine<double, 13>) at 512x256x256 from two rocprofv3 --pmc passes:
 # FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE, medians
 # over 346 dispatches.  Valid for that kernel as it is now and for that
 # workload only; None elsewhere.
-TRAFFIC_BYTES_PER_LAUNCH = {("k_gs_rb_fine<double, 14, 64>", "c5"): 1994925938}
+TRAFFIC_BYTES_PER_LAUNCH = {}
 
 # Algorithmic bytes per cell (FP64, 3-D; each array read or written once per
 # pass): the passes outside the solve, and one FP64 CG iteration (vector work
@@ -79,7 +79,7 @@ SWEEP_BYTES_PER_CELL_FP64 = 48.0
 # part of one red-black sweep of the finest level that one launch does: the
 # fused sweep where the library uses it (large 3-D grids), else one colour
 # pass
-SMOOTHER_KERNELS = {True: ("k_gs_rb_fine<double, 14, 64> (one red-black sweep, finest level)", 1.0),
+SMOOTHER_KERNELS = {True: ("k_gs_rb_fine<double, 13> (one red-black sweep, finest level)", 1.0),
                     False: ("k_gs<double, true> (one red-black colour pass, finest level)", 0.5)}
 
 

@@ -500,21 +500,23 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
 //     of the red cell below it, both in the same pair column, which the same
 //     thread computes on the planes above and below;
 //   * its x-faces are the faces of the red cell of its own pair and of the
-//     adjacent pair (the adjacent lane: a row of the block is LN consecutive
-//     pairs, one wave for LN = 64);
+//     adjacent pair (the adjacent lane: a row of the block is one wave of 64
+//     consecutive pairs; the end lanes load their outer face);
 //   * its y-faces are those of the red cells of the rows beside it (LDS).
-// A block is LN lanes by TY + 2 rows of pairs and marches up a chunk of KZ
-// planes: at plane m it forms the red values of plane m, then the black
-// values of plane m - 1, whose red neighbours are then all known.  The first
-// and last rows form a ring whose red values the block's own black cells
-// read; so do lanes 0 and LN - 1 when a row has more than LN pairs.  Ring values
-// are recomputed (the neighbouring block forms and stores them too) and
-// only the inner lanes and rows store.  Red values are formed from the
-// black plane as it stood before the launch, which the previous kernel
-// copied to bold (this launch overwrites the black plane while other blocks
-// still read it).  Each value comes from the same arithmetic on the same
-// inputs as in the two separate passes, so the results are theirs bit for
-// bit.
+// A block marches up a chunk of KZ planes: at plane m it forms the red
+// values of plane m, then the black values of plane m - 1, whose red
+// neighbours are then all known.  Its 64 lanes by TY + 2 rows of pairs store
+// every lane of the TY inner rows; the first and last rows form a ring whose
+// red values the block's own black cells read.  One more wave, the halo,
+// forms for each inner row the red values of the two pairs just beyond the
+// row's ends (lanes 0 .. TY - 1 the west pair, 32 .. 31 + TY the east one),
+// which the end lanes' black cells read from LDS.  Ring and halo values are
+// recomputed (the neighbouring block forms and stores them too).  Red values
+// are formed from the black plane as it stood before the launch, which the
+// previous kernel copied to bold (this launch overwrites the black plane
+// while other blocks still read it).  Each value comes from the same
+// arithmetic on the same inputs as in the two separate passes, so the
+// results are theirs bit for bit.
 //
 // The march is bound by memory latency, not bandwidth: a plane's work is a
 // few dozen instructions per thread against one trip to HBM.  So every load
@@ -522,49 +524,68 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
 // plane m is computed, and waits only at its first use one plane later; the
 // loop is unrolled by two so that the two planes' registers alternate
 // without copies.
+constexpr int kRbfLanes = 64;
+
 template <typename T>
 struct RbfLoads {
   T fw, fe, fs, fn, fd, fu;  // the faces of the red cell of plane m
   T bc;                      // its right-hand side
   T bo_u;                    // this pair's black value (before the launch) on plane m + 1
-  T xo, yo;                  // black values beside the ring (row ends, ring rows) on plane m
+  T xo, yo;                  // black values beside the row ends and the ring rows on plane m
   T bb;                      // the right-hand side of this pair's black cell on plane m - 1
-  T xf;                      // that cell's outer x-face, for a block row's end lanes
+  T xf;                      // that cell's outer x-face, for a row's end lanes
 };
 
-template <typename T, int TY, int LN>
-__global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, const T* __restrict__ bx,
+// what a halo lane loads for the red cell of its pair on plane m
+template <typename T>
+struct RbfHaloLoads {
+  T fw, fe, fs, fn, fd, fu, bc;
+  T own, xo;   // black values (before the launch) of its pair and of the x-adjacent pair
+  T ys, yn;    // of the rows beside it
+  T zd, zu;    // of the planes below and above
+};
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h2, const T* __restrict__ bx,
                                                                      const T* __restrict__ by,
                                                                      const T* __restrict__ bz,
                                                                      const T* __restrict__ b, T* __restrict__ e,
                                                                      const T* __restrict__ bold, int KZ) {
   constexpr int R = TY + 2;
-  __shared__ T BO[2][R][LN];    // black values (as before the launch) of a plane
-  __shared__ T RN[2][R][LN];    // red values of a plane
-  __shared__ T RYS[2][R][LN];   // their south and north faces
-  __shared__ T RYN[2][R][LN];
+  static_assert(TY <= 32, "a halo lane per inner row and side");
+  __shared__ T BO[2][R][kRbfLanes];    // black values (as before the launch) of a plane
+  __shared__ T RN[2][R][kRbfLanes];    // red values of a plane
+  __shared__ T RYS[2][R][kRbfLanes];   // their south and north faces
+  __shared__ T RYN[2][R][kRbfLanes];
+  __shared__ T HH[2][2][R];            // the halo's red values: [plane parity][west, east][row]
   const SplitGeo sg = split_geo(n);
   const Tile tl = xcd_tile();
   const int lane = threadIdx.x, r = threadIdx.y;
-  const int xr = sg.hx > LN ? 1 : 0;   // ring lanes only where a row spans several blocks
-  const int ti = tl.x * (LN - 2 * xr) - xr + lane, j = tl.y * TY - 1 + r;
-  const bool ok = ti >= 0 && ti < sg.hx && j >= 0 && j < n.ny;
-  const bool inner = ok && lane >= xr && lane < LN - xr && r >= 1 && r <= TY;
-  const int tic = min(max(ti, 0), sg.hx - 1), jc = min(max(j, 0), n.ny - 1);
+  const bool halo = r == R;            // the halo wave (wave-uniform)
+  const int tx0 = tl.x * kRbfLanes;    // this block's first pair of a row
   const int k0 = tl.z * KZ, kz1 = min(k0 + KZ, n.nz);
-  const size_t sz = (size_t)sg.hx * n.ny;                 // pairs per plane
-  const size_t prow = (size_t)tic + (size_t)sg.hx * jc;   // this pair in plane 0
-  // the pairs whose black values the ring reads: the adjacent pair for a
-  // row's end lanes, the adjacent row for the ring rows (others: their own)
-  const size_t xrow = (size_t)(lane == 0 ? max(tic - 1, 0) : lane == LN - 1 ? min(tic + 1, sg.hx - 1) : tic) +
-                      (size_t)sg.hx * jc;
-  const size_t yrow = (size_t)tic + (size_t)sg.hx * (r == 0 ? max(jc - 1, 0) : r == R - 1 ? min(jc + 1, n.ny - 1) : jc);
-  // the outer x-face of a black cell on a block row's end lane: the west
-  // face of an even column on lane 0, the east face of an odd one on lane
-  // LN - 1 (a shuffle there would return the lane's own face)
-  const int xfi = lane == 0 ? 2 * ti : 2 * ti + 2;
+  const size_t sz = (size_t)sg.hx * n.ny;   // pairs per plane
   const size_t fxs = (size_t)(n.nx + 1) * n.ny, fys = (size_t)n.nx * (n.ny + 1), fzs = (size_t)n.nx * n.ny;
   const auto clampz = [&](int m) { return (size_t)min(max(m, 0), n.nz - 1); };
+  // ---- a main lane: pair ti of row j
+  const int ti = tx0 + lane, j = tl.y * TY - 1 + r;
+  const bool ok = !halo && ti < sg.hx && j >= 0 && j < n.ny;
+  const bool inner = ok && r >= 1 && r <= TY;
+  const int tic = min(ti, sg.hx - 1), jc = min(max(j, 0), n.ny - 1);
+  const size_t prow = (size_t)tic + (size_t)sg.hx * jc;   // this pair in plane 0
+  // the pairs whose black values the row ends and the ring rows read
+  const size_t xrow = (size_t)(lane == 0 ? max(tic - 1, 0) : lane == kRbfLanes - 1 ? min(tic + 1, sg.hx - 1) : tic) +
+                      (size_t)sg.hx * jc;
+  const size_t yrow = (size_t)tic + (size_t)sg.hx * (r == 0 ? max(jc - 1, 0) : r == R - 1 ? min(jc + 1, n.ny - 1) : jc);
+  // the outer x-face of a black cell on a row's end lane: the west face of
+  // an even column on lane 0, the east face of an odd one on lane 63 (a
+  // shuffle there would return the lane's own face)
+  const int xfi = lane == 0 ? 2 * ti : 2 * ti + 2;
+  // ---- a halo lane: the pair beyond the west (side 0) or east (side 1) row end, inner row hr
+  const int side = lane >> 5, hr = (lane & 31) + 1;
+  const int hp = side ? tx0 + kRbfLanes : tx0 - 1, hj = tl.y * TY - 1 + hr;
+  const bool hok = halo && hr <= TY && hp >= 0 && hp < sg.hx && hj < n.ny;
+  const int hpc = min(max(hp, 0), sg.hx - 1), hjc = min(hj, n.ny - 1);
   // face indices from the unclamped cell, kept in the face range: a ring
   // cell outside the grid holds the wall face it shares with the grid; at
   // m = -1 the up face is the bed, at m = nz the down face is the open top
@@ -586,12 +607,49 @@ __global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, cons
     L.bb = b[sg.P + prow + sz * clampz(m - 1)];
     L.xf = bx[(size_t)min(max(xfi, 0), n.nx) + (size_t)(n.nx + 1) * jc + fxs * clampz(m - 1)];
   };
+  const auto load_h = [&](int m, RbfHaloLoads<T>& H) {
+    const size_t mc = clampz(m);
+    const int par = (hj + m) & 1;
+    const int iru = 2 * hp + par;
+    const int irc = min(max(iru, 0), n.nx - 1);
+    const size_t xf = (size_t)(n.nx + 1) * hjc + fxs * mc;
+    const size_t pr = (size_t)hpc + (size_t)sg.hx * hjc;
+    H.fw = bx[(size_t)min(max(iru, 0), n.nx) + xf];
+    H.fe = bx[(size_t)min(max(iru + 1, 0), n.nx) + xf];
+    H.fs = by[(size_t)irc + (size_t)n.nx * hjc + fys * mc];
+    H.fn = by[(size_t)irc + (size_t)n.nx * (hjc + 1) + fys * mc];
+    H.fd = bz[(size_t)irc + (size_t)n.nx * hjc + fzs * mc];
+    H.fu = bz[(size_t)irc + (size_t)n.nx * hjc + fzs * (mc + 1)];
+    H.bc = b[pr + sz * mc];
+    H.own = bold[pr + sz * mc];
+    H.xo = bold[(size_t)min(max(par ? hpc + 1 : hpc - 1, 0), sg.hx - 1) + (size_t)sg.hx * hjc + sz * mc];
+    H.ys = bold[(size_t)hpc + (size_t)sg.hx * max(hjc - 1, 0) + sz * mc];
+    H.yn = bold[(size_t)hpc + (size_t)sg.hx * min(hjc + 1, n.ny - 1) + sz * mc];
+    H.zd = bold[pr + sz * clampz(m - 1)];
+    H.zu = bold[pr + sz * clampz(m + 1)];
+  };
   T bo_d = bold[prow + sz * clampz(k0 - 2)], bo_c = bold[prow + sz * clampz(k0 - 1)];
   if (!(ok && k0 - 2 >= 0)) bo_d = (T)0;
   if (!(ok && k0 - 1 >= 0)) bo_c = (T)0;
   T rv1 = 0, rv2 = 0, fu1 = 0, fu2 = 0, fw1 = 0, fe1 = 0;
+  // the halo wave's plane: the red value of its pair on plane m, to LDS
+  const auto plane_h = [&](int m, const RbfHaloLoads<T>& H) {
+    const int par = (hj + m) & 1;
+    const int iru = 2 * hp + par;
+    T rv = (T)0;
+    if (hok && m >= 0 && m < n.nz && iru < n.nx) {
+      const int mc = m;
+      const T vw = par == 0 ? H.xo : H.own, ve = par == 0 ? H.own : H.xo;
+      const T vd = m > 0 ? H.zd : (T)0, vu = m + 1 < n.nz ? H.zu : (T)0;
+      const GsIn<T> g{H.fw, H.fe, H.fs, H.fn, H.fd, H.fu, H.ys, H.yn, vd, vu};
+      rv = gs_combine<T>(n, g, h2, H.bc, iru, hj, mc, vw, ve);
+    }
+    if (hr <= TY) HH[m & 1][side][hr] = rv;
+    __syncthreads();
+    __syncthreads();
+  };
   const auto plane = [&](int m, const RbfLoads<T>& L) {
-    // ---- the red cell of this pair on plane m (ring included)
+    // ---- the red cell of this pair on plane m (ring rows included)
     const int mc = (int)clampz(m);
     const int par = (j + m) & 1;
     const int iru = 2 * ti + par;                     // possibly outside the grid
@@ -600,10 +658,10 @@ __global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, cons
     const T bo_u = (ok && m + 1 >= 0 && m + 1 < n.nz) ? L.bo_u : (T)0;
     // x neighbours: this pair's black cell and the adjacent pair's (the
     // adjacent lane; the row's end lanes loaded theirs)
-    const T bl = __shfl_up(bo_c, 1, LN), br = __shfl_down(bo_c, 1, LN);
+    const T bl = __shfl_up(bo_c, 1, kRbfLanes), br = __shfl_down(bo_c, 1, kRbfLanes);
     const T xo = live ? L.xo : (T)0, yo = live ? L.yo : (T)0;
     const T vw = par == 0 ? (lane > 0 ? bl : xo) : bo_c;
-    const T ve = par == 1 ? (lane < LN - 1 ? br : xo) : bo_c;
+    const T ve = par == 1 ? (lane < kRbfLanes - 1 ? br : xo) : bo_c;
     const T vs = r > 0 ? BO[m & 1][r - 1][lane] : yo;
     const T vn = r < R - 1 ? BO[m & 1][r + 1][lane] : yo;
     T rv = (T)0;
@@ -618,8 +676,8 @@ __global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, cons
     BO[(m + 1) & 1][r][lane] = bo_u;
     // the adjacent lanes' red values and x-faces of plane m - 1 (every lane
     // takes part in the shuffles)
-    const T xfe = __shfl_up(fe1, 1, LN), xrl = __shfl_up(rv1, 1, LN);
-    const T xfw = __shfl_down(fw1, 1, LN), xrr = __shfl_down(rv1, 1, LN);
+    const T xfe = __shfl_up(fe1, 1, kRbfLanes), xrl = __shfl_up(rv1, 1, kRbfLanes);
+    const T xfw = __shfl_down(fw1, 1, kRbfLanes), xrr = __shfl_down(rv1, 1, kRbfLanes);
     __syncthreads();
     // ---- the black cell of this pair on plane m - 1 (inner threads)
     const int mb = m - 1;
@@ -627,10 +685,12 @@ __global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, cons
       const int ib = iru;      // the black cell of plane m - 1 shares the column of plane m's red cell
       if (ib < n.nx) {
         const bool even = (ib & 1) == 0;
-        const T bw = lane > 0 ? xfe : L.xf, be = lane < LN - 1 ? xfw : L.xf;
+        const T bw = lane > 0 ? xfe : L.xf, be = lane < kRbfLanes - 1 ? xfw : L.xf;
+        const T vwb = lane > 0 ? xrl : HH[mb & 1][0][r], veb = lane < kRbfLanes - 1 ? xrr : HH[mb & 1][1][r];
         const GsIn<T> g{even ? bw : fe1, even ? fw1 : be, RYN[mb & 1][r - 1][lane], RYS[mb & 1][r + 1][lane],
                         fu2, L.fd, RN[mb & 1][r - 1][lane], RN[mb & 1][r + 1][lane], rv2, rv};
-        e[sg.P + prow + sz * (size_t)mb] = gs_combine<T>(n, g, h2, L.bb, ib, j, mb, even ? xrl : rv1, even ? rv1 : xrr);
+        const T bb = L.bb;
+        e[sg.P + prow + sz * (size_t)mb] = gs_combine<T>(n, g, h2, bb, ib, j, mb, even ? vwb : rv1, even ? rv1 : veb);
       }
     }
     __syncthreads();
@@ -643,6 +703,21 @@ __global__ void __launch_bounds__(LN * (TY + 2)) k_gs_rb_fine(Dims n, T h2, cons
     bo_d = bo_c;
     bo_c = bo_u;
   };
+  if (halo) {
+    RbfHaloLoads<T> A, B;
+    load_h(k0 - 1, A);
+    __syncthreads();
+    for (int m = k0 - 1; m <= kz1; m += 2) {
+      load_h(m + 1, B);
+      __builtin_amdgcn_sched_barrier(0);
+      plane_h(m, A);
+      if (m + 1 > kz1) break;
+      load_h(m + 2, A);
+      __builtin_amdgcn_sched_barrier(0);
+      plane_h(m + 1, B);
+    }
+    return;
+  }
   RbfLoads<T> A, B;
   load(k0 - 1, A);
   BO[(k0 - 1) & 1][r][lane] = bo_c;
@@ -1549,56 +1624,72 @@ void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T
 
 // the finest level's fused red-black sweep: where it applies (a 3-D level
 // whose rows fill at least half a wave), where it pays, and its launch.  A
-// block runs TY + 2 rows of LN lanes (1024 threads) up KZ planes.  A block
-// holds its compute unit for its whole march, so whole rounds of blocks
-// matter: on 512 x 256 x 256, 64 x 16 blocks up 32 planes (760 blocks, 2.97
-// rounds of 256) took 412 us a sweep, 32 x 32 blocks (648, of which the
-// third round is half empty) 431 us though they re-read fewer ring rows,
-// and 16 x 64 blocks 498 us.
-constexpr int kRbfLanes = 64;   // lanes of a block row (LN)
-constexpr int kRbfRows = 14;    // inner rows of a block (TY)
-constexpr int kRbfPlanes = 32;  // planes a block marches (KZ)
-
-static dim3 rbf_grid(const Dims& n, int TY, int KZ, int LN) {
-  const int hx = (n.nx + 1) / 2;
-  const int step = hx > LN ? LN - 2 : LN;   // inner lanes of a block
-  return dim3((hx + step - 1) / step, (n.ny + TY - 1) / TY, (n.nz + KZ - 1) / KZ);
-}
+// block runs 64 lanes by kRbfRows + 2 rows of pairs and the halo wave (1024
+// threads) up a chunk of planes.
+constexpr int kRbfRows = 13;    // inner rows of a block (TY)
 
 bool gs_rb_fine_fits(const Dims& n) {
   return n.ny >= 4 && n.nz >= 4 && (n.nx + 1) / 2 >= 32;
 }
 
-// A block's march is a chain of dependent planes, so the launch wins over
-// two colour passes only where its blocks fill every compute unit at least
-// twice (measured: 760 blocks of 64 x 16 on 512 x 256 x 256 beat the two
-// passes by a sixth; 120 on 256 x 128 x 128 lose by a tenth).
+// A block's march is a chain of dependent planes: the launch wins over two
+// colour passes on large grids only (measured faster on 512 x 256 x 256,
+// slower on 256 x 128 x 128 and 128 x 64 x 64).
 bool gs_rb_fine_pays(const Dims& n) {
-  if (!gs_rb_fine_fits(n)) return false;
-  const dim3 g = rbf_grid(n, kRbfRows, kRbfPlanes, kRbfLanes);
-  return (long)g.x * g.y * g.z >= 512;
+  return gs_rb_fine_fits(n) && (long)n.nx * n.ny * n.nz >= (1L << 24);
 }
 
-template <typename T, int TY, int LN>
-void launch_gs_rb_fine_tile(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
-                            hipStream_t st, KTimer* kt, int KZ) {
-  static_assert(LN * (TY + 2) == 1024, "a block of 1024 threads");
-  const dim3 grid = rbf_grid(L.n, TY, KZ, LN);
-  const dim3 blk(LN, TY + 2);
-  const T h2 = (T)(L.h * L.h);
-  if (kt && kt->n < kt->cap) {
-    hipExtLaunchKernelGGL((k_gs_rb_fine<T, TY, LN>), grid, blk, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0,
-                          L.n, h2, bx, by, bz, b, e, bold, KZ);
-    ++kt->n;
-    return;
+// compute units of the current device (one block of the sweep per unit)
+static int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] > 0) return cache[dev];
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+  cache[dev] = v;
+  return v;
+}
+
+// The chunk of planes a block marches.  A block holds its compute unit for
+// its whole march (KZ + 2 planes), so the sweep takes about (rounds of
+// blocks) x (KZ + 2) plane times: the chunk is chosen to minimise that
+// product, ties going to fewer chunks.  512 x 256 x 256 gets 3 chunks of 86
+// planes, 240 blocks, one round.
+static int rbf_planes(int tiles, int nz, int cus) {
+  long best = -1;
+  int best_kz = nz;
+  for (int nzc = 1; nzc <= nz; ++nzc) {
+    const int kz = (nz + nzc - 1) / nzc;
+    const int chunks = (nz + kz - 1) / kz;
+    const long rounds = ((long)tiles * chunks + cus - 1) / cus;
+    const long cost = rounds * (kz + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_kz = kz;
+    }
   }
-  hipLaunchKernelGGL((k_gs_rb_fine<T, TY, LN>), grid, blk, 0, st, L.n, h2, bx, by, bz, b, e, bold, KZ);
+  return best_kz;
 }
 
 template <typename T>
 void launch_gs_rb_fine(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
                        hipStream_t st, KTimer* kt) {
-  launch_gs_rb_fine_tile<T, kRbfRows, kRbfLanes>(L, bx, by, bz, b, e, bold, st, kt, kRbfPlanes);
+  constexpr int TY = kRbfRows;
+  static_assert(kRbfLanes * (TY + 3) == 1024, "a block of 1024 threads");
+  const int hx = (L.n.nx + 1) / 2;
+  const int gx = (hx + kRbfLanes - 1) / kRbfLanes, gy = (L.n.ny + TY - 1) / TY;
+  const int KZ = rbf_planes(gx * gy, L.n.nz, device_cus());
+  const dim3 grid(gx, gy, (L.n.nz + KZ - 1) / KZ);
+  const dim3 blk(kRbfLanes, TY + 3);
+  const T h2 = (T)(L.h * L.h);
+  if (kt && kt->n < kt->cap) {
+    hipExtLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
+                          h2, bx, by, bz, b, e, bold, KZ);
+    ++kt->n;
+    return;
+  }
+  hipLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, L.n, h2, bx, by, bz, b, e, bold, KZ);
 }
 
 template <typename T>

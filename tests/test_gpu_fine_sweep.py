@@ -1,16 +1,16 @@
 """The finest level's fused red-black sweep (one launch per sweep, each face
 coefficient read once) against the same sweep as two colour passes, through
 the C ABI: V-cycles and whole steps must agree bit for bit, in FP64 and
-with the FP32 V-cycle.  A block is 64 lanes by 16 rows of cell pairs (14
-inner) marching up 32 planes.  Rows of at most 64 pairs run without ring
-lanes (lanes 0 and 63 are cells of the grid when the row has 64 pairs):
-C2's 64, a 127-cell row (64 pairs, the last a single cell), the
-half-resolution tank (32 pairs), a 63-cell row (32 pairs, the last single)
-and a ragged 35 pairs.  Longer rows take ring lanes: 66 pairs (two blocks,
-the second with 4 of its 62 inner pairs).  The grids' rows and planes are
-not multiples of the block's 14 rows and 32 planes, several span more than
-one row block, and one has several plane chunks (100 planes: three of 32
-and one of 4)."""
+with the FP32 V-cycle.  A block is 64 lanes by 15 rows of cell pairs (13
+stored) plus a halo wave that forms the red values just beyond the row
+ends, marching up a chunk of planes chosen per grid.  Rows of at most 64
+pairs fit one block (C2's 64; a 127-cell row, 64 pairs with a single last
+cell; the half-resolution tank's 32; a 63-cell row; a ragged 35 pairs).
+Longer rows span several blocks whose end lanes read the halo: 66 pairs
+(two blocks) and 150 pairs (three, the middle one with both halos inside
+the grid).  Rows and planes are not multiples of the block's 13 rows or
+its chunk, and most grids span several row blocks and plane chunks."""
+
 
 
 import numpy as np
@@ -37,13 +37,17 @@ def case(name):
                           bodies=[I.Body(1, (2.0, 0.3, 0.0), (0.3, 0.7, 1.5))])
     if name == "c2half":
         return I.workload("c2half")
+    if name == "g300":
+        return I.workload("tiny3d", nx=300, ny=30, nz=40, h=4.0 / 300, seed=34, depth=0.3,
+                          wave={"kind": "airy", "a": 0.01, "T": 1.2, "phase": 0.0},
+                          bodies=[I.Body(1, (2.0, 0.2, 0.0), (0.1, 0.1, 0.45))])
     if name == "g132":
         return I.workload("tiny3d", nx=132, ny=26, nz=100, h=4.0 / 132, seed=31,
                           bodies=[I.Body(1, (2.0, 0.4, 0.0), (0.3, 0.7, 1.5))])
     return parity_case(name)
 
 
-CASES = ["c2", "g63", "g127", "c2half", "ragged3d", "rbragged", "g132"]
+CASES = ["c2", "g63", "g127", "c2half", "ragged3d", "rbragged", "g132", "g300"]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -70,7 +74,7 @@ def test_fused_sweep_vcycle_is_bitwise_the_two_passes(orc, name, prec):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["c2", "g63", "g127", "g132"])
+@pytest.mark.parametrize("name", ["c2", "g63", "g127", "g132", "g300"])
 def test_fused_sweep_steps_are_bitwise_the_two_passes(orc, name):
     """Three whole steps (graph-replayed V-cycles inside CG) with the fused
     sweep and three with the two colour passes, from the same state."""
@@ -110,9 +114,9 @@ def test_fused_sweep_switch_refuses_grids_it_does_not_fit(orc):
 
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_fused_sweep_default_follows_the_grid_size(orc, name):
-    """The 128x64x64 and 256x128x128 tanks give the fused launch fewer than
-    512 workgroups: the library starts with the two colour passes, and the
-    switch turns the fused launch on and off again."""
+    """On the 128x64x64 and 256x128x128 tanks (fewer than 2^24 cells) the
+    library starts with the two colour passes, and the switch turns the
+    fused launch on and off again."""
     ns = _ns()
     wl = case(name)
     S = ns.Solver(ns.params(wl), ns.device_fields(I.make_fields(wl)))
