@@ -553,11 +553,17 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
                                                                      const T* __restrict__ bold, int KZ) {
   constexpr int R = TY + 2;
   static_assert(TY <= 32, "a halo lane per inner row and side");
+  // One barrier per plane, between its red and black phases.  A wave may
+  // then form the red values of plane m + 1 while another still reads those
+  // of plane m - 1 in its black phase, so the red values, their y-faces and
+  // the halo's values take three slots (plane mod 3); the black values
+  // before the launch need two, since their readers (the red phase) all
+  // finish before the barrier.
   __shared__ T BO[2][R][kRbfLanes];    // black values (as before the launch) of a plane
-  __shared__ T RN[2][R][kRbfLanes];    // red values of a plane
-  __shared__ T RYS[2][R][kRbfLanes];   // their south and north faces
-  __shared__ T RYN[2][R][kRbfLanes];
-  __shared__ T HH[2][2][R];            // the halo's red values: [plane parity][west, east][row]
+  __shared__ T RN[3][R][kRbfLanes];    // red values of a plane
+  __shared__ T RYS[3][R][kRbfLanes];   // their south and north faces
+  __shared__ T RYN[3][R][kRbfLanes];
+  __shared__ T HH[3][2][R];            // the halo's red values: [plane mod 3][west, east][row]
   const SplitGeo sg = split_geo(n);
   const Tile tl = xcd_tile();
   const int lane = threadIdx.x, r = threadIdx.y;
@@ -644,8 +650,7 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
       const GsIn<T> g{H.fw, H.fe, H.fs, H.fn, H.fd, H.fu, H.ys, H.yn, vd, vu};
       rv = gs_combine<T>(n, g, h2, H.bc, iru, hj, mc, vw, ve);
     }
-    if (hr <= TY) HH[m & 1][side][hr] = rv;
-    __syncthreads();
+    if (hr <= TY) HH[(m + 3) % 3][side][hr] = rv;
     __syncthreads();
   };
   const auto plane = [&](int m, const RbfLoads<T>& L) {
@@ -670,9 +675,10 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
       rv = gs_combine<T>(n, g, h2, L.bc, irc, jc, mc, vw, ve);
       if (inner && m >= k0 && m < kz1) e[prow + sz * mc] = rv;
     }
-    RN[m & 1][r][lane] = rv;
-    RYS[m & 1][r][lane] = L.fs;
-    RYN[m & 1][r][lane] = L.fn;
+    const int sm = (m + 3) % 3, sb = (m + 2) % 3;   // the slots of planes m and m - 1
+    RN[sm][r][lane] = rv;
+    RYS[sm][r][lane] = L.fs;
+    RYN[sm][r][lane] = L.fn;
     BO[(m + 1) & 1][r][lane] = bo_u;
     // the adjacent lanes' red values and x-faces of plane m - 1 (every lane
     // takes part in the shuffles)
@@ -686,14 +692,13 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
       if (ib < n.nx) {
         const bool even = (ib & 1) == 0;
         const T bw = lane > 0 ? xfe : L.xf, be = lane < kRbfLanes - 1 ? xfw : L.xf;
-        const T vwb = lane > 0 ? xrl : HH[mb & 1][0][r], veb = lane < kRbfLanes - 1 ? xrr : HH[mb & 1][1][r];
-        const GsIn<T> g{even ? bw : fe1, even ? fw1 : be, RYN[mb & 1][r - 1][lane], RYS[mb & 1][r + 1][lane],
-                        fu2, L.fd, RN[mb & 1][r - 1][lane], RN[mb & 1][r + 1][lane], rv2, rv};
+        const T vwb = lane > 0 ? xrl : HH[sb][0][r], veb = lane < kRbfLanes - 1 ? xrr : HH[sb][1][r];
+        const GsIn<T> g{even ? bw : fe1, even ? fw1 : be, RYN[sb][r - 1][lane], RYS[sb][r + 1][lane],
+                        fu2, L.fd, RN[sb][r - 1][lane], RN[sb][r + 1][lane], rv2, rv};
         const T bb = L.bb;
         e[sg.P + prow + sz * (size_t)mb] = gs_combine<T>(n, g, h2, bb, ib, j, mb, even ? vwb : rv1, even ? rv1 : veb);
       }
     }
-    __syncthreads();
     rv2 = rv1;
     rv1 = rv;
     fu2 = fu1;
