@@ -9,7 +9,9 @@ cell; the half-resolution tank's 32; a 63-cell row; a ragged 35 pairs).
 Longer rows span several blocks whose end lanes read the halo: 66 pairs
 (two blocks) and 150 pairs (three, the middle one with both halos inside
 the grid).  Rows and planes are not multiples of the block's 13 rows or
-its chunk, and most grids span several row blocks and plane chunks."""
+its chunk, and most grids span several row blocks and plane chunks.  The
+512x256x256 tank runs the launch the library uses there: 4 x 20 tiles in
+3 chunks of 86 planes, one round of 240 blocks."""
 
 
 
@@ -47,7 +49,7 @@ def case(name):
     return parity_case(name)
 
 
-CASES = ["c2", "g63", "g127", "c2half", "ragged3d", "rbragged", "g132", "g300"]
+CASES = ["c2", "g63", "g127", "c2half", "ragged3d", "rbragged", "g132", "g300", "c5"]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -112,15 +114,15 @@ def test_fused_sweep_switch_refuses_grids_it_does_not_fit(orc):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-def test_fused_sweep_default_follows_the_grid_size(orc, name):
+@pytest.mark.parametrize("name,default", [("c2", False), ("c3", False), ("c5", True)])
+def test_fused_sweep_default_follows_the_grid_size(orc, name, default):
     """On the 128x64x64 and 256x128x128 tanks (fewer than 2^24 cells) the
-    library starts with the two colour passes, and the switch turns the
-    fused launch on and off again."""
+    library starts with the two colour passes, on the 512x256x256 tank with
+    the fused launch, and the switch turns the fused launch on and off."""
     ns = _ns()
     wl = case(name)
     S = ns.Solver(ns.params(wl), ns.device_fields(I.make_fields(wl)))
-    assert not S.fine_sweep()
+    assert S.fine_sweep() == default
     S.set_fine_sweep(True)
     assert S.fine_sweep()
     S.set_fine_sweep(False)
