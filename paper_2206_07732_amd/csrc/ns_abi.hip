@@ -522,11 +522,15 @@ void launch_tail(ns_ctx* X, int l0, const T* b, T* e, size_t bytes) {
 struct DotsReq {
   const double* r;
   const double* zold;
+  double* z;     // the cycle's FP64 result, natural order
   int nparts;
 };
 
+// b0d: an FP32 cycle's finest-level right-hand side in FP64 (natural), read
+// by its first kernel in place of b0 (the levels below the finest, the
+// tail, and a cycle without pre-smoothing read b0)
 template <typename T>
-void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
+void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr, const double* b0d = nullptr) {
   const ns_params& P = X->P;
   const Level& L = X->lev[l];
   hipStream_t st = X->st;
@@ -539,16 +543,25 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
   const T *bx = LV<T>::bx(L), *by = LV<T>::by(L), *bz = LV<T>::bz(L);
   KTimer* kt = (l == 0 && X->timed_kernel == NS_TIME_SMOOTH0) ? &X->kt : nullptr;
   const size_t nsplit = 2 * (size_t)((L.n.nx + 1) / 2) * L.n.ny * L.n.nz;
-  // the red pass that writes the cycle's result e0 (level 0): with the
-  // products fused when they are requested (FP64, no kernel timer on it)
+  // the red pass that writes the cycle's result (level 0): with the
+  // products fused, into the FP64 z, when they are requested (no kernel
+  // timer on it), else into e0
   auto last_red = [&]() {
-    if constexpr (sizeof(T) == 8) {
-      if (dq && !kt) {
-        dq->nparts = launch_gs_last_dots(L, bx, by, bz, b, e, e0, dq->r, dq->zold, X->partials, st);
+    if (dq && !kt) {
+      dq->nparts = launch_gs_last_dots<T>(L, bx, by, bz, b, e, dq->z, dq->r, dq->zold, X->partials, st);
+      return;
+    }
+    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, e0);
+  };
+  // the first pre-smoothing kernel (red from zero + black)
+  auto first = [&](T* bcopy) {
+    if constexpr (sizeof(T) == 4) {
+      if (l == 0 && b0d) {
+        launch_gs_first_nat64(L, bx, by, bz, b0d, LV<T>::invd(L), e, b, st, bcopy);
         return;
       }
     }
-    launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, e0);
+    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st, bcopy);
   };
   if (l == X->L - 1) {
     // a coarsest level too large for the tail: its sweeps with the
@@ -562,7 +575,7 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
         launch_fill<T>(e, nsplit, st);
       return;
     }
-    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st);
+    first(nullptr);
     for (int s = 1; s < S; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
@@ -594,8 +607,7 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
   // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
     const bool rb_pre = rb && P.nu_pre >= 2;
-    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st,
-                       rb_pre ? ecopy : nullptr);
+    first(rb_pre ? ecopy : nullptr);
     int s = 1;
     if (rb_pre) {
       fused();
@@ -651,14 +663,19 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr) {
 // the cycle's last kernel also leaves the partials of r z and r z_old in
 // X->partials when it can; returns how many (0: not fused, or not asked).
 int precond_launch(ns_ctx* X, const double* r, double* z, const double* zold = nullptr) {
+  DotsReq dq{r, zold, z, 0};
   if (X->P.prec == NS_PREC_FP64) {
-    DotsReq dq{r, zold, 0};
     vcycle<double>(X, 0, r, z, zold ? &dq : nullptr);
     return dq.nparts;
   }
+  // FP32 cycle: its first kernel reads r itself, rounding it to FP32, where
+  // the finest level is above the tail and pre-smooths; its last kernel
+  // writes z in FP64 with the products when it can
   Level& L0 = X->lev[0];
-  launch_d2f(r, L0.bfn, X->nc, X->st);
-  vcycle<float>(X, 0, L0.bfn, L0.efn);
+  const bool direct = tail_start<float>(X) > 0 && X->P.nu_pre > 0;
+  if (!direct) launch_d2f(r, L0.bfn, X->nc, X->st);
+  vcycle<float>(X, 0, L0.bfn, L0.efn, zold ? &dq : nullptr, direct ? r : nullptr);
+  if (dq.nparts > 0) return dq.nparts;
   if (zold) return launch_f2d_dots(L0.efn, z, X->nc, r, zold, X->partials, X->st);
   launch_f2d(L0.efn, z, X->nc, X->st);
   return 0;

@@ -240,11 +240,16 @@ template <typename T>
 void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st);
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st);
 void launch_f2d(const float* a, double* b, size_t n, hipStream_t st);
-// the V-cycle's last kernel fused with the flexible CG's two products (r z,
-// r z_old): per-block partials, two per block; each returns the block count
-int launch_gs_last_dots(const Level& L, const double* bx, const double* by, const double* bz, const double* b,
-                        const double* e, double* nat, const double* r, const double* zold, double* partials,
-                        hipStream_t st);
+// the V-cycle's last kernel (its FP64 result z in natural order) fused with
+// the flexible CG's two products (r z, r z_old): per-block partials, two per
+// block; each returns the block count
+template <typename T>
+int launch_gs_last_dots(const Level& L, const T* bx, const T* by, const T* bz, const T* b, const T* e,
+                        double* nat, const double* r, const double* zold, double* partials, hipStream_t st);
+// the finest level's first kernel of an FP32 cycle reading its natural b in
+// FP64 (the CG residual), rounded as it is read
+void launch_gs_first_nat64(const Level& L, const float* bx, const float* by, const float* bz, const double* b,
+                           const float* invd, float* e, float* bs, hipStream_t st, float* bcopy = nullptr);
 int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
                     hipStream_t st);
 

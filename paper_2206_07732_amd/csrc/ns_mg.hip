@@ -220,17 +220,17 @@ __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ 
   if (nat && io < n.nx) nat[row + io] = eo[pos];
 }
 
-// The last red pass of the finest level in FP64, writing the V-cycle's
-// result z in natural order (as k_gs with nat), fused with the two products
-// the flexible CG needs next: per block, sum over its cells of r z and
-// r z_old, red cell then black cell of each pair, in tile order.  Every
-// thread reaches the block reduction (no early return).
-__global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const double* __restrict__ bx,
-                                                      const double* __restrict__ by,
-                                                      const double* __restrict__ bz,
-                                                      const double* __restrict__ b,
-                                                      const double* __restrict__ e, double* __restrict__ nat,
-                                                      const double* __restrict__ r,
+// The last red pass of the finest level, writing the V-cycle's result z in
+// natural order and in FP64 (as k_gs with nat; an FP32 cycle's values are
+// widened exactly), fused with the two products the flexible CG needs next:
+// per block, sum over its cells of r z and r z_old, red cell then black cell
+// of each pair, in tile order.  Every thread reaches the block reduction (no
+// early return).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, T h2, const T* __restrict__ bx,
+                                                      const T* __restrict__ by, const T* __restrict__ bz,
+                                                      const T* __restrict__ b, const T* __restrict__ e,
+                                                      double* __restrict__ nat, const double* __restrict__ r,
                                                       const double* __restrict__ zold,
                                                       double* __restrict__ partials) {
   const Tile tl = xcd_tile();
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const d
   double v[2] = {0.0, 0.0};
   const bool live = j < n.ny && k < n.nz && ti < sg.hx;
   const size_t pos = live ? (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k) : 0;
-  const double* eo = e + sg.P;   // the black plane
+  const T* eo = e + sg.P;   // the black plane
   // This pair's black value.  The red cell's x neighbours are this pair's
   // black cell and the adjacent pair's, which the adjacent lane holds (a
   // wavefront is 64 consecutive pairs of one row); every lane takes part in
@@ -256,26 +256,26 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const d
   const size_t sxy = (size_t)n.nx * n.ny;
   const size_t row = (size_t)n.nx * jj + sxy * kk;
   const int lane = threadIdx.x;
-  const double eb = eo[pos];
-  const GsIn<double> g = gs_gather<double>(n, sg, bx, by, bz, ir, jj, kk, pos, [&](size_t q) { return eo[q]; });
-  const double bc = b[pos];
-  double ex = 0.0;   // the row-end lanes' x neighbour from outside the wavefront
+  const T eb = eo[pos];
+  const GsIn<T> g = gs_gather<T>(n, sg, bx, by, bz, ir, jj, kk, pos, [&](size_t q) { return eo[q]; });
+  const T bc = b[pos];
+  T ex = 0;   // the row-end lanes' x neighbour from outside the wavefront
   if (live && lane == 0 && par == 0 && ir > 0) ex = eo[pos - 1];
   if (live && lane == 63 && par == 1 && ir < n.nx - 1) ex = eo[pos + 1];
   const double rr = r[row + ir], zr = zold[row + ir], rq = r[row + iq], zq = zold[row + iq];
   __builtin_amdgcn_sched_barrier(0);
-  const double ebl = __shfl_up(eb, 1, 64), ebr = __shfl_down(eb, 1, 64);
+  const T ebl = __shfl_up(eb, 1, 64), ebr = __shfl_down(eb, 1, 64);
   // formed on every lane from in-grid values, then kept by selects: a use
   // under a branch would let the compiler sink r's and z_old's loads past
   // the shuffles
-  double vw = eb, ve = eb;   // par 1: west is this pair's black; par 0: east is
+  T vw = eb, ve = eb;   // par 1: west is this pair's black; par 0: east is
   if (par == 0 && ir > 0) vw = lane > 0 ? ebl : ex;
   if (par == 1 && ir < n.nx - 1) ve = lane < 63 ? ebr : ex;
-  const double z = gs_combine<double>(n, g, h2, bc, ir, jj, kk, vw, ve);
+  const double z = (double)gs_combine<T>(n, g, h2, bc, ir, jj, kk, vw, ve), zb = (double)eb;
   const bool red_ok = live && i < n.nx, black_ok = live && io < n.nx;
   if (red_ok) nat[row + i] = z;
-  if (black_ok) nat[row + io] = eb;
-  v[0] = (red_ok ? rr * z : 0.0) + (black_ok ? rq * eb : 0.0);
+  if (black_ok) nat[row + io] = zb;
+  v[0] = (red_ok ? rr * z : 0.0) + (black_ok ? rq * zb : 0.0);
   v[1] = (red_ok ? rr * zr : 0.0) + (black_ok ? rq * zq : 0.0);
   block_partials<2>(v, partials, tl.lin);
 }
@@ -283,12 +283,14 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, double h2, const d
 // red pass from a zero guess followed by the black pass, in one launch: the
 // red values the black cells need are recomputed from b and 1/D.  NAT: b is
 // read in natural order (the finest level, whose b is a CG vector) and its
-// colour-split copy is written to bs for the later passes.
-template <typename T, bool FINE, bool NAT>
+// colour-split copy is written to bs for the later passes; a natural b may
+// be FP64 under an FP32 cycle (TB = double), rounded to T as it is read.
+template <typename T, bool FINE, bool NAT, typename TB = T>
 __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
-                                                  const T* __restrict__ bz, const T* __restrict__ b,
+                                                  const T* __restrict__ bz, const TB* __restrict__ b,
                                                   const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
                                                   T* __restrict__ bcopy) {
+  static_assert(NAT || sizeof(TB) == sizeof(T), "a colour-split b has the cycle's type");
   PAIR_INDEX;
   const int par = (j + k) & 1;
   const int ir = 2 * ti + par, ib = 2 * ti + 1 - par;
@@ -296,9 +298,9 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   // b of the cell (ii, jj, kk) of colour c with pair index q
   auto bval = [&](int c, size_t q, int ii, int jj, int kk) -> T {
     if constexpr (NAT)
-      return b[(size_t)ii + (size_t)n.nx * jj + sxy * kk];
+      return (T)b[(size_t)ii + (size_t)n.nx * jj + sxy * kk];
     else
-      return b[(size_t)c * sg.P + q];
+      return (T)b[(size_t)c * sg.P + q];
   };
   // This pair's red value h2 b / D, formed also where the red cell lies past
   // the row's end (b clamped into the row, an unused 1/D entry), since the
@@ -520,11 +522,16 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
 //
 // The march is bound by memory latency, not bandwidth: a plane's work is a
 // few dozen instructions per thread against one trip to HBM.  So every load
-// of plane m + 1 is issued, unconditionally from clamped addresses, before
-// plane m is computed, and waits only at its first use one plane later; the
-// loop is unrolled by two so that the two planes' registers alternate
-// without copies.
+// of a plane is issued, unconditionally from clamped addresses, before the
+// planes below it are computed, and waits only at its first use: one plane
+// ahead in FP64, two in FP32, whose planes carry half the bytes each (with
+// one plane in flight the FP32 march moved 3.2 TB/s, the FP64 one 4.3; a
+// second FP64 plane would not fit the 128 registers a 1024-thread block
+// allows).  The loop is unrolled by the depth so that the planes' registers
+// rotate without copies.
 constexpr int kRbfLanes = 64;
+template <typename T>
+constexpr int rbf_depth() { return sizeof(T) == 4 ? 3 : 2; }
 
 template <typename T>
 struct RbfLoads {
@@ -708,33 +715,70 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
     bo_d = bo_c;
     bo_c = bo_u;
   };
+  // plane p's loads sit in buffer (p - k0 + 1) % D; the halo wave and the
+  // main waves pass the same planes, so they meet the same barriers (the
+  // two-deep form is written out: as the general loop it spilled in FP64)
+  constexpr int D = rbf_depth<T>();
   if (halo) {
-    RbfHaloLoads<T> A, B;
-    load_h(k0 - 1, A);
-    __syncthreads();
-    for (int m = k0 - 1; m <= kz1; m += 2) {
-      load_h(m + 1, B);
-      __builtin_amdgcn_sched_barrier(0);
-      plane_h(m, A);
-      if (m + 1 > kz1) break;
-      load_h(m + 2, A);
-      __builtin_amdgcn_sched_barrier(0);
-      plane_h(m + 1, B);
+    if constexpr (D == 2) {
+      RbfHaloLoads<T> A, B;
+      load_h(k0 - 1, A);
+      __syncthreads();
+      for (int m = k0 - 1; m <= kz1; m += 2) {
+        load_h(m + 1, B);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_h(m, A);
+        if (m + 1 > kz1) break;
+        load_h(m + 2, A);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_h(m + 1, B);
+      }
+    } else {
+      RbfHaloLoads<T> H[D];
+#pragma unroll
+      for (int q = 0; q < D - 1; ++q) load_h(k0 - 1 + q, H[q]);
+      __syncthreads();
+      for (int m = k0 - 1; m <= kz1; m += D) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          if (q > 0 && m + q > kz1) return;
+          load_h(m + q + D - 1, H[(q + D - 1) % D]);
+          __builtin_amdgcn_sched_barrier(0);
+          plane_h(m + q, H[q]);
+        }
+      }
     }
     return;
   }
-  RbfLoads<T> A, B;
-  load(k0 - 1, A);
-  BO[(k0 - 1) & 1][r][lane] = bo_c;
-  __syncthreads();
-  for (int m = k0 - 1; m <= kz1; m += 2) {
-    load(m + 1, B);
-    __builtin_amdgcn_sched_barrier(0);
-    plane(m, A);
-    if (m + 1 > kz1) break;
-    load(m + 2, A);
-    __builtin_amdgcn_sched_barrier(0);
-    plane(m + 1, B);
+  if constexpr (D == 2) {
+    RbfLoads<T> A, B;
+    load(k0 - 1, A);
+    BO[(k0 - 1) & 1][r][lane] = bo_c;
+    __syncthreads();
+    for (int m = k0 - 1; m <= kz1; m += 2) {
+      load(m + 1, B);
+      __builtin_amdgcn_sched_barrier(0);
+      plane(m, A);
+      if (m + 1 > kz1) break;
+      load(m + 2, A);
+      __builtin_amdgcn_sched_barrier(0);
+      plane(m + 1, B);
+    }
+  } else {
+    RbfLoads<T> A[D];
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) load(k0 - 1 + q, A[q]);
+    BO[(k0 - 1) & 1][r][lane] = bo_c;
+    __syncthreads();
+    for (int m = k0 - 1; m <= kz1; m += D) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        if (q > 0 && m + q > kz1) return;
+        load(m + q + D - 1, A[(q + D - 1) % D]);
+        __builtin_amdgcn_sched_barrier(0);
+        plane(m + q, A[q]);
+      }
+    }
   }
 }
 
@@ -1759,13 +1803,20 @@ void launch_d2f(const double* a, float* b, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
 }
 
-int launch_gs_last_dots(const Level& L, const double* bx, const double* by, const double* bz, const double* b,
-                        const double* e, double* nat, const double* r, const double* zold, double* partials,
-                        hipStream_t st) {
+template <typename T>
+int launch_gs_last_dots(const Level& L, const T* bx, const T* by, const T* bz, const T* b, const T* e,
+                        double* nat, const double* r, const double* zold, double* partials, hipStream_t st) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
-  hipLaunchKernelGGL(k_gs_last_dots, g.grid, g.block, 0, st, L.n, L.h * L.h, bx, by, bz, b, e, nat, r, zold,
-                     partials);
+  hipLaunchKernelGGL(k_gs_last_dots<T>, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, nat, r,
+                     zold, partials);
   return (int)(g.grid.x * g.grid.y * g.grid.z);
+}
+
+void launch_gs_first_nat64(const Level& L, const float* bx, const float* by, const float* bz, const double* b,
+                           const float* invd, float* e, float* bs, hipStream_t st, float* bcopy) {
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
+  hipLaunchKernelGGL((k_gs_first<float, true, true, double>), g.grid, g.block, 0, st, L.n, (float)(L.h * L.h), bx,
+                     by, bz, b, invd, e, bs, bcopy);
 }
 
 int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
@@ -1871,6 +1922,8 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
 #define NSK_INST(T)                                                                                   \
   template void launch_gs<T>(const Level&, const T*, const T*, const T*, const T*, T*, int, hipStream_t,   \
                              KTimer*, T*);                                                                \
+  template int launch_gs_last_dots<T>(const Level&, const T*, const T*, const T*, const T*, const T*,     \
+                                      double*, const double*, const double*, double*, hipStream_t);       \
   template void launch_gs_first<T>(const Level&, const T*, const T*, const T*, const T*, bool, const T*,  \
                                    T*, T*, hipStream_t, T*);                                              \
   template void launch_gs_prolong<T>(const Level&, const T*, const T*, const T*, const T*, T*,           \
