@@ -782,6 +782,17 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
   }
 }
 
+// the residual b - A x of one cell from its value, its neighbours' (a wall
+// neighbour given as the cell's own value) and its six faces; up: the cell
+// is below the top row (else the open top's ghost term 2 beta_top x_c)
+template <typename T>
+__device__ __forceinline__ T cell_resid(T bcell, T ih2, T xc, T xw, T xe, T xs, T xn, T xd, T xu, T cw, T ce, T cs,
+                                        T cn, T cd, T bu, bool up) {
+  T acc = cw * (xc - xw) + ce * (xc - xe) + cs * (xc - xs) + cn * (xc - xn) + cd * (xc - xd);
+  acc += up ? bu * (xc - xu) : (T)2 * bu * xc;
+  return bcell - ih2 * acc;
+}
+
 // coarse rhs = mean over the children of the fine residual b - A e (fine b,
 // e colour-split; the coarse b colour-split when csplit, else natural).  A
 // block takes a tile of fine cells (32 x 4 x 2; 64 x 1 x 4 in 2-D), one
@@ -828,9 +839,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
     // all loads above are in flight together: the compiler may not sink the
     // up neighbour's load into the branch that uses it
     __builtin_amdgcn_sched_barrier(0);
-    T acc = cw * (xc - xw) + ce * (xc - xe) + cs * (xc - xs) + cn * (xc - xn) + cd * (xc - xd);
-    acc += (k < nf.nz - 1) ? bu * (xc - xu) : (T)2 * bu * xc;
-    r = bcell - ih2 * acc;
+    r = cell_resid<T>(bcell, ih2, xc, xw, xe, xs, xn, xd, xu, cw, ce, cs, cn, cd, bu, k < nf.nz - 1);
   }
   const int t = (tz * TY + ty) * TX + tx;
   sr[t] = r;
@@ -847,6 +856,74 @@ __global__ void __launch_bounds__(256) k_resid_restrict(Dims nf, int fx, int fy,
   for (int dk = 0; dk < fz; ++dk)
     for (int dj = 0; dj < fy; ++dj)
       for (int di = 0; di < fx; ++di) sum += sr[((tz + dk) * TY + ty + dj) * TX + tx + di];
+  const int chx = (nc.nx + 1) >> 1, cP = chx * nc.ny * nc.nz;
+  const int ci = csplit ? ((I + J + K) & 1) * cP + (I >> 1) + chx * (J + nc.ny * K) : I + nc.nx * (J + nc.ny * K);
+  bc[ci] = sum * inv;
+}
+
+// The same on a level whose extents are all even and which is halved in
+// every direction, so that coarse cell (I, J, K) holds fine pair I of rows
+// 2J, 2J + 1 and planes 2K, 2K + 1.  One thread per pair of cells: every
+// load of a wave is 64 consecutive pairs of one colour, or the faces of one
+// row (y and z faces as two-element vector loads), and a pair's x
+// neighbours come from the adjacent lanes; a cell-per-thread tile issues
+// half as many loads again, at stride two.  A block takes 64 pairs x 2 rows
+// x 2 planes, the children of 64 coarse cells, and its first wave sums each
+// coarse cell's eight residuals in k_resid_restrict's order (dk, dj, di), so
+// the result is the same.
+template <typename T>
+__global__ void __launch_bounds__(256) k_resid_restrict_pairs(Dims nf, T ih2, const T* __restrict__ bx,
+                                                              const T* __restrict__ by, const T* __restrict__ bz,
+                                                              const T* __restrict__ b, const T* __restrict__ e,
+                                                              Dims nc, int csplit, T inv, T* __restrict__ bc) {
+  using T2 = T __attribute__((ext_vector_type(2)));
+  __shared__ T sr[2][2][2][64];   // [dk][dj][di][lane]
+  const Tile tl = xcd_tile();
+  const int lane = threadIdx.x, dj = threadIdx.y, dk = threadIdx.z;
+  const int hx = nf.nx >> 1;
+  const int ti = tl.x * 64 + lane, j = 2 * tl.y + dj, k = 2 * tl.z + dk;
+  const bool live = ti < hx;
+  const int tc = live ? ti : hx - 1;   // lanes past the row's end work on its last pair and store nothing
+  // 32-bit index arithmetic: every array of a level has fewer than 2^31 entries
+  const int P = hx * nf.ny * nf.nz, sz = hx * nf.ny, sxy = nf.nx * nf.ny;
+  const int pos = tc + hx * (j + nf.ny * k);
+  const int par = (j + k) & 1;   // colour of the pair's first cell A (i = 2 tc); B is i = 2 tc + 1
+  const int pa = par * P + pos, pb = (1 - par) * P + pos;
+  const bool W = tc > 0, E = tc < hx - 1, S = j > 0, N = j < nf.ny - 1, D = k > 0, U = k < nf.nz - 1;
+  // A's y and z neighbours have B's colour, and B's have A's; a wall
+  // neighbour reads the cell's own entry
+  const T xa = e[pa], xb = e[pb];
+  const T xas = e[S ? pb - hx : pa], xan = e[N ? pb + hx : pa], xad = e[D ? pb - sz : pa], xau = e[U ? pb + sz : pa];
+  const T xbs = e[S ? pa - hx : pb], xbn = e[N ? pa + hx : pb], xbd = e[D ? pa - sz : pb], xbu = e[U ? pa + sz : pb];
+  // outside the wavefront: lane 0 loads A's west neighbour (B of the pair
+  // before), lane 63 B's east one (A of the pair after)
+  const T xo = e[lane == 0 ? (W ? pb - 1 : pa) : lane == 63 ? (E ? pa + 1 : pb) : pa];
+  const int fx = 2 * tc + (nf.nx + 1) * (j + nf.ny * k);
+  const int fy = 2 * tc + nf.nx * (j + (nf.ny + 1) * k);
+  const int c = 2 * tc + nf.nx * j + sxy * k;
+  const T fwa = bx[fx], fab = bx[fx + 1];   // A's west face; the face between A and B
+  const T feo = bx[lane == 63 ? fx + 2 : fx];   // B's east face, for lane 63
+  const T2 fs = *reinterpret_cast<const T2*>(by + fy), fn = *reinterpret_cast<const T2*>(by + fy + nf.nx);
+  const T2 fd = *reinterpret_cast<const T2*>(bz + c), fu = *reinterpret_cast<const T2*>(bz + c + sxy);
+  const T ba = b[pa], bb = b[pb];
+  __builtin_amdgcn_sched_barrier(0);
+  const T xbl = __shfl_up(xb, 1, 64), xar = __shfl_down(xa, 1, 64), fwr = __shfl_down(fwa, 1, 64);
+  const T xaw = W ? (lane > 0 ? xbl : xo) : xa;
+  const T xbe = E ? (lane < 63 ? xar : xo) : xb;
+  const T feb = lane < 63 ? fwr : feo;
+  sr[dk][dj][0][lane] = cell_resid<T>(ba, ih2, xa, xaw, xb, xas, xan, xad, xau, fwa, fab, fs.x, fn.x, fd.x, fu.x, U);
+  sr[dk][dj][1][lane] = cell_resid<T>(bb, ih2, xb, xa, xbe, xbs, xbn, xbd, xbu, fab, feb, fs.y, fn.y, fd.y, fu.y, U);
+  __syncthreads();
+  if (dj | dk) return;
+  T sum = 0;
+#pragma unroll
+  for (int qk = 0; qk < 2; ++qk)
+#pragma unroll
+    for (int qj = 0; qj < 2; ++qj)
+#pragma unroll
+      for (int qi = 0; qi < 2; ++qi) sum += sr[qk][qj][qi][lane];
+  if (!live) return;
+  const int I = ti, J = tl.y, K = tl.z;
   const int chx = (nc.nx + 1) >> 1, cP = chx * nc.ny * nc.nz;
   const int ci = csplit ? ((I + J + K) & 1) * cP + (I >> 1) + chx * (J + nc.ny * K) : I + nc.nx * (J + nc.ny * K);
   bc[ci] = sum * inv;
@@ -1741,13 +1818,25 @@ void launch_gs_rb_fine(const Level& L, const T* bx, const T* by, const T* bz, co
   hipLaunchKernelGGL((k_gs_rb_fine<T, TY>), grid, blk, 0, st, L.n, h2, bx, by, bz, b, e, bold, KZ);
 }
 
+// the pair form of the residual-restriction: even extents, halved in every
+// direction (the fine level is colour-split wherever it is called)
+static bool resid_pairs_fit(const Level& F) {
+  return F.f[0] == 2 && F.f[1] == 2 && F.f[2] == 2 && F.n.nx % 2 == 0 && F.n.ny % 2 == 0 && F.n.nz % 2 == 0;
+}
+
 template <typename T>
 void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz, const T* b,
                            const T* e, const Level& C, T* bc, bool c_split, hipStream_t st) {
+  const T ih2 = (T)(1.0 / (F.h * F.h));
+  if (resid_pairs_fit(F)) {
+    const dim3 grid((F.n.nx / 2 + 63) / 64, F.n.ny / 2, F.n.nz / 2);
+    hipLaunchKernelGGL(k_resid_restrict_pairs<T>, grid, dim3(64, 2, 2), 0, st, F.n, ih2, bx, by, bz, b, e, C.n,
+                       c_split ? 1 : 0, (T)0.125, bc);
+    return;
+  }
   // fine-cell tiles with even extents (a coarse cell's children in one tile)
   const dim3 blk = (F.n.ny > 1) ? dim3(32, 4, 2) : dim3(64, 1, 4);
   const Geo g{dim3((F.n.nx + blk.x - 1) / blk.x, (F.n.ny + blk.y - 1) / blk.y, (F.n.nz + blk.z - 1) / blk.z), blk};
-  const T ih2 = (T)(1.0 / (F.h * F.h));
   const T inv = (T)(1.0 / (F.f[0] * F.f[1] * F.f[2]));
   hipLaunchKernelGGL(k_resid_restrict<T>, g.grid, g.block, 0, st, F.n, F.f[0], F.f[1], F.f[2], ih2, bx,
                      by, bz, b, e, C.n, c_split ? 1 : 0, inv, bc);
