@@ -1405,7 +1405,9 @@ ns_status projection_solve(ns_ctx* X, double dt, ns_stats* stats) {
     }
     if (trial) {   // net_guess synchronised the stream
       const double bb = host_total(X, 2, 1, S_BB), rr = host_total(X, 2, 0, S_RR);
-      rel_prev = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+      // formed as the solve forms its starting relative residual, so that a
+      // guess equal to p_prev compares equal
+      rel_prev = bb > 0.0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
       float ms = 0.f;
       HIPCHK(X, hipEventElapsedTime(&ms, X->ax.ev[0], X->ax.ev[1]));
       X->ax.t_inf = ms;
