@@ -14,25 +14,40 @@ namespace nsk {
 // The tile (block coordinates in the launch grid) a workgroup works on.
 // Workgroups are handed to the eight XCDs round-robin by linear id, and each
 // XCD has its own L2; this gives XCD x the contiguous run of tiles
-// [start(x), start(x + 1)) in x-fastest tile order, so that tiles sharing
-// halo rows and planes mostly share an L2.  It is a bijection for any grid,
-// so no result depends on the dispatch order.  lin is the tile's linear
-// index, which also numbers its reduction partial.
+// [start(x), start(x + 1)) of the tile order, so that tiles sharing halo
+// rows and planes mostly share an L2.  The order takes the tile rows in
+// bands of kTileBand (x fastest, then y within the band, then z, then the
+// next band) where the band divides the grid's rows, so that a tile's
+// z-neighbours run a band's width of tiles after it rather than a whole
+// plane's, and the planes a stencil reads three times are still in the L2
+// (on 512x256x256 the finest-level stencils took 2-7% less time than in
+// plain x, y, z order, which the other grids keep).  xcd_tile_flat keeps
+// plain order for kernels that march along z themselves.  Both are
+// bijections for any grid, so no result depends on the dispatch order.  lin
+// is the tile's position in the order, which also numbers its reduction
+// partial.
 struct Tile {
   int x, y, z, lin;
 };
-__device__ __forceinline__ Tile xcd_tile() {
+constexpr int kTileBand = 8;
+__device__ __forceinline__ Tile xcd_tile_order(int band) {
   const int gx = gridDim.x, gy = gridDim.y;
   const int nb = gx * gy * (int)gridDim.z;
   const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   Tile t;
   t.lin = x * q + (x < r ? x : r) + (b >> 3);
-  t.x = t.lin % gx;
-  const int yz = t.lin / gx;
-  t.y = yz % gy;
-  t.z = yz / gy;
+  const int per = gx * band * (int)gridDim.z;   // tiles per band
+  const int bi = t.lin / per, rem = t.lin - bi * per;
+  t.x = rem % gx;
+  const int yz = rem / gx;
+  t.y = bi * band + yz % band;
+  t.z = yz / band;
   return t;
+}
+__device__ __forceinline__ Tile xcd_tile_flat() { return xcd_tile_order(gridDim.y); }
+__device__ __forceinline__ Tile xcd_tile() {
+  return xcd_tile_order(gridDim.y % kTileBand == 0 ? kTileBand : gridDim.y);
 }
 
 struct Dims {

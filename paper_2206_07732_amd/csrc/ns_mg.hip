@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(kRbThreads) k_gs_rb(Dims n, T h2, const T* __r
                                                       const T* __restrict__ bold, int TX, int TY, int TZ) {
   __shared__ T R[kRbMaxExt];
   const SplitGeo sg = split_geo(n);
-  const Tile tl = xcd_tile();
+  const Tile tl = xcd_tile_flat();
   const int ty0 = tl.y * TY, tz0 = tl.z * TZ;
   const int ry = n.ny > 1 ? 1 : 0;   // ring width in y (none in a 2-D tank)
   const int EY = TY + 2 * ry, NE = TX * EY * (TZ + 2);
@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(kRbfLanes * (TY + 3)) k_gs_rb_fine(Dims n, T h
   __shared__ T RYN[3][R][kRbfLanes];
   __shared__ T HH[3][2][R];            // the halo's red values: [plane mod 3][west, east][row]
   const SplitGeo sg = split_geo(n);
-  const Tile tl = xcd_tile();
+  const Tile tl = xcd_tile_flat();
   const int lane = threadIdx.x, r = threadIdx.y;
   const bool halo = r == R;            // the halo wave (wave-uniform)
   const int tx0 = tl.x * kRbfLanes;    // this block's first pair of a row
