@@ -65,7 +65,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE, medians
 # over 346 dispatches.  Valid for that kernel as it is now and for that
 # workload only; None elsewhere.
-TRAFFIC_BYTES_PER_LAUNCH = {("k_gs_rb_fine<double, 13>", "c5"): 2031984981}
+TRAFFIC_BYTES_PER_LAUNCH = {("k_gs_rb_fine<double, 13>", "c5"): 2033923410}
 
 # Algorithmic bytes per cell (FP64, 3-D; each array read or written once per
 # pass): the passes outside the solve, and one FP64 CG iteration (vector work
