@@ -157,23 +157,44 @@ __global__ void __launch_bounds__(256) k_conv(VDims d, const uint16_t* __restric
   fetch(0);
   put(0);
   __syncthreads();
+  // The tap pairs are software-pipelined: the four activation fragments of
+  // pair p + 1 are read from LDS, and the weight fragments of pair p + WD
+  // requested, before pair p's MFMAs issue, so that an MFMA never waits on
+  // the read just before it (with the reads one fragment ahead, each MFMA
+  // waited out an LDS round trip and the layer ran at a quarter of the MFMA
+  // peak).  The first pairs' weights are requested before the next chunk's
+  // tile pieces, which the in-order load counter would otherwise make them
+  // wait behind.
+  constexpr int WD = NT == 1 ? 3 : 1;   // weight prefetch distance in tap pairs
+  bf16x8 aq[2][4], bq[WD + 1][NT];
 #pragma unroll 1
   for (int c = 0; c < NC; ++c) {
-    if (c + 1 < NC) fetch(c + 1);
     const u32x4* T = tile[c & 1] + lbase;
-#pragma unroll
-    for (int p = 0; p < 14; ++p) {
+    auto lda = [&](int p, bf16x8 (&a)[4]) {
       const bool tv = 2 * p + (kg >> 1) < 27;
       const int o = (kg >> 1) ? tap_off(2 * p + 1) : tap_off(2 * p);
-      bf16x8 b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = wfrag(p, t, c);
+      for (int m = 0; m < 4; ++m) a[m] = as_bf16x8(tv ? T[o + m * kHX] : zero);
+    };
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const bf16x8 a = as_bf16x8(tv ? T[o + m * kHX] : zero);
+    for (int q = 0; q < WD; ++q)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+      for (int t = 0; t < NT; ++t) bq[q][t] = wfrag(q, t, c);
+    if (c + 1 < NC) fetch(c + 1);
+    lda(0, aq[0]);
+#pragma unroll
+    for (int p = 0; p < 14; ++p) {
+      if (p + WD < 14) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bq[(p + WD) % (WD + 1)][t] = wfrag(p + WD, t, c);
       }
+      if (p + 1 < 14) lda(p + 1, aq[(p + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[p & 1][m], bq[p % (WD + 1)][t], acc[m][t], 0, 0, 0);
     }
     if (c + 1 < NC) put((c + 1) & 1);
     __syncthreads();
