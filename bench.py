@@ -60,12 +60,15 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 
-# HBM bytes per launch of the dominant kernel (the fused finest-level sweep
-# k_gs_rb_fine<double, 13>) at 512x256x256 from two rocprofv3 --pmc passes:
-# FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE, medians
-# over 346 dispatches.  Valid for that kernel as it is now and for that
-# workload only; None elsewhere.
-TRAFFIC_BYTES_PER_LAUNCH = {("k_gs_rb_fine<double, 13>", "c5"): 2033923410}
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
+# passes: FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE,
+# medians over the run's dispatches (the fused finest-level sweep at
+# 512x256x256, 346; the colour pass at 128x64x64, 556).  Valid for those
+# kernels as they are now and for those workloads only; None elsewhere.
+TRAFFIC_BYTES_PER_LAUNCH = {
+    ("k_gs_rb_fine<double, 13>", "c5"): 2033923410,
+    ("k_gs<double, true>", "c2"): 19614207,
+}
 
 # Algorithmic bytes per cell (FP64, 3-D; each array read or written once per
 # pass): the passes outside the solve, and one FP64 CG iteration (vector work
