@@ -304,9 +304,10 @@ ns_status ns_set_launch_mode(ns_ctx* ctx, int mode);
  * fused = 1 as one launch that reads each face coefficient once, the black
  * values taking theirs from the red values' loads; fused = 0 as two colour
  * passes.  The fused launch applies to 3-D levels with ny, nz >= 4 and at
- * least 32 cell pairs per row; ns_create picks it where it applies and the
- * finest level has at least 2^24 cells, the two passes elsewhere (its planes
- * are a chain of dependent steps, which smaller grids cannot cover).
+ * least 32 cell pairs per row; ns_create picks it for an FP64 cycle where it
+ * applies and the finest level has at least 2^24 cells, the two passes
+ * elsewhere (its planes are a chain of dependent steps, which smaller grids
+ * cannot cover, and an FP32 cycle's planes carry too few bytes to hide).
  * Results are bitwise the same either way.  Recorded V-cycle graphs are released and recorded again on their
  * next use (synchronises the stream).  NS_EINVAL for another value, or
  * fused = 1 on a grid it does not apply to. */
