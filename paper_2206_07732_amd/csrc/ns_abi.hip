@@ -812,13 +812,23 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     });
   };
   // (four kernels: launched directly, a graph launch would cost the device
-  // more than it saves the host)
+  // more than it saves the host).  x += alpha d is applied one iteration
+  // late, by the next direction update, which reads d anyway: the vector
+  // update then reads and writes only r (8 bytes per cell less per
+  // iteration, the same arithmetic).  xpend: x lacks the latest alpha d;
+  // sync_x applies it before anything reads x.
+  bool xpend = false;
   auto dir_update = [&](const double* zz, const double* dold, double* dnew, int first) {
     launch_dir_spmv(n, h, L0.bx, L0.by, L0.bz, zz, dold, dnew, X->q, first, cs, X->st,
-                    X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr);
-    launch_cg_update(n, dnew, X->q, x, X->r, cs, X->st);
+                    X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr, xpend ? x : nullptr);
+    launch_cg_update(n, X->q, X->r, cs, X->st);
+    xpend = true;
     HIPCHK(X, hipGetLastError());
     return NS_OK;
+  };
+  auto sync_x = [&](const double* dcur) {
+    if (xpend) launch_x_update(n, dcur, x, cs, X->st);
+    xpend = false;
   };
   prepare_hierarchy(X);
   launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
@@ -871,6 +881,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     S.rel_resid = std::sqrt(rr) / bnorm;
     if (rr <= tol2) {
       // confirm on the true residual; restart from it when it fails
+      sync_x(d);
       launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
       if ((s = wait_host(X)) != NS_OK) return s;
       rr = true_rr = host_total(X, 2, 0, S_RR);
@@ -889,6 +900,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     if (!ahead && (s = precond_beta(zn, z)) != NS_OK) return s;
     std::swap(z, zn);
   }
+  sync_x(d);
   if (!conv) {
     // true residual at exit (into q, leaving r as the recursion left it)
     launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st);

@@ -285,11 +285,15 @@ void launch_dot_rho(const Dims& n, const double* r, const double* z, const CgScr
 void launch_finalize_beta(const CgScratch& cs, int nparts, hipStream_t st);
 void launch_dots_beta(const Dims& n, const double* r, const double* zn, const double* z,
                       const CgScratch& cs, hipStream_t st);
+// d = z + beta d_old and q = A d; with x, also the previous iteration's
+// pending x += alpha d_old
 void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                      const double* zn, const double* dold, double* dnew, double* q, int first,
-                     const CgScratch& cs, hipStream_t st, KTimer* kt = nullptr);
-void launch_cg_update(const Dims& n, const double* d, const double* q, double* x, double* r,
-                      const CgScratch& cs, hipStream_t st);
+                     const CgScratch& cs, hipStream_t st, KTimer* kt = nullptr, double* x = nullptr);
+// r -= alpha q and ||r||^2; x += alpha d is left pending
+void launch_cg_update(const Dims& n, const double* q, double* r, const CgScratch& cs, hipStream_t st);
+// the pending x += alpha d
+void launch_x_update(const Dims& n, const double* d, double* x, const CgScratch& cs, hipStream_t st);
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                     const double* x, double* y, hipStream_t st);
 

@@ -1518,7 +1518,9 @@ __global__ void __launch_bounds__(256) k_dots_beta(Dims n, const double* __restr
 // d = zn + beta d_old, q = A d = A zn + beta q_old (first: d = zn, q = A zn);
 // alpha = rho / <d, q>.  Carrying q = A d by its recurrence keeps the
 // stencil on zn alone, and d_old and q_old are read pointwise: the stencil's
-// load count, not its bytes, limits this kernel.  A wavefront is one x-row of
+// load count, not its bytes, limits this kernel.  With xupd it also applies
+// the previous iteration's x += alpha d_old (alpha still in scal, d_old
+// already loaded here), which the vector update then leaves out.  A wavefront is one x-row of
 // 64 cells (blockDim.x == 64), so the x neighbours of zn come from the
 // adjacent lanes and only a row's end lanes load them; every lane takes part
 // in the shuffles (c is 0 outside the grid).
@@ -1529,7 +1531,8 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
                                                   const double* __restrict__ dold,
                                                   double* __restrict__ dnew, double* __restrict__ q,
                                                   int first, const double* __restrict__ scal,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials, double* __restrict__ x,
+                                                  int xupd) {
   CELL_INDEX;
   double v[1] = {0.0};
   // Every load is issued before the shuffles wait for zc: the faces and the
@@ -1549,9 +1552,11 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
   if (lane == 0 && ii > 0) zx = zn[c - 1];
   if (lane == 63 && ii < n.nx - 1) zx = zn[c + 1];
   const double dol = dold[c], qol = q[c];
+  const double xo = xupd ? x[c] : 0.0;
   __builtin_amdgcn_sched_barrier(0);
   const double zl = __shfl_up(zc, 1, 64), zr = __shfl_down(zc, 1, 64);
   if (inside) {
+    if (xupd) x[c] = xo + scal[S_ALPHA] * dol;
     double zw = zc, ze = zc;
     if (i > 0) zw = lane > 0 ? zl : zx;
     if (i < n.nx - 1) ze = lane < 63 ? zr : zx;
@@ -1571,21 +1576,26 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
   block_partials<1>(v, partials, tl.lin);
 }
 
-// x += alpha d; r -= alpha q; ||r||^2
-__global__ void __launch_bounds__(256) k_cg_update(Dims n, const double* __restrict__ d,
-                                                   const double* __restrict__ q, double* __restrict__ x,
-                                                   double* __restrict__ r, const double* __restrict__ scal,
+// r -= alpha q; ||r||^2 (the matching x += alpha d is applied by the next
+// direction update, or by k_x_update before x is read)
+__global__ void __launch_bounds__(256) k_cg_update(Dims n, const double* __restrict__ q, double* __restrict__ r,
+                                                   const double* __restrict__ scal,
                                                    double* __restrict__ partials) {
   CELL_INDEX;
   double v[1] = {0.0};
   if (inside) {
-    const double alpha = scal[S_ALPHA];
-    x[c] += alpha * d[c];
-    const double rc = r[c] - alpha * q[c];
+    const double rc = r[c] - scal[S_ALPHA] * q[c];
     r[c] = rc;
     v[0] = rc * rc;
   }
   block_partials<1>(v, partials, tl.lin);
+}
+
+// x += alpha d: the update the CG vector update leaves pending
+__global__ void __launch_bounds__(256) k_x_update(Dims n, const double* __restrict__ d, double* __restrict__ x,
+                                                  const double* __restrict__ scal) {
+  CELL_INDEX;
+  if (inside) x[c] = x[c] + scal[S_ALPHA] * d[c];
 }
 
 __global__ void __launch_bounds__(256) k_apply_A(Dims n, double ih2, const double* __restrict__ bx,
@@ -1981,27 +1991,32 @@ void launch_dots_beta(const Dims& n, const double* r, const double* zn, const do
 
 void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                      const double* zn, const double* dold, double* dnew, double* q, int first,
-                     const CgScratch& cs, hipStream_t st, KTimer* kt) {
+                     const CgScratch& cs, hipStream_t st, KTimer* kt, double* x) {
   Geo g = geo3(n.nx, n.ny, n.nz);
+  const int xupd = x ? 1 : 0;
   if (kt && kt->n < kt->cap) {
     (void)hipStreamSynchronize(st);
     hipExtLaunchKernelGGL(k_dir_spmv, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0,
                           n, 1.0 / (h * h), bx, by, bz, zn, dold, dnew, q, first, (const double*)cs.scal,
-                          cs.partials);
+                          cs.partials, x, xupd);
     ++kt->n;
   } else {
     hipLaunchKernelGGL(k_dir_spmv, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, zn, dold, dnew, q,
-                       first, (const double*)cs.scal, cs.partials);
+                       first, (const double*)cs.scal, cs.partials, x, xupd);
   }
   finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_ALPHA, st);
 }
 
-void launch_cg_update(const Dims& n, const double* d, const double* q, double* x, double* r,
-                      const CgScratch& cs, hipStream_t st) {
+void launch_cg_update(const Dims& n, const double* q, double* r, const CgScratch& cs, hipStream_t st) {
   Geo g = geo3(n.nx, n.ny, n.nz);
-  hipLaunchKernelGGL(k_cg_update, g.grid, g.block, 0, st, n, d, q, x, r, (const double*)cs.scal,
+  hipLaunchKernelGGL(k_cg_update, g.grid, g.block, 0, st, n, q, r, (const double*)cs.scal,
                      cs.hpart ? cs.hpart : cs.partials);
   if (!cs.hpart) finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_RR, st);
+}
+
+void launch_x_update(const Dims& n, const double* d, double* x, const CgScratch& cs, hipStream_t st) {
+  Geo g = geo3(n.nx, n.ny, n.nz);
+  hipLaunchKernelGGL(k_x_update, g.grid, g.block, 0, st, n, d, x, (const double*)cs.scal);
 }
 
 void launch_apply_A(const Dims& n, double h, const double* bx, const double* by, const double* bz,
