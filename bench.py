@@ -63,10 +63,10 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
 # passes: FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE,
 # medians over the run's dispatches (the fused finest-level sweep at
-# 512x256x256, 346; the colour pass at 128x64x64, 556).  Valid for those
+# 512x256x256, 336; the colour pass at 128x64x64, 556).  Valid for those
 # kernels as they are now and for those workloads only; None elsewhere.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("k_gs_rb_fine<double, 13>", "c5"): 2033923410,
+    ("k_gs_rb_fine<double, 13>", "c5"): 2027212498,
     ("k_gs<double, true>", "c2"): 19614207,
 }
 
