@@ -143,3 +143,44 @@ def test_c5_one_step_windows_and_properties(orc):
     for k in ("p", "u", "v", "w"):
         gate(f"fullsize mixed vs fp64 {k}", dev32[k], p64[k], 1e-8, sc.of(k, p64[k].cpu().numpy()))
     S32.close()
+
+
+def test_c5_operator_and_vcycle_parity(orc):
+    """The operator and one V-cycle on the whole 512x256x256 grid against the
+    oracle's (a few seconds of CPU each), with the face coefficients of a
+    predictor step: FP64 in the launch the library uses there (the finest
+    level's sweeps fused, 3 chunks of 86 planes; the residual-restriction by
+    cell pairs on levels halved in every direction; the banded tile order),
+    and the FP32 cycle (two colour passes on the finest level) against the
+    oracle's FP32 cycle."""
+    ns = _ns()
+    wl = I.workload("c5")
+    f = I.make_fields(wl)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
+    dev = ns.device_fields(f)
+    S = ns.Solver(ns.params(wl), dev)
+    assert S.fine_sweep()
+    S.momentum_step(dt, dt)
+    torch.cuda.synchronize()
+    bx, by, bz = (S.buffer(k).cpu().numpy() for k in ("bx", "by", "bz"))
+    x = np.random.default_rng(9).standard_normal(f["p"].shape)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty_like(xd)
+    S.apply_A(xd, y)
+    torch.cuda.synchronize()
+    yo = orc.apply_A(wl.nx, wl.ny, wl.nz, wl.h, bx, by, bz, x)
+    gate("c5 A x", y, yo, 1e-13, float(np.max(np.abs(yo))))
+    S.vcycle(xd, y)
+    torch.cuda.synchronize()
+    print("[fullsize] GPU V-cycle done, oracle V-cycle", flush=True)
+    zo = orc.vcycle(orc.params(wl), bx, by, bz, x)
+    gate("c5 V-cycle fp64", y, zo, 1e-12, float(np.max(np.abs(zo))))
+    S.close()
+    S32 = ns.Solver(ns.params(wl, prec=ns.PREC_MIXED), dev)
+    assert not S32.fine_sweep()
+    S32.momentum_step(dt, dt)
+    S32.vcycle(xd, y)
+    torch.cuda.synchronize()
+    zo32 = orc.vcycle(orc.params(wl, prec=1), bx, by, bz, x)
+    gate("c5 V-cycle fp32", y, zo32, 5e-7, float(np.max(np.abs(zo32))))
+    S32.close()
