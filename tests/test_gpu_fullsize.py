@@ -184,3 +184,28 @@ def test_c5_operator_and_vcycle_parity(orc):
     zo32 = orc.vcycle(orc.params(wl, prec=1), bx, by, bz, x)
     gate("c5 V-cycle fp32", y, zo32, 5e-7, float(np.max(np.abs(zo32))))
     S32.close()
+
+
+def test_c5_step_parity_forced_iterations(orc):
+    """One whole FP64 ns_step on the 512x256x256 tank, in the library's launch
+    there, against the oracle's step over all 33.5 M cells with the CG count
+    forced to the library's own count at rtol 1e-10 (the oracle's step takes
+    about half a minute on one host core)."""
+    ns = _ns()
+    wl = I.workload("c5")
+    f = I.make_fields(wl)
+    dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
+    dev = ns.device_fields(f)
+    S = ns.Solver(ns.params(wl), dev)
+    k = S.step(dt, 0.0)["iters"]
+    S.close()
+    print(f"[fullsize] GPU step took {k} CG iterations; oracle step with {k}", flush=True)
+    ref, sto, rc = orc.step(orc.params(wl, max_iters=k, rtol=0.0), f, dt, 0.0)
+    dev = ns.device_fields(f)
+    S = ns.Solver(ns.params(wl, max_iters=k, rtol=0.0), dev)
+    assert S.fine_sweep()
+    sg = S.step(dt, 0.0, allow_noconv=True)
+    torch.cuda.synchronize()
+    assert sg["iters"] == k
+    gate_fields("c5 step parity", dev, ref, ("sigma", "u", "v", "w", "p"), 1e-10, Scales(wl, f, dt))
+    S.close()
