@@ -1,5 +1,8 @@
-"""Full-size checks at the largest tank, 512x256x256 (33.5 M cells), where the
-oracle cannot run whole: one FP64 step through the C ABI is checked
+"""Full-size checks at the largest tank, 512x256x256 (33.5 M cells), in the
+launch the library uses there.  The oracle runs the operator, one V-cycle
+and one whole step with the CG count forced over the whole grid (seconds to
+half a minute on one host core), and they are compared over all cells.
+One FP64 step through the C ABI is also checked
 
   * stage by stage on sampled windows: the oracle runs the level-set,
     property, momentum and face-coefficient stages on a window of the same
