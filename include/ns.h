@@ -316,6 +316,21 @@ ns_status ns_set_fine_sweep(ns_ctx* ctx, int fused);
  * NS_EINVAL for a null argument. */
 ns_status ns_get_fine_sweep(const ns_ctx* ctx, int* fused);
 
+/* Line tables of the finest level's face coefficients (on = 1, the
+ * default).  Each solve first records, for every x-line of each face array
+ * (the faces along x at one j, k), whether all its faces hold one value (for
+ * x-faces: every interior face, the two wall faces being zero), and that
+ * value.  In a two-phase tank most lines lie wholly in water or wholly in
+ * air, where 1/rho is one constant; the finest level's kernels then read one
+ * table entry for such a line instead of its faces, about a third of the
+ * bytes a CG iteration moves.  The face arrays themselves are unchanged and
+ * results are bitwise the same either way.  Recorded V-cycle graphs are
+ * released and recorded again on their next use (synchronises the stream).
+ * NS_EINVAL for another value. */
+ns_status ns_set_face_tables(ns_ctx* ctx, int on);
+/* *on = 1 if the line tables are used, else 0.  NS_EINVAL for a null argument. */
+ns_status ns_get_face_tables(const ns_ctx* ctx, int* on);
+
 /* Kernel timing, a profiling aid.  While enabled for a kernel, each of its
  * next max_launches dispatches on the context's stream carries a start and
  * stop HIP event recorded by the dispatch itself (hipExtLaunchKernelGGL),

@@ -52,6 +52,7 @@ struct ns_ctx {
   hipEvent_t ev_rr;   // marks the residual read-back of a CG iteration
   int launch_mode;    // ns_launch_mode
   bool fine_rb;       // the finest level's red-black sweeps as one launch each
+  bool face_tabs;     // the finest level's kernels read uniform face lines through their tables
   struct {
     double F[3];      // last hydrodynamic force (eqn_int_fh)
     double fpto;      // last power take-off force
@@ -329,6 +330,20 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       V.by = cv.take<double>(fv);
       V.bz = cv.take<double>(fw);
       V.invd = cv.take<double>(c2);
+    }
+    // the finest level's line tables of its face arrays (one entry per x-line)
+    V.tx = V.ty = V.tz = nullptr;
+    V.txf = V.tyf = V.tzf = nullptr;
+    V.tab_ok = V.tabf_ok = false;
+    if (l == 0) {
+      const size_t lx = (size_t)V.n.ny * V.n.nz, ly = (size_t)(V.n.ny + 1) * V.n.nz;
+      const size_t lz = (size_t)V.n.ny * (V.n.nz + 1);
+      V.tx = cv.take<double>(lx);
+      V.ty = cv.take<double>(ly);
+      V.tz = cv.take<double>(lz);
+      V.txf = cv.take<float>(lx);
+      V.tyf = cv.take<float>(ly);
+      V.tzf = cv.take<float>(lz);
     }
     // b and e: colour-split (2 ceil(nx/2) ny nz entries) above the tail,
     // natural on tail levels; level 0 keeps its own split pair (its natural
@@ -733,7 +748,23 @@ ns_status issue(ns_ctx* X, int kind, const void* a, const void* b, const void* c
   return NS_OK;
 }
 
+// The finest level's line tables, built from its face arrays as they are now
+// (a solve's kernels then take uniform lines from them), or left invalid
+// when switched off.  Whatever writes the face arrays marks them invalid.
+void build_face_tables(ns_ctx* X) {
+  Level& L0 = X->lev[0];
+  L0.tab_ok = L0.tabf_ok = false;
+  if (!X->face_tabs) return;
+  launch_face_tables<double>(L0.n, L0.bx, L0.by, L0.bz, L0.tx, L0.ty, L0.tz, X->st);
+  L0.tab_ok = true;
+  if (X->P.prec != NS_PREC_FP64) {
+    launch_face_tables<float>(L0.n, L0.bxf, L0.byf, L0.bzf, L0.txf, L0.tyf, L0.tzf, X->st);
+    L0.tabf_ok = true;
+  }
+}
+
 void prepare_hierarchy(ns_ctx* X) {
+  build_face_tables(X);
   if (X->P.prec == NS_PREC_FP64)
     build_hierarchy<double>(X);
   else
@@ -820,7 +851,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   bool xpend = false;
   auto dir_update = [&](const double* zz, const double* dold, double* dnew, int first) {
     launch_dir_spmv(n, h, L0.bx, L0.by, L0.bz, zz, dold, dnew, X->q, first, cs, X->st,
-                    X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr, xpend ? x : nullptr);
+                    X->timed_kernel == NS_TIME_SPMV ? &X->kt : nullptr, xpend ? x : nullptr, face_tab(L0, L0.bx));
     launch_cg_update(n, X->q, X->r, cs, X->st);
     xpend = true;
     HIPCHK(X, hipGetLastError());
@@ -831,7 +862,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     xpend = false;
   };
   prepare_hierarchy(X);
-  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
+  launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st, face_tab(L0, L0.bx));
   HIPCHK(X, hipEventRecord(X->ev_rr, st));
   // first direction d = z = M r, rho = <r, z>, queued before the host has
   // seen ||b|| and ||r||; unused if b = 0 or the guess already converges
@@ -882,7 +913,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
     if (rr <= tol2) {
       // confirm on the true residual; restart from it when it fails
       sync_x(d);
-      launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st);
+      launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->r, cs, FIN_RESID0, st, face_tab(L0, L0.bx));
       if ((s = wait_host(X)) != NS_OK) return s;
       rr = true_rr = host_total(X, 2, 0, S_RR);
       S.rel_resid = std::sqrt(rr) / bnorm;
@@ -903,7 +934,7 @@ ns_status pcg(ns_ctx* X, ns_stats* stats) {
   sync_x(d);
   if (!conv) {
     // true residual at exit (into q, leaving r as the recursion left it)
-    launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st);
+    launch_resid_norm(n, h, L0.bx, L0.by, L0.bz, X->b, x, X->q, cs, FIN_TRR, st, face_tab(L0, L0.bx));
     if ((s = wait_host(X)) != NS_OK) return s;
     true_rr = host_total(X, 2, 0, S_TRR);
   }
@@ -1048,6 +1079,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
   }
   X->launch_mode = NS_LAUNCH_GRAPH;
   X->fine_rb = gs_rb_fine_pays(X->lev[0].n, X->P.prec == NS_PREC_FP64);
+  X->face_tabs = true;
   X->ngs = 0;
   X->have_beta = false;
   X->timed_kernel = -1;
@@ -1123,6 +1155,24 @@ ns_status ns_set_fine_sweep(ns_ctx* X, int fused) {
 ns_status ns_get_fine_sweep(const ns_ctx* X, int* fused) {
   if (!X || !fused) return NS_EINVAL;
   *fused = X->fine_rb ? 1 : 0;
+  return NS_OK;
+}
+
+ns_status ns_set_face_tables(ns_ctx* X, int on) {
+  if (!X) return NS_EINVAL;
+  if (on != 0 && on != 1) return fail(X, NS_EINVAL, "on must be 0 or 1");
+  X->face_tabs = on != 0;
+  X->lev[0].tab_ok = X->lev[0].tabf_ok = false;   // built again by the next solve when on
+  // the recorded V-cycle graphs hold the tables' addresses or none: record them again
+  HIPCHK(X, hipStreamSynchronize(X->st));
+  for (int q = 0; q < X->ngs; ++q) (void)hipGraphExecDestroy(X->gs[q].exec);
+  X->ngs = 0;
+  return NS_OK;
+}
+
+ns_status ns_get_face_tables(const ns_ctx* X, int* on) {
+  if (!X || !on) return NS_EINVAL;
+  *on = X->face_tabs ? 1 : 0;
   return NS_OK;
 }
 
@@ -1341,6 +1391,7 @@ ns_status momentum_step(ns_ctx* X, double dt, double t_np1) {
                   S > 0 ? X->cn_rhs : nullptr, S > 0 ? X->cn_diag : nullptr, X->host_dev + S_FLAGS, st);
   X->last_cn = 0;
   X->have_beta = false;
+  L0.tab_ok = L0.tabf_ok = false;   // new face coefficients
   if (S > 0) {
     // batches of S sweeps, the last of each measuring its largest change,
     // until that change is below cn_tol of the largest |u*|
@@ -1579,6 +1630,9 @@ ns_status ns_buffer(ns_ctx* X, int which, void** dev_ptr, size_t* count) {
   if (count) *count = c;
   if (which == NS_BUF_BX || which == NS_BUF_BY || which == NS_BUF_BZ || which == NS_BUF_RHS)
     X->have_beta = true;   // the caller may fill the projection inputs directly
+  if (which == NS_BUF_BX || which == NS_BUF_BY || which == NS_BUF_BZ || which == NS_BUF_BXF || which == NS_BUF_BYF ||
+      which == NS_BUF_BZF)
+    X->lev[0].tab_ok = X->lev[0].tabf_ok = false;   // the caller may write them
   return NS_OK;
 }
 

@@ -90,6 +90,21 @@ struct Phys {
 
 // One multigrid level.  Level 0 of the FP64 hierarchy aliases the CG
 // vectors (b = r, e = z); level 0 of the FP32 hierarchy has its own b, e.
+// Line tables of a level's face coefficients.  A line is the faces along x
+// of one (j, k): (nx + 1) x-faces (ny nz lines), nx y-faces ((ny + 1) nz
+// lines), nx z-faces (ny (nz + 1) lines).  Entry (line) holds the value
+// every face of the line takes (for an x-line: every interior face, its two
+// wall faces being zero), or the all-ones marker where they differ.  In a
+// two-phase tank most lines lie wholly in water or wholly in air, so a
+// kernel whose wavefront covers one line reads one entry instead of the
+// line's faces.  The face arrays stay complete; a table only spares loads.
+template <typename T>
+struct FaceTab {
+  const T* x = nullptr;
+  const T* y = nullptr;
+  const T* z = nullptr;
+};
+
 struct Level {
   Dims n;
   double h;
@@ -102,7 +117,25 @@ struct Level {
   float *bfn, *efn;             // level 0, FP32: natural-order b and e of the mixed V-cycle
   double* invd;                 // 1 / diagonal (h^2 scaled), FP64
   float* invdf;                 // FP32
+  // level 0: line tables of bx, by, bz (FP64) and of their FP32 copies;
+  // valid while tab_ok / tabf_ok (the arrays unchanged since they were built)
+  double *tx, *ty, *tz;
+  float *txf, *tyf, *tzf;
+  bool tab_ok, tabf_ok;
 };
+
+// the line tables of L's face arrays of type T when they are current and
+// bx is that array, else none
+template <typename T>
+inline FaceTab<T> face_tab(const Level& L, const T* bx) {
+  FaceTab<T> t;
+  if constexpr (sizeof(T) == 8) {
+    if (L.tab_ok && bx == L.bx) t = FaceTab<T>{L.tx, L.ty, L.tz};
+  } else {
+    if (L.tabf_ok && bx == L.bxf) t = FaceTab<T>{L.txf, L.tyf, L.tzf};
+  }
+  return t;
+}
 
 // Device scalars of the CG iteration (one cache line each group).
 enum ScalIdx {
@@ -259,6 +292,9 @@ void launch_coarsen_level(const Level& F, const T* fbx, const T* fby, const T* f
                           T* cby, T* cbz, T* invd, bool split, hipStream_t st);
 template <typename T>
 void launch_fill(T* a, size_t n, hipStream_t st);
+// the line tables tx, ty, tz of the face arrays bx, by, bz of a level with extents n
+template <typename T>
+void launch_face_tables(const Dims& n, const T* bx, const T* by, const T* bz, T* tx, T* ty, T* tz, hipStream_t st);
 template <typename T>
 void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st);
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st);
@@ -279,7 +315,7 @@ int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const 
 int cg_blocks(const Dims& n);
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                        const double* b, const double* x, double* r, const CgScratch& cs, int mode,
-                       hipStream_t st);
+                       hipStream_t st, const FaceTab<double>& ft = FaceTab<double>{});
 void launch_dot_rho(const Dims& n, const double* r, const double* z, const CgScratch& cs, hipStream_t st);
 // beta and rho from two-valued partials already in cs.partials
 void launch_finalize_beta(const CgScratch& cs, int nparts, hipStream_t st);
@@ -289,7 +325,8 @@ void launch_dots_beta(const Dims& n, const double* r, const double* zn, const do
 // pending x += alpha d_old
 void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                      const double* zn, const double* dold, double* dnew, double* q, int first,
-                     const CgScratch& cs, hipStream_t st, KTimer* kt = nullptr, double* x = nullptr);
+                     const CgScratch& cs, hipStream_t st, KTimer* kt = nullptr, double* x = nullptr,
+                     const FaceTab<double>& ft = FaceTab<double>{});
 // r -= alpha q and ||r||^2; x += alpha d is left pending
 void launch_cg_update(const Dims& n, const double* q, double* r, const CgScratch& cs, hipStream_t st);
 // the pending x += alpha d

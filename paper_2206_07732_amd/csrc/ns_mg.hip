@@ -61,6 +61,99 @@ __device__ __forceinline__ T stencil(const Dims& n, const T* __restrict__ bx, co
   return acc;
 }
 
+// ------------------------------------------------------------ line tables
+template <typename T>
+struct TabBits;
+template <>
+struct TabBits<double> {
+  using U = unsigned long long;
+};
+template <>
+struct TabBits<float> {
+  using U = unsigned;
+};
+
+// true with v the value every face of the line holds, where the table says
+// so; else false (v = 0), also without a table.  With a line that is the
+// same on every lane the entry is a scalar load, and a branch on the result
+// a scalar branch.
+template <typename T>
+__device__ __forceinline__ bool line_val(const T* __restrict__ tab, int line, T& v) {
+  using U = typename TabBits<T>::U;
+  v = (T)0;
+  if (tab == nullptr) return false;
+  const T t = tab[line];
+  if (__builtin_bit_cast(U, t) == ~U(0)) return false;
+  v = t;
+  return true;
+}
+
+// The six faces of one cell per lane, for a wavefront whose lanes share the
+// cell's j and k (ju, ku: those values, the same on every lane; blockDim.x is
+// 64): the x-line (j, k), the y-lines j and j + 1 and the z-lines k and k + 1
+// of plane k, each taken from its table where the line is one value, else
+// loaded.  load() issues the loads, under scalar branches, so that a
+// wavefront on lines of one value issues none; get(), called after the
+// caller's loads are all in flight (past its sched_barrier), picks the
+// values, so no wait is placed between the loads.
+template <typename T>
+struct FaceLd {
+  T t[5];
+  bool u[5];
+  T l[6];
+  // fx, fy: the x- and y-face index of the cell's west and south faces; fz:
+  // its down face (the cell's natural index)
+  __device__ __forceinline__ void load(const Dims& n, const FaceTab<T>& ft, const T* __restrict__ bx,
+                                       const T* __restrict__ by, const T* __restrict__ bz, int ju, int ku,
+                                       size_t fx, size_t fy, size_t fz) {
+    u[0] = line_val(ft.x, ju + n.ny * ku, t[0]);
+    u[1] = line_val(ft.y, ju + (n.ny + 1) * ku, t[1]);
+    u[2] = line_val(ft.y, ju + 1 + (n.ny + 1) * ku, t[2]);
+    u[3] = line_val(ft.z, ju + n.ny * ku, t[3]);
+    u[4] = line_val(ft.z, ju + n.ny * (ku + 1), t[4]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) l[q] = (T)0;
+    if (!u[0]) {
+      l[0] = bx[fx];
+      l[1] = bx[fx + 1];
+    }
+    if (!u[1]) l[2] = by[fy];
+    if (!u[2]) l[3] = by[fy + n.nx];
+    if (!u[3]) l[4] = bz[fz];
+    if (!u[4]) l[5] = bz[fz + (size_t)n.nx * n.ny];
+  }
+  // the faces of the lane's cell, in column i (a line of one value has zero
+  // wall faces)
+  __device__ __forceinline__ void get(const Dims& n, int i, T& bw, T& be, T& bs, T& bn, T& bd, T& bu) const {
+    bw = u[0] ? (i > 0 ? t[0] : (T)0) : l[0];
+    be = u[0] ? (i < n.nx - 1 ? t[0] : (T)0) : l[1];
+    bs = u[1] ? t[1] : l[2];
+    bn = u[2] ? t[2] : l[3];
+    bd = u[3] ? t[3] : l[4];
+    bu = u[4] ? t[4] : l[5];
+  }
+};
+
+// the line table of one face array, a wavefront per line of len faces (xw:
+// an x-line, whose first and last faces are walls and must be zero); the
+// comparison is of bit patterns, so a line of equal values is exactly one
+// value
+template <typename T>
+__global__ void __launch_bounds__(256) k_face_table(const T* __restrict__ a, int len, int nlines, int xw,
+                                                    T* __restrict__ tab) {
+  using U = typename TabBits<T>::U;
+  const int line = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (line >= nlines) return;
+  const T* p = a + (size_t)line * len;
+  const int lo = xw ? 1 : 0, hi = xw ? len - 1 : len;
+  const U v = lo < hi ? __builtin_bit_cast(U, p[lo]) : U(0);
+  bool same = true;
+  for (int i = lo + lane; i < hi; i += 64) same &= __builtin_bit_cast(U, p[i]) == v;
+  if (xw && lane == 0) same &= __builtin_bit_cast(U, p[0]) == U(0) && __builtin_bit_cast(U, p[len - 1]) == U(0);
+  const bool all = __all(same);
+  if (lane == 0) tab[line] = __builtin_bit_cast(T, all ? v : ~U(0));
+}
+
 // --------------------------------------------------------------- reductions
 __device__ __forceinline__ int block_tid() {
   return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
@@ -168,6 +261,17 @@ __device__ __forceinline__ GsIn<T> gs_gather(const Dims& n, const SplitGeo& sg, 
   const size_t pd = D ? pos - sz : pos, pu = top ? pos : pos + sz;
   return GsIn<T>{bx[fx], bx[fx + 1], by[fy], by[fy + n.nx], bz[c], bz[c + sxy], o(ps), o(pn), o(pd), o(pu)};
 }
+// the neighbour values of gs_gather alone (the faces left zero, for a
+// FaceLd to fill)
+template <typename T, typename O>
+__device__ __forceinline__ GsIn<T> gs_gather_nb(const Dims& n, const SplitGeo& sg, int j, int k, size_t pos, O o) {
+  const bool top = (k == n.nz - 1);
+  const bool S = j > 0, N = j < n.ny - 1, D = k > 0;
+  const size_t sz = (size_t)sg.hx * n.ny;
+  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos;
+  const size_t pd = D ? pos - sz : pos, pu = top ? pos : pos + sz;
+  return GsIn<T>{(T)0, (T)0, (T)0, (T)0, (T)0, (T)0, o(ps), o(pn), o(pd), o(pu)};
+}
 template <typename T>
 __device__ __forceinline__ T gs_combine(const Dims& n, const GsIn<T>& g, T h2, T bc, int i, int j, int k, T vw,
                                         T ve) {
@@ -204,14 +308,27 @@ __device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                             const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
-                                            int colour, T* __restrict__ nat) {
+                                            int colour, T* __restrict__ nat, FaceTab<T> ft) {
   PAIR_INDEX;
   const int par = (j + k + colour) & 1;
   const int i = 2 * ti + par, io = 2 * ti + 1 - par;
   const T* eo = e + (size_t)(1 - colour) * sg.P;
+  // a cell past the row's end gathers through the row's last cell and stores nothing
+  const int ic = i < n.nx ? i : n.nx - 1;
+  const auto o = [&](size_t q) { return eo[q]; };
+  const bool W = ic > 0, E = ic < n.nx - 1;
+  const size_t pw = W ? pos - (size_t)((ic & 1) ? 0 : 1) : pos;
+  const size_t pe = E ? pos + (size_t)((ic & 1) ? 1 : 0) : pos;
+  GsIn<T> g = gs_gather_nb<T>(n, sg, j, k, pos, o);
+  const T vw = o(pw), ve = o(pe), bc = b[(size_t)colour * sg.P + pos];
+  FaceLd<T> F;
+  F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
+         ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
+         row + ic);
+  __builtin_amdgcn_sched_barrier(0);
+  F.get(n, ic, g.bw, g.be, g.bs, g.bn, g.bd, g.bu);
   if (i < n.nx) {
-    const T v = gs_split_value<T>(n, sg, h2, bx, by, bz, b[(size_t)colour * sg.P + pos], i, j, k, pos,
-                                  [&](size_t q) { return eo[q]; });
+    const T v = gs_combine<T>(n, g, h2, bc, i, j, k, vw, ve);
     if (nat)
       nat[row + i] = v;
     else
@@ -232,7 +349,7 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, T h2, const T* __r
                                                       const T* __restrict__ b, const T* __restrict__ e,
                                                       double* __restrict__ nat, const double* __restrict__ r,
                                                       const double* __restrict__ zold,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ partials, FaceTab<T> ft) {
   const Tile tl = xcd_tile();
   const int ti = tl.x * blockDim.x + threadIdx.x;
   const int j = tl.y * blockDim.y + threadIdx.y;
@@ -257,13 +374,18 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, T h2, const T* __r
   const size_t row = (size_t)n.nx * jj + sxy * kk;
   const int lane = threadIdx.x;
   const T eb = eo[pos];
-  const GsIn<T> g = gs_gather<T>(n, sg, bx, by, bz, ir, jj, kk, pos, [&](size_t q) { return eo[q]; });
+  GsIn<T> g = gs_gather_nb<T>(n, sg, jj, kk, pos, [&](size_t q) { return eo[q]; });
+  FaceLd<T> F;   // the wavefront's lines (j, k), clamped into the grid for a wavefront outside it
+  F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(min(j, n.ny - 1)),
+         __builtin_amdgcn_readfirstlane(min(k, n.nz - 1)), ir + (size_t)(n.nx + 1) * (jj + (size_t)n.ny * kk),
+         ir + (size_t)n.nx * (jj + (size_t)(n.ny + 1) * kk), row + ir);
   const T bc = b[pos];
   T ex = 0;   // the row-end lanes' x neighbour from outside the wavefront
   if (live && lane == 0 && par == 0 && ir > 0) ex = eo[pos - 1];
   if (live && lane == 63 && par == 1 && ir < n.nx - 1) ex = eo[pos + 1];
   const double rr = r[row + ir], zr = zold[row + ir], rq = r[row + iq], zq = zold[row + iq];
   __builtin_amdgcn_sched_barrier(0);
+  F.get(n, ir, g.bw, g.be, g.bs, g.bn, g.bd, g.bu);
   const T ebl = __shfl_up(eb, 1, 64), ebr = __shfl_down(eb, 1, 64);
   // formed on every lane from in-grid values, then kept by selects: a use
   // under a branch would let the compiler sink r's and z_old's loads past
@@ -289,7 +411,7 @@ template <typename T, bool FINE, bool NAT, typename TB = T>
 __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                                   const T* __restrict__ bz, const TB* __restrict__ b,
                                                   const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
-                                                  T* __restrict__ bcopy) {
+                                                  T* __restrict__ bcopy, FaceTab<T> ft) {
   static_assert(NAT || sizeof(TB) == sizeof(T), "a colour-split b has the cycle's type");
   PAIR_INDEX;
   const int par = (j + k) & 1;
@@ -332,8 +454,11 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   const size_t c = row + ibc;
   const size_t fx = ibc + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = ibc + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  const T bw = bx[fx], be = bx[fx + 1], bsy = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  FaceLd<T> F;
+  F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k), fx, fy, c);
   __builtin_amdgcn_sched_barrier(0);
+  T bw, be, bsy, bn, bd, bu;
+  F.get(n, ibc, bw, be, bsy, bn, bd, bu);
   const T rv = h2 * br * idr;
   if (ir < n.nx) {
     e[pos] = rv;
@@ -363,7 +488,7 @@ template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                                     const T* __restrict__ bz, const T* __restrict__ b,
                                                     T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
-                                                    const T* __restrict__ ec, T* __restrict__ bcopy) {
+                                                    const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
   PAIR_INDEX;
   const int i = 2 * ti + 1 - ((j + k) & 1);   // the black cell
   if (i >= n.nx) return;
@@ -386,9 +511,12 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
   const size_t c = row + i;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  const T bw = bx[fx], be = bx[fx + 1], bs = by[fy], bn = by[fy + n.nx], bd = bz[c], bu = bz[c + sxy];
+  FaceLd<T> F;
+  F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k), fx, fy, c);
   const T bcell = b[sg.P + pos];
   __builtin_amdgcn_sched_barrier(0);
+  T bw, be, bs, bn, bd, bu;
+  F.get(n, i, bw, be, bs, bn, bd, bu);
   const T vw = ew + qw, ve = ee + qe, vs = es + qs, vn = en + qn, vd = ed + qd, vu = eu + qu;
   const bool top = !U;
   const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
@@ -875,7 +1003,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_resid_restrict_pairs(Dims nf, T ih2, const T* __restrict__ bx,
                                                               const T* __restrict__ by, const T* __restrict__ bz,
                                                               const T* __restrict__ b, const T* __restrict__ e,
-                                                              Dims nc, int csplit, T inv, T* __restrict__ bc) {
+                                                              Dims nc, int csplit, T inv, T* __restrict__ bc,
+                                                              FaceTab<T> ft) {
   using T2 = T __attribute__((ext_vector_type(2)));
   __shared__ T sr[2][2][2][64];   // [dk][dj][di][lane]
   const Tile tl = xcd_tile();
@@ -901,12 +1030,36 @@ __global__ void __launch_bounds__(256) k_resid_restrict_pairs(Dims nf, T ih2, co
   const int fx = 2 * tc + (nf.nx + 1) * (j + nf.ny * k);
   const int fy = 2 * tc + nf.nx * (j + (nf.ny + 1) * k);
   const int c = 2 * tc + nf.nx * j + sxy * k;
-  const T fwa = bx[fx], fab = bx[fx + 1];   // A's west face; the face between A and B
-  const T feo = bx[lane == 63 ? fx + 2 : fx];   // B's east face, for lane 63
-  const T2 fs = *reinterpret_cast<const T2*>(by + fy), fn = *reinterpret_cast<const T2*>(by + fy + nf.nx);
-  const T2 fd = *reinterpret_cast<const T2*>(bz + c), fu = *reinterpret_cast<const T2*>(bz + c + sxy);
+  // the faces: each line (the x-line j, k; y-lines j, j + 1; z-lines k, k + 1)
+  // through its table where it is one value (the wavefront is one row), else
+  // loaded under a scalar branch; picked after every load is in flight
+  const int ju = __builtin_amdgcn_readfirstlane(j), ku = __builtin_amdgcn_readfirstlane(k);
+  T tx, ts, tn, td, tu;
+  const bool ux = line_val(ft.x, ju + nf.ny * ku, tx), us = line_val(ft.y, ju + (nf.ny + 1) * ku, ts);
+  const bool un = line_val(ft.y, ju + 1 + (nf.ny + 1) * ku, tn), ud = line_val(ft.z, ju + nf.ny * ku, td);
+  const bool uu = line_val(ft.z, ju + nf.ny * (ku + 1), tu);
+  T fwa = 0, fab = 0, feo = 0;   // A's west face; the face between A and B; B's east face, for lane 63
+  T2 fs = {0, 0}, fn = {0, 0}, fd = {0, 0}, fu = {0, 0};
+  if (!ux) {
+    fwa = bx[fx];
+    fab = bx[fx + 1];
+    feo = bx[lane == 63 ? fx + 2 : fx];
+  }
+  if (!us) fs = *reinterpret_cast<const T2*>(by + fy);
+  if (!un) fn = *reinterpret_cast<const T2*>(by + fy + nf.nx);
+  if (!ud) fd = *reinterpret_cast<const T2*>(bz + c);
+  if (!uu) fu = *reinterpret_cast<const T2*>(bz + c + sxy);
   const T ba = b[pa], bb = b[pb];
   __builtin_amdgcn_sched_barrier(0);
+  if (ux) {   // walls: face 0 and face nx (nx is even, so 2 tc + 1 is inside)
+    fwa = tc > 0 ? tx : (T)0;
+    fab = tx;
+    feo = 2 * tc + 2 < nf.nx ? tx : (T)0;
+  }
+  if (us) fs = T2{ts, ts};
+  if (un) fn = T2{tn, tn};
+  if (ud) fd = T2{td, td};
+  if (uu) fu = T2{tu, tu};
   const T xbl = __shfl_up(xb, 1, 64), xar = __shfl_down(xa, 1, 64), fwr = __shfl_down(fwa, 1, 64);
   const T xaw = W ? (lane > 0 ? xbl : xo) : xa;
   const T xbe = E ? (lane < 63 ? xar : xo) : xb;
@@ -1479,12 +1632,30 @@ __global__ void __launch_bounds__(256) k_resid_norm(Dims n, double ih2, const do
                                                     const double* __restrict__ b,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ r,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials, FaceTab<double> ft) {
   CELL_INDEX;
   double v[2] = {0.0, 0.0};
+  // the faces of the wavefront's lines (blockDim.x == 64), through their
+  // tables where a line is one value
+  const int ju = __builtin_amdgcn_readfirstlane(min(j, n.ny - 1)), ku = __builtin_amdgcn_readfirstlane(min(k, n.nz - 1));
+  const int ii = inside ? i : 0;
+  const size_t fx = ii + (size_t)(n.nx + 1) * (ju + (size_t)n.ny * ku);
+  const size_t fy = ii + (size_t)n.nx * (ju + (size_t)(n.ny + 1) * ku);
+  const size_t cf = ii + (size_t)n.nx * (ju + (size_t)n.ny * ku);
+  FaceLd<double> F;
+  F.load(n, ft, bx, by, bz, ju, ku, fx, fy, cf);
+  double cw, ce, cs, cn, cd, cu;
+  F.get(n, ii, cw, ce, cs, cn, cd, cu);
   if (inside) {
+    const size_t sxy = (size_t)n.nx * n.ny;
+    const double xc = x[c];
+    const double xw = x[i > 0 ? c - 1 : c], xe = x[i < n.nx - 1 ? c + 1 : c];
+    const double xs = x[j > 0 ? c - n.nx : c], xn = x[j < n.ny - 1 ? c + n.nx : c];
+    const double xd = x[k > 0 ? c - sxy : c], xu = x[k < n.nz - 1 ? c + sxy : c];
+    double acc = cw * (xc - xw) + ce * (xc - xe) + cs * (xc - xs) + cn * (xc - xn) + cd * (xc - xd);
+    acc += (k < n.nz - 1) ? cu * (xc - xu) : 2.0 * cu * xc;
     const double bc = b[c];
-    const double rc = bc - ih2 * stencil<double>(n, bx, by, bz, x, i, j, k, c);
+    const double rc = bc - ih2 * acc;
     r[c] = rc;
     v[0] = rc * rc;
     v[1] = bc * bc;
@@ -1532,7 +1703,7 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
                                                   double* __restrict__ dnew, double* __restrict__ q,
                                                   int first, const double* __restrict__ scal,
                                                   double* __restrict__ partials, double* __restrict__ x,
-                                                  int xupd) {
+                                                  int xupd, FaceTab<double> ft) {
   CELL_INDEX;
   double v[1] = {0.0};
   // Every load is issued before the shuffles wait for zc: the faces and the
@@ -1545,7 +1716,6 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
   const size_t fx = ii + (size_t)(n.nx + 1) * (jj + (size_t)n.ny * kk);
   const size_t fy = ii + (size_t)n.nx * (jj + (size_t)(n.ny + 1) * kk);
   const double zc = zn[c];
-  const double cw = bx[fx], ce = bx[fx + 1], cs = by[fy], cn = by[fy + n.nx], cd = bz[c], cu = bz[c + sxy];
   const double zs = zn[jj > 0 ? c - n.nx : c], zno = zn[jj < n.ny - 1 ? c + n.nx : c];
   const double zd = zn[kk > 0 ? c - sxy : c], zu = zn[kk < n.nz - 1 ? c + sxy : c];
   double zx = 0.0;   // lane 0's west and lane 63's east neighbour lie outside the wavefront
@@ -1553,7 +1723,14 @@ __global__ void __launch_bounds__(256) k_dir_spmv(Dims n, double ih2, const doub
   if (lane == 63 && ii < n.nx - 1) zx = zn[c + 1];
   const double dol = dold[c], qol = q[c];
   const double xo = xupd ? x[c] : 0.0;
+  // the faces: of the wavefront's x-line (j, k), the y-lines j, j + 1 and the
+  // z-lines k, k + 1, each through its table where the line is one value
+  const int ju = __builtin_amdgcn_readfirstlane(min(j, n.ny - 1)), ku = __builtin_amdgcn_readfirstlane(min(k, n.nz - 1));
+  FaceLd<double> F;
+  F.load(n, ft, bx, by, bz, ju, ku, fx, fy, c);
   __builtin_amdgcn_sched_barrier(0);
+  double cw, ce, cs, cn, cd, cu;
+  F.get(n, ii, cw, ce, cs, cn, cd, cu);
   const double zl = __shfl_up(zc, 1, 64), zr = __shfl_down(zc, 1, 64);
   if (inside) {
     if (xupd) x[c] = xo + scal[S_ALPHA] * dol;
@@ -1699,11 +1876,12 @@ void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b
   auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
   if (kt && kt->n < kt->cap) {
     hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
-                          (T)(L.h * L.h), bx, by, bz, b, e, colour, nat);
+                          (T)(L.h * L.h), bx, by, bz, b, e, colour, nat, face_tab(L, bx));
     ++kt->n;
     return;
   }
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, nat);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, nat,
+                     face_tab(L, bx));
 }
 
 template <typename T>
@@ -1711,12 +1889,13 @@ void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, cons
                      const T* invd, T* e, T* bs, hipStream_t st, T* bcopy) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
-  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*, T*);
+  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*, T*, FaceTab<T>);
   if (b_natural)
     kern = fine ? k_gs_first<T, true, true> : k_gs_first<T, false, true>;
   else
     kern = fine ? k_gs_first<T, true, false> : k_gs_first<T, false, false>;
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy,
+                     face_tab(L, bx));
 }
 
 template <typename T>
@@ -1725,7 +1904,7 @@ void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, co
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
   hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0] >> 1,
-                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy);
+                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy, face_tab(L, bx));
 }
 
 // the fused red-black pass's tile (TX lanes per row, TY rows, TZ planes), or
@@ -1843,7 +2022,7 @@ void launch_resid_restrict(const Level& F, const T* bx, const T* by, const T* bz
   if (resid_pairs_fit(F)) {
     const dim3 grid((F.n.nx / 2 + 63) / 64, F.n.ny / 2, F.n.nz / 2);
     hipLaunchKernelGGL(k_resid_restrict_pairs<T>, grid, dim3(64, 2, 2), 0, st, F.n, ih2, bx, by, bz, b, e, C.n,
-                       c_split ? 1 : 0, (T)0.125, bc);
+                       c_split ? 1 : 0, (T)0.125, bc, face_tab(F, bx));
     return;
   }
   // fine-cell tiles with even extents (a coarse cell's children in one tile)
@@ -1899,6 +2078,14 @@ void launch_fill(T* a, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n);
 }
 
+template <typename T>
+void launch_face_tables(const Dims& n, const T* bx, const T* by, const T* bz, T* tx, T* ty, T* tz, hipStream_t st) {
+  const int lx = n.ny * n.nz, ly = (n.ny + 1) * n.nz, lz = n.ny * (n.nz + 1);
+  hipLaunchKernelGGL(k_face_table<T>, dim3((lx + 3) / 4), dim3(256), 0, st, bx, n.nx + 1, lx, 1, tx);
+  hipLaunchKernelGGL(k_face_table<T>, dim3((ly + 3) / 4), dim3(256), 0, st, by, n.nx, ly, 0, ty);
+  hipLaunchKernelGGL(k_face_table<T>, dim3((lz + 3) / 4), dim3(256), 0, st, bz, n.nx, lz, 0, tz);
+}
+
 
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
@@ -1909,7 +2096,7 @@ int launch_gs_last_dots(const Level& L, const T* bx, const T* by, const T* bz, c
                         double* nat, const double* r, const double* zold, double* partials, hipStream_t st) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   hipLaunchKernelGGL(k_gs_last_dots<T>, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, nat, r,
-                     zold, partials);
+                     zold, partials, face_tab(L, bx));
   return (int)(g.grid.x * g.grid.y * g.grid.z);
 }
 
@@ -1917,7 +2104,7 @@ void launch_gs_first_nat64(const Level& L, const float* bx, const float* by, con
                            const float* invd, float* e, float* bs, hipStream_t st, float* bcopy) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   hipLaunchKernelGGL((k_gs_first<float, true, true, double>), g.grid, g.block, 0, st, L.n, (float)(L.h * L.h), bx,
-                     by, bz, b, invd, e, bs, bcopy);
+                     by, bz, b, invd, e, bs, bcopy, face_tab(L, bx));
 }
 
 int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
@@ -1969,10 +2156,10 @@ void launch_finalize_beta(const CgScratch& cs, int nparts, hipStream_t st) { fin
 
 void launch_resid_norm(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                        const double* b, const double* x, double* r, const CgScratch& cs, int mode,
-                       hipStream_t st) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
+                       hipStream_t st, const FaceTab<double>& ft) {
+  Geo g = geo3(n.nx, n.ny, n.nz);   // blockDim.x == 64: a wavefront per x-line
   hipLaunchKernelGGL(k_resid_norm, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, b, x, r,
-                     cs.hpart ? cs.hpart : cs.partials);
+                     cs.hpart ? cs.hpart : cs.partials, ft);
   if (!cs.hpart) finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), mode, st);
 }
 
@@ -1991,18 +2178,18 @@ void launch_dots_beta(const Dims& n, const double* r, const double* zn, const do
 
 void launch_dir_spmv(const Dims& n, double h, const double* bx, const double* by, const double* bz,
                      const double* zn, const double* dold, double* dnew, double* q, int first,
-                     const CgScratch& cs, hipStream_t st, KTimer* kt, double* x) {
-  Geo g = geo3(n.nx, n.ny, n.nz);
+                     const CgScratch& cs, hipStream_t st, KTimer* kt, double* x, const FaceTab<double>& ft) {
+  Geo g = geo3(n.nx, n.ny, n.nz);   // blockDim.x == 64: a wavefront per x-line
   const int xupd = x ? 1 : 0;
   if (kt && kt->n < kt->cap) {
     (void)hipStreamSynchronize(st);
     hipExtLaunchKernelGGL(k_dir_spmv, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0,
                           n, 1.0 / (h * h), bx, by, bz, zn, dold, dnew, q, first, (const double*)cs.scal,
-                          cs.partials, x, xupd);
+                          cs.partials, x, xupd, ft);
     ++kt->n;
   } else {
     hipLaunchKernelGGL(k_dir_spmv, g.grid, g.block, 0, st, n, 1.0 / (h * h), bx, by, bz, zn, dold, dnew, q,
-                       first, (const double*)cs.scal, cs.partials, x, xupd);
+                       first, (const double*)cs.scal, cs.partials, x, xupd, ft);
   }
   finalize(cs, (int)(g.grid.x * g.grid.y * g.grid.z), FIN_ALPHA, st);
 }
@@ -2046,6 +2233,7 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
   template void launch_coarsen_level<T>(const Level&, const T*, const T*, const T*, const Level&, T*, \
                                         T*, T*, T*, bool, hipStream_t);                               \
   template void launch_fill<T>(T*, size_t, hipStream_t);                                              \
+  template void launch_face_tables<T>(const Dims&, const T*, const T*, const T*, T*, T*, T*, hipStream_t); \
   template void launch_vcycle_tail<T>(const TailDesc<T>&, size_t, hipStream_t);
 NSK_INST(double)
 NSK_INST(float)

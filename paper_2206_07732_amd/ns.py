@@ -124,6 +124,8 @@ def lib() -> C.CDLL:
             "ns_phase_timing": ([vp, i], i),
             "ns_set_fine_sweep": ([vp, i], i),
             "ns_get_fine_sweep": ([vp, C.POINTER(i)], i),
+            "ns_set_face_tables": ([vp, i], i),
+            "ns_get_face_tables": ([vp, C.POINTER(i)], i),
             "ns_last_error": ([vp], C.c_char_p),
             "ns_destroy": ([vp], None),
         }
@@ -142,7 +144,7 @@ EXPORTED = ["ns_workspace_bytes", "ns_init", "levelset_advect_reinit", "momentum
             "ns_net_create", "ns_net_destroy", "ns_net_last_error", "ns_net_set_params",
             "ns_net_get_params", "ns_net_get_grads", "ns_net_set_input", "ns_net_forward",
             "ns_net_train_step", "ns_attach_net", "ns_features", "ns_target", "ns_cfl_dt", "ns_phase_timing", "ns_cfl_dt_noalloc",
-            "ns_set_fine_sweep", "ns_get_fine_sweep"]
+            "ns_set_fine_sweep", "ns_get_fine_sweep", "ns_set_face_tables", "ns_get_face_tables"]
 TIME_SMOOTH0, TIME_SPMV = 0, 1
 LAUNCH_STREAM, LAUNCH_GRAPH = 0, 1
 
@@ -319,6 +321,17 @@ class Solver:
         """Whether the finest level's red-black sweeps run as one launch each."""
         v = C.c_int()
         self._chk("ns_get_fine_sweep", lib().ns_get_fine_sweep(self.ctx, C.byref(v)))
+        return bool(v.value)
+
+    def set_face_tables(self, on: bool):
+        """Whether the finest level's kernels read face lines of one value
+        through their line tables (the default) or load every face."""
+        self._chk("ns_set_face_tables", lib().ns_set_face_tables(self.ctx, 1 if on else 0))
+
+    def face_tables(self) -> bool:
+        """Whether the line tables are used."""
+        v = C.c_int()
+        self._chk("ns_get_face_tables", lib().ns_get_face_tables(self.ctx, C.byref(v)))
         return bool(v.value)
 
     def timing_enable(self, kernel: int, max_launches: int):
