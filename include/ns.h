@@ -304,10 +304,11 @@ ns_status ns_set_launch_mode(ns_ctx* ctx, int mode);
  * fused = 1 as one launch that reads each face coefficient once, the black
  * values taking theirs from the red values' loads; fused = 0 as two colour
  * passes.  The fused launch applies to 3-D levels with ny, nz >= 4 and at
- * least 32 cell pairs per row; ns_create picks it for an FP64 cycle where it
- * applies and the finest level has at least 2^24 cells, the two passes
- * elsewhere (its planes are a chain of dependent steps, which smaller grids
- * cannot cover, and an FP32 cycle's planes carry too few bytes to hide).
+ * least 32 cell pairs per row.  ns_create picks the two passes: with the line
+ * tables on (ns_set_face_tables, the default) a colour pass loads few faces,
+ * and two passes take less time than the fused launch, whose planes are a
+ * chain of dependent steps.  The fused launch paid only for an FP64 cycle
+ * loading every face, on levels of at least 2^24 cells.
  * Results are bitwise the same either way.  Recorded V-cycle graphs are released and recorded again on their
  * next use (synchronises the stream).  NS_EINVAL for another value, or
  * fused = 1 on a grid it does not apply to. */

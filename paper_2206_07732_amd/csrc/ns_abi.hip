@@ -1078,8 +1078,8 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     return NS_EHIP;
   }
   X->launch_mode = NS_LAUNCH_GRAPH;
-  X->fine_rb = gs_rb_fine_pays(X->lev[0].n, X->P.prec == NS_PREC_FP64);
   X->face_tabs = true;
+  X->fine_rb = gs_rb_fine_pays(X->lev[0].n, X->P.prec == NS_PREC_FP64, X->face_tabs);
   X->ngs = 0;
   X->have_beta = false;
   X->timed_kernel = -1;

@@ -271,9 +271,10 @@ void launch_gs_rb(const Level& L, const T* bx, const T* by, const T* bz, const T
                   hipStream_t st);
 // the finest level's red then black pass in one launch, each face coefficient
 // read once (3-D levels where gs_rb_fine_fits; the default where
-// gs_rb_fine_pays for the cycle's precision); bold: the black plane's copy
+// gs_rb_fine_pays for the cycle's precision and the line tables' use); bold:
+// the black plane's copy
 bool gs_rb_fine_fits(const Dims& n);
-bool gs_rb_fine_pays(const Dims& n, bool fp64);
+bool gs_rb_fine_pays(const Dims& n, bool fp64, bool tables);
 template <typename T>
 void launch_gs_rb_fine(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, const T* bold,
                        hipStream_t st, KTimer* kt = nullptr);

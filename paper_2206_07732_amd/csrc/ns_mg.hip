@@ -1948,12 +1948,14 @@ bool gs_rb_fine_fits(const Dims& n) {
 }
 
 // A block's march is a chain of dependent planes: the launch wins over two
-// colour passes on large grids only, and in FP64 only (on 512 x 256 x 256
-// 378 us against 2 x 223 in FP64, but 249 against 2 x 116 in FP32, whose
-// planes carry half the bytes for the same instructions; slower in both on
-// 256 x 128 x 128 and 128 x 64 x 64).
-bool gs_rb_fine_pays(const Dims& n, bool fp64) {
-  return fp64 && gs_rb_fine_fits(n) && (long)n.nx * n.ny * n.nz >= (1L << 24);
+// colour passes on large grids only, in FP64 only, and only where the
+// passes load every face (on 512 x 256 x 256 378 us against 2 x 223 in FP64,
+// but 249 against 2 x 116 in FP32, whose planes carry half the bytes for the
+// same instructions; slower in both on 256 x 128 x 128 and 128 x 64 x 64).
+// With the line tables a colour pass loads few faces and takes 153 us there,
+// and the two passes win (the march's loads stay as many).
+bool gs_rb_fine_pays(const Dims& n, bool fp64, bool tables) {
+  return fp64 && !tables && gs_rb_fine_fits(n) && (long)n.nx * n.ny * n.nz >= (1L << 24);
 }
 
 // compute units of the current device (one block of the sweep per unit)

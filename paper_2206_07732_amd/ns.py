@@ -313,8 +313,7 @@ class Solver:
 
     def set_fine_sweep(self, fused: bool):
         """The finest level's red-black sweeps as one launch each (True) or
-        as two colour passes (False); the library's default is the fused
-        launch on large 3-D grids."""
+        as two colour passes (False, the library's default)."""
         self._chk("ns_set_fine_sweep", lib().ns_set_fine_sweep(self.ctx, 1 if fused else 0))
 
     def fine_sweep(self) -> bool:
