@@ -14,14 +14,15 @@ inputs already resident in device memory when the timed region starts.
 
 Printed: ONE JSON line with
   value        Mcell-steps/s over the K timed steps (cells x K / seconds)
-  roofline     the dominant kernel (the finest-level red-black smoothing:
-               on 512x256x256 the fused sweep, one launch per red-black
-               sweep): its algorithmic bytes per launch (48 B per cell per
-               sweep: beta on the three face arrays once, b, e read and e
-               written once; 24 B per cell for a single colour pass) over
-               its average duration from HIP events on the library's
-               stream, against the published 8 TB/s; traffic from rocprofv3
-               counters
+  roofline     the dominant kernel (the finest-level red-black smoothing,
+               one colour pass per launch): its algorithmic bytes per launch
+               (48 B per cell per red-black sweep: beta on the three face
+               arrays once, b, e read and e written once; 24 B per cell per
+               colour pass) over its average duration from HIP events on
+               the library's stream, against the published 8 TB/s; traffic
+               from rocprofv3 counters, below the algorithmic bytes because
+               face lines of one value are read from the line tables (the
+               fraction of such lines is reported)
   step_roofline  the whole step's algorithmic bytes (380 B per cell outside
                the solve, 387 B per cell per FP64 CG iteration) over the
                measured step time
@@ -62,10 +63,13 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
 # passes: FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE,
-# medians over the run's dispatches (the fused finest-level sweep at
-# 512x256x256, 336; the colour pass at 128x64x64, 556).  Valid for those
-# kernels as they are now and for those workloads only; None elsewhere.
+# medians over the run's dispatches (the finest-level colour pass at
+# 512x256x256 with the line tables, 606; the fused sweep there, reading
+# every face, 336; the colour pass at 128x64x64 before the line tables,
+# 556).  Valid for those kernels as they are now and for those workloads
+# only; None elsewhere.
 TRAFFIC_BYTES_PER_LAUNCH = {
+    ("k_gs<double, true>", "c5"): 545554076,
     ("k_gs_rb_fine<double, 13>", "c5"): 2027212498,
     ("k_gs<double, true>", "c2"): 19614207,
 }
@@ -88,6 +92,24 @@ SMOOTHER_KERNELS = {True: ("k_gs_rb_fine<double, 13> (one red-black sweep, fines
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def line_table_fractions(S):
+    """The fraction of the finest level's face lines (along x, per j, k)
+    that the library reads from its line tables: every face of the line one
+    value, bit for bit (an x-line: every interior face, both wall faces
+    zero).  From the current coefficients, on the device."""
+    import torch
+    out = {}
+    for k in ("bx", "by", "bz"):
+        a = S.buffer(k).view(torch.int64)
+        if k == "bx":
+            inner = a[..., 1:-1]
+            one = (inner == inner[..., :1]).all(-1) & (a[..., 0] == 0) & (a[..., -1] == 0)
+        else:
+            one = (a == a[..., :1]).all(-1)
+        out[k] = round(float(one.double().mean()), 4)
+    return out
 
 
 def timed_steps(S, wl, steps: int, t0: float = 0.0):
@@ -150,6 +172,7 @@ def run_gpu(args):
     # recorded with each dispatch inside steps (lower: there a sweep follows
     # the kernel that wrote its inputs, part of them still on chip).
     reps = 100
+    tables = line_table_fractions(S) if S.face_tables() else None
     fused = S.fine_sweep()
     smoother_kernel, sweeps_per_launch = SMOOTHER_KERNELS[fused]
     avg_ms = S.time_kernel(ns.TIME_SMOOTH0, reps)
@@ -175,7 +198,8 @@ def run_gpu(args):
                 "avg_us": round(avg_ms * 1e3, 3), "launches": reps, "timing": "HIP events around "
                 "a batch of back-to-back dispatches on the library's stream",
                 "in_step_avg_us": round(in_step_ms * 1e3, 3), "in_step_launches": kn,
-                "in_step_frac": round(achieved_in_step / HBM_PEAK_GBS, 4)}
+                "in_step_frac": round(achieved_in_step / HBM_PEAK_GBS, 4),
+                "line_tables": tables}
     log(f"[bench] smoother: {avg_ms * 1e3:.2f} us per launch back to back ({achieved:.0f} GB/s, "
         f"{100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s); {in_step_ms * 1e3:.2f} us inside steps")
     mean_it = statistics.mean(iters)

@@ -351,9 +351,10 @@ ns_status ns_timing_read(ns_ctx* ctx, double* total_ms, int* launches);
 /* Average duration (ms) of `reps` back-to-back dispatches of one kernel on
  * the context's stream, bracketed by one pair of HIP events: the finest-level
  * smoother pass (one colour, params.prec precision) or the CG operator
- * application.  Runs on the current coefficients with vectors that are dead
- * between steps, so it may be called between time steps without changing
- * the state; synchronises the stream.  Needs momentum_step (or filled
+ * application.  Runs on the current coefficients, read as a solve reads
+ * them (the line tables built first when they are on), with vectors that
+ * are dead between steps, so it may be called between time steps without
+ * changing the state; synchronises the stream.  Needs momentum_step (or filled
  * coefficients) first, else NS_ESTATE. */
 ns_status ns_time_kernel(ns_ctx* ctx, int kernel, int reps, double* avg_ms);
 

@@ -1223,6 +1223,7 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
   Level& L0 = X->lev[0];
   const Dims n = L0.n;
   const CgScratch cs{X->partials, X->scal, X->host_dev, nullptr};
+  build_face_tables(X);   // as a solve reads the coefficients
   (void)hipStreamSynchronize(X->st);
   (void)hipEventRecord(a, X->st);
   for (int q = 0; q < reps; ++q) {
@@ -1243,7 +1244,8 @@ ns_status ns_time_kernel(ns_ctx* X, int kernel, int reps, double* avg_ms) {
           launch_gs<float>(L0, L0.bxf, L0.byf, L0.bzf, L0.bf, L0.ef, q & 1, X->st);
       }
     } else {
-      launch_dir_spmv(n, X->P.h, L0.bx, L0.by, L0.bz, X->zn, X->d, X->d2, X->q, 1, cs, X->st);
+      launch_dir_spmv(n, X->P.h, L0.bx, L0.by, L0.bz, X->zn, X->d, X->d2, X->q, 1, cs, X->st, nullptr, nullptr,
+                      face_tab(L0, L0.bx));
     }
   }
   (void)hipEventRecord(b, X->st);
