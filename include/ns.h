@@ -304,11 +304,11 @@ ns_status ns_set_launch_mode(ns_ctx* ctx, int mode);
  * fused = 1 as one launch that reads each face coefficient once, the black
  * values taking theirs from the red values' loads; fused = 0 as two colour
  * passes.  The fused launch applies to 3-D levels with ny, nz >= 4 and at
- * least 32 cell pairs per row.  ns_create picks the two passes: with the line
- * tables on (ns_set_face_tables, the default) a colour pass loads few faces,
- * and two passes take less time than the fused launch, whose planes are a
- * chain of dependent steps.  The fused launch paid only for an FP64 cycle
- * loading every face, on levels of at least 2^24 cells.
+ * least 32 cell pairs per row.  ns_create picks the two passes: the fused
+ * launch, whose planes are a chain of dependent steps, pays only for an FP64
+ * cycle on levels of at least 2^24 cells whose passes load every face, and
+ * there the line tables (ns_set_face_tables) are on, a colour pass loads few
+ * faces, and two passes take less time.
  * Results are bitwise the same either way.  Recorded V-cycle graphs are released and recorded again on their
  * next use (synchronises the stream).  NS_EINVAL for another value, or
  * fused = 1 on a grid it does not apply to. */
@@ -317,8 +317,11 @@ ns_status ns_set_fine_sweep(ns_ctx* ctx, int fused);
  * NS_EINVAL for a null argument. */
 ns_status ns_get_fine_sweep(const ns_ctx* ctx, int* fused);
 
-/* Line tables of the finest level's face coefficients (on = 1, the
- * default).  Each solve first records, for every x-line of each face array
+/* Line tables of the finest level's face coefficients (on = 1; ns_create
+ * turns them on for a finest level of at least 2^21 cells, where they pay:
+ * a kernel reading them waits one cache round trip for its lines' entries,
+ * which a smaller, latency-bound level cannot hide).  Each solve first
+ * records, for every x-line of each face array
  * (the faces along x at one j, k), whether all its faces hold one value (for
  * x-faces: every interior face, the two wall faces being zero), and that
  * value.  In a two-phase tank most lines lie wholly in water or wholly in

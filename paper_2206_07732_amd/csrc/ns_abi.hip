@@ -1078,7 +1078,7 @@ ns_status ns_init(const ns_params* params, ns_fields fields, void* workspace, si
     return NS_EHIP;
   }
   X->launch_mode = NS_LAUNCH_GRAPH;
-  X->face_tabs = true;
+  X->face_tabs = face_tables_pay(X->lev[0].n);
   X->fine_rb = gs_rb_fine_pays(X->lev[0].n, X->P.prec == NS_PREC_FP64, X->face_tabs);
   X->ngs = 0;
   X->have_beta = false;

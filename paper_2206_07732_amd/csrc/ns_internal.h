@@ -296,6 +296,8 @@ void launch_fill(T* a, size_t n, hipStream_t st);
 // the line tables tx, ty, tz of the face arrays bx, by, bz of a level with extents n
 template <typename T>
 void launch_face_tables(const Dims& n, const T* bx, const T* by, const T* bz, T* tx, T* ty, T* tz, hipStream_t st);
+// whether the library turns the line tables on for a finest level of extents n
+bool face_tables_pay(const Dims& n);
 template <typename T>
 void launch_vcycle_tail(const TailDesc<T>& D, size_t lds_bytes, hipStream_t st);
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st);

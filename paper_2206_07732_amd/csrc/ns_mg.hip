@@ -95,8 +95,9 @@ __device__ __forceinline__ bool line_val(const T* __restrict__ tab, int line, T&
 // loaded.  load() issues the loads, under scalar branches, so that a
 // wavefront on lines of one value issues none; get(), called after the
 // caller's loads are all in flight (past its sched_barrier), picks the
-// values, so no wait is placed between the loads.
-template <typename T>
+// values, so no wait is placed between the loads.  TAB false (the coarse
+// levels' instances, which never have tables): plain loads, no table code.
+template <typename T, bool TAB = true>
 struct FaceLd {
   T t[5];
   bool u[5];
@@ -106,6 +107,20 @@ struct FaceLd {
   __device__ __forceinline__ void load(const Dims& n, const FaceTab<T>& ft, const T* __restrict__ bx,
                                        const T* __restrict__ by, const T* __restrict__ bz, int ju, int ku,
                                        size_t fx, size_t fy, size_t fz) {
+    if constexpr (!TAB) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        u[q] = false;
+        t[q] = (T)0;
+      }
+      l[0] = bx[fx];
+      l[1] = bx[fx + 1];
+      l[2] = by[fy];
+      l[3] = by[fy + n.nx];
+      l[4] = bz[fz];
+      l[5] = bz[fz + (size_t)n.nx * n.ny];
+      return;
+    }
     u[0] = line_val(ft.x, ju + n.ny * ku, t[0]);
     u[1] = line_val(ft.y, ju + (n.ny + 1) * ku, t[1]);
     u[2] = line_val(ft.y, ju + 1 + (n.ny + 1) * ku, t[2]);
@@ -134,16 +149,34 @@ struct FaceLd {
   }
 };
 
-// the line table of one face array, a wavefront per line of len faces (xw:
-// an x-line, whose first and last faces are walls and must be zero); the
-// comparison is of bit patterns, so a line of equal values is exactly one
-// value
+// the line tables of a level's three face arrays in one launch, a
+// wavefront per line: lines [0, lx) of bx ((nx + 1) faces each, walls first
+// and last, which must be zero), then [lx, lx + ly) of by and the rest of bz
+// (nx faces each); the comparison is of bit patterns, so a line of equal
+// values is exactly one value
 template <typename T>
-__global__ void __launch_bounds__(256) k_face_table(const T* __restrict__ a, int len, int nlines, int xw,
-                                                    T* __restrict__ tab) {
+__global__ void __launch_bounds__(256) k_face_table(Dims n, const T* __restrict__ bx, const T* __restrict__ by,
+                                                    const T* __restrict__ bz, T* __restrict__ tx,
+                                                    T* __restrict__ ty, T* __restrict__ tz) {
   using U = typename TabBits<T>::U;
-  const int line = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (line >= nlines) return;
+  const int lx = n.ny * n.nz, ly = (n.ny + 1) * n.nz, lz = n.ny * (n.nz + 1);
+  int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (line >= lx + ly + lz) return;
+  const bool xw = line < lx;
+  const T* a = bx;
+  T* tab = tx;
+  if (!xw) {
+    line -= lx;
+    a = by;
+    tab = ty;
+    if (line >= ly) {
+      line -= ly;
+      a = bz;
+      tab = tz;
+    }
+  }
+  const int len = xw ? n.nx + 1 : n.nx;
   const T* p = a + (size_t)line * len;
   const int lo = xw ? 1 : 0, hi = xw ? len - 1 : len;
   const U v = lo < hi ? __builtin_bit_cast(U, p[lo]) : U(0);
@@ -321,7 +354,7 @@ __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ 
   const size_t pe = E ? pos + (size_t)((ic & 1) ? 1 : 0) : pos;
   GsIn<T> g = gs_gather_nb<T>(n, sg, j, k, pos, o);
   const T vw = o(pw), ve = o(pe), bc = b[(size_t)colour * sg.P + pos];
-  FaceLd<T> F;
+  FaceLd<T, FINE> F;
   F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
          ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
          row + ic);
@@ -454,7 +487,7 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   const size_t c = row + ibc;
   const size_t fx = ibc + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = ibc + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  FaceLd<T> F;
+  FaceLd<T, FINE> F;
   F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k), fx, fy, c);
   __builtin_amdgcn_sched_barrier(0);
   T bw, be, bsy, bn, bd, bu;
@@ -511,7 +544,7 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
   const size_t c = row + i;
   const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  FaceLd<T> F;
+  FaceLd<T, FINE> F;
   F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k), fx, fy, c);
   const T bcell = b[sg.P + pos];
   __builtin_amdgcn_sched_barrier(0);
@@ -2082,11 +2115,16 @@ void launch_fill(T* a, size_t n, hipStream_t st) {
 
 template <typename T>
 void launch_face_tables(const Dims& n, const T* bx, const T* by, const T* bz, T* tx, T* ty, T* tz, hipStream_t st) {
-  const int lx = n.ny * n.nz, ly = (n.ny + 1) * n.nz, lz = n.ny * (n.nz + 1);
-  hipLaunchKernelGGL(k_face_table<T>, dim3((lx + 3) / 4), dim3(256), 0, st, bx, n.nx + 1, lx, 1, tx);
-  hipLaunchKernelGGL(k_face_table<T>, dim3((ly + 3) / 4), dim3(256), 0, st, by, n.nx, ly, 0, ty);
-  hipLaunchKernelGGL(k_face_table<T>, dim3((lz + 3) / 4), dim3(256), 0, st, bz, n.nx, lz, 0, tz);
+  const int lines = n.ny * n.nz + (n.ny + 1) * n.nz + n.ny * (n.nz + 1);
+  hipLaunchKernelGGL(k_face_table<T>, dim3((lines + 3) / 4), dim3(256), 0, st, n, bx, by, bz, tx, ty, tz);
 }
+
+// Where the line tables pay: each kernel that reads them waits one cache
+// round trip for its lines' entries before it issues their faces' loads, which
+// a latency-bound level cannot hide (128 x 64 x 64: the FP64 step 2.5% slower
+// with them); from 2^21 cells on the bytes they spare win (256 x 128 x 128:
+// 7.00 -> 6.27 ms, 512 x 256 x 256: 51.1 -> 41.5 ms).
+bool face_tables_pay(const Dims& n) { return (long)n.nx * n.ny * n.nz >= (1L << 21); }
 
 
 void launch_d2f(const double* a, float* b, size_t n, hipStream_t st) {

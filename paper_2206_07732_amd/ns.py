@@ -324,7 +324,8 @@ class Solver:
 
     def set_face_tables(self, on: bool):
         """Whether the finest level's kernels read face lines of one value
-        through their line tables (the default) or load every face."""
+        through their line tables (the default from 2^21 cells) or load every
+        face."""
         self._chk("ns_set_face_tables", lib().ns_set_face_tables(self.ctx, 1 if on else 0))
 
     def face_tables(self) -> bool:

@@ -41,7 +41,6 @@ def test_vcycle_with_tables_is_bitwise_without(orc, name, prec):
     f = I.make_fields(wl)
     dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
     S = ns.Solver(ns.params(wl, prec=prec), ns.device_fields(f))
-    assert S.face_tables()
     S.momentum_step(dt, dt)
     x = torch.from_numpy(np.random.default_rng(5).standard_normal(f["p"].shape)).cuda()
     out = {}
@@ -157,11 +156,14 @@ def test_caller_written_faces_on_each_side_of_the_rules(orc, name, prec):
     S.close()
 
 
-def test_face_table_switch(orc):
+@pytest.mark.parametrize("name,default", [("tiny3d", False), ("c2", False), ("c3", True)])
+def test_face_table_switch(orc, name, default):
+    """On from 2^21 cells (256x128x128 and up), off below; the switch turns
+    them on and off and refuses another value."""
     ns = _ns()
-    wl = I.workload("tiny3d")
+    wl = case(name)
     S = ns.Solver(ns.params(wl), ns.device_fields(I.make_fields(wl)))
-    assert S.face_tables()
+    assert S.face_tables() == default
     S.set_face_tables(False)
     assert not S.face_tables()
     S.set_face_tables(True)
