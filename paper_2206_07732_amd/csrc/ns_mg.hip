@@ -338,36 +338,72 @@ __device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T
 // instance, own symbol).  With nat set (the last pass of the finest level's
 // V-cycle) the pair is written, both colours, to nat in natural order
 // instead of back into e.
+// NZ (kGsPlanes on the finest level, else 1): planes per thread.  A pass
+// over a level whose line tables spare most face loads is bound by its
+// loads' latency, a block living about one memory round trip: a thread
+// taking two planes k, k + 1 (its loads all issued before it waits on one)
+// halves the rounds of blocks.
+constexpr int kGsPlanes = 2;
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                             const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
                                             int colour, T* __restrict__ nat, FaceTab<T> ft) {
-  PAIR_INDEX;
-  const int par = (j + k + colour) & 1;
-  const int i = 2 * ti + par, io = 2 * ti + 1 - par;
+  constexpr int NZ = FINE ? kGsPlanes : 1;
+  const Tile tl = xcd_tile();
+  const int ti = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k0 = (tl.z * blockDim.z + threadIdx.z) * NZ;
+  if (j >= n.ny || k0 >= n.nz) return;
+  const SplitGeo sg = split_geo(n);
+  if (ti >= sg.hx) return;
   const T* eo = e + (size_t)(1 - colour) * sg.P;
-  // a cell past the row's end gathers through the row's last cell and stores nothing
-  const int ic = i < n.nx ? i : n.nx - 1;
   const auto o = [&](size_t q) { return eo[q]; };
-  const bool W = ic > 0, E = ic < n.nx - 1;
-  const size_t pw = W ? pos - (size_t)((ic & 1) ? 0 : 1) : pos;
-  const size_t pe = E ? pos + (size_t)((ic & 1) ? 1 : 0) : pos;
-  GsIn<T> g = gs_gather_nb<T>(n, sg, j, k, pos, o);
-  const T vw = o(pw), ve = o(pe), bc = b[(size_t)colour * sg.P + pos];
-  FaceLd<T, FINE> F;
-  F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
-         ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
-         row + ic);
-  __builtin_amdgcn_sched_barrier(0);
-  F.get(n, ic, g.bw, g.be, g.bs, g.bn, g.bd, g.bu);
-  if (i < n.nx) {
-    const T v = gs_combine<T>(n, g, h2, bc, i, j, k, vw, ve);
-    if (nat)
-      nat[row + i] = v;
-    else
-      e[(size_t)colour * sg.P + pos] = v;
+  // per plane: a plane past the grid's top repeats the last one and stores
+  // nothing; a cell past the row's end gathers through the row's last cell
+  // and stores nothing
+  int kq[NZ], iq[NZ], icq[NZ];
+  size_t posq[NZ], rowq[NZ];
+  GsIn<T> g[NZ];
+  T vw[NZ], ve[NZ], bc[NZ];
+  FaceLd<T, FINE> F[NZ];
+#pragma unroll
+  for (int q = 0; q < NZ; ++q) {
+    const int k = min(k0 + q, n.nz - 1);
+    const int par = (j + k + colour) & 1;
+    const int i = 2 * ti + par, ic = i < n.nx ? i : n.nx - 1;
+    const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k);
+    const size_t row = (size_t)n.nx * j + (size_t)n.nx * n.ny * k;
+    const bool W = ic > 0, E = ic < n.nx - 1;
+    const size_t pw = W ? pos - (size_t)((ic & 1) ? 0 : 1) : pos;
+    const size_t pe = E ? pos + (size_t)((ic & 1) ? 1 : 0) : pos;
+    g[q] = gs_gather_nb<T>(n, sg, j, k, pos, o);
+    vw[q] = o(pw);
+    ve[q] = o(pe);
+    bc[q] = b[(size_t)colour * sg.P + pos];
+    F[q].load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
+              ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
+              row + ic);
+    kq[q] = k;
+    iq[q] = i;
+    icq[q] = ic;
+    posq[q] = pos;
+    rowq[q] = row;
   }
-  if (nat && io < n.nx) nat[row + io] = eo[pos];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < NZ; ++q) {
+    if (k0 + q >= n.nz) break;
+    F[q].get(n, icq[q], g[q].bw, g[q].be, g[q].bs, g[q].bn, g[q].bd, g[q].bu);
+    const int i = iq[q], io = 2 * ti + 1 - (i & 1);
+    if (i < n.nx) {
+      const T v = gs_combine<T>(n, g[q], h2, bc[q], i, j, kq[q], vw[q], ve[q]);
+      if (nat)
+        nat[rowq[q] + i] = v;
+      else
+        e[(size_t)colour * sg.P + posq[q]] = v;
+    }
+    if (nat && io < n.nx) nat[rowq[q] + io] = eo[posq[q]];
+  }
 }
 
 // The last red pass of the finest level, writing the V-cycle's result z in
@@ -1904,8 +1940,9 @@ __global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ pa
 template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
                hipStream_t st, KTimer* kt, T* nat) {
-  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
+  // the finest level's instance takes kGsPlanes planes per thread
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, fine ? (L.n.nz + kGsPlanes - 1) / kGsPlanes : L.n.nz);
   auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
   if (kt && kt->n < kt->cap) {
     hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
