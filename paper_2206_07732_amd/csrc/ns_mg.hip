@@ -126,8 +126,9 @@ struct FaceLd {
     u[2] = line_val(ft.y, ju + 1 + (n.ny + 1) * ku, t[2]);
     u[3] = line_val(ft.z, ju + n.ny * ku, t[3]);
     u[4] = line_val(ft.z, ju + n.ny * (ku + 1), t[4]);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) l[q] = (T)0;
+    // a face of a one-value line is left unset (get() never reads it):
+    // zeroing it on that side of the branch made the compiler wait there,
+    // in some instances, for every load in flight
     if (!u[0]) {
       l[0] = bx[fx];
       l[1] = bx[fx + 1];
@@ -486,12 +487,14 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   const int par = (j + k) & 1;
   const int ir = 2 * ti + par, ib = 2 * ti + 1 - par;
   const size_t sz = (size_t)sg.hx * n.ny;
-  // b of the cell (ii, jj, kk) of colour c with pair index q
-  auto bval = [&](int c, size_t q, int ii, int jj, int kk) -> T {
+  // b of the cell (ii, jj, kk) of colour c with pair index q, as stored (an
+  // FP64 b is rounded to T after the loads: rounded as it arrived, each
+  // conversion waited for its load)
+  auto bval = [&](int c, size_t q, int ii, int jj, int kk) -> TB {
     if constexpr (NAT)
-      return (T)b[(size_t)ii + (size_t)n.nx * jj + sxy * kk];
+      return b[(size_t)ii + (size_t)n.nx * jj + sxy * kk];
     else
-      return (T)b[(size_t)c * sg.P + q];
+      return b[(size_t)c * sg.P + q];
   };
   // This pair's red value h2 b / D, formed also where the red cell lies past
   // the row's end (b clamped into the row, an unused 1/D entry), since the
@@ -502,23 +505,25 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   // gathers through the row's last cell and stores nothing.
   const int lane = threadIdx.x;
   const int irc = ir < n.nx ? ir : n.nx - 1, ibc = ib < n.nx ? ib : n.nx - 1;
-  const T br = bval(0, pos, irc, j, k), idr = invd[pos];
-  const T bb = bval(1, pos, ibc, j, k);
+  const TB br0 = bval(0, pos, irc, j, k);
+  const T idr = invd[pos];
+  const TB bb0 = bval(1, pos, ibc, j, k);
   // the red neighbours' b and 1/D through in-range indices (walls: own pair)
   const bool W = ibc > 0, E = ibc < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
   const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
   const int js = S ? j - 1 : j, jn = N ? j + 1 : j;
   const int kd = D ? k - 1 : k, ku = U ? k + 1 : k;
-  const T bS = bval(0, ps, ibc, js, k), iS = invd[ps], bN = bval(0, pn, ibc, jn, k), iN = invd[pn];
-  const T bD = bval(0, pd, ibc, j, kd), iD = invd[pd], bU = bval(0, pu, ibc, j, ku), iU = invd[pu];
-  T bX = 0, iX = 0;   // lane 63's east or lane 0's west red neighbour, outside the wavefront
-  if (lane == 63 && par == 0 && E) {
-    bX = bval(0, pos + 1, ibc + 1, j, k);
-    iX = invd[pos + 1];
-  }
-  if (lane == 0 && par == 1 && W) {
-    bX = bval(0, pos - 1, ibc - 1, j, k);
-    iX = invd[pos - 1];
+  const TB bS0 = bval(0, ps, ibc, js, k), bN0 = bval(0, pn, ibc, jn, k);
+  const T iS = invd[ps], iN = invd[pn];
+  const TB bD0 = bval(0, pd, ibc, j, kd), bU0 = bval(0, pu, ibc, j, ku);
+  const T iD = invd[pd], iU = invd[pu];
+  TB bX0 = 0;   // lane 63's east or lane 0's west red neighbour, outside the wavefront
+  T iX = 0;
+  const bool xe = lane == 63 && par == 0 && E, xw = lane == 0 && par == 1 && W;
+  if (xe || xw) {   // one block of loads: two made the second wait for the first's
+    const int dx = xe ? 1 : -1;
+    bX0 = bval(0, pos + dx, ibc + dx, j, k);
+    iX = invd[pos + dx];
   }
   const size_t c = row + ibc;
   const size_t fx = ibc + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
@@ -528,6 +533,7 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   __builtin_amdgcn_sched_barrier(0);
   T bw, be, bsy, bn, bd, bu;
   F.get(n, ibc, bw, be, bsy, bn, bd, bu);
+  const T br = (T)br0, bb = (T)bb0, bS = (T)bS0, bN = (T)bN0, bD = (T)bD0, bU = (T)bU0, bX = (T)bX0;
   const T rv = h2 * br * idr;
   if (ir < n.nx) {
     e[pos] = rv;
@@ -558,9 +564,15 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
                                                     const T* __restrict__ bz, const T* __restrict__ b,
                                                     T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
                                                     const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
-  PAIR_INDEX;
-  const int i = 2 * ti + 1 - ((j + k) & 1);   // the black cell
-  if (i >= n.nx) return;
+  // NZ planes per thread on the finest level, as in k_gs
+  constexpr int NZ = FINE ? kGsPlanes : 1;
+  const Tile tl = xcd_tile();
+  const int ti = tl.x * blockDim.x + threadIdx.x;
+  const int j = tl.y * blockDim.y + threadIdx.y;
+  const int k0 = (tl.z * blockDim.z + threadIdx.z) * NZ;
+  if (j >= n.ny || k0 >= n.nz) return;
+  const SplitGeo sg = split_geo(n);
+  if (ti >= sg.hx) return;
   // the parent's entry in 32-bit arithmetic (a level's arrays have fewer
   // than 2^31 entries; six of these per thread dominated its instruction count)
   const int chx = (nc.nx + 1) >> 1, cP = chx * nc.ny * nc.nz;
@@ -568,32 +580,72 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
     const int I = ii >> sxc, J = jj >> syc, K = kk >> szc;
     return csplit ? ((I + J + K) & 1) * cP + (I >> 1) + chx * (J + nc.ny * K) : I + nc.nx * (J + nc.ny * K);
   };
-  const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
-  const size_t sz = (size_t)sg.hx * n.ny;
-  const size_t pw = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos, pe = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
-  const size_t ps = S ? pos - sg.hx : pos, pn = N ? pos + sg.hx : pos, pd = D ? pos - sz : pos, pu = U ? pos + sz : pos;
-  // the red neighbours' values and their parents' corrections, the faces and
-  // b: every load before the first wait
-  const T ew = e[pw], ee = e[pe], es = e[ps], en = e[pn], ed = e[pd], eu = e[pu];
-  const T qw = ec[cidx(W ? i - 1 : i, j, k)], qe = ec[cidx(E ? i + 1 : i, j, k)], qs = ec[cidx(i, S ? j - 1 : j, k)];
-  const T qn = ec[cidx(i, N ? j + 1 : j, k)], qd = ec[cidx(i, j, D ? k - 1 : k)], qu = ec[cidx(i, j, U ? k + 1 : k)];
-  const size_t c = row + i;
-  const size_t fx = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
-  const size_t fy = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  FaceLd<T, FINE> F;
-  F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k), fx, fy, c);
-  const T bcell = b[sg.P + pos];
+  const size_t sz = (size_t)sg.hx * n.ny, sxy = (size_t)n.nx * n.ny;
+  // per plane (a plane past the grid's top repeats the last one, and a black
+  // cell past the row's end its row's last cell; neither is stored): the red
+  // neighbours' values and their parents' corrections, the faces and b,
+  // every load before the first wait.  The indices are all formed first:
+  // interleaved with the loads, the compiler's 32-bit multiply-adds read a
+  // register pair whose upper half was a load's destination, and waited.
+  T ev[NZ][6], qv[NZ][6], bcell[NZ];
+  int iq[NZ], kq[NZ], qi[NZ][6];
+  size_t posq[NZ], en[NZ][6], fxq[NZ], fyq[NZ], cq[NZ];
+  FaceLd<T, FINE> F[NZ];
+#pragma unroll
+  for (int q = 0; q < NZ; ++q) {
+    const int k = min(k0 + q, n.nz - 1);
+    const int ib = 2 * ti + 1 - ((j + k) & 1);   // the black cell
+    const int i = ib < n.nx ? ib : n.nx - 1;
+    const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k);
+    const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
+    en[q][0] = W ? pos - (size_t)((i & 1) ? 0 : 1) : pos;
+    en[q][1] = E ? pos + (size_t)((i & 1) ? 1 : 0) : pos;
+    en[q][2] = S ? pos - sg.hx : pos;
+    en[q][3] = N ? pos + sg.hx : pos;
+    en[q][4] = D ? pos - sz : pos;
+    en[q][5] = U ? pos + sz : pos;
+    qi[q][0] = cidx(W ? i - 1 : i, j, k);
+    qi[q][1] = cidx(E ? i + 1 : i, j, k);
+    qi[q][2] = cidx(i, S ? j - 1 : j, k);
+    qi[q][3] = cidx(i, N ? j + 1 : j, k);
+    qi[q][4] = cidx(i, j, D ? k - 1 : k);
+    qi[q][5] = cidx(i, j, U ? k + 1 : k);
+    cq[q] = (size_t)n.nx * j + sxy * k + i;
+    fxq[q] = i + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
+    fyq[q] = i + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
+    iq[q] = ib;
+    kq[q] = k;
+    posq[q] = pos;
+  }
   __builtin_amdgcn_sched_barrier(0);
-  T bw, be, bs, bn, bd, bu;
-  F.get(n, i, bw, be, bs, bn, bd, bu);
-  const T vw = ew + qw, ve = ee + qe, vs = es + qs, vn = en + qn, vd = ed + qd, vu = eu + qu;
-  const bool top = !U;
-  const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
-  const T num = h2 * bcell + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
-                (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
-  const T vb = num / diag;
-  e[sg.P + pos] = vb;
-  if (bcopy) bcopy[pos] = vb;   // the black plane as a fused red-black pass will read it
+#pragma unroll
+  for (int q = 0; q < NZ; ++q) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) ev[q][d] = e[en[q][d]];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) qv[q][d] = ec[qi[q][d]];
+    F[q].load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(kq[q]), fxq[q],
+              fyq[q], cq[q]);
+    bcell[q] = b[sg.P + posq[q]];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < NZ; ++q) {
+    if (k0 + q >= n.nz || iq[q] >= n.nx) continue;
+    const int i = iq[q], k = kq[q];
+    const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
+    T bw, be, bs, bn, bd, bu;
+    F[q].get(n, i, bw, be, bs, bn, bd, bu);
+    const T vw = ev[q][0] + qv[q][0], ve = ev[q][1] + qv[q][1], vs = ev[q][2] + qv[q][2];
+    const T vn = ev[q][3] + qv[q][3], vd = ev[q][4] + qv[q][4], vu = ev[q][5] + qv[q][5];
+    const bool top = !U;
+    const T diag = bw + be + bs + bn + bd + (top ? (T)2 * bu : bu);
+    const T num = h2 * bcell[q] + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
+                  (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
+    const T vb = num / diag;
+    e[sg.P + posq[q]] = vb;
+    if (bcopy) bcopy[posq[q]] = vb;   // the black plane as a fused red-black pass will read it
+  }
 }
 
 // A red pass then a black pass of Gauss-Seidel in one launch, on a level
@@ -1107,8 +1159,12 @@ __global__ void __launch_bounds__(256) k_resid_restrict_pairs(Dims nf, T ih2, co
   const bool ux = line_val(ft.x, ju + nf.ny * ku, tx), us = line_val(ft.y, ju + (nf.ny + 1) * ku, ts);
   const bool un = line_val(ft.y, ju + 1 + (nf.ny + 1) * ku, tn), ud = line_val(ft.z, ju + nf.ny * ku, td);
   const bool uu = line_val(ft.z, ju + nf.ny * (ku + 1), tu);
-  T fwa = 0, fab = 0, feo = 0;   // A's west face; the face between A and B; B's east face, for lane 63
-  T2 fs = {0, 0}, fn = {0, 0}, fd = {0, 0}, fu = {0, 0};
+  // A's west face; the face between A and B; B's east face, for lane 63.  A
+  // face of a one-value line is left unset until it is taken from the
+  // table below: zeroing it on that side of the branch made the FP32
+  // instance wait there for every load in flight.
+  T fwa, fab, feo;
+  T2 fs, fn, fd, fu;
   if (!ux) {
     fwa = bx[fx];
     fab = bx[fx + 1];
@@ -1971,7 +2027,8 @@ void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, cons
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
                        const Level& C, const T* ec, bool ec_split, hipStream_t st, T* bcopy) {
-  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
+  const bool fine = (L.h == L.h0);   // the finest level's instance takes kGsPlanes planes per thread
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, fine ? (L.n.nz + kGsPlanes - 1) / kGsPlanes : L.n.nz);
   auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
   hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0] >> 1,
                      L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy, face_tab(L, bx));
