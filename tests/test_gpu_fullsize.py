@@ -152,17 +152,17 @@ def test_c5_operator_and_vcycle_parity(orc):
     """The operator and one V-cycle on the whole 512x256x256 grid against the
     oracle's (a few seconds of CPU each), with the face coefficients of a
     predictor step: FP64 in the launch the library uses there (the finest
-    level's sweeps fused, 3 chunks of 86 planes; the residual-restriction by
-    cell pairs on levels halved in every direction; the banded tile order),
-    and the FP32 cycle (two colour passes on the finest level) against the
-    oracle's FP32 cycle."""
+    level's line tables, its colour passes taking two planes per thread; the
+    residual-restriction by cell pairs on levels halved in every direction;
+    the banded tile order) and with the fused one-launch sweep (3 chunks of
+    86 planes), and the FP32 cycle against the oracle's FP32 cycle."""
     ns = _ns()
     wl = I.workload("c5")
     f = I.make_fields(wl)
     dt = orc.cfl_dt(orc.params(wl), f, wl.cfl, wl.dt_max)
     dev = ns.device_fields(f)
     S = ns.Solver(ns.params(wl), dev)
-    assert S.fine_sweep()
+    assert S.face_tables() and not S.fine_sweep()
     S.momentum_step(dt, dt)
     torch.cuda.synchronize()
     bx, by, bz = (S.buffer(k).cpu().numpy() for k in ("bx", "by", "bz"))
@@ -178,9 +178,13 @@ def test_c5_operator_and_vcycle_parity(orc):
     print("[fullsize] GPU V-cycle done, oracle V-cycle", flush=True)
     zo = orc.vcycle(orc.params(wl), bx, by, bz, x)
     gate("c5 V-cycle fp64", y, zo, 1e-12, float(np.max(np.abs(zo))))
+    S.set_fine_sweep(True)
+    S.vcycle(xd, y)
+    torch.cuda.synchronize()
+    gate("c5 V-cycle fp64, fused sweep", y, zo, 1e-12, float(np.max(np.abs(zo))))
     S.close()
     S32 = ns.Solver(ns.params(wl, prec=ns.PREC_MIXED), dev)
-    assert not S32.fine_sweep()
+    assert S32.face_tables() and not S32.fine_sweep()
     S32.momentum_step(dt, dt)
     S32.vcycle(xd, y)
     torch.cuda.synchronize()
@@ -206,7 +210,7 @@ def test_c5_step_parity_forced_iterations(orc):
     ref, sto, rc = orc.step(orc.params(wl, max_iters=k, rtol=0.0), f, dt, 0.0)
     dev = ns.device_fields(f)
     S = ns.Solver(ns.params(wl, max_iters=k, rtol=0.0), dev)
-    assert S.fine_sweep()
+    assert S.face_tables()
     sg = S.step(dt, 0.0, allow_noconv=True)
     torch.cuda.synchronize()
     assert sg["iters"] == k
