@@ -86,6 +86,9 @@ SWEEP_BYTES_PER_CELL_FP64 = 48.0
 # part of one red-black sweep of the finest level that one launch does: the
 # fused sweep where the library uses it (large 3-D grids), else one colour
 # pass
+# with --precision mixed, the FP32 instances of the same kernels (half the bytes)
+SMOOTHER_KERNELS_FP32 = {True: ("k_gs_rb_fine<float, 13> (one red-black sweep, finest level)", 1.0),
+                         False: ("k_gs<float, true> (one red-black colour pass, finest level)", 0.5)}
 SMOOTHER_KERNELS = {True: ("k_gs_rb_fine<double, 13> (one red-black sweep, finest level)", 1.0),
                     False: ("k_gs<double, true> (one red-black colour pass, finest level)", 0.5)}
 
@@ -142,7 +145,8 @@ def run_gpu(args):
 
     # ---- main timed region: K whole FP64 steps
     dev = ns.device_fields(f0)
-    S = ns.Solver(ns.params(wl, prec=ns.PREC_FP64), dev)
+    mixed = args.precision == "mixed"
+    S = ns.Solver(ns.params(wl, prec=ns.PREC_MIXED if mixed else ns.PREC_FP64), dev)
     t, _, _ = timed_steps(S, wl, args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -174,7 +178,8 @@ def run_gpu(args):
     reps = 100
     tables = line_table_fractions(S) if S.face_tables() else None
     fused = S.fine_sweep()
-    smoother_kernel, sweeps_per_launch = SMOOTHER_KERNELS[fused]
+    smoother_kernel, sweeps_per_launch = (SMOOTHER_KERNELS_FP32 if mixed else SMOOTHER_KERNELS)[fused]
+    sweep_bytes = SWEEP_BYTES_PER_CELL_FP64 / (2 if mixed else 1)
     avg_ms = S.time_kernel(ns.TIME_SMOOTH0, reps)
     S.timing_enable(ns.TIME_SMOOTH0, 4096)
     for _ in range(2):
@@ -184,7 +189,7 @@ def run_gpu(args):
     kms, kn = S.timing_read()
     S.timing_enable(ns.TIME_SMOOTH0, 0)
     S.close()
-    kbytes = SWEEP_BYTES_PER_CELL_FP64 * sweeps_per_launch * ncell
+    kbytes = sweep_bytes * sweeps_per_launch * ncell
     in_step_ms = kms / max(kn, 1)
     achieved = kbytes / (avg_ms * 1e-3) / 1e9
     achieved_in_step = kbytes / (in_step_ms * 1e-3) / 1e9
@@ -194,7 +199,7 @@ def run_gpu(args):
                 "traffic": traffic,
                 "traffic_over_algorithmic": round(traffic / kbytes, 3) if traffic else None,
                 "bytes_per_launch": int(kbytes), "sweeps_per_launch": sweeps_per_launch,
-                "bytes_per_cell_per_sweep": SWEEP_BYTES_PER_CELL_FP64,
+                "bytes_per_cell_per_sweep": sweep_bytes,
                 "avg_us": round(avg_ms * 1e3, 3), "launches": reps, "timing": "HIP events around "
                 "a batch of back-to-back dispatches on the library's stream",
                 "in_step_avg_us": round(in_step_ms * 1e3, 3), "in_step_launches": kn,
@@ -210,6 +215,8 @@ def run_gpu(args):
                      "bytes_per_cell": STEP_BYTES_PER_CELL + mean_it * ITER_BYTES_PER_CELL_FP64,
                      "mean_cg_iters": mean_it}
     log(f"[bench] whole step: {step_gbs:.0f} GB/s algorithmic ({100 * step_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    if mixed:   # the byte counts above are the FP64 cycle's
+        step_roofline = {"note": "counted for the FP64 step only"}
     ceil = measured_ceilings()
     roofline["copy_ceiling_gbs"] = ceil["copy_gbs"]
     roofline["frac_of_copy"] = round(achieved / ceil["copy_gbs"], 4)
@@ -218,7 +225,8 @@ def run_gpu(args):
     config = {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "cells": ncell, "h": wl.h,
               "dt": "CFL rule on the current velocity each step", "cfl": wl.cfl,
               "dt_range": [min(dts), max(dts)],
-              "solver": "flexible PCG, V(2,2) red-black GS, FP64", "rtol": 1e-10,
+              "solver": "flexible PCG, V(2,2) red-black GS, " + ("FP32 V-cycle in FP64 CG" if mixed else "FP64"),
+              "rtol": 1e-10,
               "mg_levels": ns.num_levels(wl.nx, wl.ny, wl.nz)}
     return {"value": value, "ms_per_step": ms_per_step, "iters": iters, "roofline": roofline,
             "step_roofline": step_roofline, "phases": phases, "config": config, "wl": wl, "f0": f0,
@@ -514,6 +522,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c5")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="the main timed step's V-cycle: FP64 (the default), or FP32 inside the FP64 CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--configs", default="c1,c2,c3",
@@ -584,7 +594,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": r["config"],
         "cg_iters": r["iters"],

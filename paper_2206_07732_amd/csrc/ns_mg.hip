@@ -339,17 +339,21 @@ __device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T
 // instance, own symbol).  With nat set (the last pass of the finest level's
 // V-cycle) the pair is written, both colours, to nat in natural order
 // instead of back into e.
-// NZ (kGsPlanes on the finest level, else 1): planes per thread.  A pass
-// over a level whose line tables spare most face loads is bound by its
-// loads' latency, a block living about one memory round trip: a thread
-// taking two planes k, k + 1 (its loads all issued before it waits on one)
-// halves the rounds of blocks.
-constexpr int kGsPlanes = 2;
+// NZ (gs_planes: two on the finest level in FP32, else one): planes per
+// thread.  A pass over a level whose line tables spare most face loads is
+// bound by its loads' latency, a block living about one memory round trip: a
+// thread taking two planes k, k + 1 (its loads all issued before it waits on
+// one) halves the rounds of blocks.  On 512x256x256 that took the FP32
+// colour pass from 108 to 84 us and the prolongation pass from 128 to 123;
+// the FP64 ones, which move twice the bytes, stayed at 154 us and went from
+// 198 to 206, and keep one plane.
+template <typename T>
+constexpr int gs_planes(bool fine) { return fine && sizeof(T) == 4 ? 2 : 1; }
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                             const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
                                             int colour, T* __restrict__ nat, FaceTab<T> ft) {
-  constexpr int NZ = FINE ? kGsPlanes : 1;
+  constexpr int NZ = gs_planes<T>(FINE);
   const Tile tl = xcd_tile();
   const int ti = tl.x * blockDim.x + threadIdx.x;
   const int j = tl.y * blockDim.y + threadIdx.y;
@@ -564,8 +568,8 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
                                                     const T* __restrict__ bz, const T* __restrict__ b,
                                                     T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
                                                     const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
-  // NZ planes per thread on the finest level, as in k_gs
-  constexpr int NZ = FINE ? kGsPlanes : 1;
+  // NZ planes per thread, as in k_gs
+  constexpr int NZ = gs_planes<T>(FINE);
   const Tile tl = xcd_tile();
   const int ti = tl.x * blockDim.x + threadIdx.x;
   const int j = tl.y * blockDim.y + threadIdx.y;
@@ -1760,26 +1764,35 @@ __global__ void __launch_bounds__(256) k_resid_norm(Dims n, double ih2, const do
                                                     double* __restrict__ partials, FaceTab<double> ft) {
   CELL_INDEX;
   double v[2] = {0.0, 0.0};
-  // the faces of the wavefront's lines (blockDim.x == 64), through their
-  // tables where a line is one value
+  // As k_dir_spmv: a wavefront is one x-row of 64 cells (blockDim.x == 64);
+  // every load is issued before the first wait, through in-range indices (a
+  // lane outside the grid reads around cell 0), the x neighbours come from
+  // the adjacent lanes (a row's end lanes load theirs), and the faces of the
+  // wavefront's lines through their tables where a line is one value.
+  const int lane = threadIdx.x;
+  const int ii = inside ? i : 0, jj = inside ? j : 0, kk = inside ? k : 0;
+  const size_t sxy = (size_t)n.nx * n.ny;
+  const double xc = x[c];
+  const double xs = x[jj > 0 ? c - n.nx : c], xn = x[jj < n.ny - 1 ? c + n.nx : c];
+  const double xd = x[kk > 0 ? c - sxy : c], xu = x[kk < n.nz - 1 ? c + sxy : c];
+  const bool xlo = lane == 0 && ii > 0, xhi = lane == 63 && ii < n.nx - 1;
+  double xx = 0.0;
+  if (xlo || xhi) xx = x[xhi ? c + 1 : c - 1];
+  const double bc = b[c];
   const int ju = __builtin_amdgcn_readfirstlane(min(j, n.ny - 1)), ku = __builtin_amdgcn_readfirstlane(min(k, n.nz - 1));
-  const int ii = inside ? i : 0;
-  const size_t fx = ii + (size_t)(n.nx + 1) * (ju + (size_t)n.ny * ku);
-  const size_t fy = ii + (size_t)n.nx * (ju + (size_t)(n.ny + 1) * ku);
-  const size_t cf = ii + (size_t)n.nx * (ju + (size_t)n.ny * ku);
   FaceLd<double> F;
-  F.load(n, ft, bx, by, bz, ju, ku, fx, fy, cf);
+  F.load(n, ft, bx, by, bz, ju, ku, ii + (size_t)(n.nx + 1) * (jj + (size_t)n.ny * kk),
+         ii + (size_t)n.nx * (jj + (size_t)(n.ny + 1) * kk), c);
+  __builtin_amdgcn_sched_barrier(0);
   double cw, ce, cs, cn, cd, cu;
   F.get(n, ii, cw, ce, cs, cn, cd, cu);
+  const double xl = __shfl_up(xc, 1, 64), xr = __shfl_down(xc, 1, 64);
   if (inside) {
-    const size_t sxy = (size_t)n.nx * n.ny;
-    const double xc = x[c];
-    const double xw = x[i > 0 ? c - 1 : c], xe = x[i < n.nx - 1 ? c + 1 : c];
-    const double xs = x[j > 0 ? c - n.nx : c], xn = x[j < n.ny - 1 ? c + n.nx : c];
-    const double xd = x[k > 0 ? c - sxy : c], xu = x[k < n.nz - 1 ? c + sxy : c];
+    double xw = xc, xe = xc;
+    if (i > 0) xw = lane > 0 ? xl : xx;
+    if (i < n.nx - 1) xe = lane < 63 ? xr : xx;
     double acc = cw * (xc - xw) + ce * (xc - xe) + cs * (xc - xs) + cn * (xc - xn) + cd * (xc - xd);
     acc += (k < n.nz - 1) ? cu * (xc - xu) : 2.0 * cu * xc;
-    const double bc = b[c];
     const double rc = bc - ih2 * acc;
     r[c] = rc;
     v[0] = rc * rc;
@@ -1997,8 +2010,8 @@ template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
                hipStream_t st, KTimer* kt, T* nat) {
   const bool fine = (L.h == L.h0);
-  // the finest level's instance takes kGsPlanes planes per thread
-  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, fine ? (L.n.nz + kGsPlanes - 1) / kGsPlanes : L.n.nz);
+  const int pl = gs_planes<T>(fine);   // planes per thread
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, (L.n.nz + pl - 1) / pl);
   auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
   if (kt && kt->n < kt->cap) {
     hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
@@ -2027,8 +2040,9 @@ void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, cons
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
                        const Level& C, const T* ec, bool ec_split, hipStream_t st, T* bcopy) {
-  const bool fine = (L.h == L.h0);   // the finest level's instance takes kGsPlanes planes per thread
-  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, fine ? (L.n.nz + kGsPlanes - 1) / kGsPlanes : L.n.nz);
+  const bool fine = (L.h == L.h0);
+  const int pl = gs_planes<T>(fine);   // planes per thread
+  Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, (L.n.nz + pl - 1) / pl);
   auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
   hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0] >> 1,
                      L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy, face_tab(L, bx));
