@@ -214,9 +214,10 @@ def run_gpu(args):
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": int(step_bytes),
                      "bytes_per_cell": STEP_BYTES_PER_CELL + mean_it * ITER_BYTES_PER_CELL_FP64,
                      "mean_cg_iters": mean_it}
-    log(f"[bench] whole step: {step_gbs:.0f} GB/s algorithmic ({100 * step_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     if mixed:   # the byte counts above are the FP64 cycle's
         step_roofline = {"note": "counted for the FP64 step only"}
+    else:
+        log(f"[bench] whole step: {step_gbs:.0f} GB/s algorithmic ({100 * step_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     ceil = measured_ceilings()
     roofline["copy_ceiling_gbs"] = ceil["copy_gbs"]
     roofline["frac_of_copy"] = round(achieved / ceil["copy_gbs"], 4)
