@@ -5,8 +5,8 @@ copies in a mixed cycle), whether every face of the line holds one value
 finest-level kernels then take such a line's faces from the table instead
 of loading them.  The tables only spare loads, so every result must be
 bitwise the one computed with them switched off: V-cycles in both
-precisions on grids with one-block and multi-block rows, ragged rows and
-planes and odd extents; whole steps; and caller-written coefficients whose
+precisions on 2-D and 3-D grids with one-block and multi-block rows, ragged
+rows and planes and odd extents; whole steps; and caller-written coefficients whose
 lines are built to sit on each side of every rule (a line of one value; one
 face a unit in the last place away; an interior of one value between
 nonzero walls or walls of negative zero; a line of negative zeros)."""
@@ -30,7 +30,7 @@ def case(name):
     return sweep_case(name)
 
 
-CASES = ["tiny3d", "ragged3d", "odd1level", "rbragged", "c2", "g63", "g127", "c2half", "g300"]
+CASES = ["tiny2d", "c1", "rb2d", "tiny3d", "ragged3d", "odd1level", "rbragged", "c2", "g63", "g127", "c2half", "g300"]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -57,7 +57,7 @@ def test_vcycle_with_tables_is_bitwise_without(orc, name, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("name", ["c2", "rbragged", "g127", "g300"])
+@pytest.mark.parametrize("name", ["c1", "c2", "rbragged", "g127", "g300"])
 def test_steps_with_tables_are_bitwise_without(orc, name, prec):
     """Three whole steps (graph-replayed V-cycles inside CG) from the same
     state, with the tables and without."""
