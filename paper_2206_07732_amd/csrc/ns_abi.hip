@@ -331,11 +331,12 @@ size_t carve(const ns_params* P, ns_ctx* X, char* base) {
       V.bz = cv.take<double>(fw);
       V.invd = cv.take<double>(c2);
     }
-    // the finest level's line tables of its face arrays (one entry per x-line)
+    // the line tables of the finest and the first coarse level's face
+    // arrays (one entry per x-line)
     V.tx = V.ty = V.tz = nullptr;
     V.txf = V.tyf = V.tzf = nullptr;
     V.tab_ok = V.tabf_ok = false;
-    if (l == 0) {
+    if (l <= 1) {
       const size_t lx = (size_t)V.n.ny * V.n.nz, ly = (size_t)(V.n.ny + 1) * V.n.nz;
       const size_t lz = (size_t)V.n.ny * (V.n.nz + 1);
       V.tx = cv.take<double>(lx);
@@ -486,6 +487,18 @@ void build_hierarchy(ns_ctx* X) {
     const Level& C = X->lev[l];
     launch_coarsen_level<T>(F, LV<T>::bx(F), LV<T>::by(F), LV<T>::bz(F), C, LV<T>::bx(C), LV<T>::by(C),
                             LV<T>::bz(C), LV<T>::invd(C), l < tail_start<T>(X), X->st);
+  }
+  // the first coarse level's line tables, in the cycle's precision, where
+  // its passes run outside the tail and it is large enough for them to pay
+  if (X->face_tabs && X->L > 1 && 1 < tail_start<T>(X) && face_tables_pay(X->lev[1].n)) {
+    Level& V1 = X->lev[1];
+    if constexpr (sizeof(T) == 8) {
+      launch_face_tables<double>(V1.n, V1.bx, V1.by, V1.bz, V1.tx, V1.ty, V1.tz, X->st);
+      V1.tab_ok = true;
+    } else {
+      launch_face_tables<float>(V1.n, V1.bxf, V1.byf, V1.bzf, V1.txf, V1.tyf, V1.tzf, X->st);
+      V1.tabf_ok = true;
+    }
   }
 }
 
@@ -754,6 +767,7 @@ ns_status issue(ns_ctx* X, int kind, const void* a, const void* b, const void* c
 void build_face_tables(ns_ctx* X) {
   Level& L0 = X->lev[0];
   L0.tab_ok = L0.tabf_ok = false;
+  if (X->L > 1) X->lev[1].tab_ok = X->lev[1].tabf_ok = false;   // built again after coarsening
   if (!X->face_tabs) return;
   launch_face_tables<double>(L0.n, L0.bx, L0.by, L0.bz, L0.tx, L0.ty, L0.tz, X->st);
   L0.tab_ok = true;
@@ -1162,7 +1176,8 @@ ns_status ns_set_face_tables(ns_ctx* X, int on) {
   if (!X) return NS_EINVAL;
   if (on != 0 && on != 1) return fail(X, NS_EINVAL, "on must be 0 or 1");
   X->face_tabs = on != 0;
-  X->lev[0].tab_ok = X->lev[0].tabf_ok = false;   // built again by the next solve when on
+  for (int l = 0; l < X->L && l <= 1; ++l)
+    X->lev[l].tab_ok = X->lev[l].tabf_ok = false;   // built again by the next solve when on
   // the recorded V-cycle graphs hold the tables' addresses or none: record them again
   HIPCHK(X, hipStreamSynchronize(X->st));
   for (int q = 0; q < X->ngs; ++q) (void)hipGraphExecDestroy(X->gs[q].exec);

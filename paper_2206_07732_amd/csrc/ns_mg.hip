@@ -254,11 +254,15 @@ __device__ __forceinline__ size_t lidx(const Dims& n, const SplitGeo& g, bool sp
 
 // Threads own cell pairs (2ti, 2ti+1) of a row; the red cell of the pair is
 // 2ti + ((j+k) & 1), the black one the other; pos is the pair index.
+// (a 64 x bdy x bdz = 256-thread block of geo3; bdz is derived, since
+// reading blockDim.y and .z together made the compiler fetch both in one
+// misaligned vector load, waited on before any other load)
 #define PAIR_INDEX                                                        \
   const Tile tl = xcd_tile();                                             \
-  const int ti = tl.x * blockDim.x + threadIdx.x;                         \
-  const int j = tl.y * blockDim.y + threadIdx.y;                          \
-  const int k = tl.z * blockDim.z + threadIdx.z;                          \
+  const int bdy = blockDim.y, bdz = 4 / bdy;                              \
+  const int ti = tl.x * 64 + threadIdx.x;                                 \
+  const int j = tl.y * bdy + threadIdx.y;                                 \
+  const int k = tl.z * bdz + threadIdx.z;                                 \
   if (j >= n.ny || k >= n.nz) return;                                     \
   const SplitGeo sg = split_geo(n);                                       \
   if (ti >= sg.hx) return;                                                \
@@ -349,15 +353,21 @@ __device__ __forceinline__ T gs_split_value(const Dims& n, const SplitGeo& sg, T
 // 198 to 206, and keep one plane.
 template <typename T>
 constexpr int gs_planes(bool fine) { return fine && sizeof(T) == 4 ? 2 : 1; }
-template <typename T, bool FINE>
-__global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
-                                            const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
-                                            int colour, T* __restrict__ nat, FaceTab<T> ft) {
-  constexpr int NZ = gs_planes<T>(FINE);
+// The pass's body: TAB, the instance with line-table code (the finest
+// level's, and the first coarse level's where it has tables); NZ planes per
+// thread.
+template <typename T, bool TAB, int NZ>
+__device__ __forceinline__ void gs_body(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                        const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
+                                        int colour, T* __restrict__ nat, FaceTab<T> ft) {
+  // the block is 64 x by x bz = 256 threads (geo3); blockDim.z is derived,
+  // since reading blockDim.y and .z together made the compiler fetch both in
+  // one misaligned vector load, waited on before any other load
   const Tile tl = xcd_tile();
-  const int ti = tl.x * blockDim.x + threadIdx.x;
-  const int j = tl.y * blockDim.y + threadIdx.y;
-  const int k0 = (tl.z * blockDim.z + threadIdx.z) * NZ;
+  const int bdy = blockDim.y, bdz = 4 / bdy;
+  const int ti = tl.x * 64 + threadIdx.x;
+  const int j = tl.y * bdy + threadIdx.y;
+  const int k0 = (tl.z * bdz + threadIdx.z) * NZ;
   if (j >= n.ny || k0 >= n.nz) return;
   const SplitGeo sg = split_geo(n);
   if (ti >= sg.hx) return;
@@ -370,7 +380,7 @@ __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ 
   size_t posq[NZ], rowq[NZ];
   GsIn<T> g[NZ];
   T vw[NZ], ve[NZ], bc[NZ];
-  FaceLd<T, FINE> F[NZ];
+  FaceLd<T, TAB> F[NZ];
 #pragma unroll
   for (int q = 0; q < NZ; ++q) {
     const int k = min(k0 + q, n.nz - 1);
@@ -395,20 +405,39 @@ __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ 
     rowq[q] = row;
   }
   __builtin_amdgcn_sched_barrier(0);
+  // every value is formed (a repeated plane's or a clamped cell's too) and
+  // only the stores are guarded: a value formed under the guard let the
+  // compiler sink its loads past the barrier, into the guarded block
 #pragma unroll
   for (int q = 0; q < NZ; ++q) {
-    if (k0 + q >= n.nz) break;
     F[q].get(n, icq[q], g[q].bw, g[q].be, g[q].bs, g[q].bn, g[q].bd, g[q].bu);
     const int i = iq[q], io = 2 * ti + 1 - (i & 1);
-    if (i < n.nx) {
-      const T v = gs_combine<T>(n, g[q], h2, bc[q], i, j, kq[q], vw[q], ve[q]);
+    const T v = gs_combine<T>(n, g[q], h2, bc[q], icq[q], j, kq[q], vw[q], ve[q]);
+    const bool live = k0 + q < n.nz;
+    if (live && i < n.nx) {
       if (nat)
         nat[rowq[q] + i] = v;
       else
         e[(size_t)colour * sg.P + posq[q]] = v;
     }
-    if (nat && io < n.nx) nat[rowq[q] + io] = eo[posq[q]];
+    if (live && nat && io < n.nx) nat[rowq[q] + io] = eo[posq[q]];
   }
+}
+
+// one colour pass (FINE: the finest level's instance, its own symbol)
+template <typename T, bool FINE>
+__global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                            const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
+                                            int colour, T* __restrict__ nat, FaceTab<T> ft) {
+  gs_body<T, FINE, gs_planes<T>(FINE)>(n, h2, bx, by, bz, b, e, colour, nat, ft);
+}
+
+// the same on the first coarse level where it has line tables (own symbol)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_c1(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                               const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
+                                               int colour, T* __restrict__ nat, FaceTab<T> ft) {
+  gs_body<T, true, gs_planes<T>(true)>(n, h2, bx, by, bz, b, e, colour, nat, ft);
 }
 
 // The last red pass of the finest level, writing the V-cycle's result z in
@@ -481,11 +510,11 @@ __global__ void __launch_bounds__(256) k_gs_last_dots(Dims n, T h2, const T* __r
 // read in natural order (the finest level, whose b is a CG vector) and its
 // colour-split copy is written to bs for the later passes; a natural b may
 // be FP64 under an FP32 cycle (TB = double), rounded to T as it is read.
-template <typename T, bool FINE, bool NAT, typename TB = T>
-__global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
-                                                  const T* __restrict__ bz, const TB* __restrict__ b,
-                                                  const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
-                                                  T* __restrict__ bcopy, FaceTab<T> ft) {
+template <typename T, bool TAB, bool NAT, typename TB>
+__device__ __forceinline__ void gs_first_body(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                              const T* __restrict__ bz, const TB* __restrict__ b,
+                                              const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
+                                              T* __restrict__ bcopy, FaceTab<T> ft) {
   static_assert(NAT || sizeof(TB) == sizeof(T), "a colour-split b has the cycle's type");
   PAIR_INDEX;
   const int par = (j + k) & 1;
@@ -532,7 +561,7 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   const size_t c = row + ibc;
   const size_t fx = ibc + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k);
   const size_t fy = ibc + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k);
-  FaceLd<T, FINE> F;
+  FaceLd<T, TAB> F;
   F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k), fx, fy, c);
   __builtin_amdgcn_sched_barrier(0);
   T bw, be, bsy, bn, bd, bu;
@@ -559,21 +588,43 @@ __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restr
   if (bcopy) bcopy[pos] = vb;   // the black plane as a fused red-black pass will read it
 }
 
+// (FINE: the finest level's instance, its own symbol)
+template <typename T, bool FINE, bool NAT, typename TB = T>
+__global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                                  const T* __restrict__ bz, const TB* __restrict__ b,
+                                                  const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
+                                                  T* __restrict__ bcopy, FaceTab<T> ft) {
+  gs_first_body<T, FINE, NAT, TB>(n, h2, bx, by, bz, b, invd, e, bs, bcopy, ft);
+}
+
+// the same on the first coarse level where it has line tables (own symbol)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_first_c1(Dims n, T h2, const T* __restrict__ bx,
+                                                     const T* __restrict__ by, const T* __restrict__ bz,
+                                                     const T* __restrict__ b, const T* __restrict__ invd,
+                                                     T* __restrict__ e, T* __restrict__ bs, T* __restrict__ bcopy,
+                                                     FaceTab<T> ft) {
+  gs_first_body<T, true, false, T>(n, h2, bx, by, bz, b, invd, e, bs, bcopy, ft);
+}
+
 // prolongation e += P ec followed by the black pass, in one launch; only the
 // black cells are written (the red pass that follows overwrites the red ones
 // without reading them).  ec is the next level's correction, colour-split
 // (csplit) or natural (a tail level).
-template <typename T, bool FINE>
-__global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
-                                                    const T* __restrict__ bz, const T* __restrict__ b,
-                                                    T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
-                                                    const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
+template <typename T, bool TAB, int NZ>
+__device__ __forceinline__ void gs_prolong_body(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                                const T* __restrict__ bz, const T* __restrict__ b,
+                                                T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
+                                                const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
   // NZ planes per thread, as in k_gs
-  constexpr int NZ = gs_planes<T>(FINE);
+  // the block is 64 x by x bz = 256 threads (geo3); blockDim.z is derived,
+  // since reading blockDim.y and .z together made the compiler fetch both in
+  // one misaligned vector load, waited on before any other load
   const Tile tl = xcd_tile();
-  const int ti = tl.x * blockDim.x + threadIdx.x;
-  const int j = tl.y * blockDim.y + threadIdx.y;
-  const int k0 = (tl.z * blockDim.z + threadIdx.z) * NZ;
+  const int bdy = blockDim.y, bdz = 4 / bdy;
+  const int ti = tl.x * 64 + threadIdx.x;
+  const int j = tl.y * bdy + threadIdx.y;
+  const int k0 = (tl.z * bdz + threadIdx.z) * NZ;
   if (j >= n.ny || k0 >= n.nz) return;
   const SplitGeo sg = split_geo(n);
   if (ti >= sg.hx) return;
@@ -594,7 +645,7 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
   T ev[NZ][6], qv[NZ][6], bcell[NZ];
   int iq[NZ], kq[NZ], qi[NZ][6];
   size_t posq[NZ], en[NZ][6], fxq[NZ], fyq[NZ], cq[NZ];
-  FaceLd<T, FINE> F[NZ];
+  FaceLd<T, TAB> F[NZ];
 #pragma unroll
   for (int q = 0; q < NZ; ++q) {
     const int k = min(k0 + q, n.nz - 1);
@@ -633,10 +684,10 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
     bcell[q] = b[sg.P + posq[q]];
   }
   __builtin_amdgcn_sched_barrier(0);
+  // every value formed, only the stores guarded (as in gs_body)
 #pragma unroll
   for (int q = 0; q < NZ; ++q) {
-    if (k0 + q >= n.nz || iq[q] >= n.nx) continue;
-    const int i = iq[q], k = kq[q];
+    const int k = kq[q], i = min(iq[q], n.nx - 1);
     const bool W = i > 0, E = i < n.nx - 1, S = j > 0, N = j < n.ny - 1, D = k > 0, U = k < n.nz - 1;
     T bw, be, bs, bn, bd, bu;
     F[q].get(n, i, bw, be, bs, bn, bd, bu);
@@ -647,9 +698,30 @@ __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __res
     const T num = h2 * bcell[q] + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
                   (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
     const T vb = num / diag;
-    e[sg.P + posq[q]] = vb;
-    if (bcopy) bcopy[posq[q]] = vb;   // the black plane as a fused red-black pass will read it
+    if (k0 + q < n.nz && iq[q] < n.nx) {
+      e[sg.P + posq[q]] = vb;
+      if (bcopy) bcopy[posq[q]] = vb;   // the black plane as a fused red-black pass will read it
+    }
   }
+}
+
+// (FINE: the finest level's instance, its own symbol)
+template <typename T, bool FINE>
+__global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
+                                                    const T* __restrict__ bz, const T* __restrict__ b,
+                                                    T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
+                                                    const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
+  gs_prolong_body<T, FINE, gs_planes<T>(FINE)>(n, h2, bx, by, bz, b, e, nc, sxc, syc, szc, csplit, ec, bcopy, ft);
+}
+
+// the same on the first coarse level where it has line tables (own symbol)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_prolong_c1(Dims n, T h2, const T* __restrict__ bx,
+                                                       const T* __restrict__ by, const T* __restrict__ bz,
+                                                       const T* __restrict__ b, T* __restrict__ e, Dims nc, int sxc,
+                                                       int syc, int szc, int csplit, const T* __restrict__ ec,
+                                                       T* __restrict__ bcopy, FaceTab<T> ft) {
+  gs_prolong_body<T, true, gs_planes<T>(true)>(n, h2, bx, by, bz, b, e, nc, sxc, syc, szc, csplit, ec, bcopy, ft);
 }
 
 // A red pass then a black pass of Gauss-Seidel in one launch, on a level
@@ -2010,17 +2082,18 @@ template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
                hipStream_t st, KTimer* kt, T* nat) {
   const bool fine = (L.h == L.h0);
-  const int pl = gs_planes<T>(fine);   // planes per thread
+  const FaceTab<T> ft = face_tab(L, bx);
+  const bool tab1 = !fine && ft.x != nullptr;   // a coarse level with line tables
+  const int pl = gs_planes<T>(fine || tab1);   // planes per thread
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, (L.n.nz + pl - 1) / pl);
-  auto kern = fine ? k_gs<T, true> : k_gs<T, false>;
+  auto kern = fine ? k_gs<T, true> : tab1 ? k_gs_c1<T> : k_gs<T, false>;
   if (kt && kt->n < kt->cap) {
     hipExtLaunchKernelGGL(kern, g.grid, g.block, 0, st, kt->ev[2 * kt->n], kt->ev[2 * kt->n + 1], 0, L.n,
-                          (T)(L.h * L.h), bx, by, bz, b, e, colour, nat, face_tab(L, bx));
+                          (T)(L.h * L.h), bx, by, bz, b, e, colour, nat, ft);
     ++kt->n;
     return;
   }
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, nat,
-                     face_tab(L, bx));
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, colour, nat, ft);
 }
 
 template <typename T>
@@ -2028,24 +2101,27 @@ void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, cons
                      const T* invd, T* e, T* bs, hipStream_t st, T* bcopy) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
+  const FaceTab<T> ft = face_tab(L, bx);
+  const bool tab1 = !fine && ft.x != nullptr && !b_natural;   // a coarse level with line tables
   void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*, T*, FaceTab<T>);
   if (b_natural)
     kern = fine ? k_gs_first<T, true, true> : k_gs_first<T, false, true>;
   else
-    kern = fine ? k_gs_first<T, true, false> : k_gs_first<T, false, false>;
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy,
-                     face_tab(L, bx));
+    kern = fine ? k_gs_first<T, true, false> : tab1 ? k_gs_first_c1<T> : k_gs_first<T, false, false>;
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy, ft);
 }
 
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
                        const Level& C, const T* ec, bool ec_split, hipStream_t st, T* bcopy) {
   const bool fine = (L.h == L.h0);
-  const int pl = gs_planes<T>(fine);   // planes per thread
+  const FaceTab<T> ft = face_tab(L, bx);
+  const bool tab1 = !fine && ft.x != nullptr;   // a coarse level with line tables
+  const int pl = gs_planes<T>(fine || tab1);   // planes per thread
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, (L.n.nz + pl - 1) / pl);
-  auto kern = (L.h == L.h0) ? k_gs_prolong<T, true> : k_gs_prolong<T, false>;
+  auto kern = fine ? k_gs_prolong<T, true> : tab1 ? k_gs_prolong_c1<T> : k_gs_prolong<T, false>;
   hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, e, C.n, L.f[0] >> 1,
-                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy, face_tab(L, bx));
+                     L.f[1] >> 1, L.f[2] >> 1, ec_split ? 1 : 0, ec, bcopy, ft);
 }
 
 // the fused red-black pass's tile (TX lanes per row, TY rows, TZ planes), or

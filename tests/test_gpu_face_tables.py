@@ -6,7 +6,8 @@ finest-level kernels then take such a line's faces from the table instead
 of loading them.  The tables only spare loads, so every result must be
 bitwise the one computed with them switched off: V-cycles in both
 precisions on 2-D and 3-D grids with one-block and multi-block rows, ragged
-rows and planes and odd extents; whole steps; and caller-written coefficients whose
+rows and planes and odd extents, and on the 512x256x256 tank, whose first
+coarse level (256x128x128) has line tables of its own; whole steps; and caller-written coefficients whose
 lines are built to sit on each side of every rule (a line of one value; one
 face a unit in the last place away; an interior of one value between
 nonzero walls or walls of negative zero; a line of negative zeros)."""
@@ -30,7 +31,7 @@ def case(name):
     return sweep_case(name)
 
 
-CASES = ["tiny2d", "c1", "rb2d", "tiny3d", "ragged3d", "odd1level", "rbragged", "c2", "g63", "g127", "c2half", "g300"]
+CASES = ["tiny2d", "c1", "rb2d", "tiny3d", "ragged3d", "odd1level", "rbragged", "c2", "g63", "g127", "c2half", "g300", "c5"]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
