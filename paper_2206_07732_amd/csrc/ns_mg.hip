@@ -365,14 +365,51 @@ __device__ __forceinline__ void gs_body(Dims n, T h2, const T* __restrict__ bx, 
   // one misaligned vector load, waited on before any other load
   const Tile tl = xcd_tile();
   const int bdy = blockDim.y, bdz = 4 / bdy;
-  const int ti = tl.x * 64 + threadIdx.x;
+  const int tix = tl.x * 64 + threadIdx.x;
   const int j = tl.y * bdy + threadIdx.y;
   const int k0 = (tl.z * bdz + threadIdx.z) * NZ;
   if (j >= n.ny || k0 >= n.nz) return;
   const SplitGeo sg = split_geo(n);
-  if (ti >= sg.hx) return;
+  // a lane past the row's end works on its last pair and stores nothing:
+  // returning it early made the compiler put the other lanes' loads under
+  // that branch, past the barrier
+  const bool tlive = tix < sg.hx;
+  const int ti = tlive ? tix : sg.hx - 1;
   const T* eo = e + (size_t)(1 - colour) * sg.P;
   const auto o = [&](size_t q) { return eo[q]; };
+  if constexpr (NZ == 1) {
+    // One plane: written out.  In the per-plane form below the compiler
+    // moved this case's loads past the barrier, a second memory round trip
+    // per wavefront (the FP64 pass 153 -> 158 us on 512x256x256).
+    if (!tlive) return;
+    const int k = k0;
+    const int par = (j + k + colour) & 1;
+    const int i = 2 * ti + par, io = 2 * ti + 1 - par;
+    const size_t pos = (size_t)ti + (size_t)sg.hx * (j + (size_t)n.ny * k);
+    const size_t row = (size_t)n.nx * j + (size_t)n.nx * n.ny * k;
+    // a cell past the row's end gathers through the row's last cell and stores nothing
+    const int ic = i < n.nx ? i : n.nx - 1;
+    const bool W = ic > 0, E = ic < n.nx - 1;
+    const size_t pw = W ? pos - (size_t)((ic & 1) ? 0 : 1) : pos;
+    const size_t pe = E ? pos + (size_t)((ic & 1) ? 1 : 0) : pos;
+    GsIn<T> g = gs_gather_nb<T>(n, sg, j, k, pos, o);
+    const T vw = o(pw), ve = o(pe), bc = b[(size_t)colour * sg.P + pos];
+    FaceLd<T, TAB> F;
+    F.load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
+           ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
+           row + ic);
+    __builtin_amdgcn_sched_barrier(0);
+    F.get(n, ic, g.bw, g.be, g.bs, g.bn, g.bd, g.bu);
+    if (i < n.nx) {
+      const T v = gs_combine<T>(n, g, h2, bc, i, j, k, vw, ve);
+      if (nat)
+        nat[row + i] = v;
+      else
+        e[(size_t)colour * sg.P + pos] = v;
+    }
+    if (nat && io < n.nx) nat[row + io] = eo[pos];
+    return;
+  }
   // per plane: a plane past the grid's top repeats the last one and stores
   // nothing; a cell past the row's end gathers through the row's last cell
   // and stores nothing
@@ -391,13 +428,16 @@ __device__ __forceinline__ void gs_body(Dims n, T h2, const T* __restrict__ bx, 
     const bool W = ic > 0, E = ic < n.nx - 1;
     const size_t pw = W ? pos - (size_t)((ic & 1) ? 0 : 1) : pos;
     const size_t pe = E ? pos + (size_t)((ic & 1) ? 1 : 0) : pos;
+    // the faces' branches first, then the plain loads: issued before the
+    // branches, these were moved past the barrier (to their uses) by the
+    // compiler, a second memory round trip per wavefront
+    F[q].load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
+              ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
+              row + ic);
     g[q] = gs_gather_nb<T>(n, sg, j, k, pos, o);
     vw[q] = o(pw);
     ve[q] = o(pe);
     bc[q] = b[(size_t)colour * sg.P + pos];
-    F[q].load(n, ft, bx, by, bz, __builtin_amdgcn_readfirstlane(j), __builtin_amdgcn_readfirstlane(k),
-              ic + (size_t)(n.nx + 1) * (j + (size_t)n.ny * k), ic + (size_t)n.nx * (j + (size_t)(n.ny + 1) * k),
-              row + ic);
     kq[q] = k;
     iq[q] = i;
     icq[q] = ic;
@@ -413,7 +453,7 @@ __device__ __forceinline__ void gs_body(Dims n, T h2, const T* __restrict__ bx, 
     F[q].get(n, icq[q], g[q].bw, g[q].be, g[q].bs, g[q].bn, g[q].bd, g[q].bu);
     const int i = iq[q], io = 2 * ti + 1 - (i & 1);
     const T v = gs_combine<T>(n, g[q], h2, bc[q], icq[q], j, kq[q], vw[q], ve[q]);
-    const bool live = k0 + q < n.nz;
+    const bool live = tlive && k0 + q < n.nz;
     if (live && i < n.nx) {
       if (nat)
         nat[rowq[q] + i] = v;
@@ -424,12 +464,14 @@ __device__ __forceinline__ void gs_body(Dims n, T h2, const T* __restrict__ bx, 
   }
 }
 
-// one colour pass (FINE: the finest level's instance, its own symbol)
+// one colour pass (FINE: the finest level's instance, its own symbol).  The
+// coarse instance keeps the table code's shape with no tables: with plain
+// face loads the compiler moved all its loads past the barrier.
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                             const T* __restrict__ bz, const T* __restrict__ b, T* __restrict__ e,
                                             int colour, T* __restrict__ nat, FaceTab<T> ft) {
-  gs_body<T, FINE, gs_planes<T>(FINE)>(n, h2, bx, by, bz, b, e, colour, nat, ft);
+  gs_body<T, true, gs_planes<T>(FINE)>(n, h2, bx, by, bz, b, e, colour, nat, ft);
 }
 
 // the same on the first coarse level where it has line tables (own symbol)
@@ -622,12 +664,16 @@ __device__ __forceinline__ void gs_prolong_body(Dims n, T h2, const T* __restric
   // one misaligned vector load, waited on before any other load
   const Tile tl = xcd_tile();
   const int bdy = blockDim.y, bdz = 4 / bdy;
-  const int ti = tl.x * 64 + threadIdx.x;
+  const int tix = tl.x * 64 + threadIdx.x;
   const int j = tl.y * bdy + threadIdx.y;
   const int k0 = (tl.z * bdz + threadIdx.z) * NZ;
   if (j >= n.ny || k0 >= n.nz) return;
   const SplitGeo sg = split_geo(n);
-  if (ti >= sg.hx) return;
+  // a lane past the row's end works on its last pair and stores nothing:
+  // returning it early made the compiler put the other lanes' loads under
+  // that branch, past the barrier
+  const bool tlive = tix < sg.hx;
+  const int ti = tlive ? tix : sg.hx - 1;
   // the parent's entry in 32-bit arithmetic (a level's arrays have fewer
   // than 2^31 entries; six of these per thread dominated its instruction count)
   const int chx = (nc.nx + 1) >> 1, cP = chx * nc.ny * nc.nz;
@@ -698,20 +744,21 @@ __device__ __forceinline__ void gs_prolong_body(Dims n, T h2, const T* __restric
     const T num = h2 * bcell[q] + (W ? bw * vw : (T)0) + (E ? be * ve : (T)0) + (S ? bs * vs : (T)0) +
                   (N ? bn * vn : (T)0) + (D ? bd * vd : (T)0) + (top ? (T)0 : bu * vu);
     const T vb = num / diag;
-    if (k0 + q < n.nz && iq[q] < n.nx) {
+    if (tlive && k0 + q < n.nz && iq[q] < n.nx) {
       e[sg.P + posq[q]] = vb;
       if (bcopy) bcopy[posq[q]] = vb;   // the black plane as a fused red-black pass will read it
     }
   }
 }
 
-// (FINE: the finest level's instance, its own symbol)
+// (FINE: the finest level's instance, its own symbol; the coarse one keeps
+// the table code's shape, as k_gs)
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(256) k_gs_prolong(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                                     const T* __restrict__ bz, const T* __restrict__ b,
                                                     T* __restrict__ e, Dims nc, int sxc, int syc, int szc, int csplit,
                                                     const T* __restrict__ ec, T* __restrict__ bcopy, FaceTab<T> ft) {
-  gs_prolong_body<T, FINE, gs_planes<T>(FINE)>(n, h2, bx, by, bz, b, e, nc, sxc, syc, szc, csplit, ec, bcopy, ft);
+  gs_prolong_body<T, true, gs_planes<T>(FINE)>(n, h2, bx, by, bz, b, e, nc, sxc, syc, szc, csplit, ec, bcopy, ft);
 }
 
 // the same on the first coarse level where it has line tables (own symbol)
