@@ -69,7 +69,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # 556).  Valid for those kernels as they are now and for those workloads
 # only; None elsewhere.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("k_gs<double, true>", "c5"): 545793713,
+    ("k_gs<double, true>", "c5"): 545540231,
     ("k_gs_rb_fine<double, 13>", "c5"): 2027212498,
     ("k_gs<double, true>", "c2"): 19614207,
 }
