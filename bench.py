@@ -65,13 +65,11 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # passes: FETCH_SIZE x its copy-calibrated factor (1.9998) + WRITE_SIZE,
 # medians over the run's dispatches (the finest-level colour pass at
 # 512x256x256 with the line tables, 606; the fused sweep there, reading
-# every face, 336; the colour pass at 128x64x64 before the line tables,
-# 556).  Valid for those kernels as they are now and for those workloads
-# only; None elsewhere.
+# every face, 336).  Valid for those kernels as they are now and for that
+# workload only; None elsewhere.
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("k_gs<double, true>", "c5"): 545540231,
     ("k_gs_rb_fine<double, 13>", "c5"): 2027212498,
-    ("k_gs<double, true>", "c2"): 19614207,
 }
 
 # Algorithmic bytes per cell (FP64, 3-D; each array read or written once per
