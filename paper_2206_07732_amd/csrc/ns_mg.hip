@@ -95,8 +95,9 @@ __device__ __forceinline__ bool line_val(const T* __restrict__ tab, int line, T&
 // loaded.  load() issues the loads, under scalar branches, so that a
 // wavefront on lines of one value issues none; get(), called after the
 // caller's loads are all in flight (past its sched_barrier), picks the
-// values, so no wait is placed between the loads.  TAB false (the coarse
-// levels' instances, which never have tables): plain loads, no table code.
+// values, so no wait is placed between the loads.  TAB false: plain loads,
+// no table code (the coarse levels' first-pass instance; their colour and
+// prolongation passes keep the table code with null tables, see k_gs).
 template <typename T, bool TAB = true>
 struct FaceLd {
   T t[5];
