@@ -581,15 +581,16 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr, const d
     }
     launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt, e0);
   };
-  // the first pre-smoothing kernel (red from zero + black)
-  auto first = [&](T* bcopy) {
+  // the first pre-smoothing kernel (red from zero + black); red_out false
+  // where a red pass follows it, which overwrites the red values unread
+  auto first = [&](T* bcopy, bool red_out) {
     if constexpr (sizeof(T) == 4) {
       if (l == 0 && b0d) {
-        launch_gs_first_nat64(L, bx, by, bz, b0d, LV<T>::invd(L), e, b, st, bcopy);
+        launch_gs_first_nat64(L, bx, by, bz, b0d, LV<T>::invd(L), e, b, st, bcopy, red_out);
         return;
       }
     }
-    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st, bcopy);
+    launch_gs_first<T>(L, bx, by, bz, l == 0 ? b0 : b, l == 0, LV<T>::invd(L), e, b, st, bcopy, red_out);
   };
   if (l == X->L - 1) {
     // a coarsest level too large for the tail: its sweeps with the
@@ -603,7 +604,7 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr, const d
         launch_fill<T>(e, nsplit, st);
       return;
     }
-    first(nullptr);
+    first(nullptr, S < 2);   // a second forward sweep starts with a red pass
     for (int s = 1; s < S; ++s) {
       launch_gs<T>(L, bx, by, bz, b, e, 0, st, kt);
       launch_gs<T>(L, bx, by, bz, b, e, 1, st, kt);
@@ -635,7 +636,7 @@ void vcycle(ns_ctx* X, int l, const T* b0, T* e0, DotsReq* dq = nullptr, const d
   // pre-smoothing: (red from zero + black) fused, then red, black pairs
   if (P.nu_pre > 0) {
     const bool rb_pre = rb && P.nu_pre >= 2;
-    first(rb_pre ? ecopy : nullptr);
+    first(rb_pre ? ecopy : nullptr, P.nu_pre < 2);   // a second sweep starts with a red pass
     int s = 1;
     if (rb_pre) {
       fused();

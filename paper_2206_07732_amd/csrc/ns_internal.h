@@ -255,10 +255,11 @@ template <typename T>
 void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e, int colour,
                hipStream_t st, KTimer* kt = nullptr, T* nat = nullptr);
 // red from zero + black; b natural (b_natural, its split copy written to bs) or split
-// (bcopy, when set: a copy of the black plane, for a fused pass to read)
+// (bcopy, when set: a copy of the black plane, for a fused pass to read);
+// red_out false: the red values are not stored (the next pass is a red one)
 template <typename T>
 void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, bool b_natural,
-                     const T* invd, T* e, T* bs, hipStream_t st, T* bcopy = nullptr);
+                     const T* invd, T* e, T* bs, hipStream_t st, T* bcopy = nullptr, bool red_out = true);
 // prolongation of the next level's correction ec (split or natural) + black
 template <typename T>
 void launch_gs_prolong(const Level& L, const T* bx, const T* by, const T* bz, const T* b, T* e,
@@ -311,7 +312,8 @@ int launch_gs_last_dots(const Level& L, const T* bx, const T* by, const T* bz, c
 // the finest level's first kernel of an FP32 cycle reading its natural b in
 // FP64 (the CG residual), rounded as it is read
 void launch_gs_first_nat64(const Level& L, const float* bx, const float* by, const float* bz, const double* b,
-                           const float* invd, float* e, float* bs, hipStream_t st, float* bcopy = nullptr);
+                           const float* invd, float* e, float* bs, hipStream_t st, float* bcopy = nullptr,
+                           bool red_out = true);
 int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
                     hipStream_t st);
 

@@ -557,7 +557,7 @@ template <typename T, bool TAB, bool NAT, typename TB>
 __device__ __forceinline__ void gs_first_body(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                               const T* __restrict__ bz, const TB* __restrict__ b,
                                               const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
-                                              T* __restrict__ bcopy, FaceTab<T> ft) {
+                                              T* __restrict__ bcopy, FaceTab<T> ft, int red_out) {
   static_assert(NAT || sizeof(TB) == sizeof(T), "a colour-split b has the cycle's type");
   PAIR_INDEX;
   const int par = (j + k) & 1;
@@ -612,7 +612,9 @@ __device__ __forceinline__ void gs_first_body(Dims n, T h2, const T* __restrict_
   const T br = (T)br0, bb = (T)bb0, bS = (T)bS0, bN = (T)bN0, bD = (T)bD0, bU = (T)bU0, bX = (T)bX0;
   const T rv = h2 * br * idr;
   if (ir < n.nx) {
-    e[pos] = rv;
+    // the red values are not stored where the next pass is a red one, which
+    // overwrites them without reading them
+    if (red_out) e[pos] = rv;
     if constexpr (NAT) bs[pos] = br;
   }
   const T rl = __shfl_up(rv, 1, 64), rr = __shfl_down(rv, 1, 64);
@@ -636,8 +638,8 @@ template <typename T, bool FINE, bool NAT, typename TB = T>
 __global__ void __launch_bounds__(256) k_gs_first(Dims n, T h2, const T* __restrict__ bx, const T* __restrict__ by,
                                                   const T* __restrict__ bz, const TB* __restrict__ b,
                                                   const T* __restrict__ invd, T* __restrict__ e, T* __restrict__ bs,
-                                                  T* __restrict__ bcopy, FaceTab<T> ft) {
-  gs_first_body<T, FINE, NAT, TB>(n, h2, bx, by, bz, b, invd, e, bs, bcopy, ft);
+                                                  T* __restrict__ bcopy, FaceTab<T> ft, int red_out) {
+  gs_first_body<T, FINE, NAT, TB>(n, h2, bx, by, bz, b, invd, e, bs, bcopy, ft, red_out);
 }
 
 // the same on the first coarse level where it has line tables (own symbol)
@@ -646,8 +648,8 @@ __global__ void __launch_bounds__(256) k_gs_first_c1(Dims n, T h2, const T* __re
                                                      const T* __restrict__ by, const T* __restrict__ bz,
                                                      const T* __restrict__ b, const T* __restrict__ invd,
                                                      T* __restrict__ e, T* __restrict__ bs, T* __restrict__ bcopy,
-                                                     FaceTab<T> ft) {
-  gs_first_body<T, true, false, T>(n, h2, bx, by, bz, b, invd, e, bs, bcopy, ft);
+                                                     FaceTab<T> ft, int red_out) {
+  gs_first_body<T, true, false, T>(n, h2, bx, by, bz, b, invd, e, bs, bcopy, ft, red_out);
 }
 
 // prolongation e += P ec followed by the black pass, in one launch; only the
@@ -2146,17 +2148,18 @@ void launch_gs(const Level& L, const T* bx, const T* by, const T* bz, const T* b
 
 template <typename T>
 void launch_gs_first(const Level& L, const T* bx, const T* by, const T* bz, const T* b, bool b_natural,
-                     const T* invd, T* e, T* bs, hipStream_t st, T* bcopy) {
+                     const T* invd, T* e, T* bs, hipStream_t st, T* bcopy, bool red_out) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   const bool fine = (L.h == L.h0);
   const FaceTab<T> ft = face_tab(L, bx);
   const bool tab1 = !fine && ft.x != nullptr && !b_natural;   // a coarse level with line tables
-  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*, T*, FaceTab<T>);
+  void (*kern)(Dims, T, const T*, const T*, const T*, const T*, const T*, T*, T*, T*, FaceTab<T>, int);
   if (b_natural)
     kern = fine ? k_gs_first<T, true, true> : k_gs_first<T, false, true>;
   else
     kern = fine ? k_gs_first<T, true, false> : tab1 ? k_gs_first_c1<T> : k_gs_first<T, false, false>;
-  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy, ft);
+  hipLaunchKernelGGL(kern, g.grid, g.block, 0, st, L.n, (T)(L.h * L.h), bx, by, bz, b, invd, e, bs, bcopy, ft,
+                     red_out ? 1 : 0);
 }
 
 template <typename T>
@@ -2373,10 +2376,10 @@ int launch_gs_last_dots(const Level& L, const T* bx, const T* by, const T* bz, c
 }
 
 void launch_gs_first_nat64(const Level& L, const float* bx, const float* by, const float* bz, const double* b,
-                           const float* invd, float* e, float* bs, hipStream_t st, float* bcopy) {
+                           const float* invd, float* e, float* bs, hipStream_t st, float* bcopy, bool red_out) {
   Geo g = geo3((L.n.nx + 1) / 2, L.n.ny, L.n.nz);
   hipLaunchKernelGGL((k_gs_first<float, true, true, double>), g.grid, g.block, 0, st, L.n, (float)(L.h * L.h), bx,
-                     by, bz, b, invd, e, bs, bcopy, face_tab(L, bx));
+                     by, bz, b, invd, e, bs, bcopy, face_tab(L, bx), red_out ? 1 : 0);
 }
 
 int launch_f2d_dots(const float* a, double* z, size_t n, const double* r, const double* zold, double* partials,
@@ -2490,7 +2493,7 @@ void launch_apply_A(const Dims& n, double h, const double* bx, const double* by,
   template int launch_gs_last_dots<T>(const Level&, const T*, const T*, const T*, const T*, const T*,     \
                                       double*, const double*, const double*, double*, hipStream_t);       \
   template void launch_gs_first<T>(const Level&, const T*, const T*, const T*, const T*, bool, const T*,  \
-                                   T*, T*, hipStream_t, T*);                                              \
+                                   T*, T*, hipStream_t, T*, bool);                                        \
   template void launch_gs_prolong<T>(const Level&, const T*, const T*, const T*, const T*, T*,           \
                                      const Level&, const T*, bool, hipStream_t, T*);                      \
   template void launch_gs_rb<T>(const Level&, const T*, const T*, const T*, const T*, T*, const T*,     \
