@@ -68,7 +68,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # every face, 336).  Valid for those kernels as they are now and for that
 # workload only; None elsewhere.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("k_gs<double, true>", "c5"): 545540231,
+    ("k_gs<double, true>", "c5"): 545528840,
     ("k_gs_rb_fine<double, 13>", "c5"): 2027212498,
 }
 
